@@ -1,0 +1,221 @@
+"""Benchmark: particle-steps/s of the PM step + Born lens projection on one GPU.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg2]
+
+Workload (default): 256^3 particles on a 512^3 force mesh in a 205 Mpc/h
+box, 40 PM steps linear in a from 0.01 to 1.0, four 2048^2 convergence maps
+over 5 deg x 5 deg at z_s = 0.5, 1, 1.5, 2 (float32), seeded Gaussian white
+noise initial conditions.  A "step" is one pm_step plus the lens_project of
+its shell.  W untimed steps run first; then the initial conditions are
+regenerated (untimed) and K consecutive steps of the schedule are timed
+(the schedule restarts from fresh initial conditions, inside the timed
+region, if K exceeds it).  Per-kernel durations come from HIP events the
+library records on its own stream during the timed region.
+
+Prints ONE JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+
+
+def algorithmic_bytes(wl, esize=4):
+    """Algorithmic HBM bytes of one launch of every timed kernel class.
+
+    P = particles, M = one real mesh, S = one half spectrum (main + Nyquist
+    plane).  Counts each input read once and each output written once.
+    """
+    P = wl.np_side ** 3
+    nm = wl.nm_side
+    M = nm ** 3 * esize
+    S = M + nm * nm * 2 * esize
+    maps = len(wl.z_src) * wl.npix ** 2 * esize
+    return {
+        "kick_drift_key": 72 * P,          # R disp,mom,acc,id  W disp,mom,key,rank
+        "scatter": 64 * P,                 # R key,rank,disp,mom,id  W disp,mom,id
+        "paint": 16 * P + M,               # R disp,id  W rho
+        "fft_r2c_axis2": M + S,
+        "fft_c2c_axis1_fwd": 2 * S,
+        "fft_grad_axis0": 4 * S,           # R 1 spectrum, W 3
+        "fft_c2c_axis1_inv": 2 * S,
+        "fft_c2r_axis2": S + M,
+        "readout_kick": 3 * M + 52 * P,    # R 3 meshes, disp,id,mom  W mom,acc
+        "lens_paint": 16 * P + 2 * maps,   # R disp,id  RW maps
+        "lens_mean": 2 * maps,
+        "scan": 0,
+    }
+
+
+def load_traffic(kernel):
+    """HBM traffic per launch measured with rocprofv3 counters, if the kernel
+    source has not changed since (hash recorded with the counters)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        rec = json.load(open(path))
+        ent = rec.get(kernel)
+        if not ent:
+            return None
+        import hashlib
+        src = os.path.join(ROOT, ent["source"])
+        h = hashlib.sha256(open(src, "rb").read()).hexdigest()
+        if h != ent["sha256"]:
+            return None
+        return ent["bytes_per_launch"]
+    except Exception:
+        return None
+
+
+def cpu_baseline(wl, frac=8):
+    """The float64 oracle on a bounded sample of one step of the workload.
+
+    Sample: the oracle's own Zel'dovich state at a = 0.5; CIC paint and CIC
+    readout of 1/frac of the particles and the lens projection of the same
+    subsample for one late shell, each scaled by frac; the three full-size
+    Fourier force transforms.  Reported as particle-steps/s of one step.
+    """
+    from oracle import lens, pm
+    from oracle.cosmology import Cosmology
+    import workloads as W
+    c = Cosmology(wl.omega_m, wl.h, wl.n_s, wl.sigma8, wl.omega_b, wl.t_cmb)
+    noise = W.white_noise(wl.np_side, wl.seed)
+    x, _ = pm.zeldovich_ic(noise, c, wl.box, wl.nm_side, 0.5)
+    sub = x[:, ::frac]
+    geom = lens.MapGeometry(wl.npix, wl.fov_deg, wl.z_src, c)
+    a = wl.a_grid()
+    i = int(0.85 * wl.nsteps)
+    t0 = time.perf_counter()
+    rho = pm.cic_paint(sub, wl.nm_side, wl.box, mass=(wl.nm_side / wl.np_side) ** 3)
+    t1 = time.perf_counter()
+    f = pm.force_mesh(rho * frac, wl.box)
+    t2 = time.perf_counter()
+    for j in range(3):
+        pm.cic_readout(sub, f[j], wl.box)
+    t3 = time.perf_counter()
+    lens.project_shell(sub, a[i], a[i + 1], c, wl.box, wl.np_side, geom)
+    t4 = time.perf_counter()
+    per_step = (t1 - t0) * frac + (t2 - t1) + (t3 - t2) * frac + (t4 - t3) * frac
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"value": wl.np_side ** 3 / per_step, "unit": "particle-steps/s",
+            "cores": cores, "kind": "oracle",
+            "sample": (f"one PM step + lens shell {i} of {wl.name}: paint, readout and lens of "
+                       f"1/{frac} of the particles (scaled x{frac}) + full {wl.nm_side}^3 "
+                       f"float64 FFT force; {t4 - t0:.1f} s of CPU work, est. {per_step:.1f} s/step")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="cfg2")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true",
+                    help="no per-kernel events in the timed region (roofline omitted)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        sys.exit(2)
+
+    import torch
+    import workloads as W
+    from paper_2012_07266_amd import Simulation
+
+    wl = {"cfg1": W.CFG1.with_(name="plain_fp32_32p_32m"), "cfg2": W.CFG2,
+          "cfg3": W.CFG3, "cfg5": W.CFG5}[args.workload]
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda", 0)
+    stream = torch.cuda.current_stream()
+    noise = torch.from_numpy(W.white_noise(wl.np_side, wl.seed)).to(dev, torch.float32)
+    a = wl.a_grid()
+    sim = Simulation(wl.np_side, wl.nm_side, wl.box, wl.npix, wl.fov_deg, wl.z_src,
+                     dtype=torch.float32, omega_m=wl.omega_m, sigma8=wl.sigma8, h=wl.h,
+                     n_s=wl.n_s, omega_b=wl.omega_b, t_cmb=wl.t_cmb)
+    kappa = sim.new_maps()
+
+    def run_steps(k, i0):
+        i = i0
+        for _ in range(k):
+            if i == wl.nsteps:
+                sim.init_ic(noise, a[0])
+                kappa.zero_()
+                i = 0
+            sim.step(a[i], a[i + 1])
+            sim.lens(a[i], a[i + 1], kappa)
+            i += 1
+        return i
+
+    sim.init_ic(noise, a[0])
+    run_steps(args.warmup, 0)
+    sim.init_ic(noise, a[0])
+    kappa.zero_()
+    sim.sync()
+    if not args.no_profile:
+        sim.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run_steps(args.steps, 0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sim.sync()
+    prof = {}
+    if not args.no_profile:
+        prof = sim.profile_read()
+        sim.profile(False)
+    elapsed = t1 - t0
+    ps = wl.np_side ** 3 * args.steps / elapsed
+
+    out = {
+        "metric": "particle-steps/s at 256^3 (PM+lens) + HBM GB/s; p50/p99 served-sim latency",
+        "value": ps, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": wl.name, "np": wl.np_side, "nm": wl.nm_side, "box": wl.box,
+                   "a_range": [wl.a_start, wl.a_end], "nsteps_schedule": wl.nsteps,
+                   "maps": f"{len(wl.z_src)}x{wl.npix}^2 over {wl.fov_deg} deg",
+                   "z_src": list(wl.z_src)},
+    }
+    if prof:
+        alg = algorithmic_bytes(wl)
+        kern = {}
+        total_ms = 0.0
+        total_bytes = 0.0
+        for name, (ms, cnt) in prof.items():
+            b = alg.get(name, 0)
+            avg = ms / max(cnt, 1)
+            kern[name] = {"launches": cnt, "avg_ms": avg, "total_ms": ms,
+                          "alg_bytes_per_launch": b,
+                          "alg_gbs": (b / (avg * 1e-3) / 1e9) if avg > 0 and b else None}
+            total_ms += ms
+            total_bytes += b * cnt
+        dom = max(prof, key=lambda k: prof[k][0])
+        d = kern[dom]
+        out["roofline"] = {"kernel": dom, "bound": "hbm", "achieved": d["alg_gbs"],
+                           "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": d["alg_gbs"] / HBM_PEAK_GBS if d["alg_gbs"] else None,
+                           "traffic": load_traffic(dom)}
+        out["hbm_effective_gbs_all_kernels"] = total_bytes / (total_ms * 1e-3) / 1e9
+        out["kernels"] = kern
+    out["paper_context"] = ("MADLens on 32 Haswell cores: ~6.2e6 particle-steps/s "
+                            "(256^3, 11 steps, 30 s incl. projection; different workload)")
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(wl)
+    sim.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

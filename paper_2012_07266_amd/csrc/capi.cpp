@@ -1,0 +1,611 @@
+// C ABI of libmadlens_amd.so: parameter validation, the device arena,
+// float64 host tables, and the orchestration of the PM step, initial
+// conditions and lens projection on one HIP stream.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/madlens.h"
+#include "cosmo_host.h"
+#include "fft.h"
+#include "particles.h"
+
+using namespace ml;
+
+namespace {
+
+constexpr double PI = 3.14159265358979323846;
+
+bool only_2_3(int n) {
+    if (n <= 0) return false;
+    while (n % 2 == 0) n /= 2;
+    while (n % 3 == 0) n /= 3;
+    return n == 1;
+}
+
+struct Layout {
+    size_t bytes = 0;
+    size_t take(size_t n) {
+        size_t off = (bytes + 255) & ~size_t(255);
+        bytes = off + n;
+        return off;
+    }
+};
+
+// Offsets of every device array inside the arena.
+struct ArenaPlan {
+    size_t disp[2], mom[2], id[2], acc, key, rank, count, start, status;
+    size_t mesh[3], nyq[3], halo, tw_nm, tw_hm, twp_nm, tw_np, tw_hp, twp_np, g_pois, g_ic, atab;
+    size_t total;
+};
+
+constexpr int ATAB_N = 8192;
+constexpr double ATAB_AMIN = 0.004;
+
+ArenaPlan plan_arena(const pm_params& p, const lens_params& l, size_t es) {
+    (void)l;
+    ArenaPlan a{};
+    Layout L;
+    size_t n = (size_t)p.np * p.np * p.np;
+    size_t nm = (size_t)p.nm;
+    size_t nt = nm / TILE;
+    for (int b = 0; b < 2; ++b) {
+        a.disp[b] = L.take(3 * n * es);
+        a.mom[b] = L.take(3 * n * es);
+        a.id[b] = L.take(n * 4);
+    }
+    a.acc = L.take(3 * n * es);
+    a.key = L.take(n * 4);
+    a.rank = L.take(n * 4);
+    a.count = L.take(nt * nt * nt * 4);
+    a.start = L.take((nt * nt * nt + 1) * 4);
+    a.status = L.take(256);
+    for (int j = 0; j < 3; ++j) {
+        a.mesh[j] = L.take(nm * nm * nm * es);
+        a.nyq[j] = L.take(nm * nm * 2 * es);
+    }
+    a.halo = L.take(nt * nt * nt * HALO * es);
+    a.tw_nm = L.take(nm * 2 * es);
+    a.tw_hm = L.take(nm / 2 * 2 * es);
+    a.twp_nm = L.take((nm / 2 + 1) * 2 * es);
+    size_t np_ = (size_t)p.np;
+    a.tw_np = L.take(np_ * 2 * es);
+    a.tw_hp = L.take(np_ / 2 * 2 * es);
+    a.twp_np = L.take((np_ / 2 + 1) * 2 * es);
+    a.g_pois = L.take((3 * (nm / 2) * (nm / 2) + 1) * es);
+    a.g_ic = L.take((3 * (np_ / 2) * (np_ / 2) + 1) * es);
+    a.atab = L.take(2 * ATAB_N * es);
+    a.total = L.bytes;
+    return a;
+}
+
+int validate(const pm_params* p, const lens_params* l) {
+    if (!p || !l) return PM_EINVAL;
+    if (p->dtype != PM_F32 && p->dtype != PM_F64) return PM_EINVAL;
+    if (p->np < 16 || p->nm < 16 || p->np % 16 || p->nm % 16) return PM_EINVAL;
+    if (p->nm != p->np && p->nm != 2 * p->np) return PM_EINVAL;
+    if (!only_2_3(p->np) || !only_2_3(p->nm) || p->nm > 1024) return PM_EINVAL;
+    bool fft_ok = p->dtype == PM_F32 ? fft_supported<float>(p->nm) && fft_supported<float>(p->np)
+                                     : fft_supported<double>(p->nm) && fft_supported<double>(p->np);
+    if (!fft_ok) return PM_EINVAL;
+    if (!(p->box > 0) || !(p->omega_m > 0 && p->omega_m < 1) || !(p->h > 0) || !(p->sigma8 > 0))
+        return PM_EINVAL;
+    if (!(p->omega_b > 0 && p->omega_b < p->omega_m) || !(p->t_cmb > 0)) return PM_EINVAL;
+    if (l->npix < 16 || l->npix > 8192) return PM_EINVAL;
+    if (!(l->fov_deg > 0 && l->fov_deg <= 22.0)) return PM_EINVAL;
+    if (l->nsrc < 1 || l->nsrc > MAX_SRC || !l->z_src) return PM_EINVAL;
+    for (int s = 0; s < l->nsrc; ++s)
+        if (!(l->z_src[s] > 0 && l->z_src[s] < 20)) return PM_EINVAL;
+    return PM_OK;
+}
+
+#define HIPCHK(x)                                  \
+    do {                                           \
+        if ((x) != hipSuccess) return PM_EDEVICE;  \
+    } while (0)
+
+// Optional per-kernel timing with HIP events on the simulation's stream.
+// Events come from a pool created when profiling is switched on, so the
+// timed loop creates nothing.
+struct Prof {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    struct Rec { int name; hipEvent_t a, b; };
+    std::vector<Rec> recs;
+    std::vector<std::string> names;
+    std::vector<double> ms;
+    std::vector<long> cnt;
+    hipStream_t st = nullptr;
+    int cur = -1;
+
+    int name_id(const char* n) {
+        for (size_t i = 0; i < names.size(); ++i)
+            if (names[i] == n) return (int)i;
+        names.emplace_back(n);
+        ms.push_back(0.0);
+        cnt.push_back(0);
+        return (int)names.size() - 1;
+    }
+    void begin(const char* n) {
+        cur = -1;
+        if (!on || used + 2 > pool.size()) return;
+        cur = (int)recs.size();
+        recs.push_back({name_id(n), pool[used], pool[used + 1]});
+        used += 2;
+        (void)hipEventRecord(recs.back().a, st);
+    }
+    void end() {
+        if (cur < 0) return;
+        (void)hipEventRecord(recs[cur].b, st);
+        cur = -1;
+    }
+    int enable(bool e, hipStream_t s) {
+        st = s;
+        if (e && pool.empty()) {
+            pool.resize(16384);  // 8192 launches
+            for (auto& ev : pool)
+                if (hipEventCreate(&ev) != hipSuccess) return PM_EDEVICE;
+        }
+        on = e;
+        return PM_OK;
+    }
+    int resolve() {
+        if (recs.empty()) return PM_OK;
+        if (hipStreamSynchronize(st) != hipSuccess) return PM_EDEVICE;
+        for (auto& r : recs) {
+            float t = 0.f;
+            if (hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) return PM_EDEVICE;
+            ms[r.name] += t;
+            cnt[r.name] += 1;
+        }
+        recs.clear();
+        used = 0;
+        return PM_OK;
+    }
+    ~Prof() {
+        for (auto& ev : pool) (void)hipEventDestroy(ev);
+    }
+};
+
+struct ProfScope {
+    Prof& p;
+    ProfScope(Prof& pr, const char* n) : p(pr) { p.begin(n); }
+    ~ProfScope() { p.end(); }
+};
+
+struct SimBase {
+    Prof prof;
+    virtual ~SimBase() {}
+    virtual int init_ic(const void* noise, double a0) = 0;
+    virtual int step(double a0, double a1) = 0;
+    virtual int lens(double a0, double a1, void* kappa) = 0;
+    virtual int get_state(void* x, void* p, double* a) = 0;
+    virtual int set_state(const void* x, const void* p, double a) = 0;
+    virtual int get_force(void* rho, void* fm, void* acc) = 0;
+    virtual int sync() = 0;
+    virtual int background(double a, double out[3]) const = 0;
+    virtual hipStream_t stream() const = 0;
+};
+
+template <class T> struct Sim final : SimBase {
+    pm_params P{};
+    int npix = 0, nsrc = 0;
+    double fov = 0;
+    std::vector<double> zsrc, chisrc;
+    HostCosmo cosmo;
+    Geo geo{};
+    hipStream_t st = nullptr;
+    char* arena = nullptr;
+    ArenaPlan ap{};
+    Parts<T> cur{}, alt{};
+    SortBufs sb{};
+    uint32_t* status = nullptr;
+    T* mesh[3]{};
+    cx<T>* nyq[3]{};
+    T* halo = nullptr;
+    cx<T>*tw_nm, *tw_hm, *twp_nm, *tw_np, *tw_hp, *twp_np;
+    T *g_pois, *g_ic, *atab;
+    double dchi_tab = 0;
+    double a_cur = -1.0;
+    double cell = 0;  // mesh cell, Mpc/h
+    int ntiles = 0;
+
+    ~Sim() override {
+        if (arena) (void)hipFree(arena);
+    }
+
+    template <class U> U* at(size_t off) { return reinterpret_cast<U*>(arena + off); }
+
+    int create(const pm_params* p, const lens_params* l, void* stream) {
+        P = *p;
+        npix = l->npix;
+        nsrc = l->nsrc;
+        fov = l->fov_deg;
+        zsrc.assign(l->z_src, l->z_src + l->nsrc);
+        st = reinterpret_cast<hipStream_t>(stream);
+        cosmo.init(p->omega_m, p->h, p->n_s, p->sigma8, p->omega_b, p->t_cmb);
+        for (double z : zsrc) chisrc.push_back(cosmo.chi_of_z(z));
+        geo.np = p->np;
+        geo.nm = p->nm;
+        geo.B = p->nm / p->np;
+        geo.nt = p->nm / TILE;
+        geo.npart = (long)p->np * p->np * p->np;
+        ntiles = geo.nt * geo.nt * geo.nt;
+        cell = p->box / p->nm;
+        ap = plan_arena(*p, *l, sizeof(T));
+        if (hipMalloc(&arena, ap.total) != hipSuccess) {
+            arena = nullptr;
+            (void)hipGetLastError();
+            return PM_ENOMEM;
+        }
+        for (int b = 0; b < 2; ++b) {
+            Parts<T>& q = b ? alt : cur;
+            q.disp = at<T>(ap.disp[b]);
+            q.mom = at<T>(ap.mom[b]);
+            q.id = at<uint32_t>(ap.id[b]);
+            q.acc = at<T>(ap.acc);
+        }
+        sb.key = at<uint32_t>(ap.key);
+        sb.rank = at<uint32_t>(ap.rank);
+        sb.count = at<uint32_t>(ap.count);
+        sb.start = at<uint32_t>(ap.start);
+        status = at<uint32_t>(ap.status);
+        for (int j = 0; j < 3; ++j) {
+            mesh[j] = at<T>(ap.mesh[j]);
+            nyq[j] = at<cx<T>>(ap.nyq[j]);
+        }
+        halo = at<T>(ap.halo);
+        tw_nm = at<cx<T>>(ap.tw_nm);
+        tw_hm = at<cx<T>>(ap.tw_hm);
+        twp_nm = at<cx<T>>(ap.twp_nm);
+        tw_np = at<cx<T>>(ap.tw_np);
+        tw_hp = at<cx<T>>(ap.tw_hp);
+        twp_np = at<cx<T>>(ap.twp_np);
+        g_pois = at<T>(ap.g_pois);
+        g_ic = at<T>(ap.g_ic);
+        atab = at<T>(ap.atab);
+        return upload_tables();
+    }
+
+    static void twiddles(std::vector<T>& v, int n, int count) {
+        // exp(-2 pi i t / n), t < count
+        v.resize(2 * count);
+        for (int t = 0; t < count; ++t) {
+            double ang = -2.0 * PI * (double)t / (double)n;
+            v[2 * t] = (T)std::cos(ang);
+            v[2 * t + 1] = (T)std::sin(ang);
+        }
+    }
+
+    int upload(size_t off, const std::vector<T>& v) {
+        HIPCHK(hipMemcpy(arena + off, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+        return PM_OK;
+    }
+
+    int upload_tables() {
+        std::vector<T> v;
+        int rc;
+        const int nm = P.nm, np = P.np;
+        twiddles(v, nm, nm);
+        if ((rc = upload(ap.tw_nm, v))) return rc;
+        twiddles(v, nm / 2, nm / 2);
+        if ((rc = upload(ap.tw_hm, v))) return rc;
+        twiddles(v, nm, nm / 2 + 1);
+        if ((rc = upload(ap.twp_nm, v))) return rc;
+        twiddles(v, np, np);
+        if ((rc = upload(ap.tw_np, v))) return rc;
+        twiddles(v, np / 2, np / 2);
+        if ((rc = upload(ap.tw_hp, v))) return rc;
+        twiddles(v, np, np / 2 + 1);
+        if ((rc = upload(ap.twp_np, v))) return rc;
+        // Poisson: f_hat_j = i n_j G[n^2] delta_hat in cell units, including the
+        // 1/Nm^3 of the unnormalised inverse: G = 1 / (2 pi n^2 Nm^2)
+        {
+            int nmax = 3 * (nm / 2) * (nm / 2);
+            v.assign(nmax + 1, T(0));
+            for (int q = 1; q <= nmax; ++q) v[q] = (T)(1.0 / (2.0 * PI * q * (double)nm * nm));
+            if ((rc = upload(ap.g_pois, v))) return rc;
+        }
+        // Zel'dovich: s_hat_j (mesh cells) = i n_j G delta-per-noise with
+        // G = Nm sqrt(P(k) Np^3 / L^3) / (2 pi n^2 Np^3), k = 2 pi |n| / L
+        {
+            int nmax = 3 * (np / 2) * (np / 2);
+            v.assign(nmax + 1, T(0));
+            double L = P.box, np3 = (double)np * np * np;
+            for (int q = 1; q <= nmax; ++q) {
+                double k = 2.0 * PI * std::sqrt((double)q) / L;
+                double amp = std::sqrt(cosmo.pk(k) * np3 / (L * L * L));
+                v[q] = (T)((double)nm * amp / (2.0 * PI * q * np3));
+            }
+            if ((rc = upload(ap.g_ic, v))) return rc;
+        }
+        // a(chi) and da/dchi on a uniform chi grid for the lens weights
+        {
+            double chimax = cosmo.chi(ATAB_AMIN);
+            dchi_tab = chimax / (ATAB_N - 2);
+            v.resize(2 * ATAB_N);
+            for (int k = 0; k < ATAB_N; ++k) {
+                double a = cosmo.a_of_chi(k * dchi_tab);
+                v[2 * k] = (T)a;
+                v[2 * k + 1] = (T)cosmo.dadchi(a);
+            }
+            if ((rc = upload(ap.atab, v))) return rc;
+        }
+        launch_fill_u32(status, 0u, 1, st);
+        HIPCHK(hipStreamSynchronize(st));
+        return PM_OK;
+    }
+
+    // ---- pipeline pieces ---------------------------------------------------
+    void sort(T kick, T drift, int mode) {
+        launch_fill_u32(sb.count, 0u, ntiles, st);
+        { ProfScope ps(prof, "kick_drift_key"); launch_kick_drift_key<T>(cur, sb, geo, kick, drift, mode, status, st); }
+        { ProfScope ps(prof, "scan"); launch_scan(sb.count, sb.start, ntiles, st); }
+        { ProfScope ps(prof, "scatter"); launch_scatter<T>(cur, alt, sb, geo, st); }
+        std::swap(cur.disp, alt.disp);
+        std::swap(cur.mom, alt.mom);
+        std::swap(cur.id, alt.id);
+    }
+
+    void fft_forward_grad(int n, const T* G, const cx<T>* tw, const cx<T>* twh, const cx<T>* twp) {
+        { ProfScope ps(prof, "fft_r2c_axis2"); fft_r2c_rows<T>(n, mesh[0], nyq[0], twh, twp, st); }
+        { ProfScope ps(prof, "fft_c2c_axis1_fwd");
+          fft_c2c_axis1<T>(n, 1, reinterpret_cast<cx<T>*>(mesh[0]), nyq[0], tw, st); }
+        PtrTriple om{{mesh[0], mesh[1], mesh[2]}}, on{{nyq[0], nyq[1], nyq[2]}};
+        { ProfScope ps(prof, "fft_grad_axis0");
+          fft_grad_axis0<T>(n, reinterpret_cast<cx<T>*>(mesh[0]), nyq[0], om, on, tw, G, st); }
+        for (int j = 0; j < 3; ++j) {
+            ProfScope ps(prof, "fft_c2c_axis1_inv");
+            fft_c2c_axis1<T>(n, -1, reinterpret_cast<cx<T>*>(mesh[j]), nyq[j], tw, st);
+        }
+        for (int j = 0; j < 3; ++j) {
+            ProfScope ps(prof, "fft_c2r_axis2");
+            fft_c2r_rows<T>(n, mesh[j], nyq[j], twh, twp, st);
+        }
+    }
+
+    void paint() {
+        T mass = (T)std::pow((double)geo.B, 3);
+        ProfScope ps(prof, "paint");
+        launch_paint<T>(cur, sb, geo, mass, mesh[0], halo, st);
+    }
+
+    void force(T kick2, int do_kick) {
+        paint();
+        fft_forward_grad(P.nm, g_pois, tw_nm, tw_hm, twp_nm);
+        ProfScope ps(prof, "readout_kick");
+        launch_readout<T>(cur, sb, geo, mesh[0], mesh[1], mesh[2], kick2, do_kick, status, st);
+    }
+
+    int check_launch() {
+        return hipGetLastError() == hipSuccess ? PM_OK : PM_EDEVICE;
+    }
+
+    // ---- API ------------------------------------------------------------
+    int init_ic(const void* noise, double a0) override {
+        if (!noise || !(a0 > 0 && a0 <= 1)) return PM_EINVAL;
+        double chi0 = cosmo.chi(a0);
+        for (double c : chisrc)
+            if (c > chi0) return PM_EINVAL;
+        const int np = P.np;
+        size_t n = (size_t)np * np * np;
+        HIPCHK(hipMemcpyAsync(mesh[0], noise, n * sizeof(T), hipMemcpyDeviceToDevice, st));
+        fft_forward_grad(np, g_ic, tw_np, tw_hp, twp_np);
+        launch_init_ic<T>(cur, geo, mesh[0], mesh[1], mesh[2], (T)cosmo.D(a0), (T)cosmo.gp(a0), st);
+        sort(T(0), T(0), 0);
+        force(T(0), 0);
+        a_cur = a0;
+        return check_launch();
+    }
+
+    int step(double a0, double a1) override {
+        if (a_cur < 0 || std::fabs(a0 - a_cur) > 1e-12 * std::fabs(a_cur) + 1e-15) return PM_ESTATE;
+        if (!(a1 > 0 && a1 <= 1.5)) return PM_EINVAL;
+        double ah = 0.5 * (a0 + a1);
+        T k1 = (T)cosmo.kick(a0, ah, a0);
+        T dr = (T)cosmo.drift(a0, a1, ah);
+        T k2 = (T)cosmo.kick(ah, a1, a1);
+        sort(k1, dr, MODE_KICK | MODE_DRIFT);
+        force(k2, 1);
+        a_cur = a1;
+        return check_launch();
+    }
+
+    int lens(double a0, double a1, void* kappa) override {
+        if (!kappa) return PM_EINVAL;
+        if (a_cur < 0 || std::fabs(a1 - a_cur) > 1e-12 * std::fabs(a_cur) + 1e-15) return PM_ESTATE;
+        LensArgs<T> la{};
+        la.npix = npix;
+        la.nsrc = nsrc;
+        la.cell = (T)cell;
+        double chi_far = cosmo.chi(a0), chi_near = cosmo.chi(a1);
+        la.chi_near = (T)chi_near;
+        la.chi_far = (T)chi_far;
+        double dth = fov * PI / 180.0 / npix;
+        la.inv_dtheta = (T)(1.0 / dth);
+        double vp = std::pow(P.box / P.np, 3);
+        la.wbase = (T)(1.5 * P.omega_m / (C_H0 * C_H0) * vp / (dth * dth));
+        for (int s = 0; s < nsrc; ++s) la.chi_src[s] = (T)chisrc[s];
+        la.atab = atab;
+        la.ntab = ATAB_N;
+        la.dchi = (T)dchi_tab;
+        T* k = reinterpret_cast<T*>(kappa);
+        { ProfScope ps(prof, "lens_paint"); launch_lens<T>(cur, geo, la, k, st); }
+        T mv[MAX_SRC];
+        bool any = false;
+        for (int s = 0; s < nsrc; ++s) {
+            mv[s] = (T)cosmo.shell_mean(chi_near, chi_far, chisrc[s]);
+            any = any || mv[s] != T(0);
+        }
+        if (any) { ProfScope ps(prof, "lens_mean"); launch_add_maps<T>(k, npix, nsrc, mv, st); }
+        return check_launch();
+    }
+
+    int get_state(void* x, void* p, double* a) override {
+        if (a) *a = a_cur;
+        if (a_cur < 0) return PM_ESTATE;
+        if (x || p)
+            launch_get_state<T>(cur, geo, (T)cell, reinterpret_cast<T*>(x), reinterpret_cast<T*>(p),
+                                nullptr, st);
+        return check_launch();
+    }
+
+    int set_state(const void* x, const void* p, double a) override {
+        if (!x || !p || !(a > 0)) return PM_EINVAL;
+        launch_set_state<T>(cur, geo, (T)cell, reinterpret_cast<const T*>(x),
+                            reinterpret_cast<const T*>(p), st);
+        sort(T(0), T(0), 0);
+        force(T(0), 0);
+        a_cur = a;
+        return check_launch();
+    }
+
+    int get_force(void* rho, void* fm, void* acc) override {
+        if (a_cur < 0) return PM_ESTATE;
+        size_t n3 = (size_t)P.nm * P.nm * P.nm;
+        paint();
+        if (rho) HIPCHK(hipMemcpyAsync(rho, mesh[0], n3 * sizeof(T), hipMemcpyDeviceToDevice, st));
+        fft_forward_grad(P.nm, g_pois, tw_nm, tw_hm, twp_nm);
+        launch_readout<T>(cur, sb, geo, mesh[0], mesh[1], mesh[2], T(0), 0, status, st);
+        if (fm) {
+            // force meshes are in cell units; scale to Mpc/h into the caller's buffer
+            for (int j = 0; j < 3; ++j)
+                launch_scale_copy<T>(reinterpret_cast<T*>(fm) + j * n3, mesh[j], (T)cell, (long)n3, st);
+        }
+        if (acc)
+            launch_get_state<T>(cur, geo, (T)cell, nullptr, nullptr, reinterpret_cast<T*>(acc), st);
+        return check_launch();
+    }
+
+    int sync() override {
+        HIPCHK(hipStreamSynchronize(st));
+        uint32_t s = 0;
+        HIPCHK(hipMemcpy(&s, status, 4, hipMemcpyDeviceToHost));
+        return s ? PM_ENONFINITE : PM_OK;
+    }
+
+    hipStream_t stream() const override { return st; }
+
+    int background(double a, double out[3]) const override {
+        out[0] = cosmo.D(a);
+        out[1] = cosmo.gp(a);
+        out[2] = cosmo.chi(a);
+        return PM_OK;
+    }
+};
+
+}  // namespace
+
+struct pm_sim {
+    std::unique_ptr<SimBase> impl;
+    int dtype;
+};
+
+extern "C" {
+
+size_t pm_footprint(const pm_params* p, const lens_params* l) {
+    if (validate(p, l) != PM_OK) return 0;
+    return plan_arena(*p, *l, p->dtype == PM_F64 ? 8 : 4).total;
+}
+
+int pm_create(const pm_params* p, const lens_params* l, void* hip_stream, pm_sim** out) {
+    if (!out) return PM_EINVAL;
+    *out = nullptr;
+    int rc = validate(p, l);
+    if (rc) return rc;
+    pm_sim* s = new (std::nothrow) pm_sim;
+    if (!s) return PM_ENOMEM;
+    s->dtype = p->dtype;
+    if (p->dtype == PM_F32) {
+        auto* impl = new (std::nothrow) Sim<float>;
+        if (!impl) { delete s; return PM_ENOMEM; }
+        s->impl.reset(impl);
+        rc = impl->create(p, l, hip_stream);
+    } else {
+        auto* impl = new (std::nothrow) Sim<double>;
+        if (!impl) { delete s; return PM_ENOMEM; }
+        s->impl.reset(impl);
+        rc = impl->create(p, l, hip_stream);
+    }
+    if (rc) {
+        delete s;
+        return rc;
+    }
+    *out = s;
+    return PM_OK;
+}
+
+int pm_destroy(pm_sim* sim) {
+    if (!sim) return PM_EINVAL;
+    delete sim;
+    return PM_OK;
+}
+
+int pm_init_ic(pm_sim* sim, const void* noise, double a0) {
+    return sim ? sim->impl->init_ic(noise, a0) : PM_EINVAL;
+}
+int pm_step(pm_sim* sim, double a0, double a1) { return sim ? sim->impl->step(a0, a1) : PM_EINVAL; }
+int lens_project(pm_sim* sim, double a0, double a1, void* kappa) {
+    return sim ? sim->impl->lens(a0, a1, kappa) : PM_EINVAL;
+}
+int pm_get_state(pm_sim* sim, void* x, void* p, double* a) {
+    return sim ? sim->impl->get_state(x, p, a) : PM_EINVAL;
+}
+int pm_set_state(pm_sim* sim, const void* x, const void* p, double a) {
+    return sim ? sim->impl->set_state(x, p, a) : PM_EINVAL;
+}
+int pm_get_force(pm_sim* sim, void* rho, void* fm, void* acc) {
+    return sim ? sim->impl->get_force(rho, fm, acc) : PM_EINVAL;
+}
+int pm_sync(pm_sim* sim) { return sim ? sim->impl->sync() : PM_EINVAL; }
+int pm_background(const pm_sim* sim, double a, double out[3]) {
+    return sim && out ? sim->impl->background(a, out) : PM_EINVAL;
+}
+
+int pm_profile(pm_sim* sim, int enable) {
+    if (!sim) return PM_EINVAL;
+    return sim->impl->prof.enable(enable != 0, sim->impl->stream());
+}
+
+int pm_profile_read(pm_sim* sim, int max_kernels, char* names, double* ms_total, long* counts,
+                    int* n_out) {
+    if (!sim || !n_out || max_kernels < 0) return PM_EINVAL;
+    Prof& p = sim->impl->prof;
+    int rc = p.resolve();
+    if (rc) return rc;
+    int n = (int)p.names.size();
+    *n_out = n;
+    for (int i = 0; i < n && i < max_kernels; ++i) {
+        if (names) {
+            std::strncpy(names + 32 * i, p.names[i].c_str(), 31);
+            names[32 * i + 31] = 0;
+        }
+        if (ms_total) ms_total[i] = p.ms[i];
+        if (counts) counts[i] = p.cnt[i];
+        p.ms[i] = 0.0;
+        p.cnt[i] = 0;
+    }
+    return PM_OK;
+}
+
+const char* pm_strerror(int code) {
+    switch (code) {
+        case PM_OK: return "ok";
+        case PM_EINVAL: return "invalid argument or unsupported size";
+        case PM_ENOMEM: return "device arena could not be allocated";
+        case PM_EDEVICE: return "HIP runtime error";
+        case PM_ESTATE: return "simulation is not in the required state";
+        case PM_ENONFINITE: return "non-finite particle position";
+        case PM_EFULL: return "batch has no free slot";
+        default: return "unknown error";
+    }
+}
+
+}  // extern "C"

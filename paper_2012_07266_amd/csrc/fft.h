@@ -1,0 +1,37 @@
+// Host entry points of the LDS-staged FFT passes (see fft.hip).
+#pragma once
+#include "common.h"
+
+namespace ml {
+
+struct PtrTriple {
+    void* p[3];
+};
+
+// true when an n^3 mesh can be transformed in precision T
+template <class T> bool fft_supported(int n);
+
+// r2c along axis 2 of an n^3 real mesh, in place: io holds n*n rows of n reals
+// on input and n*n rows of n/2 complex (k2 < n/2) on output; nyq gets the
+// k2 = n/2 plane [n][n].  tw_h: exp(-2 pi i t/(n/2)), t < n/2;
+// tw_post: exp(-2 pi i k/n), k <= n/2.
+template <class T>
+void fft_r2c_rows(int n, T* io, cx<T>* nyq, const cx<T>* tw_h, const cx<T>* tw_post,
+                  hipStream_t st);
+// Unnormalised c2r along axis 2, in place (inverse of fft_r2c_rows times n).
+template <class T>
+void fft_c2r_rows(int n, T* io, const cx<T>* nyq, const cx<T>* tw_h, const cx<T>* tw_post,
+                  hipStream_t st);
+// c2c along axis 1 (sign +1 forward, -1 unnormalised inverse) on main and nyq.
+template <class T>
+void fft_c2c_axis1(int n, int sign, cx<T>* main, cx<T>* nyq, const cx<T>* tw, hipStream_t st);
+// c2c along axis 0 on main and nyq.
+template <class T>
+void fft_c2c_axis0(int n, int sign, cx<T>* main, cx<T>* nyq, const cx<T>* tw, hipStream_t st);
+// Fused axis-0 pass: forward, times i n_j G[|n|^2] (zero where |n_j| = n/2),
+// inverse, for j = 0..2.  out_main/out_nyq hold the three destinations.
+template <class T>
+void fft_grad_axis0(int n, cx<T>* main_in, cx<T>* nyq_in, PtrTriple out_main, PtrTriple out_nyq,
+                    const cx<T>* tw, const T* G, hipStream_t st);
+
+}  // namespace ml

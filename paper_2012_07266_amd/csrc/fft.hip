@@ -1,0 +1,464 @@
+// LDS-staged Stockham FFT passes for 3D real meshes on gfx950, and the
+// fused Fourier Poisson/gradient pass of the particle-mesh force.
+//
+// A real Nm^3 mesh (C order, last axis contiguous) is transformed in three
+// 1D passes.  Its half spectrum is stored as
+//   main [Nm][Nm][Nm/2]  complex, k2 = 0 .. Nm/2-1, in the same memory as
+//                        the real mesh (rows of Nm reals = Nm/2 complex),
+//   nyq  [Nm][Nm]        complex, the k2 = Nm/2 plane, in a side buffer,
+// so every row of the main block stays 2 KB aligned for Nm = 512.
+//
+//   pass 1  r2c along axis 2: one row of Nm reals is packed into Nm/2
+//           complex values, transformed, and split into Nm/2+1 outputs.
+//   pass 2  c2c along axis 1 on main and nyq.
+//   pass 3  fused along axis 0: forward transform, multiply by
+//           i n_j G(|n|^2) for the three gradient components, inverse
+//           transform each, write three spectra (one over the input).
+//   pass 4  inverse c2c along axis 1 (three spectra).
+//   pass 5  c2r along axis 2 (three spectra -> three real meshes in place).
+//
+// Each workgroup holds W pencils of one pass in LDS as [N][W+1] complex
+// (the +1 pad keeps both row loads and column butterflies free of bank
+// conflicts) and runs a mixed-radix (8, 4, 2, 3) Stockham transform in
+// place: every stage reads its butterfly inputs into registers, barriers,
+// and writes its outputs in natural-order Stockham positions.
+#include "fft.h"
+
+namespace ml {
+
+constexpr int radix_of(int n) { return n % 8 == 0 ? 8 : n % 4 == 0 ? 4 : n % 2 == 0 ? 2 : 3; }
+constexpr int plan_radix(int n, int s) {
+    for (int i = 0; i < s; ++i) n /= radix_of(n);
+    return radix_of(n);
+}
+
+constexpr int NT = 256;  // threads per workgroup of every FFT kernel
+
+// One Stockham stage of radix R at span P (product of earlier radices).
+template <class T, int N, int W, int R, int P, int S>
+__device__ __forceinline__ void fft_stage(cx<T>* buf, const cx<T>* tw, int tid) {
+    constexpr int LD = W + 1;
+    constexpr int NB = N / R;
+    constexpr int TOT = NB * W;
+    constexpr int IT = (TOT + NT - 1) / NT;
+    cx<T> u[IT][R];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        int b = tid + it * NT;
+        if (TOT % NT == 0 || b < TOT) {
+            int w = b % W, i = b / W;
+#pragma unroll
+            for (int r = 0; r < R; ++r) u[it][r] = buf[(i + r * NB) * LD + w];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        int b = tid + it * NT;
+        if (TOT % NT == 0 || b < TOT) {
+            int w = b % W, i = b / W;
+            int k = i % P;
+            if constexpr (P > 1) {
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    cx<T> t = tw[r * k * (N / (P * R))];
+                    if constexpr (S < 0) t.im = -t.im;
+                    u[it][r] = cmul(u[it][r], t);
+                }
+            }
+            dft<R, S>(u[it]);
+            int j = (i - k) * R + k;
+#pragma unroll
+            for (int r = 0; r < R; ++r) buf[(j + r * P) * LD + w] = u[it][r];
+        }
+    }
+    __syncthreads();
+}
+
+template <class T, int N, int W, int S, int STAGE = 0, int P = 1>
+__device__ __forceinline__ void fft_lds(cx<T>* buf, const cx<T>* tw, int tid) {
+    if constexpr (P < N) {
+        constexpr int R = plan_radix(N, STAGE);
+        fft_stage<T, N, W, R, P, S>(buf, tw, tid);
+        fft_lds<T, N, W, S, STAGE + 1, P * R>(buf, tw, tid);
+    }
+}
+
+template <class T, int N>
+__device__ __forceinline__ void load_twiddles(cx<T>* tw_s, const cx<T>* tw, int tid) {
+    for (int t = tid; t < N; t += NT) tw_s[t] = tw[t];
+}
+
+// ---------------------------------------------------------------------------
+// pass 1: r2c along the contiguous axis.  H = Nm/2.
+// `io` holds nrows rows of 2H reals on input and H complex on output.
+// ---------------------------------------------------------------------------
+template <class T, int H, int W>
+__global__ __launch_bounds__(NT) void k_r2c_rows(T* io, cx<T>* nyq, const cx<T>* tw_h,
+                                                 const cx<T>* tw_post) {
+    __shared__ cx<T> buf[H * (W + 1)];
+    __shared__ cx<T> tws[H];
+    constexpr int LD = W + 1;
+    const int tid = threadIdx.x;
+    const size_t r0 = (size_t)blockIdx.x * W;
+    load_twiddles<T, H>(tws, tw_h, tid);
+    const cx<T>* in = reinterpret_cast<const cx<T>*>(io) + r0 * H;
+    for (int f = tid; f < W * H; f += NT) {
+        int w = f / H, n = f % H;
+        buf[n * LD + w] = in[(size_t)w * H + n];
+    }
+    __syncthreads();
+    fft_lds<T, H, W, 1>(buf, tws, tid);
+    cx<T>* out = reinterpret_cast<cx<T>*>(io) + r0 * H;
+    constexpr int HK = H / 2 + 1;
+    for (int f = tid; f < W * HK; f += NT) {
+        int w = f / HK, k = f % HK;
+        cx<T> a = buf[k * LD + w];
+        cx<T> b = conj(buf[((H - k) % H) * LD + w]);
+        cx<T> ze = scale(a + b, T(0.5));
+        cx<T> d = scale(a - b, T(0.5));
+        cx<T> zo = {d.im, -d.re};  // (a - b) / (2i)
+        cx<T> tzo = cmul(tw_post[k], zo);
+        cx<T> xk = ze + tzo;
+        cx<T> xm = conj(ze - tzo);
+        if (k == 0) {
+            out[(size_t)w * H] = xk;
+            nyq[r0 + w] = xm;
+        } else {
+            out[(size_t)w * H + k] = xk;
+            if (H - k != k) out[(size_t)w * H + (H - k)] = xm;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// pass 5: c2r along the contiguous axis (unnormalised inverse).
+// ---------------------------------------------------------------------------
+template <class T, int H, int W>
+__global__ __launch_bounds__(NT) void k_c2r_rows(T* io, const cx<T>* nyq, const cx<T>* tw_h,
+                                                 const cx<T>* tw_post) {
+    __shared__ cx<T> buf[H * (W + 1)];
+    __shared__ cx<T> tws[H];
+    constexpr int LD = W + 1;
+    const int tid = threadIdx.x;
+    const size_t r0 = (size_t)blockIdx.x * W;
+    load_twiddles<T, H>(tws, tw_h, tid);
+    const cx<T>* in = reinterpret_cast<const cx<T>*>(io) + r0 * H;
+    constexpr int HK = H / 2 + 1;
+    for (int f = tid; f < W * HK; f += NT) {
+        int w = f / HK, k = f % HK;
+        cx<T> xk, xm;
+        if (k == 0) {
+            xk = mk<T>(in[(size_t)w * H].re, T(0));
+            xm = mk<T>(nyq[r0 + w].re, T(0));
+        } else {
+            xk = in[(size_t)w * H + k];
+            xm = in[(size_t)w * H + (H - k)];
+        }
+        cx<T> ze = xk + conj(xm);
+        cx<T> d = xk - conj(xm);
+        cx<T> tp = conj(tw_post[k]);  // exp(+2 pi i k / Nm)
+        cx<T> q = cmul(d, tp);
+        cx<T> iq = {-q.im, q.re};
+        buf[k * LD + w] = ze + iq;
+        if (k != 0 && H - k != k) {
+            cx<T> iqc = {q.im, q.re};  // i * conj(q)
+            buf[(H - k) * LD + w] = conj(ze) + iqc;
+        }
+    }
+    __syncthreads();
+    fft_lds<T, H, W, -1>(buf, tws, tid);
+    cx<T>* out = reinterpret_cast<cx<T>*>(io) + r0 * H;
+    for (int f = tid; f < W * H; f += NT) {
+        int w = f / H, n = f % H;
+        out[(size_t)w * H + n] = buf[n * LD + w];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// passes 2 and 4: c2c along a strided axis.  A "view" describes pencils of
+// length N: element n of pencil w of workgroup g sits at
+//   strided: base(g) + n*C + w,  base = (g / (C/W)) * N*C + (g % (C/W)) * W
+//   contig : g*W*N + w*N + n
+// Workgroups [0, g_main) work on view a, the rest on view b.
+// ---------------------------------------------------------------------------
+struct ViewDesc {
+    void* ptr;
+    long C;
+    int contig;
+    int n_wg;
+};
+
+template <class T, int N, int W>
+__device__ __forceinline__ long view_offset(const ViewDesc& v, int g, int w, int n) {
+    if (v.contig) return ((long)g * W + w) * N + n;
+    long cw = v.C / W;
+    long base = (g / cw) * (long)N * v.C + (g % cw) * W;
+    return base + (long)n * v.C + w;
+}
+
+template <class T, int N, int W>
+__device__ __forceinline__ void view_load(cx<T>* buf, const ViewDesc& v, int g, int tid) {
+    constexpr int LD = W + 1;
+    const cx<T>* p = reinterpret_cast<const cx<T>*>(v.ptr);
+    if (v.contig) {
+        for (int f = tid; f < W * N; f += NT) {
+            int w = f / N, n = f % N;
+            buf[n * LD + w] = p[view_offset<T, N, W>(v, g, w, n)];
+        }
+    } else {
+        for (int f = tid; f < W * N; f += NT) {
+            int n = f / W, w = f % W;
+            buf[n * LD + w] = p[view_offset<T, N, W>(v, g, w, n)];
+        }
+    }
+}
+
+template <class T, int N, int W>
+__device__ __forceinline__ void view_store(const cx<T>* buf, void* dst, const ViewDesc& v, int g,
+                                           int tid) {
+    constexpr int LD = W + 1;
+    cx<T>* p = reinterpret_cast<cx<T>*>(dst);
+    if (v.contig) {
+        for (int f = tid; f < W * N; f += NT) {
+            int w = f / N, n = f % N;
+            p[view_offset<T, N, W>(v, g, w, n)] = buf[n * LD + w];
+        }
+    } else {
+        for (int f = tid; f < W * N; f += NT) {
+            int n = f / W, w = f % W;
+            p[view_offset<T, N, W>(v, g, w, n)] = buf[n * LD + w];
+        }
+    }
+}
+
+template <class T, int N, int W, int S>
+__global__ __launch_bounds__(NT) void k_c2c_view(ViewDesc va, ViewDesc vb, const cx<T>* tw) {
+    __shared__ cx<T> buf[N * (W + 1)];
+    __shared__ cx<T> tws[N];
+    const int tid = threadIdx.x;
+    int g = blockIdx.x;
+    const ViewDesc& v = g < va.n_wg ? va : vb;
+    if (g >= va.n_wg) g -= va.n_wg;
+    load_twiddles<T, N>(tws, tw, tid);
+    view_load<T, N, W>(buf, v, g, tid);
+    __syncthreads();
+    fft_lds<T, N, W, S>(buf, tws, tid);
+    view_store<T, N, W>(buf, v.ptr, v, g, tid);
+}
+
+// ---------------------------------------------------------------------------
+// pass 3: fused outer-axis pass.  Forward FFT of W pencils along axis 0,
+// then for j = 0, 1, 2: multiply by m_j = i n_j G[n0^2+n1^2+n2^2] (zero on
+// the plane |n_j| = N/2), inverse FFT, store to out_j.  The view's column c
+// maps to (k1, k2) = (c / (N/2), c % (N/2)) on main, (c, N/2) on nyq.
+// out[j] are the bases of the three spectra (main or nyq part, matching va
+// or vb); out[0] may equal the input.
+// ---------------------------------------------------------------------------
+template <class T, int N, int W>
+__global__ __launch_bounds__(NT) void k_grad_x0(ViewDesc va, ViewDesc vb, PtrTriple outa,
+                                                PtrTriple outb, const cx<T>* tw, const T* G) {
+    __shared__ cx<T> buf[N * (W + 1)];
+    __shared__ cx<T> tws[N];
+    constexpr int LD = W + 1;
+    constexpr int HN = N / 2;
+    const int tid = threadIdx.x;
+    int g = blockIdx.x;
+    const bool is_a = g < va.n_wg;
+    const ViewDesc& v = is_a ? va : vb;
+    const PtrTriple& out = is_a ? outa : outb;
+    if (!is_a) g -= va.n_wg;
+    load_twiddles<T, N>(tws, tw, tid);
+    view_load<T, N, W>(buf, v, g, tid);
+    __syncthreads();
+    fft_lds<T, N, W, 1>(buf, tws, tid);
+
+    // first inverse stage: radix R0 at span 1, no twiddles
+    constexpr int R0 = plan_radix(N, 0);
+    constexpr int NB = N / R0;
+    constexpr int TOT = NB * W;
+    constexpr int IT = (TOT + NT - 1) / NT;
+    cx<T> spec[IT][R0];
+    T gv[IT][R0];
+    int n0v[IT][R0], n1v[IT], n2v[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        int b = tid + it * NT;
+        if (TOT % NT == 0 || b < TOT) {
+            int w = b % W, i = b / W;
+            long c = (long)g * W + w;  // column within the view (a-range is 1)
+            int k1, k2;
+            if (is_a) { k1 = (int)(c / HN); k2 = (int)(c % HN); }
+            else      { k1 = (int)c;        k2 = HN; }
+            int n1 = k1 <= HN ? k1 : k1 - N;
+            n1v[it] = n1;
+            n2v[it] = k2;
+#pragma unroll
+            for (int r = 0; r < R0; ++r) {
+                int k0 = i + r * NB;
+                int n0 = k0 <= HN ? k0 : k0 - N;
+                spec[it][r] = buf[(i + r * NB) * LD + w];
+                n0v[it][r] = n0;
+                gv[it][r] = G[n0 * n0 + n1 * n1 + k2 * k2];
+            }
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            int b = tid + it * NT;
+            if (TOT % NT == 0 || b < TOT) {
+                int w = b % W, i = b / W;
+                cx<T> u[R0];
+#pragma unroll
+                for (int r = 0; r < R0; ++r) {
+                    int nj = j == 0 ? n0v[it][r] : (j == 1 ? n1v[it] : n2v[it]);
+                    T m = (nj == HN || nj == -HN) ? T(0) : T(nj) * gv[it][r];
+                    u[r] = {-m * spec[it][r].im, m * spec[it][r].re};  // i m spec
+                }
+                dft<R0, -1>(u);
+#pragma unroll
+                for (int r = 0; r < R0; ++r) buf[(i * R0 + r) * LD + w] = u[r];
+            }
+        }
+        __syncthreads();
+        fft_lds<T, N, W, -1, 1, R0>(buf, tws, tid);
+        view_store<T, N, W>(buf, out.p[j], v, g, tid);
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// host-side dispatch
+// ---------------------------------------------------------------------------
+// Pencils per workgroup: 16 (128-byte rows) for float up to 512, 8 above
+// and for double; never more than n/2 and always a divisor of n/2, so that
+// a column block of the main half spectrum never straddles a row.
+template <class T> constexpr int lanes_w(int n) {
+    int cap = (sizeof(T) == 4 && n < 768) ? 16 : 8;
+    int w = cap;
+    while (w > 1 && ((n / 2) % w != 0)) w /= 2;
+    return w;
+}
+// Rows per workgroup of the contiguous-axis passes (n*n rows, n % 16 == 0).
+template <class T> constexpr int rows_w(int n) { return (sizeof(T) == 4 && n < 768) ? 16 : 8; }
+
+#define ML_LAUNCH(kern, grid, stream, ...)                                         \
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(NT), 0, stream, __VA_ARGS__)
+
+template <class T, int H>
+static void r2c_rows_n(T* io, cx<T>* nyq, const cx<T>* tw_h, const cx<T>* tw_post, long nrows,
+                       hipStream_t st) {
+    constexpr int W = rows_w<T>(2 * H);
+    ML_LAUNCH((k_r2c_rows<T, H, W>), nrows / W, st, io, nyq, tw_h, tw_post);
+}
+template <class T, int H>
+static void c2r_rows_n(T* io, const cx<T>* nyq, const cx<T>* tw_h, const cx<T>* tw_post,
+                       long nrows, hipStream_t st) {
+    constexpr int W = rows_w<T>(2 * H);
+    ML_LAUNCH((k_c2r_rows<T, H, W>), nrows / W, st, io, nyq, tw_h, tw_post);
+}
+
+template <class T, int N, int S>
+static void c2c_axis1_n(cx<T>* main, cx<T>* nyq, const cx<T>* tw, hipStream_t st) {
+    constexpr int W = lanes_w<T>(N);
+    ViewDesc va{main, N / 2, 0, (int)((long)N * (N / 2) / W)};
+    ViewDesc vb{nyq, 1, 1, N / W};
+    ML_LAUNCH((k_c2c_view<T, N, W, S>), va.n_wg + vb.n_wg, st, va, vb, tw);
+}
+
+template <class T, int N, int S>
+static void c2c_axis0_n(cx<T>* main, cx<T>* nyq, const cx<T>* tw, hipStream_t st) {
+    constexpr int W = lanes_w<T>(N);
+    ViewDesc va{main, (long)N * (N / 2), 0, (int)((long)N * (N / 2) / W)};
+    ViewDesc vb{nyq, N, 0, N / W};
+    ML_LAUNCH((k_c2c_view<T, N, W, S>), va.n_wg + vb.n_wg, st, va, vb, tw);
+}
+
+template <class T, int N>
+static void grad_axis0_n(cx<T>* main_in, cx<T>* nyq_in, PtrTriple out_main, PtrTriple out_nyq,
+                         const cx<T>* tw, const T* G, hipStream_t st) {
+    constexpr int W = lanes_w<T>(N);
+    ViewDesc va{main_in, (long)N * (N / 2), 0, (int)((long)N * (N / 2) / W)};
+    ViewDesc vb{nyq_in, N, 0, N / W};
+    ML_LAUNCH((k_grad_x0<T, N, W>), va.n_wg + vb.n_wg, st, va, vb, out_main, out_nyq, tw, G);
+}
+
+// Supported lengths.  float: every mesh length; double: up to 256.
+#define ML_SIZES_F(X) X(16) X(32) X(48) X(64) X(96) X(128) X(192) X(256) X(384) X(512) X(768) X(1024)
+#define ML_SIZES_D(X) X(16) X(32) X(48) X(64) X(96) X(128) X(192) X(256)
+
+template <class T> bool fft_supported(int n) {
+#define ML_CASE(v) if (n == v) return true;
+    if constexpr (sizeof(T) == 4) { ML_SIZES_F(ML_CASE) }
+    else { ML_SIZES_D(ML_CASE) }
+#undef ML_CASE
+    return false;
+}
+
+template <class T>
+void fft_r2c_rows(int n, T* io, cx<T>* nyq, const cx<T>* tw_h, const cx<T>* tw_post, hipStream_t st) {
+    long rows = (long)n * n;
+#define ML_CASE(v) if (n == v) return r2c_rows_n<T, v / 2>(io, nyq, tw_h, tw_post, rows, st);
+    if constexpr (sizeof(T) == 4) { ML_SIZES_F(ML_CASE) }
+    else { ML_SIZES_D(ML_CASE) }
+#undef ML_CASE
+}
+
+template <class T>
+void fft_c2r_rows(int n, T* io, const cx<T>* nyq, const cx<T>* tw_h, const cx<T>* tw_post,
+                  hipStream_t st) {
+    long rows = (long)n * n;
+#define ML_CASE(v) if (n == v) return c2r_rows_n<T, v / 2>(io, nyq, tw_h, tw_post, rows, st);
+    if constexpr (sizeof(T) == 4) { ML_SIZES_F(ML_CASE) }
+    else { ML_SIZES_D(ML_CASE) }
+#undef ML_CASE
+}
+
+template <class T>
+void fft_c2c_axis1(int n, int sign, cx<T>* main, cx<T>* nyq, const cx<T>* tw, hipStream_t st) {
+#define ML_CASE(v)                                                                  \
+    if (n == v) {                                                                   \
+        if (sign > 0) return c2c_axis1_n<T, v, 1>(main, nyq, tw, st);               \
+        return c2c_axis1_n<T, v, -1>(main, nyq, tw, st);                            \
+    }
+    if constexpr (sizeof(T) == 4) { ML_SIZES_F(ML_CASE) }
+    else { ML_SIZES_D(ML_CASE) }
+#undef ML_CASE
+}
+
+template <class T>
+void fft_c2c_axis0(int n, int sign, cx<T>* main, cx<T>* nyq, const cx<T>* tw, hipStream_t st) {
+#define ML_CASE(v)                                                                  \
+    if (n == v) {                                                                   \
+        if (sign > 0) return c2c_axis0_n<T, v, 1>(main, nyq, tw, st);               \
+        return c2c_axis0_n<T, v, -1>(main, nyq, tw, st);                            \
+    }
+    if constexpr (sizeof(T) == 4) { ML_SIZES_F(ML_CASE) }
+    else { ML_SIZES_D(ML_CASE) }
+#undef ML_CASE
+}
+
+template <class T>
+void fft_grad_axis0(int n, cx<T>* main_in, cx<T>* nyq_in, PtrTriple out_main, PtrTriple out_nyq,
+                    const cx<T>* tw, const T* G, hipStream_t st) {
+#define ML_CASE(v) if (n == v) return grad_axis0_n<T, v>(main_in, nyq_in, out_main, out_nyq, tw, G, st);
+    if constexpr (sizeof(T) == 4) { ML_SIZES_F(ML_CASE) }
+    else { ML_SIZES_D(ML_CASE) }
+#undef ML_CASE
+}
+
+#define ML_INST(T)                                                                                  \
+    template bool fft_supported<T>(int);                                                            \
+    template void fft_r2c_rows<T>(int, T*, cx<T>*, const cx<T>*, const cx<T>*, hipStream_t);       \
+    template void fft_c2r_rows<T>(int, T*, const cx<T>*, const cx<T>*, const cx<T>*, hipStream_t); \
+    template void fft_c2c_axis1<T>(int, int, cx<T>*, cx<T>*, const cx<T>*, hipStream_t);           \
+    template void fft_c2c_axis0<T>(int, int, cx<T>*, cx<T>*, const cx<T>*, hipStream_t);           \
+    template void fft_grad_axis0<T>(int, cx<T>*, cx<T>*, PtrTriple, PtrTriple, const cx<T>*,        \
+                                    const T*, hipStream_t);
+ML_INST(float)
+ML_INST(double)
+
+}  // namespace ml

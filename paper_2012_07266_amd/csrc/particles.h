@@ -1,0 +1,102 @@
+// Host entry points of the particle kernels (see particles.hip, lens.hip).
+#pragma once
+#include "common.h"
+
+namespace ml {
+
+constexpr int TILE = 16;                         // mesh cells per tile side
+constexpr int TE = TILE + 1;                     // LDS tile side incl. +1 halo
+constexpr int HALO = TE * TE + TILE * TE + TILE * TILE;  // 817 upper-shell cells
+
+// Particle-lattice and mesh geometry.  Positions are stored as displacements
+// from the lattice point in mesh-cell units; the lattice point of particle
+// (i0, i1, i2) is u = B*i + 1/2 cells.
+struct Geo {
+    int np;      // particles per side
+    int nm;      // mesh cells per side
+    int B;       // nm / np
+    int nt;      // tiles per side = nm / TILE
+    long npart;  // np^3
+};
+
+// Particle state in tile-sorted order (SoA, [3][npart] each).
+template <class T> struct Parts {
+    T* disp;        // displacement from the lattice point, cells
+    T* mom;         // momentum, cells (p / H)
+    T* acc;         // force at the particle, cells (f / H)
+    uint32_t* id;   // lattice index (i0*np + i1)*np + i2
+};
+
+struct SortBufs {
+    uint32_t* key;    // tile of each particle
+    uint32_t* rank;   // rank within its tile
+    uint32_t* count;  // [ntiles] histogram
+    uint32_t* start;  // [ntiles+1] exclusive prefix
+};
+
+enum { MODE_KICK = 1, MODE_DRIFT = 2 };
+
+// lattice coordinates (i0, i1, i2) of a particle id
+__device__ __forceinline__ void lattice_of_l(uint32_t id, int np, int* i) {
+    i[2] = (int)(id % (uint32_t)np);
+    uint32_t r = id / (uint32_t)np;
+    i[1] = (int)(r % (uint32_t)np);
+    i[0] = (int)(r / (uint32_t)np);
+}
+
+template <class T>
+void launch_fill(T* p, T v, long n, hipStream_t st);
+// dst[i] = s * src[i]
+template <class T>
+void launch_scale_copy(T* dst, const T* src, T s, long n, hipStream_t st);
+void launch_fill_u32(uint32_t* p, uint32_t v, long n, hipStream_t st);
+
+// mom += kick*acc (MODE_KICK), disp += drift*mom (MODE_DRIFT); then tile
+// key, histogram and rank of every particle.  `count` must be zero.
+template <class T>
+void launch_kick_drift_key(Parts<T> p, SortBufs s, Geo g, T kick, T drift, int mode,
+                           uint32_t* status, hipStream_t st);
+void launch_scan(const uint32_t* count, uint32_t* start, int n, hipStream_t st);
+// Permute disp, mom and id into tile order (dst).
+template <class T>
+void launch_scatter(Parts<T> src, Parts<T> dst, SortBufs s, Geo g, hipStream_t st);
+// CIC paint of tile-sorted particles: interior cells of every tile go to rho,
+// the tile's upper halo shell to halo[ntiles][HALO]; then the halos are
+// added into the low faces of the neighbouring tiles.
+template <class T>
+void launch_paint(Parts<T> p, SortBufs s, Geo g, T mass, T* rho, T* halo, hipStream_t st);
+// CIC readout of the three force meshes; acc = f; mom += kick*acc if do_kick.
+template <class T>
+void launch_readout(Parts<T> p, SortBufs s, Geo g, const T* f0, const T* f1, const T* f2,
+                    T kick, int do_kick, uint32_t* status, hipStream_t st);
+// Zel'dovich: disp = dfac*s, mom = pfac*s from the three displacement meshes
+// on the particle lattice (cells), id = lattice index.
+template <class T>
+void launch_init_ic(Parts<T> p, Geo g, const T* s0, const T* s1, const T* s2, T dfac, T pfac,
+                    hipStream_t st);
+// State out in lattice order: x in [0, box) and p (Mpc/h), acc (Mpc/h).
+template <class T>
+void launch_get_state(Parts<T> p, Geo g, T cell, T* x, T* mom_out, T* acc_out, hipStream_t st);
+// State in (lattice order, Mpc/h) -> displacement (minimum image), momentum.
+template <class T>
+void launch_set_state(Parts<T> p, Geo g, T cell, const T* x, const T* mom_in, hipStream_t st);
+
+// Born projection of one shell (lens.hip).
+constexpr int MAX_SRC = 16;
+template <class T> struct LensArgs {
+    int npix, nsrc;
+    T cell;             // mesh cell size, Mpc/h
+    T chi_near, chi_far;
+    T inv_dtheta;       // 1 / pixel size (radians)
+    T wbase;            // 3/2 Om (H0/c)^2 V_p / Omega_pix
+    T chi_src[MAX_SRC];
+    const T* atab;      // [ntab][2]: a(chi_k), da/dchi(chi_k) at chi_k = k * dchi
+    int ntab;
+    T dchi;
+};
+template <class T>
+void launch_lens(Parts<T> p, Geo g, const LensArgs<T>& la, T* kappa, hipStream_t st);
+template <class T>
+void launch_add_maps(T* kappa, int npix, int nsrc, const T* vals, hipStream_t st);
+
+}  // namespace ml

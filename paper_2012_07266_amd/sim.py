@@ -1,0 +1,167 @@
+"""Python front end of the C ABI: one simulation per handle.
+
+Torch provides device memory and the HIP stream; every step of the
+computation runs in the library's kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import torch
+
+from . import _lib
+from ._lib import LensParams, PmParams, check, lib
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    if t is None:
+        return None
+    if not t.is_cuda or not t.is_contiguous():
+        raise ValueError("expected a contiguous device tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def make_params(np_side, nm_side, box, omega_m=0.3, sigma8=0.8, h=0.7, n_s=0.96,
+                omega_b=0.05, t_cmb=2.7255, dtype=torch.float32):
+    p = PmParams()
+    p.np, p.nm, p.box = int(np_side), int(nm_side), float(box)
+    p.omega_m, p.omega_b, p.h, p.n_s = float(omega_m), float(omega_b), float(h), float(n_s)
+    p.sigma8, p.t_cmb = float(sigma8), float(t_cmb)
+    p.dtype = _lib.PM_F64 if dtype == torch.float64 else _lib.PM_F32
+    return p
+
+
+def make_lens(npix, fov_deg, z_src: Sequence[float]):
+    arr = (ctypes.c_double * len(z_src))(*[float(z) for z in z_src])
+    l = LensParams()
+    l.npix, l.fov_deg, l.nsrc = int(npix), float(fov_deg), len(z_src)
+    l.z_src = ctypes.cast(arr, ctypes.POINTER(ctypes.c_double))
+    l._keep = arr  # keep the host array alive for the call
+    return l
+
+
+def footprint(np_side, nm_side, box, npix, fov_deg, z_src, dtype=torch.float32, **cosmo):
+    p = make_params(np_side, nm_side, box, dtype=dtype, **cosmo)
+    l = make_lens(npix, fov_deg, z_src)
+    return int(lib().pm_footprint(ctypes.byref(p), ctypes.byref(l)))
+
+
+class Simulation:
+    """A PM + lightcone simulation resident on one GPU."""
+
+    def __init__(self, np_side, nm_side, box, npix, fov_deg, z_src, *,
+                 dtype=torch.float32, stream: Optional[torch.cuda.Stream] = None,
+                 **cosmo):
+        self.np_side, self.nm_side, self.box = int(np_side), int(nm_side), float(box)
+        self.npix, self.fov_deg, self.z_src = int(npix), float(fov_deg), tuple(z_src)
+        self.dtype = dtype
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.stream = stream if stream is not None else torch.cuda.current_stream()
+        p = make_params(np_side, nm_side, box, dtype=dtype, **cosmo)
+        l = make_lens(npix, fov_deg, z_src)
+        h = ctypes.c_void_p()
+        check(lib().pm_create(ctypes.byref(p), ctypes.byref(l),
+                              ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(h)),
+              "pm_create")
+        self._h = h
+        self.a = None
+
+    @property
+    def n_particles(self):
+        return self.np_side ** 3
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().pm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- the hot path -----------------------------------------------------
+    def init_ic(self, noise: torch.Tensor, a0: float):
+        noise = noise.to(device=self.device, dtype=self.dtype).contiguous()
+        self._noise_keep = noise
+        check(lib().pm_init_ic(self._h, _ptr(noise), float(a0)), "pm_init_ic")
+        self.a = float(a0)
+
+    def step(self, a0: float, a1: float):
+        check(lib().pm_step(self._h, float(a0), float(a1)), "pm_step")
+        self.a = float(a1)
+
+    def lens(self, a0: float, a1: float, kappa: torch.Tensor):
+        check(lib().lens_project(self._h, float(a0), float(a1), _ptr(kappa)), "lens_project")
+
+    def new_maps(self):
+        return torch.zeros((len(self.z_src), self.npix, self.npix), dtype=self.dtype,
+                           device=self.device)
+
+    def run(self, noise, a_grid, kappa=None):
+        """ICs at a_grid[0], then for every interval a step and its shell."""
+        if kappa is None:
+            kappa = self.new_maps()
+        self.init_ic(noise, a_grid[0])
+        for i in range(len(a_grid) - 1):
+            self.step(a_grid[i], a_grid[i + 1])
+            self.lens(a_grid[i], a_grid[i + 1], kappa)
+        return kappa
+
+    # -- state and introspection ------------------------------------------
+    def get_state(self):
+        n = self.n_particles
+        x = torch.empty((3, n), dtype=self.dtype, device=self.device)
+        p = torch.empty((3, n), dtype=self.dtype, device=self.device)
+        a = ctypes.c_double()
+        check(lib().pm_get_state(self._h, _ptr(x), _ptr(p), ctypes.byref(a)), "pm_get_state")
+        return x, p
+
+    def set_state(self, x: torch.Tensor, p: torch.Tensor, a: float):
+        x = x.to(device=self.device, dtype=self.dtype).contiguous()
+        p = p.to(device=self.device, dtype=self.dtype).contiguous()
+        check(lib().pm_set_state(self._h, _ptr(x), _ptr(p), float(a)), "pm_set_state")
+        self._state_keep = (x, p)
+        self.a = float(a)
+
+    def get_force(self):
+        nm, n = self.nm_side, self.n_particles
+        rho = torch.empty((nm, nm, nm), dtype=self.dtype, device=self.device)
+        fm = torch.empty((3, nm, nm, nm), dtype=self.dtype, device=self.device)
+        acc = torch.empty((3, n), dtype=self.dtype, device=self.device)
+        check(lib().pm_get_force(self._h, _ptr(rho), _ptr(fm), _ptr(acc)), "pm_get_force")
+        return rho, fm, acc
+
+    def sync(self):
+        check(lib().pm_sync(self._h), "pm_sync")
+
+    def profile(self, enable: bool):
+        check(lib().pm_profile(self._h, 1 if enable else 0), "pm_profile")
+
+    def profile_read(self):
+        """{kernel name: (total ms, launches)} since the last read."""
+        cap = 64
+        names = ctypes.create_string_buffer(32 * cap)
+        ms = (ctypes.c_double * cap)()
+        cnt = (ctypes.c_long * cap)()
+        n = ctypes.c_int()
+        check(lib().pm_profile_read(self._h, cap, names, ms, cnt, ctypes.byref(n)),
+              "pm_profile_read")
+        out = {}
+        for i in range(min(n.value, cap)):
+            nm = names.raw[32 * i:32 * i + 32].split(b"\0", 1)[0].decode()
+            out[nm] = (ms[i], cnt[i])
+        return out
+
+    def background(self, a):
+        out = (ctypes.c_double * 3)()
+        check(lib().pm_background(self._h, float(a), out), "pm_background")
+        return tuple(out)

@@ -1,0 +1,168 @@
+"""GPU parity: the HIP path through the C ABI against the float64 oracle.
+
+Float64 instantiations must agree to round-off (1e-10 relative or better);
+float32 ones to the stated tolerances: positions within 1e-4 of a mesh cell,
+convergence maps within 1e-4 relative RMS.
+"""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from tests.gpu_util import cosmo_of, log, new_sim, periodic_cells, rel_rms, to_np
+
+pytestmark = pytest.mark.gpu
+
+DTYPES = [torch.float64, torch.float32]
+# (Np, Nm, box): B = 2 with 2^3 tiles, B = 1, and radix-3 lengths (48, 96)
+SHAPES = [(16, 32, 40.0), (32, 32, 64.0), (48, 96, 100.0)]
+
+
+def _wl(np_side, nm, box, **kw):
+    return W.Workload(f"t{np_side}_{nm}", np_side, nm, box, 0.1, 1.0, 4, 32, 2.0, (1.0,), **kw)
+
+
+def _tol(dtype, f64, f32):
+    return f64 if dtype == torch.float64 else f32
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+def test_background_tables(dtype):
+    wl = _wl(16, 32, 40.0)
+    c = cosmo_of(wl)
+    with new_sim(wl, dtype) as sim:
+        for a in (0.01, 0.1, 0.5, 0.97):
+            d, g, chi = sim.background(a)
+            assert abs(d - c.D(a)) < 1e-12 * c.D(a)
+            assert abs(g - c.gp(a)) < 1e-12 * c.gp(a)
+            assert abs(chi - c.chi(a)) < 1e-11 * c.chi(a)
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: f"{s[0]}p{s[1]}m")
+def test_density_force_readout(dtype, shape):
+    from oracle import pm
+    np_side, nm, box = shape
+    log(f"density/force {shape} {dtype}")
+    wl = _wl(np_side, nm, box)
+    x = W.clustered_positions(np_side, nm, box, seed=31)
+    p = W.random_momenta(np_side ** 3, 1.0, seed=32)
+    with new_sim(wl, dtype) as sim:
+        sim.set_state(torch.from_numpy(x), torch.from_numpy(p), 0.5)
+        rho_g, fm_g, acc_g = (to_np(t) for t in sim.get_force())
+        sim.sync()
+    rho = pm.density(x, np_side, nm, box)
+    f = pm.force_mesh(rho, box)
+    acc = np.stack([pm.cic_readout(x, f[j], box) for j in range(3)])
+    # float32: positions are rounded to float32 on the way in (about 1e-5 of a
+    # cell for coordinates of ~100 cells), which moves each CIC weight by up
+    # to that much; clumps of thousands of particles add these up.
+    e_rho = np.max(np.abs(rho_g - rho)) / np.max(rho)
+    e_f = rel_rms(fm_g, f)
+    e_fmax = np.max(np.abs(fm_g - f)) / np.max(np.abs(f))
+    e_acc = rel_rms(acc_g, acc)
+    log(f"{shape} {dtype}: rho {e_rho:.2e} force rms {e_f:.2e} max {e_fmax:.2e} acc {e_acc:.2e}")
+    assert abs(rho_g.sum() - nm ** 3) < _tol(dtype, 1e-9, 1e-3) * nm ** 3
+    assert e_rho <= _tol(dtype, 1e-12, 2e-5)
+    assert e_f <= _tol(dtype, 1e-12, 2e-5)
+    assert e_fmax <= _tol(dtype, 1e-12, 1e-4)
+    assert e_acc <= _tol(dtype, 1e-12, 2e-5)
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+@pytest.mark.parametrize("shape", [(16, 32, 40.0), (32, 32, 64.0), (48, 96, 100.0)],
+                         ids=lambda s: f"{s[0]}p{s[1]}m")
+def test_zeldovich_ic(dtype, shape):
+    from oracle import pm
+    np_side, nm, box = shape
+    log(f"ic {shape} {dtype}")
+    wl = _wl(np_side, nm, box)
+    c = cosmo_of(wl)
+    noise = W.white_noise(np_side, 41)
+    a0 = 0.2
+    with new_sim(wl, dtype) as sim:
+        sim.init_ic(torch.from_numpy(noise), a0)
+        xg, pg = (to_np(t) for t in sim.get_state())
+        sim.sync()
+    x, p = pm.zeldovich_ic(noise, c, box, nm, a0)
+    err = periodic_cells(xg - x, box, nm)
+    log(f"ic {shape} {dtype}: pos max {err.max():.2e} cells, mom rel-rms {rel_rms(pg, p):.2e}")
+    # float32 output positions alone carry half an ulp of the box coordinate,
+    # about 3e-8 Nm cells
+    assert err.max() <= _tol(dtype, 1e-10, 2e-5)
+    assert rel_rms(pg, p) <= _tol(dtype, 1e-12, 1e-5)
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+def test_cfg1_positions_and_kappa(dtype):
+    """The full 32^3 / 32^3, 5-step run with its 64^2 map at z_s = 1."""
+    from oracle import lens
+    wl = W.CFG1
+    log(f"cfg1 full run {dtype}")
+    c = cosmo_of(wl)
+    noise = W.white_noise(wl.np_side, wl.seed)
+    a = wl.a_grid()
+    with new_sim(wl, dtype) as sim:
+        kap_g = to_np(sim.run(torch.from_numpy(noise), a))
+        xg, pg = (to_np(t) for t in sim.get_state())
+        sim.sync()
+    geom = lens.MapGeometry(wl.npix, wl.fov_deg, wl.z_src, c)
+    kap, x, p = lens.run_lensing(noise, c, wl.box, wl.nm_side, a, geom)
+    err = periodic_cells(xg - x, wl.box, wl.nm_side)
+    log(f"cfg1 {dtype}: pos max {err.max():.3e} rms {np.sqrt((err**2).mean()):.3e} cells; "
+        f"kappa rel-rms {rel_rms(kap_g, kap):.3e}")
+    assert err.max() <= _tol(dtype, 1e-8, 1e-4)
+    assert rel_rms(pg, p) <= _tol(dtype, 1e-10, 1e-4)
+    assert rel_rms(kap_g, kap) <= _tol(dtype, 1e-10, 1e-4)
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+def test_lens_shell_of_static_field(dtype):
+    """One shell at a thick early step: several box replicas along the line of
+    sight and across the field, four source planes.  Clustered particles, so
+    the map is not a cancellation of the particle and mean terms; float32 is
+    also held to 1e-5 of the particle term alone (rounding of ~10^4 atomic
+    additions per pixel)."""
+    from oracle import lens
+    wl = W.Workload("lens", 32, 32, 64.0, 0.1, 1.0, 4, 48, 6.0, (0.5, 1.0, 1.5, 2.0))
+    c = cosmo_of(wl)
+    x = W.clustered_positions(32, 32, wl.box, seed=51)
+    p = np.zeros_like(x)
+    a_far, a_near = 0.45, 0.6
+    log(f"lens static {dtype}")
+    with new_sim(wl, dtype) as sim:
+        sim.set_state(torch.from_numpy(x), torch.from_numpy(p), a_near)
+        k = sim.new_maps()
+        sim.lens(a_far, a_near, k)
+        kg = to_np(k)
+        sim.sync()
+    geom = lens.MapGeometry(wl.npix, wl.fov_deg, wl.z_src, c)
+    ko = lens.project_shell(x, a_far, a_near, c, wl.box, 32, geom)
+    kp = lens.project_shell(x, a_far, a_near, c, wl.box, 32, geom, include_mean=False)
+    e_tot = rel_rms(kg, ko)
+    e_part = float(np.sqrt(np.mean((kg - ko) ** 2) / np.mean(kp ** 2)))
+    log(f"lens static {dtype}: kappa rel-rms {e_tot:.2e}, vs particle term {e_part:.2e}")
+    assert e_tot <= _tol(dtype, 1e-10, 1e-4)
+    assert e_part <= _tol(dtype, 1e-12, 1e-5)
+
+
+def test_error_paths():
+    from paper_2012_07266_amd import MadlensError
+    from paper_2012_07266_amd._lib import PM_ESTATE, PM_ENONFINITE
+    wl = _wl(16, 32, 40.0)
+    with new_sim(wl) as sim:
+        with pytest.raises(MadlensError) as e:
+            sim.step(0.1, 0.2)          # no state yet
+        assert e.value.code == PM_ESTATE
+        sim.init_ic(torch.from_numpy(W.white_noise(16, 1)), 0.1)
+        with pytest.raises(MadlensError) as e:
+            sim.step(0.3, 0.4)          # state is at 0.1
+        assert e.value.code == PM_ESTATE
+        sim.sync()
+        # a non-finite position forced from the host is reported, not hidden
+        x = torch.from_numpy(W.random_positions(16 ** 3, 40.0, seed=2))
+        x[1, 77] = float("nan")
+        sim.set_state(x, torch.zeros_like(x), 0.2)
+        with pytest.raises(MadlensError) as e:
+            sim.sync()
+        assert e.value.code == PM_ENONFINITE
