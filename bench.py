@@ -51,16 +51,73 @@ def algorithmic_bytes(wl, esize=4):
         "fft_c2c_axis1_inv": 2 * S,
         "fft_c2r_axis2": S + M,
         "readout_kick": 3 * M + 52 * P,    # R 3 meshes, disp,id,mom  W mom,acc
-        "lens_paint": 16 * P + 2 * maps,   # R disp,id  RW maps
-        "lens_mean": 2 * maps,
+        "lens_gather": 16 * P + 2 * maps,  # R disp,id  RW maps (incl. mean term)
         "scan": 0,
     }
+
+
+TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
+# kernel class -> (substring of the HIP kernel name in rocprofv3 output, source)
+KERNEL_SYMBOL = {
+    "fft_grad_axis0": ("k_grad_x0<float, 512", "paper_2012_07266_amd/csrc/fft.hip"),
+    "readout_kick": ("k_readout<float>", "paper_2012_07266_amd/csrc/particles.hip"),
+    "paint": ("k_paint_group<float", "paper_2012_07266_amd/csrc/particles.hip"),
+    "fft_c2c_axis1_inv": ("k_c2c_view<float, 512, 16, -1>", "paper_2012_07266_amd/csrc/fft.hip"),
+    "fft_c2r_axis2": ("k_c2r_rows<float, 256", "paper_2012_07266_amd/csrc/fft.hip"),
+    "lens_gather": ("k_lens_gather<float>", "paper_2012_07266_amd/csrc/lens.hip"),
+}
+COPY_BYTES = 1 << 30  # the calibration copy moves 1 GiB in and 1 GiB out
+
+
+def traffic_from_pmc(fetch_csv, write_csv):
+    """Write profiles/traffic.json from two rocprofv3 --pmc runs of
+    `bench.py --calibrate-copy` (FETCH_SIZE, then WRITE_SIZE, in KiB per
+    dispatch).  Each counter is scaled by what it reads for the 1 GiB
+    calibration copy, whose true traffic is known."""
+    import csv
+    import hashlib
+
+    def per_kernel(path, counter):
+        acc = {}
+        for r in csv.DictReader(open(path)):
+            if r["Counter_Name"] != counter:
+                continue
+            acc.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]) * 1024.0)
+        return acc
+
+    fetch = per_kernel(fetch_csv, "FETCH_SIZE")
+    write = per_kernel(write_csv, "WRITE_SIZE")
+
+    def find(d, sub):
+        hits = [x for k, v in d.items() if sub in k for x in v]
+        return sum(hits) / len(hits) if hits else None
+
+    def calib(d):  # the largest copy dispatch is the 1 GiB calibration copy
+        vals = [x for k, v in d.items() if "copy" in k.lower() for x in v]
+        return max(vals) if vals else None
+
+    cf, cw = calib(fetch), calib(write)
+    sf = COPY_BYTES / cf if cf else 1.0
+    sw = COPY_BYTES / cw if cw else 1.0
+    out = {"_about": "HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled "
+                     "by the counters of a 1 GiB device copy",
+           "_scale": {"fetch": sf, "write": sw}}
+    for cls, (sub, src) in KERNEL_SYMBOL.items():
+        f, w = find(fetch, sub), find(write, sub)
+        if f is None or w is None:
+            continue
+        h = hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()
+        out[cls] = {"symbol": sub, "source": src, "sha256": h,
+                    "fetch_bytes": f * sf, "write_bytes": w * sw,
+                    "bytes_per_launch": f * sf + w * sw}
+    json.dump(out, open(TRAFFIC_JSON, "w"), indent=1)
+    print(json.dumps(out))
 
 
 def load_traffic(kernel):
     """HBM traffic per launch measured with rocprofv3 counters, if the kernel
     source has not changed since (hash recorded with the counters)."""
-    path = os.path.join(ROOT, "profiles", "traffic.json")
+    path = TRAFFIC_JSON
     if not os.path.exists(path):
         return None
     try:
@@ -124,7 +181,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="no per-kernel events in the timed region (roofline omitted)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a 1 GiB device copy (counter calibration for --pmc runs)")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/traffic.json from two rocprofv3 --pmc CSVs and exit")
     args = ap.parse_args()
+    if args.traffic_from:
+        traffic_from_pmc(*args.traffic_from)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
@@ -157,6 +221,12 @@ def main():
             i += 1
         return i
 
+    if args.calibrate_copy:
+        src = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     sim.init_ic(noise, a[0])
     run_steps(args.warmup, 0)
     sim.init_ic(noise, a[0])

@@ -41,7 +41,7 @@ struct Layout {
 // Offsets of every device array inside the arena.
 struct ArenaPlan {
     size_t disp[2], mom[2], id[2], acc, key, rank, count, start, status;
-    size_t mesh[3], nyq[3], halo, tw_nm, tw_hm, twp_nm, tw_np, tw_hp, twp_np, g_pois, g_ic, atab;
+    size_t mesh[3], nyq[3], halo, tw_nm, tw_hm, twp_nm, tw_np, tw_hp, twp_np, g_ic, atab;
     size_t total;
 };
 
@@ -70,7 +70,7 @@ ArenaPlan plan_arena(const pm_params& p, const lens_params& l, size_t es) {
         a.mesh[j] = L.take(nm * nm * nm * es);
         a.nyq[j] = L.take(nm * nm * 2 * es);
     }
-    a.halo = L.take(nt * nt * nt * HALO * es);
+    a.halo = L.take((size_t)paint_halo_elems((int)nt, (int)es) * es);
     a.tw_nm = L.take(nm * 2 * es);
     a.tw_hm = L.take(nm / 2 * 2 * es);
     a.twp_nm = L.take((nm / 2 + 1) * 2 * es);
@@ -78,7 +78,6 @@ ArenaPlan plan_arena(const pm_params& p, const lens_params& l, size_t es) {
     a.tw_np = L.take(np_ * 2 * es);
     a.tw_hp = L.take(np_ / 2 * 2 * es);
     a.twp_np = L.take((np_ / 2 + 1) * 2 * es);
-    a.g_pois = L.take((3 * (nm / 2) * (nm / 2) + 1) * es);
     a.g_ic = L.take((3 * (np_ / 2) * (np_ / 2) + 1) * es);
     a.atab = L.take(2 * ATAB_N * es);
     a.total = L.bytes;
@@ -211,7 +210,7 @@ template <class T> struct Sim final : SimBase {
     cx<T>* nyq[3]{};
     T* halo = nullptr;
     cx<T>*tw_nm, *tw_hm, *twp_nm, *tw_np, *tw_hp, *twp_np;
-    T *g_pois, *g_ic, *atab;
+    T *g_ic, *atab;
     double dchi_tab = 0;
     double a_cur = -1.0;
     double cell = 0;  // mesh cell, Mpc/h
@@ -268,7 +267,6 @@ template <class T> struct Sim final : SimBase {
         tw_np = at<cx<T>>(ap.tw_np);
         tw_hp = at<cx<T>>(ap.tw_hp);
         twp_np = at<cx<T>>(ap.twp_np);
-        g_pois = at<T>(ap.g_pois);
         g_ic = at<T>(ap.g_ic);
         atab = at<T>(ap.atab);
         return upload_tables();
@@ -305,14 +303,6 @@ template <class T> struct Sim final : SimBase {
         if ((rc = upload(ap.tw_hp, v))) return rc;
         twiddles(v, np, np / 2 + 1);
         if ((rc = upload(ap.twp_np, v))) return rc;
-        // Poisson: f_hat_j = i n_j G[n^2] delta_hat in cell units, including the
-        // 1/Nm^3 of the unnormalised inverse: G = 1 / (2 pi n^2 Nm^2)
-        {
-            int nmax = 3 * (nm / 2) * (nm / 2);
-            v.assign(nmax + 1, T(0));
-            for (int q = 1; q <= nmax; ++q) v[q] = (T)(1.0 / (2.0 * PI * q * (double)nm * nm));
-            if ((rc = upload(ap.g_pois, v))) return rc;
-        }
         // Zel'dovich: s_hat_j (mesh cells) = i n_j G delta-per-noise with
         // G = Nm sqrt(P(k) Np^3 / L^3) / (2 pi n^2 Np^3), k = 2 pi |n| / L
         {
@@ -355,12 +345,14 @@ template <class T> struct Sim final : SimBase {
     }
 
     void fft_forward_grad(int n, const T* G, const cx<T>* tw, const cx<T>* twh, const cx<T>* twp) {
+        // Poisson: G(q) = 1 / (2 pi q Nm^2) computed in the kernel (G == NULL)
+        const T gscale = (T)(1.0 / (2.0 * PI * (double)n * (double)n));
         { ProfScope ps(prof, "fft_r2c_axis2"); fft_r2c_rows<T>(n, mesh[0], nyq[0], twh, twp, st); }
         { ProfScope ps(prof, "fft_c2c_axis1_fwd");
           fft_c2c_axis1<T>(n, 1, reinterpret_cast<cx<T>*>(mesh[0]), nyq[0], tw, st); }
         PtrTriple om{{mesh[0], mesh[1], mesh[2]}}, on{{nyq[0], nyq[1], nyq[2]}};
         { ProfScope ps(prof, "fft_grad_axis0");
-          fft_grad_axis0<T>(n, reinterpret_cast<cx<T>*>(mesh[0]), nyq[0], om, on, tw, G, st); }
+          fft_grad_axis0<T>(n, reinterpret_cast<cx<T>*>(mesh[0]), nyq[0], om, on, tw, G, gscale, st); }
         for (int j = 0; j < 3; ++j) {
             ProfScope ps(prof, "fft_c2c_axis1_inv");
             fft_c2c_axis1<T>(n, -1, reinterpret_cast<cx<T>*>(mesh[j]), nyq[j], tw, st);
@@ -379,7 +371,7 @@ template <class T> struct Sim final : SimBase {
 
     void force(T kick2, int do_kick) {
         paint();
-        fft_forward_grad(P.nm, g_pois, tw_nm, tw_hm, twp_nm);
+        fft_forward_grad(P.nm, nullptr, tw_nm, tw_hm, twp_nm);
         ProfScope ps(prof, "readout_kick");
         launch_readout<T>(cur, sb, geo, mesh[0], mesh[1], mesh[2], kick2, do_kick, status, st);
     }
@@ -436,15 +428,11 @@ template <class T> struct Sim final : SimBase {
         la.atab = atab;
         la.ntab = ATAB_N;
         la.dchi = (T)dchi_tab;
+        la.rs = 32;
         T* k = reinterpret_cast<T*>(kappa);
-        { ProfScope ps(prof, "lens_paint"); launch_lens<T>(cur, geo, la, k, st); }
-        T mv[MAX_SRC];
-        bool any = false;
-        for (int s = 0; s < nsrc; ++s) {
-            mv[s] = (T)cosmo.shell_mean(chi_near, chi_far, chisrc[s]);
-            any = any || mv[s] != T(0);
-        }
-        if (any) { ProfScope ps(prof, "lens_mean"); launch_add_maps<T>(k, npix, nsrc, mv, st); }
+        MapAdd<T> mv{};
+        for (int s = 0; s < nsrc; ++s) mv.v[s] = (T)cosmo.shell_mean(chi_near, chi_far, chisrc[s]);
+        { ProfScope ps(prof, "lens_gather"); launch_lens_gather<T>(cur, sb, geo, la, mv, k, st); }
         return check_launch();
     }
 
@@ -472,7 +460,7 @@ template <class T> struct Sim final : SimBase {
         size_t n3 = (size_t)P.nm * P.nm * P.nm;
         paint();
         if (rho) HIPCHK(hipMemcpyAsync(rho, mesh[0], n3 * sizeof(T), hipMemcpyDeviceToDevice, st));
-        fft_forward_grad(P.nm, g_pois, tw_nm, tw_hm, twp_nm);
+        fft_forward_grad(P.nm, nullptr, tw_nm, tw_hm, twp_nm);
         launch_readout<T>(cur, sb, geo, mesh[0], mesh[1], mesh[2], T(0), 0, status, st);
         if (fm) {
             // force meshes are in cell units; scale to Mpc/h into the caller's buffer

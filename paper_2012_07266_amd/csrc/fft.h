@@ -28,10 +28,11 @@ void fft_c2c_axis1(int n, int sign, cx<T>* main, cx<T>* nyq, const cx<T>* tw, hi
 // c2c along axis 0 on main and nyq.
 template <class T>
 void fft_c2c_axis0(int n, int sign, cx<T>* main, cx<T>* nyq, const cx<T>* tw, hipStream_t st);
-// Fused axis-0 pass: forward, times i n_j G[|n|^2] (zero where |n_j| = n/2),
-// inverse, for j = 0..2.  out_main/out_nyq hold the three destinations.
+// Fused axis-0 pass: forward, times i n_j G(|n|^2) (zero where |n_j| = n/2),
+// inverse, for j = 0..2.  G(q) is the table G[q], or gscale / q when G is
+// NULL (q > 0; G(0) = 0).  out_main/out_nyq hold the three destinations.
 template <class T>
 void fft_grad_axis0(int n, cx<T>* main_in, cx<T>* nyq_in, PtrTriple out_main, PtrTriple out_nyq,
-                    const cx<T>* tw, const T* G, hipStream_t st);
+                    const cx<T>* tw, const T* G, T gscale, hipStream_t st);
 
 }  // namespace ml

@@ -84,9 +84,106 @@ __device__ __forceinline__ void fft_lds(cx<T>* buf, const cx<T>* tw, int tid) {
     }
 }
 
-template <class T, int N>
+template <class T, int N, int NTT = NT>
 __device__ __forceinline__ void load_twiddles(cx<T>* tw_s, const cx<T>* tw, int tid) {
-    for (int t = tid; t < N; t += NT) tw_s[t] = tw[t];
+    for (int t = tid; t < N; t += NTT) tw_s[t] = tw[t];
+}
+
+// ---------------------------------------------------------------------------
+// Register-resident variant for the strided passes.  Each thread keeps the
+// E = W*N/NT values of its butterflies in registers across a stage; LDS is
+// used only to exchange values between stages.  The first stage reads its
+// inputs straight from global memory and the last stage writes its outputs
+// straight back: both touch element (w, i + r*N/R), which is contiguous
+// across the W pencils of a row.  Requires (N/R)*W % NT == 0 for every stage.
+// ---------------------------------------------------------------------------
+constexpr int num_stages(int n) {
+    int c = 0;
+    while (n > 1) { n /= radix_of(n); ++c; }
+    return c;
+}
+constexpr int span_before(int n, int s) {  // product of the first s radices
+    int p = 1;
+    for (int i = 0; i < s; ++i) { int r = radix_of(n); p *= r; n /= r; }
+    return p;
+}
+template <int N, int W, int NTT = NT> constexpr bool reg_path_ok() {
+    int n = N;
+    while (n > 1) {
+        int r = radix_of(n);
+        if (((N / r) * W) % NTT != 0) return false;
+        n /= r;
+    }
+    return true;
+}
+
+template <class T, int N, int W, int R, int P, int S, int NTT = NT>
+__device__ __forceinline__ void reg_compute(cx<T>* v, const cx<T>* tw, int tid) {
+    constexpr int IT = (N / R) * W / NTT;
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        int i = (tid + it * NTT) / W;
+        int k = i % P;
+        if constexpr (P > 1) {
+#pragma unroll
+            for (int r = 1; r < R; ++r) {
+                cx<T> t = tw[r * k * (N / (P * R))];
+                if constexpr (S < 0) t.im = -t.im;
+                v[it * R + r] = cmul(v[it * R + r], t);
+            }
+        }
+        dft<R, S>(v + it * R);
+    }
+}
+
+template <class T, int N, int W, int R, int P, int NTT = NT>
+__device__ __forceinline__ void reg_write_lds(const cx<T>* v, cx<T>* buf, int tid) {
+    constexpr int IT = (N / R) * W / NTT;
+    constexpr int LD = W + 1;
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        int b = tid + it * NTT, w = b % W, i = b / W;
+        int k = i % P;
+        int j = (i - k) * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) buf[(j + r * P) * LD + w] = v[it * R + r];
+    }
+}
+
+template <class T, int N, int W, int R, int NTT = NT>
+__device__ __forceinline__ void reg_read_lds(cx<T>* v, const cx<T>* buf, int tid) {
+    constexpr int IT = (N / R) * W / NTT;
+    constexpr int LD = W + 1;
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        int b = tid + it * NTT, w = b % W, i = b / W;
+#pragma unroll
+        for (int r = 0; r < R; ++r) v[it * R + r] = buf[(i + r * (N / R)) * LD + w];
+    }
+}
+
+// Element (w, n) of the tile for register slot (it, r) of a radix-R stage in
+// its input pattern n = i + r*N/R.
+template <int N, int W, int R, int NTT = NT>
+__device__ __forceinline__ void slot_pos(int tid, int it, int r, int& w, int& n) {
+    int b = tid + it * NTT;
+    w = b % W;
+    n = b / W + r * (N / R);
+}
+
+// Stages STAGE.. of a transform whose stage STAGE-1 outputs sit in v.
+template <class T, int N, int W, int S, int STAGE, int NTT = NT>
+__device__ __forceinline__ void reg_chain(cx<T>* v, cx<T>* buf, const cx<T>* tw, int tid) {
+    if constexpr (STAGE < num_stages(N)) {
+        constexpr int RP = plan_radix(N, STAGE - 1), PP = span_before(N, STAGE - 1);
+        constexpr int R = plan_radix(N, STAGE), P = span_before(N, STAGE);
+        reg_write_lds<T, N, W, RP, PP, NTT>(v, buf, tid);
+        __syncthreads();
+        reg_read_lds<T, N, W, R, NTT>(v, buf, tid);
+        __syncthreads();
+        reg_compute<T, N, W, R, P, S, NTT>(v, tw, tid);
+        reg_chain<T, N, W, S, STAGE + 1, NTT>(v, buf, tw, tid);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -103,9 +200,19 @@ __global__ __launch_bounds__(NT) void k_r2c_rows(T* io, cx<T>* nyq, const cx<T>*
     const size_t r0 = (size_t)blockIdx.x * W;
     load_twiddles<T, H>(tws, tw_h, tid);
     const cx<T>* in = reinterpret_cast<const cx<T>*>(io) + r0 * H;
-    for (int f = tid; f < W * H; f += NT) {
-        int w = f / H, n = f % H;
-        buf[n * LD + w] = in[(size_t)w * H + n];
+    {
+        constexpr int IT = (W * H + NT - 1) / NT;
+        cx<T> v[IT];
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            int f = tid + it * NT;
+            if ((W * H) % NT == 0 || f < W * H) v[it] = in[f];  // rows are contiguous
+        }
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            int f = tid + it * NT;
+            if ((W * H) % NT == 0 || f < W * H) buf[(f % H) * LD + f / H] = v[it];
+        }
     }
     __syncthreads();
     fft_lds<T, H, W, 1>(buf, tws, tid);
@@ -145,15 +252,26 @@ __global__ __launch_bounds__(NT) void k_c2r_rows(T* io, const cx<T>* nyq, const 
     load_twiddles<T, H>(tws, tw_h, tid);
     const cx<T>* in = reinterpret_cast<const cx<T>*>(io) + r0 * H;
     constexpr int HK = H / 2 + 1;
-    for (int f = tid; f < W * HK; f += NT) {
+    constexpr int ITK = (W * HK + NT - 1) / NT;
+    cx<T> xkv[ITK], xmv[ITK];
+#pragma unroll
+    for (int it = 0; it < ITK; ++it) {
+        int f = tid + it * NT;
+        if (f < W * HK) {
+            int w = f / HK, k = f % HK;
+            xkv[it] = in[(size_t)w * H + k];
+            xmv[it] = k == 0 ? nyq[r0 + w] : in[(size_t)w * H + (H - k)];
+        }
+    }
+#pragma unroll
+    for (int it = 0; it < ITK; ++it) {
+        int f = tid + it * NT;
+        if (f >= W * HK) continue;
         int w = f / HK, k = f % HK;
-        cx<T> xk, xm;
+        cx<T> xk = xkv[it], xm = xmv[it];
         if (k == 0) {
-            xk = mk<T>(in[(size_t)w * H].re, T(0));
-            xm = mk<T>(nyq[r0 + w].re, T(0));
-        } else {
-            xk = in[(size_t)w * H + k];
-            xm = in[(size_t)w * H + (H - k)];
+            xk.im = T(0);
+            xm.im = T(0);
         }
         cx<T> ze = xk + conj(xm);
         cx<T> d = xk - conj(xm);
@@ -169,9 +287,10 @@ __global__ __launch_bounds__(NT) void k_c2r_rows(T* io, const cx<T>* nyq, const 
     __syncthreads();
     fft_lds<T, H, W, -1>(buf, tws, tid);
     cx<T>* out = reinterpret_cast<cx<T>*>(io) + r0 * H;
-    for (int f = tid; f < W * H; f += NT) {
-        int w = f / H, n = f % H;
-        out[(size_t)w * H + n] = buf[n * LD + w];
+#pragma unroll
+    for (int it = 0; it < (W * H + NT - 1) / NT; ++it) {
+        int f = tid + it * NT;
+        if ((W * H) % NT == 0 || f < W * H) out[f] = buf[(f % H) * LD + f / H];
     }
 }
 
@@ -197,19 +316,48 @@ __device__ __forceinline__ long view_offset(const ViewDesc& v, int g, int w, int
     return base + (long)n * v.C + w;
 }
 
+template <class T, int N, int W, bool CONTIG>
+__device__ __forceinline__ void view_load_t(cx<T>* buf, const ViewDesc& v, int g, int tid) {
+    constexpr int LD = W + 1;
+    constexpr int IT = (W * N + NT - 1) / NT;
+    const cx<T>* p = reinterpret_cast<const cx<T>*>(v.ptr);
+    cx<T> r[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        int f = tid + it * NT;
+        if ((W * N) % NT == 0 || f < W * N) {
+            int w = CONTIG ? f / N : f % W, n = CONTIG ? f % N : f / W;
+            r[it] = p[view_offset<T, N, W>(v, g, w, n)];
+        }
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        int f = tid + it * NT;
+        if ((W * N) % NT == 0 || f < W * N) {
+            int w = CONTIG ? f / N : f % W, n = CONTIG ? f % N : f / W;
+            buf[n * LD + w] = r[it];
+        }
+    }
+}
+
 template <class T, int N, int W>
 __device__ __forceinline__ void view_load(cx<T>* buf, const ViewDesc& v, int g, int tid) {
+    if (v.contig) view_load_t<T, N, W, true>(buf, v, g, tid);
+    else view_load_t<T, N, W, false>(buf, v, g, tid);
+}
+
+template <class T, int N, int W, bool CONTIG>
+__device__ __forceinline__ void view_store_t(const cx<T>* buf, void* dst, const ViewDesc& v, int g,
+                                             int tid) {
     constexpr int LD = W + 1;
-    const cx<T>* p = reinterpret_cast<const cx<T>*>(v.ptr);
-    if (v.contig) {
-        for (int f = tid; f < W * N; f += NT) {
-            int w = f / N, n = f % N;
-            buf[n * LD + w] = p[view_offset<T, N, W>(v, g, w, n)];
-        }
-    } else {
-        for (int f = tid; f < W * N; f += NT) {
-            int n = f / W, w = f % W;
-            buf[n * LD + w] = p[view_offset<T, N, W>(v, g, w, n)];
+    constexpr int IT = (W * N + NT - 1) / NT;
+    cx<T>* p = reinterpret_cast<cx<T>*>(dst);
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        int f = tid + it * NT;
+        if ((W * N) % NT == 0 || f < W * N) {
+            int w = CONTIG ? f / N : f % W, n = CONTIG ? f % N : f / W;
+            p[view_offset<T, N, W>(v, g, w, n)] = buf[n * LD + w];
         }
     }
 }
@@ -217,19 +365,8 @@ __device__ __forceinline__ void view_load(cx<T>* buf, const ViewDesc& v, int g, 
 template <class T, int N, int W>
 __device__ __forceinline__ void view_store(const cx<T>* buf, void* dst, const ViewDesc& v, int g,
                                            int tid) {
-    constexpr int LD = W + 1;
-    cx<T>* p = reinterpret_cast<cx<T>*>(dst);
-    if (v.contig) {
-        for (int f = tid; f < W * N; f += NT) {
-            int w = f / N, n = f % N;
-            p[view_offset<T, N, W>(v, g, w, n)] = buf[n * LD + w];
-        }
-    } else {
-        for (int f = tid; f < W * N; f += NT) {
-            int n = f / W, w = f % W;
-            p[view_offset<T, N, W>(v, g, w, n)] = buf[n * LD + w];
-        }
-    }
+    if (v.contig) view_store_t<T, N, W, true>(buf, dst, v, g, tid);
+    else view_store_t<T, N, W, false>(buf, dst, v, g, tid);
 }
 
 template <class T, int N, int W, int S>
@@ -241,6 +378,36 @@ __global__ __launch_bounds__(NT) void k_c2c_view(ViewDesc va, ViewDesc vb, const
     const ViewDesc& v = g < va.n_wg ? va : vb;
     if (g >= va.n_wg) g -= va.n_wg;
     load_twiddles<T, N>(tws, tw, tid);
+    if constexpr (reg_path_ok<N, W>()) {
+        if (!v.contig) {
+            constexpr int E = W * N / NT;
+            constexpr int R0 = plan_radix(N, 0);
+            constexpr int RL = plan_radix(N, num_stages(N) - 1);
+            const cx<T>* src = reinterpret_cast<const cx<T>*>(v.ptr);
+            cx<T> r[E];
+#pragma unroll
+            for (int it = 0; it < E / R0; ++it)
+#pragma unroll
+                for (int q = 0; q < R0; ++q) {
+                    int w, n;
+                    slot_pos<N, W, R0>(tid, it, q, w, n);
+                    r[it * R0 + q] = src[view_offset<T, N, W>(v, g, w, n)];
+                }
+            __syncthreads();  // twiddles in LDS
+            reg_compute<T, N, W, R0, 1, S>(r, tws, tid);
+            reg_chain<T, N, W, S, 1>(r, buf, tws, tid);
+            cx<T>* dst = reinterpret_cast<cx<T>*>(v.ptr);
+#pragma unroll
+            for (int it = 0; it < E / RL; ++it)
+#pragma unroll
+                for (int q = 0; q < RL; ++q) {
+                    int w, n;
+                    slot_pos<N, W, RL>(tid, it, q, w, n);
+                    dst[view_offset<T, N, W>(v, g, w, n)] = r[it * RL + q];
+                }
+            return;
+        }
+    }
     view_load<T, N, W>(buf, v, g, tid);
     __syncthreads();
     fft_lds<T, N, W, S>(buf, tws, tid);
@@ -255,9 +422,9 @@ __global__ __launch_bounds__(NT) void k_c2c_view(ViewDesc va, ViewDesc vb, const
 // out[j] are the bases of the three spectra (main or nyq part, matching va
 // or vb); out[0] may equal the input.
 // ---------------------------------------------------------------------------
-template <class T, int N, int W>
-__global__ __launch_bounds__(NT) void k_grad_x0(ViewDesc va, ViewDesc vb, PtrTriple outa,
-                                                PtrTriple outb, const cx<T>* tw, const T* G) {
+template <class T, int N, int W, int NTG>
+__global__ __launch_bounds__(NTG) void k_grad_x0(ViewDesc va, ViewDesc vb, PtrTriple outa,
+                                                PtrTriple outb, const cx<T>* tw, const T* G, T gscale) {
     __shared__ cx<T> buf[N * (W + 1)];
     __shared__ cx<T> tws[N];
     constexpr int LD = W + 1;
@@ -268,13 +435,96 @@ __global__ __launch_bounds__(NT) void k_grad_x0(ViewDesc va, ViewDesc vb, PtrTri
     const ViewDesc& v = is_a ? va : vb;
     const PtrTriple& out = is_a ? outa : outb;
     if (!is_a) g -= va.n_wg;
-    load_twiddles<T, N>(tws, tw, tid);
+    load_twiddles<T, N, NTG>(tws, tw, tid);
+    constexpr int R0 = plan_radix(N, 0);
+    constexpr int RL = plan_radix(N, num_stages(N) - 1);
+    constexpr int PL = span_before(N, num_stages(N) - 1);
+
+    if constexpr (reg_path_ok<N, W, NTG>()) {
+        constexpr int E = W * N / NTG;
+        const cx<T>* src = reinterpret_cast<const cx<T>*>(v.ptr);
+        cx<T> spec[E];
+#pragma unroll
+        for (int it = 0; it < E / R0; ++it)
+#pragma unroll
+            for (int q = 0; q < R0; ++q) {
+                int w, n;
+                slot_pos<N, W, R0, NTG>(tid, it, q, w, n);
+                spec[it * R0 + q] = src[view_offset<T, N, W>(v, g, w, n)];
+            }
+        __syncthreads();
+        reg_compute<T, N, W, R0, 1, 1, NTG>(spec, tws, tid);
+        reg_chain<T, N, W, 1, 1, NTG>(spec, buf, tws, tid);
+        if constexpr (RL != R0) {
+            // bring the spectrum into the stage-0 input pattern
+            reg_write_lds<T, N, W, RL, PL, NTG>(spec, buf, tid);
+            __syncthreads();
+            reg_read_lds<T, N, W, R0, NTG>(spec, buf, tid);
+            __syncthreads();
+        }
+        // spec[it*R0 + q] holds k0 = i + q*N/R0 of pencil w; replace it by
+        // h = i G(|n|^2) spec so that component j is just n_j h
+#pragma unroll
+        for (int it = 0; it < E / R0; ++it) {
+            int b = tid + it * NTG, w = b % W;
+            long c = (long)g * W + w;
+            int k1 = is_a ? (int)(c / HN) : (int)c;
+            int k2 = is_a ? (int)(c % HN) : HN;
+            int n1 = k1 <= HN ? k1 : k1 - N;
+#pragma unroll
+            for (int q = 0; q < R0; ++q) {
+                int ww, k0;
+                slot_pos<N, W, R0, NTG>(tid, it, q, ww, k0);
+                int n0 = k0 <= HN ? k0 : k0 - N;
+                int nsq = n0 * n0 + n1 * n1 + k2 * k2;
+                T gg = G ? G[nsq] : (nsq ? gscale / T(nsq) : T(0));
+                cx<T> sp = spec[it * R0 + q];
+                spec[it * R0 + q] = {-gg * sp.im, gg * sp.re};
+            }
+        }
+#pragma unroll 1
+        for (int j = 0; j < 3; ++j) {
+            cx<T> u[E];
+#pragma unroll
+            for (int it = 0; it < E / R0; ++it) {
+                int b = tid + it * NTG, w = b % W;
+                long c = (long)g * W + w;
+                int k1 = is_a ? (int)(c / HN) : (int)c;
+                int k2 = is_a ? (int)(c % HN) : HN;
+                int n1 = k1 <= HN ? k1 : k1 - N;
+#pragma unroll
+                for (int q = 0; q < R0; ++q) {
+                    int ww, k0;
+                    slot_pos<N, W, R0, NTG>(tid, it, q, ww, k0);
+                    int n0 = k0 <= HN ? k0 : k0 - N;
+                    int nj = j == 0 ? n0 : (j == 1 ? n1 : k2);
+                    T m = (nj == HN || nj == -HN) ? T(0) : T(nj);
+                    u[it * R0 + q] = scale(spec[it * R0 + q], m);
+                }
+            }
+            reg_compute<T, N, W, R0, 1, -1, NTG>(u, tws, tid);
+            reg_chain<T, N, W, -1, 1, NTG>(u, buf, tws, tid);
+            cx<T>* dst = reinterpret_cast<cx<T>*>(out.p[j]);
+#pragma unroll
+            for (int it = 0; it < E / RL; ++it)
+#pragma unroll
+                for (int q = 0; q < RL; ++q) {
+                    int w, n;
+                    slot_pos<N, W, RL, NTG>(tid, it, q, w, n);
+                    dst[view_offset<T, N, W>(v, g, w, n)] = u[it * RL + q];
+                }
+            __syncthreads();  // the next component reuses buf
+        }
+        return;
+    }
+
+    static_assert(NTG == NT || reg_path_ok<N, W, NTG>(), "LDS path needs NT threads");
+    if constexpr (NTG == NT) {
     view_load<T, N, W>(buf, v, g, tid);
     __syncthreads();
     fft_lds<T, N, W, 1>(buf, tws, tid);
 
     // first inverse stage: radix R0 at span 1, no twiddles
-    constexpr int R0 = plan_radix(N, 0);
     constexpr int NB = N / R0;
     constexpr int TOT = NB * W;
     constexpr int IT = (TOT + NT - 1) / NT;
@@ -299,7 +549,8 @@ __global__ __launch_bounds__(NT) void k_grad_x0(ViewDesc va, ViewDesc vb, PtrTri
                 int n0 = k0 <= HN ? k0 : k0 - N;
                 spec[it][r] = buf[(i + r * NB) * LD + w];
                 n0v[it][r] = n0;
-                gv[it][r] = G[n0 * n0 + n1 * n1 + k2 * k2];
+                int nsq = n0 * n0 + n1 * n1 + k2 * k2;
+                gv[it][r] = G ? G[nsq] : (nsq ? gscale / T(nsq) : T(0));
             }
         }
     }
@@ -327,6 +578,7 @@ __global__ __launch_bounds__(NT) void k_grad_x0(ViewDesc va, ViewDesc vb, PtrTri
         fft_lds<T, N, W, -1, 1, R0>(buf, tws, tid);
         view_store<T, N, W>(buf, out.p[j], v, g, tid);
         __syncthreads();
+    }
     }
 }
 
@@ -377,13 +629,20 @@ static void c2c_axis0_n(cx<T>* main, cx<T>* nyq, const cx<T>* tw, hipStream_t st
     ML_LAUNCH((k_c2c_view<T, N, W, S>), va.n_wg + vb.n_wg, st, va, vb, tw);
 }
 
+// The fused pass holds the spectrum and one component in registers; from 512
+// up it runs 512 threads per workgroup so that each thread holds half as
+// many values and the CU keeps four waves per SIMD.
+template <class T> constexpr int grad_nt(int n) { return (n >= 512 && sizeof(T) == 4) ? 512 : NT; }
+
 template <class T, int N>
 static void grad_axis0_n(cx<T>* main_in, cx<T>* nyq_in, PtrTriple out_main, PtrTriple out_nyq,
-                         const cx<T>* tw, const T* G, hipStream_t st) {
+                         const cx<T>* tw, const T* G, T gscale, hipStream_t st) {
     constexpr int W = lanes_w<T>(N);
+    constexpr int NTG = (grad_nt<T>(N) == 512 && reg_path_ok<N, W, 512>()) ? 512 : NT;
     ViewDesc va{main_in, (long)N * (N / 2), 0, (int)((long)N * (N / 2) / W)};
     ViewDesc vb{nyq_in, N, 0, N / W};
-    ML_LAUNCH((k_grad_x0<T, N, W>), va.n_wg + vb.n_wg, st, va, vb, out_main, out_nyq, tw, G);
+    hipLaunchKernelGGL((k_grad_x0<T, N, W, NTG>), dim3(va.n_wg + vb.n_wg), dim3(NTG), 0, st, va, vb,
+                       out_main, out_nyq, tw, G, gscale);
 }
 
 // Supported lengths.  float: every mesh length; double: up to 256.
@@ -443,8 +702,8 @@ void fft_c2c_axis0(int n, int sign, cx<T>* main, cx<T>* nyq, const cx<T>* tw, hi
 
 template <class T>
 void fft_grad_axis0(int n, cx<T>* main_in, cx<T>* nyq_in, PtrTriple out_main, PtrTriple out_nyq,
-                    const cx<T>* tw, const T* G, hipStream_t st) {
-#define ML_CASE(v) if (n == v) return grad_axis0_n<T, v>(main_in, nyq_in, out_main, out_nyq, tw, G, st);
+                    const cx<T>* tw, const T* G, T gscale, hipStream_t st) {
+#define ML_CASE(v) if (n == v) return grad_axis0_n<T, v>(main_in, nyq_in, out_main, out_nyq, tw, G, gscale, st);
     if constexpr (sizeof(T) == 4) { ML_SIZES_F(ML_CASE) }
     else { ML_SIZES_D(ML_CASE) }
 #undef ML_CASE
@@ -457,7 +716,7 @@ void fft_grad_axis0(int n, cx<T>* main_in, cx<T>* nyq_in, PtrTriple out_main, Pt
     template void fft_c2c_axis1<T>(int, int, cx<T>*, cx<T>*, const cx<T>*, hipStream_t);           \
     template void fft_c2c_axis0<T>(int, int, cx<T>*, cx<T>*, const cx<T>*, hipStream_t);           \
     template void fft_grad_axis0<T>(int, cx<T>*, cx<T>*, PtrTriple, PtrTriple, const cx<T>*,        \
-                                    const T*, hipStream_t);
+                                    const T*, T, hipStream_t);
 ML_INST(float)
 ML_INST(double)
 

@@ -114,6 +114,199 @@ void launch_lens(Parts<T> p, Geo g, const LensArgs<T>& la, T* kappa, hipStream_t
     hipLaunchKernelGGL(k_lens<T>, dim3(blocks), dim3(LB), 0, st, p, g, la, kappa);
 }
 
+// ---------------------------------------------------------------------------
+// Region-driven projection: a workgroup owns a RS x RS pixel region of every
+// map.  For each box replica it bounds the part of the shell that projects
+// into the region (with a one-pixel margin for bilinear spill), visits the
+// particle tiles inside that bound (tile-sorted particles, so each (tx, ty)
+// column over a z range is one contiguous index range), and accumulates the
+// region in LDS.  float: 64-bit fixed point with 40 fractional bits (exact,
+// order-independent sums at full integer-atomic rate); an image weight of
+// 2^22 or more (a particle within ~1e-5 Mpc/h of the observer) goes to the
+// map directly with a float atomic.  double: float64 LDS atomics.  Each
+// pixel is then written by exactly one workgroup, together with the shell's
+// mean term.
+// ---------------------------------------------------------------------------
+template <class T> struct LensAcc;
+template <> struct LensAcc<float> {
+    using S = unsigned long long;
+    static constexpr float LIM = 4194304.0f;  // 2^22
+    static __device__ __forceinline__ S enc(float w) {
+        return (S)__float2ull_rn(w * 1099511627776.0f);  // 2^40
+    }
+    static __device__ __forceinline__ float dec(S v) {
+        return (float)((double)v * (1.0 / 1099511627776.0));
+    }
+};
+template <> struct LensAcc<double> {
+    using S = double;
+    static constexpr double LIM = 1e300;
+    static __device__ __forceinline__ S enc(double w) { return w; }
+    static __device__ __forceinline__ double dec(S v) { return v; }
+};
+
+template <class T>
+__device__ __forceinline__ void splat_region(typename LensAcc<T>::S* acc, int rs, int p0x, int p0y,
+                                             int npix, T* kmap, T t0, T t1, T w) {
+    using A = LensAcc<T>;
+    T fl0 = floor(t0), fl1 = floor(t1);
+    int j0 = (int)fl0, j1 = (int)fl1;
+    T f0 = t0 - fl0, f1 = t1 - fl1;
+    T wa[2] = {T(1) - f0, f0}, wb[2] = {T(1) - f1, f1};
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        int r = j0 + a;
+        if (r < p0x || r >= p0x + rs || r >= npix) continue;
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            int c = j1 + b;
+            if (c < p0y || c >= p0y + rs || c >= npix) continue;
+            T v = w * wa[a] * wb[b];
+            if (v < T(A::LIM)) atomicAdd(&acc[(r - p0x) * rs + (c - p0y)], A::enc(v));
+            else unsafeAtomicAdd(&kmap[(long)r * npix + c], v);
+        }
+    }
+}
+
+constexpr int LG = 256;  // threads per lens-gather workgroup
+constexpr int LU = 4;    // particles per thread in flight
+
+template <class T>
+__global__ __launch_bounds__(LG) void k_lens_gather(Parts<T> p, SortBufs sb, Geo g, LensArgs<T> la,
+                                                    MapAdd<T> mean, T* kappa) {
+    using A = LensAcc<T>;
+    using S = typename A::S;
+    extern __shared__ unsigned char smem[];
+    S* acc = reinterpret_cast<S*>(smem);
+    const int rs = la.rs;
+    const int nreg = (la.npix + rs - 1) / rs;
+    // renumber workgroups so each of the 8 XCDs (round-robin dispatch) walks a
+    // contiguous band of regions: neighbouring regions read the same particle
+    // tiles, which then stay in that XCD's L2
+    int b = blockIdx.x;
+    if (gridDim.x % 8 == 0) b = (b % 8) * (gridDim.x / 8) + b / 8;
+    const int rx = b / nreg, ry = b % nreg;
+    const int p0x = rx * rs, p0y = ry * rs;
+    const int tid = threadIdx.x;
+    const int ncell = la.nsrc * rs * rs;
+    for (int i = tid; i < ncell; i += LG) acc[i] = S(0);
+    __syncthreads();
+
+    const long n = g.npart;
+    const int nm = g.nm, nt = g.nt;
+    const T nmf = T(nm), half = T(0.5) * nmf;
+    const T hp = T(0.5) * T(la.npix) - T(0.5);
+    const T cnear = la.chi_near / la.cell, cfar = la.chi_far / la.cell;  // cells
+    T chi_max_src = la.chi_src[0];
+    for (int s = 1; s < la.nsrc; ++s) chi_max_src = max(chi_max_src, la.chi_src[s]);
+    const T cmax = min(cfar, chi_max_src / la.cell);
+    const T dth = T(1) / la.inv_dtheta;
+    // angular window of images touching the region: t in [p0 - 1, p0 + rs)
+    const T a0lo = (T(p0x - 1) - hp) * dth, a0hi = (T(p0x + rs) - hp) * dth;
+    const T a1lo = (T(p0y - 1) - hp) * dth, a1hi = (T(p0y + rs) - hp) * dth;
+    const T margin = T(1);  // cells of slack on every bound
+    const int npix2 = la.npix * la.npix;
+
+    int nz0 = (int)floor(cnear / nmf) - 1;
+    if (nz0 < 0) nz0 = 0;
+    const int nz1 = (int)floor(cmax / nmf);
+    for (int nz = nz0; nz <= nz1; ++nz) {
+        T zlo = max(cnear - T(nz) * nmf, T(0)), zhi = min(cmax - T(nz) * nmf, nmf);
+        if (!(zlo < zhi)) continue;
+        T ca = zlo + T(nz) * nmf, cb = zhi + T(nz) * nmf;  // depth range, cells
+        T x0lo = min(a0lo * ca, a0lo * cb) - margin, x0hi = max(a0hi * ca, a0hi * cb) + margin;
+        T x1lo = min(a1lo * ca, a1lo * cb) - margin, x1hi = max(a1hi * ca, a1hi * cb) + margin;
+        int tz0 = max((int)floor((zlo - margin) / T(TILE)), 0);
+        int tz1 = min((int)floor((zhi + margin) / T(TILE)), nt - 1);
+        int nx0 = (int)floor((x0lo + half) / nmf), nx1 = (int)floor((x0hi + half) / nmf);
+        int ny0 = (int)floor((x1lo + half) / nmf), ny1 = (int)floor((x1hi + half) / nmf);
+        for (int nx = nx0; nx <= nx1; ++nx) {
+            T bxlo = x0lo + half - T(nx) * nmf, bxhi = x0hi + half - T(nx) * nmf;  // box x, cells
+            int tx0 = max((int)floor(bxlo / T(TILE)), 0), tx1 = min((int)floor(bxhi / T(TILE)), nt - 1);
+            for (int ny = ny0; ny <= ny1; ++ny) {
+                T bylo = x1lo + half - T(ny) * nmf, byhi = x1hi + half - T(ny) * nmf;
+                int ty0 = max((int)floor(bylo / T(TILE)), 0), ty1 = min((int)floor(byhi / T(TILE)), nt - 1);
+                for (int tx = tx0; tx <= tx1; ++tx)
+                    for (int ty = ty0; ty <= ty1; ++ty) {
+                        const int col = (tx * nt + ty) * nt;
+                        const uint32_t lo = sb.start[col + tz0], hi = sb.start[col + tz1 + 1];
+                        for (uint32_t base = lo; base < hi; base += LG * LU) {
+                            uint32_t idv[LU];
+                            T dv[LU][3];
+#pragma unroll
+                            for (int u = 0; u < LU; ++u) {
+                                uint32_t k = base + u * LG + tid;
+                                if (k < hi) {
+                                    idv[u] = p.id[k];
+                                    dv[u][0] = p.disp[k];
+                                    dv[u][1] = p.disp[n + k];
+                                    dv[u][2] = p.disp[2 * n + k];
+                                }
+                            }
+#pragma unroll
+                            for (int u = 0; u < LU; ++u) {
+                                uint32_t k = base + u * LG + tid;
+                                if (k >= hi) continue;
+                                int li[3];
+                                lattice_of_l(idv[u], g.np, li);
+                                T uu[3];
+#pragma unroll
+                                for (int a = 0; a < 3; ++a) {
+                                    T v = T(0.5) + dv[u][a];
+                                    T fl = floor(v);
+                                    int c = g.B * li[a] + (int)fl;
+                                    if ((unsigned)c >= (unsigned)nm) c = pmod(c, nm);
+                                    uu[a] = T(c) + (v - fl);
+                                }
+                                T rz = uu[2] + T(nz) * nmf;
+                                if (!(rz > cnear && rz <= cfar && rz > T(0))) continue;
+                                T chi = rz * la.cell;
+                                if (!(chi < chi_max_src)) continue;
+                                T inv = la.inv_dtheta / rz;
+                                T t0 = (uu[0] + T(nx) * nmf - half) * inv + hp;
+                                T t1 = (uu[1] + T(ny) * nmf - half) * inv + hp;
+                                if (!(t0 >= T(p0x - 1) && t0 < T(p0x + rs) && t0 > T(-1) &&
+                                      t1 >= T(p0y - 1) && t1 < T(p0y + rs) && t1 > T(-1)))
+                                    continue;
+                                T base_w = la.wbase / (chi * a_of_chi(la, chi));
+                                for (int s = 0; s < la.nsrc; ++s) {
+                                    T cs = la.chi_src[s];
+                                    if (chi < cs)
+                                        splat_region<T>(acc + s * rs * rs, rs, p0x, p0y, la.npix,
+                                                        kappa + (long)s * npix2, t0, t1,
+                                                        base_w * (cs - chi) / cs);
+                                }
+                            }
+                        }
+                    }
+            }
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < ncell; i += LG) {
+        int s = i / (rs * rs), r = (i / rs) % rs, c = i % rs;
+        int px = p0x + r, py = p0y + c;
+        if (px < la.npix && py < la.npix) {
+            long o = (long)s * npix2 + (long)px * la.npix + py;
+            kappa[o] += A::dec(acc[i]) + mean.v[s];
+        }
+    }
+}
+
+template <class T>
+void launch_lens_gather(Parts<T> p, SortBufs sb, Geo g, const LensArgs<T>& la,
+                        const MapAdd<T>& mean, T* kappa, hipStream_t st) {
+    int nreg = (la.npix + la.rs - 1) / la.rs;
+    size_t lds = (size_t)la.nsrc * la.rs * la.rs * sizeof(typename LensAcc<T>::S);
+    hipLaunchKernelGGL(k_lens_gather<T>, dim3(nreg * nreg), dim3(LG), lds, st, p, sb, g, la, mean,
+                       kappa);
+}
+
+template void launch_lens_gather<float>(Parts<float>, SortBufs, Geo, const LensArgs<float>&,
+                                        const MapAdd<float>&, float*, hipStream_t);
+template void launch_lens_gather<double>(Parts<double>, SortBufs, Geo, const LensArgs<double>&,
+                                         const MapAdd<double>&, double*, hipStream_t);
+
 template <class T> struct MapVals { T v[MAX_SRC]; };
 
 template <class T>

@@ -24,7 +24,7 @@ template <class T> struct Parts {
     T* disp;        // displacement from the lattice point, cells
     T* mom;         // momentum, cells (p / H)
     T* acc;         // force at the particle, cells (f / H)
-    uint32_t* id;   // lattice index (i0*np + i1)*np + i2
+    uint32_t* id;   // packed lattice coordinates, see pack_id
 };
 
 struct SortBufs {
@@ -36,12 +36,20 @@ struct SortBufs {
 
 enum { MODE_KICK = 1, MODE_DRIFT = 2 };
 
-// lattice coordinates (i0, i1, i2) of a particle id
+// Particle ids pack the lattice coordinates (i0, i1, i2), each < 1024, as
+// i0 << 20 | i1 << 10 | i2.
+__device__ __forceinline__ uint32_t pack_id(int i0, int i1, int i2) {
+    return ((uint32_t)i0 << 20) | ((uint32_t)i1 << 10) | (uint32_t)i2;
+}
 __device__ __forceinline__ void lattice_of_l(uint32_t id, int np, int* i) {
-    i[2] = (int)(id % (uint32_t)np);
-    uint32_t r = id / (uint32_t)np;
-    i[1] = (int)(r % (uint32_t)np);
-    i[0] = (int)(r / (uint32_t)np);
+    (void)np;
+    i[0] = (int)(id >> 20);
+    i[1] = (int)((id >> 10) & 1023u);
+    i[2] = (int)(id & 1023u);
+}
+// position in lattice order, (i0 * np + i1) * np + i2
+__device__ __forceinline__ long lattice_index(uint32_t id, int np) {
+    return ((long)(id >> 20) * np + ((id >> 10) & 1023u)) * np + (id & 1023u);
 }
 
 template <class T>
@@ -60,9 +68,11 @@ void launch_scan(const uint32_t* count, uint32_t* start, int n, hipStream_t st);
 // Permute disp, mom and id into tile order (dst).
 template <class T>
 void launch_scatter(Parts<T> src, Parts<T> dst, SortBufs s, Geo g, hipStream_t st);
-// CIC paint of tile-sorted particles: interior cells of every tile go to rho,
-// the tile's upper halo shell to halo[ntiles][HALO]; then the halos are
-// added into the low faces of the neighbouring tiles.
+// CIC paint of tile-sorted particles by groups of tiles along axis 2:
+// interior cells go to rho, each group's upper halo shell to `halo` (size
+// paint_halo_elems); then the shells are added into the neighbours' faces.
+int paint_group_size(int nt, int esize);
+long paint_halo_elems(int nt, int esize);
 template <class T>
 void launch_paint(Parts<T> p, SortBufs s, Geo g, T mass, T* rho, T* halo, hipStream_t st);
 // CIC readout of the three force meshes; acc = f; mom += kick*acc if do_kick.
@@ -93,7 +103,14 @@ template <class T> struct LensArgs {
     const T* atab;      // [ntab][2]: a(chi_k), da/dchi(chi_k) at chi_k = k * dchi
     int ntab;
     T dchi;
+    int rs;             // region side (pixels) of the gather projection
 };
+template <class T> struct MapAdd { T v[MAX_SRC]; };
+// Region-driven projection (each pixel written by one workgroup) that also
+// adds mean.v[s] to every pixel of map s.  Particles must be tile-sorted.
+template <class T>
+void launch_lens_gather(Parts<T> p, SortBufs sb, Geo g, const LensArgs<T>& la,
+                        const MapAdd<T>& mean, T* kappa, hipStream_t st);
 template <class T>
 void launch_lens(Parts<T> p, Geo g, const LensArgs<T>& la, T* kappa, hipStream_t st);
 template <class T>

@@ -14,10 +14,10 @@ namespace ml {
 constexpr int PB = 256;  // threads per workgroup of the particle kernels
 
 __device__ __forceinline__ void lattice_of(uint32_t id, int np, int& i0, int& i1, int& i2) {
-    i2 = (int)(id % (uint32_t)np);
-    uint32_t r = id / (uint32_t)np;
-    i1 = (int)(r % (uint32_t)np);
-    i0 = (int)(r / (uint32_t)np);
+    (void)np;
+    i0 = (int)(id >> 20);
+    i1 = (int)((id >> 10) & 1023u);
+    i2 = (int)(id & 1023u);
 }
 
 // Base cell (wrapped) and fraction along one axis from the lattice index and
@@ -27,7 +27,8 @@ __device__ __forceinline__ void cell_of(int B, int i, T disp, int nm, int& c, T&
     T v = T(0.5) + disp;
     T fl = floor(v);
     t = v - fl;
-    c = pmod(B * i + (int)fl, nm);
+    c = B * i + (int)fl;
+    if ((unsigned)c >= (unsigned)nm) c = pmod(c, nm);
 }
 
 template <class T>
@@ -197,83 +198,151 @@ void launch_scatter(Parts<T> src, Parts<T> dst, SortBufs s, Geo g, hipStream_t s
 }
 
 // ---------------------------------------------------------------------------
-// LDS-tiled CIC paint
+// LDS-tiled CIC paint.  A workgroup owns a group of G consecutive tiles
+// along axis 2 (16 x 16 x 16G cells; the sort key orders those tiles
+// consecutively, so their particles form one contiguous range).  It paints
+// into a 17 x 17 x (16G+1) LDS box, stores the 16 x 16 x 16G interior with
+// plain stores and its upper shell (x = 16, y = 16 or z = 16G) to a halo
+// buffer; a second kernel adds the shells into the low faces of the
+// neighbouring groups in a fixed order.  The x and y faces are contiguous
+// along axis 2, so both kernels move whole rows.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int halo_index(int x, int y, int z) {
-    if (x == TILE) return y * TE + z;
-    if (y == TILE) return TE * TE + x * TE + z;
-    return TE * TE + TILE * TE + x * TILE + y;
+template <int G> struct PaintBox {
+    static constexpr int LZ = TILE * G;          // interior depth along axis 2
+    static constexpr int EZ = LZ + 1;
+    static constexpr int CELLS = TE * TE * EZ;
+    static constexpr int HALO = 33 * EZ + TILE * TILE;  // x-face, y-face, z-face
+};
+
+template <int G>
+__device__ __forceinline__ int halo_index_g(int x, int y, int z) {
+    constexpr int EZ = PaintBox<G>::EZ;
+    if (x == TILE) return y * EZ + z;
+    if (y == TILE) return TE * EZ + x * EZ + z;
+    return 33 * EZ + x * TILE + y;
 }
 
-__device__ __forceinline__ void halo_coords(int h, int& x, int& y, int& z) {
-    if (h < TE * TE) { x = TILE; y = h / TE; z = h % TE; return; }
-    h -= TE * TE;
-    if (h < TILE * TE) { x = h / TE; y = TILE; z = h % TE; return; }
-    h -= TILE * TE;
-    x = h / TILE; y = h % TILE; z = TILE;
+template <int G>
+__device__ __forceinline__ void halo_coords_g(int h, int& x, int& y, int& z) {
+    constexpr int EZ = PaintBox<G>::EZ;
+    if (h < TE * EZ) { x = TILE; y = h / EZ; z = h % EZ; return; }
+    h -= TE * EZ;
+    if (h < TILE * EZ) { x = h / EZ; y = TILE; z = h % EZ; return; }
+    h -= TILE * EZ;
+    x = h / TILE; y = h % TILE; z = PaintBox<G>::LZ;
 }
 
-template <class T>
-__global__ __launch_bounds__(PB) void k_paint_tile(Parts<T> p, SortBufs s, Geo g, T mass, T* rho,
-                                                   T* halo) {
-    __shared__ T tile[TE * TE * TE];
+constexpr int PU = 4;    // particles per thread in flight
+constexpr int PBP = 512; // threads per paint workgroup
+
+// LDS accumulator of the paint box.  float: 64-bit fixed point with 32
+// fractional bits (integer LDS atomics run at full rate on gfx950 while
+// float ones do not, and the integer sum is exact and order-independent);
+// double: float64 atomics.
+template <class T> struct PaintAcc;
+template <> struct PaintAcc<float> {
+    using S = unsigned long long;
+    static __device__ __forceinline__ S enc(float w) {
+        return (S)__float2ull_rn(w * 4294967296.0f);
+    }
+    static __device__ __forceinline__ float dec(S v) {
+        return (float)((double)v * (1.0 / 4294967296.0));
+    }
+};
+template <> struct PaintAcc<double> {
+    using S = double;
+    static __device__ __forceinline__ S enc(double w) { return w; }
+    static __device__ __forceinline__ double dec(S v) { return v; }
+};
+
+template <class T, int G>
+__global__ __launch_bounds__(PBP) void k_paint_group(Parts<T> p, SortBufs s, Geo g, T mass, T* rho,
+                                                     T* halo) {
+    using BX = PaintBox<G>;
+    using A = PaintAcc<T>;
+    using S = typename A::S;
+    __shared__ S box[BX::CELLS];
     const int tid = threadIdx.x;
-    const int t = blockIdx.x;
-    const int tx = t / (g.nt * g.nt), ty = (t / g.nt) % g.nt, tz = t % g.nt;
-    const int ox = tx * TILE, oy = ty * TILE, oz = tz * TILE;
-    for (int i = tid; i < TE * TE * TE; i += PB) tile[i] = T(0);
+    const int ng = g.nt / G;  // groups along axis 2
+    const int grp = blockIdx.x;
+    const int tx = grp / (g.nt * ng), ty = (grp / ng) % g.nt, gz = grp % ng;
+    const int ox = tx * TILE, oy = ty * TILE, oz = gz * BX::LZ;
+    for (int i = tid; i < BX::CELLS; i += PBP) box[i] = S(0);
     __syncthreads();
     const long n = g.npart;
-    const uint32_t lo = s.start[t], hi = s.start[t + 1];
-    for (uint32_t k = lo + tid; k < hi; k += PB) {
-        int i0, i1, i2;
-        lattice_of(p.id[k], g.np, i0, i1, i2);
-        int c0, c1, c2;
-        T f0, f1, f2;
-        cell_of(g.B, i0, p.disp[k], g.nm, c0, f0);
-        cell_of(g.B, i1, p.disp[n + k], g.nm, c1, f1);
-        cell_of(g.B, i2, p.disp[2 * n + k], g.nm, c2, f2);
-        int l0 = min(max(c0 - ox, 0), TILE - 1);
-        int l1 = min(max(c1 - oy, 0), TILE - 1);
-        int l2 = min(max(c2 - oz, 0), TILE - 1);
-        T w0[2] = {T(1) - f0, f0}, w1[2] = {T(1) - f1, f1}, w2[2] = {(T(1) - f2) * mass, f2 * mass};
+    const int t0 = (tx * g.nt + ty) * g.nt + gz * G;
+    const uint32_t lo = s.start[t0], hi = s.start[t0 + G];
+    for (uint32_t base = lo; base < hi; base += PBP * PU) {
+        uint32_t idv[PU];
+        T dv[PU][3];
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int b = 0; b < 2; ++b) {
-                T wab = w0[a] * w1[b];
-                int base = ((l0 + a) * TE + (l1 + b)) * TE + l2;
-                atomicAdd(&tile[base], wab * w2[0]);
-                atomicAdd(&tile[base + 1], wab * w2[1]);
+        for (int u = 0; u < PU; ++u) {
+            uint32_t k = base + u * PBP + tid;
+            if (k < hi) {
+                idv[u] = p.id[k];
+                dv[u][0] = p.disp[k];
+                dv[u][1] = p.disp[n + k];
+                dv[u][2] = p.disp[2 * n + k];
             }
+        }
+#pragma unroll
+        for (int u = 0; u < PU; ++u) {
+            uint32_t k = base + u * PBP + tid;
+            if (k >= hi) continue;
+            int i0, i1, i2;
+            lattice_of(idv[u], g.np, i0, i1, i2);
+            int c0, c1, c2;
+            T f0, f1, f2;
+            cell_of(g.B, i0, dv[u][0], g.nm, c0, f0);
+            cell_of(g.B, i1, dv[u][1], g.nm, c1, f1);
+            cell_of(g.B, i2, dv[u][2], g.nm, c2, f2);
+            int l0 = min(max(c0 - ox, 0), TILE - 1);
+            int l1 = min(max(c1 - oy, 0), TILE - 1);
+            int l2 = min(max(c2 - oz, 0), BX::LZ - 1);
+            T w0[2] = {T(1) - f0, f0}, w1[2] = {T(1) - f1, f1};
+            T w2[2] = {(T(1) - f2) * mass, f2 * mass};
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    T wab = w0[a] * w1[b];
+                    int cell = ((l0 + a) * TE + (l1 + b)) * BX::EZ + l2;
+                    atomicAdd(&box[cell], A::enc(wab * w2[0]));
+                    atomicAdd(&box[cell + 1], A::enc(wab * w2[1]));
+                }
+        }
     }
     __syncthreads();
     const long nm = g.nm;
-    for (int i = tid; i < TILE * TILE * TILE; i += PB) {
-        int x = i >> 8, y = (i >> 4) & 15, z = i & 15;
-        rho[((ox + x) * nm + (oy + y)) * nm + (oz + z)] = tile[(x * TE + y) * TE + z];
+    constexpr int NI = TILE * TILE * BX::LZ;
+    for (int i = tid; i < NI; i += PBP) {
+        int x = i / (TILE * BX::LZ), y = (i / BX::LZ) % TILE, z = i % BX::LZ;
+        rho[((ox + x) * nm + (oy + y)) * nm + (oz + z)] = A::dec(box[(x * TE + y) * BX::EZ + z]);
     }
-    for (int h = tid; h < HALO; h += PB) {
+    for (int h = tid; h < BX::HALO; h += PBP) {
         int x, y, z;
-        halo_coords(h, x, y, z);
-        halo[(long)t * HALO + h] = tile[(x * TE + y) * TE + z];
+        halo_coords_g<G>(h, x, y, z);
+        halo[(long)grp * BX::HALO + h] = A::dec(box[(x * TE + y) * BX::EZ + z]);
     }
 }
 
-// Add the upper halo shells of the neighbouring tiles into the low faces of
-// each tile (fixed order, no atomics).
-template <class T>
-__global__ __launch_bounds__(PB) void k_paint_halo(T* rho, const T* halo, Geo g) {
-    const int t = blockIdx.x;
-    const int nt = g.nt;
-    const int tx = t / (nt * nt), ty = (t / nt) % nt, tz = t % nt;
+// Add the upper shells of the neighbouring groups into the low faces of each
+// group (fixed order, no atomics).
+template <class T, int G>
+__global__ __launch_bounds__(PB) void k_paint_halo_group(T* rho, const T* halo, Geo g) {
+    using BX = PaintBox<G>;
+    constexpr int LZ = BX::LZ;
+    const int grp = blockIdx.x;
+    const int nt = g.nt, ng = nt / G;
+    const int tx = grp / (nt * ng), ty = (grp / ng) % nt, gz = grp % ng;
     const long nm = g.nm;
-    // 721 low-face cells: lx == 0 (256), ly == 0 && lx > 0 (240), lz == 0 && lx, ly > 0 (225)
-    for (int f = threadIdx.x; f < 721; f += PB) {
+    // low faces: lx == 0 (16 LZ), ly == 0 && lx > 0 (15 LZ), lz == 0 && lx, ly > 0 (225)
+    constexpr int NF = 31 * LZ + 225;
+    for (int f = threadIdx.x; f < NF; f += PB) {
         int lx, ly, lz;
-        if (f < 256) { lx = 0; ly = f >> 4; lz = f & 15; }
-        else if (f < 496) { int h = f - 256; lx = 1 + h / 16; ly = 0; lz = h % 16; }
-        else { int h = f - 496; lx = 1 + h / 15; ly = 1 + h % 15; lz = 0; }
+        if (f < TILE * LZ) { lx = 0; ly = f / LZ; lz = f % LZ; }
+        else if (f < 31 * LZ) { int h = f - TILE * LZ; lx = 1 + h / LZ; ly = 0; lz = h % LZ; }
+        else { int h = f - 31 * LZ; lx = 1 + h / 15; ly = 1 + h % 15; lz = 0; }
         T acc = T(0);
 #pragma unroll
         for (int dx = 0; dx < 2; ++dx)
@@ -285,83 +354,151 @@ __global__ __launch_bounds__(PB) void k_paint_halo(T* rho, const T* halo, Geo g)
                     if ((dx && lx) || (dy && ly) || (dz && lz)) continue;
                     int nx = tx - dx < 0 ? nt - 1 : tx - dx;
                     int ny = ty - dy < 0 ? nt - 1 : ty - dy;
-                    int nz = tz - dz < 0 ? nt - 1 : tz - dz;
-                    long nb = ((long)nx * nt + ny) * nt + nz;
-                    acc += halo[nb * HALO + halo_index(lx + TILE * dx, ly + TILE * dy, lz + TILE * dz)];
+                    int nz = gz - dz < 0 ? ng - 1 : gz - dz;
+                    long nb = ((long)nx * nt + ny) * ng + nz;
+                    acc += halo[nb * BX::HALO +
+                                halo_index_g<G>(lx + TILE * dx, ly + TILE * dy, lz + LZ * dz)];
                 }
-        long cell = ((long)(tx * TILE + lx) * nm + (ty * TILE + ly)) * nm + (tz * TILE + lz);
+        long cell = ((long)(tx * TILE + lx) * nm + (ty * TILE + ly)) * nm + (gz * LZ + lz);
         rho[cell] += acc;
     }
 }
 
+int paint_group_size(int nt, int esize) {
+    (void)esize;
+    int G = 2;
+    while (G > 1 && nt % G) G /= 2;
+    return G;
+}
+
+long paint_halo_elems(int nt, int esize) {
+    int G = paint_group_size(nt, esize);
+    long groups = (long)nt * nt * (nt / G);
+    long h = 33L * (TILE * G + 1) + TILE * TILE;
+    return groups * h;
+}
+
 template <class T>
 void launch_paint(Parts<T> p, SortBufs s, Geo g, T mass, T* rho, T* halo, hipStream_t st) {
-    int ntiles = g.nt * g.nt * g.nt;
-    hipLaunchKernelGGL(k_paint_tile<T>, dim3(ntiles), dim3(PB), 0, st, p, s, g, mass, rho, halo);
-    hipLaunchKernelGGL(k_paint_halo<T>, dim3(ntiles), dim3(PB), 0, st, rho, halo, g);
+    int G = paint_group_size(g.nt, sizeof(T));
+    int groups = g.nt * g.nt * (g.nt / G);
+    if (G == 2) {
+        hipLaunchKernelGGL((k_paint_group<T, 2>), dim3(groups), dim3(PBP), 0, st, p, s, g, mass, rho, halo);
+        hipLaunchKernelGGL((k_paint_halo_group<T, 2>), dim3(groups), dim3(PB), 0, st, rho, halo, g);
+    } else {
+        hipLaunchKernelGGL((k_paint_group<T, 1>), dim3(groups), dim3(PBP), 0, st, p, s, g, mass, rho, halo);
+        hipLaunchKernelGGL((k_paint_halo_group<T, 1>), dim3(groups), dim3(PB), 0, st, rho, halo, g);
+    }
 }
 
 // ---------------------------------------------------------------------------
 // LDS-staged CIC readout + kick
 // ---------------------------------------------------------------------------
+constexpr int PBR = 512;  // threads per readout workgroup
+
+// Workgroups are handed to the 8 XCDs round-robin.  Renumber them so that
+// each XCD walks a contiguous run of tiles: neighbouring tiles along axis 2
+// then share the 128-byte lines of their one-cell overlap in the same L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+    constexpr int NX = 8;
+    if (nb % NX) return b;
+    return (b % NX) * (nb / NX) + b / NX;
+}
+
 template <class T>
-__global__ __launch_bounds__(PB) void k_readout(Parts<T> p, SortBufs s, Geo g, const T* f0,
+__global__ __launch_bounds__(PBR) void k_readout(Parts<T> p, SortBufs s, Geo g, const T* f0,
                                                 const T* f1, const T* f2, T kick, int do_kick,
                                                 uint32_t* status) {
-    __shared__ T ft[3][TE * TE * TE];
+    constexpr int TC = TE * TE * TE;
+    __shared__ T ft[3][TC];
     const int tid = threadIdx.x;
-    const int t = blockIdx.x;
+    const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int tx = t / (g.nt * g.nt), ty = (t / g.nt) % g.nt, tz = t % g.nt;
     const int ox = tx * TILE, oy = ty * TILE, oz = tz * TILE;
     const uint32_t lo = s.start[t], hi = s.start[t + 1];
     if (lo == hi) return;  // uniform across the workgroup
     const int nm = g.nm;
-    for (int i = tid; i < TE * TE * TE; i += PB) {
-        int x = i / (TE * TE), y = (i / TE) % TE, z = i % TE;
-        int gx = ox + x, gy = oy + y, gz = oz + z;
-        if (gx >= nm) gx -= nm;
-        if (gy >= nm) gy -= nm;
-        if (gz >= nm) gz -= nm;
-        long c = ((long)gx * nm + gy) * nm + gz;
-        ft[0][i] = f0[c];
-        ft[1][i] = f1[c];
-        ft[2][i] = f2[c];
+    {
+        constexpr int IT = (TC + PBR - 1) / PBR;
+        T v0[IT], v1[IT], v2[IT];
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            int i = tid + it * PBR;
+            if (i < TC) {
+                int x = i / (TE * TE), y = (i / TE) % TE, z = i % TE;
+                int gx = ox + x, gy = oy + y, gz = oz + z;
+                if (gx >= nm) gx -= nm;
+                if (gy >= nm) gy -= nm;
+                if (gz >= nm) gz -= nm;
+                long c = ((long)gx * nm + gy) * nm + gz;
+                v0[it] = f0[c];
+                v1[it] = f1[c];
+                v2[it] = f2[c];
+            }
+        }
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            int i = tid + it * PBR;
+            if (i < TC) {
+                ft[0][i] = v0[it];
+                ft[1][i] = v1[it];
+                ft[2][i] = v2[it];
+            }
+        }
     }
     __syncthreads();
     const long n = g.npart;
-    for (uint32_t k = lo + tid; k < hi; k += PB) {
-        int i0, i1, i2;
-        lattice_of(p.id[k], g.np, i0, i1, i2);
-        T d0 = p.disp[k], d1 = p.disp[n + k], d2 = p.disp[2 * n + k];
-        if (!finite3(d0, d1, d2)) atomicOr(status, 1u);
-        int c0, c1, c2;
-        T w0, w1, w2;
-        cell_of(g.B, i0, d0, nm, c0, w0);
-        cell_of(g.B, i1, d1, nm, c1, w1);
-        cell_of(g.B, i2, d2, nm, c2, w2);
-        int l0 = min(max(c0 - ox, 0), TILE - 1);
-        int l1 = min(max(c1 - oy, 0), TILE - 1);
-        int l2 = min(max(c2 - oz, 0), TILE - 1);
-        T wa[2] = {T(1) - w0, w0}, wb[2] = {T(1) - w1, w1}, wc[2] = {T(1) - w2, w2};
-        T a0 = 0, a1 = 0, a2 = 0;
+    for (uint32_t base = lo; base < hi; base += PBR * PU) {
+        uint32_t idv[PU];
+        T dv[PU][3], mv[PU][3];
 #pragma unroll
-        for (int a = 0; a < 2; ++a)
+        for (int u = 0; u < PU; ++u) {
+            uint32_t k = base + u * PBR + tid;
+            if (k < hi) {
+                idv[u] = p.id[k];
 #pragma unroll
-            for (int b = 0; b < 2; ++b) {
-                int base = ((l0 + a) * TE + (l1 + b)) * TE + l2;
-                T wab = wa[a] * wb[b];
-                T v0 = wab * wc[0], v1 = wab * wc[1];
-                a0 += v0 * ft[0][base] + v1 * ft[0][base + 1];
-                a1 += v0 * ft[1][base] + v1 * ft[1][base + 1];
-                a2 += v0 * ft[2][base] + v1 * ft[2][base + 1];
+                for (int a = 0; a < 3; ++a) {
+                    dv[u][a] = p.disp[a * n + k];
+                    if (do_kick) mv[u][a] = p.mom[a * n + k];
+                }
             }
-        p.acc[k] = a0;
-        p.acc[n + k] = a1;
-        p.acc[2 * n + k] = a2;
-        if (do_kick) {
-            p.mom[k] += kick * a0;
-            p.mom[n + k] += kick * a1;
-            p.mom[2 * n + k] += kick * a2;
+        }
+#pragma unroll
+        for (int u = 0; u < PU; ++u) {
+            uint32_t k = base + u * PBR + tid;
+            if (k >= hi) continue;
+            int i0, i1, i2;
+            lattice_of(idv[u], g.np, i0, i1, i2);
+            if (!finite3(dv[u][0], dv[u][1], dv[u][2])) atomicOr(status, 1u);
+            int c0, c1, c2;
+            T w0, w1, w2;
+            cell_of(g.B, i0, dv[u][0], nm, c0, w0);
+            cell_of(g.B, i1, dv[u][1], nm, c1, w1);
+            cell_of(g.B, i2, dv[u][2], nm, c2, w2);
+            int l0 = min(max(c0 - ox, 0), TILE - 1);
+            int l1 = min(max(c1 - oy, 0), TILE - 1);
+            int l2 = min(max(c2 - oz, 0), TILE - 1);
+            T wa[2] = {T(1) - w0, w0}, wb[2] = {T(1) - w1, w1}, wc[2] = {T(1) - w2, w2};
+            T a0 = 0, a1 = 0, a2 = 0;
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) {
+                    int cb = ((l0 + a) * TE + (l1 + b)) * TE + l2;
+                    T wab = wa[a] * wb[b];
+                    T v0 = wab * wc[0], v1 = wab * wc[1];
+                    a0 += v0 * ft[0][cb] + v1 * ft[0][cb + 1];
+                    a1 += v0 * ft[1][cb] + v1 * ft[1][cb + 1];
+                    a2 += v0 * ft[2][cb] + v1 * ft[2][cb + 1];
+                }
+            p.acc[k] = a0;
+            p.acc[n + k] = a1;
+            p.acc[2 * n + k] = a2;
+            if (do_kick) {
+                p.mom[k] = mv[u][0] + kick * a0;
+                p.mom[n + k] = mv[u][1] + kick * a1;
+                p.mom[2 * n + k] = mv[u][2] + kick * a2;
+            }
         }
     }
 }
@@ -370,7 +507,7 @@ template <class T>
 void launch_readout(Parts<T> p, SortBufs s, Geo g, const T* f0, const T* f1, const T* f2,
                     T kick, int do_kick, uint32_t* status, hipStream_t st) {
     int ntiles = g.nt * g.nt * g.nt;
-    hipLaunchKernelGGL(k_readout<T>, dim3(ntiles), dim3(PB), 0, st, p, s, g, f0, f1, f2, kick,
+    hipLaunchKernelGGL(k_readout<T>, dim3(ntiles), dim3(PBR), 0, st, p, s, g, f0, f1, f2, kick,
                        do_kick, status);
 }
 
@@ -389,7 +526,8 @@ __global__ void k_init_ic(Parts<T> p, Geo g, const T* s0, const T* s1, const T* 
             p.mom[a * n + k] = pfac * v[a];
             p.acc[a * n + k] = T(0);
         }
-        p.id[k] = (uint32_t)k;
+        int i2 = (int)(k % g.np), i1 = (int)((k / g.np) % g.np), i0 = (int)(k / ((long)g.np * g.np));
+        p.id[k] = pack_id(i0, i1, i2);
     }
 }
 
@@ -405,9 +543,10 @@ template <class T>
 __global__ void k_get_state(Parts<T> p, Geo g, T cell, T* x, T* mo, T* ac) {
     const long n = g.npart;
     for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
-        uint32_t id = p.id[k];
+        uint32_t pid = p.id[k];
+        long id = lattice_index(pid, g.np);
         int i[3];
-        lattice_of(id, g.np, i[0], i[1], i[2]);
+        lattice_of(pid, g.np, i[0], i[1], i[2]);
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             if (x) {
@@ -436,8 +575,7 @@ __global__ void k_set_state(Parts<T> p, Geo g, T cell, const T* x, const T* mi) 
     const long n = g.npart;
     const T nmf = T(g.nm);
     for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
-        int i[3];
-        lattice_of((uint32_t)k, g.np, i[0], i[1], i[2]);
+        int i[3] = {(int)(k / ((long)g.np * g.np)), (int)((k / g.np) % g.np), (int)(k % g.np)};
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             T u = x[a * n + k] / cell;
@@ -447,7 +585,7 @@ __global__ void k_set_state(Parts<T> p, Geo g, T cell, const T* x, const T* mi) 
             p.mom[a * n + k] = mi[a * n + k] / cell;
             p.acc[a * n + k] = T(0);
         }
-        p.id[k] = (uint32_t)k;
+        p.id[k] = pack_id(i[0], i[1], i[2]);
     }
 }
 
