@@ -109,13 +109,18 @@ def shell_images(x, box, chi_near, chi_far, geom: MapGeometry):
 
 
 def project_shell(x, a_far, a_near, cosmo: Cosmology, box, np_side,
-                  geom: MapGeometry, include_mean=True):
+                  geom: MapGeometry, include_mean=True, chi_bounds=None):
     """Convergence of one PM step's shell, [nsrc][npix][npix].
 
     x are the positions at a_near (end of the step a_far -> a_near).
+    `chi_bounds` = (chi_near, chi_far) overrides the shell's distance range
+    (used to hold the shell partition fixed while the cosmology varies).
     """
-    chi_far = float(cosmo.chi(a_far))
-    chi_near = float(cosmo.chi(a_near))
+    if chi_bounds is None:
+        chi_far = float(cosmo.chi(a_far))
+        chi_near = float(cosmo.chi(a_near))
+    else:
+        chi_near, chi_far = (float(v) for v in chi_bounds)
     pref = lens_prefactor(cosmo.omega_m)
     vp = (box / np_side) ** 3
     out = np.zeros((len(geom.chi_src), geom.npix, geom.npix))
