@@ -195,11 +195,13 @@ def ic_displacement_transpose(s_bar, cosmo: Cosmology, box):
 # ---------------------------------------------------------------------------
 # full reverse pass
 # ---------------------------------------------------------------------------
-def forward_with_checkpoints(noise, cosmo, box, nm_side, a_grid, geom, shell_chis=None):
+def forward_with_checkpoints(noise, cosmo, box, nm_side, a_grid, geom, shell_chis=None,
+                             src_cut=None):
     """Forward model; returns (kappa, states) with states[i] = (x_i, p_i).
 
-    `shell_chis[i]` overrides chi(a_grid[i]) as shell boundary (to hold the
-    shell partition fixed while the cosmology varies)."""
+    `shell_chis[i]` overrides chi(a_grid[i]) as shell boundary and `src_cut`
+    the distances of the in-front-of-source test (to hold the shell partition
+    and the source membership fixed while the cosmology varies)."""
     np_side = noise.shape[0]
     x, p = pm.zeldovich_ic(noise, cosmo, box, nm_side, a_grid[0])
     f = pm.particle_force(x, np_side, nm_side, box)
@@ -210,7 +212,7 @@ def forward_with_checkpoints(noise, cosmo, box, nm_side, a_grid, geom, shell_chi
         states.append((x, p))
         cb = None if shell_chis is None else (shell_chis[i + 1], shell_chis[i])
         kappa += lens.project_shell(x, a_grid[i], a_grid[i + 1], cosmo, box, np_side, geom,
-                                    chi_bounds=cb)
+                                    chi_bounds=cb, src_cut=src_cut)
     return kappa, states
 
 
@@ -254,7 +256,7 @@ def _with_om(cosmo: Cosmology, om):
 
 
 def kappa_vjp_cosmo(noise, kappa_bar, cosmo: Cosmology, box, nm_side, a_grid,
-                    geom: lens.MapGeometry, dom=1e-5):
+                    geom: lens.MapGeometry, dom=1e-5, terms=None):
     """(noise_bar, d/dOmega_m, d/dsigma_8) of sum(kappa * kappa_bar).
 
     Omega_m follows the paper's scheme: the reverse pass gives the cotangent
@@ -264,9 +266,15 @@ def kappa_vjp_cosmo(noise, kappa_bar, cosmo: Cosmology, box, nm_side, a_grid,
     projection and the initial displacement field are differenced in
     Omega_m at fixed particle positions / fixed noise.  The shell partition
     (the distance bounds chi(a_i) of the shells, for the particle term and
-    the mean term alike) is held at the central cosmology: membership is
-    piecewise constant and gets no gradient.  sigma_8 enters only as the
+    the mean term alike) and the test "image in front of source s" are held
+    at the central cosmology: membership is piecewise constant and gets no
+    gradient.  The lens weight vanishes at chi = chi_s, so holding the source
+    membership changes nothing but keeps a difference quotient from
+    straddling the kink of (chi_s - chi)_+ when an image lies within
+    |dchi_s/dOmega_m| dom of a source plane.  sigma_8 enters only as the
     amplitude of the noise: d/dsigma8 = <noise_bar, noise>/sigma8.
+    If `terms` is a list, every additive contribution to d/dOmega_m is
+    appended to it (their magnitudes set the conditioning of the sum).
     """
     np_side = noise.shape[0]
     cp, cm = _with_om(cosmo, cosmo.omega_m + dom), _with_om(cosmo, cosmo.omega_m - dom)
@@ -288,32 +296,36 @@ def kappa_vjp_cosmo(noise, kappa_bar, cosmo: Cosmology, box, nm_side, a_grid,
     xbar = np.zeros((3, np_side ** 3))
     pbar = np.zeros((3, np_side ** 3))
     g_om = 0.0
-    forces = {}
+
+    def add(v):
+        if terms is not None:
+            terms.append(float(v))
+        return float(v)
     for i in range(n - 1, -1, -1):
         x1, p1 = states[i + 1]
         k1, dr, k2 = fac[i]
         # lens at fixed positions: cosmology part and position part
         cb = (cosmo.chi(a_grid[i + 1]), cosmo.chi(a_grid[i]))
         kp = lens.project_shell(x1, a_grid[i], a_grid[i + 1], cp, box, np_side, geom_p,
-                                chi_bounds=cb)
+                                chi_bounds=cb, src_cut=geom.chi_src)
         km = lens.project_shell(x1, a_grid[i], a_grid[i + 1], cm, box, np_side, geom_m,
-                                chi_bounds=cb)
-        g_om += np.sum(kappa_bar * (kp - km)) / (2 * dom)
+                                chi_bounds=cb, src_cut=geom.chi_src)
+        g_om += add(np.sum(kappa_bar * (kp - km)) / (2 * dom))
         xbar += lens_vjp(x1, a_grid[i], a_grid[i + 1], kappa_bar, cosmo, box, np_side, geom)
         f1 = pm.particle_force(x1, np_side, nm_side, box)
         dot = np.sum(pbar * f1)            # cotangent of K2_i and of K1_{i+1}
-        g_om += dot * dfac[i][2]
+        g_om += add(dot * dfac[i][2])
         kf = k2
         if i + 1 < n:
-            g_om += dot * dfac[i + 1][0]
+            g_om += add(dot * dfac[i + 1][0])
             kf += fac[i + 1][0]
         xbar += force_vjp(x1, kf * pbar, np_side, nm_side, box)
         ph = p1 - k2 * f1                  # momentum at the half step
-        g_om += np.sum(xbar * ph) * dfac[i][1]
+        g_om += add(np.sum(xbar * ph) * dfac[i][1])
         pbar = pbar + dr * xbar
     x0, p0 = states[0]
     f0 = pm.particle_force(x0, np_side, nm_side, box)
-    g_om += np.sum(pbar * f0) * dfac[0][0]
+    g_om += add(np.sum(pbar * f0) * dfac[0][0])
     xbar += force_vjp(x0, fac[0][0] * pbar, np_side, nm_side, box)
     a0 = a_grid[0]
     s = zeldovich_s = pm.zeldovich_displacement(noise, cosmo, box)
@@ -322,7 +334,8 @@ def kappa_vjp_cosmo(noise, kappa_bar, cosmo: Cosmology, box, nm_side, a_grid,
     dD = (cp.D(a0) - cm.D(a0)) / (2 * dom)
     dgp = (cp.gp(a0) - cm.gp(a0)) / (2 * dom)
     ds = (s_p - s_m) / (2 * dom)
-    g_om += np.sum(xbar * (dD * s + cosmo.D(a0) * ds)) + np.sum(pbar * (dgp * s + cosmo.gp(a0) * ds))
+    g_om += add(np.sum(xbar * (dD * s + cosmo.D(a0) * ds)))
+    g_om += add(np.sum(pbar * (dgp * s + cosmo.gp(a0) * ds)))
     s_bar = cosmo.D(a0) * xbar + cosmo.gp(a0) * pbar
     noise_bar = ic_displacement_transpose(s_bar, cosmo, box)
     g_s8 = float(np.sum(s_bar * zeldovich_s)) / cosmo.sigma8

@@ -109,12 +109,15 @@ def shell_images(x, box, chi_near, chi_far, geom: MapGeometry):
 
 
 def project_shell(x, a_far, a_near, cosmo: Cosmology, box, np_side,
-                  geom: MapGeometry, include_mean=True, chi_bounds=None):
+                  geom: MapGeometry, include_mean=True, chi_bounds=None, src_cut=None):
     """Convergence of one PM step's shell, [nsrc][npix][npix].
 
     x are the positions at a_near (end of the step a_far -> a_near).
     `chi_bounds` = (chi_near, chi_far) overrides the shell's distance range
     (used to hold the shell partition fixed while the cosmology varies).
+    `src_cut[s]` overrides chi_s in the test "image in front of source s"
+    only (the weight keeps geom.chi_src): it holds that membership fixed
+    while the cosmology varies.
     """
     if chi_bounds is None:
         chi_far = float(cosmo.chi(a_far))
@@ -136,7 +139,7 @@ def project_shell(x, a_far, a_near, cosmo: Cosmology, box, np_side,
         t0, t1, chi = np.concatenate(t0s), np.concatenate(t1s), np.concatenate(chis)
         a = cosmo.a_of_chi_vec(chi)
         for s, chis_ in enumerate(geom.chi_src):
-            src = chi < chis_
+            src = chi < (chis_ if src_cut is None else src_cut[s])
             if not np.any(src):
                 continue
             w = pref * vp * (chis_ - chi[src]) / (chis_ * chi[src] * a[src]

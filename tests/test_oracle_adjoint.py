@@ -125,10 +125,10 @@ def test_sigma8_gradient_is_noise_scaling():
 @pytest.mark.parametrize("h", [1e-4, 1e-5])
 def test_cosmology_gradients_match_end_to_end_finite_difference(h):
     """Omega_m and sigma_8 cotangents against central differences of the whole
-    forward model with the shell partition (chi bounds of the shells) held at
-    the central cosmology: membership is piecewise constant and not
-    differentiated (a boundary crossing would otherwise put an O(1/h) jump
-    into the difference quotient)."""
+    forward model with the shell partition (chi bounds of the shells) and the
+    in-front-of-source test held at the central cosmology: membership is
+    piecewise constant and not differentiated (a boundary crossing would
+    otherwise put an O(1/h) jump into the difference quotient)."""
     c, np_side, nm, box, geom, a, noise, kbar = _loss_setup()
     nb, g_om, g_s8 = adjoint.kappa_vjp_cosmo(noise, kbar, c, box, nm, a, geom, dom=h)
     ref = adjoint.kappa_vjp_noise(noise, kbar, c, box, nm, a, geom)
@@ -138,10 +138,42 @@ def test_cosmology_gradients_match_end_to_end_finite_difference(h):
     def loss(om=0.3, s8=0.8):
         cc = Cosmology(om, sigma8=s8)
         gg = lens.MapGeometry(geom.npix, np.degrees(geom.fov), geom.z_src, cc)
-        k, _ = adjoint.forward_with_checkpoints(noise, cc, box, nm, a, gg, shell_chis=chis)
+        k, _ = adjoint.forward_with_checkpoints(noise, cc, box, nm, a, gg, shell_chis=chis,
+                                                src_cut=geom.chi_src)
         return np.sum(k * kbar)
     fd_om = (loss(om=0.3 + h) - loss(om=0.3 - h)) / (2 * h)
     fd_s8 = (loss(s8=0.8 + 1e-6) - loss(s8=0.8 - 1e-6)) / 2e-6
     assert abs(fd_s8 - g_s8) < 1e-5 * abs(g_s8)
     # both sides difference in Omega_m with the same h: they agree to O(h^2)
     assert abs(fd_om - g_om) < 2 * h * abs(g_om)
+
+
+def test_source_membership_hold_leaves_the_derivative_unchanged():
+    """The lens weight is continuous in chi_s (it vanishes at chi = chi_s), so
+    holding the in-front-of-source test at the central chi_s must give the
+    true derivative.  Shell a 0.4 -> 0.6 straddles the z = 1 source plane and
+    holds images 0.005 Mpc in front of it; a step h = 1e-7 in Omega_m moves
+    chi_s by 1.4e-4 Mpc and crosses none of them, a step 1e-5 (1.4e-2 Mpc)
+    does.  Held membership at 1e-5 must match the free difference at 1e-7."""
+    c = Cosmology(0.3)
+    geom = lens.MapGeometry(16, 3.0, (1.0,), c)
+    a = np.linspace(0.4, 1.0, 4)
+    _, states = adjoint.forward_with_checkpoints(W.white_noise(16, 11), c, 48.0, 32, a, geom)
+    kbar = np.random.default_rng(12).standard_normal((1, 16, 16))
+    x1 = states[1][0]
+    cb = (c.chi(a[1]), c.chi(a[0]))
+
+    def d(h, cut):
+        vals = []
+        for om in (0.3 + h, 0.3 - h):
+            cc = Cosmology(om)
+            g = lens.MapGeometry(16, 3.0, (1.0,), cc)
+            vals.append(np.sum(kbar * lens.project_shell(x1, a[0], a[1], cc, 48.0, 16, g,
+                                                         include_mean=False, chi_bounds=cb,
+                                                         src_cut=cut)))
+        return (vals[0] - vals[1]) / (2 * h)
+    ref = d(1e-7, None)
+    held = d(1e-5, geom.chi_src)
+    free = d(1e-5, None)
+    assert abs(held - ref) < 1e-6 * abs(ref)
+    assert abs(free - ref) > 1e-4 * abs(ref)     # the kink the hold avoids
