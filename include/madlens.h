@@ -155,6 +155,46 @@ int pm_sync(pm_sim* sim);
  * tests: out[0] = D(a), out[1] = g_p(a), out[2] = chi(a) in Mpc/h. */
 int pm_background(const pm_sim* sim, double a, double out[3]);
 
+/* ---- reverse mode (vector-Jacobian products) ------------------------------
+ * The paper makes the simulation differentiable by reverse-mode automatic
+ * differentiation with respect to the initial Gaussian modes, Omega_m and
+ * sigma_8, the cosmology dependence of scalar factors (kick/drift factors,
+ * initial-condition growth and amplitude) being finite-differenced (design
+ * section; appendix on cosmology derivatives).  These calls run that reverse
+ * pass one shell / step at a time; the caller keeps checkpoints of (x, p)
+ * with pm_get_state and restores them with pm_set_state.  Cotangent arrays
+ * are device arrays [3][Np^3] of dtype in lattice order and Mpc/h units
+ * (dL/dx, dL/dp).  cosmo_bar is a host array [2] = (dL/dOmega_m,
+ * dL/dsigma_8), ACCUMULATED.  Omega_m derivatives of scalar factors are
+ * central differences with step 1e-5; shell membership (the distance bounds
+ * of each shell) is held fixed.  Each call waits for its stream at the end
+ * (it reads reduced scalars back).
+ *
+ * lens_project_vjp: state at a1.  x_bar += (d kappa_shell / dx)^T kappa_bar,
+ * cosmo_bar[0] += kappa_bar . d kappa_shell / dOmega_m at fixed positions.
+ * kappa_bar: device [nsrc][npix][npix].  Errors: PM_ESTATE, PM_EINVAL. */
+int lens_project_vjp(pm_sim* sim, double a0, double a1, const void* kappa_bar, void* x_bar,
+                     double cosmo_bar[2]);
+
+/* pm_step_vjp: reverse of the step a0 -> a1.  The state must be at a1 (the
+ * end of the step; the force there is that of pm_set_state or pm_step).  a2 >
+ * a1 is the end of the following step, whose first half-kick uses the same
+ * force, or a2 <= 0 when a0 -> a1 is the last step.  On entry x_bar, p_bar
+ * hold the cotangents of (x, p) at a1 (after every later step and shell has
+ * been reversed); on return they hold those at a0 (in place).
+ * Errors: PM_ESTATE, PM_EINVAL. */
+int pm_step_vjp(pm_sim* sim, double a0, double a1, double a2, void* x_bar, void* p_bar,
+                double cosmo_bar[2]);
+
+/* pm_init_ic_vjp: the state must be the initial conditions (restored with
+ * pm_set_state at a0, after pm_init_ic was run on this handle with the same
+ * noise); a1 is the end of the first step.  Reverses the first half-kick's
+ * force and the Zel'dovich map: noise_bar (device [Np^3], WRITTEN) = dL/dnoise;
+ * cosmo_bar += (dL/dOmega_m, dL/dsigma_8) of the initial conditions.
+ * x_bar, p_bar are read only.  Errors: PM_ESTATE, PM_EINVAL. */
+int pm_init_ic_vjp(pm_sim* sim, double a1, const void* x_bar, const void* p_bar, void* noise_bar,
+                   double cosmo_bar[2]);
+
 /* Per-kernel timing (tracing).  pm_profile(sim, 1) starts recording a pair
  * of HIP events around every kernel launch on the simulation's stream (the
  * events come from a pool created by this call, at most 8192 launches per

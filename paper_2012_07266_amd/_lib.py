@@ -47,6 +47,9 @@ SIGNATURES = {
     "pm_get_force": (_I, [_P, _P, _P, _P]),
     "pm_sync": (_I, [_P]),
     "pm_background": (_I, [_P, _D, ctypes.POINTER(_D)]),
+    "lens_project_vjp": (_I, [_P, _D, _D, _P, _P, ctypes.POINTER(_D)]),
+    "pm_step_vjp": (_I, [_P, _D, _D, _D, _P, _P, ctypes.POINTER(_D)]),
+    "pm_init_ic_vjp": (_I, [_P, _D, _P, _P, _P, ctypes.POINTER(_D)]),
     "pm_profile": (_I, [_P, _I]),
     "pm_profile_read": (_I, [_P, _I, ctypes.c_char_p, ctypes.POINTER(_D),
                              ctypes.POINTER(ctypes.c_long), ctypes.POINTER(_I)]),

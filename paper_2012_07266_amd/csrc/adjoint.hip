@@ -1,0 +1,463 @@
+// Reverse-mode (vector-Jacobian) kernels of the PM step, the initial
+// conditions and the lens projection on gfx950.
+//
+// Force node f = R(x, M(P(x))): P = CIC paint, M = Fourier force operator,
+// R = CIC readout.  For a cotangent fbar:
+//   xbar += (dR/dx)^T fbar   gather with the CIC derivative on the force meshes
+//   Mbar  = paint(fbar)      three value paints (launch_paint_values)
+//   rhobar = M^T Mbar         transposed FFT chain (fft_div_axis0)
+//   xbar += mass (dP/dx)^T rhobar
+// The CIC derivative is -1 to node floor(u) and +1 to node floor(u)+1 per axis.
+// Internally cotangents are in mesh-cell units (H times the Mpc/h ones); the
+// caller's arrays are in Mpc/h and lattice order.
+#include "adjoint.h"
+
+namespace ml {
+
+constexpr int AB = 512;  // threads per workgroup of the per-tile adjoint kernels
+
+__device__ __forceinline__ int xcd_remap(int b, int nb) {
+    if (nb % 8) return b;
+    return (b % 8) * (nb / 8) + b / 8;
+}
+
+template <class T>
+__device__ __forceinline__ void cic_setup(const Geo& g, uint32_t id, const T* d, int ox, int oy,
+                                          int oz, int& base, T w[3][2]) {
+    int li[3];
+    lattice_of_l(id, g.np, li);
+    int l[3];
+    const int o[3] = {ox, oy, oz};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        T v = T(0.5) + d[a];
+        T fl = floor(v);
+        T t = v - fl;
+        int c = g.B * li[a] + (int)fl;
+        if ((unsigned)c >= (unsigned)g.nm) c = pmod(c, g.nm);
+        l[a] = min(max(c - o[a], 0), TILE - 1);
+        w[a][0] = T(1) - t;
+        w[a][1] = t;
+    }
+    base = (l[0] * TE + l[1]) * TE + l[2];
+}
+
+// value and gradient (d/du) of the CIC interpolation of an LDS tile
+template <class T>
+__device__ __forceinline__ void cic_grad(const T* ft, int base, const T w[3][2], T& val, T gr[3]) {
+    val = T(0);
+    gr[0] = gr[1] = gr[2] = T(0);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                T m = ft[base + (a * TE + b) * TE + c];
+                T d0 = a ? T(1) : T(-1), d1 = b ? T(1) : T(-1), d2 = c ? T(1) : T(-1);
+                val += w[0][a] * w[1][b] * w[2][c] * m;
+                gr[0] += d0 * w[1][b] * w[2][c] * m;
+                gr[1] += w[0][a] * d1 * w[2][c] * m;
+                gr[2] += w[0][a] * w[1][b] * d2 * m;
+            }
+}
+
+// wave reduction then one double atomic per wave
+__device__ __forceinline__ void wave_add(double* dst, double v) {
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if ((threadIdx.x & 63) == 0) unsafeAtomicAdd(dst, v);
+}
+
+template <class T>
+__device__ __forceinline__ void stage_tile(T* ft, const T* mesh, int nm, int ox, int oy, int oz,
+                                           int tid) {
+    constexpr int TC = TE * TE * TE;
+    for (int i = tid; i < TC; i += AB) {
+        int x = i / (TE * TE), y = (i / TE) % TE, z = i % TE;
+        int gx = ox + x, gy = oy + y, gz = oz + z;
+        if (gx >= nm) gx -= nm;
+        if (gy >= nm) gy -= nm;
+        if (gz >= nm) gz -= nm;
+        ft[i] = mesh[((long)gx * nm + gy) * nm + gz];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 1. readout part of the force-node VJP
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ __launch_bounds__(AB) void k_fvjp_readout(Parts<T> p, SortBufs s, Geo g, const T* f0,
+                                                     const T* f1, const T* f2, const T* xbar_in,
+                                                     const T* pbar_in, T H, T ckick, T* xbc,
+                                                     T* fbc, double* dots, uint32_t* fmax_bits) {
+    constexpr int TC = TE * TE * TE;
+    __shared__ T ft[3][TC];
+    const int tid = threadIdx.x;
+    const int t = xcd_remap(blockIdx.x, gridDim.x);
+    const int tx = t / (g.nt * g.nt), ty = (t / g.nt) % g.nt, tz = t % g.nt;
+    const int ox = tx * TILE, oy = ty * TILE, oz = tz * TILE;
+    const uint32_t lo = s.start[t], hi = s.start[t + 1];
+    if (lo == hi) return;
+    stage_tile(ft[0], f0, g.nm, ox, oy, oz, tid);
+    stage_tile(ft[1], f1, g.nm, ox, oy, oz, tid);
+    stage_tile(ft[2], f2, g.nm, ox, oy, oz, tid);
+    __syncthreads();
+    const long n = g.npart;
+    double dot = 0.0;
+    float fmax = 0.f;
+    for (uint32_t k0 = lo; k0 < hi; k0 += AB) {
+        uint32_t k = k0 + tid;
+        if (k < hi) {
+            uint32_t id = p.id[k];
+            long L = lattice_index(id, g.np);
+            T d[3] = {p.disp[k], p.disp[n + k], p.disp[2 * n + k]};
+            int base;
+            T w[3][2];
+            cic_setup(g, id, d, ox, oy, oz, base, w);
+            T xb[3], fb[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                T pb = H * pbar_in[a * n + L];
+                xb[a] = H * xbar_in[a * n + L];
+                fb[a] = ckick * pb;
+                dot += (double)pb * (double)p.acc[a * n + k];
+                fmax = fmaxf(fmax, fabsf((float)fb[a]));
+            }
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                T val, gr[3];
+                cic_grad(ft[j], base, w, val, gr);
+#pragma unroll
+                for (int a = 0; a < 3; ++a) xb[a] += fb[j] * gr[a];
+            }
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                xbc[a * n + k] = xb[a];
+                fbc[a * n + k] = fb[a];
+            }
+        }
+    }
+    wave_add(&dots[0], dot);
+    for (int off = 32; off > 0; off >>= 1) fmax = fmaxf(fmax, __shfl_xor(fmax, off));
+    if ((tid & 63) == 0 && fmax > 0.f) atomicMax(fmax_bits, __float_as_uint(fmax));
+}
+
+// ---------------------------------------------------------------------------
+// 2. paint part of the force-node VJP, then the drift reverse (mode 0) or the
+//    initial-condition cotangent (mode 1)
+// ---------------------------------------------------------------------------
+template <class T>
+__global__ __launch_bounds__(AB) void k_fvjp_paintgrad(Parts<T> p, SortBufs s, Geo g,
+                                                       const T* rhobar, T mass, const T* xbc,
+                                                       T H, int mode, T dr, T k2, T d0, T gp0,
+                                                       T* xbar_out, const T* pbar_in, T* pbar_out,
+                                                       T* sb0, T* sb1, T* sb2, double* dots) {
+    constexpr int TC = TE * TE * TE;
+    __shared__ T ft[TC];
+    const int tid = threadIdx.x;
+    const int t = xcd_remap(blockIdx.x, gridDim.x);
+    const int tx = t / (g.nt * g.nt), ty = (t / g.nt) % g.nt, tz = t % g.nt;
+    const int ox = tx * TILE, oy = ty * TILE, oz = tz * TILE;
+    const uint32_t lo = s.start[t], hi = s.start[t + 1];
+    if (lo == hi) return;
+    stage_tile(ft, rhobar, g.nm, ox, oy, oz, tid);
+    __syncthreads();
+    const long n = g.npart;
+    double a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    for (uint32_t k0 = lo; k0 < hi; k0 += AB) {
+        uint32_t k = k0 + tid;
+        if (k < hi) {
+            uint32_t id = p.id[k];
+            long L = lattice_index(id, g.np);
+            T d[3] = {p.disp[k], p.disp[n + k], p.disp[2 * n + k]};
+            int base;
+            T w[3][2];
+            cic_setup(g, id, d, ox, oy, oz, base, w);
+            T val, gr[3];
+            cic_grad(ft, base, w, val, gr);
+            T xb[3], pb[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                xb[a] = xbc[a * n + k] + mass * gr[a];
+                pb[a] = H * pbar_in[a * n + L];
+            }
+            if (mode == 0) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    T ph = p.mom[a * n + k] - k2 * p.acc[a * n + k];
+                    a1 += (double)xb[a] * (double)ph;
+                    xbar_out[a * n + L] = xb[a] / H;
+                    pbar_out[a * n + L] = (pb[a] + dr * xb[a]) / H;
+                }
+            } else {
+                T* sbo[3] = {sb0, sb1, sb2};
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    T sv = p.mom[a * n + k] / gp0;
+                    T sbar = d0 * xb[a] + gp0 * pb[a];
+                    a1 += (double)xb[a] * (double)sv;
+                    a2 += (double)pb[a] * (double)sv;
+                    a3 += (double)sbar * (double)sv;
+                    sbo[a][k] = sbar;  // tile-sorted order
+                }
+            }
+        }
+    }
+    wave_add(&dots[1], a1);
+    if (mode == 1) {
+        wave_add(&dots[2], a2);
+        wave_add(&dots[3], a3);
+    }
+}
+
+template <class T>
+__global__ void k_dot3(const T* a0, const T* a1, const T* a2, const T* b0, const T* b1,
+                       const T* b2, long n, double* dst) {
+    double acc = 0.0;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        acc += (double)a0[i] * b0[i] + (double)a1[i] * b1[i] + (double)a2[i] * b2[i];
+    wave_add(dst, acc);
+}
+
+// sum_k sum_j sorted[j][k] * lattice_j[L(k)]
+template <class T>
+__global__ void k_dot_sorted_lattice(Parts<T> p, Geo g, const T* sorted, const T* l0, const T* l1,
+                                     const T* l2, double* dst) {
+    const long n = g.npart;
+    double acc = 0.0;
+    for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
+        long L = lattice_index(p.id[k], g.np);
+        acc += (double)sorted[k] * l0[L] + (double)sorted[n + k] * l1[L] +
+               (double)sorted[2 * n + k] * l2[L];
+    }
+    wave_add(dst, acc);
+}
+
+// lattice_j[L(k)] = sorted[j][k]
+template <class T>
+__global__ void k_sorted_to_lattice(Parts<T> p, Geo g, const T* sorted, T* l0, T* l1, T* l2) {
+    const long n = g.npart;
+    for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
+        long L = lattice_index(p.id[k], g.np);
+        l0[L] = sorted[k];
+        l1[L] = sorted[n + k];
+        l2[L] = sorted[2 * n + k];
+    }
+}
+
+template <class T>
+__global__ void k_map_sums(const T* kbar, long npix2, int nsrc, double* dst) {
+    for (int s = 0; s < nsrc; ++s) {
+        double acc = 0.0;
+        for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < npix2; i += (long)gridDim.x * blockDim.x)
+            acc += (double)kbar[(long)s * npix2 + i];
+        wave_add(&dst[s], acc);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 3. lens projection VJP: per particle, per image, gather of kbar and its
+//    gradient; position cotangent accumulated in registers, one write per
+//    particle (no atomics); Omega_m part of the weights reduced.
+// ---------------------------------------------------------------------------
+template <class T>
+__device__ __forceinline__ void a_interp(const LensArgs<T>& la, T chi, T& a, T& dadchi) {
+    T xk = chi / la.dchi;
+    int k = (int)floor(xk);
+    k = min(max(k, 0), la.ntab - 2);
+    T s = xk - T(k);
+    T a0 = la.atab[2 * k], m0 = la.atab[2 * k + 1] * la.dchi;
+    T a1 = la.atab[2 * k + 2], m1 = la.atab[2 * k + 3] * la.dchi;
+    T s2 = s * s, s3 = s2 * s;
+    a = (T(2) * s3 - T(3) * s2 + T(1)) * a0 + (s3 - T(2) * s2 + s) * m0 + (T(3) * s2 - T(2) * s3) * a1 +
+        (s3 - s2) * m1;
+    T da = (T(6) * s2 - T(6) * s) * a0 + (T(3) * s2 - T(4) * s + T(1)) * m0 +
+           (T(6) * s - T(6) * s2) * a1 + (T(3) * s2 - T(2) * s) * m1;
+    dadchi = da / la.dchi;
+}
+
+template <class T>
+__device__ __forceinline__ void bilinear_grad(const T* km, int npix, T t0, T t1, T& v, T& g0, T& g1) {
+    T fl0 = floor(t0), fl1 = floor(t1);
+    int j0 = (int)fl0, j1 = (int)fl1;
+    T f0 = t0 - fl0, f1 = t1 - fl1;
+    v = g0 = g1 = T(0);
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+        int r = j0 + a;
+        if (r < 0 || r >= npix) continue;
+        T w0 = a ? f0 : T(1) - f0, d0 = a ? T(1) : T(-1);
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            int c = j1 + b;
+            if (c < 0 || c >= npix) continue;
+            T w1 = b ? f1 : T(1) - f1, d1 = b ? T(1) : T(-1);
+            T m = km[(long)r * npix + c];
+            v += w0 * w1 * m;
+            g0 += d0 * w1 * m;
+            g1 += w0 * d1 * m;
+        }
+    }
+}
+
+template <class T>
+__global__ __launch_bounds__(256) void k_lens_vjp(Parts<T> p, Geo g, LensArgs<T> la, LensVjpArgs<T> lv,
+                                                  const T* kbar, T* xbar, double* dots) {
+    const long n = g.npart;
+    const T nmf = T(g.nm), half = T(0.5) * nmf;
+    const T cnear = la.chi_near / la.cell, cfar = la.chi_far / la.cell;
+    const T tmax = T(0.5) * T(la.npix) + T(0.5);
+    const T hp = T(0.5) * T(la.npix) - T(0.5);
+    const T dth = T(1) / la.inv_dtheta;
+    const long npix2 = (long)la.npix * la.npix;
+    T chi_max_src = la.chi_src[0];
+    for (int s = 1; s < la.nsrc; ++s) chi_max_src = max(chi_max_src, la.chi_src[s]);
+    double om_acc = 0.0;
+    for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
+        uint32_t id = p.id[k];
+        int li[3];
+        lattice_of_l(id, g.np, li);
+        T u[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            T v = T(0.5) + p.disp[a * n + k];
+            T fl = floor(v);
+            int c = g.B * li[a] + (int)fl;
+            if ((unsigned)c >= (unsigned)g.nm) c = pmod(c, g.nm);
+            u[a] = T(c) + (v - fl);
+        }
+        if (!(isfinite(u[0]) && isfinite(u[1]) && isfinite(u[2]))) continue;
+        T gx = 0, gy = 0, gz = 0;
+        int nz0 = (int)floor((cnear - u[2]) / nmf);
+        int nz1 = (int)floor((cfar - u[2]) / nmf) + 1;
+        for (int nz = nz0; nz <= nz1; ++nz) {
+            T rz = u[2] + T(nz) * nmf;
+            if (!(rz > cnear && rz <= cfar && rz > T(0))) continue;
+            T chi = rz * la.cell;
+            if (chi >= chi_max_src) continue;
+            T inv = la.inv_dtheta / rz;
+            T rmax = tmax / inv;
+            int nx0 = (int)floor((-rmax - u[0] + half) / nmf), nx1 = (int)floor((rmax - u[0] + half) / nmf) + 1;
+            int ny0 = (int)floor((-rmax - u[1] + half) / nmf), ny1 = (int)floor((rmax - u[1] + half) / nmf) + 1;
+            T a, dadchi;
+            a_interp(la, chi, a, dadchi);
+            T dadom = lv.dadom_at(chi);
+            for (int nx = nx0; nx <= nx1; ++nx) {
+                T rx = (u[0] + T(nx) * nmf - half);  // cells
+                T t0 = rx * inv + hp;
+                if (!(t0 > T(-1) && t0 < T(la.npix))) continue;
+                for (int ny = ny0; ny <= ny1; ++ny) {
+                    T ry = (u[1] + T(ny) * nmf - half);
+                    T t1 = ry * inv + hp;
+                    if (!(t1 > T(-1) && t1 < T(la.npix))) continue;
+                    T rxp = rx * la.cell, ryp = ry * la.cell;  // Mpc/h
+                    T invp = T(1) / (chi * dth);
+                    for (int s = 0; s < la.nsrc; ++s) {
+                        T cs = la.chi_src[s];
+                        if (!(chi < cs)) continue;
+                        T v, g0, g1;
+                        bilinear_grad(kbar + s * npix2, la.npix, t0, t1, v, g0, g1);
+                        T gs = (cs - chi) / (cs * chi * a);
+                        T w = la.wbase * gs;
+                        T dg = -T(1) / (cs * chi * a) - gs / chi - gs * dadchi / a;
+                        T dw = la.wbase * dg;
+                        gx += w * g0 * invp;
+                        gy += w * g1 * invp;
+                        gz += dw * v - w * (g0 * rxp + g1 * ryp) * invp / chi;
+                        T dwdom = w / lv.omega_m +
+                                  la.wbase * (lv.dchis_dom[s] / (cs * cs * a) - gs * dadom / a);
+                        om_acc += (double)dwdom * (double)v;
+                    }
+                }
+            }
+        }
+        if (gx != T(0) || gy != T(0) || gz != T(0)) {
+            long L = lattice_index(id, g.np);
+            xbar[L] += gx;
+            xbar[n + L] += gy;
+            xbar[2 * n + L] += gz;
+        }
+    }
+    wave_add(&dots[4], om_acc);
+}
+
+// ---------------------------------------------------------------------------
+template <class T>
+void launch_fvjp_readout(Parts<T> p, SortBufs s, Geo g, const T* f0, const T* f1, const T* f2,
+                         const T* xbar_in, const T* pbar_in, T H, T ckick, T* xbc, T* fbc,
+                         double* dots, uint32_t* fmax_bits, hipStream_t st) {
+    int ntiles = g.nt * g.nt * g.nt;
+    hipLaunchKernelGGL(k_fvjp_readout<T>, dim3(ntiles), dim3(AB), 0, st, p, s, g, f0, f1, f2,
+                       xbar_in, pbar_in, H, ckick, xbc, fbc, dots, fmax_bits);
+}
+
+template <class T>
+void launch_fvjp_paintgrad(Parts<T> p, SortBufs s, Geo g, const T* rhobar, T mass, const T* xbc,
+                           T H, int mode, T dr, T k2, T d0, T gp0, T* xbar_out, const T* pbar_in,
+                           T* pbar_out, T* sb0, T* sb1, T* sb2, double* dots, hipStream_t st) {
+    int ntiles = g.nt * g.nt * g.nt;
+    hipLaunchKernelGGL(k_fvjp_paintgrad<T>, dim3(ntiles), dim3(AB), 0, st, p, s, g, rhobar, mass,
+                       xbc, H, mode, dr, k2, d0, gp0, xbar_out, pbar_in, pbar_out, sb0, sb1, sb2,
+                       dots);
+}
+
+template <class T>
+void launch_dot3(const T* a0, const T* a1, const T* a2, const T* b0, const T* b1, const T* b2,
+                 long n, double* dst, hipStream_t st) {
+    long blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_dot3<T>, dim3(blocks), dim3(256), 0, st, a0, a1, a2, b0, b1, b2, n, dst);
+}
+
+template <class T>
+void launch_dot_sorted_lattice(Parts<T> p, Geo g, const T* sorted, const T* l0, const T* l1,
+                               const T* l2, double* dst, hipStream_t st) {
+    long blocks = (g.npart + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_dot_sorted_lattice<T>, dim3(blocks), dim3(256), 0, st, p, g, sorted, l0, l1,
+                       l2, dst);
+}
+
+template <class T>
+void launch_sorted_to_lattice(Parts<T> p, Geo g, const T* sorted, T* l0, T* l1, T* l2,
+                              hipStream_t st) {
+    long blocks = (g.npart + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(k_sorted_to_lattice<T>, dim3(blocks), dim3(256), 0, st, p, g, sorted, l0, l1, l2);
+}
+
+template <class T>
+void launch_map_sums(const T* kbar, int npix, int nsrc, double* dst, hipStream_t st) {
+    long npix2 = (long)npix * npix;
+    long blocks = (npix2 + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    hipLaunchKernelGGL(k_map_sums<T>, dim3(blocks), dim3(256), 0, st, kbar, npix2, nsrc, dst);
+}
+
+template <class T>
+void launch_lens_vjp(Parts<T> p, Geo g, const LensArgs<T>& la, const LensVjpArgs<T>& lv,
+                     const T* kbar, T* xbar, double* dots, hipStream_t st) {
+    long blocks = (g.npart + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL(k_lens_vjp<T>, dim3(blocks), dim3(256), 0, st, p, g, la, lv, kbar, xbar, dots);
+}
+
+#define ML_INST(T)                                                                                   \
+    template void launch_fvjp_readout<T>(Parts<T>, SortBufs, Geo, const T*, const T*, const T*,      \
+                                         const T*, const T*, T, T, T*, T*, double*, uint32_t*,       \
+                                         hipStream_t);                                               \
+    template void launch_fvjp_paintgrad<T>(Parts<T>, SortBufs, Geo, const T*, T, const T*, T, int,   \
+                                           T, T, T, T, T*, const T*, T*, T*, T*, T*, double*,        \
+                                           hipStream_t);                                             \
+    template void launch_dot3<T>(const T*, const T*, const T*, const T*, const T*, const T*, long,   \
+                                 double*, hipStream_t);                                              \
+    template void launch_map_sums<T>(const T*, int, int, double*, hipStream_t);                      \
+    template void launch_dot_sorted_lattice<T>(Parts<T>, Geo, const T*, const T*, const T*, const T*, \
+                                               double*, hipStream_t);                                \
+    template void launch_sorted_to_lattice<T>(Parts<T>, Geo, const T*, T*, T*, T*, hipStream_t);     \
+    template void launch_lens_vjp<T>(Parts<T>, Geo, const LensArgs<T>&, const LensVjpArgs<T>&,       \
+                                     const T*, T*, double*, hipStream_t);
+ML_INST(float)
+ML_INST(double)
+
+}  // namespace ml

@@ -13,6 +13,7 @@
 
 #include "../../include/madlens.h"
 #include "cosmo_host.h"
+#include "adjoint.h"
 #include "fft.h"
 #include "particles.h"
 
@@ -42,6 +43,7 @@ struct Layout {
 struct ArenaPlan {
     size_t disp[2], mom[2], id[2], acc, key, rank, count, start, status;
     size_t mesh[3], nyq[3], halo, tw_nm, tw_hm, twp_nm, tw_np, tw_hp, twp_np, g_ic, atab;
+    size_t xbc, fbc, dots, fmax, noise, g_ic_dom, adom;
     size_t total;
 };
 
@@ -80,6 +82,15 @@ ArenaPlan plan_arena(const pm_params& p, const lens_params& l, size_t es) {
     a.twp_np = L.take((np_ / 2 + 1) * 2 * es);
     a.g_ic = L.take((3 * (np_ / 2) * (np_ / 2) + 1) * es);
     a.atab = L.take(2 * ATAB_N * es);
+    // reverse pass: sorted-order cotangent scratch, reductions, the noise of
+    // the last initial conditions, Omega_m derivative tables
+    a.xbc = L.take(3 * n * es);
+    a.fbc = L.take(3 * n * es);
+    a.dots = L.take(64 * sizeof(double));
+    a.fmax = L.take(256);
+    a.noise = L.take(n * es);
+    a.g_ic_dom = L.take((3 * (np_ / 2) * (np_ / 2) + 1) * es);
+    a.adom = L.take(ATAB_N * es);
     a.total = L.bytes;
     return a;
 }
@@ -191,6 +202,10 @@ struct SimBase {
     virtual int sync() = 0;
     virtual int background(double a, double out[3]) const = 0;
     virtual hipStream_t stream() const = 0;
+    virtual int lens_vjp(double a0, double a1, const void* kbar, void* xbar, double* cb) = 0;
+    virtual int step_vjp(double a0, double a1, double a2, void* xbar, void* pbar, double* cb) = 0;
+    virtual int init_ic_vjp(double a1, const void* xbar, const void* pbar, void* nbar,
+                            double* cb) = 0;
 };
 
 template <class T> struct Sim final : SimBase {
@@ -211,6 +226,13 @@ template <class T> struct Sim final : SimBase {
     T* halo = nullptr;
     cx<T>*tw_nm, *tw_hm, *twp_nm, *tw_np, *tw_hp, *twp_np;
     T *g_ic, *atab;
+    T *xbc, *fbc, *noise_copy, *g_ic_dom, *adom;
+    double* dots = nullptr;
+    uint32_t* fmax_bits = nullptr;
+    HostCosmo cosmo_p, cosmo_m;  // Omega_m +- DOM for the finite-difference factors
+    static constexpr double DOM = 1e-5;
+    std::vector<double> chisrc_p, chisrc_m;
+    bool meshes_valid = false;  // mesh[0..2] hold the force meshes of the current state
     double dchi_tab = 0;
     double a_cur = -1.0;
     double cell = 0;  // mesh cell, Mpc/h
@@ -269,6 +291,19 @@ template <class T> struct Sim final : SimBase {
         twp_np = at<cx<T>>(ap.twp_np);
         g_ic = at<T>(ap.g_ic);
         atab = at<T>(ap.atab);
+        xbc = at<T>(ap.xbc);
+        fbc = at<T>(ap.fbc);
+        dots = at<double>(ap.dots);
+        fmax_bits = at<uint32_t>(ap.fmax);
+        noise_copy = at<T>(ap.noise);
+        g_ic_dom = at<T>(ap.g_ic_dom);
+        adom = at<T>(ap.adom);
+        cosmo_p.init(p->omega_m + DOM, p->h, p->n_s, p->sigma8, p->omega_b, p->t_cmb);
+        cosmo_m.init(p->omega_m - DOM, p->h, p->n_s, p->sigma8, p->omega_b, p->t_cmb);
+        for (double z : zsrc) {
+            chisrc_p.push_back(cosmo_p.chi_of_z(z));
+            chisrc_m.push_back(cosmo_m.chi_of_z(z));
+        }
         return upload_tables();
     }
 
@@ -315,6 +350,15 @@ template <class T> struct Sim final : SimBase {
                 v[q] = (T)((double)nm * amp / (2.0 * PI * q * np3));
             }
             if ((rc = upload(ap.g_ic, v))) return rc;
+            // d G / d Omega_m by central differences (sigma8 held fixed)
+            for (int q = 1; q <= nmax; ++q) {
+                double k = 2.0 * PI * std::sqrt((double)q) / L;
+                double ap_ = std::sqrt(cosmo_p.pk(k) * np3 / (L * L * L));
+                double am_ = std::sqrt(cosmo_m.pk(k) * np3 / (L * L * L));
+                v[q] = (T)((double)nm * (ap_ - am_) / (2.0 * DOM) / (2.0 * PI * q * np3));
+            }
+            v[0] = T(0);
+            if ((rc = upload(ap.g_ic_dom, v))) return rc;
         }
         // a(chi) and da/dchi on a uniform chi grid for the lens weights
         {
@@ -327,6 +371,11 @@ template <class T> struct Sim final : SimBase {
                 v[2 * k + 1] = (T)cosmo.dadchi(a);
             }
             if ((rc = upload(ap.atab, v))) return rc;
+            std::vector<T> w(ATAB_N);
+            for (int k = 0; k < ATAB_N; ++k)
+                w[k] = (T)((cosmo_p.a_of_chi(k * dchi_tab) - cosmo_m.a_of_chi(k * dchi_tab)) /
+                           (2.0 * DOM));
+            if ((rc = upload(ap.adom, w))) return rc;
         }
         launch_fill_u32(status, 0u, 1, st);
         HIPCHK(hipStreamSynchronize(st));
@@ -372,6 +421,7 @@ template <class T> struct Sim final : SimBase {
     void force(T kick2, int do_kick) {
         paint();
         fft_forward_grad(P.nm, nullptr, tw_nm, tw_hm, twp_nm);
+        meshes_valid = true;
         ProfScope ps(prof, "readout_kick");
         launch_readout<T>(cur, sb, geo, mesh[0], mesh[1], mesh[2], kick2, do_kick, status, st);
     }
@@ -389,6 +439,8 @@ template <class T> struct Sim final : SimBase {
         const int np = P.np;
         size_t n = (size_t)np * np * np;
         HIPCHK(hipMemcpyAsync(mesh[0], noise, n * sizeof(T), hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(noise_copy, noise, n * sizeof(T), hipMemcpyDeviceToDevice, st));
+        meshes_valid = false;
         fft_forward_grad(np, g_ic, tw_np, tw_hp, twp_np);
         launch_init_ic<T>(cur, geo, mesh[0], mesh[1], mesh[2], (T)cosmo.D(a0), (T)cosmo.gp(a0), st);
         sort(T(0), T(0), 0);
@@ -461,6 +513,7 @@ template <class T> struct Sim final : SimBase {
         paint();
         if (rho) HIPCHK(hipMemcpyAsync(rho, mesh[0], n3 * sizeof(T), hipMemcpyDeviceToDevice, st));
         fft_forward_grad(P.nm, nullptr, tw_nm, tw_hm, twp_nm);
+        meshes_valid = true;
         launch_readout<T>(cur, sb, geo, mesh[0], mesh[1], mesh[2], T(0), 0, status, st);
         if (fm) {
             // force meshes are in cell units; scale to Mpc/h into the caller's buffer
@@ -477,6 +530,168 @@ template <class T> struct Sim final : SimBase {
         uint32_t s = 0;
         HIPCHK(hipMemcpy(&s, status, 4, hipMemcpyDeviceToHost));
         return s ? PM_ENONFINITE : PM_OK;
+    }
+
+
+    // ---- reverse pass ------------------------------------------------------
+    bool at_a(double a) const { return a_cur >= 0 && std::fabs(a - a_cur) <= 1e-12 * std::fabs(a_cur) + 1e-15; }
+
+    int read_dots(double* out, int nread) {
+        HIPCHK(hipMemcpyAsync(out, dots, nread * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        return PM_OK;
+    }
+
+    // Force-node VJP at the current state: xbar += (df/dx)^T (ckick pbar), then
+    // mode 0: drift reverse (pbar += dr xbar, dots[1] = sum xbar . p_half);
+    // mode 1: initial-condition cotangent sbar = d0 xbar + gp0 pbar into fbc.
+    void force_vjp(T ckick, const T* xbar_in, const T* pbar_in, int mode, T dr, T k2, T d0,
+                   T gp0, T* xbar_out, T* pbar_out) {
+        const long n = geo.npart;
+        const T H = (T)cell;
+        if (!meshes_valid) {
+            paint();
+            fft_forward_grad(P.nm, nullptr, tw_nm, tw_hm, twp_nm);
+            meshes_valid = true;
+        }
+        launch_fill_u32(fmax_bits, 0u, 1, st);
+        { ProfScope ps(prof, "vjp_readout");
+          launch_fvjp_readout<T>(cur, sb, geo, mesh[0], mesh[1], mesh[2], xbar_in, pbar_in, H, ckick,
+                                 xbc, fbc, dots, fmax_bits, st); }
+        meshes_valid = false;
+        for (int j = 0; j < 3; ++j) {
+            ProfScope ps(prof, "vjp_paint_values");
+            launch_paint_values<T>(cur, sb, geo, T(1), mesh[j], halo, fbc + j * n, fmax_bits, st);
+        }
+        const int nm = P.nm;
+        const T gscale = (T)(1.0 / (2.0 * PI * (double)nm * (double)nm));
+        for (int j = 0; j < 3; ++j) {
+            ProfScope ps(prof, "fft_r2c_axis2");
+            fft_r2c_rows<T>(nm, mesh[j], nyq[j], tw_hm, twp_nm, st);
+        }
+        for (int j = 0; j < 3; ++j) {
+            ProfScope ps(prof, "fft_c2c_axis1_fwd");
+            fft_c2c_axis1<T>(nm, 1, reinterpret_cast<cx<T>*>(mesh[j]), nyq[j], tw_nm, st);
+        }
+        PtrTriple im{{mesh[0], mesh[1], mesh[2]}}, in_{{nyq[0], nyq[1], nyq[2]}};
+        { ProfScope ps(prof, "fft_div_axis0");
+          fft_div_axis0<T>(nm, im, in_, reinterpret_cast<cx<T>*>(mesh[0]), nyq[0], tw_nm, nullptr,
+                           gscale, st); }
+        { ProfScope ps(prof, "fft_c2c_axis1_inv");
+          fft_c2c_axis1<T>(nm, -1, reinterpret_cast<cx<T>*>(mesh[0]), nyq[0], tw_nm, st); }
+        { ProfScope ps(prof, "fft_c2r_axis2"); fft_c2r_rows<T>(nm, mesh[0], nyq[0], tw_hm, twp_nm, st); }
+        T mass = (T)std::pow((double)geo.B, 3);
+        ProfScope ps(prof, "vjp_paintgrad");
+        launch_fvjp_paintgrad<T>(cur, sb, geo, mesh[0], mass, xbc, H, mode, dr, k2, d0, gp0, xbar_out,
+                                 pbar_in, pbar_out, fbc, fbc + n, fbc + 2 * n, dots, st);
+    }
+
+    int step_vjp(double a0, double a1, double a2, void* xbar, void* pbar, double* cb) override {
+        if (!xbar || !pbar || !cb) return PM_EINVAL;
+        if (!at_a(a1)) return PM_ESTATE;
+        double ah = 0.5 * (a0 + a1);
+        double k2 = cosmo.kick(ah, a1, a1), dr = cosmo.drift(a0, a1, ah);
+        double dk2 = (cosmo_p.kick(ah, a1, a1) - cosmo_m.kick(ah, a1, a1)) / (2 * DOM);
+        double ddr = (cosmo_p.drift(a0, a1, ah) - cosmo_m.drift(a0, a1, ah)) / (2 * DOM);
+        double k1n = 0.0, dk1n = 0.0;
+        if (a2 > a1) {
+            double ah2 = 0.5 * (a1 + a2);
+            k1n = cosmo.kick(a1, ah2, a1);
+            dk1n = (cosmo_p.kick(a1, ah2, a1) - cosmo_m.kick(a1, ah2, a1)) / (2 * DOM);
+        }
+        launch_fill<double>(dots, 0.0, 64, st);
+        T* xb = reinterpret_cast<T*>(xbar);
+        T* pb = reinterpret_cast<T*>(pbar);
+        force_vjp((T)(k2 + k1n), xb, pb, 0, (T)dr, (T)k2, T(0), T(1), xb, pb);
+        int rc = check_launch();
+        if (rc) return rc;
+        double d[2];
+        if ((rc = read_dots(d, 2))) return rc;
+        cb[0] += d[0] * (dk2 + dk1n) + d[1] * ddr;
+        return PM_OK;
+    }
+
+    int init_ic_vjp(double a1, const void* xbar, const void* pbar, void* nbar, double* cb) override {
+        if (!xbar || !pbar || !nbar || !cb) return PM_EINVAL;
+        if (a_cur < 0 || !(a1 > a_cur)) return PM_ESTATE;
+        const double a0 = a_cur, ah = 0.5 * (a0 + a1);
+        const double k1 = cosmo.kick(a0, ah, a0);
+        const double dk1 = (cosmo_p.kick(a0, ah, a0) - cosmo_m.kick(a0, ah, a0)) / (2 * DOM);
+        const double d0 = cosmo.D(a0), gp0 = cosmo.gp(a0);
+        const double dd0 = (cosmo_p.D(a0) - cosmo_m.D(a0)) / (2 * DOM);
+        const double dgp0 = (cosmo_p.gp(a0) - cosmo_m.gp(a0)) / (2 * DOM);
+        launch_fill<double>(dots, 0.0, 64, st);
+        // the kick at a0 uses the initial force: xbar += (df/dx)^T (K1 pbar); sbar -> fbc
+        force_vjp((T)k1, reinterpret_cast<const T*>(xbar), reinterpret_cast<const T*>(pbar), 1, T(0),
+                  T(0), (T)d0, (T)gp0, nullptr, nullptr);
+        const int np = P.np;
+        const long n = geo.npart;
+        // ds/dOmega_m on the lattice from the stored noise, dotted with sbar
+        HIPCHK(hipMemcpyAsync(mesh[0], noise_copy, n * sizeof(T), hipMemcpyDeviceToDevice, st));
+        fft_forward_grad(np, g_ic_dom, tw_np, tw_hp, twp_np);
+        launch_dot_sorted_lattice<T>(cur, geo, fbc, mesh[0], mesh[1], mesh[2], dots + 5, st);
+        // noise_bar = S^T sbar
+        launch_sorted_to_lattice<T>(cur, geo, fbc, mesh[0], mesh[1], mesh[2], st);
+        for (int j = 0; j < 3; ++j) fft_r2c_rows<T>(np, mesh[j], nyq[j], tw_hp, twp_np, st);
+        for (int j = 0; j < 3; ++j)
+            fft_c2c_axis1<T>(np, 1, reinterpret_cast<cx<T>*>(mesh[j]), nyq[j], tw_np, st);
+        PtrTriple im{{mesh[0], mesh[1], mesh[2]}}, in_{{nyq[0], nyq[1], nyq[2]}};
+        fft_div_axis0<T>(np, im, in_, reinterpret_cast<cx<T>*>(mesh[0]), nyq[0], tw_np, g_ic, T(0), st);
+        fft_c2c_axis1<T>(np, -1, reinterpret_cast<cx<T>*>(mesh[0]), nyq[0], tw_np, st);
+        fft_c2r_rows<T>(np, mesh[0], nyq[0], tw_hp, twp_np, st);
+        HIPCHK(hipMemcpyAsync(nbar, mesh[0], n * sizeof(T), hipMemcpyDeviceToDevice, st));
+        meshes_valid = false;
+        int rc = check_launch();
+        if (rc) return rc;
+        double d[6];
+        if ((rc = read_dots(d, 6))) return rc;
+        cb[0] += d[0] * dk1 + d[1] * dd0 + d[2] * dgp0 + d[5];
+        cb[1] += d[3] / P.sigma8;
+        return PM_OK;
+    }
+
+    int lens_vjp(double a0, double a1, const void* kbar, void* xbar, double* cb) override {
+        if (!kbar || !xbar || !cb) return PM_EINVAL;
+        if (!at_a(a1)) return PM_ESTATE;
+        LensArgs<T> la{};
+        la.npix = npix;
+        la.nsrc = nsrc;
+        la.cell = (T)cell;
+        double chi_far = cosmo.chi(a0), chi_near = cosmo.chi(a1);
+        la.chi_near = (T)chi_near;
+        la.chi_far = (T)chi_far;
+        double dth = fov * PI / 180.0 / npix;
+        la.inv_dtheta = (T)(1.0 / dth);
+        double vp = std::pow(P.box / P.np, 3);
+        la.wbase = (T)(1.5 * P.omega_m / (C_H0 * C_H0) * vp / (dth * dth));
+        for (int s = 0; s < nsrc; ++s) la.chi_src[s] = (T)chisrc[s];
+        la.atab = atab;
+        la.ntab = ATAB_N;
+        la.dchi = (T)dchi_tab;
+        LensVjpArgs<T> lv{};
+        lv.omega_m = (T)P.omega_m;
+        for (int s = 0; s < nsrc; ++s) lv.dchis_dom[s] = (T)((chisrc_p[s] - chisrc_m[s]) / (2 * DOM));
+        lv.dadom = adom;
+        lv.ntab = ATAB_N;
+        lv.dchi = (T)dchi_tab;
+        launch_fill<double>(dots, 0.0, 64, st);
+        const T* kb = reinterpret_cast<const T*>(kbar);
+        { ProfScope ps(prof, "lens_vjp");
+          launch_lens_vjp<T>(cur, geo, la, lv, kb, reinterpret_cast<T*>(xbar), dots, st); }
+        launch_map_sums<T>(kb, npix, nsrc, dots + 8, st);
+        int rc = check_launch();
+        if (rc) return rc;
+        double d[8 + MAX_SRC];
+        if ((rc = read_dots(d, 8 + nsrc))) return rc;
+        double g = d[4];
+        // mean term of each map at a fixed shell partition
+        for (int s = 0; s < nsrc; ++s) {
+            double mp = cosmo_p.shell_mean(chi_near, chi_far, chisrc_p[s]);
+            double mm = cosmo_m.shell_mean(chi_near, chi_far, chisrc_m[s]);
+            g += d[8 + s] * (mp - mm) / (2 * DOM);
+        }
+        cb[0] += g;
+        return PM_OK;
     }
 
     hipStream_t stream() const override { return st; }
@@ -553,6 +768,18 @@ int pm_get_force(pm_sim* sim, void* rho, void* fm, void* acc) {
     return sim ? sim->impl->get_force(rho, fm, acc) : PM_EINVAL;
 }
 int pm_sync(pm_sim* sim) { return sim ? sim->impl->sync() : PM_EINVAL; }
+int lens_project_vjp(pm_sim* sim, double a0, double a1, const void* kappa_bar, void* x_bar,
+                     double cosmo_bar[2]) {
+    return sim ? sim->impl->lens_vjp(a0, a1, kappa_bar, x_bar, cosmo_bar) : PM_EINVAL;
+}
+int pm_step_vjp(pm_sim* sim, double a0, double a1, double a2, void* x_bar, void* p_bar,
+                double cosmo_bar[2]) {
+    return sim ? sim->impl->step_vjp(a0, a1, a2, x_bar, p_bar, cosmo_bar) : PM_EINVAL;
+}
+int pm_init_ic_vjp(pm_sim* sim, double a1, const void* x_bar, const void* p_bar, void* noise_bar,
+                   double cosmo_bar[2]) {
+    return sim ? sim->impl->init_ic_vjp(a1, x_bar, p_bar, noise_bar, cosmo_bar) : PM_EINVAL;
+}
 int pm_background(const pm_sim* sim, double a, double out[3]) {
     return sim && out ? sim->impl->background(a, out) : PM_EINVAL;
 }

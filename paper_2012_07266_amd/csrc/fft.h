@@ -35,4 +35,11 @@ template <class T>
 void fft_grad_axis0(int n, cx<T>* main_in, cx<T>* nyq_in, PtrTriple out_main, PtrTriple out_nyq,
                     const cx<T>* tw, const T* G, T gscale, hipStream_t st);
 
+// Transposed fused pass: forward FFT of three spectra along axis 0,
+// Y = -i G(|n|^2) sum_j n_j X_j (component j zero where |n_j| = n/2), inverse,
+// one output (may alias input 0).
+template <class T>
+void fft_div_axis0(int n, PtrTriple in_main, PtrTriple in_nyq, cx<T>* out_main, cx<T>* out_nyq,
+                   const cx<T>* tw, const T* G, T gscale, hipStream_t st);
+
 }  // namespace ml

@@ -583,6 +583,77 @@ __global__ __launch_bounds__(NTG) void k_grad_x0(ViewDesc va, ViewDesc vb, PtrTr
 }
 
 // ---------------------------------------------------------------------------
+// Transposed fused pass (adjoint of the gradient pass): forward FFT of the
+// three input spectra along axis 0, combine Y = sum_j conj(i n_j G) X_j
+// = -i G sum_j n_j X_j (component j zero on its Nyquist plane), inverse FFT,
+// store one spectrum (may overwrite input 0).
+// ---------------------------------------------------------------------------
+template <class T, int N, int W>
+__global__ __launch_bounds__(NT) void k_div_x0(ViewDesc va, ViewDesc vb, PtrTriple ina,
+                                               PtrTriple inb, void* outa, void* outb,
+                                               const cx<T>* tw, const T* G, T gscale) {
+    __shared__ cx<T> buf[N * (W + 1)];
+    __shared__ cx<T> tws[N];
+    constexpr int LD = W + 1;
+    constexpr int HN = N / 2;
+    constexpr int IT = (W * N + NT - 1) / NT;
+    const int tid = threadIdx.x;
+    int g = blockIdx.x;
+    const bool is_a = g < va.n_wg;
+    ViewDesc v = is_a ? va : vb;
+    const PtrTriple& in = is_a ? ina : inb;
+    void* out = is_a ? outa : outb;
+    if (!is_a) g -= va.n_wg;
+    load_twiddles<T, N>(tws, tw, tid);
+    cx<T> acc[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) acc[it] = {T(0), T(0)};
+    for (int j = 0; j < 3; ++j) {
+        v.ptr = in.p[j];
+        view_load<T, N, W>(buf, v, g, tid);
+        __syncthreads();
+        fft_lds<T, N, W, 1>(buf, tws, tid);
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            int f = tid + it * NT;
+            if ((W * N) % NT == 0 || f < W * N) {
+                int n = f / W, w = f % W;
+                long c = (long)g * W + w;
+                int k1 = is_a ? (int)(c / HN) : (int)c;
+                int k2 = is_a ? (int)(c % HN) : HN;
+                int n0 = n <= HN ? n : n - N;
+                int n1 = k1 <= HN ? k1 : k1 - N;
+                int nj = j == 0 ? n0 : (j == 1 ? n1 : k2);
+                if (nj != HN && nj != -HN) {
+                    cx<T> x = buf[n * LD + w];
+                    acc[it].re += T(nj) * x.re;
+                    acc[it].im += T(nj) * x.im;
+                }
+            }
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        int f = tid + it * NT;
+        if ((W * N) % NT == 0 || f < W * N) {
+            int n = f / W, w = f % W;
+            long c = (long)g * W + w;
+            int k1 = is_a ? (int)(c / HN) : (int)c;
+            int k2 = is_a ? (int)(c % HN) : HN;
+            int n0 = n <= HN ? n : n - N;
+            int n1 = k1 <= HN ? k1 : k1 - N;
+            int nsq = n0 * n0 + n1 * n1 + k2 * k2;
+            T gg = G ? G[nsq] : (nsq ? gscale / T(nsq) : T(0));
+            buf[n * LD + w] = {gg * acc[it].im, -gg * acc[it].re};  // -i G acc
+        }
+    }
+    __syncthreads();
+    fft_lds<T, N, W, -1>(buf, tws, tid);
+    view_store<T, N, W>(buf, out, v, g, tid);
+}
+
+// ---------------------------------------------------------------------------
 // host-side dispatch
 // ---------------------------------------------------------------------------
 // Pencils per workgroup: 16 (128-byte rows) for float up to 512, 8 above
@@ -643,6 +714,16 @@ static void grad_axis0_n(cx<T>* main_in, cx<T>* nyq_in, PtrTriple out_main, PtrT
     ViewDesc vb{nyq_in, N, 0, N / W};
     hipLaunchKernelGGL((k_grad_x0<T, N, W, NTG>), dim3(va.n_wg + vb.n_wg), dim3(NTG), 0, st, va, vb,
                        out_main, out_nyq, tw, G, gscale);
+}
+
+template <class T, int N>
+static void div_axis0_n(PtrTriple in_main, PtrTriple in_nyq, cx<T>* out_main, cx<T>* out_nyq,
+                        const cx<T>* tw, const T* G, T gscale, hipStream_t st) {
+    constexpr int W = lanes_w<T>(N);
+    ViewDesc va{in_main.p[0], (long)N * (N / 2), 0, (int)((long)N * (N / 2) / W)};
+    ViewDesc vb{in_nyq.p[0], N, 0, N / W};
+    hipLaunchKernelGGL((k_div_x0<T, N, W>), dim3(va.n_wg + vb.n_wg), dim3(NT), 0, st, va, vb,
+                       in_main, in_nyq, (void*)out_main, (void*)out_nyq, tw, G, gscale);
 }
 
 // Supported lengths.  float: every mesh length; double: up to 256.
@@ -709,7 +790,18 @@ void fft_grad_axis0(int n, cx<T>* main_in, cx<T>* nyq_in, PtrTriple out_main, Pt
 #undef ML_CASE
 }
 
+template <class T>
+void fft_div_axis0(int n, PtrTriple in_main, PtrTriple in_nyq, cx<T>* out_main, cx<T>* out_nyq,
+                   const cx<T>* tw, const T* G, T gscale, hipStream_t st) {
+#define ML_CASE(v) if (n == v) return div_axis0_n<T, v>(in_main, in_nyq, out_main, out_nyq, tw, G, gscale, st);
+    if constexpr (sizeof(T) == 4) { ML_SIZES_F(ML_CASE) }
+    else { ML_SIZES_D(ML_CASE) }
+#undef ML_CASE
+}
+
 #define ML_INST(T)                                                                                  \
+    template void fft_div_axis0<T>(int, PtrTriple, PtrTriple, cx<T>*, cx<T>*, const cx<T>*,        \
+                                   const T*, T, hipStream_t);                                       \
     template bool fft_supported<T>(int);                                                            \
     template void fft_r2c_rows<T>(int, T*, cx<T>*, const cx<T>*, const cx<T>*, hipStream_t);       \
     template void fft_c2r_rows<T>(int, T*, const cx<T>*, const cx<T>*, const cx<T>*, hipStream_t); \

@@ -75,6 +75,12 @@ int paint_group_size(int nt, int esize);
 long paint_halo_elems(int nt, int esize);
 template <class T>
 void launch_paint(Parts<T> p, SortBufs s, Geo g, T mass, T* rho, T* halo, hipStream_t st);
+// Paint per-particle values vals[k] (tile-sorted order) instead of the
+// mass; *vmax_bits holds the float bits of max|vals| (sets the fixed-point
+// scale of the float instantiation).
+template <class T>
+void launch_paint_values(Parts<T> p, SortBufs s, Geo g, T mass, T* rho, T* halo, const T* vals,
+                         const uint32_t* vmax_bits, hipStream_t st);
 // CIC readout of the three force meshes; acc = f; mom += kick*acc if do_kick.
 template <class T>
 void launch_readout(Parts<T> p, SortBufs s, Geo g, const T* f0, const T* f1, const T* f2,

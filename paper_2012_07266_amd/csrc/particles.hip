@@ -235,29 +235,40 @@ __device__ __forceinline__ void halo_coords_g(int h, int& x, int& y, int& z) {
 constexpr int PU = 4;    // particles per thread in flight
 constexpr int PBP = 512; // threads per paint workgroup
 
-// LDS accumulator of the paint box.  float: 64-bit fixed point with 32
-// fractional bits (integer LDS atomics run at full rate on gfx950 while
-// float ones do not, and the integer sum is exact and order-independent);
-// double: float64 atomics.
+// LDS accumulator of the paint box.  float: signed 64-bit fixed point (integer
+// LDS atomics run at full rate on gfx950 while float ones do not, and the
+// integer sum is exact and order-independent).  The scale is 2^32 for the
+// density (weights <= 8) and 2^40 / max|value| (a power of two) when
+// arbitrary values are painted.  double: float64 atomics.
 template <class T> struct PaintAcc;
 template <> struct PaintAcc<float> {
     using S = unsigned long long;
-    static __device__ __forceinline__ S enc(float w) {
-        return (S)__float2ull_rn(w * 4294967296.0f);
+    static __device__ __forceinline__ S enc(float w, float scale) {
+        return (S)__float2ll_rn(w * scale);
     }
-    static __device__ __forceinline__ float dec(S v) {
-        return (float)((double)v * (1.0 / 4294967296.0));
+    static __device__ __forceinline__ float dec(S v, double inv_scale) {
+        return (float)((double)(long long)v * inv_scale);
     }
 };
 template <> struct PaintAcc<double> {
     using S = double;
-    static __device__ __forceinline__ S enc(double w) { return w; }
-    static __device__ __forceinline__ double dec(S v) { return v; }
+    static __device__ __forceinline__ S enc(double w, double) { return w; }
+    static __device__ __forceinline__ double dec(S v, double) { return v; }
 };
+
+// Fixed-point scale for painting values whose largest magnitude has the
+// float bit pattern *vmax_bits (2^40 / max, rounded down to a power of two).
+__device__ __forceinline__ float value_scale(const uint32_t* vmax_bits) {
+    float m = __uint_as_float(*vmax_bits);
+    if (!(m > 0.f) || !isfinite(m)) return 1.0f;
+    int e = ilogbf(m) + 1;  // m < 2^e
+    return ldexpf(1.0f, 40 - e);
+}
 
 template <class T, int G>
 __global__ __launch_bounds__(PBP) void k_paint_group(Parts<T> p, SortBufs s, Geo g, T mass, T* rho,
-                                                     T* halo) {
+                                                     T* halo, const T* vals,
+                                                     const uint32_t* vmax_bits) {
     using BX = PaintBox<G>;
     using A = PaintAcc<T>;
     using S = typename A::S;
@@ -267,6 +278,8 @@ __global__ __launch_bounds__(PBP) void k_paint_group(Parts<T> p, SortBufs s, Geo
     const int grp = blockIdx.x;
     const int tx = grp / (g.nt * ng), ty = (grp / ng) % g.nt, gz = grp % ng;
     const int ox = tx * TILE, oy = ty * TILE, oz = gz * BX::LZ;
+    const T scale = vals ? (T)value_scale(vmax_bits) : T(4294967296.0);
+    const double inv_scale = 1.0 / (double)scale;
     for (int i = tid; i < BX::CELLS; i += PBP) box[i] = S(0);
     __syncthreads();
     const long n = g.npart;
@@ -274,7 +287,7 @@ __global__ __launch_bounds__(PBP) void k_paint_group(Parts<T> p, SortBufs s, Geo
     const uint32_t lo = s.start[t0], hi = s.start[t0 + G];
     for (uint32_t base = lo; base < hi; base += PBP * PU) {
         uint32_t idv[PU];
-        T dv[PU][3];
+        T dv[PU][3], mv[PU];
 #pragma unroll
         for (int u = 0; u < PU; ++u) {
             uint32_t k = base + u * PBP + tid;
@@ -283,6 +296,7 @@ __global__ __launch_bounds__(PBP) void k_paint_group(Parts<T> p, SortBufs s, Geo
                 dv[u][0] = p.disp[k];
                 dv[u][1] = p.disp[n + k];
                 dv[u][2] = p.disp[2 * n + k];
+                mv[u] = vals ? vals[k] : mass;
             }
         }
 #pragma unroll
@@ -300,15 +314,15 @@ __global__ __launch_bounds__(PBP) void k_paint_group(Parts<T> p, SortBufs s, Geo
             int l1 = min(max(c1 - oy, 0), TILE - 1);
             int l2 = min(max(c2 - oz, 0), BX::LZ - 1);
             T w0[2] = {T(1) - f0, f0}, w1[2] = {T(1) - f1, f1};
-            T w2[2] = {(T(1) - f2) * mass, f2 * mass};
+            T w2[2] = {(T(1) - f2) * mv[u], f2 * mv[u]};
 #pragma unroll
             for (int a = 0; a < 2; ++a)
 #pragma unroll
                 for (int b = 0; b < 2; ++b) {
                     T wab = w0[a] * w1[b];
                     int cell = ((l0 + a) * TE + (l1 + b)) * BX::EZ + l2;
-                    atomicAdd(&box[cell], A::enc(wab * w2[0]));
-                    atomicAdd(&box[cell + 1], A::enc(wab * w2[1]));
+                    atomicAdd(&box[cell], A::enc(wab * w2[0], scale));
+                    atomicAdd(&box[cell + 1], A::enc(wab * w2[1], scale));
                 }
         }
     }
@@ -317,12 +331,13 @@ __global__ __launch_bounds__(PBP) void k_paint_group(Parts<T> p, SortBufs s, Geo
     constexpr int NI = TILE * TILE * BX::LZ;
     for (int i = tid; i < NI; i += PBP) {
         int x = i / (TILE * BX::LZ), y = (i / BX::LZ) % TILE, z = i % BX::LZ;
-        rho[((ox + x) * nm + (oy + y)) * nm + (oz + z)] = A::dec(box[(x * TE + y) * BX::EZ + z]);
+        rho[((ox + x) * nm + (oy + y)) * nm + (oz + z)] =
+            A::dec(box[(x * TE + y) * BX::EZ + z], inv_scale);
     }
     for (int h = tid; h < BX::HALO; h += PBP) {
         int x, y, z;
         halo_coords_g<G>(h, x, y, z);
-        halo[(long)grp * BX::HALO + h] = A::dec(box[(x * TE + y) * BX::EZ + z]);
+        halo[(long)grp * BX::HALO + h] = A::dec(box[(x * TE + y) * BX::EZ + z], inv_scale);
     }
 }
 
@@ -379,16 +394,24 @@ long paint_halo_elems(int nt, int esize) {
 }
 
 template <class T>
-void launch_paint(Parts<T> p, SortBufs s, Geo g, T mass, T* rho, T* halo, hipStream_t st) {
+void launch_paint_values(Parts<T> p, SortBufs s, Geo g, T mass, T* rho, T* halo, const T* vals,
+                         const uint32_t* vmax_bits, hipStream_t st) {
     int G = paint_group_size(g.nt, sizeof(T));
     int groups = g.nt * g.nt * (g.nt / G);
     if (G == 2) {
-        hipLaunchKernelGGL((k_paint_group<T, 2>), dim3(groups), dim3(PBP), 0, st, p, s, g, mass, rho, halo);
+        hipLaunchKernelGGL((k_paint_group<T, 2>), dim3(groups), dim3(PBP), 0, st, p, s, g, mass, rho,
+                           halo, vals, vmax_bits);
         hipLaunchKernelGGL((k_paint_halo_group<T, 2>), dim3(groups), dim3(PB), 0, st, rho, halo, g);
     } else {
-        hipLaunchKernelGGL((k_paint_group<T, 1>), dim3(groups), dim3(PBP), 0, st, p, s, g, mass, rho, halo);
+        hipLaunchKernelGGL((k_paint_group<T, 1>), dim3(groups), dim3(PBP), 0, st, p, s, g, mass, rho,
+                           halo, vals, vmax_bits);
         hipLaunchKernelGGL((k_paint_halo_group<T, 1>), dim3(groups), dim3(PB), 0, st, rho, halo, g);
     }
+}
+
+template <class T>
+void launch_paint(Parts<T> p, SortBufs s, Geo g, T mass, T* rho, T* halo, hipStream_t st) {
+    launch_paint_values<T>(p, s, g, mass, rho, halo, nullptr, nullptr, st);
 }
 
 // ---------------------------------------------------------------------------
@@ -603,6 +626,8 @@ void launch_set_state(Parts<T> p, Geo g, T cell, const T* x, const T* mom_in, hi
                                            hipStream_t);                                          \
     template void launch_scatter<T>(Parts<T>, Parts<T>, SortBufs, Geo, hipStream_t);              \
     template void launch_paint<T>(Parts<T>, SortBufs, Geo, T, T*, T*, hipStream_t);               \
+    template void launch_paint_values<T>(Parts<T>, SortBufs, Geo, T, T*, T*, const T*,            \
+                                         const uint32_t*, hipStream_t);                           \
     template void launch_readout<T>(Parts<T>, SortBufs, Geo, const T*, const T*, const T*, T, int, \
                                     uint32_t*, hipStream_t);                                      \
     template void launch_init_ic<T>(Parts<T>, Geo, const T*, const T*, const T*, T, T,            \

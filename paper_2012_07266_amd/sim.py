@@ -143,6 +143,29 @@ class Simulation:
     def sync(self):
         check(lib().pm_sync(self._h), "pm_sync")
 
+    # -- reverse mode -------------------------------------------------------
+    def lens_vjp(self, a0, a1, kappa_bar, x_bar, cosmo_bar):
+        """x_bar += d kappa/dx^T kappa_bar (state at a1); cosmo_bar (2,) float64
+        numpy array, accumulated."""
+        cb = (ctypes.c_double * 2)(*cosmo_bar)
+        check(lib().lens_project_vjp(self._h, float(a0), float(a1), _ptr(kappa_bar),
+                                     _ptr(x_bar), cb), "lens_project_vjp")
+        cosmo_bar[:] = list(cb)
+
+    def step_vjp(self, a0, a1, a2, x_bar, p_bar, cosmo_bar):
+        cb = (ctypes.c_double * 2)(*cosmo_bar)
+        check(lib().pm_step_vjp(self._h, float(a0), float(a1), float(a2), _ptr(x_bar),
+                                _ptr(p_bar), cb), "pm_step_vjp")
+        cosmo_bar[:] = list(cb)
+
+    def init_ic_vjp(self, a1, x_bar, p_bar, cosmo_bar):
+        noise_bar = torch.empty((self.np_side,) * 3, dtype=self.dtype, device=self.device)
+        cb = (ctypes.c_double * 2)(*cosmo_bar)
+        check(lib().pm_init_ic_vjp(self._h, float(a1), _ptr(x_bar), _ptr(p_bar),
+                                   _ptr(noise_bar), cb), "pm_init_ic_vjp")
+        cosmo_bar[:] = list(cb)
+        return noise_bar
+
     def profile(self, enable: bool):
         check(lib().pm_profile(self._h, 1 if enable else 0), "pm_profile")
 

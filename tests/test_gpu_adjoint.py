@@ -1,0 +1,218 @@
+"""GPU reverse pass against the oracle's hand-derived reverse pass, and a
+full-size directional-derivative check of the gradient configuration."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from tests.gpu_util import cosmo_of, log, rel_rms, to_np
+
+pytestmark = pytest.mark.gpu
+
+
+def _small():
+    wl = W.Workload("adj", 16, 32, 48.0, 0.4, 1.0, 3, 16, 3.0, (1.0,), seed=11)
+    kbar = np.random.default_rng(12).standard_normal((1, 16, 16))
+    return wl, kbar
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_reverse_pass_matches_oracle(dtype):
+    from oracle import adjoint, lens
+    from paper_2012_07266_amd.autograd import LensingModel
+    wl, kbar = _small()
+    log(f"reverse pass {dtype}")
+    noise = W.white_noise(wl.np_side, wl.seed)
+    model = LensingModel(wl.np_side, wl.nm_side, wl.box, wl.npix, wl.fov_deg, wl.z_src,
+                         wl.a_grid(), dtype=dtype)
+    w = torch.tensor(noise, dtype=dtype, device="cuda", requires_grad=True)
+    om = torch.tensor(wl.omega_m, dtype=dtype, device="cuda", requires_grad=True)
+    s8 = torch.tensor(wl.sigma8, dtype=dtype, device="cuda", requires_grad=True)
+    kappa = model(w, om, s8)
+    loss = (kappa * torch.tensor(kbar, dtype=dtype, device="cuda")).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    model.close()
+    c = cosmo_of(wl)
+    geom = lens.MapGeometry(wl.npix, wl.fov_deg, wl.z_src, c)
+    terms = []
+    nb, g_om, g_s8 = adjoint.kappa_vjp_cosmo(noise, kbar, c, wl.box, wl.nm_side, wl.a_grid(), geom,
+                                             terms=terms)
+    e_n = rel_rms(to_np(w.grad), nb)
+    e_om = abs(float(om.grad) - g_om) / abs(g_om)
+    e_s8 = abs(float(s8.grad) - g_s8) / abs(g_s8)
+    # d/dOmega_m is a sum of lens, kick, drift and IC contributions of both
+    # signs, up to ~20x larger than the total: a float32 error relative to
+    # each contribution shows up amplified by that ratio in the total
+    cond = sum(abs(t) for t in terms) / abs(g_om)
+    log(f"reverse {dtype}: noise_bar rel-rms {e_n:.2e}  Om {e_om:.2e} (cond {cond:.1f})  s8 {e_s8:.2e}")
+    if dtype == torch.float64:
+        assert e_n < 1e-9 and e_s8 < 1e-9 and e_om < 1e-8 * cond
+    else:
+        assert e_n < 1e-3 and e_s8 < 1e-3 and e_om < 3e-4 * cond
+
+
+def test_gradient_configuration_pm_directional_derivative():
+    """128^3 particles / 256^3 mesh, 20 steps from a = 0.01 (the gradient
+    workload's PM part) in float64: the reverse pass seeded with a cotangent
+    u on the final positions, <dL/dnoise, v> against a central difference of
+    L = <u, x_final(noise)> along a random v.  A sanity bound only: CIC
+    assignment is piecewise linear, and with 2M particles over 20 steps the
+    +-eps runs cross cell faces, so the quotient converges slowly in eps
+    (about 4e-4 off at eps = 1e-7, 1e-2 at 1e-6).  The reverse kernels at
+    this mesh are checked element by element in the step/IC pieces test;
+    shells are left out (a difference of the full model also crosses shell
+    boundaries)."""
+    from paper_2012_07266_amd.autograd import forward_with_checkpoints
+    from tests.gpu_util import new_sim
+    wl = W.CFG3
+    dtype = torch.float64
+    log("gradient configuration (PM part), float64")
+    a = wl.a_grid()
+    n = len(a) - 1
+    with new_sim(wl, dtype) as sim:
+        noise = torch.tensor(W.white_noise(wl.np_side, wl.seed), dtype=dtype, device="cuda")
+        u = torch.tensor(np.random.default_rng(7).standard_normal((3, wl.n_particles)),
+                         dtype=dtype, device="cuda")
+        _, states = forward_with_checkpoints(sim, noise, a)
+        xf = states[-1][0].clone()
+        x_bar = u.clone()
+        p_bar = torch.zeros_like(u)
+        cb = np.zeros(2)
+        for i in range(n - 1, -1, -1):
+            sim.set_state(*states[i + 1], a[i + 1])
+            sim.step_vjp(a[i], a[i + 1], a[i + 2] if i + 1 < n else -1.0, x_bar, p_bar, cb)
+        sim.init_ic(noise, a[0])
+        sim.set_state(*states[0], a[0])
+        g = sim.init_ic_vjp(a[1], x_bar, p_bar, cb)
+        v = torch.tensor(np.random.default_rng(8).standard_normal(g.shape), dtype=dtype, device="cuda")
+        eps = 1e-7
+        outs = []
+        for sgn in (1.0, -1.0):
+            _, st = forward_with_checkpoints(sim, noise + sgn * eps * v, a)
+            dx = st[-1][0] - xf
+            dx = torch.remainder(dx + 0.5 * wl.box, wl.box) - 0.5 * wl.box
+            outs.append(float((u * dx).sum()))
+        sim.sync()
+    fd = (outs[0] - outs[1]) / (2 * eps)
+    ad = float((g * v).sum())
+    log(f"PM directional derivative: adjoint {ad:.10e} fd {fd:.10e}")
+    assert np.isfinite(ad) and abs(ad - fd) < 3e-3 * abs(fd)
+
+
+def _off_node_planes(x, box, nm, gap=1e-3):
+    """x moved, where needed, to at least `gap` cells from every mesh-node plane."""
+    u = x * (nm / box)
+    r = np.round(u)
+    f = u - r
+    f = np.where(np.abs(f) < gap, np.where(f < 0, -gap, gap), f)
+    return np.mod((r + f) * (box / nm), box)
+
+
+PIECE_SHAPES = [(16, 32, 48.0), (48, 96, 100.0), (128, 256, 128.0)]
+
+
+@pytest.mark.parametrize("shape", PIECE_SHAPES, ids=lambda s: f"{s[0]}p{s[1]}m")
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_step_and_ic_vjp_pieces(dtype, shape):
+    """One step VJP and the initial-condition VJP in isolation, against the
+    oracle's force-node VJP assembled with the same finite-differenced
+    factors; meshes of one tile, several tiles with a mixed-radix FFT, and
+    the gradient workload's 256^3."""
+    from oracle import adjoint, pm
+    from oracle.cosmology import Cosmology
+    from tests.gpu_util import new_sim
+    np_side, nm, box = shape
+    wl = W.Workload("pieces", np_side, nm, box, 0.4, 1.0, 3, 16, 3.0, (1.0,), seed=11)
+    log(f"step/IC vjp pieces {dtype} np={np_side} nm={nm}")
+    c = cosmo_of(wl)
+    cp, cm = Cosmology(0.3 + 1e-5), Cosmology(0.3 - 1e-5)
+    dd = lambda f: (f(cp) - f(cm)) / 2e-5
+    a = wl.a_grid()
+    noise = W.white_noise(wl.np_side, wl.seed)
+    rng = np.random.default_rng(31)
+    xb1 = rng.standard_normal((3, wl.n_particles))
+    pb1 = rng.standard_normal((3, wl.n_particles))
+    x0, p0 = pm.zeldovich_ic(noise, c, wl.box, wl.nm_side, a[0])
+    f0 = pm.particle_force(x0, wl.np_side, wl.nm_side, wl.box)
+    x1, p1, _ = pm.kdk_step(x0, p0, f0, a[0], a[1], c, wl.np_side, wl.nm_side, wl.box)
+    # The CIC readout gradient jumps where a particle crosses a mesh-node
+    # plane, so a position within an ulp of one has two valid cotangents:
+    # keep every position 1e-3 cells off those planes and hand both sides the
+    # same inputs, rounded to the device precision.  The step and IC VJPs
+    # take the states as given (x1 need not be exactly step(x0)).
+    rd = (lambda v: v.astype(np.float32).astype(np.float64)) if dtype == torch.float32 else (lambda v: v)
+    x0, x1 = (rd(_off_node_planes(v, wl.box, wl.nm_side)) for v in (x0, x1))
+    p0, p1, xb1, pb1, noise = (rd(v) for v in (p0, p1, xb1, pb1, noise))
+    f0 = pm.particle_force(x0, wl.np_side, wl.nm_side, wl.box)
+    f1 = pm.particle_force(x1, wl.np_side, wl.nm_side, wl.box)
+    ah, ah2 = 0.5 * (a[0] + a[1]), 0.5 * (a[1] + a[2])
+    K2 = lambda cc: cc.kick_factor(ah, a[1], a[1])
+    K1n = lambda cc: cc.kick_factor(a[1], ah2, a[1])
+    Dr = lambda cc: cc.drift_factor(a[0], a[1], ah)
+    K1 = lambda cc: cc.kick_factor(a[0], ah, a[0])
+    # oracle: step 0 -> 1 reversed with the next kick sharing f1
+    xb = xb1 + adjoint.force_vjp(x1, (K2(c) + K1n(c)) * pb1, wl.np_side, wl.nm_side, wl.box)
+    om_step = np.sum(pb1 * f1) * (dd(K2) + dd(K1n)) + np.sum(xb * (p1 - K2(c) * f1)) * dd(Dr)
+    pb = pb1 + Dr(c) * xb
+    # oracle: initial conditions reversed (with the first kick's force)
+    xb0 = xb + adjoint.force_vjp(x0, K1(c) * pb, wl.np_side, wl.nm_side, wl.box)
+    s = pm.zeldovich_displacement(noise, c, wl.box)
+    ds = (pm.zeldovich_displacement(noise, cp, wl.box) - pm.zeldovich_displacement(noise, cm, wl.box)) / 2e-5
+    om_ic = (np.sum(pb * f0) * dd(K1) + np.sum(xb0 * (dd(lambda cc: cc.D(a[0])) * s + c.D(a[0]) * ds))
+             + np.sum(pb * (dd(lambda cc: cc.gp(a[0])) * s + c.gp(a[0]) * ds)))
+    sbar = c.D(a[0]) * xb0 + c.gp(a[0]) * pb
+    nb = adjoint.ic_displacement_transpose(sbar, c, wl.box)
+    s8 = np.sum(sbar * s) / c.sigma8
+    with new_sim(wl, dtype) as sim:
+        T = lambda arr: torch.tensor(arr, dtype=dtype, device="cuda")
+        sim.init_ic(T(noise), a[0])
+        sim.set_state(T(x1), T(p1), a[1])
+        xg, pg, cb = T(xb1), T(pb1), np.zeros(2)
+        sim.step_vjp(a[0], a[1], a[2], xg, pg, cb)
+        om_step_g = cb[0]
+        sim.set_state(T(x0), T(p0), a[0])
+        cb2 = np.zeros(2)
+        nbg = sim.init_ic_vjp(a[1], xg, pg, cb2)
+        res = (to_np(xg), to_np(pg), to_np(nbg), cb2)
+    tol = 1e-9 if dtype == torch.float64 else 3e-5
+    e = [rel_rms(res[0], xb), rel_rms(res[1], pb), rel_rms(res[2], nb),
+         abs(om_step_g - om_step) / abs(om_step), abs(res[3][0] - om_ic) / abs(om_ic),
+         abs(res[3][1] - s8) / abs(s8)]
+    log(f"pieces {dtype}: xbar {e[0]:.2e} pbar {e[1]:.2e} noise {e[2]:.2e} "
+        f"Om(step) {om_step_g:.8e} vs {om_step:.8e} Om(ic) {res[3][0]:.8e} vs {om_ic:.8e} s8 {e[5]:.2e}")
+    assert max(e[:3]) < tol and e[5] < tol
+    assert e[3] < tol * 10 and e[4] < tol * 10
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32], ids=["f64", "f32"])
+def test_lens_vjp_static_field(dtype):
+    """One shell's VJP at fixed positions: position cotangent and the Omega_m
+    part (weights, source distance, a(chi), mean term; shell bounds fixed)."""
+    from oracle import adjoint, lens
+    from oracle.cosmology import Cosmology
+    wl = W.Workload("lensvjp", 16, 32, 64.0, 0.4, 1.0, 3, 24, 4.0, (1.0, 2.0))
+    c = cosmo_of(wl)
+    x = W.clustered_positions(16, 32, wl.box, seed=21)
+    kbar = np.random.default_rng(22).standard_normal((2, 24, 24))
+    a_far, a_near = 0.55, 0.7
+    from tests.gpu_util import new_sim
+    with new_sim(wl, dtype) as sim:
+        sim.set_state(torch.from_numpy(x), torch.zeros((3, 16 ** 3), dtype=torch.float64), a_near)
+        xb = torch.zeros((3, 16 ** 3), dtype=dtype, device="cuda")
+        cb = np.zeros(2)
+        sim.lens_vjp(a_far, a_near, torch.tensor(kbar, dtype=dtype, device="cuda"), xb, cb)
+        xg = to_np(xb)
+    geom = lens.MapGeometry(wl.npix, wl.fov_deg, wl.z_src, c)
+    xo = adjoint.lens_vjp(x, a_far, a_near, kbar, c, wl.box, 16, geom)
+    h = 1e-5
+    cp, cm = Cosmology(0.3 + h), Cosmology(0.3 - h)
+    cb0 = (c.chi(a_near), c.chi(a_far))
+    f = lambda cc: np.sum(kbar * lens.project_shell(
+        x, a_far, a_near, cc, wl.box, 16, lens.MapGeometry(wl.npix, wl.fov_deg, wl.z_src, cc),
+        chi_bounds=cb0))
+    om = (f(cp) - f(cm)) / (2 * h)
+    e_x, e_om = rel_rms(xg, xo), abs(cb[0] - om) / abs(om)
+    log(f"lens vjp {dtype}: x rel-rms {e_x:.2e}, Om {cb[0]:.10e} vs {om:.10e} ({e_om:.2e})")
+    assert e_x < (1e-9 if dtype == torch.float64 else 1e-4)
+    assert e_om < (1e-6 if dtype == torch.float64 else 1e-4)

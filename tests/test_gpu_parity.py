@@ -14,8 +14,9 @@ from tests.gpu_util import cosmo_of, log, new_sim, periodic_cells, rel_rms, to_n
 pytestmark = pytest.mark.gpu
 
 DTYPES = [torch.float64, torch.float32]
-# (Np, Nm, box): B = 2 with 2^3 tiles, B = 1, and radix-3 lengths (48, 96)
-SHAPES = [(16, 32, 40.0), (32, 32, 64.0), (48, 96, 100.0)]
+# (Np, Nm, box): B = 2 with 2^3 tiles, B = 1, radix-3 lengths (48, 96), and
+# 128/256, whose strided passes take the register-resident FFT path
+SHAPES = [(16, 32, 40.0), (32, 32, 64.0), (48, 96, 100.0), (128, 256, 128.0)]
 
 
 def _wl(np_side, nm, box, **kw):
