@@ -422,8 +422,11 @@ __global__ __launch_bounds__(NT) void k_c2c_view(ViewDesc va, ViewDesc vb, const
 // out[j] are the bases of the three spectra (main or nyq part, matching va
 // or vb); out[0] may equal the input.
 // ---------------------------------------------------------------------------
+// With 512 threads the bound asks for 4 waves per SIMD, i.e. two workgroups
+// per CU, so that one workgroup's loads and stores overlap the other's
+// transforms.
 template <class T, int N, int W, int NTG>
-__global__ __launch_bounds__(NTG) void k_grad_x0(ViewDesc va, ViewDesc vb, PtrTriple outa,
+__global__ __launch_bounds__(NTG, (NTG == 512 ? 4 : 1)) void k_grad_x0(ViewDesc va, ViewDesc vb, PtrTriple outa,
                                                 PtrTriple outb, const cx<T>* tw, const T* G, T gscale) {
     __shared__ cx<T> buf[N * (W + 1)];
     __shared__ cx<T> tws[N];
@@ -442,16 +445,21 @@ __global__ __launch_bounds__(NTG) void k_grad_x0(ViewDesc va, ViewDesc vb, PtrTr
 
     if constexpr (reg_path_ok<N, W, NTG>()) {
         constexpr int E = W * N / NTG;
-        const cx<T>* src = reinterpret_cast<const cx<T>*>(v.ptr);
+        static_assert(NTG % W == 0, "a thread keeps one column");
+        // Register slot (it, q) of a radix-R pattern holds row
+        // tid / W + it * (NTG / W) + q * (N / R) of column tid % W: one
+        // per-thread element offset plus a row count known at compile time
+        // times the (uniform) row stride.
+        const int wcol = tid % W;
+        const long tbase = view_offset<T, N, W>(v, g, wcol, tid / W);
+        const long C = v.C;
+        const cx<T>* src = reinterpret_cast<const cx<T>*>(v.ptr) + tbase;
         cx<T> spec[E];
 #pragma unroll
         for (int it = 0; it < E / R0; ++it)
 #pragma unroll
-            for (int q = 0; q < R0; ++q) {
-                int w, n;
-                slot_pos<N, W, R0, NTG>(tid, it, q, w, n);
-                spec[it * R0 + q] = src[view_offset<T, N, W>(v, g, w, n)];
-            }
+            for (int q = 0; q < R0; ++q)
+                spec[it * R0 + q] = src[(long)(it * (NTG / W) + q * (N / R0)) * C];
         __syncthreads();
         reg_compute<T, N, W, R0, 1, 1, NTG>(spec, tws, tid);
         reg_chain<T, N, W, 1, 1, NTG>(spec, buf, tws, tid);
@@ -462,19 +470,18 @@ __global__ __launch_bounds__(NTG) void k_grad_x0(ViewDesc va, ViewDesc vb, PtrTr
             reg_read_lds<T, N, W, R0, NTG>(spec, buf, tid);
             __syncthreads();
         }
-        // spec[it*R0 + q] holds k0 = i + q*N/R0 of pencil w; replace it by
-        // h = i G(|n|^2) spec so that component j is just n_j h
+        // spec[it*R0 + q] holds k0 = tid/W + it*(NTG/W) + q*N/R0 of pencil
+        // wcol; replace it by h = i G(|n|^2) spec so that component j is
+        // just n_j h
+        const long c = (long)g * W + wcol;
+        const int k1 = is_a ? (int)(c / HN) : (int)c;
+        const int k2 = is_a ? (int)(c % HN) : HN;
+        const int n1 = k1 <= HN ? k1 : k1 - N;
 #pragma unroll
         for (int it = 0; it < E / R0; ++it) {
-            int b = tid + it * NTG, w = b % W;
-            long c = (long)g * W + w;
-            int k1 = is_a ? (int)(c / HN) : (int)c;
-            int k2 = is_a ? (int)(c % HN) : HN;
-            int n1 = k1 <= HN ? k1 : k1 - N;
 #pragma unroll
             for (int q = 0; q < R0; ++q) {
-                int ww, k0;
-                slot_pos<N, W, R0, NTG>(tid, it, q, ww, k0);
+                int k0 = tid / W + it * (NTG / W) + q * (N / R0);
                 int n0 = k0 <= HN ? k0 : k0 - N;
                 int nsq = n0 * n0 + n1 * n1 + k2 * k2;
                 T gg = G ? G[nsq] : (nsq ? gscale / T(nsq) : T(0));
@@ -487,15 +494,9 @@ __global__ __launch_bounds__(NTG) void k_grad_x0(ViewDesc va, ViewDesc vb, PtrTr
             cx<T> u[E];
 #pragma unroll
             for (int it = 0; it < E / R0; ++it) {
-                int b = tid + it * NTG, w = b % W;
-                long c = (long)g * W + w;
-                int k1 = is_a ? (int)(c / HN) : (int)c;
-                int k2 = is_a ? (int)(c % HN) : HN;
-                int n1 = k1 <= HN ? k1 : k1 - N;
 #pragma unroll
                 for (int q = 0; q < R0; ++q) {
-                    int ww, k0;
-                    slot_pos<N, W, R0, NTG>(tid, it, q, ww, k0);
+                    int k0 = tid / W + it * (NTG / W) + q * (N / R0);
                     int n0 = k0 <= HN ? k0 : k0 - N;
                     int nj = j == 0 ? n0 : (j == 1 ? n1 : k2);
                     T m = (nj == HN || nj == -HN) ? T(0) : T(nj);
@@ -504,15 +505,12 @@ __global__ __launch_bounds__(NTG) void k_grad_x0(ViewDesc va, ViewDesc vb, PtrTr
             }
             reg_compute<T, N, W, R0, 1, -1, NTG>(u, tws, tid);
             reg_chain<T, N, W, -1, 1, NTG>(u, buf, tws, tid);
-            cx<T>* dst = reinterpret_cast<cx<T>*>(out.p[j]);
+            cx<T>* dst = reinterpret_cast<cx<T>*>(out.p[j]) + tbase;
 #pragma unroll
             for (int it = 0; it < E / RL; ++it)
 #pragma unroll
-                for (int q = 0; q < RL; ++q) {
-                    int w, n;
-                    slot_pos<N, W, RL, NTG>(tid, it, q, w, n);
-                    dst[view_offset<T, N, W>(v, g, w, n)] = u[it * RL + q];
-                }
+                for (int q = 0; q < RL; ++q)
+                    dst[(long)(it * (NTG / W) + q * (N / RL)) * C] = u[it * RL + q];
             __syncthreads();  // the next component reuses buf
         }
         return;
