@@ -12,6 +12,12 @@ regenerated (untimed) and K consecutive steps of the schedule are timed
 region, if K exceeds it).  Per-kernel durations come from HIP events the
 library records on its own stream during the timed region.
 
+The line also carries the serving figures named by the metric: p50/p99
+latency (arrival to maps on the host) and throughput of Poisson streams of
+mixed-size requests, served (continuous batching) and plain (one
+simulation at a time), see serving_bench; and the float64 oracle timed on
+a bounded sample of the same step (cpu_baseline).
+
 Prints ONE JSON line.
 """
 from __future__ import annotations
@@ -47,8 +53,9 @@ def algorithmic_bytes(wl, esize=4):
         "paint": 16 * P + M,               # R disp,id  W rho
         "fft_r2c_axis2": M + S,
         "fft_c2c_axis1_fwd": 2 * S,
-        "fft_grad_axis0": 4 * S,           # R 1 spectrum, W 3
+        "fft_grad_axis0": 3 * S,           # R 1 spectrum, W 2
         "fft_c2c_axis1_inv": 2 * S,
+        "fft_c2c_axis1_dual": 3 * S,       # R 1 spectrum, W 2
         "fft_c2r_axis2": S + M,
         "readout_kick": 3 * M + 52 * P,    # R 3 meshes, disp,id,mom  W mom,acc
         "lens_gather": 16 * P + 2 * maps,  # R disp,id  RW maps (incl. mean term)
@@ -63,6 +70,7 @@ KERNEL_SYMBOL = {
     "readout_kick": ("k_readout<float>", "paper_2012_07266_amd/csrc/particles.hip"),
     "paint": ("k_paint_group<float", "paper_2012_07266_amd/csrc/particles.hip"),
     "fft_c2c_axis1_inv": ("k_c2c_view<float, 512, 16, -1>", "paper_2012_07266_amd/csrc/fft.hip"),
+    "fft_c2c_axis1_dual": ("k_c2c_view_dual<float, 512", "paper_2012_07266_amd/csrc/fft.hip"),
     "fft_c2r_axis2": ("k_c2r_rows<float, 256", "paper_2012_07266_amd/csrc/fft.hip"),
     "lens_gather": ("k_lens_gather<float>", "paper_2012_07266_amd/csrc/lens.hip"),
 }
@@ -172,6 +180,32 @@ def cpu_baseline(wl, frac=8):
                        f"float64 FFT force; {t4 - t0:.1f} s of CPU work, est. {per_step:.1f} s/step")}
 
 
+def serving_bench(n_requests):
+    """Poisson streams of serving requests: sizes 64^3/128^3, 128^3/256^3,
+    192^3/384^3 (box = Np Mpc/h), 10-30 steps from a = 0.1, Om ~ U[0.25, 0.35],
+    s8 ~ U[0.7, 0.9], one 512^2 map over 2 deg at z_s = 1; served (up to 8
+    concurrent, continuous batching) against plain (one at a time, FIFO),
+    at 20 requests/s and at a saturating 100 requests/s."""
+    import workloads as W
+    from paper_2012_07266_amd.serve import poisson_arrivals, run_stream
+    gen = np.random.Generator(np.random.Philox(key=6))
+    reqs = [W.serve_request(i, gen) for i in range(n_requests)]
+    budget = 64 << 30
+    res = {"workload": (f"{n_requests} requests, sizes uniform over 64^3/128^3, 128^3/256^3, "
+                        "192^3/384^3, 10-30 steps, 1 x 512^2 map; Poisson arrivals"),
+           "hbm_budget_gb": budget / 2 ** 30, "served_max_active": 8}
+    for rate in (20.0, 100.0):
+        arr = poisson_arrivals(n_requests, rate, seed=int(rate))
+        row = {}
+        for form, act in (("served", 8), ("plain", 1)):
+            r, _ = run_stream(reqs, arr, budget, act)
+            row[form] = {"p50_ms": r.latency_p50_ms, "p99_ms": r.latency_p99_ms,
+                         "mean_ms": r.latency_mean_ms, "particle_steps_per_s": r.throughput,
+                         "makespan_s": r.makespan_s, "peak_running": r.peak_running}
+        res[f"rate_{int(rate)}_per_s"] = row
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -181,6 +215,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="no per-kernel events in the timed region (roofline omitted)")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the serving streams (p50/p99 latency, served vs plain)")
+    ap.add_argument("--serve-requests", type=int, default=100)
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 1 GiB device copy (counter calibration for --pmc runs)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -279,6 +316,8 @@ def main():
                            "traffic": load_traffic(dom)}
         out["hbm_effective_gbs_all_kernels"] = total_bytes / (total_ms * 1e-3) / 1e9
         out["kernels"] = kern
+    if not args.no_serving:
+        out["serving"] = serving_bench(args.serve_requests)
     out["paper_context"] = ("MADLens on 32 Haswell cores: ~6.2e6 particle-steps/s "
                             "(256^3, 11 steps, 30 s incl. projection; different workload)")
     if not args.no_cpu_baseline:

@@ -51,7 +51,7 @@ extern "C" {
 #define PM_EDEVICE     -3   /* a HIP runtime call failed                     */
 #define PM_ESTATE      -4   /* the simulation is not in the required state   */
 #define PM_ENONFINITE  -5   /* a kernel produced a non-finite position       */
-#define PM_EFULL       -6   /* a batch has no free slot                      */
+#define PM_EAGAIN      -7   /* not finished yet (serving)                    */
 
 #define PM_F32 0
 #define PM_F64 1
@@ -111,6 +111,26 @@ int pm_destroy(pm_sim* sim);
  * farthest source plane). */
 int pm_init_ic(pm_sim* sim, const void* noise, double a0);
 
+/* The same initial conditions from noise drawn on the device from `seed`:
+ * element i of the Np^3 lattice (C order) is normal i of a counter-based
+ * stream, Philox4x64-10 (Salmon et al., SC 2011) with key (seed, 0); block c
+ * uses counter (c + 1, 0, 0, 0), its four words w become uniforms
+ * u = (w >> 11) 2^-53 and, pairwise, normals by Box-Muller:
+ * r = sqrt(-2 ln(1 - u0)), (r cos 2 pi u1, r sin 2 pi u1).  The noise is kept
+ * for pm_init_ic_vjp as with pm_init_ic.  Errors as pm_init_ic. */
+int pm_init_ic_seed(pm_sim* sim, uint64_t seed, double a0);
+
+/* That noise alone, written to the device array noise_out [Np^3] (dtype).
+ * Errors: PM_EINVAL (NULL noise_out). */
+int pm_noise(pm_sim* sim, uint64_t seed, void* noise_out);
+
+/* Reuse the arena for new physical parameters: cosmology, box, field of view
+ * and source redshifts may change; Np, Nm, dtype, npix and nsrc must equal
+ * those of pm_create.  Rebuilds and uploads the float64 tables and clears
+ * the state (pm_init_ic* must follow).  Waits for the stream.
+ * Errors: PM_EINVAL (invalid or arena-changing parameters), PM_EDEVICE. */
+int pm_reconfigure(pm_sim* sim, const pm_params* p, const lens_params* l);
+
 /* One kick-drift-kick PM step from a0 to a1 (package design section: FastPM
  * kick and drift factors that keep linear displacement exact in every step):
  *   p += K(a0, ah; a0) f(x),  x += Dr(a0, a1; ah) p,  p += K(ah, a1; a1) f(x'),
@@ -166,8 +186,9 @@ int pm_background(const pm_sim* sim, double a, double out[3]);
  * are device arrays [3][Np^3] of dtype in lattice order and Mpc/h units
  * (dL/dx, dL/dp).  cosmo_bar is a host array [2] = (dL/dOmega_m,
  * dL/dsigma_8), ACCUMULATED.  Omega_m derivatives of scalar factors are
- * central differences with step 1e-5; shell membership (the distance bounds
- * of each shell) is held fixed.  Each call waits for its stream at the end
+ * central differences with step 1e-5; membership is held fixed: the distance
+ * bounds of each shell, and which images lie in front of each source plane
+ * (the lens weight vanishes there, so this changes no derivative).  Each call waits for its stream at the end
  * (it reads reduced scalars back).
  *
  * lens_project_vjp: state at a1.  x_bar += (d kappa_shell / dx)^T kappa_bar,
@@ -206,6 +227,63 @@ int pm_init_ic_vjp(pm_sim* sim, double a1, const void* x_bar, const void* p_bar,
 int pm_profile(pm_sim* sim, int enable);
 int pm_profile_read(pm_sim* sim, int max_kernels, char* names, double* ms_total, long* counts,
                     int* n_out);
+
+/* ---- serving ---------------------------------------------------------------
+ * A request loop for many independent simulations on one GPU (the paper's
+ * use case of fast simulations over many cosmologies): requests of any size
+ * and cosmology are queued as they arrive, admitted in arrival order while
+ * fewer than max_active run and the HBM footprint of their arenas
+ * (pm_footprint plus the maps) fits hbm_budget, and run concurrently, each
+ * on a stream of its own, their steps interleaved so that their kernels
+ * overlap on the device (continuous batching).  Arenas of finished requests
+ * stay allocated and are reused by later requests of the same shape, or
+ * freed, least recently used first, when a new shape needs the memory.
+ * max_active = 1 gives the plain form: one simulation at a time, first in
+ * first out, with the same kernels.  Two host threads (admission, issue) run
+ * inside the server; every call below is thread-safe. */
+typedef struct pm_request {
+    pm_params   p;         /* sizes, cosmology, dtype                          */
+    lens_params l;         /* maps; z_src is copied at submission              */
+    double      a_start;   /* initial conditions at a_start                    */
+    double      a_end;     /* nsteps PM steps linear in a up to a_end          */
+    int32_t     nsteps;
+    uint64_t    seed;      /* white noise as in pm_init_ic_seed                */
+} pm_request;
+
+typedef struct pm_srv_stats {
+    int64_t submitted, completed, failed;
+    int32_t running, queued, peak_running;
+    size_t  bytes_in_use, peak_bytes;  /* HBM held by arenas and maps        */
+    double  now;                       /* server clock, seconds              */
+} pm_srv_stats;
+
+typedef struct pm_srv pm_srv;
+
+/* Errors: PM_EINVAL (max_active < 1, zero budget), PM_ENOMEM. */
+int pm_srv_create(size_t hbm_budget, int32_t max_active, pm_srv** out);
+
+/* Queue a request; *id_out identifies it.  The request's maps start at zero
+ * and receive every shell of its steps.  Errors: PM_EINVAL (invalid
+ * parameters or time range), PM_ENOMEM (footprint above the budget),
+ * PM_ESTATE (server shutting down). */
+int pm_srv_submit(pm_srv* s, const pm_request* r, int64_t* id_out);
+
+/* Wait until the request has finished (successfully or not), at most
+ * timeout_s seconds (< 0: no limit).  PM_OK when finished, PM_EAGAIN on
+ * timeout, PM_EINVAL for an unknown id. */
+int pm_srv_wait(pm_srv* s, int64_t id, double timeout_s);
+
+/* For a finished request: copy its maps to the host buffer kappa_host
+ * [nsrc][npix][npix] (dtype; may be NULL) and times[3] = (submitted,
+ * admitted, finished) on the server clock, in seconds (may be NULL); then
+ * forget the request.  Returns the request's status (PM_OK or the error that
+ * ended it), PM_EAGAIN if it has not finished, PM_EINVAL for an unknown id. */
+int pm_srv_result(pm_srv* s, int64_t id, void* kappa_host, double times[3]);
+
+int pm_srv_stats_get(pm_srv* s, pm_srv_stats* out);
+
+/* Drop queued requests, let running ones finish, free every arena. */
+int pm_srv_destroy(pm_srv* s);
 
 const char* pm_strerror(int code);
 

@@ -12,8 +12,8 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmadlens_amd.so")
 
-PM_OK, PM_EINVAL, PM_ENOMEM, PM_EDEVICE, PM_ESTATE, PM_ENONFINITE, PM_EFULL = \
-    0, -1, -2, -3, -4, -5, -6
+PM_OK, PM_EINVAL, PM_ENOMEM, PM_EDEVICE, PM_ESTATE, PM_ENONFINITE, PM_EAGAIN = \
+    0, -1, -2, -3, -4, -5, -7
 PM_F32, PM_F64 = 0, 1
 
 
@@ -30,6 +30,20 @@ class LensParams(ctypes.Structure):
                 ("nsrc", ctypes.c_int32), ("z_src", ctypes.POINTER(ctypes.c_double))]
 
 
+class PmRequest(ctypes.Structure):
+    _fields_ = [("p", PmParams), ("l", LensParams), ("a_start", ctypes.c_double),
+                ("a_end", ctypes.c_double), ("nsteps", ctypes.c_int32),
+                ("seed", ctypes.c_uint64)]
+
+
+class PmSrvStats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("failed", ctypes.c_int64), ("running", ctypes.c_int32),
+                ("queued", ctypes.c_int32), ("peak_running", ctypes.c_int32),
+                ("bytes_in_use", ctypes.c_size_t), ("peak_bytes", ctypes.c_size_t),
+                ("now", ctypes.c_double)]
+
+
 # name -> (restype, argtypes); every entry point declared in include/madlens.h
 _P = ctypes.c_void_p
 _D = ctypes.c_double
@@ -40,6 +54,9 @@ SIGNATURES = {
                        ctypes.POINTER(_P)]),
     "pm_destroy": (_I, [_P]),
     "pm_init_ic": (_I, [_P, _P, _D]),
+    "pm_init_ic_seed": (_I, [_P, ctypes.c_uint64, _D]),
+    "pm_noise": (_I, [_P, ctypes.c_uint64, _P]),
+    "pm_reconfigure": (_I, [_P, ctypes.POINTER(PmParams), ctypes.POINTER(LensParams)]),
     "pm_step": (_I, [_P, _D, _D]),
     "lens_project": (_I, [_P, _D, _D, _P]),
     "pm_get_state": (_I, [_P, _P, _P, ctypes.POINTER(_D)]),
@@ -53,6 +70,12 @@ SIGNATURES = {
     "pm_profile": (_I, [_P, _I]),
     "pm_profile_read": (_I, [_P, _I, ctypes.c_char_p, ctypes.POINTER(_D),
                              ctypes.POINTER(ctypes.c_long), ctypes.POINTER(_I)]),
+    "pm_srv_create": (_I, [ctypes.c_size_t, ctypes.c_int32, ctypes.POINTER(_P)]),
+    "pm_srv_submit": (_I, [_P, ctypes.POINTER(PmRequest), ctypes.POINTER(ctypes.c_int64)]),
+    "pm_srv_wait": (_I, [_P, ctypes.c_int64, _D]),
+    "pm_srv_result": (_I, [_P, ctypes.c_int64, _P, ctypes.POINTER(_D)]),
+    "pm_srv_stats_get": (_I, [_P, ctypes.POINTER(PmSrvStats)]),
+    "pm_srv_destroy": (_I, [_P]),
     "pm_strerror": (ctypes.c_char_p, [_I]),
 }
 

@@ -16,7 +16,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libmadlens_amd.so")
-SOURCES = ["fft.hip", "particles.hip", "lens.hip", "adjoint.hip", "cosmo_host.cpp", "capi.cpp"]
+SOURCES = ["fft.hip", "particles.hip", "lens.hip", "adjoint.hip", "cosmo_host.cpp", "capi.cpp",
+           "server.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -5,6 +5,7 @@
 
 #include <cmath>
 #include <complex>
+#include <algorithm>
 #include <cstring>
 #include <memory>
 #include <new>
@@ -41,7 +42,7 @@ struct Layout {
 
 // Offsets of every device array inside the arena.
 struct ArenaPlan {
-    size_t disp[2], mom[2], id[2], acc, key, rank, count, start, status;
+    size_t disp[2], mom[2], id[2], acc, key, rank, count, start, scan_sum, status;
     size_t mesh[3], nyq[3], halo, tw_nm, tw_hm, twp_nm, tw_np, tw_hp, twp_np, g_ic, atab;
     size_t xbc, fbc, dots, fmax, noise, g_ic_dom, adom;
     size_t total;
@@ -67,6 +68,7 @@ ArenaPlan plan_arena(const pm_params& p, const lens_params& l, size_t es) {
     a.rank = L.take(n * 4);
     a.count = L.take(nt * nt * nt * 4);
     a.start = L.take((nt * nt * nt + 1) * 4);
+    a.scan_sum = L.take((nt * nt * nt + 1023) / 1024 * 4);
     a.status = L.take(256);
     for (int j = 0; j < 3; ++j) {
         a.mesh[j] = L.take(nm * nm * nm * es);
@@ -194,6 +196,9 @@ struct SimBase {
     Prof prof;
     virtual ~SimBase() {}
     virtual int init_ic(const void* noise, double a0) = 0;
+    virtual int init_ic_seed(uint64_t seed, double a0) = 0;
+    virtual int noise(uint64_t seed, void* out) = 0;
+    virtual int reconfigure(const pm_params* p, const lens_params* l) = 0;
     virtual int step(double a0, double a1) = 0;
     virtual int lens(double a0, double a1, void* kappa) = 0;
     virtual int get_state(void* x, void* p, double* a) = 0;
@@ -221,6 +226,7 @@ template <class T> struct Sim final : SimBase {
     Parts<T> cur{}, alt{};
     SortBufs sb{};
     uint32_t* status = nullptr;
+    uint32_t* scan_sum = nullptr;
     T* mesh[3]{};
     cx<T>* nyq[3]{};
     T* halo = nullptr;
@@ -244,22 +250,39 @@ template <class T> struct Sim final : SimBase {
 
     template <class U> U* at(size_t off) { return reinterpret_cast<U*>(arena + off); }
 
-    int create(const pm_params* p, const lens_params* l, void* stream) {
+    // Cosmology, box and map geometry: everything of the parameters that does
+    // not change the arena.
+    void set_physics(const pm_params* p, const lens_params* l) {
         P = *p;
         npix = l->npix;
         nsrc = l->nsrc;
         fov = l->fov_deg;
         zsrc.assign(l->z_src, l->z_src + l->nsrc);
-        st = reinterpret_cast<hipStream_t>(stream);
         cosmo.init(p->omega_m, p->h, p->n_s, p->sigma8, p->omega_b, p->t_cmb);
-        for (double z : zsrc) chisrc.push_back(cosmo.chi_of_z(z));
+        cosmo_p.init(p->omega_m + DOM, p->h, p->n_s, p->sigma8, p->omega_b, p->t_cmb);
+        cosmo_m.init(p->omega_m - DOM, p->h, p->n_s, p->sigma8, p->omega_b, p->t_cmb);
+        chisrc.clear();
+        chisrc_p.clear();
+        chisrc_m.clear();
+        for (double z : zsrc) {
+            chisrc.push_back(cosmo.chi_of_z(z));
+            chisrc_p.push_back(cosmo_p.chi_of_z(z));
+            chisrc_m.push_back(cosmo_m.chi_of_z(z));
+        }
+        cell = p->box / p->nm;
+        a_cur = -1.0;
+        meshes_valid = false;
+    }
+
+    int create(const pm_params* p, const lens_params* l, void* stream) {
+        st = reinterpret_cast<hipStream_t>(stream);
+        set_physics(p, l);
         geo.np = p->np;
         geo.nm = p->nm;
         geo.B = p->nm / p->np;
         geo.nt = p->nm / TILE;
         geo.npart = (long)p->np * p->np * p->np;
         ntiles = geo.nt * geo.nt * geo.nt;
-        cell = p->box / p->nm;
         ap = plan_arena(*p, *l, sizeof(T));
         if (hipMalloc(&arena, ap.total) != hipSuccess) {
             arena = nullptr;
@@ -277,6 +300,7 @@ template <class T> struct Sim final : SimBase {
         sb.rank = at<uint32_t>(ap.rank);
         sb.count = at<uint32_t>(ap.count);
         sb.start = at<uint32_t>(ap.start);
+        scan_sum = at<uint32_t>(ap.scan_sum);
         status = at<uint32_t>(ap.status);
         for (int j = 0; j < 3; ++j) {
             mesh[j] = at<T>(ap.mesh[j]);
@@ -298,12 +322,15 @@ template <class T> struct Sim final : SimBase {
         noise_copy = at<T>(ap.noise);
         g_ic_dom = at<T>(ap.g_ic_dom);
         adom = at<T>(ap.adom);
-        cosmo_p.init(p->omega_m + DOM, p->h, p->n_s, p->sigma8, p->omega_b, p->t_cmb);
-        cosmo_m.init(p->omega_m - DOM, p->h, p->n_s, p->sigma8, p->omega_b, p->t_cmb);
-        for (double z : zsrc) {
-            chisrc_p.push_back(cosmo_p.chi_of_z(z));
-            chisrc_m.push_back(cosmo_m.chi_of_z(z));
-        }
+        return upload_tables();
+    }
+
+    int reconfigure(const pm_params* p, const lens_params* l) override {
+        if (p->np != P.np || p->nm != P.nm || p->dtype != P.dtype || l->npix != npix ||
+            l->nsrc != nsrc)
+            return PM_EINVAL;
+        HIPCHK(hipStreamSynchronize(st));
+        set_physics(p, l);
         return upload_tables();
     }
 
@@ -364,17 +391,18 @@ template <class T> struct Sim final : SimBase {
         {
             double chimax = cosmo.chi(ATAB_AMIN);
             dchi_tab = chimax / (ATAB_N - 2);
+            std::vector<double> a0(ATAB_N), ap_(ATAB_N), am_(ATAB_N);
+            cosmo.a_of_chi_grid(dchi_tab, ATAB_N, a0.data());
+            cosmo_p.a_of_chi_grid(dchi_tab, ATAB_N, ap_.data());
+            cosmo_m.a_of_chi_grid(dchi_tab, ATAB_N, am_.data());
             v.resize(2 * ATAB_N);
             for (int k = 0; k < ATAB_N; ++k) {
-                double a = cosmo.a_of_chi(k * dchi_tab);
-                v[2 * k] = (T)a;
-                v[2 * k + 1] = (T)cosmo.dadchi(a);
+                v[2 * k] = (T)a0[k];
+                v[2 * k + 1] = (T)cosmo.dadchi(a0[k]);
             }
             if ((rc = upload(ap.atab, v))) return rc;
             std::vector<T> w(ATAB_N);
-            for (int k = 0; k < ATAB_N; ++k)
-                w[k] = (T)((cosmo_p.a_of_chi(k * dchi_tab) - cosmo_m.a_of_chi(k * dchi_tab)) /
-                           (2.0 * DOM));
+            for (int k = 0; k < ATAB_N; ++k) w[k] = (T)((ap_[k] - am_[k]) / (2.0 * DOM));
             if ((rc = upload(ap.adom, w))) return rc;
         }
         launch_fill_u32(status, 0u, 1, st);
@@ -386,41 +414,48 @@ template <class T> struct Sim final : SimBase {
     void sort(T kick, T drift, int mode) {
         launch_fill_u32(sb.count, 0u, ntiles, st);
         { ProfScope ps(prof, "kick_drift_key"); launch_kick_drift_key<T>(cur, sb, geo, kick, drift, mode, status, st); }
-        { ProfScope ps(prof, "scan"); launch_scan(sb.count, sb.start, ntiles, st); }
+        { ProfScope ps(prof, "scan"); launch_scan(sb.count, sb.start, scan_sum, ntiles, st); }
         { ProfScope ps(prof, "scatter"); launch_scatter<T>(cur, alt, sb, geo, st); }
         std::swap(cur.disp, alt.disp);
         std::swap(cur.mom, alt.mom);
         std::swap(cur.id, alt.id);
     }
 
-    void fft_forward_grad(int n, const T* G, const cx<T>* tw, const cx<T>* twh, const cx<T>* twp) {
+    void fft_forward_grad(int n, const T* G, const cx<T>* tw, const cx<T>* twh, const cx<T>* twp,
+                          HaloMerge<T> hm = HaloMerge<T>()) {
         // Poisson: G(q) = 1 / (2 pi q Nm^2) computed in the kernel (G == NULL)
         const T gscale = (T)(1.0 / (2.0 * PI * (double)n * (double)n));
-        { ProfScope ps(prof, "fft_r2c_axis2"); fft_r2c_rows<T>(n, mesh[0], nyq[0], twh, twp, st); }
+        { ProfScope ps(prof, "fft_r2c_axis2"); fft_r2c_rows<T>(n, mesh[0], nyq[0], twh, twp, st, hm); }
         { ProfScope ps(prof, "fft_c2c_axis1_fwd");
           fft_c2c_axis1<T>(n, 1, reinterpret_cast<cx<T>*>(mesh[0]), nyq[0], tw, st); }
         PtrTriple om{{mesh[0], mesh[1], mesh[2]}}, on{{nyq[0], nyq[1], nyq[2]}};
+        // axis 0: IFFT0(n0 h) -> mesh 0, IFFT0(h) -> mesh 1 (h = i G X)
         { ProfScope ps(prof, "fft_grad_axis0");
           fft_grad_axis0<T>(n, reinterpret_cast<cx<T>*>(mesh[0]), nyq[0], om, on, tw, G, gscale, st); }
-        for (int j = 0; j < 3; ++j) {
-            ProfScope ps(prof, "fft_c2c_axis1_inv");
-            fft_c2c_axis1<T>(n, -1, reinterpret_cast<cx<T>*>(mesh[j]), nyq[j], tw, st);
-        }
+        { ProfScope ps(prof, "fft_c2c_axis1_inv");
+          fft_c2c_axis1<T>(n, -1, reinterpret_cast<cx<T>*>(mesh[0]), nyq[0], tw, st); }
+        // axis 1: n1 times mesh 1 in place, the plain transform into mesh 2
+        { ProfScope ps(prof, "fft_c2c_axis1_dual");
+          fft_c2c_axis1_dual<T>(n, reinterpret_cast<cx<T>*>(mesh[1]), nyq[1],
+                                reinterpret_cast<cx<T>*>(mesh[2]), nyq[2], tw, st); }
+        // axis 2, the last component times n2
         for (int j = 0; j < 3; ++j) {
             ProfScope ps(prof, "fft_c2r_axis2");
-            fft_c2r_rows<T>(n, mesh[j], nyq[j], twh, twp, st);
+            fft_c2r_rows<T>(n, mesh[j], nyq[j], twh, twp, st, j == 2);
         }
     }
 
-    void paint() {
+    // CIC density into mesh[0].  With defer_merge the paint boxes' shells are
+    // left in `halo` for the r2c pass to merge (force path).
+    void paint(bool defer_merge = false) {
         T mass = (T)std::pow((double)geo.B, 3);
         ProfScope ps(prof, "paint");
-        launch_paint<T>(cur, sb, geo, mass, mesh[0], halo, st);
+        launch_paint<T>(cur, sb, geo, mass, mesh[0], halo, st, !defer_merge);
     }
 
     void force(T kick2, int do_kick) {
-        paint();
-        fft_forward_grad(P.nm, nullptr, tw_nm, tw_hm, twp_nm);
+        paint(true);
+        fft_forward_grad(P.nm, nullptr, tw_nm, tw_hm, twp_nm, paint_halo_merge<T>(geo, halo));
         meshes_valid = true;
         ProfScope ps(prof, "readout_kick");
         launch_readout<T>(cur, sb, geo, mesh[0], mesh[1], mesh[2], kick2, do_kick, status, st);
@@ -431,15 +466,41 @@ template <class T> struct Sim final : SimBase {
     }
 
     // ---- API ------------------------------------------------------------
-    int init_ic(const void* noise, double a0) override {
-        if (!noise || !(a0 > 0 && a0 <= 1)) return PM_EINVAL;
+    int check_a0(double a0) {
+        if (!(a0 > 0 && a0 <= 1)) return PM_EINVAL;
         double chi0 = cosmo.chi(a0);
         for (double c : chisrc)
             if (c > chi0) return PM_EINVAL;
+        return PM_OK;
+    }
+
+    int init_ic(const void* noise, double a0) override {
+        if (!noise) return PM_EINVAL;
+        int rc = check_a0(a0);
+        if (rc) return rc;
+        const size_t n = (size_t)P.np * P.np * P.np;
+        HIPCHK(hipMemcpyAsync(noise_copy, noise, n * sizeof(T), hipMemcpyDeviceToDevice, st));
+        return init_from_noise_copy(a0);
+    }
+
+    int init_ic_seed(uint64_t seed, double a0) override {
+        int rc = check_a0(a0);
+        if (rc) return rc;
+        launch_noise<T>(noise_copy, (long)P.np * P.np * P.np, seed, st);
+        return init_from_noise_copy(a0);
+    }
+
+    int noise(uint64_t seed, void* out) override {
+        if (!out) return PM_EINVAL;
+        launch_noise<T>(reinterpret_cast<T*>(out), (long)P.np * P.np * P.np, seed, st);
+        return check_launch();
+    }
+
+    // Zel'dovich initial conditions from the noise held in noise_copy.
+    int init_from_noise_copy(double a0) {
         const int np = P.np;
         size_t n = (size_t)np * np * np;
-        HIPCHK(hipMemcpyAsync(mesh[0], noise, n * sizeof(T), hipMemcpyDeviceToDevice, st));
-        HIPCHK(hipMemcpyAsync(noise_copy, noise, n * sizeof(T), hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(mesh[0], noise_copy, n * sizeof(T), hipMemcpyDeviceToDevice, st));
         meshes_valid = false;
         fft_forward_grad(np, g_ic, tw_np, tw_hp, twp_np);
         launch_init_ic<T>(cur, geo, mesh[0], mesh[1], mesh[2], (T)cosmo.D(a0), (T)cosmo.gp(a0), st);
@@ -470,6 +531,11 @@ template <class T> struct Sim final : SimBase {
         la.nsrc = nsrc;
         la.cell = (T)cell;
         double chi_far = cosmo.chi(a0), chi_near = cosmo.chi(a1);
+        // a shell wholly behind the farthest source plane adds nothing (its
+        // images and its mean term both need chi < chi_s)
+        double chis_max = 0;
+        for (double c : chisrc) chis_max = std::max(chis_max, c);
+        if (chi_near >= chis_max) return PM_OK;
         la.chi_near = (T)chi_near;
         la.chi_far = (T)chi_far;
         double dth = fov * PI / 180.0 / npix;
@@ -480,7 +546,10 @@ template <class T> struct Sim final : SimBase {
         la.atab = atab;
         la.ntab = ATAB_N;
         la.dchi = (T)dchi_tab;
-        la.rs = 32;
+        // 64 x 64-pixel regions when their fixed-point accumulators fit in
+        // 128 KB of LDS: each region's frustum is then twice as wide, and
+        // the tile columns it reads hold fewer particles outside it
+        la.rs = ((size_t)nsrc * 64 * 64 * 8 <= 131072 && npix >= 256) ? 64 : 32;
         T* k = reinterpret_cast<T*>(kappa);
         MapAdd<T> mv{};
         for (int s = 0; s < nsrc; ++s) mv.v[s] = (T)cosmo.shell_mean(chi_near, chi_far, chisrc[s]);
@@ -658,6 +727,11 @@ template <class T> struct Sim final : SimBase {
         la.nsrc = nsrc;
         la.cell = (T)cell;
         double chi_far = cosmo.chi(a0), chi_near = cosmo.chi(a1);
+        // a shell wholly behind the farthest source plane adds nothing (its
+        // images and its mean term both need chi < chi_s)
+        double chis_max = 0;
+        for (double c : chisrc) chis_max = std::max(chis_max, c);
+        if (chi_near >= chis_max) return PM_OK;
         la.chi_near = (T)chi_near;
         la.chi_far = (T)chi_far;
         double dth = fov * PI / 180.0 / npix;
@@ -754,6 +828,17 @@ int pm_destroy(pm_sim* sim) {
 int pm_init_ic(pm_sim* sim, const void* noise, double a0) {
     return sim ? sim->impl->init_ic(noise, a0) : PM_EINVAL;
 }
+int pm_init_ic_seed(pm_sim* sim, uint64_t seed, double a0) {
+    return sim ? sim->impl->init_ic_seed(seed, a0) : PM_EINVAL;
+}
+int pm_noise(pm_sim* sim, uint64_t seed, void* noise_out) {
+    return sim ? sim->impl->noise(seed, noise_out) : PM_EINVAL;
+}
+int pm_reconfigure(pm_sim* sim, const pm_params* p, const lens_params* l) {
+    if (!sim) return PM_EINVAL;
+    int rc = validate(p, l);
+    return rc ? rc : sim->impl->reconfigure(p, l);
+}
 int pm_step(pm_sim* sim, double a0, double a1) { return sim ? sim->impl->step(a0, a1) : PM_EINVAL; }
 int lens_project(pm_sim* sim, double a0, double a1, void* kappa) {
     return sim ? sim->impl->lens(a0, a1, kappa) : PM_EINVAL;
@@ -818,7 +903,7 @@ const char* pm_strerror(int code) {
         case PM_EDEVICE: return "HIP runtime error";
         case PM_ESTATE: return "simulation is not in the required state";
         case PM_ENONFINITE: return "non-finite particle position";
-        case PM_EFULL: return "batch has no free slot";
+        case PM_EAGAIN: return "not finished yet";
         default: return "unknown error";
     }
 }

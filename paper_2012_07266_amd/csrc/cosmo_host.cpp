@@ -121,6 +121,36 @@ double HostCosmo::a_of_chi(double c) const {
     return t * t;
 }
 
+void HostCosmo::a_of_chi_grid(double dchi, int n, double* a_out) const {
+    // chi(t) = 2 (c/H0) int_t^1 g, g(t) = 1/sqrt(Om + (1-Om) t^6), t = sqrt(a).
+    // Node k starts Newton's method from node k-1 and measures chi(t) as
+    // chi(t_prev) plus the integral over [t, t_prev] (one Gauss-Legendre
+    // panel on an interval of one table step).
+    auto g = [&](double t) {
+        double t2 = t * t;
+        return 1.0 / std::sqrt(om + (1.0 - om) * t2 * t2 * t2);
+    };
+    if (n <= 0) return;
+    a_out[0] = 1.0;
+    double t_prev = 1.0, chi_prev = 0.0;
+    for (int k = 1; k < n; ++k) {
+        const double c = k * dchi;
+        double t = t_prev - (c - chi_prev) / (2.0 * C_H0 * g(t_prev));
+        if (t < 1e-4) t = 1e-4;
+        double chi_t = chi_prev;
+        for (int it = 0; it < 50; ++it) {
+            chi_t = chi_prev + 2.0 * C_H0 * integrate(g, t, t_prev, 1);
+            double step = (chi_t - c) / (-2.0 * C_H0 * g(t));
+            t -= step;
+            if (t < 1e-4) t = 1e-4;
+            if (std::fabs(step) < 1e-15) break;
+        }
+        chi_prev = chi_prev + 2.0 * C_H0 * integrate(g, t, t_prev, 1);
+        t_prev = t;
+        a_out[k] = t * t;
+    }
+}
+
 double HostCosmo::dadchi(double a) const { return -a * a * E(a) / C_H0; }
 
 double HostCosmo::growth_integral(double a) const {

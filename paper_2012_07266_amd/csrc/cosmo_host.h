@@ -28,6 +28,9 @@ struct HostCosmo {
     double chi(double a) const;             // Mpc/h
     double chi_of_z(double z) const { return chi(1.0 / (1.0 + z)); }
     double a_of_chi(double c) const;
+    // a(k dchi) for k = 0..n-1, marching outward from a = 1 (same accuracy as
+    // a_of_chi, far fewer distance integrals)
+    void a_of_chi_grid(double dchi, int n, double* a_out) const;
     double dadchi(double a) const;          // da/dchi = -a^2 E / (c/H0)
     double D(double a) const;
     double dDda(double a) const;

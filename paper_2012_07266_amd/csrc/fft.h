@@ -1,6 +1,7 @@
 // Host entry points of the LDS-staged FFT passes (see fft.hip).
 #pragma once
 #include "common.h"
+#include "paint_halo.h"
 
 namespace ml {
 
@@ -15,22 +16,34 @@ template <class T> bool fft_supported(int n);
 // on input and n*n rows of n/2 complex (k2 < n/2) on output; nyq gets the
 // k2 = n/2 plane [n][n].  tw_h: exp(-2 pi i t/(n/2)), t < n/2;
 // tw_post: exp(-2 pi i k/n), k <= n/2.
+// `hm`: paint-box shells to merge into the rows while loading (none by
+// default).
 template <class T>
 void fft_r2c_rows(int n, T* io, cx<T>* nyq, const cx<T>* tw_h, const cx<T>* tw_post,
-                  hipStream_t st);
+                  hipStream_t st, HaloMerge<T> hm = HaloMerge<T>());
 // Unnormalised c2r along axis 2, in place (inverse of fft_r2c_rows times n).
+// mul_k2: multiply the spectrum by n2 = k2 first (zero on the nyq plane).
 template <class T>
 void fft_c2r_rows(int n, T* io, const cx<T>* nyq, const cx<T>* tw_h, const cx<T>* tw_post,
-                  hipStream_t st);
+                  hipStream_t st, bool mul_k2 = false);
 // c2c along axis 1 (sign +1 forward, -1 unnormalised inverse) on main and nyq.
 template <class T>
 void fft_c2c_axis1(int n, int sign, cx<T>* main, cx<T>* nyq, const cx<T>* tw, hipStream_t st);
+// Unnormalised inverse c2c along axis 1 with two outputs from H = (main,
+// nyq): IFFT1(n1 H) in place (zero where |n1| = n/2) and IFFT1(H) into
+// (main2, nyq2).
+template <class T>
+void fft_c2c_axis1_dual(int n, cx<T>* main, cx<T>* nyq, cx<T>* main2, cx<T>* nyq2, const cx<T>* tw,
+                        hipStream_t st);
 // c2c along axis 0 on main and nyq.
 template <class T>
 void fft_c2c_axis0(int n, int sign, cx<T>* main, cx<T>* nyq, const cx<T>* tw, hipStream_t st);
-// Fused axis-0 pass: forward, times i n_j G(|n|^2) (zero where |n_j| = n/2),
-// inverse, for j = 0..2.  G(q) is the table G[q], or gscale / q when G is
-// NULL (q > 0; G(0) = 0).  out_main/out_nyq hold the three destinations.
+// Fused axis-0 pass: forward, h = i G(|n|^2) X, then inverse of n0 h (zero
+// where |n0| = n/2) into out[0] and inverse of h into out[1] (out[2] is not
+// used).  G(q) is the table G[q], or gscale / q when G is NULL (q > 0;
+// G(0) = 0).  Followed by fft_c2c_axis1 on out[0], fft_c2c_axis1_dual on
+// out[1] (-> out[1], out[2]) and fft_c2r_rows on the three, the last with
+// mul_k2, this yields the three gradient components i n_j G X.
 template <class T>
 void fft_grad_axis0(int n, cx<T>* main_in, cx<T>* nyq_in, PtrTriple out_main, PtrTriple out_nyq,
                     const cx<T>* tw, const T* G, T gscale, hipStream_t st);

@@ -190,9 +190,13 @@ __device__ __forceinline__ void reg_chain(cx<T>* v, cx<T>* buf, const cx<T>* tw,
 // pass 1: r2c along the contiguous axis.  H = Nm/2.
 // `io` holds nrows rows of 2H reals on input and H complex on output.
 // ---------------------------------------------------------------------------
+// When hm.halo is set, the rows are a freshly painted density whose paint
+// boxes' upper shells have not been merged yet: each loaded cell adds the
+// shells owed to it (the same sum, in the same order, as the merge kernel of
+// the paint), so the transform sees the merged density.
 template <class T, int H, int W>
 __global__ __launch_bounds__(NT) void k_r2c_rows(T* io, cx<T>* nyq, const cx<T>* tw_h,
-                                                 const cx<T>* tw_post) {
+                                                 const cx<T>* tw_post, HaloMerge<T> hm) {
     __shared__ cx<T> buf[H * (W + 1)];
     __shared__ cx<T> tws[H];
     constexpr int LD = W + 1;
@@ -207,6 +211,18 @@ __global__ __launch_bounds__(NT) void k_r2c_rows(T* io, cx<T>* nyq, const cx<T>*
         for (int it = 0; it < IT; ++it) {
             int f = tid + it * NT;
             if ((W * H) % NT == 0 || f < W * H) v[it] = in[f];  // rows are contiguous
+        }
+        if (hm.halo) {
+#pragma unroll
+            for (int it = 0; it < IT; ++it) {
+                int f = tid + it * NT;
+                if ((W * H) % NT == 0 || f < W * H) {
+                    const size_t r = r0 + f / H;  // row r = X * 2H + Y
+                    const int X = (int)(r / (2 * H)), Y = (int)(r % (2 * H)), Z = 2 * (f % H);
+                    v[it].re += halo_sum<T>(hm, X, Y, Z);
+                    v[it].im += halo_sum<T>(hm, X, Y, Z + 1);
+                }
+            }
         }
 #pragma unroll
         for (int it = 0; it < IT; ++it) {
@@ -241,9 +257,12 @@ __global__ __launch_bounds__(NT) void k_r2c_rows(T* io, cx<T>* nyq, const cx<T>*
 // ---------------------------------------------------------------------------
 // pass 5: c2r along the contiguous axis (unnormalised inverse).
 // ---------------------------------------------------------------------------
+// With mul_k2 the spectrum is multiplied by n2 = k2 as it is loaded (zero on
+// the Nyquist plane k2 = N/2): the axis-2 gradient component of the fused
+// axis-0 pass.
 template <class T, int H, int W>
 __global__ __launch_bounds__(NT) void k_c2r_rows(T* io, const cx<T>* nyq, const cx<T>* tw_h,
-                                                 const cx<T>* tw_post) {
+                                                 const cx<T>* tw_post, int mul_k2) {
     __shared__ cx<T> buf[H * (W + 1)];
     __shared__ cx<T> tws[H];
     constexpr int LD = W + 1;
@@ -261,6 +280,10 @@ __global__ __launch_bounds__(NT) void k_c2r_rows(T* io, const cx<T>* nyq, const 
             int w = f / HK, k = f % HK;
             xkv[it] = in[(size_t)w * H + k];
             xmv[it] = k == 0 ? nyq[r0 + w] : in[(size_t)w * H + (H - k)];
+            if (mul_k2) {
+                xkv[it] = scale(xkv[it], T(k));
+                xmv[it] = scale(xmv[it], k == 0 ? T(0) : T(H - k));
+            }
         }
     }
 #pragma unroll
@@ -415,12 +438,109 @@ __global__ __launch_bounds__(NT) void k_c2c_view(ViewDesc va, ViewDesc vb, const
 }
 
 // ---------------------------------------------------------------------------
+// Inverse pass along axis 1 that produces two outputs from one input H:
+//   in place:  IFFT1(n1 H)   (zero on the plane |n1| = N/2)
+//   out2:      IFFT1(H)
+// (the gradient components along axes 1 and 2 of the fused axis-0 pass).
+// `dst2a`/`dst2b` are the bases of the second output matching va / vb.
+// ---------------------------------------------------------------------------
+template <class T, int N>
+__device__ __forceinline__ T n1_mult(int n) {
+    constexpr int HN = N / 2;
+    return n == HN ? T(0) : T(n <= HN ? n : n - N);
+}
+
+template <class T, int N, int W>
+__global__ __launch_bounds__(NT) void k_c2c_view_dual(ViewDesc va, ViewDesc vb, cx<T>* dst2a,
+                                                      cx<T>* dst2b, const cx<T>* tw) {
+    __shared__ cx<T> buf[N * (W + 1)];
+    __shared__ cx<T> tws[N];
+    constexpr int LD = W + 1;
+    const int tid = threadIdx.x;
+    int g = blockIdx.x;
+    const bool is_a = g < va.n_wg;
+    const ViewDesc& v = is_a ? va : vb;
+    cx<T>* dst2 = is_a ? dst2a : dst2b;
+    if (!is_a) g -= va.n_wg;
+    load_twiddles<T, N>(tws, tw, tid);
+    if constexpr (reg_path_ok<N, W>()) {
+        if (!v.contig) {
+            constexpr int E = W * N / NT;
+            constexpr int R0 = plan_radix(N, 0);
+            constexpr int RL = plan_radix(N, num_stages(N) - 1);
+            static_assert(NT % W == 0, "a thread keeps one column");
+            // slot (it, q) of a radix-R pattern: row tid/W + it*(NT/W) + q*(N/R)
+            // of column tid % W, i.e. a per-thread offset plus a row count
+            // known at compile time times the uniform stride
+            const long tbase = view_offset<T, N, W>(v, g, tid % W, tid / W);
+            const long C = v.C;
+            const cx<T>* src = reinterpret_cast<const cx<T>*>(v.ptr) + tbase;
+            cx<T> r[E];
+#pragma unroll
+            for (int it = 0; it < E / R0; ++it)
+#pragma unroll
+                for (int q = 0; q < R0; ++q)
+                    r[it * R0 + q] = src[(long)(it * (NT / W) + q * (N / R0)) * C];
+            __syncthreads();  // twiddles in LDS
+            reg_compute<T, N, W, R0, 1, -1>(r, tws, tid);
+            reg_chain<T, N, W, -1, 1>(r, buf, tws, tid);
+            cx<T>* d2 = dst2 + tbase;
+#pragma unroll
+            for (int it = 0; it < E / RL; ++it)
+#pragma unroll
+                for (int q = 0; q < RL; ++q)
+                    d2[(long)(it * (NT / W) + q * (N / RL)) * C] = r[it * RL + q];
+            // reload H (this workgroup's pencils, still in L2) scaled by n1
+#pragma unroll
+            for (int it = 0; it < E / R0; ++it)
+#pragma unroll
+                for (int q = 0; q < R0; ++q) {
+                    const int n = tid / W + it * (NT / W) + q * (N / R0);
+                    r[it * R0 + q] =
+                        scale(src[(long)(it * (NT / W) + q * (N / R0)) * C], n1_mult<T, N>(n));
+                }
+            __syncthreads();  // the first transform is done with buf
+            reg_compute<T, N, W, R0, 1, -1>(r, tws, tid);
+            reg_chain<T, N, W, -1, 1>(r, buf, tws, tid);
+            cx<T>* d1 = reinterpret_cast<cx<T>*>(v.ptr) + tbase;
+#pragma unroll
+            for (int it = 0; it < E / RL; ++it)
+#pragma unroll
+                for (int q = 0; q < RL; ++q)
+                    d1[(long)(it * (NT / W) + q * (N / RL)) * C] = r[it * RL + q];
+            return;
+        }
+    }
+    // LDS path: transform H, store it to out2; reload H scaled by n1,
+    // transform, store in place
+    view_load<T, N, W>(buf, v, g, tid);
+    __syncthreads();
+    fft_lds<T, N, W, -1>(buf, tws, tid);
+    view_store<T, N, W>(buf, dst2, v, g, tid);
+    __syncthreads();
+    view_load<T, N, W>(buf, v, g, tid);
+    __syncthreads();
+    for (int f = tid; f < N * W; f += NT) {
+        int n = f / W, w = f % W;
+        buf[n * LD + w] = scale(buf[n * LD + w], n1_mult<T, N>(n));
+    }
+    __syncthreads();
+    fft_lds<T, N, W, -1>(buf, tws, tid);
+    view_store<T, N, W>(buf, v.ptr, v, g, tid);
+}
+
+// ---------------------------------------------------------------------------
 // pass 3: fused outer-axis pass.  Forward FFT of W pencils along axis 0,
-// then for j = 0, 1, 2: multiply by m_j = i n_j G[n0^2+n1^2+n2^2] (zero on
-// the plane |n_j| = N/2), inverse FFT, store to out_j.  The view's column c
-// maps to (k1, k2) = (c / (N/2), c % (N/2)) on main, (c, N/2) on nyq.
-// out[j] are the bases of the three spectra (main or nyq part, matching va
-// or vb); out[0] may equal the input.
+// h = i G[n0^2+n1^2+n2^2] X, then two inverse FFTs along axis 0:
+//   out0 = IFFT0(n0 h)  (zero on the plane |n0| = N/2)
+//   out1 = IFFT0(h).
+// The gradient components along axes 1 and 2 are n1 and n2 times h, and n1,
+// n2 are constant along axis 0, so both follow from out1: the axis-1 pass
+// multiplies by n1 (fft_c2c_axis1_dual), the axis-2 pass by n2
+// (fft_c2r_rows with mul_k2).  The view's column c maps to (k1, k2) =
+// (c / (N/2), c % (N/2)) on main, (c, N/2) on nyq.  out[j] are the bases of
+// the two spectra (main or nyq part, matching va or vb); out[0] may equal
+// the input.
 // ---------------------------------------------------------------------------
 // With 512 threads the bound asks for 4 waves per SIMD, i.e. two workgroups
 // per CU, so that one workgroup's loads and stores overlap the other's
@@ -489,8 +609,8 @@ __global__ __launch_bounds__(NTG, (NTG == 512 ? 4 : 1)) void k_grad_x0(ViewDesc 
                 spec[it * R0 + q] = {-gg * sp.im, gg * sp.re};
             }
         }
-#pragma unroll 1
-        for (int j = 0; j < 3; ++j) {
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
             cx<T> u[E];
 #pragma unroll
             for (int it = 0; it < E / R0; ++it) {
@@ -498,8 +618,7 @@ __global__ __launch_bounds__(NTG, (NTG == 512 ? 4 : 1)) void k_grad_x0(ViewDesc 
                 for (int q = 0; q < R0; ++q) {
                     int k0 = tid / W + it * (NTG / W) + q * (N / R0);
                     int n0 = k0 <= HN ? k0 : k0 - N;
-                    int nj = j == 0 ? n0 : (j == 1 ? n1 : k2);
-                    T m = (nj == HN || nj == -HN) ? T(0) : T(nj);
+                    T m = j == 1 ? T(1) : (n0 == HN || n0 == -HN) ? T(0) : T(n0);
                     u[it * R0 + q] = scale(spec[it * R0 + q], m);
                 }
             }
@@ -528,7 +647,7 @@ __global__ __launch_bounds__(NTG, (NTG == 512 ? 4 : 1)) void k_grad_x0(ViewDesc 
     constexpr int IT = (TOT + NT - 1) / NT;
     cx<T> spec[IT][R0];
     T gv[IT][R0];
-    int n0v[IT][R0], n1v[IT], n2v[IT];
+    int n0v[IT][R0];
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
         int b = tid + it * NT;
@@ -539,8 +658,6 @@ __global__ __launch_bounds__(NTG, (NTG == 512 ? 4 : 1)) void k_grad_x0(ViewDesc 
             if (is_a) { k1 = (int)(c / HN); k2 = (int)(c % HN); }
             else      { k1 = (int)c;        k2 = HN; }
             int n1 = k1 <= HN ? k1 : k1 - N;
-            n1v[it] = n1;
-            n2v[it] = k2;
 #pragma unroll
             for (int r = 0; r < R0; ++r) {
                 int k0 = i + r * NB;
@@ -554,7 +671,7 @@ __global__ __launch_bounds__(NTG, (NTG == 512 ? 4 : 1)) void k_grad_x0(ViewDesc 
     }
     __syncthreads();
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
+    for (int j = 0; j < 2; ++j) {
 #pragma unroll
         for (int it = 0; it < IT; ++it) {
             int b = tid + it * NT;
@@ -563,8 +680,9 @@ __global__ __launch_bounds__(NTG, (NTG == 512 ? 4 : 1)) void k_grad_x0(ViewDesc 
                 cx<T> u[R0];
 #pragma unroll
                 for (int r = 0; r < R0; ++r) {
-                    int nj = j == 0 ? n0v[it][r] : (j == 1 ? n1v[it] : n2v[it]);
-                    T m = (nj == HN || nj == -HN) ? T(0) : T(nj) * gv[it][r];
+                    int n0 = n0v[it][r];
+                    T m = j == 1 ? gv[it][r]
+                                 : (n0 == HN || n0 == -HN) ? T(0) : T(n0) * gv[it][r];
                     u[r] = {-m * spec[it][r].im, m * spec[it][r].re};  // i m spec
                 }
                 dft<R0, -1>(u);
@@ -671,15 +789,15 @@ template <class T> constexpr int rows_w(int n) { return (sizeof(T) == 4 && n < 7
 
 template <class T, int H>
 static void r2c_rows_n(T* io, cx<T>* nyq, const cx<T>* tw_h, const cx<T>* tw_post, long nrows,
-                       hipStream_t st) {
+                       hipStream_t st, HaloMerge<T> hm) {
     constexpr int W = rows_w<T>(2 * H);
-    ML_LAUNCH((k_r2c_rows<T, H, W>), nrows / W, st, io, nyq, tw_h, tw_post);
+    ML_LAUNCH((k_r2c_rows<T, H, W>), nrows / W, st, io, nyq, tw_h, tw_post, hm);
 }
 template <class T, int H>
 static void c2r_rows_n(T* io, const cx<T>* nyq, const cx<T>* tw_h, const cx<T>* tw_post,
-                       long nrows, hipStream_t st) {
+                       long nrows, hipStream_t st, int mul_k2) {
     constexpr int W = rows_w<T>(2 * H);
-    ML_LAUNCH((k_c2r_rows<T, H, W>), nrows / W, st, io, nyq, tw_h, tw_post);
+    ML_LAUNCH((k_c2r_rows<T, H, W>), nrows / W, st, io, nyq, tw_h, tw_post, mul_k2);
 }
 
 template <class T, int N, int S>
@@ -688,6 +806,15 @@ static void c2c_axis1_n(cx<T>* main, cx<T>* nyq, const cx<T>* tw, hipStream_t st
     ViewDesc va{main, N / 2, 0, (int)((long)N * (N / 2) / W)};
     ViewDesc vb{nyq, 1, 1, N / W};
     ML_LAUNCH((k_c2c_view<T, N, W, S>), va.n_wg + vb.n_wg, st, va, vb, tw);
+}
+
+template <class T, int N>
+static void c2c_axis1_dual_n(cx<T>* main, cx<T>* nyq, cx<T>* main2, cx<T>* nyq2, const cx<T>* tw,
+                             hipStream_t st) {
+    constexpr int W = lanes_w<T>(N);
+    ViewDesc va{main, N / 2, 0, (int)((long)N * (N / 2) / W)};
+    ViewDesc vb{nyq, 1, 1, N / W};
+    ML_LAUNCH((k_c2c_view_dual<T, N, W>), va.n_wg + vb.n_wg, st, va, vb, main2, nyq2, tw);
 }
 
 template <class T, int N, int S>
@@ -737,9 +864,10 @@ template <class T> bool fft_supported(int n) {
 }
 
 template <class T>
-void fft_r2c_rows(int n, T* io, cx<T>* nyq, const cx<T>* tw_h, const cx<T>* tw_post, hipStream_t st) {
+void fft_r2c_rows(int n, T* io, cx<T>* nyq, const cx<T>* tw_h, const cx<T>* tw_post, hipStream_t st,
+                  HaloMerge<T> hm) {
     long rows = (long)n * n;
-#define ML_CASE(v) if (n == v) return r2c_rows_n<T, v / 2>(io, nyq, tw_h, tw_post, rows, st);
+#define ML_CASE(v) if (n == v) return r2c_rows_n<T, v / 2>(io, nyq, tw_h, tw_post, rows, st, hm);
     if constexpr (sizeof(T) == 4) { ML_SIZES_F(ML_CASE) }
     else { ML_SIZES_D(ML_CASE) }
 #undef ML_CASE
@@ -747,9 +875,10 @@ void fft_r2c_rows(int n, T* io, cx<T>* nyq, const cx<T>* tw_h, const cx<T>* tw_p
 
 template <class T>
 void fft_c2r_rows(int n, T* io, const cx<T>* nyq, const cx<T>* tw_h, const cx<T>* tw_post,
-                  hipStream_t st) {
+                  hipStream_t st, bool mul_k2) {
     long rows = (long)n * n;
-#define ML_CASE(v) if (n == v) return c2r_rows_n<T, v / 2>(io, nyq, tw_h, tw_post, rows, st);
+#define ML_CASE(v) \
+    if (n == v) return c2r_rows_n<T, v / 2>(io, nyq, tw_h, tw_post, rows, st, mul_k2 ? 1 : 0);
     if constexpr (sizeof(T) == 4) { ML_SIZES_F(ML_CASE) }
     else { ML_SIZES_D(ML_CASE) }
 #undef ML_CASE
@@ -762,6 +891,16 @@ void fft_c2c_axis1(int n, int sign, cx<T>* main, cx<T>* nyq, const cx<T>* tw, hi
         if (sign > 0) return c2c_axis1_n<T, v, 1>(main, nyq, tw, st);               \
         return c2c_axis1_n<T, v, -1>(main, nyq, tw, st);                            \
     }
+    if constexpr (sizeof(T) == 4) { ML_SIZES_F(ML_CASE) }
+    else { ML_SIZES_D(ML_CASE) }
+#undef ML_CASE
+}
+
+template <class T>
+void fft_c2c_axis1_dual(int n, cx<T>* main, cx<T>* nyq, cx<T>* main2, cx<T>* nyq2, const cx<T>* tw,
+                        hipStream_t st) {
+#define ML_CASE(v) \
+    if (n == v) return c2c_axis1_dual_n<T, v>(main, nyq, main2, nyq2, tw, st);
     if constexpr (sizeof(T) == 4) { ML_SIZES_F(ML_CASE) }
     else { ML_SIZES_D(ML_CASE) }
 #undef ML_CASE
@@ -801,9 +940,13 @@ void fft_div_axis0(int n, PtrTriple in_main, PtrTriple in_nyq, cx<T>* out_main, 
     template void fft_div_axis0<T>(int, PtrTriple, PtrTriple, cx<T>*, cx<T>*, const cx<T>*,        \
                                    const T*, T, hipStream_t);                                       \
     template bool fft_supported<T>(int);                                                            \
-    template void fft_r2c_rows<T>(int, T*, cx<T>*, const cx<T>*, const cx<T>*, hipStream_t);       \
-    template void fft_c2r_rows<T>(int, T*, const cx<T>*, const cx<T>*, const cx<T>*, hipStream_t); \
+    template void fft_r2c_rows<T>(int, T*, cx<T>*, const cx<T>*, const cx<T>*, hipStream_t,        \
+                                  HaloMerge<T>);                                                  \
+    template void fft_c2r_rows<T>(int, T*, const cx<T>*, const cx<T>*, const cx<T>*, hipStream_t,  \
+                                  bool);                                                          \
     template void fft_c2c_axis1<T>(int, int, cx<T>*, cx<T>*, const cx<T>*, hipStream_t);           \
+    template void fft_c2c_axis1_dual<T>(int, cx<T>*, cx<T>*, cx<T>*, cx<T>*, const cx<T>*,          \
+                                        hipStream_t);                                             \
     template void fft_c2c_axis0<T>(int, int, cx<T>*, cx<T>*, const cx<T>*, hipStream_t);           \
     template void fft_grad_axis0<T>(int, cx<T>*, cx<T>*, PtrTriple, PtrTriple, const cx<T>*,        \
                                     const T*, T, hipStream_t);

@@ -7,15 +7,10 @@
 // of its distance shell, every particle image r = x + n L - O (observer O at
 // (L/2, L/2, 0), line of sight along axis 2, chi = r_2, theta = r_perp/chi)
 // adds  wbase (chi_s - chi) / (chi_s chi a(chi))  to the map, bilinearly, and
-// the shell's mean term is added to every pixel by a second kernel.  The
-// replica range of each particle is computed directly from the shell depth
-// and the field of view, so the work is proportional to the images that
-// land on the map.
+// the shell's mean term is added to every pixel in the same pass.
 #include "particles.h"
 
 namespace ml {
-
-constexpr int LB = 256;
 
 template <class T>
 __device__ __forceinline__ T a_of_chi(const LensArgs<T>& la, T chi) {
@@ -29,89 +24,6 @@ __device__ __forceinline__ T a_of_chi(const LensArgs<T>& la, T chi) {
     T s2 = s * s, s3 = s2 * s;
     return (T(2) * s3 - T(3) * s2 + T(1)) * a0 + (s3 - T(2) * s2 + s) * d0 +
            (T(3) * s2 - T(2) * s3) * a1 + (s3 - s2) * d1;
-}
-
-template <class T>
-__device__ __forceinline__ void splat(T* map, int npix, T t0, T t1, T w) {
-    T fl0 = floor(t0), fl1 = floor(t1);
-    int j0 = (int)fl0, j1 = (int)fl1;
-    T f0 = t0 - fl0, f1 = t1 - fl1;
-    T wa[2] = {T(1) - f0, f0}, wb[2] = {T(1) - f1, f1};
-#pragma unroll
-    for (int a = 0; a < 2; ++a) {
-        int r = j0 + a;
-        if (r < 0 || r >= npix) continue;
-#pragma unroll
-        for (int b = 0; b < 2; ++b) {
-            int c = j1 + b;
-            if (c < 0 || c >= npix) continue;
-            unsafeAtomicAdd(&map[(long)r * npix + c], w * wa[a] * wb[b]);
-        }
-    }
-}
-
-template <class T>
-__global__ __launch_bounds__(LB) void k_lens(Parts<T> p, Geo g, LensArgs<T> la, T* kappa) {
-    const long n = g.npart;
-    const T nmf = T(g.nm);
-    const T half = T(0.5) * nmf;
-    const T cnear = la.chi_near / la.cell, cfar = la.chi_far / la.cell;  // cells
-    const T tmax = T(0.5) * T(la.npix) + T(0.5);   // |theta|/dtheta bound incl. one pixel
-    const T hp = T(0.5) * T(la.npix) - T(0.5);
-    const long npix2 = (long)la.npix * la.npix;
-    T chi_max_src = la.chi_src[0];
-    for (int s = 1; s < la.nsrc; ++s) chi_max_src = max(chi_max_src, la.chi_src[s]);
-    for (long k = blockIdx.x * (long)LB + threadIdx.x; k < n; k += (long)gridDim.x * LB) {
-        int i[3];
-        lattice_of_l(p.id[k], g.np, i);
-        T u[3];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            int c;
-            T f;
-            T v = T(0.5) + p.disp[a * n + k];
-            T fl = floor(v);
-            f = v - fl;
-            c = pmod(g.B * i[a] + (int)fl, g.nm);
-            u[a] = T(c) + f;
-        }
-        if (!(isfinite(u[0]) && isfinite(u[1]) && isfinite(u[2]))) continue;
-        int nz0 = (int)floor((cnear - u[2]) / nmf);
-        int nz1 = (int)floor((cfar - u[2]) / nmf) + 1;
-        for (int nz = nz0; nz <= nz1; ++nz) {
-            T rz = u[2] + T(nz) * nmf;
-            if (!(rz > cnear && rz <= cfar && rz > T(0))) continue;
-            T chi = rz * la.cell;
-            if (chi >= chi_max_src) continue;
-            T inv = la.inv_dtheta / rz;  // pixels per cell at this distance
-            T rmax = tmax / inv;          // |r_perp| bound in cells
-            int nx0 = (int)floor((-rmax - u[0] + half) / nmf);
-            int nx1 = (int)floor((rmax - u[0] + half) / nmf) + 1;
-            int ny0 = (int)floor((-rmax - u[1] + half) / nmf);
-            int ny1 = (int)floor((rmax - u[1] + half) / nmf) + 1;
-            T ach = a_of_chi(la, chi);
-            T base = la.wbase / (chi * ach);
-            for (int nx = nx0; nx <= nx1; ++nx) {
-                T t0 = (u[0] + T(nx) * nmf - half) * inv + hp;
-                if (!(t0 > T(-1) && t0 < T(la.npix))) continue;
-                for (int ny = ny0; ny <= ny1; ++ny) {
-                    T t1 = (u[1] + T(ny) * nmf - half) * inv + hp;
-                    if (!(t1 > T(-1) && t1 < T(la.npix))) continue;
-                    for (int s = 0; s < la.nsrc; ++s) {
-                        T cs = la.chi_src[s];
-                        if (chi < cs) splat(kappa + s * npix2, la.npix, t0, t1, base * (cs - chi) / cs);
-                    }
-                }
-            }
-        }
-    }
-}
-
-template <class T>
-void launch_lens(Parts<T> p, Geo g, const LensArgs<T>& la, T* kappa, hipStream_t st) {
-    long blocks = (g.npart + LB - 1) / LB;
-    if (blocks > 16384) blocks = 16384;
-    hipLaunchKernelGGL(k_lens<T>, dim3(blocks), dim3(LB), 0, st, p, g, la, kappa);
 }
 
 // ---------------------------------------------------------------------------
@@ -168,10 +80,36 @@ __device__ __forceinline__ void splat_region(typename LensAcc<T>::S* acc, int rs
     }
 }
 
-constexpr int LG = 256;  // threads per lens-gather workgroup
-constexpr int LU = 4;    // particles per thread in flight
-
+// Depth range [zmin, zmax] (cells from the observer) over which images of a
+// tile column whose transverse coordinate spans [Xa, Xa + TILE) can fall in
+// the angular window [alo, ahi] (X / Z in the window, with `margin` cells of
+// slack); false when empty.  The window of a map region is a thin slanted
+// pencil, so a column meets it over one depth interval.
 template <class T>
+__device__ __forceinline__ bool column_depths(T alo, T ahi, T Xa, T margin, T& zmin, T& zmax) {
+    const T U = Xa + T(TILE) + margin, L = Xa - margin;
+    // alo Z <= U
+    if (alo > T(0)) zmax = min(zmax, U / alo);
+    else if (U < T(0)) {
+        if (alo < T(0)) zmin = max(zmin, U / alo);
+        else return false;
+    }
+    // ahi Z >= L
+    if (ahi < T(0)) {
+        if (L < T(0)) zmax = min(zmax, L / ahi);
+        else return false;
+    } else if (L > T(0)) {
+        if (ahi > T(0)) zmin = max(zmin, L / ahi);
+        else return false;
+    }
+    return zmin <= zmax;
+}
+
+constexpr int LU = 4;  // particles per thread in flight
+
+// LG threads per workgroup: 256 for 32 x 32-pixel regions, 1024 for 64 x 64
+// (one workgroup per CU then holds the LDS, so it brings 16 waves)
+template <class T, int LG>
 __global__ __launch_bounds__(LG) void k_lens_gather(Parts<T> p, SortBufs sb, Geo g, LensArgs<T> la,
                                                     MapAdd<T> mean, T* kappa) {
     using A = LensAcc<T>;
@@ -228,8 +166,19 @@ __global__ __launch_bounds__(LG) void k_lens_gather(Parts<T> p, SortBufs sb, Geo
                 int ty0 = max((int)floor(bylo / T(TILE)), 0), ty1 = min((int)floor(byhi / T(TILE)), nt - 1);
                 for (int tx = tx0; tx <= tx1; ++tx)
                     for (int ty = ty0; ty <= ty1; ++ty) {
+                        // only the tiles of this column that the region's
+                        // pencil crosses
+                        T zmin = ca - margin, zmax = cb + margin;
+                        if (!column_depths(a0lo, a0hi, T(tx * TILE) + T(nx) * nmf - half, margin,
+                                           zmin, zmax) ||
+                            !column_depths(a1lo, a1hi, T(ty * TILE) + T(ny) * nmf - half, margin,
+                                           zmin, zmax))
+                            continue;
+                        const int tza = max(tz0, (int)floor((zmin - T(nz) * nmf) / T(TILE)));
+                        const int tzb = min(tz1, (int)floor((zmax - T(nz) * nmf) / T(TILE)));
+                        if (tza > tzb) continue;
                         const int col = (tx * nt + ty) * nt;
-                        const uint32_t lo = sb.start[col + tz0], hi = sb.start[col + tz1 + 1];
+                        const uint32_t lo = sb.start[col + tza], hi = sb.start[col + tzb + 1];
                         for (uint32_t base = lo; base < hi; base += LG * LU) {
                             uint32_t idv[LU];
                             T dv[LU][3];
@@ -298,8 +247,19 @@ void launch_lens_gather(Parts<T> p, SortBufs sb, Geo g, const LensArgs<T>& la,
                         const MapAdd<T>& mean, T* kappa, hipStream_t st) {
     int nreg = (la.npix + la.rs - 1) / la.rs;
     size_t lds = (size_t)la.nsrc * la.rs * la.rs * sizeof(typename LensAcc<T>::S);
-    hipLaunchKernelGGL(k_lens_gather<T>, dim3(nreg * nreg), dim3(LG), lds, st, p, sb, g, la, mean,
-                       kappa);
+    if (la.rs >= 64) {
+        static bool lds_raised = false;  // more than the default dynamic LDS
+        if (!lds_raised) {
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_lens_gather<T, 1024>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, 131072);
+            lds_raised = true;
+        }
+        hipLaunchKernelGGL((k_lens_gather<T, 1024>), dim3(nreg * nreg), dim3(1024), lds, st, p, sb, g,
+                           la, mean, kappa);
+    }
+    else
+        hipLaunchKernelGGL((k_lens_gather<T, 256>), dim3(nreg * nreg), dim3(256), lds, st, p, sb, g,
+                           la, mean, kappa);
 }
 
 template void launch_lens_gather<float>(Parts<float>, SortBufs, Geo, const LensArgs<float>&,
@@ -307,28 +267,5 @@ template void launch_lens_gather<float>(Parts<float>, SortBufs, Geo, const LensA
 template void launch_lens_gather<double>(Parts<double>, SortBufs, Geo, const LensArgs<double>&,
                                          const MapAdd<double>&, double*, hipStream_t);
 
-template <class T> struct MapVals { T v[MAX_SRC]; };
-
-template <class T>
-__global__ void k_add_maps(T* kappa, long npix2, int nsrc, MapVals<T> mv) {
-    long total = npix2 * nsrc;
-    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x)
-        kappa[i] += mv.v[i / npix2];
-}
-
-template <class T>
-void launch_add_maps(T* kappa, int npix, int nsrc, const T* vals, hipStream_t st) {
-    MapVals<T> mv;
-    for (int s = 0; s < MAX_SRC; ++s) mv.v[s] = s < nsrc ? vals[s] : T(0);
-    long npix2 = (long)npix * npix;
-    long blocks = (npix2 * nsrc + LB - 1) / LB;
-    if (blocks > 16384) blocks = 16384;
-    hipLaunchKernelGGL(k_add_maps<T>, dim3(blocks), dim3(LB), 0, st, kappa, npix2, nsrc, mv);
-}
-
-template void launch_lens<float>(Parts<float>, Geo, const LensArgs<float>&, float*, hipStream_t);
-template void launch_lens<double>(Parts<double>, Geo, const LensArgs<double>&, double*, hipStream_t);
-template void launch_add_maps<float>(float*, int, int, const float*, hipStream_t);
-template void launch_add_maps<double>(double*, int, int, const double*, hipStream_t);
 
 }  // namespace ml

@@ -64,23 +64,33 @@ void launch_fill_u32(uint32_t* p, uint32_t v, long n, hipStream_t st);
 template <class T>
 void launch_kick_drift_key(Parts<T> p, SortBufs s, Geo g, T kick, T drift, int mode,
                            uint32_t* status, hipStream_t st);
-void launch_scan(const uint32_t* count, uint32_t* start, int n, hipStream_t st);
+// Exclusive prefix sum of count[0..n) into start[0..n], start[n] = total;
+// block_sum: scratch of (n + 1023) / 1024 entries (n <= 1024 * 1024).
+void launch_scan(const uint32_t* count, uint32_t* start, uint32_t* block_sum, int n,
+                 hipStream_t st);
 // Permute disp, mom and id into tile order (dst).
 template <class T>
 void launch_scatter(Parts<T> src, Parts<T> dst, SortBufs s, Geo g, hipStream_t st);
 // CIC paint of tile-sorted particles by groups of tiles along axis 2:
 // interior cells go to rho, each group's upper halo shell to `halo` (size
-// paint_halo_elems); then the shells are added into the neighbours' faces.
+// paint_halo_elems); then the shells are added into the neighbours' faces,
+// unless merge_halo is false: the caller then merges them while reading rho
+// (fft_r2c_rows with paint_halo_merge).
 int paint_group_size(int nt, int esize);
 long paint_halo_elems(int nt, int esize);
 template <class T>
-void launch_paint(Parts<T> p, SortBufs s, Geo g, T mass, T* rho, T* halo, hipStream_t st);
+void launch_paint(Parts<T> p, SortBufs s, Geo g, T mass, T* rho, T* halo, hipStream_t st,
+                  bool merge_halo = true);
 // Paint per-particle values vals[k] (tile-sorted order) instead of the
 // mass; *vmax_bits holds the float bits of max|vals| (sets the fixed-point
 // scale of the float instantiation).
 template <class T>
 void launch_paint_values(Parts<T> p, SortBufs s, Geo g, T mass, T* rho, T* halo, const T* vals,
-                         const uint32_t* vmax_bits, hipStream_t st);
+                         const uint32_t* vmax_bits, hipStream_t st, bool merge_halo = true);
+template <class T> struct HaloMerge;
+// The shells of the last paint into `halo`, for a merge during the r2c pass.
+template <class T>
+HaloMerge<T> paint_halo_merge(Geo g, const T* halo);
 // CIC readout of the three force meshes; acc = f; mom += kick*acc if do_kick.
 template <class T>
 void launch_readout(Parts<T> p, SortBufs s, Geo g, const T* f0, const T* f1, const T* f2,
@@ -96,6 +106,9 @@ void launch_get_state(Parts<T> p, Geo g, T cell, T* x, T* mom_out, T* acc_out, h
 // State in (lattice order, Mpc/h) -> displacement (minimum image), momentum.
 template <class T>
 void launch_set_state(Parts<T> p, Geo g, T cell, const T* x, const T* mom_in, hipStream_t st);
+// N(0,1) noise [n] from Philox4x64-10 keyed by (seed, 0) and Box-Muller
+template <class T>
+void launch_noise(T* out, long n, uint64_t seed, hipStream_t st);
 
 // Born projection of one shell (lens.hip).
 constexpr int MAX_SRC = 16;
@@ -117,9 +130,5 @@ template <class T> struct MapAdd { T v[MAX_SRC]; };
 template <class T>
 void launch_lens_gather(Parts<T> p, SortBufs sb, Geo g, const LensArgs<T>& la,
                         const MapAdd<T>& mean, T* kappa, hipStream_t st);
-template <class T>
-void launch_lens(Parts<T> p, Geo g, const LensArgs<T>& la, T* kappa, hipStream_t st);
-template <class T>
-void launch_add_maps(T* kappa, int npix, int nsrc, const T* vals, hipStream_t st);
 
 }  // namespace ml

@@ -8,6 +8,7 @@
 // (node m at u = m) gives weight (1 - t) to node floor(u) and t to node
 // floor(u) + 1 along each axis, t = u - floor(u), nodes taken modulo Nm.
 #include "particles.h"
+#include "paint_halo.h"
 
 namespace ml {
 
@@ -146,33 +147,66 @@ void launch_kick_drift_key(Parts<T> p, SortBufs s, Geo g, T kick, T drift, int m
 // ---------------------------------------------------------------------------
 // exclusive scan of the tile histogram (one workgroup, chunk per thread)
 // ---------------------------------------------------------------------------
-constexpr int SCAN_T = 1024;
-__global__ __launch_bounds__(SCAN_T) void k_scan(const uint32_t* count, uint32_t* start, int n) {
-    __shared__ uint32_t part[SCAN_T];
-    const int t = threadIdx.x;
-    const int chunk = (n + SCAN_T - 1) / SCAN_T;
-    const int lo = t * chunk;
-    const int hi = min(n, lo + chunk);
-    uint32_t sum = 0;
-    for (int i = lo; i < hi; ++i) sum += count[i];
-    part[t] = sum;
+constexpr int SCAN_T = 1024;  // counts per scan block (one per thread)
+
+// Exclusive prefix sum of v over the 1024 threads of the block; *total gets
+// the block's sum.  Wave-level shuffles, then the 16 wave sums in LDS.
+__device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* total) {
+    __shared__ uint32_t ws[SCAN_T / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    uint32_t x = v;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        uint32_t y = __shfl_up(x, o, 64);
+        if (lane >= o) x += y;
+    }
+    if (lane == 63) ws[wid] = x;
     __syncthreads();
-    for (int off = 1; off < SCAN_T; off <<= 1) {
-        uint32_t v = t >= off ? part[t - off] : 0u;
-        __syncthreads();
-        part[t] += v;
-        __syncthreads();
+    if (wid == 0) {
+        uint32_t w = lane < SCAN_T / 64 ? ws[lane] : 0u;
+#pragma unroll
+        for (int o = 1; o < SCAN_T / 64; o <<= 1) {
+            uint32_t y = __shfl_up(w, o, 64);
+            if (lane >= o) w += y;
+        }
+        if (lane < SCAN_T / 64) ws[lane] = w;
     }
-    uint32_t run = part[t] - sum;  // exclusive prefix of this chunk
-    for (int i = lo; i < hi; ++i) {
-        start[i] = run;
-        run += count[i];
-    }
-    if (t == SCAN_T - 1) start[n] = part[t];
+    __syncthreads();
+    *total = ws[SCAN_T / 64 - 1];
+    return (wid ? ws[wid - 1] : 0u) + x - v;
 }
 
-void launch_scan(const uint32_t* count, uint32_t* start, int n, hipStream_t st) {
-    hipLaunchKernelGGL(k_scan, dim3(1), dim3(SCAN_T), 0, st, count, start, n);
+// pass 1: every block scans its 1024 counts (coalesced) and records its sum
+__global__ __launch_bounds__(SCAN_T) void k_scan_blocks(const uint32_t* count, uint32_t* start,
+                                                        uint32_t* block_sum, int n) {
+    const int i = blockIdx.x * SCAN_T + threadIdx.x;
+    uint32_t total;
+    uint32_t e = block_exclusive_scan(i < n ? count[i] : 0u, &total);
+    if (i < n) start[i] = e;
+    if (threadIdx.x == 0) block_sum[blockIdx.x] = total;
+}
+
+// pass 2: every block adds the sum of the blocks before it; the last one
+// also writes start[n] (the particle count)
+__global__ __launch_bounds__(SCAN_T) void k_scan_add(uint32_t* start, const uint32_t* block_sum,
+                                                     int n, int nblocks) {
+    const int t = threadIdx.x;
+    uint32_t total;
+    // nblocks <= SCAN_T: one block sum per thread
+    uint32_t off = block_exclusive_scan(t < nblocks ? block_sum[t] : 0u, &total);
+    __shared__ uint32_t mine;
+    if (t == (int)blockIdx.x) mine = off;
+    __syncthreads();
+    const int i = blockIdx.x * SCAN_T + t;
+    if (i < n) start[i] += mine;
+    if (blockIdx.x == nblocks - 1 && t == 0) start[n] = total;
+}
+
+void launch_scan(const uint32_t* count, uint32_t* start, uint32_t* block_sum, int n,
+                 hipStream_t st) {
+    const int nb = (n + SCAN_T - 1) / SCAN_T;
+    hipLaunchKernelGGL(k_scan_blocks, dim3(nb), dim3(SCAN_T), 0, st, count, start, block_sum, n);
+    hipLaunchKernelGGL(k_scan_add, dim3(nb), dim3(SCAN_T), 0, st, start, block_sum, n, nb);
 }
 
 // ---------------------------------------------------------------------------
@@ -207,31 +241,6 @@ void launch_scatter(Parts<T> src, Parts<T> dst, SortBufs s, Geo g, hipStream_t s
 // neighbouring groups in a fixed order.  The x and y faces are contiguous
 // along axis 2, so both kernels move whole rows.
 // ---------------------------------------------------------------------------
-template <int G> struct PaintBox {
-    static constexpr int LZ = TILE * G;          // interior depth along axis 2
-    static constexpr int EZ = LZ + 1;
-    static constexpr int CELLS = TE * TE * EZ;
-    static constexpr int HALO = 33 * EZ + TILE * TILE;  // x-face, y-face, z-face
-};
-
-template <int G>
-__device__ __forceinline__ int halo_index_g(int x, int y, int z) {
-    constexpr int EZ = PaintBox<G>::EZ;
-    if (x == TILE) return y * EZ + z;
-    if (y == TILE) return TE * EZ + x * EZ + z;
-    return 33 * EZ + x * TILE + y;
-}
-
-template <int G>
-__device__ __forceinline__ void halo_coords_g(int h, int& x, int& y, int& z) {
-    constexpr int EZ = PaintBox<G>::EZ;
-    if (h < TE * EZ) { x = TILE; y = h / EZ; z = h % EZ; return; }
-    h -= TE * EZ;
-    if (h < TILE * EZ) { x = h / EZ; y = TILE; z = h % EZ; return; }
-    h -= TILE * EZ;
-    x = h / TILE; y = h % TILE; z = PaintBox<G>::LZ;
-}
-
 constexpr int PU = 4;    // particles per thread in flight
 constexpr int PBP = 512; // threads per paint workgroup
 
@@ -358,24 +367,8 @@ __global__ __launch_bounds__(PB) void k_paint_halo_group(T* rho, const T* halo, 
         if (f < TILE * LZ) { lx = 0; ly = f / LZ; lz = f % LZ; }
         else if (f < 31 * LZ) { int h = f - TILE * LZ; lx = 1 + h / LZ; ly = 0; lz = h % LZ; }
         else { int h = f - 31 * LZ; lx = 1 + h / 15; ly = 1 + h % 15; lz = 0; }
-        T acc = T(0);
-#pragma unroll
-        for (int dx = 0; dx < 2; ++dx)
-#pragma unroll
-            for (int dy = 0; dy < 2; ++dy)
-#pragma unroll
-                for (int dz = 0; dz < 2; ++dz) {
-                    if ((dx | dy | dz) == 0) continue;
-                    if ((dx && lx) || (dy && ly) || (dz && lz)) continue;
-                    int nx = tx - dx < 0 ? nt - 1 : tx - dx;
-                    int ny = ty - dy < 0 ? nt - 1 : ty - dy;
-                    int nz = gz - dz < 0 ? ng - 1 : gz - dz;
-                    long nb = ((long)nx * nt + ny) * ng + nz;
-                    acc += halo[nb * BX::HALO +
-                                halo_index_g<G>(lx + TILE * dx, ly + TILE * dy, lz + LZ * dz)];
-                }
-        long cell = ((long)(tx * TILE + lx) * nm + (ty * TILE + ly)) * nm + (gz * LZ + lz);
-        rho[cell] += acc;
+        const int X = tx * TILE + lx, Y = ty * TILE + ly, Z = gz * LZ + lz;
+        rho[((long)X * nm + Y) * nm + Z] += halo_sum_g<T, G>(halo, nt, X, Y, Z);
     }
 }
 
@@ -395,23 +388,35 @@ long paint_halo_elems(int nt, int esize) {
 
 template <class T>
 void launch_paint_values(Parts<T> p, SortBufs s, Geo g, T mass, T* rho, T* halo, const T* vals,
-                         const uint32_t* vmax_bits, hipStream_t st) {
+                         const uint32_t* vmax_bits, hipStream_t st, bool merge_halo) {
     int G = paint_group_size(g.nt, sizeof(T));
     int groups = g.nt * g.nt * (g.nt / G);
     if (G == 2) {
         hipLaunchKernelGGL((k_paint_group<T, 2>), dim3(groups), dim3(PBP), 0, st, p, s, g, mass, rho,
                            halo, vals, vmax_bits);
-        hipLaunchKernelGGL((k_paint_halo_group<T, 2>), dim3(groups), dim3(PB), 0, st, rho, halo, g);
+        if (merge_halo)
+            hipLaunchKernelGGL((k_paint_halo_group<T, 2>), dim3(groups), dim3(PB), 0, st, rho, halo, g);
     } else {
         hipLaunchKernelGGL((k_paint_group<T, 1>), dim3(groups), dim3(PBP), 0, st, p, s, g, mass, rho,
                            halo, vals, vmax_bits);
-        hipLaunchKernelGGL((k_paint_halo_group<T, 1>), dim3(groups), dim3(PB), 0, st, rho, halo, g);
+        if (merge_halo)
+            hipLaunchKernelGGL((k_paint_halo_group<T, 1>), dim3(groups), dim3(PB), 0, st, rho, halo, g);
     }
 }
 
 template <class T>
-void launch_paint(Parts<T> p, SortBufs s, Geo g, T mass, T* rho, T* halo, hipStream_t st) {
-    launch_paint_values<T>(p, s, g, mass, rho, halo, nullptr, nullptr, st);
+void launch_paint(Parts<T> p, SortBufs s, Geo g, T mass, T* rho, T* halo, hipStream_t st,
+                  bool merge_halo) {
+    launch_paint_values<T>(p, s, g, mass, rho, halo, nullptr, nullptr, st, merge_halo);
+}
+
+template <class T>
+HaloMerge<T> paint_halo_merge(Geo g, const T* halo) {
+    HaloMerge<T> hm;
+    hm.halo = halo;
+    hm.nt = g.nt;
+    hm.G = paint_group_size(g.nt, sizeof(T));
+    return hm;
 }
 
 // ---------------------------------------------------------------------------
@@ -619,21 +624,82 @@ void launch_set_state(Parts<T> p, Geo g, T cell, const T* x, const T* mom_in, hi
     hipLaunchKernelGGL(k_set_state<T>, dim3(blocks), dim3(PB), 0, st, p, g, cell, x, mom_in);
 }
 
+// ---------------------------------------------------------------------------
+// White noise from a counter-based generator: Philox4x64-10 (Salmon, Moraes,
+// Dror, Shaw, SC 2011) keyed by (seed, 0); block c uses the counter
+// (c + 1, 0, 0, 0) and yields 4 words, turned into uniforms (w >> 11) 2^-53
+// and, pairwise, into 4 normals by Box-Muller: r = sqrt(-2 ln(1 - u0)),
+// (r cos 2 pi u1, r sin 2 pi u1).  Element i of the lattice is normal i.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox4x64_10(uint64_t c[4], uint64_t k0, uint64_t k1) {
+    constexpr uint64_t M0 = 0xD2E7470EE14C6C93ull, M1 = 0xCA5A826395121157ull;
+    constexpr uint64_t W0 = 0x9E3779B97F4A7C15ull, W1 = 0xBB67AE8584CAA73Bull;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += W0;
+            k1 += W1;
+        }
+        uint64_t hi0 = __umul64hi(M0, c[0]), lo0 = M0 * c[0];
+        uint64_t hi1 = __umul64hi(M1, c[2]), lo1 = M1 * c[2];
+        uint64_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+    }
+}
+
+template <class T>
+__global__ void k_noise(T* out, long n, uint64_t key0, uint64_t key1) {
+    const long nblk = (n + 3) / 4;
+    for (long b = blockIdx.x * (long)blockDim.x + threadIdx.x; b < nblk;
+         b += (long)gridDim.x * blockDim.x) {
+        uint64_t c[4] = {(uint64_t)b + 1u, 0u, 0u, 0u};
+        philox4x64_10(c, key0, key1);
+        double z[4];
+#pragma unroll
+        for (int j = 0; j < 4; j += 2) {
+            double u0 = (double)(c[j] >> 11) * 0x1.0p-53;
+            double u1 = (double)(c[j + 1] >> 11) * 0x1.0p-53;
+            double r = sqrt(-2.0 * log1p(-u0));
+            double sn, cs;
+            sincos(2.0 * 3.14159265358979323846 * u1, &sn, &cs);
+            z[j] = r * cs;
+            z[j + 1] = r * sn;
+        }
+        const long i0 = 4 * b;
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+            if (i0 + j < n) out[i0 + j] = (T)z[j];
+    }
+}
+
+template <class T>
+void launch_noise(T* out, long n, uint64_t seed, hipStream_t st) {
+    long blocks = ((n + 3) / 4 + PB - 1) / PB;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_noise<T>, dim3(blocks), dim3(PB), 0, st, out, n, seed, (uint64_t)0);
+}
+
 #define ML_INST(T)                                                                                \
     template void launch_fill<T>(T*, T, long, hipStream_t);                                       \
     template void launch_scale_copy<T>(T*, const T*, T, long, hipStream_t);                       \
     template void launch_kick_drift_key<T>(Parts<T>, SortBufs, Geo, T, T, int, uint32_t*,        \
                                            hipStream_t);                                          \
     template void launch_scatter<T>(Parts<T>, Parts<T>, SortBufs, Geo, hipStream_t);              \
-    template void launch_paint<T>(Parts<T>, SortBufs, Geo, T, T*, T*, hipStream_t);               \
+    template void launch_paint<T>(Parts<T>, SortBufs, Geo, T, T*, T*, hipStream_t, bool);         \
     template void launch_paint_values<T>(Parts<T>, SortBufs, Geo, T, T*, T*, const T*,            \
-                                         const uint32_t*, hipStream_t);                           \
+                                         const uint32_t*, hipStream_t, bool);                     \
+    template HaloMerge<T> paint_halo_merge<T>(Geo, const T*);                                     \
     template void launch_readout<T>(Parts<T>, SortBufs, Geo, const T*, const T*, const T*, T, int, \
                                     uint32_t*, hipStream_t);                                      \
     template void launch_init_ic<T>(Parts<T>, Geo, const T*, const T*, const T*, T, T,            \
                                     hipStream_t);                                                 \
     template void launch_get_state<T>(Parts<T>, Geo, T, T*, T*, T*, hipStream_t);                 \
-    template void launch_set_state<T>(Parts<T>, Geo, T, const T*, const T*, hipStream_t);
+    template void launch_set_state<T>(Parts<T>, Geo, T, const T*, const T*, hipStream_t);    \
+    template void launch_noise<T>(T*, long, uint64_t, hipStream_t);
 ML_INST(float)
 ML_INST(double)
 

@@ -95,6 +95,29 @@ class Simulation:
         check(lib().pm_init_ic(self._h, _ptr(noise), float(a0)), "pm_init_ic")
         self.a = float(a0)
 
+    def init_ic_seed(self, seed: int, a0: float):
+        """Initial conditions from noise drawn on the device from `seed`."""
+        check(lib().pm_init_ic_seed(self._h, int(seed), float(a0)), "pm_init_ic_seed")
+        self.a = float(a0)
+
+    def noise(self, seed: int) -> torch.Tensor:
+        out = torch.empty((self.np_side,) * 3, dtype=self.dtype, device=self.device)
+        check(lib().pm_noise(self._h, int(seed), _ptr(out)), "pm_noise")
+        return out
+
+    def reconfigure(self, box=None, fov_deg=None, z_src=None, **cosmo):
+        """New cosmology / box / map geometry on the same arena."""
+        self.box = float(box) if box is not None else self.box
+        self.fov_deg = float(fov_deg) if fov_deg is not None else self.fov_deg
+        if z_src is not None:
+            if len(z_src) != len(self.z_src):
+                raise ValueError("the number of source planes is fixed by the arena")
+            self.z_src = tuple(z_src)
+        p = make_params(self.np_side, self.nm_side, self.box, dtype=self.dtype, **cosmo)
+        l = make_lens(self.npix, self.fov_deg, self.z_src)
+        check(lib().pm_reconfigure(self._h, ctypes.byref(p), ctypes.byref(l)), "pm_reconfigure")
+        self.a = None
+
     def step(self, a0: float, a1: float):
         check(lib().pm_step(self._h, float(a0), float(a1)), "pm_step")
         self.a = float(a1)

@@ -4,6 +4,8 @@ Float64 instantiations must agree to round-off (1e-10 relative or better);
 float32 ones to the stated tolerances: positions within 1e-4 of a mesh cell,
 convergence maps within 1e-4 relative RMS.
 """
+import functools
+
 import numpy as np
 import pytest
 import torch
@@ -117,29 +119,52 @@ def test_cfg1_positions_and_kappa(dtype):
     assert rel_rms(kap_g, kap) <= _tol(dtype, 1e-10, 1e-4)
 
 
-@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
-def test_lens_shell_of_static_field(dtype):
-    """One shell at a thick early step: several box replicas along the line of
-    sight and across the field, four source planes.  Clustered particles, so
-    the map is not a cancellation of the particle and mean terms; float32 is
-    also held to 1e-5 of the particle term alone (rounding of ~10^4 atomic
-    additions per pixel)."""
+LENS_GEOMETRIES = {
+    # thick early shell: ~13 box replicas along the line of sight, several
+    # across the 6 deg field, four source planes
+    "thick": (32, 64.0, 48, 6.0, (0.5, 1.0, 1.5, 2.0), 0.45, 0.6),
+    # 8 deg field through a thin shell that straddles z_s = 2 and lies behind
+    # z_s = 1: ~8 transverse replicas per axis at the far edge
+    "wide": (16, 64.0, 64, 8.0, (1.0, 2.0), 0.33, 0.345),
+    # the last shell, reaching the observer
+    "near": (32, 64.0, 48, 6.0, (0.5, 1.0), 0.9, 1.0),
+    # a 256^2 map: 64 x 64-pixel regions with 1024-thread workgroups
+    "regions64": (16, 64.0, 256, 4.0, (1.0, 2.0), 0.5, 0.6),
+}
+
+
+@functools.lru_cache(maxsize=None)
+def _lens_oracle(geometry):
+    """Oracle maps (with and without the mean term) of a geometry's shell."""
     from oracle import lens
-    wl = W.Workload("lens", 32, 32, 64.0, 0.1, 1.0, 4, 48, 6.0, (0.5, 1.0, 1.5, 2.0))
+    np_side, box, npix, fov, zs, a_far, a_near = LENS_GEOMETRIES[geometry]
+    c = cosmo_of(W.Workload("lens", np_side, np_side, box, 0.1, 1.0, 4, npix, fov, zs))
+    x = W.clustered_positions(np_side, np_side, box, seed=51)
+    geom = lens.MapGeometry(npix, fov, zs, c)
+    return (lens.project_shell(x, a_far, a_near, c, box, np_side, geom),
+            lens.project_shell(x, a_far, a_near, c, box, np_side, geom, include_mean=False))
+
+
+@pytest.mark.parametrize("geometry", list(LENS_GEOMETRIES))
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+def test_lens_shell_of_static_field(dtype, geometry):
+    """One shell of a static particle field against the oracle.  Clustered
+    particles, so the map is not a cancellation of the particle and mean
+    terms; float32 is also held to 1e-5 of the particle term alone (rounding
+    of ~10^4 atomic additions per pixel)."""
+    np_side, box, npix, fov, zs, a_far, a_near = LENS_GEOMETRIES[geometry]
+    wl = W.Workload("lens", np_side, np_side, box, 0.1, 1.0, 4, npix, fov, zs)
     c = cosmo_of(wl)
-    x = W.clustered_positions(32, 32, wl.box, seed=51)
+    x = W.clustered_positions(np_side, np_side, wl.box, seed=51)
     p = np.zeros_like(x)
-    a_far, a_near = 0.45, 0.6
-    log(f"lens static {dtype}")
+    log(f"lens static {dtype} {geometry}")
     with new_sim(wl, dtype) as sim:
         sim.set_state(torch.from_numpy(x), torch.from_numpy(p), a_near)
         k = sim.new_maps()
         sim.lens(a_far, a_near, k)
         kg = to_np(k)
         sim.sync()
-    geom = lens.MapGeometry(wl.npix, wl.fov_deg, wl.z_src, c)
-    ko = lens.project_shell(x, a_far, a_near, c, wl.box, 32, geom)
-    kp = lens.project_shell(x, a_far, a_near, c, wl.box, 32, geom, include_mean=False)
+    ko, kp = _lens_oracle(geometry)
     e_tot = rel_rms(kg, ko)
     e_part = float(np.sqrt(np.mean((kg - ko) ** 2) / np.mean(kp ** 2)))
     log(f"lens static {dtype}: kappa rel-rms {e_tot:.2e}, vs particle term {e_part:.2e}")
