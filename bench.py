@@ -5,14 +5,16 @@
 Workload (default): 256^3 particles on a 512^3 force mesh in a 205 Mpc/h
 box, 40 PM steps linear in a from 0.01 to 1.0, four 2048^2 convergence maps
 over 5 deg x 5 deg at z_s = 0.5, 1, 1.5, 2 (float32), seeded Gaussian white
-noise initial conditions.  A "step" is one pm_step plus the lens_project of
-its shell.  W untimed steps run first; then the initial conditions are
-regenerated (untimed) and K consecutive steps of the schedule are timed
+noise initial conditions.  A "step" is one step of pm_run: a KDK step and
+the Born projection of its shell (bit for bit pm_step + lens_project).  W
+untimed steps run first; then the initial conditions are regenerated
+(untimed) and K consecutive steps of the schedule are timed
 (the schedule restarts from fresh initial conditions, inside the timed
 region, if K exceeds it).  Per-kernel durations come from HIP events the
 library records on its own stream during the timed region.
 
-The line also carries the serving figures named by the metric: p50/p99
+The line also carries the forward + reverse timing of the gradient
+workload (gradient_bench), the serving figures named by the metric: p50/p99
 latency (arrival to maps on the host) and throughput of Poisson streams of
 mixed-size requests, served (continuous batching) and plain (one
 simulation at a time), see serving_bench; and the float64 oracle timed on
@@ -58,6 +60,8 @@ def algorithmic_bytes(wl, esize=4):
         "fft_c2c_axis1_dual": 3 * S,       # R 1 spectrum, W 2
         "fft_c2r_axis2": S + M,
         "readout_kick": 3 * M + 52 * P,    # R 3 meshes, disp,id,mom  W mom,acc
+        # fused with the next step's kick, drift and keys:
+        "readout_kick_drift_key": 3 * M + 60 * P,  # R 3 meshes, disp,id,mom  W disp,mom,key,rank
         "lens_gather": 16 * P + 2 * maps,  # R disp,id  RW maps (incl. mean term)
         "scan": 0,
     }
@@ -68,11 +72,12 @@ TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
 KERNEL_SYMBOL = {
     "fft_grad_axis0": ("k_grad_x0<float, 512", "paper_2012_07266_amd/csrc/fft.hip"),
     "readout_kick": ("k_readout<float>", "paper_2012_07266_amd/csrc/particles.hip"),
+    "readout_kick_drift_key": ("k_readout<float>", "paper_2012_07266_amd/csrc/particles.hip"),
     "paint": ("k_paint_group<float", "paper_2012_07266_amd/csrc/particles.hip"),
     "fft_c2c_axis1_inv": ("k_c2c_view<float, 512, 16, -1>", "paper_2012_07266_amd/csrc/fft.hip"),
     "fft_c2c_axis1_dual": ("k_c2c_view_dual<float, 512", "paper_2012_07266_amd/csrc/fft.hip"),
     "fft_c2r_axis2": ("k_c2r_rows<float, 256", "paper_2012_07266_amd/csrc/fft.hip"),
-    "lens_gather": ("k_lens_gather<float>", "paper_2012_07266_amd/csrc/lens.hip"),
+    "lens_gather": ("k_lens_gather<float", "paper_2012_07266_amd/csrc/lens.hip"),
 }
 COPY_BYTES = 1 << 30  # the calibration copy moves 1 GiB in and 1 GiB out
 
@@ -180,6 +185,58 @@ def cpu_baseline(wl, frac=8):
                        f"float64 FFT force; {t4 - t0:.1f} s of CPU work, est. {per_step:.1f} s/step")}
 
 
+def gradient_bench(reps=3):
+    """Forward + hand-written reverse pass of the gradient workload: 128^3
+    particles on a 256^3 mesh, 128 Mpc/h, 20 steps from a = 0.01, one
+    1024^2 map over 2 deg at z_s = 1, float32; loss chi^2 = sum (kappa -
+    kappa_t)^2 / sigma^2 against a target map from another seed with
+    Gaussian pixel noise sigma = 0.01; gradients with respect to the 128^3
+    noise values, Omega_m and sigma_8, with per-step checkpoints."""
+    import torch
+    import workloads as W
+    from paper_2012_07266_amd import Simulation
+    from paper_2012_07266_amd.autograd import forward_with_checkpoints, reverse_pass
+    wl = W.CFG3
+    a = wl.a_grid()
+    dev = torch.device("cuda", 0)
+    sim = Simulation(wl.np_side, wl.nm_side, wl.box, wl.npix, wl.fov_deg, wl.z_src,
+                     dtype=torch.float32, omega_m=wl.omega_m, sigma8=wl.sigma8, h=wl.h,
+                     n_s=wl.n_s, omega_b=wl.omega_b, t_cmb=wl.t_cmb)
+    sigma = 0.01
+    target, _ = forward_with_checkpoints(
+        sim, torch.from_numpy(W.white_noise(wl.np_side, 4)).to(dev, torch.float32), a)
+    gen = np.random.Generator(np.random.Philox(key=5))
+    target = target + torch.from_numpy(
+        gen.normal(0.0, sigma, size=tuple(target.shape))).to(dev, torch.float32)
+    noise = torch.from_numpy(W.white_noise(wl.np_side, wl.seed)).to(dev, torch.float32)
+    t_f, t_b = [], []
+    for r in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        kappa, states = forward_with_checkpoints(sim, noise, a)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        kbar = 2.0 * (kappa - target) / sigma ** 2
+        sim.init_ic(noise, a[0])  # the reverse of the IC reads this noise
+        nb, g_om, g_s8 = reverse_pass(sim, a, states, kbar)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if r > 0:  # the first pass is a warm-up
+            t_f.append(t1 - t0)
+            t_b.append(t2 - t1)
+        del states
+    sim.close()
+    f, b = float(np.median(t_f)), float(np.median(t_b))
+    ps = wl.np_side ** 3 * wl.nsteps
+    return {"workload": (f"{wl.name}: 128^3 particles, 256^3 mesh, 20 steps, 1 x 1024^2 map, "
+                         "float32, chi^2 loss, gradients w.r.t. noise, Omega_m, sigma_8"),
+            "forward_ms": 1e3 * f, "reverse_ms": 1e3 * b, "reverse_over_forward": b / f,
+            "forward_particle_steps_per_s": ps / f,
+            "forward_plus_reverse_particle_steps_per_s": ps / (f + b),
+            "grad_finite": bool(torch.isfinite(nb).all().item() and np.isfinite(g_om)
+                                and np.isfinite(g_s8))}
+
+
 def serving_bench(n_requests):
     """Poisson streams of serving requests: sizes 64^3/128^3, 128^3/256^3,
     192^3/384^3 (box = Np Mpc/h), 10-30 steps from a = 0.1, Om ~ U[0.25, 0.35],
@@ -215,6 +272,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="no per-kernel events in the timed region (roofline omitted)")
+    ap.add_argument("--no-gradient", action="store_true",
+                    help="skip the forward + reverse timing of the gradient workload")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving streams (p50/p99 latency, served vs plain)")
     ap.add_argument("--serve-requests", type=int, default=100)
@@ -247,15 +306,18 @@ def main():
     kappa = sim.new_maps()
 
     def run_steps(k, i0):
+        """k steps of the schedule from step i0 (pm_run over each contiguous
+        stretch; a new run restarts from fresh initial conditions)."""
         i = i0
-        for _ in range(k):
+        while k > 0:
             if i == wl.nsteps:
                 sim.init_ic(noise, a[0])
                 kappa.zero_()
                 i = 0
-            sim.step(a[i], a[i + 1])
-            sim.lens(a[i], a[i + 1], kappa)
-            i += 1
+            m = min(k, wl.nsteps - i)
+            sim.steps(a[i:i + m + 1], kappa)
+            i += m
+            k -= m
         return i
 
     if args.calibrate_copy:
@@ -316,6 +378,8 @@ def main():
                            "traffic": load_traffic(dom)}
         out["hbm_effective_gbs_all_kernels"] = total_bytes / (total_ms * 1e-3) / 1e9
         out["kernels"] = kern
+    if not args.no_gradient:
+        out["gradient"] = gradient_bench()
     if not args.no_serving:
         out["serving"] = serving_bench(args.serve_requests)
     out["paper_context"] = ("MADLens on 32 Haswell cores: ~6.2e6 particle-steps/s "

@@ -151,6 +151,16 @@ int pm_step(pm_sim* sim, double a0, double a1);
  * Errors: PM_ESTATE, PM_EINVAL (NULL kappa). */
 int lens_project(pm_sim* sim, double a0, double a1, void* kappa);
 
+/* nsteps PM steps along the host array a_grid[0..nsteps] with the Born
+ * projection of every step's shell into kappa (device [nsrc][npix][npix],
+ * ACCUMULATED): the same results as pm_step(a_i, a_i+1) followed by
+ * lens_project(a_i, a_i+1) for i = 0..nsteps-1, bit for bit, with less
+ * memory traffic (each step's force readout also starts the next step:
+ * half-kick, drift and sort keys).  The state must be at a_grid[0]; it ends
+ * at a_grid[nsteps].  Errors: PM_EINVAL (NULL array, nsteps < 1),
+ * PM_ESTATE. */
+int pm_run(pm_sim* sim, const double* a_grid, int32_t nsteps, void* kappa);
+
 /* Copy the state out, in lattice order: x [3][Np^3] in [0, L), p [3][Np^3]
  * (device arrays; either may be NULL).  *a_out receives the current scale
  * factor when a_out is non-NULL (a host pointer). */

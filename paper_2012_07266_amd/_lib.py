@@ -58,6 +58,7 @@ SIGNATURES = {
     "pm_noise": (_I, [_P, ctypes.c_uint64, _P]),
     "pm_reconfigure": (_I, [_P, ctypes.POINTER(PmParams), ctypes.POINTER(LensParams)]),
     "pm_step": (_I, [_P, _D, _D]),
+    "pm_run": (_I, [_P, ctypes.POINTER(_D), ctypes.c_int32, _P]),
     "lens_project": (_I, [_P, _D, _D, _P]),
     "pm_get_state": (_I, [_P, _P, _P, ctypes.POINTER(_D)]),
     "pm_set_state": (_I, [_P, _P, _P, _D]),

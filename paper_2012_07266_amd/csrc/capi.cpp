@@ -201,6 +201,7 @@ struct SimBase {
     virtual int reconfigure(const pm_params* p, const lens_params* l) = 0;
     virtual int step(double a0, double a1) = 0;
     virtual int lens(double a0, double a1, void* kappa) = 0;
+    virtual int run(const double* agrid, int nsteps, void* kappa) = 0;
     virtual int get_state(void* x, void* p, double* a) = 0;
     virtual int set_state(const void* x, const void* p, double a) = 0;
     virtual int get_force(void* rho, void* fm, void* acc) = 0;
@@ -526,6 +527,13 @@ template <class T> struct Sim final : SimBase {
     int lens(double a0, double a1, void* kappa) override {
         if (!kappa) return PM_EINVAL;
         if (a_cur < 0 || std::fabs(a1 - a_cur) > 1e-12 * std::fabs(a_cur) + 1e-15) return PM_ESTATE;
+        project_shell(a0, a1, reinterpret_cast<T*>(kappa));
+        return check_launch();
+    }
+
+    // Born projection of the shell (chi(a1), chi(a0)] of the current,
+    // tile-sorted positions (which must be those at a1) into kappa.
+    void project_shell(double a0, double a1, T* kappa) {
         LensArgs<T> la{};
         la.npix = npix;
         la.nsrc = nsrc;
@@ -535,7 +543,7 @@ template <class T> struct Sim final : SimBase {
         // images and its mean term both need chi < chi_s)
         double chis_max = 0;
         for (double c : chisrc) chis_max = std::max(chis_max, c);
-        if (chi_near >= chis_max) return PM_OK;
+        if (chi_near >= chis_max) return;
         la.chi_near = (T)chi_near;
         la.chi_far = (T)chi_far;
         double dth = fov * PI / 180.0 / npix;
@@ -550,10 +558,52 @@ template <class T> struct Sim final : SimBase {
         // 128 KB of LDS: each region's frustum is then twice as wide, and
         // the tile columns it reads hold fewer particles outside it
         la.rs = ((size_t)nsrc * 64 * 64 * 8 <= 131072 && npix >= 256) ? 64 : 32;
-        T* k = reinterpret_cast<T*>(kappa);
         MapAdd<T> mv{};
         for (int s = 0; s < nsrc; ++s) mv.v[s] = (T)cosmo.shell_mean(chi_near, chi_far, chisrc[s]);
-        { ProfScope ps(prof, "lens_gather"); launch_lens_gather<T>(cur, sb, geo, la, mv, k, st); }
+        { ProfScope ps(prof, "lens_gather"); launch_lens_gather<T>(cur, sb, geo, la, mv, kappa, st); }
+    }
+
+    // nsteps KDK steps along agrid with the projection of every shell: the
+    // same operations as pm_step and lens_project in turn, but each step's
+    // readout also applies the next step's first half-kick and drift and
+    // computes its sort keys (no separate kick/drift pass, no force array
+    // in between), and each shell is projected right after the paint, while
+    // the particles are at the end of their step.
+    int run(const double* agrid, int nsteps, void* kappa) override {
+        if (!agrid || !kappa || nsteps < 1) return PM_EINVAL;
+        if (a_cur < 0 || std::fabs(agrid[0] - a_cur) > 1e-12 * std::fabs(a_cur) + 1e-15)
+            return PM_ESTATE;
+        for (int i = 0; i < nsteps; ++i)
+            if (!(agrid[i + 1] > 0 && agrid[i + 1] <= 1.5)) return PM_EINVAL;
+        T* kap = reinterpret_cast<T*>(kappa);
+        for (int i = 0; i < nsteps; ++i) {
+            const double a0 = agrid[i], a1 = agrid[i + 1], ah = 0.5 * (a0 + a1);
+            if (i == 0) {
+                sort((T)cosmo.kick(a0, ah, a0), (T)cosmo.drift(a0, a1, ah), MODE_KICK | MODE_DRIFT);
+            } else {  // keys and ranks come from the previous readout
+                { ProfScope ps(prof, "scan"); launch_scan(sb.count, sb.start, scan_sum, ntiles, st); }
+                { ProfScope ps(prof, "scatter"); launch_scatter<T>(cur, alt, sb, geo, st); }
+                std::swap(cur.disp, alt.disp);
+                std::swap(cur.mom, alt.mom);
+                std::swap(cur.id, alt.id);
+            }
+            paint(true);
+            project_shell(a0, a1, kap);
+            fft_forward_grad(P.nm, nullptr, tw_nm, tw_hm, twp_nm, paint_halo_merge<T>(geo, halo));
+            const T k2 = (T)cosmo.kick(ah, a1, a1);
+            ReadoutNext<T> nx;
+            if (i + 1 < nsteps) {
+                const double a2 = agrid[i + 2], ah2 = 0.5 * (a1 + a2);
+                nx.on = 1;
+                nx.kick = (T)cosmo.kick(a1, ah2, a1);
+                nx.drift = (T)cosmo.drift(a1, a2, ah2);
+                launch_fill_u32(sb.count, 0u, ntiles, st);
+            }
+            ProfScope ps(prof, nx.on ? "readout_kick_drift_key" : "readout_kick");
+            launch_readout<T>(cur, sb, geo, mesh[0], mesh[1], mesh[2], k2, 1, status, st, nx);
+        }
+        meshes_valid = true;
+        a_cur = agrid[nsteps];
         return check_launch();
     }
 
@@ -840,6 +890,9 @@ int pm_reconfigure(pm_sim* sim, const pm_params* p, const lens_params* l) {
     return rc ? rc : sim->impl->reconfigure(p, l);
 }
 int pm_step(pm_sim* sim, double a0, double a1) { return sim ? sim->impl->step(a0, a1) : PM_EINVAL; }
+int pm_run(pm_sim* sim, const double* a_grid, int32_t nsteps, void* kappa) {
+    return sim ? sim->impl->run(a_grid, nsteps, kappa) : PM_EINVAL;
+}
 int lens_project(pm_sim* sim, double a0, double a1, void* kappa) {
     return sim ? sim->impl->lens(a0, a1, kappa) : PM_EINVAL;
 }

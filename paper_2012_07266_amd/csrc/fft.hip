@@ -191,9 +191,9 @@ __device__ __forceinline__ void reg_chain(cx<T>* v, cx<T>* buf, const cx<T>* tw,
 // `io` holds nrows rows of 2H reals on input and H complex on output.
 // ---------------------------------------------------------------------------
 // When hm.halo is set, the rows are a freshly painted density whose paint
-// boxes' upper shells have not been merged yet: each loaded cell adds the
-// shells owed to it (the same sum, in the same order, as the merge kernel of
-// the paint), so the transform sees the merged density.
+// boxes' upper shells have not been merged yet: once the rows are in LDS the
+// cells owed a shell add it (the same sum, in the same order, as the merge
+// kernel of the paint), so the transform sees the merged density.
 template <class T, int H, int W>
 __global__ __launch_bounds__(NT) void k_r2c_rows(T* io, cx<T>* nyq, const cx<T>* tw_h,
                                                  const cx<T>* tw_post, HaloMerge<T> hm) {
@@ -212,18 +212,6 @@ __global__ __launch_bounds__(NT) void k_r2c_rows(T* io, cx<T>* nyq, const cx<T>*
             int f = tid + it * NT;
             if ((W * H) % NT == 0 || f < W * H) v[it] = in[f];  // rows are contiguous
         }
-        if (hm.halo) {
-#pragma unroll
-            for (int it = 0; it < IT; ++it) {
-                int f = tid + it * NT;
-                if ((W * H) % NT == 0 || f < W * H) {
-                    const size_t r = r0 + f / H;  // row r = X * 2H + Y
-                    const int X = (int)(r / (2 * H)), Y = (int)(r % (2 * H)), Z = 2 * (f % H);
-                    v[it].re += halo_sum<T>(hm, X, Y, Z);
-                    v[it].im += halo_sum<T>(hm, X, Y, Z + 1);
-                }
-            }
-        }
 #pragma unroll
         for (int it = 0; it < IT; ++it) {
             int f = tid + it * NT;
@@ -231,6 +219,8 @@ __global__ __launch_bounds__(NT) void k_r2c_rows(T* io, cx<T>* nyq, const cx<T>*
         }
     }
     __syncthreads();
+    // rows r0 .. r0 + W - 1 share X (2H is a multiple of W)
+    if (hm.halo) merge_rows<T, H, W, NT>(hm, buf, (int)(r0 / (2 * H)), (int)(r0 % (2 * H)), tid);
     fft_lds<T, H, W, 1>(buf, tws, tid);
     cx<T>* out = reinterpret_cast<cx<T>*>(io) + r0 * H;
     constexpr int HK = H / 2 + 1;
@@ -280,10 +270,6 @@ __global__ __launch_bounds__(NT) void k_c2r_rows(T* io, const cx<T>* nyq, const 
             int w = f / HK, k = f % HK;
             xkv[it] = in[(size_t)w * H + k];
             xmv[it] = k == 0 ? nyq[r0 + w] : in[(size_t)w * H + (H - k)];
-            if (mul_k2) {
-                xkv[it] = scale(xkv[it], T(k));
-                xmv[it] = scale(xmv[it], k == 0 ? T(0) : T(H - k));
-            }
         }
     }
 #pragma unroll
@@ -292,6 +278,10 @@ __global__ __launch_bounds__(NT) void k_c2r_rows(T* io, const cx<T>* nyq, const 
         if (f >= W * HK) continue;
         int w = f / HK, k = f % HK;
         cx<T> xk = xkv[it], xm = xmv[it];
+        if (mul_k2) {  // after all loads are in flight
+            xk = scale(xk, T(k));
+            xm = scale(xm, k == 0 ? T(0) : T(H - k));
+        }
         if (k == 0) {
             xk.im = T(0);
             xm.im = T(0);

@@ -43,22 +43,18 @@ __device__ __forceinline__ void halo_coords_g(int h, int& x, int& y, int& z) {
     x = h / TILE; y = h % TILE; z = PaintBox<G>::LZ;
 }
 
-// Sum of the neighbouring shells owed to mesh cell (X, Y, Z); 0 for cells
-// off the low faces.  The seven candidate values are loaded first (each
-// only where it is owed, else 0) and then summed in the fixed order
-// (dx, dy, dz) = 001, 010, 011, 100, 101, 110, 111, so that a caller's loads
-// are all in flight at once.
+// The seven shell values that may be owed to mesh cell (X, Y, Z), in the
+// order (dx, dy, dz) = 001, 010, 011, 100, 101, 110, 111; 0 where nothing is
+// owed.  Loads only; a caller can fetch several cells before summing.
 template <class T, int G>
-__device__ __forceinline__ T halo_sum_g(const T* halo, int nt, int X, int Y, int Z) {
+__device__ __forceinline__ void halo_fetch_g(const T* halo, int nt, int X, int Y, int Z, T (&v)[7]) {
     using BX = PaintBox<G>;
     constexpr int LZ = BX::LZ;
     const int lx = X % TILE, ly = Y % TILE, lz = Z % LZ;
-    if (lx && ly && lz) return T(0);
     const int tx = X / TILE, ty = Y / TILE, gz = Z / LZ, ng = nt / G;
     const int txm = tx == 0 ? nt - 1 : tx - 1;
     const int tym = ty == 0 ? nt - 1 : ty - 1;
     const int gzm = gz == 0 ? ng - 1 : gz - 1;
-    T v[7];
 #pragma unroll
     for (int d = 1; d < 8; ++d) {
         const int dx = d >> 2, dy = (d >> 1) & 1, dz = d & 1;
@@ -69,10 +65,25 @@ __device__ __forceinline__ T halo_sum_g(const T* halo, int nt, int X, int Y, int
         const long at = owed ? nb * BX::HALO + hi : 0;
         v[d - 1] = owed ? halo[at] : T(0);
     }
+}
+
+template <class T>
+__device__ __forceinline__ T halo_add(const T (&v)[7]) {
     T acc = T(0);
 #pragma unroll
     for (int d = 0; d < 7; ++d) acc += v[d];
     return acc;
+}
+
+// Sum of the neighbouring shells owed to mesh cell (X, Y, Z) (0 for cells
+// off the low faces), summed in the fixed order above.
+template <class T, int G>
+__device__ __forceinline__ T halo_sum_g(const T* halo, int nt, int X, int Y, int Z) {
+    constexpr int LZ = PaintBox<G>::LZ;
+    if ((X % TILE) && (Y % TILE) && (Z % LZ)) return T(0);
+    T v[7];
+    halo_fetch_g<T, G>(halo, nt, X, Y, Z, v);
+    return halo_add<T>(v);
 }
 
 // Shells still to be merged into a painted mesh (halo == nullptr: none).
@@ -82,10 +93,62 @@ template <class T> struct HaloMerge {
     int G = 1;   // tiles per paint group along axis 2
 };
 
-template <class T>
-__device__ __forceinline__ T halo_sum(const HaloMerge<T>& hm, int X, int Y, int Z) {
-    return hm.G == 2 ? halo_sum_g<T, 2>(hm.halo, hm.nt, X, Y, Z)
-                     : halo_sum_g<T, 1>(hm.halo, hm.nt, X, Y, Z);
+// Add the shells owed to the rows X, Y0 .. Y0 + W - 1 (all 2H cells along
+// axis 2 each) held in LDS as buf[(Z / 2) * LD + w] (.re: even Z, .im: odd
+// Z).  Only the owed cells are visited: every cell when X is on a tile's low
+// face, else the whole row on a tile's low y-face and the low z-face cells
+// of the others.  Each thread fetches BATCH cells before summing any, so its
+// loads are in flight together.  Ends with a barrier.
+template <class T, int G, int H, int W, int NTT>
+__device__ __forceinline__ void merge_rows_g(const HaloMerge<T>& hm, cx<T>* buf, int X, int Y0,
+                                             int tid) {
+    constexpr int LD = W + 1, NZ = 2 * H, LZ = PaintBox<G>::LZ, BATCH = 4;
+    const bool all = (X % TILE) == 0;
+    int wy = -1;  // the row on a tile's low y-face, if any
+    for (int w = 0; w < W; ++w)
+        if ((Y0 + w) % TILE == 0) wy = w;
+    const int nz_face = NZ / LZ;
+    const int owed = all ? W * NZ : (wy >= 0 ? NZ + (W - 1) * nz_face : W * nz_face);
+    for (int c0 = tid; c0 < owed; c0 += NTT * BATCH) {
+        T v[BATCH][7];
+        int ws[BATCH], zs[BATCH];
+#pragma unroll
+        for (int b = 0; b < BATCH; ++b) {
+            const int c = c0 + b * NTT;
+            int w = 0, z = 0;
+            if (all) {
+                w = c / NZ;
+                z = c % NZ;
+            } else if (wy >= 0 && c < NZ) {
+                w = wy;
+                z = c;
+            } else {
+                const int e = wy >= 0 ? c - NZ : c;  // among the other rows
+                const int r = e / nz_face;
+                w = (wy >= 0 && r >= wy) ? r + 1 : r;
+                z = (e % nz_face) * LZ;
+            }
+            ws[b] = w;
+            zs[b] = z;
+            if (c < owed) halo_fetch_g<T, G>(hm.halo, hm.nt, X, Y0 + w, z, v[b]);
+        }
+#pragma unroll
+        for (int b = 0; b < BATCH; ++b) {
+            if (c0 + b * NTT >= owed) continue;
+            const T add = halo_add<T>(v[b]);
+            cx<T>& e = buf[(zs[b] >> 1) * LD + ws[b]];
+            if (zs[b] & 1) e.im += add;
+            else e.re += add;
+        }
+    }
+    __syncthreads();
+}
+
+template <class T, int H, int W, int NTT>
+__device__ __forceinline__ void merge_rows(const HaloMerge<T>& hm, cx<T>* buf, int X, int Y0,
+                                           int tid) {
+    if (hm.G == 2) merge_rows_g<T, 2, H, W, NTT>(hm, buf, X, Y0, tid);
+    else merge_rows_g<T, 1, H, W, NTT>(hm, buf, X, Y0, tid);
 }
 
 }  // namespace ml

@@ -91,10 +91,20 @@ template <class T> struct HaloMerge;
 // The shells of the last paint into `halo`, for a merge during the r2c pass.
 template <class T>
 HaloMerge<T> paint_halo_merge(Geo g, const T* halo);
+// With `on`, the readout also starts the next step: after mom += kick*f it
+// applies mom += kick'*f and disp += drift'*mom and writes the particles'
+// tile keys and ranks (count must be zero), as launch_kick_drift_key would;
+// acc is then not written.
+template <class T> struct ReadoutNext {
+    int on = 0;
+    T kick = T(0);   // K1 of the next step
+    T drift = T(0);  // Dr of the next step
+};
 // CIC readout of the three force meshes; acc = f; mom += kick*acc if do_kick.
 template <class T>
 void launch_readout(Parts<T> p, SortBufs s, Geo g, const T* f0, const T* f1, const T* f2,
-                    T kick, int do_kick, uint32_t* status, hipStream_t st);
+                    T kick, int do_kick, uint32_t* status, hipStream_t st,
+                    ReadoutNext<T> nx = ReadoutNext<T>());
 // Zel'dovich: disp = dfac*s, mom = pfac*s from the three displacement meshes
 // on the particle lattice (cells), id = lattice index.
 template <class T>

@@ -71,11 +71,47 @@ void launch_scale_copy(T* dst, const T* src, T s, long n, hipStream_t st) {
 // ---------------------------------------------------------------------------
 // kick / drift / tile key with wave-aggregated histogram atomics
 // ---------------------------------------------------------------------------
+// Tile of a particle displaced by d (cells) from its lattice point.
+template <class T>
+__device__ __forceinline__ uint32_t tile_key(uint32_t id, const T (&d)[3], const Geo& g) {
+    int i0, i1, i2;
+    lattice_of(id, g.np, i0, i1, i2);
+    int c0, c1, c2;
+    T t;
+    cell_of(g.B, i0, d[0], g.nm, c0, t);
+    cell_of(g.B, i1, d[1], g.nm, c1, t);
+    cell_of(g.B, i2, d[2], g.nm, c2, t);
+    return (uint32_t)(((c0 / TILE) * g.nt + c1 / TILE) * g.nt + c2 / TILE);
+}
+
+// Rank of each valid lane among the particles of its tile (key), from the
+// tile's counter: one atomic per distinct key per wave, lanes of equal key
+// ranked in lane order.  Every lane of the wave must call it.
+__device__ __forceinline__ uint32_t wave_rank(bool valid, uint32_t key, uint32_t* count) {
+    const int lane = threadIdx.x & 63;
+    bool pending = valid;
+    uint32_t myrank = 0;
+    while (__any(pending)) {
+        unsigned long long m = __ballot(pending);
+        int leader = __ffsll((long long)m) - 1;
+        uint32_t lkey = __shfl(key, leader);
+        bool mine = pending && key == lkey;
+        unsigned long long same = __ballot(mine);
+        uint32_t b0 = 0;
+        if (lane == leader) b0 = atomicAdd(&count[lkey], (uint32_t)__popcll(same));
+        b0 = __shfl(b0, leader);
+        if (mine) {
+            myrank = b0 + (uint32_t)__popcll(same & ((1ull << lane) - 1ull));
+            pending = false;
+        }
+    }
+    return myrank;
+}
+
 template <class T>
 __global__ __launch_bounds__(PB) void k_kick_drift_key(Parts<T> p, SortBufs s, Geo g, T kick,
                                                        T drift, int mode, uint32_t* status) {
     const long n = g.npart;
-    const int lane = threadIdx.x & 63;
     for (long base = blockIdx.x * (long)PB; base < n; base += (long)gridDim.x * PB) {
         long k = base + threadIdx.x;
         bool valid = k < n;
@@ -104,34 +140,11 @@ __global__ __launch_bounds__(PB) void k_kick_drift_key(Parts<T> p, SortBufs s, G
                 p.disp[a * n + k] = d[a];
                 if (mode & MODE_KICK) p.mom[a * n + k] = m[a];
             }
-            int i0, i1, i2;
-            lattice_of(p.id[k], g.np, i0, i1, i2);
-            int c0, c1, c2;
-            T t;
-            cell_of(g.B, i0, d[0], g.nm, c0, t);
-            cell_of(g.B, i1, d[1], g.nm, c1, t);
-            cell_of(g.B, i2, d[2], g.nm, c2, t);
-            key = (uint32_t)(((c0 / TILE) * g.nt + c1 / TILE) * g.nt + c2 / TILE);
+            key = tile_key<T>(p.id[k], d, g);
             s.key[k] = key;
         }
-        // wave-aggregated rank assignment: one atomic per distinct key per wave
-        bool pending = valid;
-        uint32_t myrank = 0;
-        while (__any(pending)) {
-            unsigned long long m = __ballot(pending);
-            int leader = __ffsll((long long)m) - 1;
-            uint32_t lkey = __shfl(key, leader);
-            bool mine = pending && key == lkey;
-            unsigned long long same = __ballot(mine);
-            uint32_t b0 = 0;
-            if (lane == leader) b0 = atomicAdd(&s.count[lkey], (uint32_t)__popcll(same));
-            b0 = __shfl(b0, leader);
-            if (mine) {
-                myrank = b0 + (uint32_t)__popcll(same & ((1ull << lane) - 1ull));
-                pending = false;
-            }
-        }
-        if (valid) s.rank[k] = myrank;
+        uint32_t r = wave_rank(valid, key, s.count);
+        if (valid) s.rank[k] = r;
     }
 }
 
@@ -274,6 +287,25 @@ __device__ __forceinline__ float value_scale(const uint32_t* vmax_bits) {
     return ldexpf(1.0f, 40 - e);
 }
 
+// Particles k0, k0 + PBP, ... (PU of them, below hi) of a paint batch.
+template <class T>
+__device__ __forceinline__ void paint_load_batch(const Parts<T>& p, long n, uint32_t k0,
+                                                 uint32_t hi, const T* vals, T mass,
+                                                 uint32_t (&idv)[PU], T (&dv)[PU][3],
+                                                 T (&mv)[PU]) {
+#pragma unroll
+    for (int u = 0; u < PU; ++u) {
+        uint32_t k = k0 + u * PBP;
+        if (k < hi) {
+            idv[u] = p.id[k];
+            dv[u][0] = p.disp[k];
+            dv[u][1] = p.disp[n + k];
+            dv[u][2] = p.disp[2 * n + k];
+            mv[u] = vals ? vals[k] : mass;
+        }
+    }
+}
+
 template <class T, int G>
 __global__ __launch_bounds__(PBP) void k_paint_group(Parts<T> p, SortBufs s, Geo g, T mass, T* rho,
                                                      T* halo, const T* vals,
@@ -289,25 +321,17 @@ __global__ __launch_bounds__(PBP) void k_paint_group(Parts<T> p, SortBufs s, Geo
     const int ox = tx * TILE, oy = ty * TILE, oz = gz * BX::LZ;
     const T scale = vals ? (T)value_scale(vmax_bits) : T(4294967296.0);
     const double inv_scale = 1.0 / (double)scale;
-    for (int i = tid; i < BX::CELLS; i += PBP) box[i] = S(0);
-    __syncthreads();
     const long n = g.npart;
     const int t0 = (tx * g.nt + ty) * g.nt + gz * G;
     const uint32_t lo = s.start[t0], hi = s.start[t0 + G];
+    uint32_t idv[PU];
+    T dv[PU][3], mv[PU];
+    // the first batch is in flight while the box is cleared
+    paint_load_batch<T>(p, n, lo + tid, hi, vals, mass, idv, dv, mv);
+    for (int i = tid; i < BX::CELLS; i += PBP) box[i] = S(0);
+    __syncthreads();
     for (uint32_t base = lo; base < hi; base += PBP * PU) {
-        uint32_t idv[PU];
-        T dv[PU][3], mv[PU];
-#pragma unroll
-        for (int u = 0; u < PU; ++u) {
-            uint32_t k = base + u * PBP + tid;
-            if (k < hi) {
-                idv[u] = p.id[k];
-                dv[u][0] = p.disp[k];
-                dv[u][1] = p.disp[n + k];
-                dv[u][2] = p.disp[2 * n + k];
-                mv[u] = vals ? vals[k] : mass;
-            }
-        }
+        if (base != lo) paint_load_batch<T>(p, n, base + tid, hi, vals, mass, idv, dv, mv);
 #pragma unroll
         for (int u = 0; u < PU; ++u) {
             uint32_t k = base + u * PBP + tid;
@@ -433,10 +457,98 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
     return (b % NX) * (nb / NX) + b / NX;
 }
 
+// CIC force at a particle (displacement d from lattice point id) from the
+// 17^3 LDS tile of the three components at origin (ox, oy, oz).
+template <class T>
+__device__ __forceinline__ void tile_force(const Geo& g, uint32_t id, const T (&d)[3],
+                                           const T (*ft)[TE * TE * TE], int ox, int oy, int oz,
+                                           T& a0, T& a1, T& a2) {
+    int i0, i1, i2;
+    lattice_of(id, g.np, i0, i1, i2);
+    int c0, c1, c2;
+    T w0, w1, w2;
+    cell_of(g.B, i0, d[0], g.nm, c0, w0);
+    cell_of(g.B, i1, d[1], g.nm, c1, w1);
+    cell_of(g.B, i2, d[2], g.nm, c2, w2);
+    int l0 = min(max(c0 - ox, 0), TILE - 1);
+    int l1 = min(max(c1 - oy, 0), TILE - 1);
+    int l2 = min(max(c2 - oz, 0), TILE - 1);
+    T wa[2] = {T(1) - w0, w0}, wb[2] = {T(1) - w1, w1}, wc[2] = {T(1) - w2, w2};
+    a0 = a1 = a2 = T(0);
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+            int cb = ((l0 + a) * TE + (l1 + b)) * TE + l2;
+            T wab = wa[a] * wb[b];
+            T v0 = wab * wc[0], v1 = wab * wc[1];
+            a0 += v0 * ft[0][cb] + v1 * ft[0][cb + 1];
+            a1 += v0 * ft[1][cb] + v1 * ft[1][cb + 1];
+            a2 += v0 * ft[2][cb] + v1 * ft[2][cb + 1];
+        }
+}
+
+// Readout fused with the start of the next step: p += K2 f, then the next
+// step's p += K1' f and disp += Dr' p, and the particle's new tile key and
+// rank (the work of k_kick_drift_key, with f still in registers).  The same
+// operations in the same order as the separate kernels.
+template <class T>
+__device__ __forceinline__ void readout_kick_drift_key(
+    Parts<T>& p, const SortBufs& s, const Geo& g, long n, uint32_t k, bool valid, uint32_t id,
+    const T (&dv)[3], const T (&mv)[3], const T (*ft)[TE * TE * TE], int ox, int oy, int oz,
+    T kick, const ReadoutNext<T>& nx, uint32_t* status) {
+    uint32_t key = 0;
+    if (valid) {
+        if (!finite3(dv[0], dv[1], dv[2])) atomicOr(status, 1u);
+        T f[3];
+        tile_force<T>(g, id, dv, ft, ox, oy, oz, f[0], f[1], f[2]);
+        T m[3], d[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            m[a] = mv[a] + kick * f[a];   // end of this step
+            m[a] += nx.kick * f[a];       // first half-kick of the next
+            d[a] = dv[a];
+            d[a] += nx.drift * m[a];      // and its drift
+        }
+        if (!finite3(d[0], d[1], d[2])) {
+            atomicOr(status, 1u);
+            d[0] = d[1] = d[2] = T(0);
+        }
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            p.disp[a * n + k] = d[a];
+            p.mom[a * n + k] = m[a];
+        }
+        key = tile_key<T>(id, d, g);
+        s.key[k] = key;
+    }
+    uint32_t r = wave_rank(valid, key, s.count);
+    if (valid) s.rank[k] = r;
+}
+
+// Particles k0, k0 + PBR, ... (PU of them, below hi) of a readout batch.
+template <class T>
+__device__ __forceinline__ void readout_load_batch(const Parts<T>& p, long n, uint32_t k0,
+                                                   uint32_t hi, int do_kick, uint32_t (&idv)[PU],
+                                                   T (&dv)[PU][3], T (&mv)[PU][3]) {
+#pragma unroll
+    for (int u = 0; u < PU; ++u) {
+        uint32_t k = k0 + u * PBR;
+        if (k < hi) {
+            idv[u] = p.id[k];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                dv[u][a] = p.disp[a * n + k];
+                if (do_kick) mv[u][a] = p.mom[a * n + k];
+            }
+        }
+    }
+}
+
 template <class T>
 __global__ __launch_bounds__(PBR) void k_readout(Parts<T> p, SortBufs s, Geo g, const T* f0,
                                                 const T* f1, const T* f2, T kick, int do_kick,
-                                                uint32_t* status) {
+                                                uint32_t* status, ReadoutNext<T> nx) {
     constexpr int TC = TE * TE * TE;
     __shared__ T ft[3][TC];
     const int tid = threadIdx.x;
@@ -446,6 +558,12 @@ __global__ __launch_bounds__(PBR) void k_readout(Parts<T> p, SortBufs s, Geo g, 
     const uint32_t lo = s.start[t], hi = s.start[t + 1];
     if (lo == hi) return;  // uniform across the workgroup
     const int nm = g.nm;
+    const long n = g.npart;
+    uint32_t idv[PU];
+    T dv[PU][3], mv[PU][3];
+    // the first batch of particles is loaded together with the force tile,
+    // so the two waits overlap
+    readout_load_batch<T>(p, n, lo + tid, hi, do_kick, idv, dv, mv);
     {
         constexpr int IT = (TC + PBR - 1) / PBR;
         T v0[IT], v1[IT], v2[IT];
@@ -475,50 +593,21 @@ __global__ __launch_bounds__(PBR) void k_readout(Parts<T> p, SortBufs s, Geo g, 
         }
     }
     __syncthreads();
-    const long n = g.npart;
     for (uint32_t base = lo; base < hi; base += PBR * PU) {
-        uint32_t idv[PU];
-        T dv[PU][3], mv[PU][3];
+        if (base != lo) readout_load_batch<T>(p, n, base + tid, hi, do_kick, idv, dv, mv);
 #pragma unroll
         for (int u = 0; u < PU; ++u) {
             uint32_t k = base + u * PBR + tid;
-            if (k < hi) {
-                idv[u] = p.id[k];
-#pragma unroll
-                for (int a = 0; a < 3; ++a) {
-                    dv[u][a] = p.disp[a * n + k];
-                    if (do_kick) mv[u][a] = p.mom[a * n + k];
-                }
+            const bool valid = k < hi;
+            if (nx.on) {  // wave-uniform: every lane takes part in the ranking
+                readout_kick_drift_key<T>(p, s, g, n, k, valid, idv[u], dv[u], mv[u], ft, ox, oy,
+                                          oz, kick, nx, status);
+                continue;
             }
-        }
-#pragma unroll
-        for (int u = 0; u < PU; ++u) {
-            uint32_t k = base + u * PBR + tid;
-            if (k >= hi) continue;
-            int i0, i1, i2;
-            lattice_of(idv[u], g.np, i0, i1, i2);
+            if (!valid) continue;
             if (!finite3(dv[u][0], dv[u][1], dv[u][2])) atomicOr(status, 1u);
-            int c0, c1, c2;
-            T w0, w1, w2;
-            cell_of(g.B, i0, dv[u][0], nm, c0, w0);
-            cell_of(g.B, i1, dv[u][1], nm, c1, w1);
-            cell_of(g.B, i2, dv[u][2], nm, c2, w2);
-            int l0 = min(max(c0 - ox, 0), TILE - 1);
-            int l1 = min(max(c1 - oy, 0), TILE - 1);
-            int l2 = min(max(c2 - oz, 0), TILE - 1);
-            T wa[2] = {T(1) - w0, w0}, wb[2] = {T(1) - w1, w1}, wc[2] = {T(1) - w2, w2};
-            T a0 = 0, a1 = 0, a2 = 0;
-#pragma unroll
-            for (int a = 0; a < 2; ++a)
-#pragma unroll
-                for (int b = 0; b < 2; ++b) {
-                    int cb = ((l0 + a) * TE + (l1 + b)) * TE + l2;
-                    T wab = wa[a] * wb[b];
-                    T v0 = wab * wc[0], v1 = wab * wc[1];
-                    a0 += v0 * ft[0][cb] + v1 * ft[0][cb + 1];
-                    a1 += v0 * ft[1][cb] + v1 * ft[1][cb + 1];
-                    a2 += v0 * ft[2][cb] + v1 * ft[2][cb + 1];
-                }
+            T a0, a1, a2;
+            tile_force<T>(g, idv[u], dv[u], ft, ox, oy, oz, a0, a1, a2);
             p.acc[k] = a0;
             p.acc[n + k] = a1;
             p.acc[2 * n + k] = a2;
@@ -533,10 +622,10 @@ __global__ __launch_bounds__(PBR) void k_readout(Parts<T> p, SortBufs s, Geo g, 
 
 template <class T>
 void launch_readout(Parts<T> p, SortBufs s, Geo g, const T* f0, const T* f1, const T* f2,
-                    T kick, int do_kick, uint32_t* status, hipStream_t st) {
+                    T kick, int do_kick, uint32_t* status, hipStream_t st, ReadoutNext<T> nx) {
     int ntiles = g.nt * g.nt * g.nt;
     hipLaunchKernelGGL(k_readout<T>, dim3(ntiles), dim3(PBR), 0, st, p, s, g, f0, f1, f2, kick,
-                       do_kick, status);
+                       do_kick, status, nx);
 }
 
 // ---------------------------------------------------------------------------
@@ -694,7 +783,7 @@ void launch_noise(T* out, long n, uint64_t seed, hipStream_t st) {
                                          const uint32_t*, hipStream_t, bool);                     \
     template HaloMerge<T> paint_halo_merge<T>(Geo, const T*);                                     \
     template void launch_readout<T>(Parts<T>, SortBufs, Geo, const T*, const T*, const T*, T, int, \
-                                    uint32_t*, hipStream_t);                                      \
+                                    uint32_t*, hipStream_t, ReadoutNext<T>);                      \
     template void launch_init_ic<T>(Parts<T>, Geo, const T*, const T*, const T*, T, T,            \
                                     hipStream_t);                                                 \
     template void launch_get_state<T>(Parts<T>, Geo, T, T*, T*, T*, hipStream_t);                 \

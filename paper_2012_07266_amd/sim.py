@@ -8,6 +8,7 @@ from __future__ import annotations
 import ctypes
 from typing import Optional, Sequence
 
+import numpy as np
 import torch
 
 from . import _lib
@@ -129,8 +130,25 @@ class Simulation:
         return torch.zeros((len(self.z_src), self.npix, self.npix), dtype=self.dtype,
                            device=self.device)
 
+    def steps(self, a_grid, kappa):
+        """Steps along a_grid (from the current state at a_grid[0]) with the
+        projection of every shell into kappa: pm_run, the fused form of
+        step + lens per interval."""
+        a = np.ascontiguousarray(a_grid, dtype=np.float64)
+        check(lib().pm_run(self._h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                           len(a) - 1, _ptr(kappa)), "pm_run")
+        self.a = float(a[-1])
+        return kappa
+
     def run(self, noise, a_grid, kappa=None):
-        """ICs at a_grid[0], then for every interval a step and its shell."""
+        """ICs at a_grid[0], then every step and its shell (pm_run)."""
+        if kappa is None:
+            kappa = self.new_maps()
+        self.init_ic(noise, a_grid[0])
+        return self.steps(a_grid, kappa)
+
+    def run_stepwise(self, noise, a_grid, kappa=None):
+        """The same with one pm_step and one lens_project per interval."""
         if kappa is None:
             kappa = self.new_maps()
         self.init_ic(noise, a_grid[0])

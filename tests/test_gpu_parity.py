@@ -172,6 +172,33 @@ def test_lens_shell_of_static_field(dtype, geometry):
     assert e_part <= _tol(dtype, 1e-12, 1e-5)
 
 
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: f"{s[0]}p{s[1]}m")
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+def test_fused_run_equals_step_and_lens(dtype, shape):
+    """pm_run (each readout also starts the next step; shells projected after
+    the paint) gives the maps and state of pm_step + lens_project per
+    interval: bit for bit in float32, whose paint and projection accumulate
+    in fixed point; to round-off in float64, whose LDS accumulators are
+    float64 atomics and so depend on the order of arrival."""
+    np_side, nm, box = shape
+    wl = W.Workload("fused", np_side, nm, box, 0.2, 1.0, 5, 64, 4.0, (1.0, 1.5), seed=9)
+    log(f"fused run vs stepwise {dtype} np={np_side} nm={nm}")
+    noise = torch.from_numpy(W.white_noise(np_side, wl.seed))
+    a = wl.a_grid()
+    with new_sim(wl, dtype) as sim:
+        k1 = sim.run_stepwise(noise, a).clone()
+        x1, p1 = (t.clone() for t in sim.get_state())
+        k2 = sim.run(noise, a)
+        x2, p2 = sim.get_state()
+        sim.sync()
+        assert torch.abs(k1).max() > 0
+        if dtype == torch.float32:
+            assert torch.equal(k1, k2) and torch.equal(x1, x2) and torch.equal(p1, p2)
+        else:
+            assert rel_rms(to_np(k2), to_np(k1)) < 1e-12 and rel_rms(to_np(p2), to_np(p1)) < 1e-12
+            assert periodic_cells(to_np(x2) - to_np(x1), box, nm).max() < 1e-10
+
+
 def test_error_paths():
     from paper_2012_07266_amd import MadlensError
     from paper_2012_07266_amd._lib import PM_ESTATE, PM_ENONFINITE
