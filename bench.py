@@ -50,8 +50,8 @@ def algorithmic_bytes(wl, esize=4):
     S = M + nm * nm * 2 * esize
     maps = len(wl.z_src) * wl.npix ** 2 * esize
     return {
-        "kick_drift_key": 72 * P,          # R disp,mom,acc,id  W disp,mom,key,rank
-        "scatter": 64 * P,                 # R key,rank,disp,mom,id  W disp,mom,id
+        "kick_drift_key": 68 * P,          # R disp,mom,acc,id  W disp,mom,key
+        "scatter": 60 * P,                 # R key,disp,mom,id  W disp,mom,id
         "paint": 16 * P + M,               # R disp,id  W rho
         "fft_r2c_axis2": M + S,
         "fft_c2c_axis1_fwd": 2 * S,
@@ -61,7 +61,7 @@ def algorithmic_bytes(wl, esize=4):
         "fft_c2r_axis2": S + M,
         "readout_kick": 3 * M + 52 * P,    # R 3 meshes, disp,id,mom  W mom,acc
         # fused with the next step's kick, drift and keys:
-        "readout_kick_drift_key": 3 * M + 60 * P,  # R 3 meshes, disp,id,mom  W disp,mom,key,rank
+        "readout_kick_drift_key": 3 * M + 56 * P,  # R 3 meshes, disp,id,mom  W disp,mom,key
         "lens_gather": 16 * P + 2 * maps,  # R disp,id  RW maps (incl. mean term)
         "scan": 0,
     }

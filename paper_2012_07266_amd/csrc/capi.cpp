@@ -42,7 +42,7 @@ struct Layout {
 
 // Offsets of every device array inside the arena.
 struct ArenaPlan {
-    size_t disp[2], mom[2], id[2], acc, key, rank, count, start, scan_sum, status;
+    size_t disp[2], mom[2], id[2], acc, key, count, start, scan_sum, status;
     size_t mesh[3], nyq[3], halo, tw_nm, tw_hm, twp_nm, tw_np, tw_hp, twp_np, g_ic, atab;
     size_t xbc, fbc, dots, fmax, noise, g_ic_dom, adom;
     size_t total;
@@ -65,7 +65,6 @@ ArenaPlan plan_arena(const pm_params& p, const lens_params& l, size_t es) {
     }
     a.acc = L.take(3 * n * es);
     a.key = L.take(n * 4);
-    a.rank = L.take(n * 4);
     a.count = L.take(nt * nt * nt * 4);
     a.start = L.take((nt * nt * nt + 1) * 4);
     a.scan_sum = L.take((nt * nt * nt + 1023) / 1024 * 4);
@@ -298,7 +297,6 @@ template <class T> struct Sim final : SimBase {
             q.acc = at<T>(ap.acc);
         }
         sb.key = at<uint32_t>(ap.key);
-        sb.rank = at<uint32_t>(ap.rank);
         sb.count = at<uint32_t>(ap.count);
         sb.start = at<uint32_t>(ap.start);
         scan_sum = at<uint32_t>(ap.scan_sum);
@@ -580,7 +578,7 @@ template <class T> struct Sim final : SimBase {
             const double a0 = agrid[i], a1 = agrid[i + 1], ah = 0.5 * (a0 + a1);
             if (i == 0) {
                 sort((T)cosmo.kick(a0, ah, a0), (T)cosmo.drift(a0, a1, ah), MODE_KICK | MODE_DRIFT);
-            } else {  // keys and ranks come from the previous readout
+            } else {  // keys and histogram come from the previous readout
                 { ProfScope ps(prof, "scan"); launch_scan(sb.count, sb.start, scan_sum, ntiles, st); }
                 { ProfScope ps(prof, "scatter"); launch_scatter<T>(cur, alt, sb, geo, st); }
                 std::swap(cur.disp, alt.disp);

@@ -29,8 +29,7 @@ template <class T> struct Parts {
 
 struct SortBufs {
     uint32_t* key;    // tile of each particle
-    uint32_t* rank;   // rank within its tile
-    uint32_t* count;  // [ntiles] histogram
+    uint32_t* count;  // [ntiles] histogram (zero between sorts)
     uint32_t* start;  // [ntiles+1] exclusive prefix
 };
 
@@ -60,7 +59,7 @@ void launch_scale_copy(T* dst, const T* src, T s, long n, hipStream_t st);
 void launch_fill_u32(uint32_t* p, uint32_t v, long n, hipStream_t st);
 
 // mom += kick*acc (MODE_KICK), disp += drift*mom (MODE_DRIFT); then tile
-// key, histogram and rank of every particle.  `count` must be zero.
+// key and histogram of every particle.  `count` must be zero.
 template <class T>
 void launch_kick_drift_key(Parts<T> p, SortBufs s, Geo g, T kick, T drift, int mode,
                            uint32_t* status, hipStream_t st);
@@ -68,7 +67,9 @@ void launch_kick_drift_key(Parts<T> p, SortBufs s, Geo g, T kick, T drift, int m
 // block_sum: scratch of (n + 1023) / 1024 entries (n <= 1024 * 1024).
 void launch_scan(const uint32_t* count, uint32_t* start, uint32_t* block_sum, int n,
                  hipStream_t st);
-// Permute disp, mom and id into tile order (dst).
+// Permute disp, mom and id into tile order (dst), after launch_scan: each
+// particle takes a rank in its tile by counting the histogram down, which
+// leaves `count` at zero.
 template <class T>
 void launch_scatter(Parts<T> src, Parts<T> dst, SortBufs s, Geo g, hipStream_t st);
 // CIC paint of tile-sorted particles by groups of tiles along axis 2:
@@ -93,7 +94,7 @@ template <class T>
 HaloMerge<T> paint_halo_merge(Geo g, const T* halo);
 // With `on`, the readout also starts the next step: after mom += kick*f it
 // applies mom += kick'*f and disp += drift'*mom and writes the particles'
-// tile keys and ranks (count must be zero), as launch_kick_drift_key would;
+// tile keys and histogram (count must be zero), as launch_kick_drift_key would;
 // acc is then not written.
 template <class T> struct ReadoutNext {
     int on = 0;

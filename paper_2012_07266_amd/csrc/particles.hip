@@ -84,10 +84,29 @@ __device__ __forceinline__ uint32_t tile_key(uint32_t id, const T (&d)[3], const
     return (uint32_t)(((c0 / TILE) * g.nt + c1 / TILE) * g.nt + c2 / TILE);
 }
 
-// Rank of each valid lane among the particles of its tile (key), from the
-// tile's counter: one atomic per distinct key per wave, lanes of equal key
-// ranked in lane order.  Every lane of the wave must call it.
-__device__ __forceinline__ uint32_t wave_rank(bool valid, uint32_t key, uint32_t* count) {
+// Histogram of the tile keys of the valid lanes: one atomic per distinct key
+// per wave, whose result is not needed (no round trip).  Every lane of the
+// wave must call it.
+__device__ __forceinline__ void wave_count(bool valid, uint32_t key, uint32_t* count) {
+    const int lane = threadIdx.x & 63;
+    bool pending = valid;
+    while (__any(pending)) {
+        unsigned long long m = __ballot(pending);
+        int leader = __ffsll((long long)m) - 1;
+        uint32_t lkey = __shfl(key, leader);
+        bool mine = pending && key == lkey;
+        unsigned long long same = __ballot(mine);
+        if (lane == leader) atomicAdd(&count[lkey], (uint32_t)__popcll(same));
+        if (mine) pending = false;
+    }
+}
+
+// Rank of each valid lane among the particles of its tile, taken by counting
+// the tile's histogram entry down (one atomic per distinct key per wave):
+// the ranks of a tile's particles are distinct and fill [0, count), and the
+// histogram ends at zero, ready for the next step.  Every lane of the wave
+// must call it.
+__device__ __forceinline__ uint32_t wave_take(bool valid, uint32_t key, uint32_t* count) {
     const int lane = threadIdx.x & 63;
     bool pending = valid;
     uint32_t myrank = 0;
@@ -97,11 +116,11 @@ __device__ __forceinline__ uint32_t wave_rank(bool valid, uint32_t key, uint32_t
         uint32_t lkey = __shfl(key, leader);
         bool mine = pending && key == lkey;
         unsigned long long same = __ballot(mine);
-        uint32_t b0 = 0;
-        if (lane == leader) b0 = atomicAdd(&count[lkey], (uint32_t)__popcll(same));
-        b0 = __shfl(b0, leader);
+        uint32_t top = 0;
+        if (lane == leader) top = atomicSub(&count[lkey], (uint32_t)__popcll(same));
+        top = __shfl(top, leader);
         if (mine) {
-            myrank = b0 + (uint32_t)__popcll(same & ((1ull << lane) - 1ull));
+            myrank = top - 1u - (uint32_t)__popcll(same & ((1ull << lane) - 1ull));
             pending = false;
         }
     }
@@ -143,8 +162,7 @@ __global__ __launch_bounds__(PB) void k_kick_drift_key(Parts<T> p, SortBufs s, G
             key = tile_key<T>(p.id[k], d, g);
             s.key[k] = key;
         }
-        uint32_t r = wave_rank(valid, key, s.count);
-        if (valid) s.rank[k] = r;
+        wave_count(valid, key, s.count);
     }
 }
 
@@ -226,8 +244,13 @@ void launch_scan(const uint32_t* count, uint32_t* start, uint32_t* block_sum, in
 template <class T>
 __global__ __launch_bounds__(PB) void k_scatter(Parts<T> src, Parts<T> dst, SortBufs s, Geo g) {
     const long n = g.npart;
-    for (long k = blockIdx.x * (long)PB + threadIdx.x; k < n; k += (long)gridDim.x * PB) {
-        uint32_t d = s.start[s.key[k]] + s.rank[k];
+    for (long base = blockIdx.x * (long)PB; base < n; base += (long)gridDim.x * PB) {
+        const long k = base + threadIdx.x;
+        const bool valid = k < n;
+        const uint32_t key = valid ? s.key[k] : 0u;
+        const uint32_t r = wave_take(valid, key, s.count);
+        if (!valid) continue;
+        const uint32_t d = s.start[key] + r;
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             dst.disp[a * n + d] = src.disp[a * n + k];
@@ -490,7 +513,8 @@ __device__ __forceinline__ void tile_force(const Geo& g, uint32_t id, const T (&
 
 // Readout fused with the start of the next step: p += K2 f, then the next
 // step's p += K1' f and disp += Dr' p, and the particle's new tile key and
-// rank (the work of k_kick_drift_key, with f still in registers).  The same
+// its histogram count (the work of k_kick_drift_key, with f still in
+// registers).  The same
 // operations in the same order as the separate kernels.
 template <class T>
 __device__ __forceinline__ void readout_kick_drift_key(
@@ -522,8 +546,7 @@ __device__ __forceinline__ void readout_kick_drift_key(
         key = tile_key<T>(id, d, g);
         s.key[k] = key;
     }
-    uint32_t r = wave_rank(valid, key, s.count);
-    if (valid) s.rank[k] = r;
+    wave_count(valid, key, s.count);
 }
 
 // Particles k0, k0 + PBR, ... (PU of them, below hi) of a readout batch.
@@ -599,7 +622,7 @@ __global__ __launch_bounds__(PBR) void k_readout(Parts<T> p, SortBufs s, Geo g, 
         for (int u = 0; u < PU; ++u) {
             uint32_t k = base + u * PBR + tid;
             const bool valid = k < hi;
-            if (nx.on) {  // wave-uniform: every lane takes part in the ranking
+            if (nx.on) {  // wave-uniform: every lane takes part in the histogram
                 readout_kick_drift_key<T>(p, s, g, n, k, valid, idv[u], dv[u], mv[u], ft, ox, oy,
                                           oz, kick, nx, status);
                 continue;

@@ -219,3 +219,66 @@ def test_error_paths():
         with pytest.raises(MadlensError) as e:
             sim.sync()
         assert e.value.code == PM_ENONFINITE
+
+
+def _off_shell_bounds(x, box, cell, bounds, gap):
+    """x with axis-2 coordinates moved, where needed, to at least `gap` from
+    every distance in `bounds` modulo the box (the depth of an image is
+    x_2 plus a multiple of the box)."""
+    x = x.copy()
+    for b in bounds:
+        zb = np.mod(b, box)
+        d = np.mod(x[2] - zb + 0.5 * box, box) - 0.5 * box
+        near = np.abs(d) < gap
+        x[2, near] = np.mod(zb + np.where(d[near] < 0, -gap, gap), box)
+    return x
+
+
+@pytest.mark.timeout(900)
+def test_full_size_step_and_shell():
+    """The benchmark's size and launch path: 256^3 particles, 512^3 mesh,
+    box 205 Mpc/h, four 2048^2 maps over 5 deg, float32.  Zel'dovich initial
+    conditions at a = 0.01 and one pm_run step (a -> 0.03475) against the
+    float64 oracle at every particle; then the particles of that state,
+    placed at a = 0.51 and kept 0.01 cells off the shell boundaries,
+    projected over the thin shell (0.5, 0.51] (just in front of z_s = 1;
+    transverse replicas for the farther sources) against the oracle's full
+    maps."""
+    from oracle import lens, pm
+    wl = W.CFG2
+    c = cosmo_of(wl)
+    a = wl.a_grid()
+    noise = W.white_noise(wl.np_side, wl.seed)
+    log("full size: GPU IC + one step + shell")
+    with new_sim(wl, torch.float32) as sim:
+        k = sim.new_maps()
+        sim.init_ic(torch.from_numpy(noise), a[0])
+        sim.steps(a[:2], k)
+        xg, pg = (to_np(t) for t in sim.get_state())
+        # shell membership is decided in the kernels' precision: keep every
+        # image 0.01 cells off both shell boundaries, so that float32 and the
+        # float64 oracle place each one on the same side
+        xl = _off_shell_bounds(xg, wl.box, wl.box / wl.nm_side,
+                               (c.chi(0.51), c.chi(0.5)), 0.01 * wl.box / wl.nm_side)
+        xl = xl.astype(np.float32).astype(np.float64)
+        xs = torch.from_numpy(xl)
+        sim.set_state(xs, torch.zeros_like(xs), 0.51)
+        kl = sim.new_maps()
+        sim.lens(0.5, 0.51, kl)
+        klg = to_np(kl)
+        sim.sync()
+    log("full size: oracle IC + step")
+    x0, p0 = pm.zeldovich_ic(noise, c, wl.box, wl.nm_side, a[0])
+    f0 = pm.particle_force(x0, wl.np_side, wl.nm_side, wl.box)
+    x1, p1, _ = pm.kdk_step(x0, p0, f0, a[0], a[1], c, wl.np_side, wl.nm_side, wl.box)
+    err = periodic_cells(xg - x1, wl.box, wl.nm_side)
+    e_p = rel_rms(pg, p1)
+    log(f"full size step: pos max {err.max():.2e} rms {np.sqrt((err ** 2).mean()):.2e} cells, "
+        f"mom rel-rms {e_p:.2e}")
+    assert np.sqrt((err ** 2).mean()) < 1e-4 and err.max() < 1e-3 and e_p < 1e-4
+    log("full size: oracle shell")
+    geom = lens.MapGeometry(wl.npix, wl.fov_deg, wl.z_src, c)
+    ko = lens.project_shell(xl, 0.5, 0.51, c, wl.box, wl.np_side, geom)
+    e_k = rel_rms(klg, ko)
+    log(f"full size shell: kappa rel-rms {e_k:.2e}")
+    assert np.abs(ko).max() > 0 and e_k < 1e-4
