@@ -96,7 +96,8 @@ __global__ __launch_bounds__(AB) void k_fvjp_readout(Parts<T> p, SortBufs s, Geo
     const int t = xcd_remap(blockIdx.x, gridDim.x);
     const int tx = t / (g.nt * g.nt), ty = (t / g.nt) % g.nt, tz = t % g.nt;
     const int ox = tx * TILE, oy = ty * TILE, oz = tz * TILE;
-    const uint32_t lo = s.start[t], hi = s.start[t + 1];
+    const int b0 = tile_block(g, tx, ty, tz);
+    const uint32_t lo = s.start[b0], hi = s.start[b0 + TILE / KZ];
     if (lo == hi) return;
     stage_tile(ft[0], f0, g.nm, ox, oy, oz, tid);
     stage_tile(ft[1], f1, g.nm, ox, oy, oz, tid);
@@ -158,7 +159,8 @@ __global__ __launch_bounds__(AB) void k_fvjp_paintgrad(Parts<T> p, SortBufs s, G
     const int t = xcd_remap(blockIdx.x, gridDim.x);
     const int tx = t / (g.nt * g.nt), ty = (t / g.nt) % g.nt, tz = t % g.nt;
     const int ox = tx * TILE, oy = ty * TILE, oz = tz * TILE;
-    const uint32_t lo = s.start[t], hi = s.start[t + 1];
+    const int b0 = tile_block(g, tx, ty, tz);
+    const uint32_t lo = s.start[b0], hi = s.start[b0 + TILE / KZ];
     if (lo == hi) return;
     stage_tile(ft, rhobar, g.nm, ox, oy, oz, tid);
     __syncthreads();

@@ -65,9 +65,10 @@ ArenaPlan plan_arena(const pm_params& p, const lens_params& l, size_t es) {
     }
     a.acc = L.take(3 * n * es);
     a.key = L.take(n * 4);
-    a.count = L.take(nt * nt * nt * 4);
-    a.start = L.take((nt * nt * nt + 1) * 4);
-    a.scan_sum = L.take((nt * nt * nt + 1023) / 1024 * 4);
+    const size_t nkeys = nt * nt * (nm / KZ);  // sort blocks
+    a.count = L.take(nkeys * 4);
+    a.start = L.take((nkeys + 1) * 4);
+    a.scan_sum = L.take((nkeys + 1023) / 1024 * 4);
     a.status = L.take(256);
     for (int j = 0; j < 3; ++j) {
         a.mesh[j] = L.take(nm * nm * nm * es);
@@ -281,8 +282,9 @@ template <class T> struct Sim final : SimBase {
         geo.nm = p->nm;
         geo.B = p->nm / p->np;
         geo.nt = p->nm / TILE;
+        geo.nkz = p->nm / KZ;
         geo.npart = (long)p->np * p->np * p->np;
-        ntiles = geo.nt * geo.nt * geo.nt;
+        ntiles = geo.nt * geo.nt * geo.nkz;  // sort blocks (keys)
         ap = plan_arena(*p, *l, sizeof(T));
         if (hipMalloc(&arena, ap.total) != hipSuccess) {
             arena = nullptr;
@@ -525,13 +527,13 @@ template <class T> struct Sim final : SimBase {
     int lens(double a0, double a1, void* kappa) override {
         if (!kappa) return PM_EINVAL;
         if (a_cur < 0 || std::fabs(a1 - a_cur) > 1e-12 * std::fabs(a_cur) + 1e-15) return PM_ESTATE;
-        project_shell(a0, a1, reinterpret_cast<T*>(kappa));
-        return check_launch();
+        int rc = project_shell(a0, a1, reinterpret_cast<T*>(kappa));
+        return rc ? rc : check_launch();
     }
 
     // Born projection of the shell (chi(a1), chi(a0)] of the current,
     // tile-sorted positions (which must be those at a1) into kappa.
-    void project_shell(double a0, double a1, T* kappa) {
+    int project_shell(double a0, double a1, T* kappa) {
         LensArgs<T> la{};
         la.npix = npix;
         la.nsrc = nsrc;
@@ -541,7 +543,7 @@ template <class T> struct Sim final : SimBase {
         // images and its mean term both need chi < chi_s)
         double chis_max = 0;
         for (double c : chisrc) chis_max = std::max(chis_max, c);
-        if (chi_near >= chis_max) return;
+        if (chi_near >= chis_max) return PM_OK;
         la.chi_near = (T)chi_near;
         la.chi_far = (T)chi_far;
         double dth = fov * PI / 180.0 / npix;
@@ -559,6 +561,7 @@ template <class T> struct Sim final : SimBase {
         MapAdd<T> mv{};
         for (int s = 0; s < nsrc; ++s) mv.v[s] = (T)cosmo.shell_mean(chi_near, chi_far, chisrc[s]);
         { ProfScope ps(prof, "lens_gather"); launch_lens_gather<T>(cur, sb, geo, la, mv, kappa, st); }
+        return PM_OK;
     }
 
     // nsteps KDK steps along agrid with the projection of every shell: the
@@ -586,7 +589,8 @@ template <class T> struct Sim final : SimBase {
                 std::swap(cur.id, alt.id);
             }
             paint(true);
-            project_shell(a0, a1, kap);
+            int rc = project_shell(a0, a1, kap);
+            if (rc) return rc;
             fft_forward_grad(P.nm, nullptr, tw_nm, tw_hm, twp_nm, paint_halo_merge<T>(geo, halo));
             const T k2 = (T)cosmo.kick(ah, a1, a1);
             ReadoutNext<T> nx;

@@ -154,8 +154,10 @@ __global__ __launch_bounds__(LG) void k_lens_gather(Parts<T> p, SortBufs sb, Geo
         T ca = zlo + T(nz) * nmf, cb = zhi + T(nz) * nmf;  // depth range, cells
         T x0lo = min(a0lo * ca, a0lo * cb) - margin, x0hi = max(a0hi * ca, a0hi * cb) + margin;
         T x1lo = min(a1lo * ca, a1lo * cb) - margin, x1hi = max(a1hi * ca, a1hi * cb) + margin;
-        int tz0 = max((int)floor((zlo - margin) / T(TILE)), 0);
-        int tz1 = min((int)floor((zhi + margin) / T(TILE)), nt - 1);
+        // sort blocks (KZ cells deep) along axis 2 that the replica's depth
+        // range can reach
+        int tz0 = max((int)floor((zlo - margin) / T(KZ)), 0);
+        int tz1 = min((int)floor((zhi + margin) / T(KZ)), g.nkz - 1);
         int nx0 = (int)floor((x0lo + half) / nmf), nx1 = (int)floor((x0hi + half) / nmf);
         int ny0 = (int)floor((x1lo + half) / nmf), ny1 = (int)floor((x1hi + half) / nmf);
         for (int nx = nx0; nx <= nx1; ++nx) {
@@ -174,10 +176,10 @@ __global__ __launch_bounds__(LG) void k_lens_gather(Parts<T> p, SortBufs sb, Geo
                             !column_depths(a1lo, a1hi, T(ty * TILE) + T(ny) * nmf - half, margin,
                                            zmin, zmax))
                             continue;
-                        const int tza = max(tz0, (int)floor((zmin - T(nz) * nmf) / T(TILE)));
-                        const int tzb = min(tz1, (int)floor((zmax - T(nz) * nmf) / T(TILE)));
+                        const int tza = max(tz0, (int)floor((zmin - T(nz) * nmf) / T(KZ)));
+                        const int tzb = min(tz1, (int)floor((zmax - T(nz) * nmf) / T(KZ)));
                         if (tza > tzb) continue;
-                        const int col = (tx * nt + ty) * nt;
+                        const int col = (tx * nt + ty) * g.nkz;
                         const uint32_t lo = sb.start[col + tza], hi = sb.start[col + tzb + 1];
                         for (uint32_t base = lo; base < hi; base += LG * LU) {
                             uint32_t idv[LU];

@@ -11,13 +11,25 @@ constexpr int HALO = TE * TE + TILE * TE + TILE * TILE;  // 817 upper-shell cell
 // Particle-lattice and mesh geometry.  Positions are stored as displacements
 // from the lattice point in mesh-cell units; the lattice point of particle
 // (i0, i1, i2) is u = B*i + 1/2 cells.
+// Particles are sorted by blocks of TILE x TILE x KZ cells (the key), z
+// fastest: the two blocks of a 16^3 tile, and the tiles of a column along
+// axis 2, are consecutive, so any run of them is one index range.
+constexpr int KZ = 8;
+
 struct Geo {
     int np;      // particles per side
     int nm;      // mesh cells per side
     int B;       // nm / np
     int nt;      // tiles per side = nm / TILE
     long npart;  // np^3
+    int nkz;     // sort blocks along axis 2 = nm / KZ
 };
+
+// Index of the first sort block of tile (tx, ty, tz); the tile's particles
+// are start[b] .. start[b + TILE / KZ].
+__host__ __device__ __forceinline__ int tile_block(const Geo& g, int tx, int ty, int tz) {
+    return (tx * g.nt + ty) * g.nkz + tz * (TILE / KZ);
+}
 
 // Particle state in tile-sorted order (SoA, [3][npart] each).
 template <class T> struct Parts {

@@ -81,7 +81,7 @@ __device__ __forceinline__ uint32_t tile_key(uint32_t id, const T (&d)[3], const
     cell_of(g.B, i0, d[0], g.nm, c0, t);
     cell_of(g.B, i1, d[1], g.nm, c1, t);
     cell_of(g.B, i2, d[2], g.nm, c2, t);
-    return (uint32_t)(((c0 / TILE) * g.nt + c1 / TILE) * g.nt + c2 / TILE);
+    return (uint32_t)(((c0 / TILE) * g.nt + c1 / TILE) * g.nkz + c2 / KZ);
 }
 
 // Histogram of the tile keys of the valid lanes: one atomic per distinct key
@@ -345,8 +345,8 @@ __global__ __launch_bounds__(PBP) void k_paint_group(Parts<T> p, SortBufs s, Geo
     const T scale = vals ? (T)value_scale(vmax_bits) : T(4294967296.0);
     const double inv_scale = 1.0 / (double)scale;
     const long n = g.npart;
-    const int t0 = (tx * g.nt + ty) * g.nt + gz * G;
-    const uint32_t lo = s.start[t0], hi = s.start[t0 + G];
+    const int b0 = tile_block(g, tx, ty, gz * G);
+    const uint32_t lo = s.start[b0], hi = s.start[b0 + G * (TILE / KZ)];
     uint32_t idv[PU];
     T dv[PU][3], mv[PU];
     // the first batch is in flight while the box is cleared
@@ -469,7 +469,14 @@ HaloMerge<T> paint_halo_merge(Geo g, const T* halo) {
 // ---------------------------------------------------------------------------
 // LDS-staged CIC readout + kick
 // ---------------------------------------------------------------------------
+// The readout works on one 16^3 tile (its two sort blocks) per workgroup,
+// with the tile's 17^3 force values of each component in LDS.  (Blocks of
+// 16 x 16 x 8 with a 17 x 17 x 9 box would fit more workgroups per CU, but
+// their 9-value rows along axis 2 waste most of each memory segment, and
+// measure slower.)
 constexpr int PBR = 512;  // threads per readout workgroup
+constexpr int RZ = TE;    // LDS depth of the readout box
+constexpr int RC = TE * TE * RZ;  // LDS cells of the readout box
 
 // Workgroups are handed to the 8 XCDs round-robin.  Renumber them so that
 // each XCD walks a contiguous run of tiles: neighbouring tiles along axis 2
@@ -484,7 +491,7 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 // 17^3 LDS tile of the three components at origin (ox, oy, oz).
 template <class T>
 __device__ __forceinline__ void tile_force(const Geo& g, uint32_t id, const T (&d)[3],
-                                           const T (*ft)[TE * TE * TE], int ox, int oy, int oz,
+                                           const T (*ft)[RC], int ox, int oy, int oz,
                                            T& a0, T& a1, T& a2) {
     int i0, i1, i2;
     lattice_of(id, g.np, i0, i1, i2);
@@ -502,7 +509,7 @@ __device__ __forceinline__ void tile_force(const Geo& g, uint32_t id, const T (&
     for (int a = 0; a < 2; ++a)
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-            int cb = ((l0 + a) * TE + (l1 + b)) * TE + l2;
+            int cb = ((l0 + a) * TE + (l1 + b)) * RZ + l2;
             T wab = wa[a] * wb[b];
             T v0 = wab * wc[0], v1 = wab * wc[1];
             a0 += v0 * ft[0][cb] + v1 * ft[0][cb + 1];
@@ -519,7 +526,7 @@ __device__ __forceinline__ void tile_force(const Geo& g, uint32_t id, const T (&
 template <class T>
 __device__ __forceinline__ void readout_kick_drift_key(
     Parts<T>& p, const SortBufs& s, const Geo& g, long n, uint32_t k, bool valid, uint32_t id,
-    const T (&dv)[3], const T (&mv)[3], const T (*ft)[TE * TE * TE], int ox, int oy, int oz,
+    const T (&dv)[3], const T (&mv)[3], const T (*ft)[RC], int ox, int oy, int oz,
     T kick, const ReadoutNext<T>& nx, uint32_t* status) {
     uint32_t key = 0;
     if (valid) {
@@ -572,21 +579,22 @@ template <class T>
 __global__ __launch_bounds__(PBR) void k_readout(Parts<T> p, SortBufs s, Geo g, const T* f0,
                                                 const T* f1, const T* f2, T kick, int do_kick,
                                                 uint32_t* status, ReadoutNext<T> nx) {
-    constexpr int TC = TE * TE * TE;
+    constexpr int TC = RC;
     __shared__ T ft[3][TC];
     const int tid = threadIdx.x;
     const int t = xcd_tile(blockIdx.x, gridDim.x);
     const int tx = t / (g.nt * g.nt), ty = (t / g.nt) % g.nt, tz = t % g.nt;
     const int ox = tx * TILE, oy = ty * TILE, oz = tz * TILE;
-    const uint32_t lo = s.start[t], hi = s.start[t + 1];
-    if (lo == hi) return;  // uniform across the workgroup
     const int nm = g.nm;
+    const int b0 = tile_block(g, tx, ty, tz);
     const long n = g.npart;
     uint32_t idv[PU];
     T dv[PU][3], mv[PU][3];
-    // the first batch of particles is loaded together with the force tile,
-    // so the two waits overlap
-    readout_load_batch<T>(p, n, lo + tid, hi, do_kick, idv, dv, mv);
+    // Loads complete in issue order, so: the tile's particle range first,
+    // then the force tile (which does not depend on it), then the first
+    // batch of particles, which waits only for the range; all three are in
+    // flight together.
+    const uint32_t lo = s.start[b0], hi = s.start[b0 + TILE / KZ];
     {
         constexpr int IT = (TC + PBR - 1) / PBR;
         T v0[IT], v1[IT], v2[IT];
@@ -594,7 +602,7 @@ __global__ __launch_bounds__(PBR) void k_readout(Parts<T> p, SortBufs s, Geo g, 
         for (int it = 0; it < IT; ++it) {
             int i = tid + it * PBR;
             if (i < TC) {
-                int x = i / (TE * TE), y = (i / TE) % TE, z = i % TE;
+                int x = i / (TE * RZ), y = (i / RZ) % TE, z = i % RZ;
                 int gx = ox + x, gy = oy + y, gz = oz + z;
                 if (gx >= nm) gx -= nm;
                 if (gy >= nm) gy -= nm;
@@ -605,6 +613,8 @@ __global__ __launch_bounds__(PBR) void k_readout(Parts<T> p, SortBufs s, Geo g, 
                 v2[it] = f2[c];
             }
         }
+        if (lo == hi) return;  // uniform across the workgroup
+        readout_load_batch<T>(p, n, lo + tid, hi, do_kick, idv, dv, mv);
 #pragma unroll
         for (int it = 0; it < IT; ++it) {
             int i = tid + it * PBR;

@@ -9,12 +9,12 @@
 //    pm_reconfigure), else frees idle arenas, least recently used first,
 //    and creates one on a stream of its own.  It then enqueues the seeded
 //    initial conditions and hands the slot to the issue thread.
-//  - issue: keeps up to `depth` PM steps (pm_step + lens_project of the
-//    shell) in flight on every running slot, round-robin over slots, so the
-//    kernels of different requests overlap on the device; when a slot has
-//    issued its last step it copies the maps to pinned host memory, and on
-//    completion of that copy it hands the maps to the request and returns the
-//    arena to the idle pool.
+//  - issue: keeps up to `depth` chunks of PM steps (pm_run: steps with the
+//    projection of their shells) in flight on every running slot,
+//    round-robin over slots, so the kernels of different requests overlap
+//    on the device.  When a slot has issued its last step it copies the
+//    maps to pinned host memory; when that copy completes it hands the maps
+//    to the request and returns the arena to the idle pool.
 // The same kernels run as for a lone simulation, and paint and projection
 // accumulate in fixed point, so a request's maps are bitwise the same alone
 // and in any mix.
@@ -102,7 +102,8 @@ Key key_of(const pm_request& r) {
 struct pm_srv {
     size_t budget = 0;
     int max_active = 1;
-    int depth = 2;
+    int depth = 2;   // chunks in flight per request
+    int chunk = 1;   // steps per chunk (1: finest interleaving)
     clk::time_point t0 = clk::now();
 
     std::mutex mu;
@@ -253,9 +254,10 @@ void pm_srv::issue_loop() {
             int rc = PM_OK;
             while (rc == PM_OK && !s.finishing && (int)s.inflight.size() < depth &&
                    s.next < q.r.nsteps) {
-                double a0 = q.agrid[s.next], a1 = q.agrid[s.next + 1];
-                rc = pm_step(s.sim, a0, a1);
-                if (rc == PM_OK) rc = lens_project(s.sim, a0, a1, s.kdev);
+                // a chunk of steps with their shells (pm_run: each readout also
+                // starts the next step of the chunk)
+                const int m = std::min(chunk, q.r.nsteps - s.next);
+                rc = pm_run(s.sim, &q.agrid[s.next], m, s.kdev);
                 hipEvent_t e = nullptr;
                 if (!s.spare.empty()) {
                     e = s.spare.back();
@@ -265,7 +267,7 @@ void pm_srv::issue_loop() {
                 }
                 if (rc == PM_OK && hipEventRecord(e, s.st) != hipSuccess) rc = PM_EDEVICE;
                 if (e) s.inflight.push_back(e);
-                ++s.next;
+                s.next += m;
                 progress = true;
             }
             if (rc == PM_OK && !s.finishing && s.next == q.r.nsteps) {
