@@ -101,30 +101,52 @@ __device__ __forceinline__ void wave_count(bool valid, uint32_t key, uint32_t* c
     }
 }
 
-// Rank of each valid lane among the particles of its tile, taken by counting
-// the tile's histogram entry down (one atomic per distinct key per wave):
-// the ranks of a tile's particles are distinct and fill [0, count), and the
-// histogram ends at zero, ready for the next step.  Every lane of the wave
-// must call it.
-__device__ __forceinline__ uint32_t wave_take(bool valid, uint32_t key, uint32_t* count) {
+// Lanes of a wave grouped by key: the group's first lane (its leader) and,
+// for each lane, the number of group members in lower lanes; the leader
+// also holds the group size.  Arithmetic only (one ballot round per
+// distinct key), no memory traffic.
+struct WaveGroup {
+    int leader;
+    uint32_t before;  // group members in lower lanes
+    uint32_t size;    // group size (leader lane only, else 0)
+};
+
+__device__ __forceinline__ WaveGroup wave_group(bool valid, uint32_t key) {
     const int lane = threadIdx.x & 63;
+    WaveGroup w{0, 0u, 0u};
     bool pending = valid;
-    uint32_t myrank = 0;
     while (__any(pending)) {
         unsigned long long m = __ballot(pending);
         int leader = __ffsll((long long)m) - 1;
         uint32_t lkey = __shfl(key, leader);
         bool mine = pending && key == lkey;
         unsigned long long same = __ballot(mine);
-        uint32_t top = 0;
-        if (lane == leader) top = atomicSub(&count[lkey], (uint32_t)__popcll(same));
-        top = __shfl(top, leader);
         if (mine) {
-            myrank = top - 1u - (uint32_t)__popcll(same & ((1ull << lane) - 1ull));
+            w.leader = leader;
+            w.before = (uint32_t)__popcll(same & ((1ull << lane) - 1ull));
             pending = false;
         }
+        if (lane == leader) w.size = (uint32_t)__popcll(same);
     }
-    return myrank;
+    return w;
+}
+
+// Rank of each valid lane among the particles of its tile, taken by counting
+// the tile's histogram entry down: every group leader subtracts its group's
+// size in the same atomic instruction, and the members number themselves
+// below the returned value.  The ranks of a tile's particles are distinct and
+// fill [0, count), and the histogram ends at zero, ready for the next step.
+// Split in two so that several rank requests of one thread share a round
+// trip: wave_take_issue for each, then wave_take_rank for each.  Every lane
+// of the wave must call both.
+__device__ __forceinline__ uint32_t wave_take_issue(const WaveGroup& w, uint32_t key,
+                                                    uint32_t* count) {
+    uint32_t top = 0;
+    if (w.size) top = atomicSub(&count[key], w.size);
+    return top;
+}
+__device__ __forceinline__ uint32_t wave_take_rank(const WaveGroup& w, uint32_t top) {
+    return __shfl(top, w.leader) - 1u - w.before;
 }
 
 template <class T>
@@ -241,28 +263,62 @@ void launch_scan(const uint32_t* count, uint32_t* start, uint32_t* block_sum, in
 }
 
 // ---------------------------------------------------------------------------
+// Particles k = base + u * PB + thread (u < SU) of a scatter batch: keys,
+// destinations and data are all loaded before the one atomic round trip of
+// the batch's ranks.  Lanes past the end load the last particle (so that no
+// load is conditional and the loads stay in flight together) and store
+// nothing.
+constexpr int SU = 4;
+
 template <class T>
 __global__ __launch_bounds__(PB) void k_scatter(Parts<T> src, Parts<T> dst, SortBufs s, Geo g) {
     const long n = g.npart;
-    for (long base = blockIdx.x * (long)PB; base < n; base += (long)gridDim.x * PB) {
-        const long k = base + threadIdx.x;
-        const bool valid = k < n;
-        const uint32_t key = valid ? s.key[k] : 0u;
-        const uint32_t r = wave_take(valid, key, s.count);
-        if (!valid) continue;
-        const uint32_t d = s.start[key] + r;
+    for (long base = blockIdx.x * (long)(PB * SU); base < n; base += (long)gridDim.x * PB * SU) {
+        bool valid[SU];
+        long kc[SU];
+        uint32_t key[SU], first[SU], idv[SU], top[SU];
+        T dv[SU][3], mv[SU][3];
+        WaveGroup w[SU];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            dst.disp[a * n + d] = src.disp[a * n + k];
-            dst.mom[a * n + d] = src.mom[a * n + k];
+        for (int u = 0; u < SU; ++u) {
+            const long k = base + u * PB + threadIdx.x;
+            valid[u] = k < n;
+            kc[u] = valid[u] ? k : n - 1;
+            key[u] = s.key[kc[u]];
         }
-        dst.id[d] = src.id[k];
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+            idv[u] = src.id[kc[u]];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                dv[u][a] = src.disp[a * n + kc[u]];
+                mv[u][a] = src.mom[a * n + kc[u]];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < SU; ++u) first[u] = s.start[key[u]];
+#pragma unroll
+        for (int u = 0; u < SU; ++u) w[u] = wave_group(valid[u], key[u]);
+#pragma unroll
+        for (int u = 0; u < SU; ++u) top[u] = wave_take_issue(w[u], key[u], s.count);
+#pragma unroll
+        for (int u = 0; u < SU; ++u) {
+            const uint32_t r = wave_take_rank(w[u], top[u]);
+            if (!valid[u]) continue;
+            const uint32_t d = first[u] + r;
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                dst.disp[a * n + d] = dv[u][a];
+                dst.mom[a * n + d] = mv[u][a];
+            }
+            dst.id[d] = idv[u];
+        }
     }
 }
 
 template <class T>
 void launch_scatter(Parts<T> src, Parts<T> dst, SortBufs s, Geo g, hipStream_t st) {
-    long blocks = (g.npart + PB - 1) / PB;
+    long blocks = (g.npart + PB * SU - 1) / (PB * SU);
     if (blocks > 16384) blocks = 16384;
     hipLaunchKernelGGL(k_scatter<T>, dim3(blocks), dim3(PB), 0, st, src, dst, s, g);
 }
@@ -556,21 +612,24 @@ __device__ __forceinline__ void readout_kick_drift_key(
     wave_count(valid, key, s.count);
 }
 
-// Particles k0, k0 + PBR, ... (PU of them, below hi) of a readout batch.
+// Particles k0, k0 + PBR, ... (PU of them) of a readout batch.  Slots at or
+// past hi load particle hi - 1 instead (hi > lo, so it exists) and are not
+// used: with no load conditional, the compiler keeps every load of the
+// batch and of the force tile in flight together.  Momenta are loaded even
+// without a kick.
 template <class T>
 __device__ __forceinline__ void readout_load_batch(const Parts<T>& p, long n, uint32_t k0,
-                                                   uint32_t hi, int do_kick, uint32_t (&idv)[PU],
+                                                   uint32_t hi, uint32_t (&idv)[PU],
                                                    T (&dv)[PU][3], T (&mv)[PU][3]) {
 #pragma unroll
     for (int u = 0; u < PU; ++u) {
         uint32_t k = k0 + u * PBR;
-        if (k < hi) {
-            idv[u] = p.id[k];
+        k = k < hi ? k : hi - 1u;
+        idv[u] = p.id[k];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                dv[u][a] = p.disp[a * n + k];
-                if (do_kick) mv[u][a] = p.mom[a * n + k];
-            }
+        for (int a = 0; a < 3; ++a) {
+            dv[u][a] = p.disp[a * n + k];
+            mv[u][a] = p.mom[a * n + k];
         }
     }
 }
@@ -590,10 +649,13 @@ __global__ __launch_bounds__(PBR) void k_readout(Parts<T> p, SortBufs s, Geo g, 
     const long n = g.npart;
     uint32_t idv[PU];
     T dv[PU][3], mv[PU][3];
-    // Loads complete in issue order, so: the tile's particle range first,
-    // then the force tile (which does not depend on it), then the first
-    // batch of particles, which waits only for the range; all three are in
-    // flight together.
+    // Issue order: the tile's particle range and the force tile (which does
+    // not depend on it), then the first batch of particles, which waits
+    // only for the range; then the force tile goes to LDS.  The empty asm
+    // statements are compiler-only fences that keep this order (the
+    // compiler would otherwise test the range before issuing the force
+    // loads, and move LDS stores, each waiting for its load, in between
+    // the particle loads); they emit no instruction.
     const uint32_t lo = s.start[b0], hi = s.start[b0 + TILE / KZ];
     {
         constexpr int IT = (TC + PBR - 1) / PBR;
@@ -601,7 +663,8 @@ __global__ __launch_bounds__(PBR) void k_readout(Parts<T> p, SortBufs s, Geo g, 
 #pragma unroll
         for (int it = 0; it < IT; ++it) {
             int i = tid + it * PBR;
-            if (i < TC) {
+            i = i < TC ? i : TC - 1;  // a repeat load, not stored
+            {
                 int x = i / (TE * RZ), y = (i / RZ) % TE, z = i % RZ;
                 int gx = ox + x, gy = oy + y, gz = oz + z;
                 if (gx >= nm) gx -= nm;
@@ -613,8 +676,10 @@ __global__ __launch_bounds__(PBR) void k_readout(Parts<T> p, SortBufs s, Geo g, 
                 v2[it] = f2[c];
             }
         }
+        asm volatile("" ::: "memory");
         if (lo == hi) return;  // uniform across the workgroup
-        readout_load_batch<T>(p, n, lo + tid, hi, do_kick, idv, dv, mv);
+        readout_load_batch<T>(p, n, lo + tid, hi, idv, dv, mv);
+        asm volatile("" ::: "memory");
 #pragma unroll
         for (int it = 0; it < IT; ++it) {
             int i = tid + it * PBR;
@@ -627,7 +692,7 @@ __global__ __launch_bounds__(PBR) void k_readout(Parts<T> p, SortBufs s, Geo g, 
     }
     __syncthreads();
     for (uint32_t base = lo; base < hi; base += PBR * PU) {
-        if (base != lo) readout_load_batch<T>(p, n, base + tid, hi, do_kick, idv, dv, mv);
+        if (base != lo) readout_load_batch<T>(p, n, base + tid, hi, idv, dv, mv);
 #pragma unroll
         for (int u = 0; u < PU; ++u) {
             uint32_t k = base + u * PBR + tid;
