@@ -8,6 +8,12 @@ namespace ml {
 
 template <class T> struct cx { T re, im; };
 
+// Compiler-only fence: no memory access moves across it.  Used to keep
+// loads that should be in flight together ahead of the LDS stores that
+// consume them (and of branches that would delay their issue); it emits no
+// instruction.
+__device__ __forceinline__ void issue_fence() { asm volatile("" ::: "memory"); }
+
 template <class T> __device__ __forceinline__ cx<T> mk(T r, T i) { return {r, i}; }
 template <class T> __device__ __forceinline__ cx<T> operator+(cx<T> a, cx<T> b) { return {a.re + b.re, a.im + b.im}; }
 template <class T> __device__ __forceinline__ cx<T> operator-(cx<T> a, cx<T> b) { return {a.re - b.re, a.im - b.im}; }

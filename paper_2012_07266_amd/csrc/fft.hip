@@ -84,10 +84,30 @@ __device__ __forceinline__ void fft_lds(cx<T>* buf, const cx<T>* tw, int tid) {
     }
 }
 
+// A table of N twiddles, fetched into registers as a kernel's first loads
+// and stored to LDS once its data loads are issued: loads complete in issue
+// order, so the store waits for the table alone and no round trip to memory
+// comes before the data loads.  Slots past N repeat the last entry.
 template <class T, int N, int NTT = NT>
-__device__ __forceinline__ void load_twiddles(cx<T>* tw_s, const cx<T>* tw, int tid) {
-    for (int t = tid; t < N; t += NTT) tw_s[t] = tw[t];
-}
+struct TwFetch {
+    static constexpr int IT = (N + NTT - 1) / NTT;
+    cx<T> v[IT];
+    __device__ __forceinline__ void fetch(const cx<T>* tw, int tid) {
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            int t = tid + it * NTT;
+            v[it] = tw[t < N ? t : N - 1];
+        }
+    }
+    __device__ __forceinline__ void store(cx<T>* tw_s, int tid) const {
+        issue_fence();
+#pragma unroll
+        for (int it = 0; it < IT; ++it) {
+            int t = tid + it * NTT;
+            if (N % NTT == 0 || t < N) tw_s[t] = v[it];
+        }
+    }
+};
 
 // ---------------------------------------------------------------------------
 // Register-resident variant for the strided passes.  Each thread keeps the
@@ -199,10 +219,14 @@ __global__ __launch_bounds__(NT) void k_r2c_rows(T* io, cx<T>* nyq, const cx<T>*
                                                  const cx<T>* tw_post, HaloMerge<T> hm) {
     __shared__ cx<T> buf[H * (W + 1)];
     __shared__ cx<T> tws[H];
+    __shared__ cx<T> twp[H / 2 + 1];
     constexpr int LD = W + 1;
     const int tid = threadIdx.x;
     const size_t r0 = (size_t)blockIdx.x * W;
-    load_twiddles<T, H>(tws, tw_h, tid);
+    TwFetch<T, H> twr;
+    TwFetch<T, H / 2 + 1> twq;
+    twr.fetch(tw_h, tid);
+    twq.fetch(tw_post, tid);
     const cx<T>* in = reinterpret_cast<const cx<T>*>(io) + r0 * H;
     {
         constexpr int IT = (W * H + NT - 1) / NT;
@@ -212,6 +236,8 @@ __global__ __launch_bounds__(NT) void k_r2c_rows(T* io, cx<T>* nyq, const cx<T>*
             int f = tid + it * NT;
             if ((W * H) % NT == 0 || f < W * H) v[it] = in[f];  // rows are contiguous
         }
+        twr.store(tws, tid);
+        twq.store(twp, tid);
 #pragma unroll
         for (int it = 0; it < IT; ++it) {
             int f = tid + it * NT;
@@ -231,7 +257,7 @@ __global__ __launch_bounds__(NT) void k_r2c_rows(T* io, cx<T>* nyq, const cx<T>*
         cx<T> ze = scale(a + b, T(0.5));
         cx<T> d = scale(a - b, T(0.5));
         cx<T> zo = {d.im, -d.re};  // (a - b) / (2i)
-        cx<T> tzo = cmul(tw_post[k], zo);
+        cx<T> tzo = cmul(twp[k], zo);
         cx<T> xk = ze + tzo;
         cx<T> xm = conj(ze - tzo);
         if (k == 0) {
@@ -258,20 +284,24 @@ __global__ __launch_bounds__(NT) void k_c2r_rows(T* io, const cx<T>* nyq, const 
     constexpr int LD = W + 1;
     const int tid = threadIdx.x;
     const size_t r0 = (size_t)blockIdx.x * W;
-    load_twiddles<T, H>(tws, tw_h, tid);
+    TwFetch<T, H> twr;
+    twr.fetch(tw_h, tid);
     const cx<T>* in = reinterpret_cast<const cx<T>*>(io) + r0 * H;
     constexpr int HK = H / 2 + 1;
     constexpr int ITK = (W * HK + NT - 1) / NT;
-    cx<T> xkv[ITK], xmv[ITK];
+    cx<T> xkv[ITK], xmv[ITK], tpv[ITK];
+    // every load unconditional (slots past the end repeat the last one and
+    // are not used), so that all are in flight together
 #pragma unroll
     for (int it = 0; it < ITK; ++it) {
         int f = tid + it * NT;
-        if (f < W * HK) {
-            int w = f / HK, k = f % HK;
-            xkv[it] = in[(size_t)w * H + k];
-            xmv[it] = k == 0 ? nyq[r0 + w] : in[(size_t)w * H + (H - k)];
-        }
+        f = f < W * HK ? f : W * HK - 1;
+        int w = f / HK, k = f % HK;
+        xkv[it] = in[(size_t)w * H + k];
+        xmv[it] = k == 0 ? nyq[r0 + w] : in[(size_t)w * H + (H - k)];
+        tpv[it] = tw_post[k];
     }
+    twr.store(tws, tid);
 #pragma unroll
     for (int it = 0; it < ITK; ++it) {
         int f = tid + it * NT;
@@ -288,7 +318,7 @@ __global__ __launch_bounds__(NT) void k_c2r_rows(T* io, const cx<T>* nyq, const 
         }
         cx<T> ze = xk + conj(xm);
         cx<T> d = xk - conj(xm);
-        cx<T> tp = conj(tw_post[k]);  // exp(+2 pi i k / Nm)
+        cx<T> tp = conj(tpv[it]);  // exp(+2 pi i k / Nm)
         cx<T> q = cmul(d, tp);
         cx<T> iq = {-q.im, q.re};
         buf[k * LD + w] = ze + iq;
@@ -390,7 +420,8 @@ __global__ __launch_bounds__(NT) void k_c2c_view(ViewDesc va, ViewDesc vb, const
     int g = blockIdx.x;
     const ViewDesc& v = g < va.n_wg ? va : vb;
     if (g >= va.n_wg) g -= va.n_wg;
-    load_twiddles<T, N>(tws, tw, tid);
+    TwFetch<T, N> twr;
+    twr.fetch(tw, tid);
     if constexpr (reg_path_ok<N, W>()) {
         if (!v.contig) {
             constexpr int E = W * N / NT;
@@ -406,6 +437,7 @@ __global__ __launch_bounds__(NT) void k_c2c_view(ViewDesc va, ViewDesc vb, const
                     slot_pos<N, W, R0>(tid, it, q, w, n);
                     r[it * R0 + q] = src[view_offset<T, N, W>(v, g, w, n)];
                 }
+            twr.store(tws, tid);
             __syncthreads();  // twiddles in LDS
             reg_compute<T, N, W, R0, 1, S>(r, tws, tid);
             reg_chain<T, N, W, S, 1>(r, buf, tws, tid);
@@ -422,6 +454,7 @@ __global__ __launch_bounds__(NT) void k_c2c_view(ViewDesc va, ViewDesc vb, const
         }
     }
     view_load<T, N, W>(buf, v, g, tid);
+    twr.store(tws, tid);
     __syncthreads();
     fft_lds<T, N, W, S>(buf, tws, tid);
     view_store<T, N, W>(buf, v.ptr, v, g, tid);
@@ -452,7 +485,8 @@ __global__ __launch_bounds__(NT) void k_c2c_view_dual(ViewDesc va, ViewDesc vb, 
     const ViewDesc& v = is_a ? va : vb;
     cx<T>* dst2 = is_a ? dst2a : dst2b;
     if (!is_a) g -= va.n_wg;
-    load_twiddles<T, N>(tws, tw, tid);
+    TwFetch<T, N> twr;
+    twr.fetch(tw, tid);
     if constexpr (reg_path_ok<N, W>()) {
         if (!v.contig) {
             constexpr int E = W * N / NT;
@@ -471,6 +505,7 @@ __global__ __launch_bounds__(NT) void k_c2c_view_dual(ViewDesc va, ViewDesc vb, 
 #pragma unroll
                 for (int q = 0; q < R0; ++q)
                     r[it * R0 + q] = src[(long)(it * (NT / W) + q * (N / R0)) * C];
+            twr.store(tws, tid);
             __syncthreads();  // twiddles in LDS
             reg_compute<T, N, W, R0, 1, -1>(r, tws, tid);
             reg_chain<T, N, W, -1, 1>(r, buf, tws, tid);
@@ -504,6 +539,7 @@ __global__ __launch_bounds__(NT) void k_c2c_view_dual(ViewDesc va, ViewDesc vb, 
     // LDS path: transform H, store it to out2; reload H scaled by n1,
     // transform, store in place
     view_load<T, N, W>(buf, v, g, tid);
+    twr.store(tws, tid);
     __syncthreads();
     fft_lds<T, N, W, -1>(buf, tws, tid);
     view_store<T, N, W>(buf, dst2, v, g, tid);
@@ -548,7 +584,8 @@ __global__ __launch_bounds__(NTG, (NTG == 512 ? 4 : 1)) void k_grad_x0(ViewDesc 
     const ViewDesc& v = is_a ? va : vb;
     const PtrTriple& out = is_a ? outa : outb;
     if (!is_a) g -= va.n_wg;
-    load_twiddles<T, N, NTG>(tws, tw, tid);
+    TwFetch<T, N, NTG> twr;
+    twr.fetch(tw, tid);
     constexpr int R0 = plan_radix(N, 0);
     constexpr int RL = plan_radix(N, num_stages(N) - 1);
     constexpr int PL = span_before(N, num_stages(N) - 1);
@@ -570,6 +607,7 @@ __global__ __launch_bounds__(NTG, (NTG == 512 ? 4 : 1)) void k_grad_x0(ViewDesc 
 #pragma unroll
             for (int q = 0; q < R0; ++q)
                 spec[it * R0 + q] = src[(long)(it * (NTG / W) + q * (N / R0)) * C];
+        twr.store(tws, tid);
         __syncthreads();
         reg_compute<T, N, W, R0, 1, 1, NTG>(spec, tws, tid);
         reg_chain<T, N, W, 1, 1, NTG>(spec, buf, tws, tid);
@@ -628,6 +666,7 @@ __global__ __launch_bounds__(NTG, (NTG == 512 ? 4 : 1)) void k_grad_x0(ViewDesc 
     static_assert(NTG == NT || reg_path_ok<N, W, NTG>(), "LDS path needs NT threads");
     if constexpr (NTG == NT) {
     view_load<T, N, W>(buf, v, g, tid);
+    twr.store(tws, tid);
     __syncthreads();
     fft_lds<T, N, W, 1>(buf, tws, tid);
 
@@ -710,13 +749,15 @@ __global__ __launch_bounds__(NT) void k_div_x0(ViewDesc va, ViewDesc vb, PtrTrip
     const PtrTriple& in = is_a ? ina : inb;
     void* out = is_a ? outa : outb;
     if (!is_a) g -= va.n_wg;
-    load_twiddles<T, N>(tws, tw, tid);
+    TwFetch<T, N> twr;
+    twr.fetch(tw, tid);
     cx<T> acc[IT];
 #pragma unroll
     for (int it = 0; it < IT; ++it) acc[it] = {T(0), T(0)};
     for (int j = 0; j < 3; ++j) {
         v.ptr = in.p[j];
         view_load<T, N, W>(buf, v, g, tid);
+        if (j == 0) twr.store(tws, tid);
         __syncthreads();
         fft_lds<T, N, W, 1>(buf, tws, tid);
 #pragma unroll
@@ -739,19 +780,27 @@ __global__ __launch_bounds__(NT) void k_div_x0(ViewDesc va, ViewDesc vb, PtrTrip
         }
         __syncthreads();
     }
+    T gg[IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        int f = tid + it * NT;
+        f = (W * N) % NT == 0 || f < W * N ? f : W * N - 1;
+        int n = f / W, w = f % W;
+        long c = (long)g * W + w;
+        int k1 = is_a ? (int)(c / HN) : (int)c;
+        int k2 = is_a ? (int)(c % HN) : HN;
+        int n0 = n <= HN ? n : n - N;
+        int n1 = k1 <= HN ? k1 : k1 - N;
+        int nsq = n0 * n0 + n1 * n1 + k2 * k2;
+        gg[it] = nsq ? gscale / T(nsq) : T(0);
+        if (G) gg[it] = G[nsq];  // uniform: the table loads issue together
+    }
 #pragma unroll
     for (int it = 0; it < IT; ++it) {
         int f = tid + it * NT;
         if ((W * N) % NT == 0 || f < W * N) {
             int n = f / W, w = f % W;
-            long c = (long)g * W + w;
-            int k1 = is_a ? (int)(c / HN) : (int)c;
-            int k2 = is_a ? (int)(c % HN) : HN;
-            int n0 = n <= HN ? n : n - N;
-            int n1 = k1 <= HN ? k1 : k1 - N;
-            int nsq = n0 * n0 + n1 * n1 + k2 * k2;
-            T gg = G ? G[nsq] : (nsq ? gscale / T(nsq) : T(0));
-            buf[n * LD + w] = {gg * acc[it].im, -gg * acc[it].re};  // -i G acc
+            buf[n * LD + w] = {gg[it] * acc[it].im, -gg[it] * acc[it].re};  // -i G acc
         }
     }
     __syncthreads();

@@ -651,11 +651,10 @@ __global__ __launch_bounds__(PBR) void k_readout(Parts<T> p, SortBufs s, Geo g, 
     T dv[PU][3], mv[PU][3];
     // Issue order: the tile's particle range and the force tile (which does
     // not depend on it), then the first batch of particles, which waits
-    // only for the range; then the force tile goes to LDS.  The empty asm
-    // statements are compiler-only fences that keep this order (the
-    // compiler would otherwise test the range before issuing the force
-    // loads, and move LDS stores, each waiting for its load, in between
-    // the particle loads); they emit no instruction.
+    // only for the range; then the force tile goes to LDS.  The fences keep
+    // this order (the compiler would otherwise test the range before issuing
+    // the force loads, and move LDS stores, each waiting for its load, in
+    // between the particle loads).
     const uint32_t lo = s.start[b0], hi = s.start[b0 + TILE / KZ];
     {
         constexpr int IT = (TC + PBR - 1) / PBR;
@@ -676,10 +675,10 @@ __global__ __launch_bounds__(PBR) void k_readout(Parts<T> p, SortBufs s, Geo g, 
                 v2[it] = f2[c];
             }
         }
-        asm volatile("" ::: "memory");
+        issue_fence();
         if (lo == hi) return;  // uniform across the workgroup
         readout_load_batch<T>(p, n, lo + tid, hi, idv, dv, mv);
-        asm volatile("" ::: "memory");
+        issue_fence();
 #pragma unroll
         for (int it = 0; it < IT; ++it) {
             int i = tid + it * PBR;
