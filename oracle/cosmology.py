@@ -144,6 +144,17 @@ class Cosmology:
         """Linear growth factor normalised to D(1) = 1."""
         return self._du(a) / self.du1
 
+    # vectorised D(a) for many scale factors: the growth integral after the
+    # substitution a' = a u^2, which makes the integrand analytic on [0, 1]:
+    # I(a) = 2 a^(5/2) int_0^1 u^4 (Om + (1 - Om) a^3 u^6)^(-3/2) du
+    def D_vec(self, a):
+        a = np.asarray(a, dtype=np.float64)
+        u = 0.5 * (self._GL_X + 1.0)
+        a3 = (a ** 3)[..., None]
+        g = u ** 4 / (self.omega_m + (1.0 - self.omega_m) * a3 * u ** 6) ** 1.5
+        integral = 2.0 * a ** 2.5 * 0.5 * np.sum(g * self._GL_W, axis=-1)
+        return 2.5 * self.omega_m * self.E(a) * integral / self.du1
+
     def dD_da(self, a):
         """dD/da = (5 Om/2) [E'(a) I(a) + 1/(a^3 E^2)] / D_u(1)."""
         a = float(a)

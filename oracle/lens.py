@@ -22,6 +22,9 @@ section).  Readings fixed here where the paper is silent:
              and floor(t)+1 per axis, contributions off the map dropped
   mean       each shell adds -pref int q(chi)/a(chi) dchi over the shell
              below chi_s to every pixel (the -1 of delta = rho/rho_bar - 1)
+  sub-evolution (optional) an image keeps the shell of its end-of-step
+             depth and is moved along its step's drift to the scale factor
+             of that depth before projection (project_shell's `sub`)
 
 Images are enumerated by brute force over a generous box of replica
 offsets; each is tested exactly.  Pins (tests/test_oracle_lens.py): single
@@ -109,7 +112,8 @@ def shell_images(x, box, chi_near, chi_far, geom: MapGeometry):
 
 
 def project_shell(x, a_far, a_near, cosmo: Cosmology, box, np_side,
-                  geom: MapGeometry, include_mean=True, chi_bounds=None, src_cut=None):
+                  geom: MapGeometry, include_mean=True, chi_bounds=None, src_cut=None,
+                  sub=None):
     """Convergence of one PM step's shell, [nsrc][npix][npix].
 
     x are the positions at a_near (end of the step a_far -> a_near).
@@ -118,6 +122,15 @@ def project_shell(x, a_far, a_near, cosmo: Cosmology, box, np_side,
     `src_cut[s]` overrides chi_s in the test "image in front of source s"
     only (the weight keeps geom.chi_src): it holds that membership fixed
     while the cosmology varies.
+
+    `sub` = (p_h, a_h) turns on sub-evolution (the package-design section's
+    sub-evolution step): p_h [3][N] is the momentum the step drifted with and
+    a_h its midpoint.  The step's drift moves a particle along
+    x(a) = x(a_near) + Dr(a_near, a; a_h) p_h, linear in D(a).  An image keeps
+    the shell its end-of-step depth chi_e puts it in, and is moved to
+    a_p = a(chi_e), the scale factor of its own distance (one fixed-point
+    iteration of chi -> depth of x(a(chi))); its angles, depth, a(chi) and
+    weight are then those of the moved image.
     """
     if chi_bounds is None:
         chi_far = float(cosmo.chi(a_far))
@@ -128,10 +141,19 @@ def project_shell(x, a_far, a_near, cosmo: Cosmology, box, np_side,
     vp = (box / np_side) ** 3
     out = np.zeros((len(geom.chi_src), geom.npix, geom.npix))
     t0s, t1s, chis = [], [], []
-    for _, rx, ry, chi in shell_images(x, box, chi_near, chi_far, geom):
+    if sub is not None:
+        p_h, a_h = sub
+        d_near, gp_h = cosmo.D(a_near), cosmo.gp(a_h)
+    for inz, rx, ry, chi in shell_images(x, box, chi_near, chi_far, geom):
+        if sub is not None:
+            dr = (cosmo.D_vec(cosmo.a_of_chi_vec(chi)) - d_near) / gp_h
+            rx = rx + dr * p_h[0, inz]
+            ry = ry + dr * p_h[1, inz]
+            chi = chi + dr * p_h[2, inz]
         t0 = rx / chi / geom.dtheta + 0.5 * geom.npix - 0.5
         t1 = ry / chi / geom.dtheta + 0.5 * geom.npix - 0.5
-        keep = (t0 > -1.0) & (t0 < geom.npix) & (t1 > -1.0) & (t1 < geom.npix)
+        keep = ((t0 > -1.0) & (t0 < geom.npix) & (t1 > -1.0) & (t1 < geom.npix)
+                & (chi > 0.0))
         t0s.append(t0[keep])
         t1s.append(t1[keep])
         chis.append(chi[keep])
@@ -181,21 +203,24 @@ def shell_mean_adaptive(cosmo: Cosmology, chi_near, chi_far, chi_s):
 
 
 def run_lensing(noise, cosmo: Cosmology, box, nm_side, a_grid, geom: MapGeometry,
-                states=None):
+                states=None, interpolation=False):
     """Full forward model: PM run plus the projection after every step.
 
     Returns (kappa, x_final, p_final).  If `states` is a list, the state
-    after each step is appended to it.
+    after each step is appended to it.  `interpolation` projects with
+    sub-evolution (project_shell's `sub`).
     """
     from . import pm
     np_side = noise.shape[0]
     kappa = np.zeros((len(geom.chi_src), geom.npix, geom.npix))
 
-    def cb(i, x, p):
-        kappa[...] += project_shell(x, a_grid[i], a_grid[i + 1], cosmo, box,
-                                    np_side, geom)
+    def cb(i, x, p, p_h):
+        a0, a1 = a_grid[i], a_grid[i + 1]
+        sub = (p_h, 0.5 * (a0 + a1)) if interpolation else None
+        kappa[...] += project_shell(x, a0, a1, cosmo, box, np_side, geom, sub=sub)
         if states is not None:
             states.append((x.copy(), p.copy()))
 
-    x, p = pm.run_pm(noise, cosmo, box, nm_side, a_grid, callback=cb)
+    x, p = pm.run_pm(noise, cosmo, box, nm_side, a_grid, callback=cb,
+                     drift_momentum=True)
     return kappa, x, p

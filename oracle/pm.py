@@ -185,32 +185,42 @@ def particle_force(x, np_side, nm_side, box):
 # ---------------------------------------------------------------------------
 # time stepping
 # ---------------------------------------------------------------------------
-def kdk_step(x, p, f, a0, a1, cosmo: Cosmology, np_side, nm_side, box):
+def kdk_step(x, p, f, a0, a1, cosmo: Cosmology, np_side, nm_side, box,
+             drift_momentum=False):
     """One kick-drift-kick step a0 -> a1 with force f = f(x) given at a0.
 
     p += K(a0, ah; a0) f;  x += Dr(a0, a1; ah) p;  f' = f(x);
-    p += K(ah, a1; a1) f'.  Returns (x, p, f').
+    p += K(ah, a1; a1) f'.  Returns (x, p, f'), and with `drift_momentum`
+    also the momentum the drift used.
     """
     ah = 0.5 * (a0 + a1)
     p = p + cosmo.kick_factor(a0, ah, a0) * f
+    p_h = p
     x = np.mod(x + cosmo.drift_factor(a0, a1, ah) * p, box)
     f = particle_force(x, np_side, nm_side, box)
     p = p + cosmo.kick_factor(ah, a1, a1) * f
+    if drift_momentum:
+        return x, p, f, p_h
     return x, p, f
 
 
-def run_pm(noise, cosmo: Cosmology, box, nm_side, a_grid, callback=None):
+def run_pm(noise, cosmo: Cosmology, box, nm_side, a_grid, callback=None,
+           drift_momentum=False):
     """Zel'dovich ICs at a_grid[0], then one KDK step per interval.
 
     `callback(i, x, p)` is called after each step with the state at
-    a_grid[i+1].  Returns the final (x, p).
+    a_grid[i+1] (`callback(i, x, p, p_h)` with `drift_momentum`, p_h being
+    the momentum of the step's drift).  Returns the final (x, p).
     """
     np_side = noise.shape[0]
     x, p = zeldovich_ic(noise, cosmo, box, nm_side, a_grid[0])
     f = particle_force(x, np_side, nm_side, box)
     for i in range(len(a_grid) - 1):
-        x, p, f = kdk_step(x, p, f, a_grid[i], a_grid[i + 1], cosmo,
-                           np_side, nm_side, box)
+        x, p, f, p_h = kdk_step(x, p, f, a_grid[i], a_grid[i + 1], cosmo,
+                                np_side, nm_side, box, drift_momentum=True)
         if callback is not None:
-            callback(i, x, p)
+            if drift_momentum:
+                callback(i, x, p, p_h)
+            else:
+                callback(i, x, p)
     return x, p

@@ -1,0 +1,104 @@
+"""Pins of the oracle's sub-evolution projection (the package-design
+section's sub-evolution step): an image keeps the shell of its end-of-step
+depth and is moved along its step's drift, x(a) = x(a_near) +
+Dr(a_near, a; a_h) p_h, to a_p = a(chi_e) before projection."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import lens, pm
+from oracle.cosmology import Cosmology
+
+
+@pytest.fixture(scope="module")
+def geom(cosmo):
+    return lens.MapGeometry(48, 3.0, (1.0, 2.0), cosmo)
+
+
+@pytest.mark.parametrize("om", [0.25, 0.3, 0.35])
+def test_growth_vectorised_matches_quadrature(om):
+    c = Cosmology(om)
+    a = np.array([0.01, 0.03, 0.1, 0.25, 0.5, 0.8, 1.0, 1.3])
+    ref = np.array([c.D(v) for v in a])
+    assert np.max(np.abs(c.D_vec(a) / ref - 1.0)) < 1e-13
+    # growing mode: D ~ a at early times in this normalisation's units
+    assert abs(c.D_vec(1e-4) / c.D_vec(2e-4) - 0.5) < 1e-6
+
+
+def test_zero_drift_momentum_is_the_plain_projection(cosmo, geom):
+    box, np_side = 180.0, 14
+    x = W.random_positions(np_side ** 3, box, seed=21)
+    a_far, a_near = 0.45, 0.5
+    plain = lens.project_shell(x, a_far, a_near, cosmo, box, np_side, geom)
+    sub = lens.project_shell(x, a_far, a_near, cosmo, box, np_side, geom,
+                             sub=(np.zeros_like(x), 0.5 * (a_far + a_near)))
+    np.testing.assert_array_equal(sub, plain)
+
+
+def test_moved_image_is_the_drift_path_from_the_step_start(cosmo, geom):
+    """The image projected with sub-evolution from the end of the step is the
+    one the step's own drift reaches at a(chi_e), computed here from the
+    start of the step instead: x_s + Dr(a_far, a_p; a_h) p_h."""
+    box, np_side = 3000.0, 10       # one replica along the line of sight
+    a_far, a_near = 0.5, 0.56
+    a_h = 0.5 * (a_far + a_near)
+    chi_far, chi_near = cosmo.chi(a_far), cosmo.chi(a_near)
+    rng = np.random.default_rng(5)
+    n = 40
+    # images well inside the shell, near the line of sight
+    depth = chi_near + (chi_far - chi_near) * rng.uniform(0.3, 0.7, n)
+    th = rng.uniform(-0.35, 0.35, (2, n)) * geom.fov
+    p_h = rng.normal(0.0, 400.0, (3, n))   # Mpc/h per unit of the drift factor
+    x_e = np.stack([0.5 * box + th[0] * depth, 0.5 * box + th[1] * depth, depth])
+    dr_step = cosmo.drift_factor(a_far, a_near, a_h)
+    x_s = x_e - dr_step * p_h
+    a_p = np.array([cosmo.a_of_chi(c) for c in x_e[2]])
+    y = np.stack([x_s[:, i] + cosmo.drift_factor(a_far, a_p[i], a_h) * p_h[:, i]
+                  for i in range(n)], axis=1)
+    # the moved depths stay inside the shell, so plain membership agrees
+    assert np.all((y[2] > chi_near) & (y[2] <= chi_far))
+    assert np.max(np.abs(y - x_e)) > 1.0      # the move is not negligible
+    sub = lens.project_shell(x_e, a_far, a_near, cosmo, box, np_side, geom,
+                             include_mean=False, sub=(p_h, a_h))
+    ref = lens.project_shell(y, a_far, a_near, cosmo, box, np_side, geom,
+                             include_mean=False)
+    assert np.abs(ref).max() > 0
+    assert np.max(np.abs(sub - ref)) < 1e-10 * np.abs(ref).max()
+
+
+def test_run_hands_out_the_drift_momentum(cosmo):
+    """The momentum given to the projection is the one the drift used:
+    x_{i+1} - x_i = Dr(a_i, a_{i+1}; a_h) p_h (modulo the box)."""
+    np_side, nm, box = 8, 8, 64.0
+    noise = W.white_noise(np_side, 3)
+    a_grid = np.linspace(0.2, 1.0, 4)
+    xs = [pm.zeldovich_ic(noise, cosmo, box, nm, a_grid[0])[0]]
+    seen = []
+
+    def cb(i, x, p, p_h):
+        dr = cosmo.drift_factor(a_grid[i], a_grid[i + 1], 0.5 * (a_grid[i] + a_grid[i + 1]))
+        d = np.mod(x - xs[-1] - dr * p_h + 0.5 * box, box) - 0.5 * box
+        seen.append(np.abs(d).max())
+        xs.append(x.copy())
+
+    pm.run_pm(noise, cosmo, box, nm, a_grid, callback=cb, drift_momentum=True)
+    assert len(seen) == 3 and max(seen) < 1e-9
+
+
+def test_run_with_interpolation_differs_and_keeps_the_mean(cosmo):
+    """Sub-evolution changes the maps (the particles move) but not the
+    per-shell mean terms, which do not depend on the particles."""
+    wl = W.CFG1
+    c = Cosmology(wl.omega_m)
+    g = lens.MapGeometry(24, 3.0, (1.0,), c)
+    noise = W.white_noise(8, 11)
+    a_grid = np.linspace(0.3, 1.0, 4)
+    k0, _, _ = lens.run_lensing(noise, c, 40.0, 8, a_grid, g)
+    k1, _, _ = lens.run_lensing(noise, c, 40.0, 8, a_grid, g, interpolation=True)
+    diff = np.abs(k1 - k0).max()
+    assert diff > 1e-6 * np.abs(k0).max()
+    # every image still lands once: the totals differ only through the
+    # weights of moved images (a small relative change)
+    assert abs(k1.sum() - k0.sum()) < 0.05 * np.abs(k0).sum()
