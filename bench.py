@@ -13,7 +13,8 @@ untimed steps run first; then the initial conditions are regenerated
 region, if K exceeds it).  Per-kernel durations come from HIP events the
 library records on its own stream during the timed region.
 
-The line also carries the forward + reverse timing of the gradient
+The line also carries the same run with sub-evolution projection
+(interpolation_bench), the forward + reverse timing of the gradient
 workload (gradient_bench), the serving figures named by the metric: p50/p99
 latency (arrival to maps on the host) and throughput of Poisson streams of
 mixed-size requests, served (continuous batching) and plain (one
@@ -263,6 +264,39 @@ def serving_bench(n_requests):
     return res
 
 
+def interpolation_bench(sim, noise, a, kappa, run_steps, wl, steps):
+    """The benchmark's schedule with sub-evolution projection: every image
+    moved along its step's drift to the scale factor of its own distance."""
+    import torch
+    sim.set_interpolation(True)
+    sim.init_ic(noise, a[0])
+    kappa.zero_()
+    run_steps(2, 0)
+    sim.init_ic(noise, a[0])
+    kappa.zero_()
+    sim.sync()
+    sim.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run_steps(steps, 0)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    sim.sync()
+    prof = sim.profile_read()
+    sim.profile(False)
+    sim.set_interpolation(False)
+
+    def avg(name):
+        ms, cnt = prof.get(name, (0.0, 0))
+        return ms / max(cnt, 1)
+
+    return {"what": "the same run with sub-evolution projection",
+            "ms_per_step": 1e3 * (t1 - t0) / steps,
+            "particle_steps_per_s": wl.np_side ** 3 * steps / (t1 - t0),
+            "lens_gather_avg_ms": avg("lens_gather"),
+            "drift_momentum_max_avg_ms": avg("drift_momentum_max")}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -274,6 +308,8 @@ def main():
                     help="no per-kernel events in the timed region (roofline omitted)")
     ap.add_argument("--no-gradient", action="store_true",
                     help="skip the forward + reverse timing of the gradient workload")
+    ap.add_argument("--no-interpolation", action="store_true",
+                    help="skip the run with sub-evolution projection")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving streams (p50/p99 latency, served vs plain)")
     ap.add_argument("--serve-requests", type=int, default=100)
@@ -378,6 +414,9 @@ def main():
                            "traffic": load_traffic(dom)}
         out["hbm_effective_gbs_all_kernels"] = total_bytes / (total_ms * 1e-3) / 1e9
         out["kernels"] = kern
+    # the same schedule with sub-evolution projection (pm_set_interpolation)
+    if not args.no_interpolation:
+        out["interpolation"] = interpolation_bench(sim, noise, a, kappa, run_steps, wl, args.steps)
     if not args.no_gradient:
         out["gradient"] = gradient_bench()
     if not args.no_serving:

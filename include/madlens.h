@@ -151,6 +151,19 @@ int pm_step(pm_sim* sim, double a0, double a1);
  * Errors: PM_ESTATE, PM_EINVAL (NULL kappa). */
 int lens_project(pm_sim* sim, double a0, double a1, void* kappa);
 
+/* Sub-evolution ("interpolation" of the parameter table; the package-design
+ * section's sub-evolution step), off by default.  When on, lens_project and
+ * pm_run move every image before projecting it: the image keeps the shell of
+ * its end-of-step depth chi_e, then follows its step's own drift,
+ *   x(a) = x(a1) + (D(a) - D(a1)) / g_p(a_h) p_h,   a_h = (a0 + a1) / 2,
+ * with p_h the momentum the step drifted with, to a = a(chi_e); its angles,
+ * depth, a(chi) and weight are those of the moved image (the image may then
+ * fall behind a source plane or off the map).  lens_project then needs the
+ * state that pm_step(a0, a1) (or pm_run ending at a1) left, where
+ * p_h = p - K2 f (else PM_ESTATE); lens_project_vjp refuses it (PM_EINVAL).
+ * on: 0 or 1.  Errors: PM_EINVAL (NULL sim). */
+int pm_set_interpolation(pm_sim* sim, int32_t on);
+
 /* nsteps PM steps along the host array a_grid[0..nsteps] with the Born
  * projection of every step's shell into kappa (device [nsrc][npix][npix],
  * ACCUMULATED): the same results as pm_step(a_i, a_i+1) followed by

@@ -104,11 +104,12 @@ def shell_images(x, box, chi_near, chi_far, geom: MapGeometry):
         inz = np.nonzero((rz > chi_near) & (rz <= chi_far) & (rz > 0.0))[0]
         if inz.size == 0:
             continue
+        chi = rz[inz]   # one array for every transverse replica of this depth
         for nx in range(-kxy, kxy + 1):
             rx = x[0, inz] + nx * box - half
             for ny in range(-kxy, kxy + 1):
                 ry = x[1, inz] + ny * box - half
-                yield inz, rx, ry, rz[inz]
+                yield inz, rx, ry, chi
 
 
 def project_shell(x, a_far, a_near, cosmo: Cosmology, box, np_side,
@@ -141,22 +142,40 @@ def project_shell(x, a_far, a_near, cosmo: Cosmology, box, np_side,
     vp = (box / np_side) ** 3
     out = np.zeros((len(geom.chi_src), geom.npix, geom.npix))
     t0s, t1s, chis = [], [], []
+    # Images that cannot end in front of any source plane carry no weight in
+    # any map: they are skipped before their a(chi) (with sub-evolution the
+    # slack is the largest move along the step's drift, |Dr| |p_z|).
+    cut = [chis_ if src_cut is None else src_cut[s] for s, chis_ in enumerate(geom.chi_src)]
+    cmax = max(cut)
     if sub is not None:
         p_h, a_h = sub
         d_near, gp_h = cosmo.D(a_near), cosmo.gp(a_h)
+        dr_step = abs(cosmo.drift_factor(a_far, a_near, a_h))
+    chi_seen = None
     for inz, rx, ry, chi in shell_images(x, box, chi_near, chi_far, geom):
+        if chi is not chi_seen:   # the same depth slab for every transverse replica
+            chi_seen = chi
+            if sub is None:
+                sel = np.nonzero(chi < cmax)[0]
+                chi_f = chi[sel]
+            else:
+                sel = np.nonzero(chi - dr_step * np.abs(p_h[2, inz]) < cmax)[0]
+                isel = inz[sel]
+                dr = (cosmo.D_vec(cosmo.a_of_chi_vec(chi[sel])) - d_near) / gp_h
+                chi_f = chi[sel] + dr * p_h[2, isel]
+        if sel.size == 0:
+            continue
+        rxs, rys = rx[sel], ry[sel]
         if sub is not None:
-            dr = (cosmo.D_vec(cosmo.a_of_chi_vec(chi)) - d_near) / gp_h
-            rx = rx + dr * p_h[0, inz]
-            ry = ry + dr * p_h[1, inz]
-            chi = chi + dr * p_h[2, inz]
-        t0 = rx / chi / geom.dtheta + 0.5 * geom.npix - 0.5
-        t1 = ry / chi / geom.dtheta + 0.5 * geom.npix - 0.5
+            rxs = rxs + dr * p_h[0, isel]
+            rys = rys + dr * p_h[1, isel]
+        t0 = rxs / chi_f / geom.dtheta + 0.5 * geom.npix - 0.5
+        t1 = rys / chi_f / geom.dtheta + 0.5 * geom.npix - 0.5
         keep = ((t0 > -1.0) & (t0 < geom.npix) & (t1 > -1.0) & (t1 < geom.npix)
-                & (chi > 0.0))
+                & (chi_f > 0.0))
         t0s.append(t0[keep])
         t1s.append(t1[keep])
-        chis.append(chi[keep])
+        chis.append(chi_f[keep])
     if chis:
         t0, t1, chi = np.concatenate(t0s), np.concatenate(t1s), np.concatenate(chis)
         a = cosmo.a_of_chi_vec(chi)

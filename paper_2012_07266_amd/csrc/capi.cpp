@@ -43,7 +43,7 @@ struct Layout {
 // Offsets of every device array inside the arena.
 struct ArenaPlan {
     size_t disp[2], mom[2], id[2], acc, key, count, start, scan_sum, status;
-    size_t mesh[3], nyq[3], halo, tw_nm, tw_hm, twp_nm, tw_np, tw_hp, twp_np, g_ic, atab;
+    size_t mesh[3], nyq[3], halo, tw_nm, tw_hm, twp_nm, tw_np, tw_hp, twp_np, g_ic, atab, dtab, pmax;
     size_t xbc, fbc, dots, fmax, noise, g_ic_dom, adom;
     size_t total;
 };
@@ -84,6 +84,8 @@ ArenaPlan plan_arena(const pm_params& p, const lens_params& l, size_t es) {
     a.twp_np = L.take((np_ / 2 + 1) * 2 * es);
     a.g_ic = L.take((3 * (np_ / 2) * (np_ / 2) + 1) * es);
     a.atab = L.take(2 * ATAB_N * es);
+    a.dtab = L.take(2 * ATAB_N * es);
+    a.pmax = L.take(256);
     // reverse pass: sorted-order cotangent scratch, reductions, the noise of
     // the last initial conditions, Omega_m derivative tables
     a.xbc = L.take(3 * n * es);
@@ -201,6 +203,7 @@ struct SimBase {
     virtual int reconfigure(const pm_params* p, const lens_params* l) = 0;
     virtual int step(double a0, double a1) = 0;
     virtual int lens(double a0, double a1, void* kappa) = 0;
+    virtual int set_interpolation(int on) = 0;
     virtual int run(const double* agrid, int nsteps, void* kappa) = 0;
     virtual int get_state(void* x, void* p, double* a) = 0;
     virtual int set_state(const void* x, const void* p, double a) = 0;
@@ -232,7 +235,8 @@ template <class T> struct Sim final : SimBase {
     cx<T>* nyq[3]{};
     T* halo = nullptr;
     cx<T>*tw_nm, *tw_hm, *twp_nm, *tw_np, *tw_hp, *twp_np;
-    T *g_ic, *atab;
+    T *g_ic, *atab, *dtab;
+    uint32_t* pmax_bits = nullptr;
     T *xbc, *fbc, *noise_copy, *g_ic_dom, *adom;
     double* dots = nullptr;
     uint32_t* fmax_bits = nullptr;
@@ -242,6 +246,13 @@ template <class T> struct Sim final : SimBase {
     bool meshes_valid = false;  // mesh[0..2] hold the force meshes of the current state
     double dchi_tab = 0;
     double a_cur = -1.0;
+    // sub-evolution projection (the lens moves each image along its step's
+    // drift to the scale factor of its own distance)
+    bool interp = false;
+    // the current state is the end of the KDK step kdk_a0 -> kdk_a1, whose
+    // last kick was kdk_k2 times the force now in acc (else kdk_a1 < 0)
+    double kdk_a0 = -1.0, kdk_a1 = -1.0;
+    T kdk_k2 = T(0);
     double cell = 0;  // mesh cell, Mpc/h
     int ntiles = 0;
 
@@ -272,6 +283,7 @@ template <class T> struct Sim final : SimBase {
         }
         cell = p->box / p->nm;
         a_cur = -1.0;
+        kdk_a0 = kdk_a1 = -1.0;
         meshes_valid = false;
     }
 
@@ -316,6 +328,8 @@ template <class T> struct Sim final : SimBase {
         twp_np = at<cx<T>>(ap.twp_np);
         g_ic = at<T>(ap.g_ic);
         atab = at<T>(ap.atab);
+        dtab = at<T>(ap.dtab);
+        pmax_bits = at<uint32_t>(ap.pmax);
         xbc = at<T>(ap.xbc);
         fbc = at<T>(ap.fbc);
         dots = at<double>(ap.dots);
@@ -402,6 +416,14 @@ template <class T> struct Sim final : SimBase {
                 v[2 * k + 1] = (T)cosmo.dadchi(a0[k]);
             }
             if ((rc = upload(ap.atab, v))) return rc;
+            // D(a(chi_k)) and dD/dchi on the same grid, for sub-evolution
+            std::vector<double> dk(ATAB_N), ddk(ATAB_N);
+            cosmo.growth_grid(a0.data(), ATAB_N, dk.data(), ddk.data());
+            for (int k = 0; k < ATAB_N; ++k) {
+                v[2 * k] = (T)dk[k];
+                v[2 * k + 1] = (T)(ddk[k] * cosmo.dadchi(a0[k]));
+            }
+            if ((rc = upload(ap.dtab, v))) return rc;
             std::vector<T> w(ATAB_N);
             for (int k = 0; k < ATAB_N; ++k) w[k] = (T)((ap_[k] - am_[k]) / (2.0 * DOM));
             if ((rc = upload(ap.adom, w))) return rc;
@@ -508,6 +530,7 @@ template <class T> struct Sim final : SimBase {
         sort(T(0), T(0), 0);
         force(T(0), 0);
         a_cur = a0;
+        kdk_a0 = kdk_a1 = -1.0;
         return check_launch();
     }
 
@@ -521,19 +544,33 @@ template <class T> struct Sim final : SimBase {
         sort(k1, dr, MODE_KICK | MODE_DRIFT);
         force(k2, 1);
         a_cur = a1;
+        kdk_a0 = a0;
+        kdk_a1 = a1;
+        kdk_k2 = k2;
         return check_launch();
     }
 
     int lens(double a0, double a1, void* kappa) override {
         if (!kappa) return PM_EINVAL;
         if (a_cur < 0 || std::fabs(a1 - a_cur) > 1e-12 * std::fabs(a_cur) + 1e-15) return PM_ESTATE;
-        int rc = project_shell(a0, a1, reinterpret_cast<T*>(kappa));
+        // sub-evolution needs the drift momentum of the step a0 -> a1:
+        // p - K2 f of the state that pm_step(a0, a1) left
+        if (interp && (kdk_a1 < 0 || std::fabs(a0 - kdk_a0) > 1e-12 * std::fabs(a0) + 1e-15 ||
+                       std::fabs(a1 - kdk_a1) > 1e-12 * std::fabs(a1) + 1e-15))
+            return PM_ESTATE;
+        int rc = project_shell(a0, a1, reinterpret_cast<T*>(kappa), interp ? kdk_k2 : T(0));
         return rc ? rc : check_launch();
     }
 
+    int set_interpolation(int on) override {
+        interp = on != 0;
+        return PM_OK;
+    }
+
     // Born projection of the shell (chi(a1), chi(a0)] of the current,
-    // tile-sorted positions (which must be those at a1) into kappa.
-    int project_shell(double a0, double a1, T* kappa) {
+    // tile-sorted positions (which must be those at a1) into kappa.  With
+    // sub-evolution the step's drift momentum is mom - sub_k2 * acc.
+    int project_shell(double a0, double a1, T* kappa, T sub_k2 = T(0)) {
         LensArgs<T> la{};
         la.npix = npix;
         la.nsrc = nsrc;
@@ -558,6 +595,19 @@ template <class T> struct Sim final : SimBase {
         // 128 KB of LDS: each region's frustum is then twice as wide, and
         // the tile columns it reads hold fewer particles outside it
         la.rs = ((size_t)nsrc * 64 * 64 * 8 <= 131072 && npix >= 256) ? 64 : 32;
+        if (interp) {
+            const double ah = 0.5 * (a0 + a1);
+            la.sub = 1;
+            la.dtab = dtab;
+            la.d_end = (T)cosmo.D(a1);
+            la.sub_scale = (T)(1.0 / cosmo.gp(ah));
+            la.sub_dr = (T)cosmo.drift(a0, a1, ah);
+            la.sub_k2 = sub_k2;
+            la.pmax_bits = pmax_bits;
+            launch_fill_u32(pmax_bits, 0u, 1, st);
+            { ProfScope ps(prof, "drift_momentum_max");
+              launch_drift_momentum_max<T>(cur, geo.npart, sub_k2, pmax_bits, st); }
+        }
         MapAdd<T> mv{};
         for (int s = 0; s < nsrc; ++s) mv.v[s] = (T)cosmo.shell_mean(chi_near, chi_far, chisrc[s]);
         { ProfScope ps(prof, "lens_gather"); launch_lens_gather<T>(cur, sb, geo, la, mv, kappa, st); }
@@ -589,7 +639,7 @@ template <class T> struct Sim final : SimBase {
                 std::swap(cur.id, alt.id);
             }
             paint(true);
-            int rc = project_shell(a0, a1, kap);
+            int rc = project_shell(a0, a1, kap, T(0));  // mom is the drift momentum here
             if (rc) return rc;
             fft_forward_grad(P.nm, nullptr, tw_nm, tw_hm, twp_nm, paint_halo_merge<T>(geo, halo));
             const T k2 = (T)cosmo.kick(ah, a1, a1);
@@ -606,6 +656,9 @@ template <class T> struct Sim final : SimBase {
         }
         meshes_valid = true;
         a_cur = agrid[nsteps];
+        kdk_a0 = agrid[nsteps - 1];
+        kdk_a1 = agrid[nsteps];
+        kdk_k2 = (T)cosmo.kick(0.5 * (kdk_a0 + kdk_a1), kdk_a1, kdk_a1);
         return check_launch();
     }
 
@@ -625,6 +678,7 @@ template <class T> struct Sim final : SimBase {
         sort(T(0), T(0), 0);
         force(T(0), 0);
         a_cur = a;
+        kdk_a0 = kdk_a1 = -1.0;
         return check_launch();
     }
 
@@ -773,6 +827,7 @@ template <class T> struct Sim final : SimBase {
 
     int lens_vjp(double a0, double a1, const void* kbar, void* xbar, double* cb) override {
         if (!kbar || !xbar || !cb) return PM_EINVAL;
+        if (interp) return PM_EINVAL;  // no reverse pass for sub-evolution
         if (!at_a(a1)) return PM_ESTATE;
         LensArgs<T> la{};
         la.npix = npix;
@@ -894,6 +949,9 @@ int pm_reconfigure(pm_sim* sim, const pm_params* p, const lens_params* l) {
 int pm_step(pm_sim* sim, double a0, double a1) { return sim ? sim->impl->step(a0, a1) : PM_EINVAL; }
 int pm_run(pm_sim* sim, const double* a_grid, int32_t nsteps, void* kappa) {
     return sim ? sim->impl->run(a_grid, nsteps, kappa) : PM_EINVAL;
+}
+int pm_set_interpolation(pm_sim* sim, int32_t on) {
+    return sim ? sim->impl->set_interpolation(on) : PM_EINVAL;
 }
 int lens_project(pm_sim* sim, double a0, double a1, void* kappa) {
     return sim ? sim->impl->lens(a0, a1, kappa) : PM_EINVAL;

@@ -164,6 +164,30 @@ double HostCosmo::growth_integral(double a) const {
 
 double HostCosmo::du(double a) const { return 2.5 * om * E(a) * growth_integral(a); }
 
+void HostCosmo::growth_grid(const double* a, int n, double* d_out, double* dda_out) const {
+    if (n <= 0) return;
+    // integrand of growth_integral in t = sqrt(a)
+    auto f = [&](double t) {
+        double t2 = t * t;
+        double q = om + (1.0 - om) * t2 * t2 * t2;
+        return 2.0 * t2 * t2 / (q * std::sqrt(q));
+    };
+    const bool up = a[n - 1] >= a[0];  // index order of increasing a
+    int k = up ? 0 : n - 1;
+    const int dk = up ? 1 : -1;
+    double t_prev = std::sqrt(a[k]);
+    double integral = growth_integral(a[k]);
+    for (int i = 0; i < n; ++i, k += dk) {
+        const double t = std::sqrt(a[k]);
+        if (i > 0) integral += integrate(f, t_prev, t, 1);
+        t_prev = t;
+        const double e = E(a[k]);
+        d_out[k] = 2.5 * om * e * integral / du1;
+        const double de = -1.5 * om / (a[k] * a[k] * a[k] * a[k] * e);
+        dda_out[k] = 2.5 * om * (de * integral + 1.0 / (a[k] * a[k] * a[k] * e * e)) / du1;
+    }
+}
+
 double HostCosmo::D(double a) const { return du(a) / du1; }
 
 double HostCosmo::dDda(double a) const {

@@ -32,6 +32,9 @@ struct HostCosmo {
     // a_of_chi, far fewer distance integrals)
     void a_of_chi_grid(double dchi, int n, double* a_out) const;
     double dadchi(double a) const;          // da/dchi = -a^2 E / (c/H0)
+    // D(a_k) and dD/da(a_k) for a monotonic grid a_k (one growth integral
+    // at the smallest a, then one Gauss-Legendre panel per interval upward)
+    void growth_grid(const double* a, int n, double* d_out, double* dda_out) const;
     double D(double a) const;
     double dDda(double a) const;
     double gp(double a) const;

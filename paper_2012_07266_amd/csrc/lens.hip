@@ -12,15 +12,38 @@
 
 namespace ml {
 
+// Cubic Hermite interpolation of a table [ntab][2] of values and exact
+// slopes on the grid chi_k = k dchi.
 template <class T>
-__device__ __forceinline__ T a_of_chi(const LensArgs<T>& la, T chi) {
-    // cubic Hermite interpolation of a(chi) with exact slopes da/dchi
+__device__ __forceinline__ T chi_table(const T* tab, const LensArgs<T>& la, T chi) {
     T xk = chi / la.dchi;
     int k = (int)floor(xk);
     k = min(max(k, 0), la.ntab - 2);
     T s = xk - T(k);
-    T a0 = la.atab[2 * k], d0 = la.atab[2 * k + 1] * la.dchi;
-    T a1 = la.atab[2 * k + 2], d1 = la.atab[2 * k + 3] * la.dchi;
+    T a0 = tab[2 * k], d0 = tab[2 * k + 1] * la.dchi;
+    T a1 = tab[2 * k + 2], d1 = tab[2 * k + 3] * la.dchi;
+    T s2 = s * s, s3 = s2 * s;
+    return (T(2) * s3 - T(3) * s2 + T(1)) * a0 + (s3 - T(2) * s2 + s) * d0 +
+           (T(3) * s2 - T(2) * s3) * a1 + (s3 - s2) * d1;
+}
+
+template <class T>
+__device__ __forceinline__ T a_of_chi(const LensArgs<T>& la, T chi) {
+    return chi_table(la.atab, la, chi);
+}
+
+// chi_table from a copy of entries k_lo .. k_hi held at w[2 (k - k_lo)]
+template <class T>
+__device__ __forceinline__ T chi_window(const T* w, int k_lo, int k_hi, const LensArgs<T>& la,
+                                        T chi) {
+    T xk = chi / la.dchi;
+    int k = (int)floor(xk);
+    k = min(max(k, 0), la.ntab - 2);
+    k = min(max(k, k_lo), k_hi - 1);
+    T s = xk - T(k);
+    const T* e = w + 2 * (k - k_lo);
+    T a0 = e[0], d0 = e[1] * la.dchi;
+    T a1 = e[2], d1 = e[3] * la.dchi;
     T s2 = s * s, s3 = s2 * s;
     return (T(2) * s3 - T(3) * s2 + T(1)) * a0 + (s3 - T(2) * s2 + s) * d0 +
            (T(3) * s2 - T(2) * s3) * a1 + (s3 - s2) * d1;
@@ -109,11 +132,12 @@ constexpr int LU = 4;  // particles per thread in flight
 
 // LG threads per workgroup: 256 for 32 x 32-pixel regions, 1024 for 64 x 64
 // (one workgroup per CU then holds the LDS, so it brings 16 waves)
-template <class T, int LG>
+template <class T, int LG, bool SUB>
 __global__ __launch_bounds__(LG) void k_lens_gather(Parts<T> p, SortBufs sb, Geo g, LensArgs<T> la,
                                                     MapAdd<T> mean, T* kappa) {
     using A = LensAcc<T>;
     using S = typename A::S;
+    constexpr int LUT = sizeof(T) == 4 ? LU : LU / 2;  // registers of double
     extern __shared__ unsigned char smem[];
     S* acc = reinterpret_cast<S*>(smem);
     const int rs = la.rs;
@@ -128,6 +152,21 @@ __global__ __launch_bounds__(LG) void k_lens_gather(Parts<T> p, SortBufs sb, Geo
     const int tid = threadIdx.x;
     const int ncell = la.nsrc * rs * rs;
     for (int i = tid; i < ncell; i += LG) acc[i] = S(0);
+    // sub-evolution: the part of the D(a(chi)) table that end-of-step
+    // depths in the shell can reach (one entry of margin below, two above)
+    // is copied after the accumulator when it fits in la.dwin entries; the
+    // clamp to the window never moves an index of such a depth, so the
+    // values are those of the table itself
+    T* dw = reinterpret_cast<T*>(acc + ncell);
+    int d_lo = 0, d_hi = 0;
+    bool d_lds = false;
+    if constexpr (SUB) {
+        d_lo = min(max((int)floor(la.chi_near / la.dchi) - 1, 0), la.ntab - 2);
+        d_hi = min(max((int)floor(la.chi_far / la.dchi) + 2, d_lo + 1), la.ntab - 1);
+        d_lds = d_hi - d_lo + 1 <= la.dwin;
+        if (d_lds)
+            for (int i = tid; i < 2 * (d_hi - d_lo + 1); i += LG) dw[i] = la.dtab[2 * d_lo + i];
+    }
     __syncthreads();
 
     const long n = g.npart;
@@ -142,7 +181,11 @@ __global__ __launch_bounds__(LG) void k_lens_gather(Parts<T> p, SortBufs sb, Geo
     // angular window of images touching the region: t in [p0 - 1, p0 + rs)
     const T a0lo = (T(p0x - 1) - hp) * dth, a0hi = (T(p0x + rs) - hp) * dth;
     const T a1lo = (T(p0y - 1) - hp) * dth, a1hi = (T(p0y + rs) - hp) * dth;
-    const T margin = T(1);  // cells of slack on every bound
+    // cells of slack on every bound; with sub-evolution also the largest
+    // move of an image (the step's drift factor times max |p_h|), capped at
+    // one box so that the replica ranges stay bounded whatever the momenta
+    T margin = T(1);
+    if constexpr (SUB) margin += min(la.sub_dr * (T)__uint_as_float(*la.pmax_bits), nmf);
     const int npix2 = la.npix * la.npix;
 
     int nz0 = (int)floor(cnear / nmf) - 1;
@@ -181,21 +224,29 @@ __global__ __launch_bounds__(LG) void k_lens_gather(Parts<T> p, SortBufs sb, Geo
                         if (tza > tzb) continue;
                         const int col = (tx * nt + ty) * g.nkz;
                         const uint32_t lo = sb.start[col + tza], hi = sb.start[col + tzb + 1];
-                        for (uint32_t base = lo; base < hi; base += LG * LU) {
-                            uint32_t idv[LU];
-                            T dv[LU][3];
+                        for (uint32_t base = lo; base < hi; base += LG * LUT) {
+                            uint32_t idv[LUT];
+                            T dv[LUT][3], pv[SUB ? LUT : 1][3];
 #pragma unroll
-                            for (int u = 0; u < LU; ++u) {
+                            for (int u = 0; u < LUT; ++u) {
                                 uint32_t k = base + u * LG + tid;
                                 if (k < hi) {
                                     idv[u] = p.id[k];
                                     dv[u][0] = p.disp[k];
                                     dv[u][1] = p.disp[n + k];
                                     dv[u][2] = p.disp[2 * n + k];
+                                    if constexpr (SUB) {
+#pragma unroll
+                                        for (int a = 0; a < 3; ++a) {
+                                            pv[u][a] = p.mom[a * n + k];
+                                            if (la.sub_k2 != T(0))
+                                                pv[u][a] -= la.sub_k2 * p.acc[a * n + k];
+                                        }
+                                    }
                                 }
                             }
 #pragma unroll
-                            for (int u = 0; u < LU; ++u) {
+                            for (int u = 0; u < LUT; ++u) {
                                 uint32_t k = base + u * LG + tid;
                                 if (k >= hi) continue;
                                 int li[3];
@@ -211,6 +262,19 @@ __global__ __launch_bounds__(LG) void k_lens_gather(Parts<T> p, SortBufs sb, Geo
                                 }
                                 T rz = uu[2] + T(nz) * nmf;
                                 if (!(rz > cnear && rz <= cfar && rz > T(0))) continue;
+                                if constexpr (SUB) {
+                                    // along the step's drift to a(chi) of the
+                                    // end-of-step depth
+                                    const T chi_e = rz * la.cell;
+                                    const T dd = ((d_lds ? chi_window(dw, d_lo, d_hi, la, chi_e)
+                                                         : chi_table(la.dtab, la, chi_e)) -
+                                                  la.d_end) *
+                                                 la.sub_scale;
+                                    uu[0] += dd * pv[u][0];
+                                    uu[1] += dd * pv[u][1];
+                                    rz += dd * pv[u][2];
+                                    if (!(rz > T(0))) continue;
+                                }
                                 T chi = rz * la.cell;
                                 if (!(chi < chi_max_src)) continue;
                                 T inv = la.inv_dtheta / rz;
@@ -244,25 +308,111 @@ __global__ __launch_bounds__(LG) void k_lens_gather(Parts<T> p, SortBufs sb, Geo
     }
 }
 
+// LDS bytes after the accumulator for the D(a(chi)) window of sub-evolution
+constexpr size_t DWIN_BYTES = 16384;
+
+template <class T, bool SUB>
+void launch_lens_gather_t(Parts<T> p, SortBufs sb, Geo g, LensArgs<T> la,
+                          const MapAdd<T>& mean, T* kappa, hipStream_t st) {
+    int nreg = (la.npix + la.rs - 1) / la.rs;
+    size_t lds = (size_t)la.nsrc * la.rs * la.rs * sizeof(typename LensAcc<T>::S);
+    constexpr size_t LDS_MAX = 163840;  // per workgroup on gfx950
+    la.dwin = 0;
+    if (SUB && lds + DWIN_BYTES <= LDS_MAX) {
+        la.dwin = (int)(DWIN_BYTES / (2 * sizeof(T)));
+        lds += DWIN_BYTES;
+    }
+    // above the default dynamic LDS limit: raised once per instantiation
+    static bool raised[2] = {false, false};
+    if (la.rs >= 64) {
+        if (!raised[1]) {
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_lens_gather<T, 1024, SUB>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_MAX);
+            raised[1] = true;
+        }
+        hipLaunchKernelGGL((k_lens_gather<T, 1024, SUB>), dim3(nreg * nreg), dim3(1024), lds, st, p,
+                           sb, g, la, mean, kappa);
+    } else {
+        if (!raised[0]) {
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_lens_gather<T, 256, SUB>),
+                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_MAX);
+            raised[0] = true;
+        }
+        hipLaunchKernelGGL((k_lens_gather<T, 256, SUB>), dim3(nreg * nreg), dim3(256), lds, st, p,
+                           sb, g, la, mean, kappa);
+    }
+}
+
+// The projection without sub-evolution is its own instantiation, free of
+// the momentum loads and the move.
 template <class T>
 void launch_lens_gather(Parts<T> p, SortBufs sb, Geo g, const LensArgs<T>& la,
                         const MapAdd<T>& mean, T* kappa, hipStream_t st) {
-    int nreg = (la.npix + la.rs - 1) / la.rs;
-    size_t lds = (size_t)la.nsrc * la.rs * la.rs * sizeof(typename LensAcc<T>::S);
-    if (la.rs >= 64) {
-        static bool lds_raised = false;  // more than the default dynamic LDS
-        if (!lds_raised) {
-            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_lens_gather<T, 1024>),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, 131072);
-            lds_raised = true;
-        }
-        hipLaunchKernelGGL((k_lens_gather<T, 1024>), dim3(nreg * nreg), dim3(1024), lds, st, p, sb, g,
-                           la, mean, kappa);
-    }
+    if (la.sub)
+        launch_lens_gather_t<T, true>(p, sb, g, la, mean, kappa, st);
     else
-        hipLaunchKernelGGL((k_lens_gather<T, 256>), dim3(nreg * nreg), dim3(256), lds, st, p, sb, g,
-                           la, mean, kappa);
+        launch_lens_gather_t<T, false>(p, sb, g, la, mean, kappa, st);
 }
+
+// Largest |mom - k2 acc| over particles and axes, for the frustum margin of
+// sub-evolution: a wave maximum, then one atomic per wave on the bits of a
+// non-negative float (whose unsigned order is the float order), rounded up.
+template <class T>
+__global__ __launch_bounds__(256) void k_drift_momentum_max(Parts<T> p, long n3, T k2,
+                                                            uint32_t* out) {
+    // 16 bytes a load, RU loads in flight per thread
+    constexpr int VW = 16 / (int)sizeof(T), RU = 4;
+    using V = T __attribute__((ext_vector_type(16 / sizeof(T))));
+    float m = 0.0f;
+    const long nv = n3 / VW;  // whole vectors (the arrays are 256-byte aligned)
+    for (long base = (long)blockIdx.x * 256 * RU; base < nv; base += (long)gridDim.x * 256 * RU) {
+        V v[RU], f[RU];
+#pragma unroll
+        for (int r = 0; r < RU; ++r) {
+            long i = base + r * 256 + threadIdx.x;
+            i = i < nv ? i : nv - 1;   // a repeat, harmless for a maximum
+            v[r] = reinterpret_cast<const V*>(p.mom)[i];
+            if (k2 != T(0)) f[r] = reinterpret_cast<const V*>(p.acc)[i];
+        }
+#pragma unroll
+        for (int r = 0; r < RU; ++r)
+#pragma unroll
+            for (int e = 0; e < VW; ++e) {
+                T x = v[r][e];
+                if (k2 != T(0)) x -= k2 * f[r][e];
+                m = fmaxf(m, (float)fabs(x));
+            }
+    }
+    for (long i = nv * VW + (long)blockIdx.x * 256 + threadIdx.x; i < n3;
+         i += (long)gridDim.x * 256) {  // the tail
+        T x = p.mom[i];
+        if (k2 != T(0)) x -= k2 * p.acc[i];
+        m = fmaxf(m, (float)fabs(x));
+    }
+    // workgroup maximum, then one atomic per workgroup (atomics on one
+    // address serialize in its L2 channel)
+    __shared__ float wmax[4];
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    if ((threadIdx.x & 63) == 0) wmax[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        m = fmaxf(fmaxf(wmax[0], wmax[1]), fmaxf(wmax[2], wmax[3]));
+        atomicMax(out, __float_as_uint(m * 1.00001f));
+    }
+}
+
+template <class T>
+void launch_drift_momentum_max(Parts<T> p, long n, T k2, uint32_t* out, hipStream_t st) {
+    constexpr int VW = 16 / (int)sizeof(T);
+    long blocks = (3 * n / VW + 256 * 4 - 1) / (256 * 4);
+    if (blocks > 1024) blocks = 1024;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_drift_momentum_max<T>, dim3(blocks), dim3(256), 0, st, p, 3 * n, k2, out);
+}
+
+template void launch_drift_momentum_max<float>(Parts<float>, long, float, uint32_t*, hipStream_t);
+template void launch_drift_momentum_max<double>(Parts<double>, long, double, uint32_t*,
+                                                hipStream_t);
 
 template void launch_lens_gather<float>(Parts<float>, SortBufs, Geo, const LensArgs<float>&,
                                         const MapAdd<float>&, float*, hipStream_t);

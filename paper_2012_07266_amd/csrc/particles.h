@@ -146,6 +146,17 @@ template <class T> struct LensArgs {
     int ntab;
     T dchi;
     int rs;             // region side (pixels) of the gather projection
+    // sub-evolution (sub != 0): an image keeps the shell of its end-of-step
+    // depth and moves by (D(a(chi)) - d_end) * sub_scale * p_h, p_h = mom -
+    // sub_k2 * acc being the step's drift momentum (cells)
+    int sub;
+    const T* dtab;      // [ntab][2]: D(a(chi_k)), dD/dchi, on the atab grid
+    T d_end;            // D at the end of the step
+    T sub_scale;        // 1 / g_p(a_h)
+    T sub_k2;           // 0: mom is the drift momentum; else mom - sub_k2 acc
+    T sub_dr;           // the step's drift factor: bound of the move per |p_h|
+    const uint32_t* pmax_bits;  // max |p_h| over particles and axes (float bits)
+    int dwin;           // entries of dtab the kernel may copy to LDS (set by the launcher)
 };
 template <class T> struct MapAdd { T v[MAX_SRC]; };
 // Region-driven projection (each pixel written by one workgroup) that also
@@ -153,5 +164,9 @@ template <class T> struct MapAdd { T v[MAX_SRC]; };
 template <class T>
 void launch_lens_gather(Parts<T> p, SortBufs sb, Geo g, const LensArgs<T>& la,
                         const MapAdd<T>& mean, T* kappa, hipStream_t st);
+// *out (zeroed by the caller) = bits of max |mom - k2 acc| over all
+// particles and axes, as a float rounded up
+template <class T>
+void launch_drift_momentum_max(Parts<T> p, long n, T k2, uint32_t* out, hipStream_t st);
 
 }  // namespace ml

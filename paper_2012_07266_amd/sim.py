@@ -53,7 +53,7 @@ class Simulation:
 
     def __init__(self, np_side, nm_side, box, npix, fov_deg, z_src, *,
                  dtype=torch.float32, stream: Optional[torch.cuda.Stream] = None,
-                 **cosmo):
+                 interpolation: bool = False, **cosmo):
         self.np_side, self.nm_side, self.box = int(np_side), int(nm_side), float(box)
         self.npix, self.fov_deg, self.z_src = int(npix), float(fov_deg), tuple(z_src)
         self.dtype = dtype
@@ -67,6 +67,8 @@ class Simulation:
               "pm_create")
         self._h = h
         self.a = None
+        if interpolation:
+            self.set_interpolation(True)
 
     @property
     def n_particles(self):
@@ -122,6 +124,10 @@ class Simulation:
     def step(self, a0: float, a1: float):
         check(lib().pm_step(self._h, float(a0), float(a1)), "pm_step")
         self.a = float(a1)
+
+    def set_interpolation(self, on: bool):
+        """Sub-evolution projection on or off (pm_set_interpolation)."""
+        check(lib().pm_set_interpolation(self._h, int(bool(on))), "pm_set_interpolation")
 
     def lens(self, a0: float, a1: float, kappa: torch.Tensor):
         check(lib().lens_project(self._h, float(a0), float(a1), _ptr(kappa)), "lens_project")
