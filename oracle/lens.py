@@ -222,12 +222,15 @@ def shell_mean_adaptive(cosmo: Cosmology, chi_near, chi_far, chi_s):
 
 
 def run_lensing(noise, cosmo: Cosmology, box, nm_side, a_grid, geom: MapGeometry,
-                states=None, interpolation=False):
+                states=None, interpolation=False, pgd=None):
     """Full forward model: PM run plus the projection after every step.
 
     Returns (kappa, x_final, p_final).  If `states` is a list, the state
     after each step is appended to it.  `interpolation` projects with
-    sub-evolution (project_shell's `sub`).
+    sub-evolution (project_shell's `sub`).  `pgd` = (alpha0, mu, k_l, k_s)
+    projects the positions corrected by the PGD displacement at the step's
+    end, alpha = alpha0 a^mu (pm.pgd_displacement); the run itself goes on
+    from the uncorrected state.
     """
     from . import pm
     np_side = noise.shape[0]
@@ -236,7 +239,12 @@ def run_lensing(noise, cosmo: Cosmology, box, nm_side, a_grid, geom: MapGeometry
     def cb(i, x, p, p_h):
         a0, a1 = a_grid[i], a_grid[i + 1]
         sub = (p_h, 0.5 * (a0 + a1)) if interpolation else None
-        kappa[...] += project_shell(x, a0, a1, cosmo, box, np_side, geom, sub=sub)
+        xp = x
+        if pgd is not None:
+            alpha0, mu, k_l, k_s = pgd
+            xp = np.mod(x + pm.pgd_displacement(x, np_side, nm_side, box,
+                                                alpha0 * a1 ** mu, k_l, k_s), box)
+        kappa[...] += project_shell(xp, a0, a1, cosmo, box, np_side, geom, sub=sub)
         if states is not None:
             states.append((x.copy(), p.copy()))
 

@@ -23,7 +23,8 @@ form force of one plane wave; CIC mass conservation, on-node deposit and
 exact uniformity of the unperturbed lattice; the paint/readout adjoint
 identity; momentum conservation; linear growth of one mode; time
 reversibility of the KDK step; the IC spectral identity -i k.s = delta and
-the closed-form displacement of a single mode.
+the closed-form displacement of a single mode.  The PGD correction
+(pgd_displacement) is pinned in tests/test_oracle_pgd.py.
 """
 from __future__ import annotations
 
@@ -180,6 +181,38 @@ def particle_force(x, np_side, nm_side, box):
     rho = density(x, np_side, nm_side, box)
     f = force_mesh(rho, box)
     return np.stack([cic_readout(x, f[j], box) for j in range(3)])
+
+
+# ---------------------------------------------------------------------------
+# PGD correction (the package-design section's first technique)
+# ---------------------------------------------------------------------------
+def pgd_filter(k, k_l, k_s):
+    """O_l(k) O_s(k) = exp(-k_l^2 / k^2) exp(-(k / k_s)^4), zero at k = 0.
+
+    The paper names the technique and its parameters (k_l, k_s, alpha0, mu)
+    and defers the operator to its PGD reference; this is that operator as
+    read here: a high-pass O_l removing the scales that the PM solver gets
+    right and a low-pass O_s removing the noise below the mesh scale.
+    """
+    k = np.asarray(k, dtype=np.float64)
+    ks = np.where(k > 0.0, k, 1.0)
+    return np.where(k > 0.0, np.exp(-(k_l / ks) ** 2) * np.exp(-(ks / k_s) ** 4), 0.0)
+
+
+def pgd_displacement(x, np_side, nm_side, box, alpha, k_l, k_s):
+    """S = alpha R(x, IFFT(O_l O_s i k delta_hat / k^2)), [3][N] in Mpc/h.
+
+    The filtered gradient of the potential of the particles' own CIC density
+    (the force of force_mesh with the PGD filter), read out at the particles
+    with CIC and scaled by alpha = alpha0 a^mu (the caller's).
+    """
+    rho = density(x, np_side, nm_side, box)
+    d_hat = scipy.fft.rfftn(rho - 1.0, workers=FFT_WORKERS)
+    k0, k1, k2, *_ = wavenumbers(nm_side, box)
+    o = pgd_filter(np.sqrt(k0 ** 2 + k1 ** 2 + k2 ** 2), k_l, k_s)
+    comps = gradient_inverse_laplacian(d_hat * o, nm_side, box)
+    f = [scipy.fft.irfftn(c, s=(nm_side,) * 3, workers=FFT_WORKERS) for c in comps]
+    return alpha * np.stack([cic_readout(x, f[j], box) for j in range(3)])
 
 
 # ---------------------------------------------------------------------------
