@@ -13,8 +13,8 @@ untimed steps run first; then the initial conditions are regenerated
 region, if K exceeds it).  Per-kernel durations come from HIP events the
 library records on its own stream during the timed region.
 
-The line also carries the same run with sub-evolution projection
-(interpolation_bench), the forward + reverse timing of the gradient
+The line also carries the same run with sub-evolution projection and with
+the PGD correction (mode_bench), the forward + reverse timing of the gradient
 workload (gradient_bench), the serving figures named by the metric: p50/p99
 latency (arrival to maps on the host) and throughput of Poisson streams of
 mixed-size requests, served (continuous batching) and plain (one
@@ -264,11 +264,21 @@ def serving_bench(n_requests):
     return res
 
 
-def interpolation_bench(sim, noise, a, kappa, run_steps, wl, steps):
-    """The benchmark's schedule with sub-evolution projection: every image
-    moved along its step's drift to the scale factor of its own distance."""
+# alpha0, mu, k_l, k_s [h/Mpc] for timing only: a correction of about 1% of
+# the (filtered) force, shifts of order a cell at the 512^3 mesh.  The cost
+# of the lens grows with the largest shift, which widens its frustum margin.
+PGD_TIMING = (0.005, 0.5, 0.5, 5.0)
+
+
+def mode_bench(sim, noise, a, kappa, run_steps, wl, steps, mode):
+    """The benchmark's schedule with sub-evolution projection (every image
+    moved along its step's drift to the scale factor of its own distance)
+    or with the PGD correction of the projected positions."""
     import torch
-    sim.set_interpolation(True)
+    if mode == "interpolation":
+        sim.set_interpolation(True)
+    else:
+        sim.set_pgd(*PGD_TIMING)
     sim.init_ic(noise, a[0])
     kappa.zero_()
     run_steps(2, 0)
@@ -285,16 +295,23 @@ def interpolation_bench(sim, noise, a, kappa, run_steps, wl, steps):
     prof = sim.profile_read()
     sim.profile(False)
     sim.set_interpolation(False)
+    sim.set_pgd(*PGD_TIMING, on=False)
 
     def avg(name):
         ms, cnt = prof.get(name, (0.0, 0))
         return ms / max(cnt, 1)
 
-    return {"what": "the same run with sub-evolution projection",
-            "ms_per_step": 1e3 * (t1 - t0) / steps,
-            "particle_steps_per_s": wl.np_side ** 3 * steps / (t1 - t0),
-            "lens_gather_avg_ms": avg("lens_gather"),
-            "drift_momentum_max_avg_ms": avg("drift_momentum_max")}
+    out = {"ms_per_step": 1e3 * (t1 - t0) / steps,
+           "particle_steps_per_s": wl.np_side ** 3 * steps / (t1 - t0),
+           "lens_gather_avg_ms": avg("lens_gather")}
+    if mode == "interpolation":
+        out["what"] = "the same run with sub-evolution projection"
+        out["drift_momentum_max_avg_ms"] = avg("drift_momentum_max")
+    else:
+        out["what"] = ("the same run projecting PGD-corrected positions, (alpha0, mu, k_l, k_s) = "
+                       + str(PGD_TIMING))
+        out["pgd_readout_avg_ms"] = avg("pgd_readout")
+    return out
 
 
 def main():
@@ -309,7 +326,7 @@ def main():
     ap.add_argument("--no-gradient", action="store_true",
                     help="skip the forward + reverse timing of the gradient workload")
     ap.add_argument("--no-interpolation", action="store_true",
-                    help="skip the run with sub-evolution projection")
+                    help="skip the runs with sub-evolution projection and with PGD")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving streams (p50/p99 latency, served vs plain)")
     ap.add_argument("--serve-requests", type=int, default=100)
@@ -416,7 +433,9 @@ def main():
         out["kernels"] = kern
     # the same schedule with sub-evolution projection (pm_set_interpolation)
     if not args.no_interpolation:
-        out["interpolation"] = interpolation_bench(sim, noise, a, kappa, run_steps, wl, args.steps)
+        out["interpolation"] = mode_bench(sim, noise, a, kappa, run_steps, wl, args.steps,
+                                          "interpolation")
+        out["pgd"] = mode_bench(sim, noise, a, kappa, run_steps, wl, args.steps, "pgd")
     if not args.no_gradient:
         out["gradient"] = gradient_bench()
     if not args.no_serving:

@@ -164,6 +164,22 @@ int lens_project(pm_sim* sim, double a0, double a1, void* kappa);
  * on: 0 or 1.  Errors: PM_EINVAL (NULL sim). */
 int pm_set_interpolation(pm_sim* sim, int32_t on);
 
+/* PGD correction (the package-design section's first technique; the paper
+ * names its parameters k_l, k_s, alpha0, mu and defers the operator to its
+ * PGD reference), off by default.  When on, the positions that lens_project
+ * and pm_run project at the end of step a0 -> a1 are
+ *   x + S,  S = alpha0 a1^mu R(x, IFFT(O_l O_s i k delta_hat / k^2)),
+ *   O_l = exp(-k_l^2 / k^2),  O_s = exp(-(k / k_s)^4),
+ * the CIC readout at x of the force of x's own CIC density with that
+ * filter; the run itself continues from the uncorrected state.  With
+ * sub-evolution on as well, the corrected images are then moved.  Each
+ * corrected projection costs one more paint, force transform and readout.
+ * k_l, k_s in h/Mpc; alpha0 dimensionless.  lens_project_vjp refuses the
+ * mode (PM_EINVAL).  on: 0 or 1.  Errors: PM_EINVAL (NULL sim, non-finite
+ * parameter, k_l < 0 or k_s <= 0 with on = 1), PM_ENOMEM (the filter table
+ * and the displacement buffer are allocated on first use). */
+int pm_set_pgd(pm_sim* sim, int32_t on, double alpha0, double mu, double k_l, double k_s);
+
 /* nsteps PM steps along the host array a_grid[0..nsteps] with the Born
  * projection of every step's shell into kappa (device [nsrc][npix][npix],
  * ACCUMULATED): the same results as pm_step(a_i, a_i+1) followed by

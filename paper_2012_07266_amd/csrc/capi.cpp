@@ -204,6 +204,7 @@ struct SimBase {
     virtual int step(double a0, double a1) = 0;
     virtual int lens(double a0, double a1, void* kappa) = 0;
     virtual int set_interpolation(int on) = 0;
+    virtual int set_pgd(int on, double alpha0, double mu, double k_l, double k_s) = 0;
     virtual int run(const double* agrid, int nsteps, void* kappa) = 0;
     virtual int get_state(void* x, void* p, double* a) = 0;
     virtual int set_state(const void* x, const void* p, double a) = 0;
@@ -253,11 +254,21 @@ template <class T> struct Sim final : SimBase {
     // last kick was kdk_k2 times the force now in acc (else kdk_a1 < 0)
     double kdk_a0 = -1.0, kdk_a1 = -1.0;
     T kdk_k2 = T(0);
+    // PGD correction of the projected positions: S = alpha0 a^mu times the
+    // force of the density filtered by exp(-k_l^2/k^2) exp(-(k/k_s)^4)
+    bool pgd = false;
+    double pgd_alpha0 = 0, pgd_mu = 0;
+    T* pgd_g = nullptr;            // [3 (Nm/2)^2 + 1] filtered Green's function
+    T* pgd_s = nullptr;            // [3][Np^3] filtered force at the particles
+    uint32_t* pgd_bits = nullptr;  // max |pgd_s| (float bits)
     double cell = 0;  // mesh cell, Mpc/h
     int ntiles = 0;
 
     ~Sim() override {
         if (arena) (void)hipFree(arena);
+        if (pgd_g) (void)hipFree(pgd_g);
+        if (pgd_s) (void)hipFree(pgd_s);
+        if (pgd_bits) (void)hipFree(pgd_bits);
     }
 
     template <class U> U* at(size_t off) { return reinterpret_cast<U*>(arena + off); }
@@ -558,6 +569,7 @@ template <class T> struct Sim final : SimBase {
         if (interp && (kdk_a1 < 0 || std::fabs(a0 - kdk_a0) > 1e-12 * std::fabs(a0) + 1e-15 ||
                        std::fabs(a1 - kdk_a1) > 1e-12 * std::fabs(a1) + 1e-15))
             return PM_ESTATE;
+        if (pgd) pgd_shift(a1);
         int rc = project_shell(a0, a1, reinterpret_cast<T*>(kappa), interp ? kdk_k2 : T(0));
         return rc ? rc : check_launch();
     }
@@ -567,9 +579,72 @@ template <class T> struct Sim final : SimBase {
         return PM_OK;
     }
 
+    int set_pgd(int on, double alpha0, double mu, double k_l, double k_s) override {
+        if (!on) {
+            pgd = false;
+            return PM_OK;
+        }
+        if (!std::isfinite(alpha0) || !std::isfinite(mu) || !std::isfinite(k_l) ||
+            !(k_l >= 0) || !(k_s > 0))
+            return PM_EINVAL;
+        const size_t n = (size_t)geo.npart;
+        const int h = P.nm / 2;
+        const size_t ng = 3 * (size_t)h * h + 1;
+        if (!pgd_g) {
+            if (hipMalloc(&pgd_g, ng * sizeof(T)) != hipSuccess ||
+                hipMalloc(&pgd_s, 3 * n * sizeof(T)) != hipSuccess ||
+                hipMalloc(&pgd_bits, 256) != hipSuccess) {
+                (void)hipGetLastError();
+                if (pgd_g) (void)hipFree(pgd_g);
+                if (pgd_s) (void)hipFree(pgd_s);
+                if (pgd_bits) (void)hipFree(pgd_bits);
+                pgd_g = pgd_s = nullptr;
+                pgd_bits = nullptr;
+                return PM_ENOMEM;
+            }
+        }
+        // G(q) = 1 / (2 pi q Nm^2) of the Poisson solve (mesh-cell units),
+        // times the filter at k = 2 pi sqrt(q) / L
+        std::vector<T> g(ng);
+        const double gscale = 1.0 / (2.0 * PI * (double)P.nm * (double)P.nm);
+        g[0] = T(0);
+        for (size_t q = 1; q < ng; ++q) {
+            const double k = 2.0 * PI * std::sqrt((double)q) / P.box;
+            const double kq = k / k_s;
+            g[q] = (T)(gscale / (double)q * std::exp(-(k_l * k_l) / (k * k)) *
+                       std::exp(-(kq * kq) * (kq * kq)));
+        }
+        HIPCHK(hipMemcpyAsync(pgd_g, g.data(), ng * sizeof(T), hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+        pgd_alpha0 = alpha0;
+        pgd_mu = mu;
+        pgd = true;
+        return PM_OK;
+    }
+
+    // PGD: the filtered force of the current (tile-sorted) state into pgd_s
+    // (cells) and max |pgd_s| into pgd_bits; the lens adds alpha0 a^mu times
+    // it to every image.  Uses the meshes (the force meshes are no longer
+    // valid).
+    void pgd_shift(double a) {
+        paint();
+        fft_forward_grad(P.nm, pgd_g, tw_nm, tw_hm, twp_nm);
+        Parts<T> q = cur;
+        q.acc = pgd_s;
+        { ProfScope ps(prof, "pgd_readout");
+          launch_readout<T>(q, sb, geo, mesh[0], mesh[1], mesh[2], T(0), 0, status, st); }
+        (void)a;
+        Parts<T> m = cur;
+        m.mom = pgd_s;
+        launch_fill_u32(pgd_bits, 0u, 1, st);
+        launch_drift_momentum_max<T>(m, geo.npart, T(0), pgd_bits, st);
+        meshes_valid = false;
+    }
+
     // Born projection of the shell (chi(a1), chi(a0)] of the current,
     // tile-sorted positions (which must be those at a1) into kappa.  With
     // sub-evolution the step's drift momentum is mom - sub_k2 * acc.
+    // With PGD on, pgd_shift must have run for the current state.
     int project_shell(double a0, double a1, T* kappa, T sub_k2 = T(0)) {
         LensArgs<T> la{};
         la.npix = npix;
@@ -608,9 +683,15 @@ template <class T> struct Sim final : SimBase {
             { ProfScope ps(prof, "drift_momentum_max");
               launch_drift_momentum_max<T>(cur, geo.npart, sub_k2, pmax_bits, st); }
         }
+        if (pgd) {  // images shifted by alpha0 a1^mu times the filtered force
+            la.shift = pgd_s;
+            la.shift_scale = (T)(pgd_alpha0 * std::pow(a1, pgd_mu));
+            la.shift_bits = pgd_bits;
+        }
         MapAdd<T> mv{};
         for (int s = 0; s < nsrc; ++s) mv.v[s] = (T)cosmo.shell_mean(chi_near, chi_far, chisrc[s]);
-        { ProfScope ps(prof, "lens_gather"); launch_lens_gather<T>(cur, sb, geo, la, mv, kappa, st); }
+        { ProfScope ps(prof, "lens_gather");
+          launch_lens_gather<T>(cur, sb, geo, la, mv, kappa, st); }
         return PM_OK;
     }
 
@@ -638,6 +719,7 @@ template <class T> struct Sim final : SimBase {
                 std::swap(cur.mom, alt.mom);
                 std::swap(cur.id, alt.id);
             }
+            if (pgd) pgd_shift(a1);  // before the force's paint: it uses the meshes
             paint(true);
             int rc = project_shell(a0, a1, kap, T(0));  // mom is the drift momentum here
             if (rc) return rc;
@@ -827,7 +909,7 @@ template <class T> struct Sim final : SimBase {
 
     int lens_vjp(double a0, double a1, const void* kbar, void* xbar, double* cb) override {
         if (!kbar || !xbar || !cb) return PM_EINVAL;
-        if (interp) return PM_EINVAL;  // no reverse pass for sub-evolution
+        if (interp || pgd) return PM_EINVAL;  // no reverse pass for these modes
         if (!at_a(a1)) return PM_ESTATE;
         LensArgs<T> la{};
         la.npix = npix;
@@ -952,6 +1034,9 @@ int pm_run(pm_sim* sim, const double* a_grid, int32_t nsteps, void* kappa) {
 }
 int pm_set_interpolation(pm_sim* sim, int32_t on) {
     return sim ? sim->impl->set_interpolation(on) : PM_EINVAL;
+}
+int pm_set_pgd(pm_sim* sim, int32_t on, double alpha0, double mu, double k_l, double k_s) {
+    return sim ? sim->impl->set_pgd(on, alpha0, mu, k_l, k_s) : PM_EINVAL;
 }
 int lens_project(pm_sim* sim, double a0, double a1, void* kappa) {
     return sim ? sim->impl->lens(a0, a1, kappa) : PM_EINVAL;

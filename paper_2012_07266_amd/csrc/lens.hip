@@ -132,7 +132,7 @@ constexpr int LU = 4;  // particles per thread in flight
 
 // LG threads per workgroup: 256 for 32 x 32-pixel regions, 1024 for 64 x 64
 // (one workgroup per CU then holds the LDS, so it brings 16 waves)
-template <class T, int LG, bool SUB>
+template <class T, int LG, bool EXT>
 __global__ __launch_bounds__(LG) void k_lens_gather(Parts<T> p, SortBufs sb, Geo g, LensArgs<T> la,
                                                     MapAdd<T> mean, T* kappa) {
     using A = LensAcc<T>;
@@ -160,7 +160,7 @@ __global__ __launch_bounds__(LG) void k_lens_gather(Parts<T> p, SortBufs sb, Geo
     T* dw = reinterpret_cast<T*>(acc + ncell);
     int d_lo = 0, d_hi = 0;
     bool d_lds = false;
-    if constexpr (SUB) {
+    if (EXT && la.sub) {
         d_lo = min(max((int)floor(la.chi_near / la.dchi) - 1, 0), la.ntab - 2);
         d_hi = min(max((int)floor(la.chi_far / la.dchi) + 2, d_lo + 1), la.ntab - 1);
         d_lds = d_hi - d_lo + 1 <= la.dwin;
@@ -182,17 +182,27 @@ __global__ __launch_bounds__(LG) void k_lens_gather(Parts<T> p, SortBufs sb, Geo
     const T a0lo = (T(p0x - 1) - hp) * dth, a0hi = (T(p0x + rs) - hp) * dth;
     const T a1lo = (T(p0y - 1) - hp) * dth, a1hi = (T(p0y + rs) - hp) * dth;
     // cells of slack on every bound; with sub-evolution also the largest
-    // move of an image (the step's drift factor times max |p_h|), capped at
-    // one box so that the replica ranges stay bounded whatever the momenta
+    // move of an image (the step's drift factor times max |p_h|), with a
+    // shift (PGD) its largest size; each capped at one box so that the
+    // replica ranges stay bounded whatever the inputs
     T margin = T(1);
-    if constexpr (SUB) margin += min(la.sub_dr * (T)__uint_as_float(*la.pmax_bits), nmf);
+    // a shifted image can leave its replica's box by up to the shift (it is
+    // added to the wrapped position, not wrapped again)
+    T zclip = T(0);
+    if constexpr (EXT) {
+        if (la.sub) margin += min(la.sub_dr * (T)__uint_as_float(*la.pmax_bits), nmf);
+        if (la.shift) {
+            zclip = min(fabs(la.shift_scale) * (T)__uint_as_float(*la.shift_bits), nmf);
+            margin += zclip;
+        }
+    }
     const int npix2 = la.npix * la.npix;
 
     int nz0 = (int)floor(cnear / nmf) - 1;
     if (nz0 < 0) nz0 = 0;
-    const int nz1 = (int)floor(cmax / nmf);
+    const int nz1 = (int)floor(cmax / nmf) + (zclip > T(0) ? 1 : 0);
     for (int nz = nz0; nz <= nz1; ++nz) {
-        T zlo = max(cnear - T(nz) * nmf, T(0)), zhi = min(cmax - T(nz) * nmf, nmf);
+        T zlo = max(cnear - T(nz) * nmf, -zclip), zhi = min(cmax - T(nz) * nmf, nmf + zclip);
         if (!(zlo < zhi)) continue;
         T ca = zlo + T(nz) * nmf, cb = zhi + T(nz) * nmf;  // depth range, cells
         T x0lo = min(a0lo * ca, a0lo * cb) - margin, x0hi = max(a0hi * ca, a0hi * cb) + margin;
@@ -226,7 +236,7 @@ __global__ __launch_bounds__(LG) void k_lens_gather(Parts<T> p, SortBufs sb, Geo
                         const uint32_t lo = sb.start[col + tza], hi = sb.start[col + tzb + 1];
                         for (uint32_t base = lo; base < hi; base += LG * LUT) {
                             uint32_t idv[LUT];
-                            T dv[LUT][3], pv[SUB ? LUT : 1][3];
+                            T dv[LUT][3], pv[EXT ? LUT : 1][3], sv[EXT ? LUT : 1][3];
 #pragma unroll
                             for (int u = 0; u < LUT; ++u) {
                                 uint32_t k = base + u * LG + tid;
@@ -235,12 +245,19 @@ __global__ __launch_bounds__(LG) void k_lens_gather(Parts<T> p, SortBufs sb, Geo
                                     dv[u][0] = p.disp[k];
                                     dv[u][1] = p.disp[n + k];
                                     dv[u][2] = p.disp[2 * n + k];
-                                    if constexpr (SUB) {
+                                    if constexpr (EXT) {
+                                        if (la.sub) {
 #pragma unroll
-                                        for (int a = 0; a < 3; ++a) {
-                                            pv[u][a] = p.mom[a * n + k];
-                                            if (la.sub_k2 != T(0))
-                                                pv[u][a] -= la.sub_k2 * p.acc[a * n + k];
+                                            for (int a = 0; a < 3; ++a) {
+                                                pv[u][a] = p.mom[a * n + k];
+                                                if (la.sub_k2 != T(0))
+                                                    pv[u][a] -= la.sub_k2 * p.acc[a * n + k];
+                                            }
+                                        }
+                                        if (la.shift) {
+#pragma unroll
+                                            for (int a = 0; a < 3; ++a)
+                                                sv[u][a] = la.shift[a * n + k];
                                         }
                                     }
                                 }
@@ -260,9 +277,16 @@ __global__ __launch_bounds__(LG) void k_lens_gather(Parts<T> p, SortBufs sb, Geo
                                     if ((unsigned)c >= (unsigned)nm) c = pmod(c, nm);
                                     uu[a] = T(c) + (v - fl);
                                 }
+                                if constexpr (EXT) {
+                                    if (la.shift) {  // PGD: on the wrapped position
+#pragma unroll
+                                        for (int a = 0; a < 3; ++a)
+                                            uu[a] += la.shift_scale * sv[u][a];
+                                    }
+                                }
                                 T rz = uu[2] + T(nz) * nmf;
                                 if (!(rz > cnear && rz <= cfar && rz > T(0))) continue;
-                                if constexpr (SUB) {
+                                if (EXT && la.sub) {
                                     // along the step's drift to a(chi) of the
                                     // end-of-step depth
                                     const T chi_e = rz * la.cell;
@@ -311,14 +335,14 @@ __global__ __launch_bounds__(LG) void k_lens_gather(Parts<T> p, SortBufs sb, Geo
 // LDS bytes after the accumulator for the D(a(chi)) window of sub-evolution
 constexpr size_t DWIN_BYTES = 16384;
 
-template <class T, bool SUB>
+template <class T, bool EXT>
 void launch_lens_gather_t(Parts<T> p, SortBufs sb, Geo g, LensArgs<T> la,
                           const MapAdd<T>& mean, T* kappa, hipStream_t st) {
     int nreg = (la.npix + la.rs - 1) / la.rs;
     size_t lds = (size_t)la.nsrc * la.rs * la.rs * sizeof(typename LensAcc<T>::S);
     constexpr size_t LDS_MAX = 163840;  // per workgroup on gfx950
     la.dwin = 0;
-    if (SUB && lds + DWIN_BYTES <= LDS_MAX) {
+    if (EXT && la.sub && lds + DWIN_BYTES <= LDS_MAX) {
         la.dwin = (int)(DWIN_BYTES / (2 * sizeof(T)));
         lds += DWIN_BYTES;
     }
@@ -326,29 +350,29 @@ void launch_lens_gather_t(Parts<T> p, SortBufs sb, Geo g, LensArgs<T> la,
     static bool raised[2] = {false, false};
     if (la.rs >= 64) {
         if (!raised[1]) {
-            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_lens_gather<T, 1024, SUB>),
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_lens_gather<T, 1024, EXT>),
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_MAX);
             raised[1] = true;
         }
-        hipLaunchKernelGGL((k_lens_gather<T, 1024, SUB>), dim3(nreg * nreg), dim3(1024), lds, st, p,
+        hipLaunchKernelGGL((k_lens_gather<T, 1024, EXT>), dim3(nreg * nreg), dim3(1024), lds, st, p,
                            sb, g, la, mean, kappa);
     } else {
         if (!raised[0]) {
-            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_lens_gather<T, 256, SUB>),
+            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_lens_gather<T, 256, EXT>),
                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_MAX);
             raised[0] = true;
         }
-        hipLaunchKernelGGL((k_lens_gather<T, 256, SUB>), dim3(nreg * nreg), dim3(256), lds, st, p,
+        hipLaunchKernelGGL((k_lens_gather<T, 256, EXT>), dim3(nreg * nreg), dim3(256), lds, st, p,
                            sb, g, la, mean, kappa);
     }
 }
 
-// The projection without sub-evolution is its own instantiation, free of
-// the momentum loads and the move.
+// The plain projection is its own instantiation, free of the per-particle
+// loads and moves of sub-evolution and of the PGD shift.
 template <class T>
 void launch_lens_gather(Parts<T> p, SortBufs sb, Geo g, const LensArgs<T>& la,
                         const MapAdd<T>& mean, T* kappa, hipStream_t st) {
-    if (la.sub)
+    if (la.sub || la.shift)
         launch_lens_gather_t<T, true>(p, sb, g, la, mean, kappa, st);
     else
         launch_lens_gather_t<T, false>(p, sb, g, la, mean, kappa, st);

@@ -157,6 +157,12 @@ template <class T> struct LensArgs {
     T sub_dr;           // the step's drift factor: bound of the move per |p_h|
     const uint32_t* pmax_bits;  // max |p_h| over particles and axes (float bits)
     int dwin;           // entries of dtab the kernel may copy to LDS (set by the launcher)
+    // PGD: every image is shifted by shift_scale * shift[a * npart + k]
+    // (cells) from its wrapped position before anything else (NULL: none);
+    // *shift_bits holds max |shift| as float bits, for the frustum margin
+    const T* shift;
+    T shift_scale;
+    const uint32_t* shift_bits;
 };
 template <class T> struct MapAdd { T v[MAX_SRC]; };
 // Region-driven projection (each pixel written by one workgroup) that also
@@ -168,5 +174,6 @@ void launch_lens_gather(Parts<T> p, SortBufs sb, Geo g, const LensArgs<T>& la,
 // particles and axes, as a float rounded up
 template <class T>
 void launch_drift_momentum_max(Parts<T> p, long n, T k2, uint32_t* out, hipStream_t st);
+
 
 }  // namespace ml

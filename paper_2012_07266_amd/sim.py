@@ -53,7 +53,7 @@ class Simulation:
 
     def __init__(self, np_side, nm_side, box, npix, fov_deg, z_src, *,
                  dtype=torch.float32, stream: Optional[torch.cuda.Stream] = None,
-                 interpolation: bool = False, **cosmo):
+                 interpolation: bool = False, pgd=None, **cosmo):
         self.np_side, self.nm_side, self.box = int(np_side), int(nm_side), float(box)
         self.npix, self.fov_deg, self.z_src = int(npix), float(fov_deg), tuple(z_src)
         self.dtype = dtype
@@ -69,6 +69,8 @@ class Simulation:
         self.a = None
         if interpolation:
             self.set_interpolation(True)
+        if pgd is not None:
+            self.set_pgd(*pgd)
 
     @property
     def n_particles(self):
@@ -128,6 +130,12 @@ class Simulation:
     def set_interpolation(self, on: bool):
         """Sub-evolution projection on or off (pm_set_interpolation)."""
         check(lib().pm_set_interpolation(self._h, int(bool(on))), "pm_set_interpolation")
+
+    def set_pgd(self, alpha0: float, mu: float, k_l: float, k_s: float, on: bool = True):
+        """PGD correction of the projected positions on (with its parameters:
+        alpha = alpha0 a^mu, k_l and k_s in h/Mpc) or off (pm_set_pgd)."""
+        check(lib().pm_set_pgd(self._h, int(bool(on)), float(alpha0), float(mu), float(k_l),
+                               float(k_s)), "pm_set_pgd")
 
     def lens(self, a0: float, a1: float, kappa: torch.Tensor):
         check(lib().lens_project(self._h, float(a0), float(a1), _ptr(kappa)), "lens_project")

@@ -1,0 +1,118 @@
+"""GPU parity of the PGD correction of the projected positions (pm_set_pgd)
+against the float64 oracle: every step projects x + alpha0 a^mu times the
+filtered force of x's own density; the run goes on from x.  Float64 agrees
+to round-off; float32 within 1e-4 relative RMS of the maps."""
+import numpy as np
+import pytest
+import torch
+
+import workloads as W
+from tests.gpu_util import cosmo_of, log, new_sim, rel_rms, to_np
+
+pytestmark = pytest.mark.gpu
+
+DTYPES = [torch.float64, torch.float32]
+# alpha0, mu, k_l [h/Mpc], k_s [h/Mpc]: shifts of a few cells.  A much
+# stronger high-pass (k_l = 0.3 here) leaves a filtered force that is a
+# small residual of the force, whose float32 error then flips the shell or
+# map-edge decision of a few images (rel-RMS ~1e-4 from ~6 pixels); the
+# float64 path agrees to round-off at any setting.
+PGD = (0.5, 0.5, 0.05, 1.5)
+
+
+def _tol(dtype, f64, f32):
+    return f64 if dtype == torch.float64 else f32
+
+
+def _wl(np_side, nm, box):
+    return W.Workload("pgd", np_side, nm, box, 0.3, 1.0, 5, 64, 3.0, (0.5, 1.0), seed=9)
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+@pytest.mark.parametrize("shape", [(16, 32, 40.0), (32, 32, 64.0)], ids=lambda s: f"{s[0]}p{s[1]}m")
+def test_pgd_run_matches_oracle(dtype, shape):
+    from oracle import lens
+    np_side, nm, box = shape
+    wl = _wl(np_side, nm, box)
+    log(f"pgd run {dtype} np={np_side} nm={nm}")
+    c = cosmo_of(wl)
+    noise = W.white_noise(np_side, wl.seed)
+    a = wl.a_grid()
+    with new_sim(wl, dtype) as sim:
+        sim.set_pgd(*PGD)
+        kg = to_np(sim.run(torch.from_numpy(noise), a))
+        sim.sync()
+    geom = lens.MapGeometry(wl.npix, wl.fov_deg, wl.z_src, c)
+    log("oracle runs")
+    kap, _, _ = lens.run_lensing(noise, c, box, nm, a, geom, pgd=PGD)
+    plain, _, _ = lens.run_lensing(noise, c, box, nm, a, geom)
+    e = rel_rms(kg, kap)
+    log(f"pgd {dtype} {shape}: kappa rel-rms {e:.3e} (plain vs PGD oracle {rel_rms(plain, kap):.3e})")
+    assert rel_rms(plain, kap) > 1e-3
+    assert e <= _tol(dtype, 1e-10, 1e-4)
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+def test_pgd_stepwise_equals_fused(dtype):
+    """Both paths correct the same positions with the same fixed-point paint
+    and per-particle readout: float32 maps agree bit for bit."""
+    wl = _wl(32, 64, 64.0)
+    noise = torch.from_numpy(W.white_noise(32, wl.seed))
+    a = wl.a_grid()
+    with new_sim(wl, dtype) as sim:
+        sim.set_pgd(*PGD)
+        k1 = sim.run_stepwise(noise, a).clone()
+        k2 = sim.run(noise, a)
+        sim.sync()
+        assert torch.abs(k1).max() > 0
+        if dtype == torch.float32:
+            assert torch.equal(k1, k2)
+        else:
+            assert rel_rms(to_np(k2), to_np(k1)) < 1e-12
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+def test_pgd_with_interpolation_matches_oracle(dtype):
+    from oracle import lens
+    wl = _wl(16, 32, 40.0)
+    log(f"pgd + sub-evolution run {dtype}")
+    c = cosmo_of(wl)
+    noise = W.white_noise(16, wl.seed)
+    a = wl.a_grid()
+    with new_sim(wl, dtype) as sim:
+        sim.set_pgd(*PGD)
+        sim.set_interpolation(True)
+        kg = to_np(sim.run(torch.from_numpy(noise), a))
+        sim.sync()
+    geom = lens.MapGeometry(wl.npix, wl.fov_deg, wl.z_src, c)
+    log("oracle run")
+    kap, _, _ = lens.run_lensing(noise, c, 40.0, 32, a, geom, interpolation=True, pgd=PGD)
+    e = rel_rms(kg, kap)
+    log(f"pgd + sub {dtype}: kappa rel-rms {e:.3e}")
+    assert e <= _tol(dtype, 1e-10, 1e-4)
+
+
+def test_pgd_error_paths():
+    from paper_2012_07266_amd import MadlensError
+    from paper_2012_07266_amd._lib import PM_EINVAL
+    wl = _wl(16, 32, 40.0)
+    noise = torch.from_numpy(W.white_noise(16, 3))
+    with new_sim(wl) as sim:
+        for bad in ((0.5, 0.5, -0.1, 1.0), (0.5, 0.5, 0.1, 0.0), (float("nan"), 0.5, 0.1, 1.0)):
+            with pytest.raises(MadlensError) as e:
+                sim.set_pgd(*bad)
+            assert e.value.code == PM_EINVAL
+        sim.set_pgd(*PGD)
+        kap = sim.new_maps()
+        sim.init_ic(noise, 0.3)
+        sim.step(0.3, 0.4)
+        sim.lens(0.3, 0.4, kap)
+        with pytest.raises(MadlensError) as e:
+            sim.lens_vjp(0.3, 0.4, torch.ones_like(kap),
+                         torch.zeros((3, 16 ** 3), dtype=kap.dtype, device=kap.device),
+                         np.zeros(2))
+        assert e.value.code == PM_EINVAL
+        sim.set_pgd(*PGD, on=False)
+        sim.lens(0.3, 0.4, kap)
+        sim.sync()
+        assert torch.isfinite(kap).all()
