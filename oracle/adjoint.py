@@ -139,7 +139,7 @@ def lens_vjp(x, a_far, a_near, kappa_bar, cosmo: Cosmology, box, np_side,
     vp = (box / np_side) ** 3
     xbar = np.zeros_like(x)
     c = 0.5 * geom.npix - 0.5
-    for idx, rx, ry, chi in lens.shell_images(x, box, chi_near, chi_far, geom):
+    for idx, rx, ry, chi, sym in lens.shell_images(x, box, chi_near, chi_far, geom):
         th0 = rx / chi
         th1 = ry / chi
         t0 = th0 / geom.dtheta + c
@@ -164,9 +164,10 @@ def lens_vjp(x, a_far, a_near, kappa_bar, cosmo: Cosmology, box, np_side,
             gx = w * g0 * inv
             gy = w * g1 * inv
             gz = dw * v - w * (g0 * rx[src] + g1 * ry[src]) * inv / ch
-            np.add.at(xbar[0], idx[src], gx)
-            np.add.at(xbar[1], idx[src], gy)
-            np.add.at(xbar[2], idx[src], gz)
+            # back from the image frame: image axis j is box axis perm[j]
+            perm, flips = lens.PERMS[sym // 8], sym % 8
+            for j, gj in enumerate((gx, gy, gz)):
+                np.add.at(xbar[perm[j]], idx[src], -gj if flips >> j & 1 else gj)
     return xbar
 
 

@@ -43,7 +43,10 @@ from .cosmology import Cosmology, lens_prefactor
 
 
 class MapGeometry:
-    def __init__(self, npix, fov_deg, z_src, cosmo: Cosmology):
+    def __init__(self, npix, fov_deg, z_src, cosmo: Cosmology, rotation_seed=None):
+        # rotation_seed: None for unrotated replicas, else the seed of the
+        # per-replica cube symmetry (replica_symmetry)
+        self.rotation_seed = rotation_seed
         self.npix = int(npix)
         self.fov = math.radians(float(fov_deg))
         self.dtheta = self.fov / self.npix
@@ -88,28 +91,78 @@ def bilinear_gather(t0, t1, kmap):
     return out
 
 
+# ---------------------------------------------------------------------------
+# replica rotation (the package-design section: the box is rotated before it
+# is repeated, to avoid repeated structures along the line of sight)
+# ---------------------------------------------------------------------------
+_MASK64 = (1 << 64) - 1
+# the six axis permutations in lexicographic order; symmetry s of the 48 cube
+# symmetries takes permutation s // 8 and flips image axis j when bit j of
+# s % 8 is set
+PERMS = ((0, 1, 2), (0, 2, 1), (1, 0, 2), (1, 2, 0), (2, 0, 1), (2, 1, 0))
+
+
+def _mix64(z):
+    """The 64-bit finalizer of SplitMix64 (Steele, Lea and Flood, 2014)."""
+    z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & _MASK64
+    z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & _MASK64
+    return z ^ (z >> 31)
+
+
+def replica_symmetry(nx, ny, nz, seed):
+    """Index in [0, 48) of the cube symmetry of replica (nx, ny, nz): the
+    offsets are packed as three 21-bit fields (offset by 2^20), mixed, xored
+    with the seed, mixed again, reduced modulo 48.  0 is the identity."""
+    u = (((nx + (1 << 20)) << 42) | ((ny + (1 << 20)) << 21) | (nz + (1 << 20))) & _MASK64
+    return _mix64((int(seed) & _MASK64) ^ _mix64(u)) % 48
+
+
+def apply_symmetry(v, sym, box=None):
+    """Image-frame coordinates of the vectors v ([3][N]) under symmetry sym:
+    component j is component perm[j] of v, reflected when flip j is set
+    (x -> L - x for positions, given `box`; p -> -p for vectors)."""
+    perm = PERMS[sym // 8]
+    out = np.empty_like(v)
+    for j in range(3):
+        c = v[perm[j]]
+        if (sym % 8) >> j & 1:
+            c = (box - c) if box is not None else -c
+        out[j] = c
+    return out
+
+
 def shell_images(x, box, chi_near, chi_far, geom: MapGeometry):
     """All replica images of particles x ([3][N], in [0,L)) in the shell.
 
-    Yields (particle index, r0, r1, chi) arrays for every image with
-    chi_near < chi <= chi_far and chi > 0; transverse offsets are scanned
-    over a range that covers the map plus two pixels at chi_far.
+    Yields (particle index, r0, r1, chi, sym) arrays for every image with
+    chi_near < chi <= chi_far and chi > 0, sym being the replica's cube
+    symmetry (0 without rotation); transverse offsets are scanned over a
+    range that covers the map plus two pixels at chi_far.  The same chi
+    array is yielded for every transverse replica of a depth that shares a
+    symmetry.
     """
     half = 0.5 * box
     kxy = int(math.ceil((chi_far * (0.5 * geom.fov + 2 * geom.dtheta) + box) / box)) + 1
     nz_lo = int(math.floor(chi_near / box)) - 1
     nz_hi = int(math.floor(chi_far / box)) + 1
+    seed = geom.rotation_seed
+    rotated = {}   # symmetry -> positions in the image frame
     for nz in range(nz_lo, nz_hi + 1):
-        rz = x[2] + nz * box
-        inz = np.nonzero((rz > chi_near) & (rz <= chi_far) & (rz > 0.0))[0]
-        if inz.size == 0:
-            continue
-        chi = rz[inz]   # one array for every transverse replica of this depth
+        slabs = {}
         for nx in range(-kxy, kxy + 1):
-            rx = x[0, inz] + nx * box - half
             for ny in range(-kxy, kxy + 1):
-                ry = x[1, inz] + ny * box - half
-                yield inz, rx, ry, chi
+                sym = 0 if seed is None else replica_symmetry(nx, ny, nz, seed)
+                if sym not in slabs:
+                    if sym not in rotated:
+                        rotated[sym] = x if sym == 0 else apply_symmetry(x, sym, box)
+                    xr = rotated[sym]
+                    rz = xr[2] + nz * box
+                    inz = np.nonzero((rz > chi_near) & (rz <= chi_far) & (rz > 0.0))[0]
+                    slabs[sym] = (inz, rz[inz], xr)
+                inz, chi, xr = slabs[sym]
+                if inz.size == 0:
+                    continue
+                yield inz, xr[0, inz] + nx * box - half, xr[1, inz] + ny * box - half, chi, sym
 
 
 def project_shell(x, a_far, a_near, cosmo: Cosmology, box, np_side,
@@ -152,23 +205,27 @@ def project_shell(x, a_far, a_near, cosmo: Cosmology, box, np_side,
         d_near, gp_h = cosmo.D(a_near), cosmo.gp(a_h)
         dr_step = abs(cosmo.drift_factor(a_far, a_near, a_h))
     chi_seen = None
-    for inz, rx, ry, chi in shell_images(x, box, chi_near, chi_far, geom):
+    p_rot = {}   # symmetry -> drift momenta in the image frame
+    for inz, rx, ry, chi, sym in shell_images(x, box, chi_near, chi_far, geom):
         if chi is not chi_seen:   # the same depth slab for every transverse replica
             chi_seen = chi
             if sub is None:
                 sel = np.nonzero(chi < cmax)[0]
                 chi_f = chi[sel]
             else:
-                sel = np.nonzero(chi - dr_step * np.abs(p_h[2, inz]) < cmax)[0]
+                if sym not in p_rot:
+                    p_rot[sym] = p_h if sym == 0 else apply_symmetry(p_h, sym)
+                ph = p_rot[sym]
+                sel = np.nonzero(chi - dr_step * np.abs(ph[2, inz]) < cmax)[0]
                 isel = inz[sel]
                 dr = (cosmo.D_vec(cosmo.a_of_chi_vec(chi[sel])) - d_near) / gp_h
-                chi_f = chi[sel] + dr * p_h[2, isel]
+                chi_f = chi[sel] + dr * ph[2, isel]
         if sel.size == 0:
             continue
         rxs, rys = rx[sel], ry[sel]
         if sub is not None:
-            rxs = rxs + dr * p_h[0, isel]
-            rys = rys + dr * p_h[1, isel]
+            rxs = rxs + dr * ph[0, isel]
+            rys = rys + dr * ph[1, isel]
         t0 = rxs / chi_f / geom.dtheta + 0.5 * geom.npix - 0.5
         t1 = rys / chi_f / geom.dtheta + 0.5 * geom.npix - 0.5
         keep = ((t0 > -1.0) & (t0 < geom.npix) & (t1 > -1.0) & (t1 < geom.npix)
