@@ -13,8 +13,8 @@ untimed steps run first; then the initial conditions are regenerated
 region, if K exceeds it).  Per-kernel durations come from HIP events the
 library records on its own stream during the timed region.
 
-The line also carries the same run with sub-evolution projection and with
-the PGD correction (mode_bench), the forward + reverse timing of the gradient
+The line also carries the same run with sub-evolution projection, with
+the PGD correction and with replica rotation (mode_bench), the forward + reverse timing of the gradient
 workload (gradient_bench), the serving figures named by the metric: p50/p99
 latency (arrival to maps on the host) and throughput of Poisson streams of
 mixed-size requests, served (continuous batching) and plain (one
@@ -268,6 +268,7 @@ def serving_bench(n_requests):
 # the (filtered) force, shifts of order a cell at the 512^3 mesh.  The cost
 # of the lens grows with the largest shift, which widens its frustum margin.
 PGD_TIMING = (0.005, 0.5, 0.5, 5.0)
+ROTATION_SEED = 12345
 
 
 def mode_bench(sim, noise, a, kappa, run_steps, wl, steps, mode):
@@ -277,6 +278,8 @@ def mode_bench(sim, noise, a, kappa, run_steps, wl, steps, mode):
     import torch
     if mode == "interpolation":
         sim.set_interpolation(True)
+    elif mode == "rotation":
+        sim.set_replica_rotation(ROTATION_SEED)
     else:
         sim.set_pgd(*PGD_TIMING)
     sim.init_ic(noise, a[0])
@@ -296,6 +299,7 @@ def mode_bench(sim, noise, a, kappa, run_steps, wl, steps, mode):
     sim.profile(False)
     sim.set_interpolation(False)
     sim.set_pgd(*PGD_TIMING, on=False)
+    sim.set_replica_rotation(None)
 
     def avg(name):
         ms, cnt = prof.get(name, (0.0, 0))
@@ -307,6 +311,8 @@ def mode_bench(sim, noise, a, kappa, run_steps, wl, steps, mode):
     if mode == "interpolation":
         out["what"] = "the same run with sub-evolution projection"
         out["drift_momentum_max_avg_ms"] = avg("drift_momentum_max")
+    elif mode == "rotation":
+        out["what"] = "the same run with every box replica rotated by a cube symmetry"
     else:
         out["what"] = ("the same run projecting PGD-corrected positions, (alpha0, mu, k_l, k_s) = "
                        + str(PGD_TIMING))
@@ -326,7 +332,7 @@ def main():
     ap.add_argument("--no-gradient", action="store_true",
                     help="skip the forward + reverse timing of the gradient workload")
     ap.add_argument("--no-interpolation", action="store_true",
-                    help="skip the runs with sub-evolution projection and with PGD")
+                    help="skip the runs with sub-evolution, PGD and replica rotation")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving streams (p50/p99 latency, served vs plain)")
     ap.add_argument("--serve-requests", type=int, default=100)
@@ -436,6 +442,7 @@ def main():
         out["interpolation"] = mode_bench(sim, noise, a, kappa, run_steps, wl, args.steps,
                                           "interpolation")
         out["pgd"] = mode_bench(sim, noise, a, kappa, run_steps, wl, args.steps, "pgd")
+        out["rotation"] = mode_bench(sim, noise, a, kappa, run_steps, wl, args.steps, "rotation")
     if not args.no_gradient:
         out["gradient"] = gradient_bench()
     if not args.no_serving:

@@ -180,6 +180,18 @@ int pm_set_interpolation(pm_sim* sim, int32_t on);
  * and the displacement buffer are allocated on first use). */
 int pm_set_pgd(pm_sim* sim, int32_t on, double alpha0, double mu, double k_l, double k_s);
 
+/* Replica rotation (the package-design section: the box is rotated before it
+ * is repeated, to avoid repeated structures along the line of sight), off by
+ * default.  When on, the box replica with offsets (nx, ny, nz) is the box
+ * under one of the 48 cube symmetries: index s = h % 48 of
+ *   h = mix(seed ^ mix(u)),  u = (nx + 2^20) << 42 | (ny + 2^20) << 21 | (nz + 2^20),
+ * mix being the 64-bit finalizer of SplitMix64; s takes the (s / 8)-th of
+ * the six axis permutations in lexicographic order and reflects image axis j
+ * (x -> L - x) when bit j of s % 8 is set; s = 0 is the identity.  Image
+ * axis j of a particle is box axis perm(j).  Applies to lens_project,
+ * pm_run and lens_project_vjp.  on: 0 or 1.  Errors: PM_EINVAL (NULL sim). */
+int pm_set_replica_rotation(pm_sim* sim, int32_t on, uint64_t seed);
+
 /* nsteps PM steps along the host array a_grid[0..nsteps] with the Born
  * projection of every step's shell into kappa (device [nsrc][npix][npix],
  * ACCUMULATED): the same results as pm_step(a_i, a_i+1) followed by

@@ -286,8 +286,8 @@ def run_lensing(noise, cosmo: Cosmology, box, nm_side, a_grid, geom: MapGeometry
     after each step is appended to it.  `interpolation` projects with
     sub-evolution (project_shell's `sub`).  `pgd` = (alpha0, mu, k_l, k_s)
     projects the positions corrected by the PGD displacement at the step's
-    end, alpha = alpha0 a^mu (pm.pgd_displacement); the run itself goes on
-    from the uncorrected state.
+    end, alpha = alpha0 a^mu (pm.pgd_displacement), without wrapping them
+    back into the box; the run itself goes on from the uncorrected state.
     """
     from . import pm
     np_side = noise.shape[0]
@@ -298,9 +298,10 @@ def run_lensing(noise, cosmo: Cosmology, box, nm_side, a_grid, geom: MapGeometry
         sub = (p_h, 0.5 * (a0 + a1)) if interpolation else None
         xp = x
         if pgd is not None:
+            # not wrapped back into the box: with rotated replicas, each
+            # image moves by its replica's image of the displacement
             alpha0, mu, k_l, k_s = pgd
-            xp = np.mod(x + pm.pgd_displacement(x, np_side, nm_side, box,
-                                                alpha0 * a1 ** mu, k_l, k_s), box)
+            xp = x + pm.pgd_displacement(x, np_side, nm_side, box, alpha0 * a1 ** mu, k_l, k_s)
         kappa[...] += project_shell(xp, a0, a1, cosmo, box, np_side, geom, sub=sub)
         if states is not None:
             states.append((x.copy(), p.copy()))

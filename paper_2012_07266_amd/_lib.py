@@ -62,6 +62,7 @@ SIGNATURES = {
     "lens_project": (_I, [_P, _D, _D, _P]),
     "pm_set_interpolation": (_I, [_P, ctypes.c_int32]),
     "pm_set_pgd": (_I, [_P, ctypes.c_int32, _D, _D, _D, _D]),
+    "pm_set_replica_rotation": (_I, [_P, ctypes.c_int32, ctypes.c_uint64]),
     "pm_get_state": (_I, [_P, _P, _P, ctypes.POINTER(_D)]),
     "pm_set_state": (_I, [_P, _P, _P, _D]),
     "pm_get_force": (_I, [_P, _P, _P, _P]),

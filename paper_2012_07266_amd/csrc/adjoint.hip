@@ -302,6 +302,53 @@ __device__ __forceinline__ void bilinear_grad(const T* km, int npix, T t0, T t1,
     }
 }
 
+// Position cotangent (in the image frame) and Omega_m term of one image at
+// (rx, ry, rz) cells from the observer, rz in the shell and chi = rz cell.
+template <class T>
+__device__ __forceinline__ void lens_vjp_image(const LensArgs<T>& la, const LensVjpArgs<T>& lv,
+                                               const T* kbar, long npix2, T rx, T ry, T rz, T chi,
+                                               T a, T dadchi, T dadom, T hp, T dth, T& gx,
+                                               T& gy, T& gz, double& om_acc) {
+    const T inv = la.inv_dtheta / rz;
+    const T t0 = rx * inv + hp, t1 = ry * inv + hp;
+    if (!(t0 > T(-1) && t0 < T(la.npix) && t1 > T(-1) && t1 < T(la.npix))) return;
+    const T rxp = rx * la.cell, ryp = ry * la.cell;  // Mpc/h
+    const T invp = T(1) / (chi * dth);
+    for (int s = 0; s < la.nsrc; ++s) {
+        T cs = la.chi_src[s];
+        if (!(chi < cs)) continue;
+        T v, g0, g1;
+        bilinear_grad(kbar + s * npix2, la.npix, t0, t1, v, g0, g1);
+        T gs = (cs - chi) / (cs * chi * a);
+        T w = la.wbase * gs;
+        T dg = -T(1) / (cs * chi * a) - gs / chi - gs * dadchi / a;
+        T dw = la.wbase * dg;
+        gx += w * g0 * invp;
+        gy += w * g1 * invp;
+        gz += dw * v - w * (g0 * rxp + g1 * ryp) * invp / chi;
+        T dwdom = w / lv.omega_m + la.wbase * (lv.dchis_dom[s] / (cs * cs * a) - gs * dadom / a);
+        om_acc += (double)dwdom * (double)v;
+    }
+}
+
+// Cube symmetries of the replicas (the hash and tables of the projection).
+__device__ __forceinline__ unsigned long long vjp_mix64(unsigned long long z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+__device__ __forceinline__ int vjp_replica_symmetry(int nx, int ny, int nz, unsigned long long seed) {
+    const unsigned long long u = ((unsigned long long)(nx + (1 << 20)) << 42) |
+                                 ((unsigned long long)(ny + (1 << 20)) << 21) |
+                                 (unsigned long long)(nz + (1 << 20));
+    return (int)(vjp_mix64(seed ^ vjp_mix64(u)) % 48ull);
+}
+__device__ __forceinline__ int vjp_sym_axis(int s, int j) {
+    const int p = s >> 3, f = p >> 1;
+    const int r0 = f == 0 ? 1 : 0, r1 = f == 2 ? 1 : 2;
+    return j == 0 ? f : (j == 1 ? ((p & 1) ? r1 : r0) : ((p & 1) ? r0 : r1));
+}
+
 template <class T>
 __global__ __launch_bounds__(256) void k_lens_vjp(Parts<T> p, Geo g, LensArgs<T> la, LensVjpArgs<T> lv,
                                                   const T* kbar, T* xbar, double* dots) {
@@ -330,6 +377,49 @@ __global__ __launch_bounds__(256) void k_lens_vjp(Parts<T> p, Geo g, LensArgs<T>
         }
         if (!(isfinite(u[0]) && isfinite(u[1]) && isfinite(u[2]))) continue;
         T gx = 0, gy = 0, gz = 0;
+        if (la.rot) {
+            // every replica whose box can reach the shell and the map: an
+            // image's depth in replica nz lies in [nz Nm, (nz + 1) Nm]
+            const int mz0 = max((int)floor(cnear / nmf), 0), mz1 = (int)floor(cfar / nmf);
+            for (int nz = mz0; nz <= mz1; ++nz) {
+                const T rz_hi = min(T(nz + 1) * nmf, cfar);
+                const T rmax = tmax * rz_hi / la.inv_dtheta;
+                const int mx0 = (int)floor((-rmax + half) / nmf) - 1;
+                const int mx1 = (int)floor((rmax + half) / nmf);
+                for (int nx = mx0; nx <= mx1; ++nx)
+                    for (int ny = mx0; ny <= mx1; ++ny) {
+                        const int sym = vjp_replica_symmetry(nx, ny, nz, la.rot_seed);
+                        T ui[3];
+#pragma unroll
+                        for (int j = 0; j < 3; ++j) {
+                            const int ax = vjp_sym_axis(sym, j);
+                            T c = ax == 0 ? u[0] : (ax == 1 ? u[1] : u[2]);
+                            ui[j] = ((sym >> j) & 1) ? nmf - c : c;
+                        }
+                        const T rz = ui[2] + T(nz) * nmf;
+                        if (!(rz > cnear && rz <= cfar && rz > T(0))) continue;
+                        const T chi = rz * la.cell;
+                        if (chi >= chi_max_src) continue;
+                        T a, dadchi;
+                        a_interp(la, chi, a, dadchi);
+                        T hx = 0, hy = 0, hz = 0;
+                        lens_vjp_image(la, lv, kbar, npix2, ui[0] + T(nx) * nmf - half,
+                                       ui[1] + T(ny) * nmf - half, rz, chi, a, dadchi,
+                                       lv.dadom_at(chi), hp, dth, hx, hy, hz, om_acc);
+                        // back to the box frame: image axis j is box axis
+                        // vjp_sym_axis(sym, j), reflected when flip j is set
+#pragma unroll
+                        for (int j = 0; j < 3; ++j) {
+                            T v = j == 0 ? hx : (j == 1 ? hy : hz);
+                            if ((sym >> j) & 1) v = -v;
+                            const int ax = vjp_sym_axis(sym, j);
+                            gx += ax == 0 ? v : T(0);
+                            gy += ax == 1 ? v : T(0);
+                            gz += ax == 2 ? v : T(0);
+                        }
+                    }
+            }
+        } else {
         int nz0 = (int)floor((cnear - u[2]) / nmf);
         int nz1 = (int)floor((cfar - u[2]) / nmf) + 1;
         for (int nz = nz0; nz <= nz1; ++nz) {
@@ -372,6 +462,7 @@ __global__ __launch_bounds__(256) void k_lens_vjp(Parts<T> p, Geo g, LensArgs<T>
                     }
                 }
             }
+        }
         }
         if (gx != T(0) || gy != T(0) || gz != T(0)) {
             long L = lattice_index(id, g.np);

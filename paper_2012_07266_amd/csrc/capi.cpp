@@ -204,6 +204,7 @@ struct SimBase {
     virtual int step(double a0, double a1) = 0;
     virtual int lens(double a0, double a1, void* kappa) = 0;
     virtual int set_interpolation(int on) = 0;
+    virtual int set_replica_rotation(int on, uint64_t seed) = 0;
     virtual int set_pgd(int on, double alpha0, double mu, double k_l, double k_s) = 0;
     virtual int run(const double* agrid, int nsteps, void* kappa) = 0;
     virtual int get_state(void* x, void* p, double* a) = 0;
@@ -256,6 +257,10 @@ template <class T> struct Sim final : SimBase {
     T kdk_k2 = T(0);
     // PGD correction of the projected positions: S = alpha0 a^mu times the
     // force of the density filtered by exp(-k_l^2/k^2) exp(-(k/k_s)^4)
+    // replica rotation: replica (nx, ny, nz) is the box under one of the 48
+    // cube symmetries, hashed from its offsets and rot_seed
+    bool rot = false;
+    uint64_t rot_seed = 0;
     bool pgd = false;
     double pgd_alpha0 = 0, pgd_mu = 0;
     T* pgd_g = nullptr;            // [3 (Nm/2)^2 + 1] filtered Green's function
@@ -579,6 +584,12 @@ template <class T> struct Sim final : SimBase {
         return PM_OK;
     }
 
+    int set_replica_rotation(int on, uint64_t seed) override {
+        rot = on != 0;
+        rot_seed = seed;
+        return PM_OK;
+    }
+
     int set_pgd(int on, double alpha0, double mu, double k_l, double k_s) override {
         if (!on) {
             pgd = false;
@@ -670,6 +681,8 @@ template <class T> struct Sim final : SimBase {
         // 128 KB of LDS: each region's frustum is then twice as wide, and
         // the tile columns it reads hold fewer particles outside it
         la.rs = ((size_t)nsrc * 64 * 64 * 8 <= 131072 && npix >= 256) ? 64 : 32;
+        la.rot = rot ? 1 : 0;
+        la.rot_seed = (unsigned long long)rot_seed;
         if (interp) {
             const double ah = 0.5 * (a0 + a1);
             la.sub = 1;
@@ -931,6 +944,8 @@ template <class T> struct Sim final : SimBase {
         la.atab = atab;
         la.ntab = ATAB_N;
         la.dchi = (T)dchi_tab;
+        la.rot = rot ? 1 : 0;
+        la.rot_seed = (unsigned long long)rot_seed;
         LensVjpArgs<T> lv{};
         lv.omega_m = (T)P.omega_m;
         for (int s = 0; s < nsrc; ++s) lv.dchis_dom[s] = (T)((chisrc_p[s] - chisrc_m[s]) / (2 * DOM));
@@ -1034,6 +1049,9 @@ int pm_run(pm_sim* sim, const double* a_grid, int32_t nsteps, void* kappa) {
 }
 int pm_set_interpolation(pm_sim* sim, int32_t on) {
     return sim ? sim->impl->set_interpolation(on) : PM_EINVAL;
+}
+int pm_set_replica_rotation(pm_sim* sim, int32_t on, uint64_t seed) {
+    return sim ? sim->impl->set_replica_rotation(on, seed) : PM_EINVAL;
 }
 int pm_set_pgd(pm_sim* sim, int32_t on, double alpha0, double mu, double k_l, double k_s) {
     return sim ? sim->impl->set_pgd(on, alpha0, mu, k_l, k_s) : PM_EINVAL;

@@ -50,6 +50,48 @@ __device__ __forceinline__ T chi_window(const T* w, int k_lo, int k_hi, const Le
 }
 
 // ---------------------------------------------------------------------------
+// Replica rotation: the 64-bit finalizer of SplitMix64 (Steele, Lea and
+// Flood, 2014) hashes a replica's offsets and the seed to one of the 48 cube
+// symmetries.  Symmetry s takes axis permutation s / 8 of the six in
+// lexicographic order and reflects image axis j when bit j of s % 8 is set;
+// image axis j is box axis perm(j), x -> Nm - x when reflected.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ unsigned long long mix64(unsigned long long z) {
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ int replica_symmetry(int nx, int ny, int nz, unsigned long long seed) {
+    const unsigned long long u = ((unsigned long long)(nx + (1 << 20)) << 42) |
+                                 ((unsigned long long)(ny + (1 << 20)) << 21) |
+                                 (unsigned long long)(nz + (1 << 20));
+    return (int)(mix64(seed ^ mix64(u)) % 48ull);
+}
+
+// perm(j) of symmetry s: the permutation's first entry is (s / 8) / 2, the
+// other two follow in increasing order, swapped when (s / 8) is odd
+__device__ __forceinline__ int sym_axis(int s, int j) {
+    const int p = s >> 3, f = p >> 1;
+    const int r0 = f == 0 ? 1 : 0, r1 = f == 2 ? 1 : 2;
+    return j == 0 ? f : (j == 1 ? ((p & 1) ? r1 : r0) : ((p & 1) ? r0 : r1));
+}
+
+// v in the image frame: component j is v[perm(j)], reflected (about `refl`:
+// Nm for positions, 0 with a sign flip for vectors) when flip j is set
+template <class T>
+__device__ __forceinline__ void sym_apply(int s, T (&v)[3], T refl, bool vec) {
+    const T v0 = v[0], v1 = v[1], v2 = v[2];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        const int a = sym_axis(s, j);
+        T c = a == 0 ? v0 : (a == 1 ? v1 : v2);
+        if ((s >> j) & 1) c = vec ? -c : refl - c;
+        v[j] = c;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Region-driven projection: a workgroup owns a RS x RS pixel region of every
 // map.  For each box replica it bounds the part of the shell that projects
 // into the region (with a one-pixel margin for bilinear spill), visits the
@@ -215,22 +257,55 @@ __global__ __launch_bounds__(LG) void k_lens_gather(Parts<T> p, SortBufs sb, Geo
         int ny0 = (int)floor((x1lo + half) / nmf), ny1 = (int)floor((x1hi + half) / nmf);
         for (int nx = nx0; nx <= nx1; ++nx) {
             T bxlo = x0lo + half - T(nx) * nmf, bxhi = x0hi + half - T(nx) * nmf;  // box x, cells
-            int tx0 = max((int)floor(bxlo / T(TILE)), 0), tx1 = min((int)floor(bxhi / T(TILE)), nt - 1);
             for (int ny = ny0; ny <= ny1; ++ny) {
                 T bylo = x1lo + half - T(ny) * nmf, byhi = x1hi + half - T(ny) * nmf;
-                int ty0 = max((int)floor(bylo / T(TILE)), 0), ty1 = min((int)floor(byhi / T(TILE)), nt - 1);
+                int sym = 0;
+                if constexpr (EXT) {
+                    if (la.rot) sym = replica_symmetry(nx, ny, nz, la.rot_seed);
+                }
+                // the image-frame box [b*lo, b*hi] in box axes: the tiles and
+                // sort blocks to visit (a rotated replica is culled by this
+                // box alone; an unrotated one also per column below)
+                T lo3[3] = {bxlo, bylo, zlo - margin}, hi3[3] = {bxhi, byhi, zhi + margin};
+                if (sym) {
+                    const T l0 = lo3[0], l1 = lo3[1], l2 = lo3[2];
+                    const T h0 = hi3[0], h1 = hi3[1], h2 = hi3[2];
+#pragma unroll
+                    for (int j = 0; j < 3; ++j) {  // image axis j -> box axis sym_axis(sym, j)
+                        const T lj = j == 0 ? l0 : (j == 1 ? l1 : l2);
+                        const T hj = j == 0 ? h0 : (j == 1 ? h1 : h2);
+                        const bool fl = (sym >> j) & 1;
+                        const T a = fl ? nmf - hj : lj, b = fl ? nmf - lj : hj;
+                        const int ax = sym_axis(sym, j);
+#pragma unroll
+                        for (int q = 0; q < 3; ++q)
+                            if (q == ax) {
+                                lo3[q] = a;
+                                hi3[q] = b;
+                            }
+                    }
+                }
+                const int tx0 = max((int)floor(lo3[0] / T(TILE)), 0);
+                const int tx1 = min((int)floor(hi3[0] / T(TILE)), nt - 1);
+                const int ty0 = max((int)floor(lo3[1] / T(TILE)), 0);
+                const int ty1 = min((int)floor(hi3[1] / T(TILE)), nt - 1);
+                const int kza = sym ? max((int)floor(lo3[2] / T(KZ)), 0) : tz0;
+                const int kzb = sym ? min((int)floor(hi3[2] / T(KZ)), g.nkz - 1) : tz1;
                 for (int tx = tx0; tx <= tx1; ++tx)
                     for (int ty = ty0; ty <= ty1; ++ty) {
-                        // only the tiles of this column that the region's
-                        // pencil crosses
-                        T zmin = ca - margin, zmax = cb + margin;
-                        if (!column_depths(a0lo, a0hi, T(tx * TILE) + T(nx) * nmf - half, margin,
-                                           zmin, zmax) ||
-                            !column_depths(a1lo, a1hi, T(ty * TILE) + T(ny) * nmf - half, margin,
-                                           zmin, zmax))
-                            continue;
-                        const int tza = max(tz0, (int)floor((zmin - T(nz) * nmf) / T(KZ)));
-                        const int tzb = min(tz1, (int)floor((zmax - T(nz) * nmf) / T(KZ)));
+                        int tza = kza, tzb = kzb;
+                        if (!sym) {
+                            // only the tiles of this column that the region's
+                            // pencil crosses
+                            T zmin = ca - margin, zmax = cb + margin;
+                            if (!column_depths(a0lo, a0hi, T(tx * TILE) + T(nx) * nmf - half,
+                                               margin, zmin, zmax) ||
+                                !column_depths(a1lo, a1hi, T(ty * TILE) + T(ny) * nmf - half,
+                                               margin, zmin, zmax))
+                                continue;
+                            tza = max(tz0, (int)floor((zmin - T(nz) * nmf) / T(KZ)));
+                            tzb = min(tz1, (int)floor((zmax - T(nz) * nmf) / T(KZ)));
+                        }
                         if (tza > tzb) continue;
                         const int col = (tx * nt + ty) * g.nkz;
                         const uint32_t lo = sb.start[col + tza], hi = sb.start[col + tzb + 1];
@@ -277,11 +352,20 @@ __global__ __launch_bounds__(LG) void k_lens_gather(Parts<T> p, SortBufs sb, Geo
                                     if ((unsigned)c >= (unsigned)nm) c = pmod(c, nm);
                                     uu[a] = T(c) + (v - fl);
                                 }
+                                T pimg[3] = {T(0), T(0), T(0)};
                                 if constexpr (EXT) {
                                     if (la.shift) {  // PGD: on the wrapped position
 #pragma unroll
                                         for (int a = 0; a < 3; ++a)
                                             uu[a] += la.shift_scale * sv[u][a];
+                                    }
+                                    if (la.sub) {
+#pragma unroll
+                                        for (int a = 0; a < 3; ++a) pimg[a] = pv[u][a];
+                                    }
+                                    if (sym) {  // into the replica's frame
+                                        sym_apply(sym, uu, nmf, false);
+                                        sym_apply(sym, pimg, T(0), true);
                                     }
                                 }
                                 T rz = uu[2] + T(nz) * nmf;
@@ -294,9 +378,9 @@ __global__ __launch_bounds__(LG) void k_lens_gather(Parts<T> p, SortBufs sb, Geo
                                                          : chi_table(la.dtab, la, chi_e)) -
                                                   la.d_end) *
                                                  la.sub_scale;
-                                    uu[0] += dd * pv[u][0];
-                                    uu[1] += dd * pv[u][1];
-                                    rz += dd * pv[u][2];
+                                    uu[0] += dd * pimg[0];
+                                    uu[1] += dd * pimg[1];
+                                    rz += dd * pimg[2];
                                     if (!(rz > T(0))) continue;
                                 }
                                 T chi = rz * la.cell;
@@ -372,7 +456,7 @@ void launch_lens_gather_t(Parts<T> p, SortBufs sb, Geo g, LensArgs<T> la,
 template <class T>
 void launch_lens_gather(Parts<T> p, SortBufs sb, Geo g, const LensArgs<T>& la,
                         const MapAdd<T>& mean, T* kappa, hipStream_t st) {
-    if (la.sub || la.shift)
+    if (la.sub || la.shift || la.rot)
         launch_lens_gather_t<T, true>(p, sb, g, la, mean, kappa, st);
     else
         launch_lens_gather_t<T, false>(p, sb, g, la, mean, kappa, st);

@@ -163,6 +163,10 @@ template <class T> struct LensArgs {
     const T* shift;
     T shift_scale;
     const uint32_t* shift_bits;
+    // replica rotation (rot != 0): replica (nx, ny, nz) is the box under one
+    // of the 48 cube symmetries, hashed from its offsets and rot_seed
+    int rot;
+    unsigned long long rot_seed;
 };
 template <class T> struct MapAdd { T v[MAX_SRC]; };
 // Region-driven projection (each pixel written by one workgroup) that also

@@ -131,6 +131,14 @@ class Simulation:
         """Sub-evolution projection on or off (pm_set_interpolation)."""
         check(lib().pm_set_interpolation(self._h, int(bool(on))), "pm_set_interpolation")
 
+    def set_replica_rotation(self, seed):
+        """Rotate every box replica by a cube symmetry hashed from its offsets
+        and `seed` (an unsigned 64-bit int); None turns rotation off
+        (pm_set_replica_rotation)."""
+        on = seed is not None
+        check(lib().pm_set_replica_rotation(self._h, int(on), int(seed or 0) & (2 ** 64 - 1)),
+              "pm_set_replica_rotation")
+
     def set_pgd(self, alpha0: float, mu: float, k_l: float, k_s: float, on: bool = True):
         """PGD correction of the projected positions on (with its parameters:
         alpha = alpha0 a^mu, k_l and k_s in h/Mpc) or off (pm_set_pgd)."""
