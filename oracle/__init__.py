@@ -13,6 +13,7 @@ Modules
              CIC readout, kick-drift-kick step, full forward run
   lens       Born projection of particle images onto convergence maps
   adjoint    hand-derived vector-Jacobian products of the above
+  jvp        hand-derived Jacobian-vector products (forward-mode tangents)
 
 Parity status is stated in each module header.
 """

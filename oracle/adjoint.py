@@ -279,8 +279,10 @@ def kappa_vjp_cosmo(noise, kappa_bar, cosmo: Cosmology, box, nm_side, a_grid,
     """
     np_side = noise.shape[0]
     cp, cm = _with_om(cosmo, cosmo.omega_m + dom), _with_om(cosmo, cosmo.omega_m - dom)
-    geom_p = lens.MapGeometry(geom.npix, np.degrees(geom.fov), geom.z_src, cp)
-    geom_m = lens.MapGeometry(geom.npix, np.degrees(geom.fov), geom.z_src, cm)
+    geom_p = lens.MapGeometry(geom.npix, np.degrees(geom.fov), geom.z_src, cp,
+                              rotation_seed=geom.rotation_seed)
+    geom_m = lens.MapGeometry(geom.npix, np.degrees(geom.fov), geom.z_src, cm,
+                              rotation_seed=geom.rotation_seed)
     _, states = forward_with_checkpoints(noise, cosmo, box, nm_side, a_grid, geom)
     n = len(a_grid) - 1
 
