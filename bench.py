@@ -196,7 +196,7 @@ def gradient_bench(reps=3):
     import torch
     import workloads as W
     from paper_2012_07266_amd import Simulation
-    from paper_2012_07266_amd.autograd import forward_with_checkpoints, reverse_pass
+    from paper_2012_07266_amd.autograd import forward_with_checkpoints, jvp, reverse_pass
     wl = W.CFG3
     a = wl.a_grid()
     dev = torch.device("cuda", 0)
@@ -210,7 +210,9 @@ def gradient_bench(reps=3):
     target = target + torch.from_numpy(
         gen.normal(0.0, sigma, size=tuple(target.shape))).to(dev, torch.float32)
     noise = torch.from_numpy(W.white_noise(wl.np_side, wl.seed)).to(dev, torch.float32)
-    t_f, t_b = [], []
+    # a tangent direction: noise, Omega_m and sigma_8 together
+    n_dot = torch.from_numpy(W.white_noise(wl.np_side, 6)).to(dev, torch.float32)
+    t_f, t_b, t_p, t_j = [], [], [], []
     for r in range(reps + 1):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -222,12 +224,27 @@ def gradient_bench(reps=3):
         nb, g_om, g_s8 = reverse_pass(sim, a, states, kbar)
         torch.cuda.synchronize()
         t2 = time.perf_counter()
+        del states
+        # plain forward (no checkpoints), then forward + tangent in one pass
+        sim.run_stepwise(noise, a)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        _, kd = jvp(sim, noise, a, n_dot, 0.3, 0.2)
+        torch.cuda.synchronize()
+        t4 = time.perf_counter()
         if r > 0:  # the first pass is a warm-up
             t_f.append(t1 - t0)
             t_b.append(t2 - t1)
-        del states
+            t_p.append(t3 - t2)
+            t_j.append(t4 - t3)
+    sim.profile(True)
+    jvp(sim, noise, a, n_dot, 0.3, 0.2)
+    jk = sim.profile_read()
+    sim.profile(False)
+    jvp_finite = bool(torch.isfinite(kd).all().item())
     sim.close()
     f, b = float(np.median(t_f)), float(np.median(t_b))
+    pf, jf = float(np.median(t_p)), float(np.median(t_j))
     ps = wl.np_side ** 3 * wl.nsteps
     return {"workload": (f"{wl.name}: 128^3 particles, 256^3 mesh, 20 steps, 1 x 1024^2 map, "
                          "float32, chi^2 loss, gradients w.r.t. noise, Omega_m, sigma_8"),
@@ -235,7 +252,15 @@ def gradient_bench(reps=3):
             "forward_particle_steps_per_s": ps / f,
             "forward_plus_reverse_particle_steps_per_s": ps / (f + b),
             "grad_finite": bool(torch.isfinite(nb).all().item() and np.isfinite(g_om)
-                                and np.isfinite(g_s8))}
+                                and np.isfinite(g_s8)),
+            "plain_forward_ms": 1e3 * pf,
+            "jvp_ms": 1e3 * jf,
+            "jvp_over_forward": jf / pf,
+            "jvp_what": ("forward pass carrying the tangent along (noise, Omega_m, sigma_8); "
+                         "ratio to the plain stepwise forward without checkpoints"),
+            "jvp_kernels_ms": {k: round(v[0], 3) for k, v in jk.items()
+                               if k.startswith(("jvp", "lens_jvp"))},
+            "jvp_finite": jvp_finite}
 
 
 def serving_bench(n_requests):

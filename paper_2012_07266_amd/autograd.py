@@ -4,7 +4,9 @@ Forward: Zel'dovich initial conditions from white noise, the KDK steps and
 the lens projection of every shell, keeping (x, p) after each step as a
 checkpoint (24 bytes per particle per step in float32).  Backward: for each
 step in reverse, restore its end state (which recomputes the force there),
-reverse its shell and its step, then reverse the initial conditions.  All
+reverse its shell and its step, then reverse the initial conditions.
+Forward mode (jvp): the tangent of (x, p, f) is carried with every step and
+each shell's tangent is accumulated, in one pass without checkpoints.  All
 arithmetic runs in the library; this module only orders the calls.
 """
 from __future__ import annotations
@@ -45,6 +47,22 @@ def reverse_pass(sim: Simulation, a_grid: Sequence[float], states, kappa_bar: to
     sim.set_state(x0, p0, a_grid[0])
     noise_bar = sim.init_ic_vjp(a_grid[1], x_bar, p_bar, cb)
     return noise_bar, float(cb[0]), float(cb[1])
+
+
+def jvp(sim: Simulation, noise: torch.Tensor, a_grid: Sequence[float], noise_dot: torch.Tensor,
+        omega_m_dot: float = 0.0, sigma8_dot: float = 0.0):
+    """(kappa, kappa_dot): the maps and their directional derivative along
+    (noise_dot, Omega_m_dot, sigma8_dot), in one forward pass that carries
+    the tangent of (x, p, f) with every step (no checkpoints)."""
+    kappa = sim.new_maps()
+    kappa_dot = sim.new_maps()
+    sim.init_ic(noise, a_grid[0])
+    x_dot, p_dot, f_dot = sim.init_ic_jvp(noise_dot, omega_m_dot, sigma8_dot)
+    for i in range(len(a_grid) - 1):
+        sim.step_jvp(a_grid[i], a_grid[i + 1], x_dot, p_dot, f_dot, omega_m_dot)
+        sim.lens(a_grid[i], a_grid[i + 1], kappa)
+        sim.lens_jvp(a_grid[i], a_grid[i + 1], x_dot, kappa_dot, omega_m_dot)
+    return kappa, kappa_dot
 
 
 class _Maps(torch.autograd.Function):
@@ -95,6 +113,13 @@ class LensingModel:
     def __call__(self, noise: torch.Tensor, omega_m: torch.Tensor, sigma8: torch.Tensor):
         sim = self.sim_for(float(omega_m), float(sigma8))
         return _Maps.apply(noise, omega_m, sigma8, sim, self.a_grid)
+
+    def jvp(self, noise: torch.Tensor, omega_m: float, sigma8: float, noise_dot: torch.Tensor,
+            omega_m_dot: float = 0.0, sigma8_dot: float = 0.0):
+        """(kappa, kappa_dot) at (noise, Omega_m, sigma_8) along the tangent
+        (noise_dot, Omega_m_dot, sigma8_dot)."""
+        return jvp(self.sim_for(float(omega_m), float(sigma8)), noise, self.a_grid, noise_dot,
+                   omega_m_dot, sigma8_dot)
 
     def close(self):
         for s in self._sims.values():

@@ -53,4 +53,38 @@ template <class T>
 void launch_lens_vjp(Parts<T> p, Geo g, const LensArgs<T>& la, const LensVjpArgs<T>& lv,
                      const T* kbar, T* xbar, double* dots, hipStream_t st);
 
+// ---- forward mode (tangents) -----------------------------------------------
+// y = a y + b x over n elements (y not read when a == 0).
+template <class T>
+void launch_lin(T* y, const T* x, T a, T b, long n, hipStream_t st);
+// x_dot = H (D t + cD s), p_dot = H (gp t + cgp s), lattice order; t, s in
+// cells; t may alias x_dot.
+template <class T>
+void launch_ic_tangent(const T* t0, const T* t1, const T* t2, const T* s0, const T* s1,
+                       const T* s2, T* xd, T* pd, T D, T gp, T cD, T cgp, T H, long n,
+                       hipStream_t st);
+// Tangent of a step's first half-kick and drift at the state before it.
+template <class T>
+void launch_jvp_pre(Parts<T> p, Geo g, T* xdot, T* pdot, const T* fdot, T H, T k1, T dr, T ck1,
+                    T cdr, hipStream_t st);
+// Readout part of the force tangent on the force meshes f0..f2; position
+// tangent to xbc and a bound for the tangent paint's scale to vmax_bits.
+template <class T>
+void launch_fjvp_gather(Parts<T> p, SortBufs s, Geo g, const T* f0, const T* f1, const T* f2,
+                        const T* xdot, T invH, T mass, T* xbc, T* fbc, uint32_t* vmax_bits,
+                        hipStream_t st);
+// Paint part of the force tangent from the tangent force meshes m0..m2, the
+// second half-kick of p_dot (pdot may be NULL) and f_dot.
+template <class T>
+void launch_fjvp_readout_kick(Parts<T> p, SortBufs s, Geo g, const T* m0, const T* m1, const T* m2,
+                              const T* fbc, T H, T k2, T ck2, T* pdot, T* fdot, hipStream_t st);
+// Lens projection tangent (particle term, plus om_dot times the weights'
+// Omega_m derivative) accumulated into kdot [nsrc][npix][npix].
+template <class T>
+void launch_lens_jvp(Parts<T> p, Geo g, const LensArgs<T>& la, const LensVjpArgs<T>& lv,
+                     const T* xdot, T om_dot, T* kdot, hipStream_t st);
+// kdot[s] += mv.v[s] on every pixel.
+template <class T>
+void launch_map_add(T* kdot, int npix, int nsrc, const MapAdd<T>& mv, hipStream_t st);
+
 }  // namespace ml

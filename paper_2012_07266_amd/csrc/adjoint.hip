@@ -1,5 +1,6 @@
-// Reverse-mode (vector-Jacobian) kernels of the PM step, the initial
-// conditions and the lens projection on gfx950.
+// Derivative kernels of the PM step, the initial conditions and the lens
+// projection on gfx950: reverse mode (vector-Jacobian products) and, in
+// part 4, forward mode (Jacobian-vector products, tangents).
 //
 // Force node f = R(x, M(P(x))): P = CIC paint, M = Fourier force operator,
 // R = CIC readout.  For a cotangent fbar:
@@ -475,6 +476,297 @@ __global__ __launch_bounds__(256) void k_lens_vjp(Parts<T> p, Geo g, LensArgs<T>
 }
 
 // ---------------------------------------------------------------------------
+// 4. forward-mode tangents (Jacobian-vector products).  The caller's tangent
+//    arrays are in lattice order and Mpc/h; sorted-order scratch in cells.
+// ---------------------------------------------------------------------------
+// y = a y + b x (y is not read when a == 0)
+template <class T>
+__global__ void k_lin(T* y, const T* x, T a, T b, long n) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        y[i] = (a == T(0) ? T(0) : a * y[i]) + b * x[i];
+}
+
+// Initial-condition tangent from the displacement tangent t and the
+// displacement s (lattice order, cells): x_dot = H (D t + cD s),
+// p_dot = H (gp t + cgp s).  t may alias x_dot.
+template <class T>
+__global__ void k_ic_tangent(const T* t0, const T* t1, const T* t2, const T* s0, const T* s1,
+                             const T* s2, T* xd, T* pd, T D, T gp, T cD, T cgp, T H, long n) {
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const T t[3] = {t0[i], t1[i], t2[i]};
+        const T sv[3] = {s0[i], s1[i], s2[i]};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            xd[a * n + i] = H * (D * t[a] + cD * sv[a]);
+            pd[a * n + i] = H * (gp * t[a] + cgp * sv[a]);
+        }
+    }
+}
+
+// Tangent of the first half-kick and the drift of a step, at the state
+// before it (force f = acc at x):
+//   ph_dot = p_dot + K1 f_dot + cK1 f,   x_dot += Dr ph_dot + cDr (p + K1 f)
+// with cK1, cDr the Omega_m tangent times dK1/dOm, dDr/dOm.  In place.
+template <class T>
+__global__ void k_jvp_pre(Parts<T> p, Geo g, T* xdot, T* pdot, const T* fdot, T H, T k1, T dr,
+                          T ck1, T cdr) {
+    const long n = g.npart;
+    for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
+        const long L = lattice_index(p.id[k], g.np);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const T f = H * p.acc[a * n + k];
+            const T ph = H * p.mom[a * n + k] + k1 * f;
+            const T phd = pdot[a * n + L] + k1 * fdot[a * n + L] + ck1 * f;
+            xdot[a * n + L] += dr * phd + cdr * ph;
+            pdot[a * n + L] = phd;
+        }
+    }
+}
+
+// Readout part of the force tangent: f_dot_j = u_dot . grad R(x, M_j) on the
+// force meshes M_j of the current state, into fbc (sorted, cells); the
+// position tangent u_dot = x_dot / H into xbc (sorted, cells) for the tangent
+// paint, and max of mass sum_a |u_dot_a| into vmax_bits.
+template <class T>
+__global__ __launch_bounds__(AB) void k_fjvp_gather(Parts<T> p, SortBufs s, Geo g, const T* f0,
+                                                    const T* f1, const T* f2, const T* xdot,
+                                                    T invH, T mass, T* xbc, T* fbc,
+                                                    uint32_t* vmax_bits) {
+    constexpr int TC = TE * TE * TE;
+    __shared__ T ft[3][TC];
+    const int tid = threadIdx.x;
+    const int t = xcd_remap(blockIdx.x, gridDim.x);
+    const int tx = t / (g.nt * g.nt), ty = (t / g.nt) % g.nt, tz = t % g.nt;
+    const int ox = tx * TILE, oy = ty * TILE, oz = tz * TILE;
+    const int b0 = tile_block(g, tx, ty, tz);
+    const uint32_t lo = s.start[b0], hi = s.start[b0 + TILE / KZ];
+    if (lo == hi) return;
+    stage_tile(ft[0], f0, g.nm, ox, oy, oz, tid);
+    stage_tile(ft[1], f1, g.nm, ox, oy, oz, tid);
+    stage_tile(ft[2], f2, g.nm, ox, oy, oz, tid);
+    __syncthreads();
+    const long n = g.npart;
+    float vmax = 0.f;
+    for (uint32_t k0 = lo; k0 < hi; k0 += AB) {
+        uint32_t k = k0 + tid;
+        if (k < hi) {
+            uint32_t id = p.id[k];
+            long L = lattice_index(id, g.np);
+            T d[3] = {p.disp[k], p.disp[n + k], p.disp[2 * n + k]};
+            int base;
+            T w[3][2];
+            cic_setup(g, id, d, ox, oy, oz, base, w);
+            T ud[3];
+#pragma unroll
+            for (int a = 0; a < 3; ++a) {
+                ud[a] = invH * xdot[a * n + L];
+                xbc[a * n + k] = ud[a];
+            }
+            vmax = fmaxf(vmax, (float)(mass * (fabs(ud[0]) + fabs(ud[1]) + fabs(ud[2]))));
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                T val, gr[3];
+                cic_grad(ft[j], base, w, val, gr);
+                fbc[j * n + k] = ud[0] * gr[0] + ud[1] * gr[1] + ud[2] * gr[2];
+            }
+        }
+    }
+    for (int off = 32; off > 0; off >>= 1) vmax = fmaxf(vmax, __shfl_xor(vmax, off));
+    // a bound slightly above the maximum keeps float rounding of the bound
+    // from under-sizing the fixed-point scale
+    if ((tid & 63) == 0 && vmax > 0.f) atomicMax(vmax_bits, __float_as_uint(vmax * 1.0001f));
+}
+
+// Paint part of the force tangent and the second half-kick: with M_dot_j the
+// force meshes of the tangent density, f_dot_j = fbc_j + R(x, M_dot_j);
+// f_dot (lattice, Mpc/h) = H f_dot_j and, if pdot is set,
+// p_dot += H (K2 f_dot_j + cK2 f_j).
+template <class T>
+__global__ __launch_bounds__(AB) void k_fjvp_readout_kick(Parts<T> p, SortBufs s, Geo g, const T* m0,
+                                                          const T* m1, const T* m2, const T* fbc,
+                                                          T H, T k2, T ck2, T* pdot, T* fdot) {
+    constexpr int TC = TE * TE * TE;
+    __shared__ T ft[3][TC];
+    const int tid = threadIdx.x;
+    const int t = xcd_remap(blockIdx.x, gridDim.x);
+    const int tx = t / (g.nt * g.nt), ty = (t / g.nt) % g.nt, tz = t % g.nt;
+    const int ox = tx * TILE, oy = ty * TILE, oz = tz * TILE;
+    const int b0 = tile_block(g, tx, ty, tz);
+    const uint32_t lo = s.start[b0], hi = s.start[b0 + TILE / KZ];
+    if (lo == hi) return;
+    stage_tile(ft[0], m0, g.nm, ox, oy, oz, tid);
+    stage_tile(ft[1], m1, g.nm, ox, oy, oz, tid);
+    stage_tile(ft[2], m2, g.nm, ox, oy, oz, tid);
+    __syncthreads();
+    const long n = g.npart;
+    for (uint32_t k0 = lo; k0 < hi; k0 += AB) {
+        uint32_t k = k0 + tid;
+        if (k < hi) {
+            uint32_t id = p.id[k];
+            long L = lattice_index(id, g.np);
+            T d[3] = {p.disp[k], p.disp[n + k], p.disp[2 * n + k]};
+            int base;
+            T w[3][2];
+            cic_setup(g, id, d, ox, oy, oz, base, w);
+#pragma unroll
+            for (int j = 0; j < 3; ++j) {
+                T val = T(0);
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b)
+#pragma unroll
+                        for (int c = 0; c < 2; ++c)
+                            val += w[0][a] * w[1][b] * w[2][c] * ft[j][base + (a * TE + b) * TE + c];
+                const T fd = fbc[j * n + k] + val;
+                fdot[j * n + L] = H * fd;
+                if (pdot) pdot[j * n + L] += H * (k2 * fd + ck2 * p.acc[j * n + k]);
+            }
+        }
+    }
+}
+
+// Tangent of one image's splat: kappa_dot_s += (dw/dchi z_dot + Om_dot
+// dw/dOm) B + w (dB/dt0 t0_dot + dB/dt1 t1_dot), t_dot = (r_perp_dot -
+// r_perp z_dot / chi) / (chi dtheta), (x_dot, y_dot, z_dot) the position
+// tangent in the image frame (Mpc/h).
+template <class T>
+__device__ __forceinline__ void lens_jvp_image(const LensArgs<T>& la, const LensVjpArgs<T>& lv,
+                                               T* kdot, long npix2, T rx, T ry, T rz, T chi, T a,
+                                               T dadchi, T dadom, T hp, T dth, T xd, T yd, T zd,
+                                               T om_dot) {
+    const T inv = la.inv_dtheta / rz;
+    const T t0 = rx * inv + hp, t1 = ry * inv + hp;
+    if (!(t0 > T(-1) && t0 < T(la.npix) && t1 > T(-1) && t1 < T(la.npix))) return;
+    const T rxp = rx * la.cell, ryp = ry * la.cell;  // Mpc/h
+    const T invp = T(1) / (chi * dth);
+    const T td0 = (xd - rxp * zd / chi) * invp, td1 = (yd - ryp * zd / chi) * invp;
+    const T fl0 = floor(t0), fl1 = floor(t1);
+    const int j0 = (int)fl0, j1 = (int)fl1;
+    const T f0 = t0 - fl0, f1 = t1 - fl1;
+    for (int s = 0; s < la.nsrc; ++s) {
+        const T cs = la.chi_src[s];
+        if (!(chi < cs)) continue;
+        const T gs = (cs - chi) / (cs * chi * a);
+        const T w = la.wbase * gs;
+        const T dg = -T(1) / (cs * chi * a) - gs / chi - gs * dadchi / a;
+        const T dwdom = w / lv.omega_m + la.wbase * (lv.dchis_dom[s] / (cs * cs * a) - gs * dadom / a);
+        const T c = la.wbase * dg * zd + om_dot * dwdom;
+        T* km = kdot + s * npix2;
+#pragma unroll
+        for (int ia = 0; ia < 2; ++ia) {
+            const int r = j0 + ia;
+            if (r < 0 || r >= la.npix) continue;
+            const T w0 = ia ? f0 : T(1) - f0, d0 = ia ? T(1) : T(-1);
+#pragma unroll
+            for (int ib = 0; ib < 2; ++ib) {
+                const int col = j1 + ib;
+                if (col < 0 || col >= la.npix) continue;
+                const T w1 = ib ? f1 : T(1) - f1, d1 = ib ? T(1) : T(-1);
+                unsafeAtomicAdd(&km[(long)r * la.npix + col],
+                                c * w0 * w1 + w * (d0 * w1 * td0 + w0 * d1 * td1));
+            }
+        }
+    }
+}
+
+// Lens projection tangent: every image of every particle splats its tangent
+// (same image set as the projection and its VJP).
+template <class T>
+__global__ __launch_bounds__(256) void k_lens_jvp(Parts<T> p, Geo g, LensArgs<T> la, LensVjpArgs<T> lv,
+                                                  const T* xdot, T om_dot, T* kdot) {
+    const long n = g.npart;
+    const T nmf = T(g.nm), half = T(0.5) * nmf;
+    const T cnear = la.chi_near / la.cell, cfar = la.chi_far / la.cell;
+    const T tmax = T(0.5) * T(la.npix) + T(0.5);
+    const T hp = T(0.5) * T(la.npix) - T(0.5);
+    const T dth = T(1) / la.inv_dtheta;
+    const long npix2 = (long)la.npix * la.npix;
+    T chi_max_src = la.chi_src[0];
+    for (int s = 1; s < la.nsrc; ++s) chi_max_src = max(chi_max_src, la.chi_src[s]);
+    for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
+        uint32_t id = p.id[k];
+        int li[3];
+        lattice_of_l(id, g.np, li);
+        T u[3];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            T v = T(0.5) + p.disp[a * n + k];
+            T fl = floor(v);
+            int c = g.B * li[a] + (int)fl;
+            if ((unsigned)c >= (unsigned)g.nm) c = pmod(c, g.nm);
+            u[a] = T(c) + (v - fl);
+        }
+        if (!(isfinite(u[0]) && isfinite(u[1]) && isfinite(u[2]))) continue;
+        const long L = lattice_index(id, g.np);
+        const T xb[3] = {xdot[L], xdot[n + L], xdot[2 * n + L]};
+        if (la.rot) {
+            const int mz0 = max((int)floor(cnear / nmf), 0), mz1 = (int)floor(cfar / nmf);
+            for (int nz = mz0; nz <= mz1; ++nz) {
+                const T rz_hi = min(T(nz + 1) * nmf, cfar);
+                const T rmax = tmax * rz_hi / la.inv_dtheta;
+                const int mx0 = (int)floor((-rmax + half) / nmf) - 1;
+                const int mx1 = (int)floor((rmax + half) / nmf);
+                for (int nx = mx0; nx <= mx1; ++nx)
+                    for (int ny = mx0; ny <= mx1; ++ny) {
+                        const int sym = vjp_replica_symmetry(nx, ny, nz, la.rot_seed);
+                        T ui[3], ti[3];
+#pragma unroll
+                        for (int j = 0; j < 3; ++j) {
+                            const int ax = vjp_sym_axis(sym, j);
+                            const T c = ax == 0 ? u[0] : (ax == 1 ? u[1] : u[2]);
+                            const T v = ax == 0 ? xb[0] : (ax == 1 ? xb[1] : xb[2]);
+                            const bool fl = (sym >> j) & 1;
+                            ui[j] = fl ? nmf - c : c;
+                            ti[j] = fl ? -v : v;
+                        }
+                        const T rz = ui[2] + T(nz) * nmf;
+                        if (!(rz > cnear && rz <= cfar && rz > T(0))) continue;
+                        const T chi = rz * la.cell;
+                        if (chi >= chi_max_src) continue;
+                        T a, dadchi;
+                        a_interp(la, chi, a, dadchi);
+                        lens_jvp_image(la, lv, kdot, npix2, ui[0] + T(nx) * nmf - half,
+                                       ui[1] + T(ny) * nmf - half, rz, chi, a, dadchi,
+                                       lv.dadom_at(chi), hp, dth, ti[0], ti[1], ti[2], om_dot);
+                    }
+            }
+        } else {
+            const int nz0 = (int)floor((cnear - u[2]) / nmf);
+            const int nz1 = (int)floor((cfar - u[2]) / nmf) + 1;
+            for (int nz = nz0; nz <= nz1; ++nz) {
+                const T rz = u[2] + T(nz) * nmf;
+                if (!(rz > cnear && rz <= cfar && rz > T(0))) continue;
+                const T chi = rz * la.cell;
+                if (chi >= chi_max_src) continue;
+                const T rmax = tmax * rz / la.inv_dtheta;
+                const int nx0 = (int)floor((-rmax - u[0] + half) / nmf);
+                const int nx1 = (int)floor((rmax - u[0] + half) / nmf) + 1;
+                const int ny0 = (int)floor((-rmax - u[1] + half) / nmf);
+                const int ny1 = (int)floor((rmax - u[1] + half) / nmf) + 1;
+                T a, dadchi;
+                a_interp(la, chi, a, dadchi);
+                const T dadom = lv.dadom_at(chi);
+                for (int nx = nx0; nx <= nx1; ++nx)
+                    for (int ny = ny0; ny <= ny1; ++ny)
+                        lens_jvp_image(la, lv, kdot, npix2, u[0] + T(nx) * nmf - half,
+                                       u[1] + T(ny) * nmf - half, rz, chi, a, dadchi, dadom, hp,
+                                       dth, xb[0], xb[1], xb[2], om_dot);
+            }
+        }
+    }
+}
+
+// kdot[s] += v[s] on every pixel (the shell's mean term)
+template <class T>
+__global__ void k_map_add(T* kdot, long npix2, int nsrc, MapAdd<T> mv) {
+    const long total = npix2 * nsrc;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < total; i += (long)gridDim.x * blockDim.x)
+        kdot[i] += mv.v[i / npix2];
+}
+
+// ---------------------------------------------------------------------------
 template <class T>
 void launch_fvjp_readout(Parts<T> p, SortBufs s, Geo g, const T* f0, const T* f1, const T* f2,
                          const T* xbar_in, const T* pbar_in, T H, T ckick, T* xbc, T* fbc,
@@ -534,6 +826,77 @@ void launch_lens_vjp(Parts<T> p, Geo g, const LensArgs<T>& la, const LensVjpArgs
     if (blocks > 16384) blocks = 16384;
     hipLaunchKernelGGL(k_lens_vjp<T>, dim3(blocks), dim3(256), 0, st, p, g, la, lv, kbar, xbar, dots);
 }
+
+static long grid_of(long n, long cap) {
+    long blocks = (n + 255) / 256;
+    return blocks > cap ? cap : (blocks < 1 ? 1 : blocks);
+}
+
+template <class T>
+void launch_lin(T* y, const T* x, T a, T b, long n, hipStream_t st) {
+    hipLaunchKernelGGL(k_lin<T>, dim3(grid_of(n, 16384)), dim3(256), 0, st, y, x, a, b, n);
+}
+
+template <class T>
+void launch_ic_tangent(const T* t0, const T* t1, const T* t2, const T* s0, const T* s1,
+                       const T* s2, T* xd, T* pd, T D, T gp, T cD, T cgp, T H, long n,
+                       hipStream_t st) {
+    hipLaunchKernelGGL(k_ic_tangent<T>, dim3(grid_of(n, 16384)), dim3(256), 0, st, t0, t1, t2, s0,
+                       s1, s2, xd, pd, D, gp, cD, cgp, H, n);
+}
+
+template <class T>
+void launch_jvp_pre(Parts<T> p, Geo g, T* xdot, T* pdot, const T* fdot, T H, T k1, T dr, T ck1,
+                    T cdr, hipStream_t st) {
+    hipLaunchKernelGGL(k_jvp_pre<T>, dim3(grid_of(g.npart, 16384)), dim3(256), 0, st, p, g, xdot,
+                       pdot, fdot, H, k1, dr, ck1, cdr);
+}
+
+template <class T>
+void launch_fjvp_gather(Parts<T> p, SortBufs s, Geo g, const T* f0, const T* f1, const T* f2,
+                        const T* xdot, T invH, T mass, T* xbc, T* fbc, uint32_t* vmax_bits,
+                        hipStream_t st) {
+    int ntiles = g.nt * g.nt * g.nt;
+    hipLaunchKernelGGL(k_fjvp_gather<T>, dim3(ntiles), dim3(AB), 0, st, p, s, g, f0, f1, f2, xdot,
+                       invH, mass, xbc, fbc, vmax_bits);
+}
+
+template <class T>
+void launch_fjvp_readout_kick(Parts<T> p, SortBufs s, Geo g, const T* m0, const T* m1, const T* m2,
+                              const T* fbc, T H, T k2, T ck2, T* pdot, T* fdot, hipStream_t st) {
+    int ntiles = g.nt * g.nt * g.nt;
+    hipLaunchKernelGGL(k_fjvp_readout_kick<T>, dim3(ntiles), dim3(AB), 0, st, p, s, g, m0, m1, m2,
+                       fbc, H, k2, ck2, pdot, fdot);
+}
+
+template <class T>
+void launch_lens_jvp(Parts<T> p, Geo g, const LensArgs<T>& la, const LensVjpArgs<T>& lv,
+                     const T* xdot, T om_dot, T* kdot, hipStream_t st) {
+    hipLaunchKernelGGL(k_lens_jvp<T>, dim3(grid_of(g.npart, 16384)), dim3(256), 0, st, p, g, la,
+                       lv, xdot, om_dot, kdot);
+}
+
+template <class T>
+void launch_map_add(T* kdot, int npix, int nsrc, const MapAdd<T>& mv, hipStream_t st) {
+    const long npix2 = (long)npix * npix;
+    hipLaunchKernelGGL(k_map_add<T>, dim3(grid_of(npix2 * nsrc, 4096)), dim3(256), 0, st, kdot,
+                       npix2, nsrc, mv);
+}
+
+#define ML_INST_JVP(T)                                                                               \
+    template void launch_lin<T>(T*, const T*, T, T, long, hipStream_t);                              \
+    template void launch_ic_tangent<T>(const T*, const T*, const T*, const T*, const T*, const T*,   \
+                                       T*, T*, T, T, T, T, T, long, hipStream_t);                    \
+    template void launch_jvp_pre<T>(Parts<T>, Geo, T*, T*, const T*, T, T, T, T, T, hipStream_t);   \
+    template void launch_fjvp_gather<T>(Parts<T>, SortBufs, Geo, const T*, const T*, const T*,       \
+                                        const T*, T, T, T*, T*, uint32_t*, hipStream_t);             \
+    template void launch_fjvp_readout_kick<T>(Parts<T>, SortBufs, Geo, const T*, const T*, const T*, \
+                                              const T*, T, T, T, T*, T*, hipStream_t);               \
+    template void launch_lens_jvp<T>(Parts<T>, Geo, const LensArgs<T>&, const LensVjpArgs<T>&,       \
+                                     const T*, T, T*, hipStream_t);                                  \
+    template void launch_map_add<T>(T*, int, int, const MapAdd<T>&, hipStream_t);
+ML_INST_JVP(float)
+ML_INST_JVP(double)
 
 #define ML_INST(T)                                                                                   \
     template void launch_fvjp_readout<T>(Parts<T>, SortBufs, Geo, const T*, const T*, const T*,      \

@@ -217,6 +217,11 @@ struct SimBase {
     virtual int step_vjp(double a0, double a1, double a2, void* xbar, void* pbar, double* cb) = 0;
     virtual int init_ic_vjp(double a1, const void* xbar, const void* pbar, void* nbar,
                             double* cb) = 0;
+    virtual int init_ic_jvp(const void* nd, double om_dot, double s8_dot, void* xd, void* pd,
+                            void* fd) = 0;
+    virtual int force_jvp(const void* xd, void* fd) = 0;
+    virtual int step_jvp(double a0, double a1, double om_dot, void* xd, void* pd, void* fd) = 0;
+    virtual int lens_jvp(double a0, double a1, const void* xd, double om_dot, void* kd) = 0;
 };
 
 template <class T> struct Sim final : SimBase {
@@ -248,6 +253,7 @@ template <class T> struct Sim final : SimBase {
     bool meshes_valid = false;  // mesh[0..2] hold the force meshes of the current state
     double dchi_tab = 0;
     double a_cur = -1.0;
+    bool ic_fresh = false;  // the state is the initial conditions of noise_copy
     // sub-evolution projection (the lens moves each image along its step's
     // drift to the scale factor of its own distance)
     bool interp = false;
@@ -299,6 +305,7 @@ template <class T> struct Sim final : SimBase {
         }
         cell = p->box / p->nm;
         a_cur = -1.0;
+        ic_fresh = false;
         kdk_a0 = kdk_a1 = -1.0;
         meshes_valid = false;
     }
@@ -546,6 +553,7 @@ template <class T> struct Sim final : SimBase {
         sort(T(0), T(0), 0);
         force(T(0), 0);
         a_cur = a0;
+        ic_fresh = true;
         kdk_a0 = kdk_a1 = -1.0;
         return check_launch();
     }
@@ -560,6 +568,7 @@ template <class T> struct Sim final : SimBase {
         sort(k1, dr, MODE_KICK | MODE_DRIFT);
         force(k2, 1);
         a_cur = a1;
+        ic_fresh = false;
         kdk_a0 = a0;
         kdk_a1 = a1;
         kdk_k2 = k2;
@@ -751,6 +760,7 @@ template <class T> struct Sim final : SimBase {
         }
         meshes_valid = true;
         a_cur = agrid[nsteps];
+        ic_fresh = false;
         kdk_a0 = agrid[nsteps - 1];
         kdk_a1 = agrid[nsteps];
         kdk_k2 = (T)cosmo.kick(0.5 * (kdk_a0 + kdk_a1), kdk_a1, kdk_a1);
@@ -773,6 +783,7 @@ template <class T> struct Sim final : SimBase {
         sort(T(0), T(0), 0);
         force(T(0), 0);
         a_cur = a;
+        ic_fresh = false;
         kdk_a0 = kdk_a1 = -1.0;
         return check_launch();
     }
@@ -920,20 +931,22 @@ template <class T> struct Sim final : SimBase {
         return PM_OK;
     }
 
-    int lens_vjp(double a0, double a1, const void* kbar, void* xbar, double* cb) override {
-        if (!kbar || !xbar || !cb) return PM_EINVAL;
-        if (interp || pgd) return PM_EINVAL;  // no reverse pass for these modes
-        if (!at_a(a1)) return PM_ESTATE;
-        LensArgs<T> la{};
+    // Projection arguments and the weights' Omega_m derivative for the
+    // derivative passes of the shell (chi(a1), chi(a0)]; false when the shell
+    // lies wholly behind the farthest source plane (its images and its mean
+    // term both need chi < chi_s, so it adds nothing).
+    bool derivative_lens_args(double a0, double a1, LensArgs<T>& la, LensVjpArgs<T>& lv,
+                              double& chi_near, double& chi_far) {
+        la = LensArgs<T>{};
+        lv = LensVjpArgs<T>{};
         la.npix = npix;
         la.nsrc = nsrc;
         la.cell = (T)cell;
-        double chi_far = cosmo.chi(a0), chi_near = cosmo.chi(a1);
-        // a shell wholly behind the farthest source plane adds nothing (its
-        // images and its mean term both need chi < chi_s)
+        chi_far = cosmo.chi(a0);
+        chi_near = cosmo.chi(a1);
         double chis_max = 0;
         for (double c : chisrc) chis_max = std::max(chis_max, c);
-        if (chi_near >= chis_max) return PM_OK;
+        if (chi_near >= chis_max) return false;
         la.chi_near = (T)chi_near;
         la.chi_far = (T)chi_far;
         double dth = fov * PI / 180.0 / npix;
@@ -946,12 +959,22 @@ template <class T> struct Sim final : SimBase {
         la.dchi = (T)dchi_tab;
         la.rot = rot ? 1 : 0;
         la.rot_seed = (unsigned long long)rot_seed;
-        LensVjpArgs<T> lv{};
         lv.omega_m = (T)P.omega_m;
         for (int s = 0; s < nsrc; ++s) lv.dchis_dom[s] = (T)((chisrc_p[s] - chisrc_m[s]) / (2 * DOM));
         lv.dadom = adom;
         lv.ntab = ATAB_N;
         lv.dchi = (T)dchi_tab;
+        return true;
+    }
+
+    int lens_vjp(double a0, double a1, const void* kbar, void* xbar, double* cb) override {
+        if (!kbar || !xbar || !cb) return PM_EINVAL;
+        if (interp || pgd) return PM_EINVAL;  // no reverse pass for these modes
+        if (!at_a(a1)) return PM_ESTATE;
+        LensArgs<T> la;
+        LensVjpArgs<T> lv;
+        double chi_near, chi_far;
+        if (!derivative_lens_args(a0, a1, la, lv, chi_near, chi_far)) return PM_OK;
         launch_fill<double>(dots, 0.0, 64, st);
         const T* kb = reinterpret_cast<const T*>(kbar);
         { ProfScope ps(prof, "lens_vjp");
@@ -970,6 +993,123 @@ template <class T> struct Sim final : SimBase {
         }
         cb[0] += g;
         return PM_OK;
+    }
+
+    // ---- forward mode (tangents) ---------------------------------------------
+    // Force tangent at the current state along xd (lattice, Mpc/h) into fd;
+    // with pd set, also the second half-kick p_dot += K2 f_dot + ck2 f.
+    // Leaves the meshes holding the tangent's force meshes.
+    void force_jvp_cur(const T* xd, T* pd, T* fd, T k2, T ck2) {
+        const T H = (T)cell;
+        const T mass = (T)std::pow((double)geo.B, 3);
+        if (!meshes_valid) {
+            paint();
+            fft_forward_grad(P.nm, nullptr, tw_nm, tw_hm, twp_nm);
+            meshes_valid = true;
+        }
+        launch_fill_u32(fmax_bits, 0u, 1, st);
+        { ProfScope ps(prof, "jvp_gather");
+          launch_fjvp_gather<T>(cur, sb, geo, mesh[0], mesh[1], mesh[2], xd, T(1) / H, mass, xbc, fbc,
+                                fmax_bits, st); }
+        meshes_valid = false;
+        { ProfScope ps(prof, "jvp_paint");
+          launch_paint_tangent<T>(cur, sb, geo, mass, mesh[0], halo, xbc, fmax_bits, st, false); }
+        fft_forward_grad(P.nm, nullptr, tw_nm, tw_hm, twp_nm, paint_halo_merge<T>(geo, halo));
+        { ProfScope ps(prof, "jvp_readout_kick");
+          launch_fjvp_readout_kick<T>(cur, sb, geo, mesh[0], mesh[1], mesh[2], fbc, H, k2, ck2, pd, fd,
+                                      st); }
+    }
+
+    int init_ic_jvp(const void* nd, double om_dot, double s8_dot, void* xd, void* pd,
+                    void* fd) override {
+        if (!nd || !xd || !pd || !fd || !std::isfinite(om_dot) || !std::isfinite(s8_dot))
+            return PM_EINVAL;
+        if (!ic_fresh) return PM_ESTATE;
+        const int np = P.np;
+        const long n = geo.npart;
+        const double a0 = a_cur;
+        const T H = (T)cell;
+        T* x_ = reinterpret_cast<T*>(xd);
+        T* p_ = reinterpret_cast<T*>(pd);
+        meshes_valid = false;
+        // displacement tangent of the noise direction; sigma_8 scales the
+        // noise, so its tangent adds (s8_dot / s8) noise
+        HIPCHK(hipMemcpyAsync(mesh[0], nd, n * sizeof(T), hipMemcpyDeviceToDevice, st));
+        if (s8_dot != 0.0) launch_lin<T>(mesh[0], noise_copy, T(1), (T)(s8_dot / P.sigma8), n, st);
+        fft_forward_grad(np, g_ic, tw_np, tw_hp, twp_np);
+        if (om_dot != 0.0) {
+            // + Om_dot dS/dOm (the amplitude table's Omega_m difference), then
+            // the growth factors' difference times the displacement itself
+            for (int j = 0; j < 3; ++j) launch_lin<T>(x_ + j * n, mesh[j], T(0), T(1), n, st);
+            HIPCHK(hipMemcpyAsync(mesh[0], noise_copy, n * sizeof(T), hipMemcpyDeviceToDevice, st));
+            fft_forward_grad(np, g_ic_dom, tw_np, tw_hp, twp_np);
+            for (int j = 0; j < 3; ++j) launch_lin<T>(x_ + j * n, mesh[j], T(1), (T)om_dot, n, st);
+            HIPCHK(hipMemcpyAsync(mesh[0], noise_copy, n * sizeof(T), hipMemcpyDeviceToDevice, st));
+            fft_forward_grad(np, g_ic, tw_np, tw_hp, twp_np);
+            const double dd0 = (cosmo_p.D(a0) - cosmo_m.D(a0)) / (2 * DOM);
+            const double dgp0 = (cosmo_p.gp(a0) - cosmo_m.gp(a0)) / (2 * DOM);
+            launch_ic_tangent<T>(x_, x_ + n, x_ + 2 * n, mesh[0], mesh[1], mesh[2], x_, p_,
+                                 (T)cosmo.D(a0), (T)cosmo.gp(a0), (T)(om_dot * dd0),
+                                 (T)(om_dot * dgp0), H, n, st);
+        } else {
+            launch_ic_tangent<T>(mesh[0], mesh[1], mesh[2], mesh[0], mesh[1], mesh[2], x_, p_,
+                                 (T)cosmo.D(a0), (T)cosmo.gp(a0), T(0), T(0), H, n, st);
+        }
+        force_jvp_cur(x_, nullptr, reinterpret_cast<T*>(fd), T(0), T(0));
+        return check_launch();
+    }
+
+    int force_jvp(const void* xd, void* fd) override {
+        if (!xd || !fd) return PM_EINVAL;
+        if (a_cur < 0) return PM_ESTATE;
+        force_jvp_cur(reinterpret_cast<const T*>(xd), nullptr, reinterpret_cast<T*>(fd), T(0), T(0));
+        return check_launch();
+    }
+
+    int step_jvp(double a0, double a1, double om_dot, void* xd, void* pd, void* fd) override {
+        if (!xd || !pd || !fd || !std::isfinite(om_dot)) return PM_EINVAL;
+        if (!at_a(a0)) return PM_ESTATE;
+        if (!(a1 > 0 && a1 <= 1.5)) return PM_EINVAL;
+        const double ah = 0.5 * (a0 + a1);
+        const double k1 = cosmo.kick(a0, ah, a0), dr = cosmo.drift(a0, a1, ah);
+        const double k2 = cosmo.kick(ah, a1, a1);
+        const double dk1 = (cosmo_p.kick(a0, ah, a0) - cosmo_m.kick(a0, ah, a0)) / (2 * DOM);
+        const double ddr = (cosmo_p.drift(a0, a1, ah) - cosmo_m.drift(a0, a1, ah)) / (2 * DOM);
+        const double dk2 = (cosmo_p.kick(ah, a1, a1) - cosmo_m.kick(ah, a1, a1)) / (2 * DOM);
+        T* x_ = reinterpret_cast<T*>(xd);
+        T* p_ = reinterpret_cast<T*>(pd);
+        T* f_ = reinterpret_cast<T*>(fd);
+        { ProfScope ps(prof, "jvp_kick_drift");
+          launch_jvp_pre<T>(cur, geo, x_, p_, f_, (T)cell, (T)k1, (T)dr, (T)(om_dot * dk1),
+                            (T)(om_dot * ddr), st); }
+        int rc = step(a0, a1);  // the forward step: the kernels of pm_step
+        if (rc) return rc;
+        force_jvp_cur(x_, p_, f_, (T)k2, (T)(om_dot * dk2));
+        return check_launch();
+    }
+
+    int lens_jvp(double a0, double a1, const void* xd, double om_dot, void* kd) override {
+        if (!xd || !kd || !std::isfinite(om_dot)) return PM_EINVAL;
+        if (interp || pgd) return PM_EINVAL;  // no tangent pass for these modes
+        if (!at_a(a1)) return PM_ESTATE;
+        LensArgs<T> la;
+        LensVjpArgs<T> lv;
+        double chi_near, chi_far;
+        if (!derivative_lens_args(a0, a1, la, lv, chi_near, chi_far)) return PM_OK;
+        T* kdot = reinterpret_cast<T*>(kd);
+        { ProfScope ps(prof, "lens_jvp");
+          launch_lens_jvp<T>(cur, geo, la, lv, reinterpret_cast<const T*>(xd), (T)om_dot, kdot, st); }
+        if (om_dot != 0.0) {
+            // the mean term's Omega_m derivative at a fixed shell partition
+            MapAdd<T> mv{};
+            for (int s = 0; s < nsrc; ++s) {
+                const double mp = cosmo_p.shell_mean(chi_near, chi_far, chisrc_p[s]);
+                const double mm = cosmo_m.shell_mean(chi_near, chi_far, chisrc_m[s]);
+                mv.v[s] = (T)(om_dot * (mp - mm) / (2 * DOM));
+            }
+            launch_map_add<T>(kdot, npix, nsrc, mv, st);
+        }
+        return check_launch();
     }
 
     hipStream_t stream() const override { return st; }
@@ -1080,6 +1220,22 @@ int pm_step_vjp(pm_sim* sim, double a0, double a1, double a2, void* x_bar, void*
 int pm_init_ic_vjp(pm_sim* sim, double a1, const void* x_bar, const void* p_bar, void* noise_bar,
                    double cosmo_bar[2]) {
     return sim ? sim->impl->init_ic_vjp(a1, x_bar, p_bar, noise_bar, cosmo_bar) : PM_EINVAL;
+}
+int pm_init_ic_jvp(pm_sim* sim, const void* noise_dot, double omega_m_dot, double sigma8_dot,
+                   void* x_dot, void* p_dot, void* f_dot) {
+    return sim ? sim->impl->init_ic_jvp(noise_dot, omega_m_dot, sigma8_dot, x_dot, p_dot, f_dot)
+               : PM_EINVAL;
+}
+int pm_force_jvp(pm_sim* sim, const void* x_dot, void* f_dot) {
+    return sim ? sim->impl->force_jvp(x_dot, f_dot) : PM_EINVAL;
+}
+int pm_step_jvp(pm_sim* sim, double a0, double a1, double omega_m_dot, void* x_dot, void* p_dot,
+                void* f_dot) {
+    return sim ? sim->impl->step_jvp(a0, a1, omega_m_dot, x_dot, p_dot, f_dot) : PM_EINVAL;
+}
+int lens_project_jvp(pm_sim* sim, double a0, double a1, const void* x_dot, double omega_m_dot,
+                     void* kappa_dot) {
+    return sim ? sim->impl->lens_jvp(a0, a1, x_dot, omega_m_dot, kappa_dot) : PM_EINVAL;
 }
 int pm_background(const pm_sim* sim, double a, double out[3]) {
     return sim && out ? sim->impl->background(a, out) : PM_EINVAL;

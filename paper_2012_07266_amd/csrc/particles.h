@@ -100,6 +100,13 @@ void launch_paint(Parts<T> p, SortBufs s, Geo g, T mass, T* rho, T* halo, hipStr
 template <class T>
 void launch_paint_values(Parts<T> p, SortBufs s, Geo g, T mass, T* rho, T* halo, const T* vals,
                          const uint32_t* vmax_bits, hipStream_t st, bool merge_halo = true);
+// Tangent paint: d/de of the CIC density at x + e xdot, xdot [3][n] in
+// tile-sorted order and cells; corner c of a particle receives
+// mass sum_a (dW_c/du_a) xdot_a.  *vmax_bits holds the float bits of a bound
+// of mass sum_a |xdot_a| over the particles (the fixed-point scale).
+template <class T>
+void launch_paint_tangent(Parts<T> p, SortBufs s, Geo g, T mass, T* rho, T* halo, const T* xdot,
+                          const uint32_t* vmax_bits, hipStream_t st, bool merge_halo = true);
 template <class T> struct HaloMerge;
 // The shells of the last paint into `halo`, for a merge during the r2c pass.
 template <class T>

@@ -366,12 +366,13 @@ __device__ __forceinline__ float value_scale(const uint32_t* vmax_bits) {
     return ldexpf(1.0f, 40 - e);
 }
 
-// Particles k0, k0 + PBP, ... (PU of them, below hi) of a paint batch.
-template <class T>
+// Particles k0, k0 + PBP, ... (PU of them, below hi) of a paint batch.  With
+// TAN the three components of a tangent ([3][n], cells) go to tv.
+template <class T, bool TAN>
 __device__ __forceinline__ void paint_load_batch(const Parts<T>& p, long n, uint32_t k0,
                                                  uint32_t hi, const T* vals, T mass,
                                                  uint32_t (&idv)[PU], T (&dv)[PU][3],
-                                                 T (&mv)[PU]) {
+                                                 T (&mv)[PU], T (&tv)[PU][3]) {
 #pragma unroll
     for (int u = 0; u < PU; ++u) {
         uint32_t k = k0 + u * PBP;
@@ -380,12 +381,21 @@ __device__ __forceinline__ void paint_load_batch(const Parts<T>& p, long n, uint
             dv[u][0] = p.disp[k];
             dv[u][1] = p.disp[n + k];
             dv[u][2] = p.disp[2 * n + k];
-            mv[u] = vals ? vals[k] : mass;
+            if constexpr (TAN) {
+                tv[u][0] = vals[k];
+                tv[u][1] = vals[n + k];
+                tv[u][2] = vals[2 * n + k];
+            } else {
+                mv[u] = vals ? vals[k] : mass;
+            }
         }
     }
 }
 
-template <class T, int G>
+// TAN: tangent paint, d/de of the density at x + e xdot for the tangent
+// vals = xdot ([3][n] cells): corner c of a particle receives
+// mass sum_a (dW_c/du_a) xdot_a (vmax_bits then bounds mass sum_a |xdot_a|).
+template <class T, int G, bool TAN>
 __global__ __launch_bounds__(PBP) void k_paint_group(Parts<T> p, SortBufs s, Geo g, T mass, T* rho,
                                                      T* halo, const T* vals,
                                                      const uint32_t* vmax_bits) {
@@ -404,13 +414,13 @@ __global__ __launch_bounds__(PBP) void k_paint_group(Parts<T> p, SortBufs s, Geo
     const int b0 = tile_block(g, tx, ty, gz * G);
     const uint32_t lo = s.start[b0], hi = s.start[b0 + G * (TILE / KZ)];
     uint32_t idv[PU];
-    T dv[PU][3], mv[PU];
+    T dv[PU][3], mv[PU], tv[PU][3];
     // the first batch is in flight while the box is cleared
-    paint_load_batch<T>(p, n, lo + tid, hi, vals, mass, idv, dv, mv);
+    paint_load_batch<T, TAN>(p, n, lo + tid, hi, vals, mass, idv, dv, mv, tv);
     for (int i = tid; i < BX::CELLS; i += PBP) box[i] = S(0);
     __syncthreads();
     for (uint32_t base = lo; base < hi; base += PBP * PU) {
-        if (base != lo) paint_load_batch<T>(p, n, base + tid, hi, vals, mass, idv, dv, mv);
+        if (base != lo) paint_load_batch<T, TAN>(p, n, base + tid, hi, vals, mass, idv, dv, mv, tv);
 #pragma unroll
         for (int u = 0; u < PU; ++u) {
             uint32_t k = base + u * PBP + tid;
@@ -426,6 +436,24 @@ __global__ __launch_bounds__(PBP) void k_paint_group(Parts<T> p, SortBufs s, Geo
             int l1 = min(max(c1 - oy, 0), TILE - 1);
             int l2 = min(max(c2 - oz, 0), BX::LZ - 1);
             T w0[2] = {T(1) - f0, f0}, w1[2] = {T(1) - f1, f1};
+            if constexpr (TAN) {
+                // corner (a, b, c): w2[c] A_ab + dw2[c] B_ab with
+                // A_ab = mass (dw0[a] w1[b] t0 + w0[a] dw1[b] t1),
+                // B_ab = mass w0[a] w1[b] t2, dw = -1 (low) / +1 (high)
+                const T t0 = mass * tv[u][0], t1 = mass * tv[u][1], t2 = mass * tv[u][2];
+                const T w2[2] = {T(1) - f2, f2};
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b) {
+                        const T d0 = a ? t0 : -t0, d1 = b ? t1 : -t1;
+                        const T A_ = d0 * w1[b] + w0[a] * d1;
+                        const T B_ = w0[a] * w1[b] * t2;
+                        int cell = ((l0 + a) * TE + (l1 + b)) * BX::EZ + l2;
+                        atomicAdd(&box[cell], A::enc(w2[0] * A_ - B_, scale));
+                        atomicAdd(&box[cell + 1], A::enc(w2[1] * A_ + B_, scale));
+                    }
+            } else {
             T w2[2] = {(T(1) - f2) * mv[u], f2 * mv[u]};
 #pragma unroll
             for (int a = 0; a < 2; ++a)
@@ -436,6 +464,7 @@ __global__ __launch_bounds__(PBP) void k_paint_group(Parts<T> p, SortBufs s, Geo
                     atomicAdd(&box[cell], A::enc(wab * w2[0], scale));
                     atomicAdd(&box[cell + 1], A::enc(wab * w2[1], scale));
                 }
+            }
         }
     }
     __syncthreads();
@@ -489,22 +518,34 @@ long paint_halo_elems(int nt, int esize) {
     return groups * h;
 }
 
-template <class T>
-void launch_paint_values(Parts<T> p, SortBufs s, Geo g, T mass, T* rho, T* halo, const T* vals,
-                         const uint32_t* vmax_bits, hipStream_t st, bool merge_halo) {
+template <class T, bool TAN>
+void launch_paint_group(Parts<T> p, SortBufs s, Geo g, T mass, T* rho, T* halo, const T* vals,
+                        const uint32_t* vmax_bits, hipStream_t st, bool merge_halo) {
     int G = paint_group_size(g.nt, sizeof(T));
     int groups = g.nt * g.nt * (g.nt / G);
     if (G == 2) {
-        hipLaunchKernelGGL((k_paint_group<T, 2>), dim3(groups), dim3(PBP), 0, st, p, s, g, mass, rho,
-                           halo, vals, vmax_bits);
+        hipLaunchKernelGGL((k_paint_group<T, 2, TAN>), dim3(groups), dim3(PBP), 0, st, p, s, g, mass,
+                           rho, halo, vals, vmax_bits);
         if (merge_halo)
             hipLaunchKernelGGL((k_paint_halo_group<T, 2>), dim3(groups), dim3(PB), 0, st, rho, halo, g);
     } else {
-        hipLaunchKernelGGL((k_paint_group<T, 1>), dim3(groups), dim3(PBP), 0, st, p, s, g, mass, rho,
-                           halo, vals, vmax_bits);
+        hipLaunchKernelGGL((k_paint_group<T, 1, TAN>), dim3(groups), dim3(PBP), 0, st, p, s, g, mass,
+                           rho, halo, vals, vmax_bits);
         if (merge_halo)
             hipLaunchKernelGGL((k_paint_halo_group<T, 1>), dim3(groups), dim3(PB), 0, st, rho, halo, g);
     }
+}
+
+template <class T>
+void launch_paint_values(Parts<T> p, SortBufs s, Geo g, T mass, T* rho, T* halo, const T* vals,
+                         const uint32_t* vmax_bits, hipStream_t st, bool merge_halo) {
+    launch_paint_group<T, false>(p, s, g, mass, rho, halo, vals, vmax_bits, st, merge_halo);
+}
+
+template <class T>
+void launch_paint_tangent(Parts<T> p, SortBufs s, Geo g, T mass, T* rho, T* halo, const T* xdot,
+                          const uint32_t* vmax_bits, hipStream_t st, bool merge_halo) {
+    launch_paint_group<T, true>(p, s, g, mass, rho, halo, xdot, vmax_bits, st, merge_halo);
 }
 
 template <class T>
@@ -878,6 +919,8 @@ void launch_noise(T* out, long n, uint64_t seed, hipStream_t st) {
     template void launch_paint<T>(Parts<T>, SortBufs, Geo, T, T*, T*, hipStream_t, bool);         \
     template void launch_paint_values<T>(Parts<T>, SortBufs, Geo, T, T*, T*, const T*,            \
                                          const uint32_t*, hipStream_t, bool);                     \
+    template void launch_paint_tangent<T>(Parts<T>, SortBufs, Geo, T, T*, T*, const T*,           \
+                                          const uint32_t*, hipStream_t, bool);                    \
     template HaloMerge<T> paint_halo_merge<T>(Geo, const T*);                                     \
     template void launch_readout<T>(Parts<T>, SortBufs, Geo, const T*, const T*, const T*, T, int, \
                                     uint32_t*, hipStream_t, ReadoutNext<T>);                      \
