@@ -274,53 +274,60 @@ int pm_init_ic_vjp(pm_sim* sim, double a1, const void* x_bar, const void* p_bar,
  * conditions) are Jvps against finite differences (section on validating
  * the derivatives).  These calls carry the tangent of the state along a
  * direction (noise_dot, Omega_m_dot, sigma8_dot) forward with the
- * simulation, one step / shell at a time; no checkpoints are kept.  The
- * caller owns the tangent arrays x_dot, p_dot, f_dot: device arrays
- * [3][Np^3] of dtype in lattice order and Mpc/h (dx, dp and the force
- * tangent df at the current state).  Omega_m derivatives of scalar factors
- * are the central differences (step 1e-5) of the reverse mode, with the same
- * fixed shell partition and source membership; a tangent pass and a reverse
- * pass thus satisfy <kappa_bar, J v> = <J^T kappa_bar, v>.  The calls are
- * asynchronous on the simulation's stream.  Sub-evolution and PGD have no
- * tangent pass (PM_EINVAL from lens_project_jvp); replica rotation does.
+ * simulation, one step / shell at a time, without checkpoints.  The
+ * tangent (x_dot, p_dot and the force tangent f_dot at the current state)
+ * is held by the library in its own particle order, and travels with the
+ * particles through each step's sort; it is allocated on first use (15
+ * Np^3 values of dtype, not counted by pm_footprint).  pm_set_tangent and
+ * pm_get_tangent exchange it with device arrays [3][Np^3] of dtype in
+ * lattice order and Mpc/h.  Omega_m derivatives of scalar factors are the
+ * central differences (step 1e-5) of the reverse mode, with the same fixed
+ * shell partition and source membership; a tangent pass and a reverse pass
+ * thus satisfy <kappa_bar, J v> = <J^T kappa_bar, v>.  The calls are
+ * asynchronous on the simulation's stream.  Any call that changes the state
+ * other than pm_step_jvp (pm_init_ic*, pm_step, pm_run, pm_set_state,
+ * pm_reconfigure) drops the tangent.  Sub-evolution and PGD have no tangent
+ * pass (PM_EINVAL from lens_project_jvp); replica rotation does.
  *
  * pm_init_ic_jvp: the state must be the initial conditions that pm_init_ic
  * (or pm_init_ic_seed) just made (no step, run or pm_set_state since, else
- * PM_ESTATE).  noise_dot: device [Np^3], the noise tangent.  Writes
+ * PM_ESTATE).  noise_dot: device [Np^3], the noise tangent.  Sets the tangent
  *   x_dot = D s_dot + Om_dot (dD/dOm) s,  p_dot = g_p s_dot + Om_dot (dg_p/dOm) s,
  *   s_dot = S(noise_dot + (s8_dot / s8) noise) + Om_dot dS/dOm(noise)
- * (S the Zel'dovich displacement map at D = 1) and f_dot, the force tangent
- * at the initial positions.  Errors: PM_EINVAL (NULL array, non-finite
- * scalar), PM_ESTATE. */
-int pm_init_ic_jvp(pm_sim* sim, const void* noise_dot, double omega_m_dot, double sigma8_dot,
-                   void* x_dot, void* p_dot, void* f_dot);
+ * (S the Zel'dovich displacement map at D = 1), f_dot the force tangent at
+ * the initial positions, and Omega_m_dot for the steps and shells to come.
+ * Errors: PM_EINVAL (NULL array, non-finite scalar), PM_ESTATE, PM_ENOMEM. */
+int pm_init_ic_jvp(pm_sim* sim, const void* noise_dot, double omega_m_dot, double sigma8_dot);
 
-/* pm_force_jvp: f_dot (WRITTEN) = the tangent of the force at the current
- * positions along x_dot: the force meshes' gradient along x_dot read out at
- * the particles, plus the force of the tangent density (the cloud-in-cell
- * paint differentiated along x_dot) read out at the particles.
- * Errors: PM_EINVAL, PM_ESTATE (no state). */
-int pm_force_jvp(pm_sim* sim, const void* x_dot, void* f_dot);
+/* pm_set_tangent: set the tangent of the current state to (x_dot, p_dot)
+ * (device [3][Np^3], lattice order, Mpc/h, read only) with Omega_m component
+ * omega_m_dot; f_dot becomes the force tangent at the current positions: the
+ * force meshes' gradient along x_dot read out at the particles, plus the
+ * force of the tangent density (the cloud-in-cell paint differentiated
+ * along x_dot) read out at the particles.
+ * Errors: PM_EINVAL, PM_ESTATE (no state), PM_ENOMEM. */
+int pm_set_tangent(pm_sim* sim, const void* x_dot, const void* p_dot, double omega_m_dot);
 
-/* pm_step_jvp: the step a0 -> a1 exactly as pm_step, and the tangent of
- * (x, p, f) carried across it, in place:
+/* pm_get_tangent: copy the tangent out in lattice order (device [3][Np^3]
+ * each; any may be NULL).  Errors: PM_ESTATE (no tangent). */
+int pm_get_tangent(pm_sim* sim, void* x_dot, void* p_dot, void* f_dot);
+
+/* pm_step_jvp: the step a0 -> a1 exactly as pm_step, and the tangent
+ * carried across it:
  *   ph_dot = p_dot + K1 f_dot + Om_dot K1' f,  x_dot += Dr ph_dot + Om_dot Dr' (p + K1 f),
- *   f_dot = pm_force_jvp at the new positions,  p_dot = ph_dot + K2 f_dot + Om_dot K2' f
+ *   f_dot = the force tangent at the new positions,  p_dot = ph_dot + K2 f_dot + Om_dot K2' f
  * (K1, Dr, K2 the step's kick, drift and kick factors, ' the Omega_m
- * difference).  On entry f_dot must be the force tangent at a0 (from
- * pm_init_ic_jvp, pm_force_jvp or the previous pm_step_jvp).  The state must
- * be at a0.  Errors: PM_EINVAL, PM_ESTATE. */
-int pm_step_jvp(pm_sim* sim, double a0, double a1, double omega_m_dot, void* x_dot, void* p_dot,
-                void* f_dot);
+ * difference).  The state must be at a0 with a tangent.
+ * Errors: PM_EINVAL, PM_ESTATE. */
+int pm_step_jvp(pm_sim* sim, double a0, double a1);
 
-/* lens_project_jvp: state at a1.  kappa_dot (device [nsrc][npix][npix],
- * ACCUMULATED) += d kappa_shell along (x_dot, Omega_m_dot): per image,
- * (dw/dchi chi_dot + Om_dot dw/dOm) B + w (dB/dtheta . theta_dot) with w the
- * lens weight and B the bilinear weights, plus Om_dot times the mean term's
- * Omega_m difference.  Errors: PM_EINVAL (NULL array, non-finite scalar,
+/* lens_project_jvp: state at a1, with a tangent.  kappa_dot (device
+ * [nsrc][npix][npix], ACCUMULATED) += d kappa_shell along the tangent: per
+ * image, (dw/dchi chi_dot + Om_dot dw/dOm) B + w (dB/dtheta . theta_dot)
+ * with w the lens weight and B the bilinear weights, plus Om_dot times the
+ * mean term's Omega_m difference.  Errors: PM_EINVAL (NULL array,
  * sub-evolution or PGD on), PM_ESTATE. */
-int lens_project_jvp(pm_sim* sim, double a0, double a1, const void* x_dot, double omega_m_dot,
-                     void* kappa_dot);
+int lens_project_jvp(pm_sim* sim, double a0, double a1, void* kappa_dot);
 
 /* Per-kernel timing (tracing).  pm_profile(sim, 1) starts recording a pair
  * of HIP events around every kernel launch on the simulation's stream (the

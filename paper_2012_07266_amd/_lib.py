@@ -71,10 +71,11 @@ SIGNATURES = {
     "lens_project_vjp": (_I, [_P, _D, _D, _P, _P, ctypes.POINTER(_D)]),
     "pm_step_vjp": (_I, [_P, _D, _D, _D, _P, _P, ctypes.POINTER(_D)]),
     "pm_init_ic_vjp": (_I, [_P, _D, _P, _P, _P, ctypes.POINTER(_D)]),
-    "pm_init_ic_jvp": (_I, [_P, _P, _D, _D, _P, _P, _P]),
-    "pm_force_jvp": (_I, [_P, _P, _P]),
-    "pm_step_jvp": (_I, [_P, _D, _D, _D, _P, _P, _P]),
-    "lens_project_jvp": (_I, [_P, _D, _D, _P, _D, _P]),
+    "pm_init_ic_jvp": (_I, [_P, _P, _D, _D]),
+    "pm_set_tangent": (_I, [_P, _P, _P, _D]),
+    "pm_get_tangent": (_I, [_P, _P, _P, _P]),
+    "pm_step_jvp": (_I, [_P, _D, _D]),
+    "lens_project_jvp": (_I, [_P, _D, _D, _P]),
     "pm_profile": (_I, [_P, _I]),
     "pm_profile_read": (_I, [_P, _I, ctypes.c_char_p, ctypes.POINTER(_D),
                              ctypes.POINTER(ctypes.c_long), ctypes.POINTER(_I)]),

@@ -52,16 +52,17 @@ def reverse_pass(sim: Simulation, a_grid: Sequence[float], states, kappa_bar: to
 def jvp(sim: Simulation, noise: torch.Tensor, a_grid: Sequence[float], noise_dot: torch.Tensor,
         omega_m_dot: float = 0.0, sigma8_dot: float = 0.0):
     """(kappa, kappa_dot): the maps and their directional derivative along
-    (noise_dot, Omega_m_dot, sigma8_dot), in one forward pass that carries
-    the tangent of (x, p, f) with every step (no checkpoints)."""
+    (noise_dot, Omega_m_dot, sigma8_dot), in one forward pass in which the
+    library carries the tangent of (x, p, f) with every step (no
+    checkpoints)."""
     kappa = sim.new_maps()
     kappa_dot = sim.new_maps()
     sim.init_ic(noise, a_grid[0])
-    x_dot, p_dot, f_dot = sim.init_ic_jvp(noise_dot, omega_m_dot, sigma8_dot)
+    sim.init_ic_jvp(noise_dot, omega_m_dot, sigma8_dot)
     for i in range(len(a_grid) - 1):
-        sim.step_jvp(a_grid[i], a_grid[i + 1], x_dot, p_dot, f_dot, omega_m_dot)
+        sim.step_jvp(a_grid[i], a_grid[i + 1])
         sim.lens(a_grid[i], a_grid[i + 1], kappa)
-        sim.lens_jvp(a_grid[i], a_grid[i + 1], x_dot, kappa_dot, omega_m_dot)
+        sim.lens_jvp(a_grid[i], a_grid[i + 1], kappa_dot)
     return kappa, kappa_dot
 
 

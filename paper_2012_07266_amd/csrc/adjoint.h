@@ -53,7 +53,7 @@ template <class T>
 void launch_lens_vjp(Parts<T> p, Geo g, const LensArgs<T>& la, const LensVjpArgs<T>& lv,
                      const T* kbar, T* xbar, double* dots, hipStream_t st);
 
-// ---- forward mode (tangents) -----------------------------------------------
+// ---- forward mode (tangents; tangent arrays [3][npart] in tile order, Mpc/h)
 // y = a y + b x over n elements (y not read when a == 0).
 template <class T>
 void launch_lin(T* y, const T* x, T a, T b, long n, hipStream_t st);
@@ -63,15 +63,18 @@ template <class T>
 void launch_ic_tangent(const T* t0, const T* t1, const T* t2, const T* s0, const T* s1,
                        const T* s2, T* xd, T* pd, T D, T gp, T cD, T cgp, T H, long n,
                        hipStream_t st);
+// sorted[a][k] = lattice[a][L(k)] for the current tile order.
+template <class T>
+void launch_lattice_to_sorted(Parts<T> p, Geo g, const T* lat, T* sorted, hipStream_t st);
 // Tangent of a step's first half-kick and drift at the state before it.
 template <class T>
 void launch_jvp_pre(Parts<T> p, Geo g, T* xdot, T* pdot, const T* fdot, T H, T k1, T dr, T ck1,
                     T cdr, hipStream_t st);
-// Readout part of the force tangent on the force meshes f0..f2; position
-// tangent to xbc and a bound for the tangent paint's scale to vmax_bits.
+// Readout part of the force tangent on the force meshes f0..f2 into fbc
+// (cells), and a bound for the tangent paint's scale to vmax_bits.
 template <class T>
 void launch_fjvp_gather(Parts<T> p, SortBufs s, Geo g, const T* f0, const T* f1, const T* f2,
-                        const T* xdot, T invH, T mass, T* xbc, T* fbc, uint32_t* vmax_bits,
+                        const T* xdot, T invH, T mass, T* fbc, uint32_t* vmax_bits,
                         hipStream_t st);
 // Paint part of the force tangent from the tangent force meshes m0..m2, the
 // second half-kick of p_dot (pdot may be NULL) and f_dot.

@@ -63,10 +63,31 @@ __device__ __forceinline__ void cic_grad(const T* ft, int base, const T w[3][2],
             }
 }
 
-// wave reduction then one double atomic per wave
-__device__ __forceinline__ void wave_add(double* dst, double v) {
+// Workgroup reductions with one atomic per workgroup (same-address atomics
+// from every wave serialise).  Every thread of the workgroup must call them;
+// red is LDS scratch of NT / 64 entries, reusable across calls.
+template <int NT>
+__device__ __forceinline__ void block_add(double* dst, double v, double* red) {
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    if ((threadIdx.x & 63) == 0) unsafeAtomicAdd(dst, v);
+    __syncthreads();  // a previous call may still be reading red
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int i = 0; i < NT / 64; ++i) t += red[i];
+        if (t != 0.0) unsafeAtomicAdd(dst, t);
+    }
+}
+template <int NT>
+__device__ __forceinline__ void block_max(uint32_t* dst, float v, float* red) {
+    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int i = 1; i < NT / 64; ++i) v = fmaxf(v, red[i]);
+        if (v > 0.f) atomicMax(dst, __float_as_uint(v));
+    }
 }
 
 template <class T>
@@ -93,6 +114,8 @@ __global__ __launch_bounds__(AB) void k_fvjp_readout(Parts<T> p, SortBufs s, Geo
                                                      T* fbc, double* dots, uint32_t* fmax_bits) {
     constexpr int TC = TE * TE * TE;
     __shared__ T ft[3][TC];
+    __shared__ double red[AB / 64];
+    __shared__ float redf[AB / 64];
     const int tid = threadIdx.x;
     const int t = xcd_remap(blockIdx.x, gridDim.x);
     const int tx = t / (g.nt * g.nt), ty = (t / g.nt) % g.nt, tz = t % g.nt;
@@ -139,9 +162,8 @@ __global__ __launch_bounds__(AB) void k_fvjp_readout(Parts<T> p, SortBufs s, Geo
             }
         }
     }
-    wave_add(&dots[0], dot);
-    for (int off = 32; off > 0; off >>= 1) fmax = fmaxf(fmax, __shfl_xor(fmax, off));
-    if ((tid & 63) == 0 && fmax > 0.f) atomicMax(fmax_bits, __float_as_uint(fmax));
+    block_add<AB>(&dots[0], dot, red);
+    block_max<AB>(fmax_bits, fmax, redf);
 }
 
 // ---------------------------------------------------------------------------
@@ -156,6 +178,7 @@ __global__ __launch_bounds__(AB) void k_fvjp_paintgrad(Parts<T> p, SortBufs s, G
                                                        T* sb0, T* sb1, T* sb2, double* dots) {
     constexpr int TC = TE * TE * TE;
     __shared__ T ft[TC];
+    __shared__ double red[AB / 64];
     const int tid = threadIdx.x;
     const int t = xcd_remap(blockIdx.x, gridDim.x);
     const int tx = t / (g.nt * g.nt), ty = (t / g.nt) % g.nt, tz = t % g.nt;
@@ -206,26 +229,29 @@ __global__ __launch_bounds__(AB) void k_fvjp_paintgrad(Parts<T> p, SortBufs s, G
             }
         }
     }
-    wave_add(&dots[1], a1);
+    block_add<AB>(&dots[1], a1, red);
     if (mode == 1) {
-        wave_add(&dots[2], a2);
-        wave_add(&dots[3], a3);
+        block_add<AB>(&dots[2], a2, red);
+        block_add<AB>(&dots[3], a3, red);
     }
 }
 
 template <class T>
-__global__ void k_dot3(const T* a0, const T* a1, const T* a2, const T* b0, const T* b1,
-                       const T* b2, long n, double* dst) {
+__global__ __launch_bounds__(256) void k_dot3(const T* a0, const T* a1, const T* a2, const T* b0,
+                                              const T* b1, const T* b2, long n, double* dst) {
+    __shared__ double red[4];
     double acc = 0.0;
     for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
         acc += (double)a0[i] * b0[i] + (double)a1[i] * b1[i] + (double)a2[i] * b2[i];
-    wave_add(dst, acc);
+    block_add<256>(dst, acc, red);
 }
 
 // sum_k sum_j sorted[j][k] * lattice_j[L(k)]
 template <class T>
-__global__ void k_dot_sorted_lattice(Parts<T> p, Geo g, const T* sorted, const T* l0, const T* l1,
-                                     const T* l2, double* dst) {
+__global__ __launch_bounds__(256) void k_dot_sorted_lattice(Parts<T> p, Geo g, const T* sorted,
+                                                            const T* l0, const T* l1, const T* l2,
+                                                            double* dst) {
+    __shared__ double red[4];
     const long n = g.npart;
     double acc = 0.0;
     for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
@@ -233,7 +259,7 @@ __global__ void k_dot_sorted_lattice(Parts<T> p, Geo g, const T* sorted, const T
         acc += (double)sorted[k] * l0[L] + (double)sorted[n + k] * l1[L] +
                (double)sorted[2 * n + k] * l2[L];
     }
-    wave_add(dst, acc);
+    block_add<256>(dst, acc, red);
 }
 
 // lattice_j[L(k)] = sorted[j][k]
@@ -249,12 +275,13 @@ __global__ void k_sorted_to_lattice(Parts<T> p, Geo g, const T* sorted, T* l0, T
 }
 
 template <class T>
-__global__ void k_map_sums(const T* kbar, long npix2, int nsrc, double* dst) {
+__global__ __launch_bounds__(256) void k_map_sums(const T* kbar, long npix2, int nsrc, double* dst) {
+    __shared__ double red[4];
     for (int s = 0; s < nsrc; ++s) {
         double acc = 0.0;
         for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < npix2; i += (long)gridDim.x * blockDim.x)
             acc += (double)kbar[(long)s * npix2 + i];
-        wave_add(&dst[s], acc);
+        block_add<256>(&dst[s], acc, red);
     }
 }
 
@@ -353,6 +380,7 @@ __device__ __forceinline__ int vjp_sym_axis(int s, int j) {
 template <class T>
 __global__ __launch_bounds__(256) void k_lens_vjp(Parts<T> p, Geo g, LensArgs<T> la, LensVjpArgs<T> lv,
                                                   const T* kbar, T* xbar, double* dots) {
+    __shared__ double red[4];
     const long n = g.npart;
     const T nmf = T(g.nm), half = T(0.5) * nmf;
     const T cnear = la.chi_near / la.cell, cfar = la.chi_far / la.cell;
@@ -472,12 +500,13 @@ __global__ __launch_bounds__(256) void k_lens_vjp(Parts<T> p, Geo g, LensArgs<T>
             xbar[2 * n + L] += gz;
         }
     }
-    wave_add(&dots[4], om_acc);
+    block_add<256>(&dots[4], om_acc, red);
 }
 
 // ---------------------------------------------------------------------------
-// 4. forward-mode tangents (Jacobian-vector products).  The caller's tangent
-//    arrays are in lattice order and Mpc/h; sorted-order scratch in cells.
+// 4. forward-mode tangents (Jacobian-vector products).  The tangent state
+//    (x_dot, p_dot, f_dot) is kept in tile order, in Mpc/h, and travels with
+//    the particles through the sort, so every access here is coalesced.
 // ---------------------------------------------------------------------------
 // y = a y + b x (y is not read when a == 0)
 template <class T>
@@ -503,6 +532,17 @@ __global__ void k_ic_tangent(const T* t0, const T* t1, const T* t2, const T* s0,
     }
 }
 
+// sorted[a][k] = lattice[a][L(k)]
+template <class T>
+__global__ void k_lattice_to_sorted(Parts<T> p, Geo g, const T* lat, T* sorted) {
+    const long n = g.npart;
+    for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
+        const long L = lattice_index(p.id[k], g.np);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) sorted[a * n + k] = lat[a * n + L];
+    }
+}
+
 // Tangent of the first half-kick and the drift of a step, at the state
 // before it (force f = acc at x):
 //   ph_dot = p_dot + K1 f_dot + cK1 f,   x_dot += Dr ph_dot + cDr (p + K1 f)
@@ -511,30 +551,27 @@ template <class T>
 __global__ void k_jvp_pre(Parts<T> p, Geo g, T* xdot, T* pdot, const T* fdot, T H, T k1, T dr,
                           T ck1, T cdr) {
     const long n = g.npart;
-    for (long k = blockIdx.x * (long)blockDim.x + threadIdx.x; k < n; k += (long)gridDim.x * blockDim.x) {
-        const long L = lattice_index(p.id[k], g.np);
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-            const T f = H * p.acc[a * n + k];
-            const T ph = H * p.mom[a * n + k] + k1 * f;
-            const T phd = pdot[a * n + L] + k1 * fdot[a * n + L] + ck1 * f;
-            xdot[a * n + L] += dr * phd + cdr * ph;
-            pdot[a * n + L] = phd;
-        }
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < 3 * n; i += (long)gridDim.x * blockDim.x) {
+        const T f = H * p.acc[i];
+        const T ph = H * p.mom[i] + k1 * f;
+        const T phd = pdot[i] + k1 * fdot[i] + ck1 * f;
+        xdot[i] += dr * phd + cdr * ph;
+        pdot[i] = phd;
     }
 }
 
 // Readout part of the force tangent: f_dot_j = u_dot . grad R(x, M_j) on the
-// force meshes M_j of the current state, into fbc (sorted, cells); the
-// position tangent u_dot = x_dot / H into xbc (sorted, cells) for the tangent
-// paint, and max of mass sum_a |u_dot_a| into vmax_bits.
+// force meshes M_j of the current state, into fbc (cells), u_dot = x_dot / H;
+// and a bound of mass sum_a |u_dot_a| (the tangent paint's scale) into
+// vmax_bits, one atomic per workgroup.
 template <class T>
 __global__ __launch_bounds__(AB) void k_fjvp_gather(Parts<T> p, SortBufs s, Geo g, const T* f0,
                                                     const T* f1, const T* f2, const T* xdot,
-                                                    T invH, T mass, T* xbc, T* fbc,
+                                                    T invH, T mass, T* fbc,
                                                     uint32_t* vmax_bits) {
     constexpr int TC = TE * TE * TE;
     __shared__ T ft[3][TC];
+    __shared__ float redf[AB / 64];
     const int tid = threadIdx.x;
     const int t = xcd_remap(blockIdx.x, gridDim.x);
     const int tx = t / (g.nt * g.nt), ty = (t / g.nt) % g.nt, tz = t % g.nt;
@@ -552,17 +589,13 @@ __global__ __launch_bounds__(AB) void k_fjvp_gather(Parts<T> p, SortBufs s, Geo 
         uint32_t k = k0 + tid;
         if (k < hi) {
             uint32_t id = p.id[k];
-            long L = lattice_index(id, g.np);
             T d[3] = {p.disp[k], p.disp[n + k], p.disp[2 * n + k]};
             int base;
             T w[3][2];
             cic_setup(g, id, d, ox, oy, oz, base, w);
             T ud[3];
 #pragma unroll
-            for (int a = 0; a < 3; ++a) {
-                ud[a] = invH * xdot[a * n + L];
-                xbc[a * n + k] = ud[a];
-            }
+            for (int a = 0; a < 3; ++a) ud[a] = invH * xdot[a * n + k];
             vmax = fmaxf(vmax, (float)(mass * (fabs(ud[0]) + fabs(ud[1]) + fabs(ud[2]))));
 #pragma unroll
             for (int j = 0; j < 3; ++j) {
@@ -572,16 +605,14 @@ __global__ __launch_bounds__(AB) void k_fjvp_gather(Parts<T> p, SortBufs s, Geo 
             }
         }
     }
-    for (int off = 32; off > 0; off >>= 1) vmax = fmaxf(vmax, __shfl_xor(vmax, off));
     // a bound slightly above the maximum keeps float rounding of the bound
     // from under-sizing the fixed-point scale
-    if ((tid & 63) == 0 && vmax > 0.f) atomicMax(vmax_bits, __float_as_uint(vmax * 1.0001f));
+    block_max<AB>(vmax_bits, vmax * 1.0001f, redf);
 }
 
 // Paint part of the force tangent and the second half-kick: with M_dot_j the
 // force meshes of the tangent density, f_dot_j = fbc_j + R(x, M_dot_j);
-// f_dot (lattice, Mpc/h) = H f_dot_j and, if pdot is set,
-// p_dot += H (K2 f_dot_j + cK2 f_j).
+// f_dot (Mpc/h) = H f_dot_j and, if pdot is set, p_dot += H (K2 f_dot_j + cK2 f_j).
 template <class T>
 __global__ __launch_bounds__(AB) void k_fjvp_readout_kick(Parts<T> p, SortBufs s, Geo g, const T* m0,
                                                           const T* m1, const T* m2, const T* fbc,
@@ -604,7 +635,6 @@ __global__ __launch_bounds__(AB) void k_fjvp_readout_kick(Parts<T> p, SortBufs s
         uint32_t k = k0 + tid;
         if (k < hi) {
             uint32_t id = p.id[k];
-            long L = lattice_index(id, g.np);
             T d[3] = {p.disp[k], p.disp[n + k], p.disp[2 * n + k]};
             int base;
             T w[3][2];
@@ -620,8 +650,8 @@ __global__ __launch_bounds__(AB) void k_fjvp_readout_kick(Parts<T> p, SortBufs s
                         for (int c = 0; c < 2; ++c)
                             val += w[0][a] * w[1][b] * w[2][c] * ft[j][base + (a * TE + b) * TE + c];
                 const T fd = fbc[j * n + k] + val;
-                fdot[j * n + L] = H * fd;
-                if (pdot) pdot[j * n + L] += H * (k2 * fd + ck2 * p.acc[j * n + k]);
+                fdot[j * n + k] = H * fd;
+                if (pdot) pdot[j * n + k] += H * (k2 * fd + ck2 * p.acc[j * n + k]);
             }
         }
     }
@@ -699,8 +729,7 @@ __global__ __launch_bounds__(256) void k_lens_jvp(Parts<T> p, Geo g, LensArgs<T>
             u[a] = T(c) + (v - fl);
         }
         if (!(isfinite(u[0]) && isfinite(u[1]) && isfinite(u[2]))) continue;
-        const long L = lattice_index(id, g.np);
-        const T xb[3] = {xdot[L], xdot[n + L], xdot[2 * n + L]};
+        const T xb[3] = {xdot[k], xdot[n + k], xdot[2 * n + k]};
         if (la.rot) {
             const int mz0 = max((int)floor(cnear / nmf), 0), mz1 = (int)floor(cfar / nmf);
             for (int nz = mz0; nz <= mz1; ++nz) {
@@ -846,19 +875,25 @@ void launch_ic_tangent(const T* t0, const T* t1, const T* t2, const T* s0, const
 }
 
 template <class T>
+void launch_lattice_to_sorted(Parts<T> p, Geo g, const T* lat, T* sorted, hipStream_t st) {
+    hipLaunchKernelGGL(k_lattice_to_sorted<T>, dim3(grid_of(g.npart, 16384)), dim3(256), 0, st, p, g,
+                       lat, sorted);
+}
+
+template <class T>
 void launch_jvp_pre(Parts<T> p, Geo g, T* xdot, T* pdot, const T* fdot, T H, T k1, T dr, T ck1,
                     T cdr, hipStream_t st) {
-    hipLaunchKernelGGL(k_jvp_pre<T>, dim3(grid_of(g.npart, 16384)), dim3(256), 0, st, p, g, xdot,
-                       pdot, fdot, H, k1, dr, ck1, cdr);
+    hipLaunchKernelGGL(k_jvp_pre<T>, dim3(grid_of(3 * g.npart, 16384)), dim3(256), 0, st, p, g,
+                       xdot, pdot, fdot, H, k1, dr, ck1, cdr);
 }
 
 template <class T>
 void launch_fjvp_gather(Parts<T> p, SortBufs s, Geo g, const T* f0, const T* f1, const T* f2,
-                        const T* xdot, T invH, T mass, T* xbc, T* fbc, uint32_t* vmax_bits,
+                        const T* xdot, T invH, T mass, T* fbc, uint32_t* vmax_bits,
                         hipStream_t st) {
     int ntiles = g.nt * g.nt * g.nt;
     hipLaunchKernelGGL(k_fjvp_gather<T>, dim3(ntiles), dim3(AB), 0, st, p, s, g, f0, f1, f2, xdot,
-                       invH, mass, xbc, fbc, vmax_bits);
+                       invH, mass, fbc, vmax_bits);
 }
 
 template <class T>
@@ -887,9 +922,10 @@ void launch_map_add(T* kdot, int npix, int nsrc, const MapAdd<T>& mv, hipStream_
     template void launch_lin<T>(T*, const T*, T, T, long, hipStream_t);                              \
     template void launch_ic_tangent<T>(const T*, const T*, const T*, const T*, const T*, const T*,   \
                                        T*, T*, T, T, T, T, T, long, hipStream_t);                    \
+    template void launch_lattice_to_sorted<T>(Parts<T>, Geo, const T*, T*, hipStream_t);             \
     template void launch_jvp_pre<T>(Parts<T>, Geo, T*, T*, const T*, T, T, T, T, T, hipStream_t);   \
     template void launch_fjvp_gather<T>(Parts<T>, SortBufs, Geo, const T*, const T*, const T*,       \
-                                        const T*, T, T, T*, T*, uint32_t*, hipStream_t);             \
+                                        const T*, T, T, T*, uint32_t*, hipStream_t);                 \
     template void launch_fjvp_readout_kick<T>(Parts<T>, SortBufs, Geo, const T*, const T*, const T*, \
                                               const T*, T, T, T, T*, T*, hipStream_t);               \
     template void launch_lens_jvp<T>(Parts<T>, Geo, const LensArgs<T>&, const LensVjpArgs<T>&,       \

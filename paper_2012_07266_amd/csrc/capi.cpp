@@ -217,11 +217,11 @@ struct SimBase {
     virtual int step_vjp(double a0, double a1, double a2, void* xbar, void* pbar, double* cb) = 0;
     virtual int init_ic_vjp(double a1, const void* xbar, const void* pbar, void* nbar,
                             double* cb) = 0;
-    virtual int init_ic_jvp(const void* nd, double om_dot, double s8_dot, void* xd, void* pd,
-                            void* fd) = 0;
-    virtual int force_jvp(const void* xd, void* fd) = 0;
-    virtual int step_jvp(double a0, double a1, double om_dot, void* xd, void* pd, void* fd) = 0;
-    virtual int lens_jvp(double a0, double a1, const void* xd, double om_dot, void* kd) = 0;
+    virtual int init_ic_jvp(const void* nd, double om_dot, double s8_dot) = 0;
+    virtual int set_tangent(const void* xd, const void* pd, double om_dot) = 0;
+    virtual int get_tangent(void* xd, void* pd, void* fd) = 0;
+    virtual int step_jvp(double a0, double a1) = 0;
+    virtual int lens_jvp(double a0, double a1, void* kd) = 0;
 };
 
 template <class T> struct Sim final : SimBase {
@@ -261,22 +261,31 @@ template <class T> struct Sim final : SimBase {
     // last kick was kdk_k2 times the force now in acc (else kdk_a1 < 0)
     double kdk_a0 = -1.0, kdk_a1 = -1.0;
     T kdk_k2 = T(0);
-    // PGD correction of the projected positions: S = alpha0 a^mu times the
-    // force of the density filtered by exp(-k_l^2/k^2) exp(-(k/k_s)^4)
     // replica rotation: replica (nx, ny, nz) is the box under one of the 48
     // cube symmetries, hashed from its offsets and rot_seed
     bool rot = false;
     uint64_t rot_seed = 0;
+    // PGD correction of the projected positions: S = alpha0 a^mu times the
+    // force of the density filtered by exp(-k_l^2/k^2) exp(-(k/k_s)^4)
     bool pgd = false;
     double pgd_alpha0 = 0, pgd_mu = 0;
     T* pgd_g = nullptr;            // [3 (Nm/2)^2 + 1] filtered Green's function
     T* pgd_s = nullptr;            // [3][Np^3] filtered force at the particles
     uint32_t* pgd_bits = nullptr;  // max |pgd_s| (float bits)
+    // forward-mode tangent of (x, p, f) along (noise, Omega_m, sigma_8), in
+    // tile order and Mpc/h, allocated on first use: x_dot and p_dot (each
+    // with a second buffer the sort's scatter permutes into) and f_dot
+    T* tan_mem = nullptr;
+    T *tx = nullptr, *tx_alt = nullptr, *tp = nullptr, *tp_alt = nullptr, *tf = nullptr;
+    bool tan_valid = false;  // the tangent belongs to the current state
+    bool tan_carry = false;  // the next sort permutes the tangent too
+    double tan_om = 0;       // its Omega_m component
     double cell = 0;  // mesh cell, Mpc/h
     int ntiles = 0;
 
     ~Sim() override {
         if (arena) (void)hipFree(arena);
+        if (tan_mem) (void)hipFree(tan_mem);
         if (pgd_g) (void)hipFree(pgd_g);
         if (pgd_s) (void)hipFree(pgd_s);
         if (pgd_bits) (void)hipFree(pgd_bits);
@@ -306,6 +315,7 @@ template <class T> struct Sim final : SimBase {
         cell = p->box / p->nm;
         a_cur = -1.0;
         ic_fresh = false;
+        tan_valid = false;
         kdk_a0 = kdk_a1 = -1.0;
         meshes_valid = false;
     }
@@ -461,7 +471,19 @@ template <class T> struct Sim final : SimBase {
         launch_fill_u32(sb.count, 0u, ntiles, st);
         { ProfScope ps(prof, "kick_drift_key"); launch_kick_drift_key<T>(cur, sb, geo, kick, drift, mode, status, st); }
         { ProfScope ps(prof, "scan"); launch_scan(sb.count, sb.start, scan_sum, ntiles, st); }
-        { ProfScope ps(prof, "scatter"); launch_scatter<T>(cur, alt, sb, geo, st); }
+        if (tan_carry) {
+            TanCarry<T> tc;
+            tc.x_src = tx;
+            tc.x_dst = tx_alt;
+            tc.p_src = tp;
+            tc.p_dst = tp_alt;
+            { ProfScope ps(prof, "scatter_tangent"); launch_scatter<T>(cur, alt, sb, geo, st, tc); }
+            std::swap(tx, tx_alt);
+            std::swap(tp, tp_alt);
+        } else {
+            ProfScope ps(prof, "scatter");
+            launch_scatter<T>(cur, alt, sb, geo, st);
+        }
         std::swap(cur.disp, alt.disp);
         std::swap(cur.mom, alt.mom);
         std::swap(cur.id, alt.id);
@@ -554,6 +576,7 @@ template <class T> struct Sim final : SimBase {
         force(T(0), 0);
         a_cur = a0;
         ic_fresh = true;
+        tan_valid = false;
         kdk_a0 = kdk_a1 = -1.0;
         return check_launch();
     }
@@ -569,6 +592,7 @@ template <class T> struct Sim final : SimBase {
         force(k2, 1);
         a_cur = a1;
         ic_fresh = false;
+        tan_valid = false;  // a tangent step sets it again
         kdk_a0 = a0;
         kdk_a1 = a1;
         kdk_k2 = k2;
@@ -761,6 +785,7 @@ template <class T> struct Sim final : SimBase {
         meshes_valid = true;
         a_cur = agrid[nsteps];
         ic_fresh = false;
+        tan_valid = false;
         kdk_a0 = agrid[nsteps - 1];
         kdk_a1 = agrid[nsteps];
         kdk_k2 = (T)cosmo.kick(0.5 * (kdk_a0 + kdk_a1), kdk_a1, kdk_a1);
@@ -784,6 +809,7 @@ template <class T> struct Sim final : SimBase {
         force(T(0), 0);
         a_cur = a;
         ic_fresh = false;
+        tan_valid = false;
         kdk_a0 = kdk_a1 = -1.0;
         return check_launch();
     }
@@ -996,10 +1022,26 @@ template <class T> struct Sim final : SimBase {
     }
 
     // ---- forward mode (tangents) ---------------------------------------------
-    // Force tangent at the current state along xd (lattice, Mpc/h) into fd;
-    // with pd set, also the second half-kick p_dot += K2 f_dot + ck2 f.
-    // Leaves the meshes holding the tangent's force meshes.
-    void force_jvp_cur(const T* xd, T* pd, T* fd, T k2, T ck2) {
+    int ensure_tangent() {
+        if (tan_mem) return PM_OK;
+        const size_t n3 = 3 * (size_t)geo.npart;
+        if (hipMalloc(&tan_mem, 5 * n3 * sizeof(T)) != hipSuccess) {
+            (void)hipGetLastError();
+            tan_mem = nullptr;
+            return PM_ENOMEM;
+        }
+        tx = tan_mem;
+        tx_alt = tan_mem + n3;
+        tp = tan_mem + 2 * n3;
+        tp_alt = tan_mem + 3 * n3;
+        tf = tan_mem + 4 * n3;
+        return PM_OK;
+    }
+
+    // Force tangent at the current state along tx into tf; with pd set, also
+    // the second half-kick p_dot += K2 f_dot + ck2 f.  Leaves the meshes
+    // holding the tangent's force meshes.
+    void force_jvp_cur(T* pd, T k2, T ck2) {
         const T H = (T)cell;
         const T mass = (T)std::pow((double)geo.B, 3);
         if (!meshes_valid) {
@@ -1009,28 +1051,30 @@ template <class T> struct Sim final : SimBase {
         }
         launch_fill_u32(fmax_bits, 0u, 1, st);
         { ProfScope ps(prof, "jvp_gather");
-          launch_fjvp_gather<T>(cur, sb, geo, mesh[0], mesh[1], mesh[2], xd, T(1) / H, mass, xbc, fbc,
+          launch_fjvp_gather<T>(cur, sb, geo, mesh[0], mesh[1], mesh[2], tx, T(1) / H, mass, fbc,
                                 fmax_bits, st); }
         meshes_valid = false;
+        // the tangent paint reads x_dot (Mpc/h): mass / H turns it into cells
         { ProfScope ps(prof, "jvp_paint");
-          launch_paint_tangent<T>(cur, sb, geo, mass, mesh[0], halo, xbc, fmax_bits, st, false); }
+          launch_paint_tangent<T>(cur, sb, geo, mass / H, mesh[0], halo, tx, fmax_bits, st, false); }
         fft_forward_grad(P.nm, nullptr, tw_nm, tw_hm, twp_nm, paint_halo_merge<T>(geo, halo));
         { ProfScope ps(prof, "jvp_readout_kick");
-          launch_fjvp_readout_kick<T>(cur, sb, geo, mesh[0], mesh[1], mesh[2], fbc, H, k2, ck2, pd, fd,
+          launch_fjvp_readout_kick<T>(cur, sb, geo, mesh[0], mesh[1], mesh[2], fbc, H, k2, ck2, pd, tf,
                                       st); }
     }
 
-    int init_ic_jvp(const void* nd, double om_dot, double s8_dot, void* xd, void* pd,
-                    void* fd) override {
-        if (!nd || !xd || !pd || !fd || !std::isfinite(om_dot) || !std::isfinite(s8_dot))
-            return PM_EINVAL;
+    int init_ic_jvp(const void* nd, double om_dot, double s8_dot) override {
+        if (!nd || !std::isfinite(om_dot) || !std::isfinite(s8_dot)) return PM_EINVAL;
         if (!ic_fresh) return PM_ESTATE;
+        int rc = ensure_tangent();
+        if (rc) return rc;
         const int np = P.np;
         const long n = geo.npart;
         const double a0 = a_cur;
         const T H = (T)cell;
-        T* x_ = reinterpret_cast<T*>(xd);
-        T* p_ = reinterpret_cast<T*>(pd);
+        // lattice-order tangents go to the spare buffers first
+        T* xl = tx_alt;
+        T* pl = tp_alt;
         meshes_valid = false;
         // displacement tangent of the noise direction; sigma_8 scales the
         // noise, so its tangent adds (s8_dot / s8) noise
@@ -1040,65 +1084,89 @@ template <class T> struct Sim final : SimBase {
         if (om_dot != 0.0) {
             // + Om_dot dS/dOm (the amplitude table's Omega_m difference), then
             // the growth factors' difference times the displacement itself
-            for (int j = 0; j < 3; ++j) launch_lin<T>(x_ + j * n, mesh[j], T(0), T(1), n, st);
+            for (int j = 0; j < 3; ++j) launch_lin<T>(xl + j * n, mesh[j], T(0), T(1), n, st);
             HIPCHK(hipMemcpyAsync(mesh[0], noise_copy, n * sizeof(T), hipMemcpyDeviceToDevice, st));
             fft_forward_grad(np, g_ic_dom, tw_np, tw_hp, twp_np);
-            for (int j = 0; j < 3; ++j) launch_lin<T>(x_ + j * n, mesh[j], T(1), (T)om_dot, n, st);
+            for (int j = 0; j < 3; ++j) launch_lin<T>(xl + j * n, mesh[j], T(1), (T)om_dot, n, st);
             HIPCHK(hipMemcpyAsync(mesh[0], noise_copy, n * sizeof(T), hipMemcpyDeviceToDevice, st));
             fft_forward_grad(np, g_ic, tw_np, tw_hp, twp_np);
             const double dd0 = (cosmo_p.D(a0) - cosmo_m.D(a0)) / (2 * DOM);
             const double dgp0 = (cosmo_p.gp(a0) - cosmo_m.gp(a0)) / (2 * DOM);
-            launch_ic_tangent<T>(x_, x_ + n, x_ + 2 * n, mesh[0], mesh[1], mesh[2], x_, p_,
+            launch_ic_tangent<T>(xl, xl + n, xl + 2 * n, mesh[0], mesh[1], mesh[2], xl, pl,
                                  (T)cosmo.D(a0), (T)cosmo.gp(a0), (T)(om_dot * dd0),
                                  (T)(om_dot * dgp0), H, n, st);
         } else {
-            launch_ic_tangent<T>(mesh[0], mesh[1], mesh[2], mesh[0], mesh[1], mesh[2], x_, p_,
+            launch_ic_tangent<T>(mesh[0], mesh[1], mesh[2], mesh[0], mesh[1], mesh[2], xl, pl,
                                  (T)cosmo.D(a0), (T)cosmo.gp(a0), T(0), T(0), H, n, st);
         }
-        force_jvp_cur(x_, nullptr, reinterpret_cast<T*>(fd), T(0), T(0));
+        launch_lattice_to_sorted<T>(cur, geo, xl, tx, st);
+        launch_lattice_to_sorted<T>(cur, geo, pl, tp, st);
+        force_jvp_cur(nullptr, T(0), T(0));
+        tan_om = om_dot;
+        tan_valid = true;
         return check_launch();
     }
 
-    int force_jvp(const void* xd, void* fd) override {
-        if (!xd || !fd) return PM_EINVAL;
+    int set_tangent(const void* xd, const void* pd, double om_dot) override {
+        if (!xd || !pd || !std::isfinite(om_dot)) return PM_EINVAL;
         if (a_cur < 0) return PM_ESTATE;
-        force_jvp_cur(reinterpret_cast<const T*>(xd), nullptr, reinterpret_cast<T*>(fd), T(0), T(0));
+        int rc = ensure_tangent();
+        if (rc) return rc;
+        launch_lattice_to_sorted<T>(cur, geo, reinterpret_cast<const T*>(xd), tx, st);
+        launch_lattice_to_sorted<T>(cur, geo, reinterpret_cast<const T*>(pd), tp, st);
+        force_jvp_cur(nullptr, T(0), T(0));
+        tan_om = om_dot;
+        tan_valid = true;
         return check_launch();
     }
 
-    int step_jvp(double a0, double a1, double om_dot, void* xd, void* pd, void* fd) override {
-        if (!xd || !pd || !fd || !std::isfinite(om_dot)) return PM_EINVAL;
+    int get_tangent(void* xd, void* pd, void* fd) override {
+        if (!tan_valid) return PM_ESTATE;
+        const long n = geo.npart;
+        T* out[3] = {reinterpret_cast<T*>(xd), reinterpret_cast<T*>(pd), reinterpret_cast<T*>(fd)};
+        const T* src[3] = {tx, tp, tf};
+        for (int i = 0; i < 3; ++i)
+            if (out[i])
+                launch_sorted_to_lattice<T>(cur, geo, src[i], out[i], out[i] + n, out[i] + 2 * n, st);
+        return check_launch();
+    }
+
+    int step_jvp(double a0, double a1) override {
+        if (!tan_valid) return PM_ESTATE;
         if (!at_a(a0)) return PM_ESTATE;
         if (!(a1 > 0 && a1 <= 1.5)) return PM_EINVAL;
+        const double om_dot = tan_om;
         const double ah = 0.5 * (a0 + a1);
         const double k1 = cosmo.kick(a0, ah, a0), dr = cosmo.drift(a0, a1, ah);
         const double k2 = cosmo.kick(ah, a1, a1);
         const double dk1 = (cosmo_p.kick(a0, ah, a0) - cosmo_m.kick(a0, ah, a0)) / (2 * DOM);
         const double ddr = (cosmo_p.drift(a0, a1, ah) - cosmo_m.drift(a0, a1, ah)) / (2 * DOM);
         const double dk2 = (cosmo_p.kick(ah, a1, a1) - cosmo_m.kick(ah, a1, a1)) / (2 * DOM);
-        T* x_ = reinterpret_cast<T*>(xd);
-        T* p_ = reinterpret_cast<T*>(pd);
-        T* f_ = reinterpret_cast<T*>(fd);
         { ProfScope ps(prof, "jvp_kick_drift");
-          launch_jvp_pre<T>(cur, geo, x_, p_, f_, (T)cell, (T)k1, (T)dr, (T)(om_dot * dk1),
+          launch_jvp_pre<T>(cur, geo, tx, tp, tf, (T)cell, (T)k1, (T)dr, (T)(om_dot * dk1),
                             (T)(om_dot * ddr), st); }
-        int rc = step(a0, a1);  // the forward step: the kernels of pm_step
+        // the forward step with the kernels of pm_step; its sort carries the tangent
+        tan_carry = true;
+        int rc = step(a0, a1);
+        tan_carry = false;
         if (rc) return rc;
-        force_jvp_cur(x_, p_, f_, (T)k2, (T)(om_dot * dk2));
+        force_jvp_cur(tp, (T)k2, (T)(om_dot * dk2));
+        tan_valid = true;
         return check_launch();
     }
 
-    int lens_jvp(double a0, double a1, const void* xd, double om_dot, void* kd) override {
-        if (!xd || !kd || !std::isfinite(om_dot)) return PM_EINVAL;
+    int lens_jvp(double a0, double a1, void* kd) override {
+        if (!kd) return PM_EINVAL;
         if (interp || pgd) return PM_EINVAL;  // no tangent pass for these modes
-        if (!at_a(a1)) return PM_ESTATE;
+        if (!tan_valid || !at_a(a1)) return PM_ESTATE;
         LensArgs<T> la;
         LensVjpArgs<T> lv;
         double chi_near, chi_far;
         if (!derivative_lens_args(a0, a1, la, lv, chi_near, chi_far)) return PM_OK;
+        const double om_dot = tan_om;
         T* kdot = reinterpret_cast<T*>(kd);
         { ProfScope ps(prof, "lens_jvp");
-          launch_lens_jvp<T>(cur, geo, la, lv, reinterpret_cast<const T*>(xd), (T)om_dot, kdot, st); }
+          launch_lens_jvp<T>(cur, geo, la, lv, tx, (T)om_dot, kdot, st); }
         if (om_dot != 0.0) {
             // the mean term's Omega_m derivative at a fixed shell partition
             MapAdd<T> mv{};
@@ -1221,21 +1289,20 @@ int pm_init_ic_vjp(pm_sim* sim, double a1, const void* x_bar, const void* p_bar,
                    double cosmo_bar[2]) {
     return sim ? sim->impl->init_ic_vjp(a1, x_bar, p_bar, noise_bar, cosmo_bar) : PM_EINVAL;
 }
-int pm_init_ic_jvp(pm_sim* sim, const void* noise_dot, double omega_m_dot, double sigma8_dot,
-                   void* x_dot, void* p_dot, void* f_dot) {
-    return sim ? sim->impl->init_ic_jvp(noise_dot, omega_m_dot, sigma8_dot, x_dot, p_dot, f_dot)
-               : PM_EINVAL;
+int pm_init_ic_jvp(pm_sim* sim, const void* noise_dot, double omega_m_dot, double sigma8_dot) {
+    return sim ? sim->impl->init_ic_jvp(noise_dot, omega_m_dot, sigma8_dot) : PM_EINVAL;
 }
-int pm_force_jvp(pm_sim* sim, const void* x_dot, void* f_dot) {
-    return sim ? sim->impl->force_jvp(x_dot, f_dot) : PM_EINVAL;
+int pm_set_tangent(pm_sim* sim, const void* x_dot, const void* p_dot, double omega_m_dot) {
+    return sim ? sim->impl->set_tangent(x_dot, p_dot, omega_m_dot) : PM_EINVAL;
 }
-int pm_step_jvp(pm_sim* sim, double a0, double a1, double omega_m_dot, void* x_dot, void* p_dot,
-                void* f_dot) {
-    return sim ? sim->impl->step_jvp(a0, a1, omega_m_dot, x_dot, p_dot, f_dot) : PM_EINVAL;
+int pm_get_tangent(pm_sim* sim, void* x_dot, void* p_dot, void* f_dot) {
+    return sim ? sim->impl->get_tangent(x_dot, p_dot, f_dot) : PM_EINVAL;
 }
-int lens_project_jvp(pm_sim* sim, double a0, double a1, const void* x_dot, double omega_m_dot,
-                     void* kappa_dot) {
-    return sim ? sim->impl->lens_jvp(a0, a1, x_dot, omega_m_dot, kappa_dot) : PM_EINVAL;
+int pm_step_jvp(pm_sim* sim, double a0, double a1) {
+    return sim ? sim->impl->step_jvp(a0, a1) : PM_EINVAL;
+}
+int lens_project_jvp(pm_sim* sim, double a0, double a1, void* kappa_dot) {
+    return sim ? sim->impl->lens_jvp(a0, a1, kappa_dot) : PM_EINVAL;
 }
 int pm_background(const pm_sim* sim, double a, double out[3]) {
     return sim && out ? sim->impl->background(a, out) : PM_EINVAL;

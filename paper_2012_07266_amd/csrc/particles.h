@@ -79,11 +79,20 @@ void launch_kick_drift_key(Parts<T> p, SortBufs s, Geo g, T kick, T drift, int m
 // block_sum: scratch of (n + 1023) / 1024 entries (n <= 1024 * 1024).
 void launch_scan(const uint32_t* count, uint32_t* start, uint32_t* block_sum, int n,
                  hipStream_t st);
-// Permute disp, mom and id into tile order (dst), after launch_scan: each
-// particle takes a rank in its tile by counting the histogram down, which
-// leaves `count` at zero.
+// Tangent arrays ([3][npart], tile order) that a scatter carries with the
+// particles: x_src -> x_dst and p_src -> p_dst.  x_src == NULL carries none.
+template <class T> struct TanCarry {
+    const T* x_src = nullptr;
+    T* x_dst = nullptr;
+    const T* p_src = nullptr;
+    T* p_dst = nullptr;
+};
+// Permute disp, mom and id (and the tangents of tc) into tile order (dst),
+// after launch_scan: each particle takes a rank in its tile by counting the
+// histogram down, which leaves `count` at zero.
 template <class T>
-void launch_scatter(Parts<T> src, Parts<T> dst, SortBufs s, Geo g, hipStream_t st);
+void launch_scatter(Parts<T> src, Parts<T> dst, SortBufs s, Geo g, hipStream_t st,
+                    TanCarry<T> tc = TanCarry<T>());
 // CIC paint of tile-sorted particles by groups of tiles along axis 2:
 // interior cells go to rho, each group's upper halo shell to `halo` (size
 // paint_halo_elems); then the shells are added into the neighbours' faces,

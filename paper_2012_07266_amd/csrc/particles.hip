@@ -270,14 +270,17 @@ void launch_scan(const uint32_t* count, uint32_t* start, uint32_t* block_sum, in
 // nothing.
 constexpr int SU = 4;
 
-template <class T>
-__global__ __launch_bounds__(PB) void k_scatter(Parts<T> src, Parts<T> dst, SortBufs s, Geo g) {
+// With TAN the two tangent arrays of tc ([3][n] each) travel with the
+// particles (the forward-mode pass keeps its tangents in tile order).
+template <class T, bool TAN>
+__global__ __launch_bounds__(PB) void k_scatter(Parts<T> src, Parts<T> dst, SortBufs s, Geo g,
+                                                TanCarry<T> tc) {
     const long n = g.npart;
     for (long base = blockIdx.x * (long)(PB * SU); base < n; base += (long)gridDim.x * PB * SU) {
         bool valid[SU];
         long kc[SU];
         uint32_t key[SU], first[SU], idv[SU], top[SU];
-        T dv[SU][3], mv[SU][3];
+        T dv[SU][3], mv[SU][3], xv[TAN ? SU : 1][3], pv[TAN ? SU : 1][3];
         WaveGroup w[SU];
 #pragma unroll
         for (int u = 0; u < SU; ++u) {
@@ -293,6 +296,10 @@ __global__ __launch_bounds__(PB) void k_scatter(Parts<T> src, Parts<T> dst, Sort
             for (int a = 0; a < 3; ++a) {
                 dv[u][a] = src.disp[a * n + kc[u]];
                 mv[u][a] = src.mom[a * n + kc[u]];
+                if constexpr (TAN) {
+                    xv[u][a] = tc.x_src[a * n + kc[u]];
+                    pv[u][a] = tc.p_src[a * n + kc[u]];
+                }
             }
         }
 #pragma unroll
@@ -310,6 +317,10 @@ __global__ __launch_bounds__(PB) void k_scatter(Parts<T> src, Parts<T> dst, Sort
             for (int a = 0; a < 3; ++a) {
                 dst.disp[a * n + d] = dv[u][a];
                 dst.mom[a * n + d] = mv[u][a];
+                if constexpr (TAN) {
+                    tc.x_dst[a * n + d] = xv[u][a];
+                    tc.p_dst[a * n + d] = pv[u][a];
+                }
             }
             dst.id[d] = idv[u];
         }
@@ -317,10 +328,14 @@ __global__ __launch_bounds__(PB) void k_scatter(Parts<T> src, Parts<T> dst, Sort
 }
 
 template <class T>
-void launch_scatter(Parts<T> src, Parts<T> dst, SortBufs s, Geo g, hipStream_t st) {
+void launch_scatter(Parts<T> src, Parts<T> dst, SortBufs s, Geo g, hipStream_t st,
+                    TanCarry<T> tc) {
     long blocks = (g.npart + PB * SU - 1) / (PB * SU);
     if (blocks > 16384) blocks = 16384;
-    hipLaunchKernelGGL(k_scatter<T>, dim3(blocks), dim3(PB), 0, st, src, dst, s, g);
+    if (tc.x_src)
+        hipLaunchKernelGGL((k_scatter<T, true>), dim3(blocks), dim3(PB), 0, st, src, dst, s, g, tc);
+    else
+        hipLaunchKernelGGL((k_scatter<T, false>), dim3(blocks), dim3(PB), 0, st, src, dst, s, g, tc);
 }
 
 // ---------------------------------------------------------------------------
@@ -915,7 +930,7 @@ void launch_noise(T* out, long n, uint64_t seed, hipStream_t st) {
     template void launch_scale_copy<T>(T*, const T*, T, long, hipStream_t);                       \
     template void launch_kick_drift_key<T>(Parts<T>, SortBufs, Geo, T, T, int, uint32_t*,        \
                                            hipStream_t);                                          \
-    template void launch_scatter<T>(Parts<T>, Parts<T>, SortBufs, Geo, hipStream_t);              \
+    template void launch_scatter<T>(Parts<T>, Parts<T>, SortBufs, Geo, hipStream_t, TanCarry<T>); \
     template void launch_paint<T>(Parts<T>, SortBufs, Geo, T, T*, T*, hipStream_t, bool);         \
     template void launch_paint_values<T>(Parts<T>, SortBufs, Geo, T, T*, T*, const T*,            \
                                          const uint32_t*, hipStream_t, bool);                     \

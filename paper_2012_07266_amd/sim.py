@@ -236,37 +236,35 @@ class Simulation:
         return _ptr(t)
 
     def init_ic_jvp(self, noise_dot, omega_m_dot=0.0, sigma8_dot=0.0):
-        """Tangents (x_dot, p_dot, f_dot) [3][Np^3] of the initial conditions
-        that init_ic just made, along (noise_dot, Omega_m_dot, sigma8_dot)."""
-        n = self.n_particles
+        """Start the tangent of the initial conditions that init_ic just made,
+        along (noise_dot, Omega_m_dot, sigma8_dot); the library holds it."""
         nd = noise_dot.to(device=self.device, dtype=self.dtype).contiguous()
-        out = [torch.empty((3, n), dtype=self.dtype, device=self.device) for _ in range(3)]
-        check(lib().pm_init_ic_jvp(self._h, _ptr(nd), float(omega_m_dot), float(sigma8_dot),
-                                   *(_ptr(t) for t in out)), "pm_init_ic_jvp")
+        check(lib().pm_init_ic_jvp(self._h, _ptr(nd), float(omega_m_dot), float(sigma8_dot)),
+              "pm_init_ic_jvp")
         self._tangent_keep = nd
+
+    def set_tangent(self, x_dot, p_dot, omega_m_dot=0.0):
+        """Tangent (x_dot, p_dot) [3][Np^3] of the current state, lattice order."""
+        sh = (3, self.n_particles)
+        check(lib().pm_set_tangent(self._h, self._tangent(x_dot, sh), self._tangent(p_dot, sh),
+                                   float(omega_m_dot)), "pm_set_tangent")
+        self._tangent_keep = (x_dot, p_dot)
+
+    def get_tangent(self):
+        """(x_dot, p_dot, f_dot) [3][Np^3] in lattice order."""
+        out = [torch.empty((3, self.n_particles), dtype=self.dtype, device=self.device)
+               for _ in range(3)]
+        check(lib().pm_get_tangent(self._h, *(_ptr(t) for t in out)), "pm_get_tangent")
         return tuple(out)
 
-    def force_jvp(self, x_dot):
-        """Tangent of the force at the current positions along x_dot."""
-        n = self.n_particles
-        f_dot = torch.empty((3, n), dtype=self.dtype, device=self.device)
-        check(lib().pm_force_jvp(self._h, self._tangent(x_dot, (3, n)), _ptr(f_dot)),
-              "pm_force_jvp")
-        return f_dot
-
-    def step_jvp(self, a0, a1, x_dot, p_dot, f_dot, omega_m_dot=0.0):
-        """pm_step(a0, a1) with the tangents carried along, in place."""
-        sh = (3, self.n_particles)
-        check(lib().pm_step_jvp(self._h, float(a0), float(a1), float(omega_m_dot),
-                                self._tangent(x_dot, sh), self._tangent(p_dot, sh),
-                                self._tangent(f_dot, sh)), "pm_step_jvp")
+    def step_jvp(self, a0, a1):
+        """pm_step(a0, a1) with the tangent carried along."""
+        check(lib().pm_step_jvp(self._h, float(a0), float(a1)), "pm_step_jvp")
         self.a = float(a1)
 
-    def lens_jvp(self, a0, a1, x_dot, kappa_dot, omega_m_dot=0.0):
-        """kappa_dot += the shell's tangent along (x_dot, Omega_m_dot); state at a1."""
+    def lens_jvp(self, a0, a1, kappa_dot):
+        """kappa_dot += the shell's tangent; state at a1."""
         check(lib().lens_project_jvp(self._h, float(a0), float(a1),
-                                     self._tangent(x_dot, (3, self.n_particles)),
-                                     float(omega_m_dot),
                                      self._tangent(kappa_dot, (len(self.z_src), self.npix,
                                                                self.npix))),
               "lens_project_jvp")

@@ -82,10 +82,11 @@ def test_null_handles(lib):
     assert lib.pm_destroy(None) == PM_EINVAL
     assert lib.pm_step(None, 0.1, 0.2) == PM_EINVAL
     assert lib.lens_project(None, 0.1, 0.2, None) == PM_EINVAL
-    assert lib.pm_init_ic_jvp(None, None, 0.0, 0.0, None, None, None) == PM_EINVAL
-    assert lib.pm_force_jvp(None, None, None) == PM_EINVAL
-    assert lib.pm_step_jvp(None, 0.1, 0.2, 0.0, None, None, None) == PM_EINVAL
-    assert lib.lens_project_jvp(None, 0.1, 0.2, None, 0.0, None) == PM_EINVAL
+    assert lib.pm_init_ic_jvp(None, None, 0.0, 0.0) == PM_EINVAL
+    assert lib.pm_set_tangent(None, None, None, 0.0) == PM_EINVAL
+    assert lib.pm_get_tangent(None, None, None, None) == PM_EINVAL
+    assert lib.pm_step_jvp(None, 0.1, 0.2) == PM_EINVAL
+    assert lib.lens_project_jvp(None, 0.1, 0.2, None) == PM_EINVAL
     assert lib.pm_strerror(PM_EINVAL).decode().startswith("invalid")
 
 

@@ -1,5 +1,5 @@
-"""GPU forward-mode tangents (pm_init_ic_jvp, pm_force_jvp, pm_step_jvp,
-lens_project_jvp) against the oracle's hand-derived tangents (oracle/jvp.py,
+"""GPU forward-mode tangents (pm_init_ic_jvp, pm_set_tangent / pm_get_tangent,
+pm_step_jvp, lens_project_jvp) against the oracle's hand-derived tangents (oracle/jvp.py,
 pinned by finite differences), and the transpose identity with the GPU
 reverse pass at the gradient workload's full size."""
 import numpy as np
@@ -60,10 +60,10 @@ def test_force_and_step_tangents_match_oracle(dtype, shape):
     with new_sim(wl, dtype) as sim:
         T = lambda v: torch.tensor(v, dtype=dtype, device="cuda")
         sim.set_state(T(x0), T(p0), a[0])
-        xg, pg = T(xd0), T(pd0)
-        fg = sim.force_jvp(xg)
-        f0g = to_np(fg)
-        sim.step_jvp(a[0], a[1], xg, pg, fg, om_dot)
+        sim.set_tangent(T(xd0), T(pd0), om_dot)
+        f0g = to_np(sim.get_tangent()[2])
+        sim.step_jvp(a[0], a[1])
+        xg, pg, fg = sim.get_tangent()
         x1g, _ = sim.get_state()
         res = (to_np(xg), to_np(pg), to_np(fg), to_np(x1g))
         sim.sync()
@@ -114,10 +114,14 @@ def test_lens_tangent_of_static_field(dtype, seed):
         if seed is not None:
             sim.set_replica_rotation(seed)
         sim.set_state(torch.from_numpy(x), torch.zeros((3, 16 ** 3), dtype=torch.float64), a_near)
+        xdg = torch.tensor(xd, dtype=dtype, device="cuda")
+        zero = torch.zeros_like(xdg)
         kd = sim.new_maps()
-        sim.lens_jvp(a_far, a_near, torch.tensor(xd, dtype=dtype, device="cuda"), kd, om_dot)
+        sim.set_tangent(xdg, zero, om_dot)
+        sim.lens_jvp(a_far, a_near, kd)
         kdx = sim.new_maps()
-        sim.lens_jvp(a_far, a_near, torch.tensor(xd, dtype=dtype, device="cuda"), kdx, 0.0)
+        sim.set_tangent(xdg, zero, 0.0)
+        sim.lens_jvp(a_far, a_near, kdx)
         kg, kgx = to_np(kd), to_np(kdx)
         sim.sync()
     geom = lens.MapGeometry(wl.npix, wl.fov_deg, wl.z_src, c, rotation_seed=seed)
@@ -215,32 +219,33 @@ def test_tangent_error_paths():
     noise = torch.tensor(W.white_noise(16, 3), dtype=torch.float32, device="cuda")
     n = 16 ** 3
     z = lambda: torch.zeros((3, n), dtype=torch.float32, device="cuda")
-    with new_sim(wl) as sim:
-        with pytest.raises(MadlensError) as e:      # no initial conditions yet
-            sim.init_ic_jvp(noise)
-        assert e.value.code == PM_ESTATE
-        sim.init_ic(noise, 0.4)
+
+    def code(fn, *args):
         with pytest.raises(MadlensError) as e:
-            sim.init_ic_jvp(noise, float("nan"))
-        assert e.value.code == PM_EINVAL
-        xd, pd, fd = sim.init_ic_jvp(noise, 0.2, 0.1)
-        with pytest.raises(MadlensError) as e:      # state is at 0.4
-            sim.step_jvp(0.5, 0.6, xd, pd, fd)
-        assert e.value.code == PM_ESTATE
-        with pytest.raises(ValueError):             # wrong dtype
-            sim.step_jvp(0.4, 0.5, xd.double(), pd, fd)
-        sim.step_jvp(0.4, 0.5, xd, pd, fd)
-        with pytest.raises(MadlensError) as e:      # no longer the initial conditions
-            sim.init_ic_jvp(noise)
-        assert e.value.code == PM_ESTATE
+            fn(*args)
+        return e.value.code
+    with new_sim(wl) as sim:
+        assert code(sim.init_ic_jvp, noise) == PM_ESTATE     # no initial conditions yet
+        sim.init_ic(noise, 0.4)
+        assert code(sim.step_jvp, 0.4, 0.5) == PM_ESTATE     # no tangent yet
+        assert code(sim.init_ic_jvp, noise, float("nan")) == PM_EINVAL
+        sim.init_ic_jvp(noise, 0.2, 0.1)
+        assert code(sim.step_jvp, 0.5, 0.6) == PM_ESTATE     # state is at 0.4
+        with pytest.raises(ValueError):                       # wrong dtype
+            sim.set_tangent(z().double(), z())
+        sim.step_jvp(0.4, 0.5)
+        assert code(sim.init_ic_jvp, noise) == PM_ESTATE     # no longer the initial conditions
         kd = sim.new_maps()
         sim.set_interpolation(True)
-        with pytest.raises(MadlensError) as e:
-            sim.lens_jvp(0.4, 0.5, xd, kd)
-        assert e.value.code == PM_EINVAL
+        assert code(sim.lens_jvp, 0.4, 0.5, kd) == PM_EINVAL
         sim.set_interpolation(False)
-        sim.lens_jvp(0.4, 0.5, xd, kd, 0.3)
-        f2 = sim.force_jvp(z())
+        sim.lens_jvp(0.4, 0.5, kd)
+        xd, pd, fd = sim.get_tangent()
+        sim.step(0.5, 0.6)                                     # a plain step drops the tangent
+        assert code(sim.step_jvp, 0.6, 0.7) == PM_ESTATE
+        assert code(sim.get_tangent) == PM_ESTATE
+        sim.set_tangent(z(), z())
+        f2 = sim.get_tangent()[2]
         sim.sync()
-        assert torch.isfinite(kd).all() and torch.isfinite(xd).all()
-        assert torch.count_nonzero(f2) == 0          # zero tangent, zero force tangent
+        assert torch.isfinite(kd).all() and torch.isfinite(xd).all() and torch.isfinite(fd).all()
+        assert torch.count_nonzero(f2) == 0                    # zero tangent, zero force tangent
