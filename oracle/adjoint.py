@@ -127,29 +127,50 @@ def bilinear_gather_grad(t0, t1, kmap):
 
 
 def lens_vjp(x, a_far, a_near, kappa_bar, cosmo: Cosmology, box, np_side,
-             geom: lens.MapGeometry):
+             geom: lens.MapGeometry, sub=None):
     """Cotangent of positions for the shell's convergence (particle term).
 
     Per image: kappa += w(chi) B(t0, t1), t = (r_perp / chi) / dtheta + c,
     w = pref V_p (chi_s - chi) / (chi_s chi a(chi) Omega_pix).
+
+    With `sub` = (p_h, a_h) (sub-evolution, lens.project_shell's `sub`) an
+    image at end-of-step depth chi_e is projected at r' = r + dr p_h with
+    dr = (D(a(chi_e)) - D(a_near)) / g_p(a_h); with g the gradient of the
+    splat at r', the image's cotangents are
+      r_bar = g + e_z (d dr / d chi_e) (g . p_h),   p_h_bar = dr g,
+    and the call returns (x_bar, p_h_bar).
     """
     chi_far = float(cosmo.chi(a_far))
     chi_near = float(cosmo.chi(a_near))
     pref = lens_prefactor(cosmo.omega_m)
     vp = (box / np_side) ** 3
     xbar = np.zeros_like(x)
+    phbar = np.zeros_like(x) if sub is not None else None
     c = 0.5 * geom.npix - 0.5
+    if sub is not None:
+        p_h, a_h = sub
+        d_near, gp_h = cosmo.D(a_near), cosmo.gp(a_h)
     for idx, rx, ry, chi, sym in lens.shell_images(x, box, chi_near, chi_far, geom):
-        th0 = rx / chi
-        th1 = ry / chi
-        t0 = th0 / geom.dtheta + c
-        t1 = th1 / geom.dtheta + c
-        keep = (t0 > -1.0) & (t0 < geom.npix) & (t1 > -1.0) & (t1 < geom.npix)
+        perm, flips = lens.PERMS[sym // 8], sym % 8
+        sgn = [-1.0 if flips >> j & 1 else 1.0 for j in range(3)]
+        if sub is not None:
+            # the drift momentum in the image frame, and the move along it
+            ph = [sgn[j] * p_h[perm[j], idx] for j in range(3)]
+            ae = cosmo.a_of_chi_vec(chi)
+            dr = (cosmo.D_vec(ae) - d_near) / gp_h
+            ddr = cosmo.dD_da_vec(ae) * (-ae * ae * cosmo.E(ae) / 2997.92458) / gp_h
+            rx = rx + dr * ph[0]
+            ry = ry + dr * ph[1]
+            chi = chi + dr * ph[2]
+        t0 = rx / chi / geom.dtheta + c
+        t1 = ry / chi / geom.dtheta + c
+        keep = (t0 > -1.0) & (t0 < geom.npix) & (t1 > -1.0) & (t1 < geom.npix) & (chi > 0.0)
         if not np.any(keep):
             continue
         idx, rx, ry, chi, t0, t1 = idx[keep], rx[keep], ry[keep], chi[keep], t0[keep], t1[keep]
         a = cosmo.a_of_chi_vec(chi)
         dadchi = -a * a * cosmo.E(a) / 2997.92458
+        gx, gy, gz = (np.zeros(idx.size) for _ in range(3))
         for s, chis in enumerate(geom.chi_src):
             src = chi < chis
             if not np.any(src):
@@ -161,14 +182,20 @@ def lens_vjp(x, a_far, a_near, kappa_bar, cosmo: Cosmology, box, np_side,
             dw = pref * vp * dg / geom.omega_pix
             v, g0, g1 = bilinear_gather_grad(t0[src], t1[src], kappa_bar[s])
             inv = 1.0 / (ch * geom.dtheta)
-            gx = w * g0 * inv
-            gy = w * g1 * inv
-            gz = dw * v - w * (g0 * rx[src] + g1 * ry[src]) * inv / ch
-            # back from the image frame: image axis j is box axis perm[j]
-            perm, flips = lens.PERMS[sym // 8], sym % 8
+            gx[src] += w * g0 * inv
+            gy[src] += w * g1 * inv
+            gz[src] += dw * v - w * (g0 * rx[src] + g1 * ry[src]) * inv / ch
+        img = [gx, gy, gz]
+        if sub is not None:
+            ph = [v[keep] for v in ph]
+            dr, ddr = dr[keep], ddr[keep]
+            img = [gx, gy, gz + ddr * (gx * ph[0] + gy * ph[1] + gz * ph[2])]
             for j, gj in enumerate((gx, gy, gz)):
-                np.add.at(xbar[perm[j]], idx[src], -gj if flips >> j & 1 else gj)
-    return xbar
+                np.add.at(phbar[perm[j]], idx, sgn[j] * dr * gj)
+        # back from the image frame: image axis j is box axis perm[j]
+        for j, gj in enumerate(img):
+            np.add.at(xbar[perm[j]], idx, sgn[j] * gj)
+    return xbar if sub is None else (xbar, phbar)
 
 
 # ---------------------------------------------------------------------------
@@ -197,35 +224,41 @@ def ic_displacement_transpose(s_bar, cosmo: Cosmology, box):
 # full reverse pass
 # ---------------------------------------------------------------------------
 def forward_with_checkpoints(noise, cosmo, box, nm_side, a_grid, geom, shell_chis=None,
-                             src_cut=None):
+                             src_cut=None, interpolation=False):
     """Forward model; returns (kappa, states) with states[i] = (x_i, p_i).
 
     `shell_chis[i]` overrides chi(a_grid[i]) as shell boundary and `src_cut`
     the distances of the in-front-of-source test (to hold the shell partition
-    and the source membership fixed while the cosmology varies)."""
+    and the source membership fixed while the cosmology varies).
+    `interpolation` projects with sub-evolution (project_shell's `sub`)."""
     np_side = noise.shape[0]
     x, p = pm.zeldovich_ic(noise, cosmo, box, nm_side, a_grid[0])
     f = pm.particle_force(x, np_side, nm_side, box)
     states = [(x, p)]
     kappa = np.zeros((len(geom.chi_src), geom.npix, geom.npix))
     for i in range(len(a_grid) - 1):
-        x, p, f = pm.kdk_step(x, p, f, a_grid[i], a_grid[i + 1], cosmo, np_side, nm_side, box)
+        x, p, f, p_h = pm.kdk_step(x, p, f, a_grid[i], a_grid[i + 1], cosmo, np_side, nm_side,
+                                   box, drift_momentum=True)
         states.append((x, p))
         cb = None if shell_chis is None else (shell_chis[i + 1], shell_chis[i])
+        sub = (p_h, 0.5 * (a_grid[i] + a_grid[i + 1])) if interpolation else None
         kappa += lens.project_shell(x, a_grid[i], a_grid[i + 1], cosmo, box, np_side, geom,
-                                    chi_bounds=cb, src_cut=src_cut)
+                                    chi_bounds=cb, src_cut=src_cut, sub=sub)
     return kappa, states
 
 
 def kappa_vjp_noise(noise, kappa_bar, cosmo: Cosmology, box, nm_side, a_grid,
-                    geom: lens.MapGeometry):
+                    geom: lens.MapGeometry, interpolation=False):
     """d(sum kappa * kappa_bar)/d noise (Omega_m, sigma_8 fixed), float64.
 
     Reverse pass over the KDK steps, following the merged force-node
-    cotangent f_bar(x_{i+1}) = (K2_i + K1_{i+1}) pbar.
+    cotangent f_bar(x_{i+1}) = (K2_i + K1_{i+1}) pbar.  With sub-evolution
+    the shell's cotangent of the step's drift momentum p_h = p_{i+1} - K2 f
+    joins pbar at the drift (p_h does not pass through f(x_{i+1})).
     """
     np_side = noise.shape[0]
-    _, states = forward_with_checkpoints(noise, cosmo, box, nm_side, a_grid, geom)
+    _, states = forward_with_checkpoints(noise, cosmo, box, nm_side, a_grid, geom,
+                                         interpolation=interpolation)
     n = len(a_grid) - 1
     xbar = np.zeros((3, np_side ** 3))
     pbar = np.zeros((3, np_side ** 3))
@@ -238,10 +271,17 @@ def kappa_vjp_noise(noise, kappa_bar, cosmo: Cosmology, box, nm_side, a_grid,
     for i in range(n - 1, -1, -1):
         x1, p1 = states[i + 1]
         k1, dr, k2 = fac[i]
-        xbar += lens_vjp(x1, a_grid[i], a_grid[i + 1], kappa_bar, cosmo, box, np_side, geom)
+        phbar = 0.0
+        if interpolation:
+            ph = p1 - k2 * pm.particle_force(x1, np_side, nm_side, box)
+            lx, phbar = lens_vjp(x1, a_grid[i], a_grid[i + 1], kappa_bar, cosmo, box, np_side,
+                                 geom, sub=(ph, 0.5 * (a_grid[i] + a_grid[i + 1])))
+            xbar += lx
+        else:
+            xbar += lens_vjp(x1, a_grid[i], a_grid[i + 1], kappa_bar, cosmo, box, np_side, geom)
         kf = k2 + (fac[i + 1][0] if i + 1 < n else 0.0)
         xbar += force_vjp(x1, kf * pbar, np_side, nm_side, box)
-        pbar = pbar + dr * xbar
+        pbar = pbar + dr * xbar + phbar
     x0, _ = states[0]
     xbar += force_vjp(x0, fac[0][0] * pbar, np_side, nm_side, box)
     a0 = a_grid[0]
@@ -257,7 +297,7 @@ def _with_om(cosmo: Cosmology, om):
 
 
 def kappa_vjp_cosmo(noise, kappa_bar, cosmo: Cosmology, box, nm_side, a_grid,
-                    geom: lens.MapGeometry, dom=1e-5, terms=None):
+                    geom: lens.MapGeometry, dom=1e-5, terms=None, interpolation=False):
     """(noise_bar, d/dOmega_m, d/dsigma_8) of sum(kappa * kappa_bar).
 
     Omega_m follows the paper's scheme: the reverse pass gives the cotangent
@@ -276,6 +316,9 @@ def kappa_vjp_cosmo(noise, kappa_bar, cosmo: Cosmology, box, nm_side, a_grid,
     amplitude of the noise: d/dsigma8 = <noise_bar, noise>/sigma8.
     If `terms` is a list, every additive contribution to d/dOmega_m is
     appended to it (their magnitudes set the conditioning of the sum).
+    With `interpolation` the shells use sub-evolution; the drift momentum's
+    cotangent joins pbar at the drift, and the shell's Omega_m difference is
+    taken at fixed positions and drift momentum.
     """
     np_side = noise.shape[0]
     cp, cm = _with_om(cosmo, cosmo.omega_m + dom), _with_om(cosmo, cosmo.omega_m - dom)
@@ -283,7 +326,8 @@ def kappa_vjp_cosmo(noise, kappa_bar, cosmo: Cosmology, box, nm_side, a_grid,
                               rotation_seed=geom.rotation_seed)
     geom_m = lens.MapGeometry(geom.npix, np.degrees(geom.fov), geom.z_src, cm,
                               rotation_seed=geom.rotation_seed)
-    _, states = forward_with_checkpoints(noise, cosmo, box, nm_side, a_grid, geom)
+    _, states = forward_with_checkpoints(noise, cosmo, box, nm_side, a_grid, geom,
+                                         interpolation=interpolation)
     n = len(a_grid) - 1
 
     def factors(c):
@@ -307,15 +351,24 @@ def kappa_vjp_cosmo(noise, kappa_bar, cosmo: Cosmology, box, nm_side, a_grid,
     for i in range(n - 1, -1, -1):
         x1, p1 = states[i + 1]
         k1, dr, k2 = fac[i]
-        # lens at fixed positions: cosmology part and position part
+        f1 = pm.particle_force(x1, np_side, nm_side, box)
+        ah = 0.5 * (a_grid[i] + a_grid[i + 1])
+        sub = (p1 - k2 * f1, ah) if interpolation else None
+        # lens at fixed positions (and drift momenta): cosmology part and
+        # position part
         cb = (cosmo.chi(a_grid[i + 1]), cosmo.chi(a_grid[i]))
         kp = lens.project_shell(x1, a_grid[i], a_grid[i + 1], cp, box, np_side, geom_p,
-                                chi_bounds=cb, src_cut=geom.chi_src)
+                                chi_bounds=cb, src_cut=geom.chi_src, sub=sub)
         km = lens.project_shell(x1, a_grid[i], a_grid[i + 1], cm, box, np_side, geom_m,
-                                chi_bounds=cb, src_cut=geom.chi_src)
+                                chi_bounds=cb, src_cut=geom.chi_src, sub=sub)
         g_om += add(np.sum(kappa_bar * (kp - km)) / (2 * dom))
-        xbar += lens_vjp(x1, a_grid[i], a_grid[i + 1], kappa_bar, cosmo, box, np_side, geom)
-        f1 = pm.particle_force(x1, np_side, nm_side, box)
+        phbar = 0.0
+        if interpolation:
+            lx, phbar = lens_vjp(x1, a_grid[i], a_grid[i + 1], kappa_bar, cosmo, box, np_side,
+                                 geom, sub=sub)
+            xbar += lx
+        else:
+            xbar += lens_vjp(x1, a_grid[i], a_grid[i + 1], kappa_bar, cosmo, box, np_side, geom)
         dot = np.sum(pbar * f1)            # cotangent of K2_i and of K1_{i+1}
         g_om += add(dot * dfac[i][2])
         kf = k2
@@ -325,7 +378,7 @@ def kappa_vjp_cosmo(noise, kappa_bar, cosmo: Cosmology, box, nm_side, a_grid,
         xbar += force_vjp(x1, kf * pbar, np_side, nm_side, box)
         ph = p1 - k2 * f1                  # momentum at the half step
         g_om += add(np.sum(xbar * ph) * dfac[i][1])
-        pbar = pbar + dr * xbar
+        pbar = pbar + dr * xbar + phbar
     x0, p0 = states[0]
     f0 = pm.particle_force(x0, np_side, nm_side, box)
     g_om += add(np.sum(pbar * f0) * dfac[0][0])

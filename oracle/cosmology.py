@@ -162,6 +162,15 @@ class Cosmology:
         return 2.5 * self.omega_m * (float(self.dE_da(a)) * self._growth_integral(a)
                                      + 1.0 / (a ** 3 * e * e)) / self.du1
 
+    def dD_da_vec(self, a):
+        """Vectorised dD/da: with I(a) = D D_u(1) / ((5 Om / 2) E), the
+        derivative of (5 Om / 2) E I / D_u(1) is (E'/E) D + (5 Om / 2) /
+        (a^3 E^2 D_u(1))."""
+        a = np.asarray(a, dtype=np.float64)
+        e = self.E(a)
+        return (self.dE_da(a) / e * self.D_vec(a)
+                + 2.5 * self.omega_m / (a ** 3 * e * e * self.du1))
+
     def gp(self, a):
         """g_p(a) = a^3 E(a) dD/da: momentum per unit linear displacement."""
         a = float(a)
