@@ -224,13 +224,15 @@ def ic_displacement_transpose(s_bar, cosmo: Cosmology, box):
 # full reverse pass
 # ---------------------------------------------------------------------------
 def forward_with_checkpoints(noise, cosmo, box, nm_side, a_grid, geom, shell_chis=None,
-                             src_cut=None, interpolation=False):
+                             src_cut=None, interpolation=False, hold=None):
     """Forward model; returns (kappa, states) with states[i] = (x_i, p_i).
 
     `shell_chis[i]` overrides chi(a_grid[i]) as shell boundary and `src_cut`
     the distances of the in-front-of-source test (to hold the shell partition
     and the source membership fixed while the cosmology varies).
-    `interpolation` projects with sub-evolution (project_shell's `sub`)."""
+    `interpolation` projects with sub-evolution (project_shell's `sub`);
+    `hold` then decides the source membership of moved images at that
+    cosmology (project_shell's `hold`)."""
     np_side = noise.shape[0]
     x, p = pm.zeldovich_ic(noise, cosmo, box, nm_side, a_grid[0])
     f = pm.particle_force(x, np_side, nm_side, box)
@@ -243,7 +245,7 @@ def forward_with_checkpoints(noise, cosmo, box, nm_side, a_grid, geom, shell_chi
         cb = None if shell_chis is None else (shell_chis[i + 1], shell_chis[i])
         sub = (p_h, 0.5 * (a_grid[i] + a_grid[i + 1])) if interpolation else None
         kappa += lens.project_shell(x, a_grid[i], a_grid[i + 1], cosmo, box, np_side, geom,
-                                    chi_bounds=cb, src_cut=src_cut, sub=sub)
+                                    chi_bounds=cb, src_cut=src_cut, sub=sub, hold=hold)
     return kappa, states
 
 
@@ -318,7 +320,8 @@ def kappa_vjp_cosmo(noise, kappa_bar, cosmo: Cosmology, box, nm_side, a_grid,
     appended to it (their magnitudes set the conditioning of the sum).
     With `interpolation` the shells use sub-evolution; the drift momentum's
     cotangent joins pbar at the drift, and the shell's Omega_m difference is
-    taken at fixed positions and drift momentum.
+    taken at fixed positions and drift momentum, with the source membership
+    of each moved image held at its central-cosmology depth.
     """
     np_side = noise.shape[0]
     cp, cm = _with_om(cosmo, cosmo.omega_m + dom), _with_om(cosmo, cosmo.omega_m - dom)
@@ -358,9 +361,9 @@ def kappa_vjp_cosmo(noise, kappa_bar, cosmo: Cosmology, box, nm_side, a_grid,
         # position part
         cb = (cosmo.chi(a_grid[i + 1]), cosmo.chi(a_grid[i]))
         kp = lens.project_shell(x1, a_grid[i], a_grid[i + 1], cp, box, np_side, geom_p,
-                                chi_bounds=cb, src_cut=geom.chi_src, sub=sub)
+                                chi_bounds=cb, src_cut=geom.chi_src, sub=sub, hold=cosmo)
         km = lens.project_shell(x1, a_grid[i], a_grid[i + 1], cm, box, np_side, geom_m,
-                                chi_bounds=cb, src_cut=geom.chi_src, sub=sub)
+                                chi_bounds=cb, src_cut=geom.chi_src, sub=sub, hold=cosmo)
         g_om += add(np.sum(kappa_bar * (kp - km)) / (2 * dom))
         phbar = 0.0
         if interpolation:

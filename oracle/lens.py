@@ -167,7 +167,7 @@ def shell_images(x, box, chi_near, chi_far, geom: MapGeometry):
 
 def project_shell(x, a_far, a_near, cosmo: Cosmology, box, np_side,
                   geom: MapGeometry, include_mean=True, chi_bounds=None, src_cut=None,
-                  sub=None):
+                  sub=None, hold: Cosmology = None):
     """Convergence of one PM step's shell, [nsrc][npix][npix].
 
     x are the positions at a_near (end of the step a_far -> a_near).
@@ -185,6 +185,11 @@ def project_shell(x, a_far, a_near, cosmo: Cosmology, box, np_side,
     a_p = a(chi_e), the scale factor of its own distance (one fixed-point
     iteration of chi -> depth of x(a(chi))); its angles, depth, a(chi) and
     weight are then those of the moved image.
+
+    `hold`, with `sub` and `src_cut`: the test "image in front of source s"
+    takes the depth the image is moved to under the cosmology `hold` (the
+    moved depth changes with the cosmology; holding the test keeps a
+    difference quotient in Omega_m from straddling that membership).
     """
     if chi_bounds is None:
         chi_far = float(cosmo.chi(a_far))
@@ -194,7 +199,7 @@ def project_shell(x, a_far, a_near, cosmo: Cosmology, box, np_side,
     pref = lens_prefactor(cosmo.omega_m)
     vp = (box / np_side) ** 3
     out = np.zeros((len(geom.chi_src), geom.npix, geom.npix))
-    t0s, t1s, chis = [], [], []
+    t0s, t1s, chis, chks = [], [], [], []
     # Images that cannot end in front of any source plane carry no weight in
     # any map: they are skipped before their a(chi) (with sub-evolution the
     # slack is the largest move along the step's drift, |Dr| |p_z|).
@@ -204,6 +209,8 @@ def project_shell(x, a_far, a_near, cosmo: Cosmology, box, np_side,
         p_h, a_h = sub
         d_near, gp_h = cosmo.D(a_near), cosmo.gp(a_h)
         dr_step = abs(cosmo.drift_factor(a_far, a_near, a_h))
+        if hold is not None:
+            hd_near, hgp_h = hold.D(a_near), hold.gp(a_h)
     chi_seen = None
     p_rot = {}   # symmetry -> drift momenta in the image frame
     for inz, rx, ry, chi, sym in shell_images(x, box, chi_near, chi_far, geom):
@@ -212,6 +219,7 @@ def project_shell(x, a_far, a_near, cosmo: Cosmology, box, np_side,
             if sub is None:
                 sel = np.nonzero(chi < cmax)[0]
                 chi_f = chi[sel]
+                chi_chk = chi_f
             else:
                 if sym not in p_rot:
                     p_rot[sym] = p_h if sym == 0 else apply_symmetry(p_h, sym)
@@ -220,6 +228,10 @@ def project_shell(x, a_far, a_near, cosmo: Cosmology, box, np_side,
                 isel = inz[sel]
                 dr = (cosmo.D_vec(cosmo.a_of_chi_vec(chi[sel])) - d_near) / gp_h
                 chi_f = chi[sel] + dr * ph[2, isel]
+                chi_chk = chi_f
+                if hold is not None:
+                    hdr = (hold.D_vec(hold.a_of_chi_vec(chi[sel])) - hd_near) / hgp_h
+                    chi_chk = chi[sel] + hdr * ph[2, isel]
         if sel.size == 0:
             continue
         rxs, rys = rx[sel], ry[sel]
@@ -233,11 +245,13 @@ def project_shell(x, a_far, a_near, cosmo: Cosmology, box, np_side,
         t0s.append(t0[keep])
         t1s.append(t1[keep])
         chis.append(chi_f[keep])
+        chks.append(chi_chk[keep])
     if chis:
         t0, t1, chi = np.concatenate(t0s), np.concatenate(t1s), np.concatenate(chis)
+        chk = np.concatenate(chks)
         a = cosmo.a_of_chi_vec(chi)
         for s, chis_ in enumerate(geom.chi_src):
-            src = chi < (chis_ if src_cut is None else src_cut[s])
+            src = chk < (chis_ if src_cut is None else src_cut[s])
             if not np.any(src):
                 continue
             w = pref * vp * (chis_ - chi[src]) / (chis_ * chi[src] * a[src]

@@ -189,9 +189,51 @@ def test_cosmology_gradients_with_subevolution_match_finite_differences():
         cc = Cosmology(om, sigma8=s8)
         gg = lens.MapGeometry(geom.npix, np.degrees(geom.fov), geom.z_src, cc)
         k, _ = adjoint.forward_with_checkpoints(noise, cc, box, nm, a, gg, shell_chis=chis,
-                                                src_cut=geom.chi_src, interpolation=True)
+                                                src_cut=geom.chi_src, interpolation=True,
+                                                hold=c)
         return np.sum(k * kbar)
     fd_om = (loss(om=0.3 + h) - loss(om=0.3 - h)) / (2 * h)
     fd_s8 = (loss(s8=0.8 + 1e-6) - loss(s8=0.8 - 1e-6)) / 2e-6
     assert abs(fd_s8 - g_s8) < 1e-5 * abs(g_s8)
     assert abs(fd_om - g_om) < 2 * h * abs(g_om)
+
+
+def test_held_membership_of_moved_images(cosmo):
+    """With sub-evolution an image's depth moves with Omega_m, so it can cross
+    a source plane within a difference step.  One image, moved along the line
+    of sight to 1e-6 Mpc/h in front of the z = 1 plane: holding the source
+    test at the central cosmology's moved depth gives, at h = 1e-5, the
+    derivative that an unheld difference gives at h = 1e-8 (where the image
+    stays in front), while the unheld difference at h = 1e-5 puts it behind
+    the plane on one side."""
+    geom = lens.MapGeometry(32, 2.0, (1.0,), cosmo)
+    box, np_side = 900.0, 10
+    a_far, a_near = 0.45, 0.55
+    ah = 0.5 * (a_far + a_near)
+    chis = geom.chi_src[0]
+    nz = math.floor(chis / box)
+    chi_e = chis + 2.0                       # behind the plane before the move
+    dr = (cosmo.D(cosmo.a_of_chi(chi_e)) - cosmo.D(a_near)) / cosmo.gp(ah)
+    pz = (-2.0 - 1e-6) / dr                  # moved to chi_s - 1e-6
+    # a quarter pixel off the map centre, no transverse momentum
+    off = 0.25 * geom.dtheta * chis
+    x = np.array([[0.5 * box + off], [0.5 * box - off], [chi_e - nz * box]])
+    ph = np.array([[0.0], [0.0], [pz]])
+    kbar = np.ones((1, 32, 32))
+    cb = (cosmo.chi(a_near), cosmo.chi(a_far))
+
+    def d(h, held):
+        vals = []
+        for om in (0.3 + h, 0.3 - h):
+            cc = Cosmology(om)
+            g = lens.MapGeometry(32, 2.0, (1.0,), cc)
+            vals.append(np.sum(kbar * lens.project_shell(
+                x, a_far, a_near, cc, box, np_side, g, include_mean=False, chi_bounds=cb,
+                src_cut=geom.chi_src, sub=(ph, ah), hold=cosmo if held else None)))
+        return (vals[0] - vals[1]) / (2 * h)
+    k0 = np.sum(lens.project_shell(x, a_far, a_near, cosmo, box, np_side, geom,
+                                   include_mean=False, sub=(ph, ah)))
+    assert k0 > 0                                # in front of the plane, on the map
+    ref = d(1e-8, False)
+    assert abs(d(1e-5, True) - ref) < 1e-4 * abs(ref)
+    assert abs(d(1e-5, False) - ref) > 1e-2 * abs(ref)
