@@ -160,7 +160,8 @@ int lens_project(pm_sim* sim, double a0, double a1, void* kappa);
  * depth, a(chi) and weight are those of the moved image (the image may then
  * fall behind a source plane or off the map).  lens_project then needs the
  * state that pm_step(a0, a1) (or pm_run ending at a1) left, where
- * p_h = p - K2 f (else PM_ESTATE); lens_project_vjp refuses it (PM_EINVAL).
+ * p_h = p - K2 f (else PM_ESTATE); lens_project_vjp differentiates it (see
+ * there), lens_project_jvp refuses it (PM_EINVAL).
  * on: 0 or 1.  Errors: PM_EINVAL (NULL sim). */
 int pm_set_interpolation(pm_sim* sim, int32_t on);
 
@@ -244,19 +245,31 @@ int pm_background(const pm_sim* sim, double a, double out[3]);
  *
  * lens_project_vjp: state at a1.  x_bar += (d kappa_shell / dx)^T kappa_bar,
  * cosmo_bar[0] += kappa_bar . d kappa_shell / dOmega_m at fixed positions.
- * kappa_bar: device [nsrc][npix][npix].  Errors: PM_ESTATE, PM_EINVAL. */
+ * kappa_bar: device [nsrc][npix][npix].  With sub-evolution on, the shell
+ * also depends on the step's drift momentum p_h = p - K2 f (the state's
+ * force at a1): an image at end-of-step depth chi_e is projected at
+ * r + dr p_h, dr = (D(a(chi_e)) - D(a1)) / g_p(a_h), so x_bar receives
+ * g + e_z (d dr / d chi_e)(g . p_h) per image (g the splat's gradient at the
+ * moved image), ph_bar (device [3][Np^3], lattice order, Mpc/h,
+ * ACCUMULATED; required, else PM_EINVAL) receives dr g, and cosmo_bar[0]
+ * the move's Omega_m derivative as well.  ph_bar belongs to pm_step_vjp of
+ * the same step; it may be NULL when sub-evolution is off.  The PGD
+ * correction has no reverse pass (PM_EINVAL).  Errors: PM_ESTATE, PM_EINVAL. */
 int lens_project_vjp(pm_sim* sim, double a0, double a1, const void* kappa_bar, void* x_bar,
-                     double cosmo_bar[2]);
+                     void* ph_bar, double cosmo_bar[2]);
 
 /* pm_step_vjp: reverse of the step a0 -> a1.  The state must be at a1 (the
  * end of the step; the force there is that of pm_set_state or pm_step).  a2 >
  * a1 is the end of the following step, whose first half-kick uses the same
  * force, or a2 <= 0 when a0 -> a1 is the last step.  On entry x_bar, p_bar
  * hold the cotangents of (x, p) at a1 (after every later step and shell has
- * been reversed); on return they hold those at a0 (in place).
+ * been reversed); on return they hold those at a0 (in place).  ph_bar
+ * (read only, may be NULL) is the cotangent of this step's drift momentum
+ * from lens_project_vjp(a0, a1) with sub-evolution: it joins p_bar at the
+ * drift (the drift momentum does not pass through the force at a1).
  * Errors: PM_ESTATE, PM_EINVAL. */
 int pm_step_vjp(pm_sim* sim, double a0, double a1, double a2, void* x_bar, void* p_bar,
-                double cosmo_bar[2]);
+                const void* ph_bar, double cosmo_bar[2]);
 
 /* pm_init_ic_vjp: the state must be the initial conditions (restored with
  * pm_set_state at a0, after pm_init_ic was run on this handle with the same

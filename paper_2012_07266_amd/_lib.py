@@ -68,8 +68,8 @@ SIGNATURES = {
     "pm_get_force": (_I, [_P, _P, _P, _P]),
     "pm_sync": (_I, [_P]),
     "pm_background": (_I, [_P, _D, ctypes.POINTER(_D)]),
-    "lens_project_vjp": (_I, [_P, _D, _D, _P, _P, ctypes.POINTER(_D)]),
-    "pm_step_vjp": (_I, [_P, _D, _D, _D, _P, _P, ctypes.POINTER(_D)]),
+    "lens_project_vjp": (_I, [_P, _D, _D, _P, _P, _P, ctypes.POINTER(_D)]),
+    "pm_step_vjp": (_I, [_P, _D, _D, _D, _P, _P, _P, ctypes.POINTER(_D)]),
     "pm_init_ic_vjp": (_I, [_P, _D, _P, _P, _P, ctypes.POINTER(_D)]),
     "pm_init_ic_jvp": (_I, [_P, _P, _D, _D]),
     "pm_set_tangent": (_I, [_P, _P, _P, _D]),

@@ -37,12 +37,17 @@ def reverse_pass(sim: Simulation, a_grid: Sequence[float], states, kappa_bar: to
     x_bar = torch.zeros((3, sim.n_particles), dtype=sim.dtype, device=sim.device)
     p_bar = torch.zeros_like(x_bar)
     cb = np.zeros(2)
+    # with sub-evolution each shell also has the cotangent of its step's
+    # drift momentum, which joins p_bar at that step's drift
+    ph_bar = torch.zeros_like(x_bar) if sim.interpolation else None
     for i in range(n - 1, -1, -1):
         x1, p1 = states[i + 1]
         sim.set_state(x1, p1, a_grid[i + 1])
-        sim.lens_vjp(a_grid[i], a_grid[i + 1], kappa_bar, x_bar, cb)
+        if ph_bar is not None:
+            ph_bar.zero_()
+        sim.lens_vjp(a_grid[i], a_grid[i + 1], kappa_bar, x_bar, cb, ph_bar)
         a2 = a_grid[i + 2] if i + 1 < n else -1.0
-        sim.step_vjp(a_grid[i], a_grid[i + 1], a2, x_bar, p_bar, cb)
+        sim.step_vjp(a_grid[i], a_grid[i + 1], a2, x_bar, p_bar, cb, ph_bar)
     x0, p0 = states[0]
     sim.set_state(x0, p0, a_grid[0])
     noise_bar = sim.init_ic_vjp(a_grid[1], x_bar, p_bar, cb)
@@ -96,10 +101,11 @@ class LensingModel:
     """
 
     def __init__(self, np_side, nm_side, box, npix, fov_deg, z_src, a_grid,
-                 dtype=torch.float32, **cosmo):
+                 dtype=torch.float32, interpolation=False, **cosmo):
         self.shape = (np_side, nm_side, box, npix, fov_deg, tuple(z_src))
         self.a_grid = [float(a) for a in a_grid]
         self.dtype = dtype
+        self.interpolation = bool(interpolation)
         self.cosmo = dict(cosmo)
         self._sims: Dict[Tuple[float, float], Simulation] = {}
 
@@ -108,6 +114,7 @@ class LensingModel:
         if key not in self._sims:
             np_side, nm_side, box, npix, fov, zs = self.shape
             self._sims[key] = Simulation(np_side, nm_side, box, npix, fov, zs, dtype=self.dtype,
+                                         interpolation=self.interpolation,
                                          omega_m=key[0], sigma8=key[1], **self.cosmo)
         return self._sims[key]
 

@@ -7,18 +7,28 @@ namespace ml {
 // Omega_m dependence of the lens weights at fixed particle position:
 // d chi_s / d Omega_m per source and d a(chi) / d Omega_m on the chi grid of
 // the a(chi) table (linear interpolation).
+// With sub-evolution (LensArgs::sub) also: d D(a(chi)) / d Omega_m on that
+// grid, d D(a1) / d Omega_m and d (1 / g_p(a_h)) / d Omega_m of the move, and
+// the output array of the drift-momentum cotangent ([3][npart], lattice
+// order, Mpc/h, accumulated).
 template <class T> struct LensVjpArgs {
     T omega_m;
     T dchis_dom[MAX_SRC];
     const T* dadom;  // [ntab]
     int ntab;
     T dchi;
-    __device__ __forceinline__ T dadom_at(T chi) const {
+    const T* ddom = nullptr;  // [ntab]
+    T dd_end_dom = T(0);
+    T dscale_dom = T(0);
+    T* phbar = nullptr;
+    __device__ __forceinline__ T dadom_at(T chi) const { return lin_at(dadom, chi); }
+    __device__ __forceinline__ T ddom_at(T chi) const { return lin_at(ddom, chi); }
+    __device__ __forceinline__ T lin_at(const T* tab, T chi) const {
         T xk = chi / dchi;
         int k = (int)floor(xk);
         k = min(max(k, 0), ntab - 2);
         T s = xk - T(k);
-        return (T(1) - s) * dadom[k] + s * dadom[k + 1];
+        return (T(1) - s) * tab[k] + s * tab[k + 1];
     }
 };
 
@@ -34,10 +44,12 @@ template <class T>
 void launch_fvjp_readout(Parts<T> p, SortBufs s, Geo g, const T* f0, const T* f1, const T* f2,
                          const T* xbar_in, const T* pbar_in, T H, T ckick, T* xbc, T* fbc,
                          double* dots, uint32_t* fmax_bits, hipStream_t st);
+// phbar (may be NULL): a drift-momentum cotangent added to pbar_out in mode 0.
 template <class T>
 void launch_fvjp_paintgrad(Parts<T> p, SortBufs s, Geo g, const T* rhobar, T mass, const T* xbc,
                            T H, int mode, T dr, T k2, T d0, T gp0, T* xbar_out, const T* pbar_in,
-                           T* pbar_out, T* sb0, T* sb1, T* sb2, double* dots, hipStream_t st);
+                           T* pbar_out, const T* phbar, T* sb0, T* sb1, T* sb2, double* dots,
+                           hipStream_t st);
 template <class T>
 void launch_dot3(const T* a0, const T* a1, const T* a2, const T* b0, const T* b1, const T* b2,
                  long n, double* dst, hipStream_t st);

@@ -175,7 +175,8 @@ __global__ __launch_bounds__(AB) void k_fvjp_paintgrad(Parts<T> p, SortBufs s, G
                                                        const T* rhobar, T mass, const T* xbc,
                                                        T H, int mode, T dr, T k2, T d0, T gp0,
                                                        T* xbar_out, const T* pbar_in, T* pbar_out,
-                                                       T* sb0, T* sb1, T* sb2, double* dots) {
+                                                       const T* phbar, T* sb0, T* sb1, T* sb2,
+                                                       double* dots) {
     constexpr int TC = TE * TE * TE;
     __shared__ T ft[TC];
     __shared__ double red[AB / 64];
@@ -213,7 +214,7 @@ __global__ __launch_bounds__(AB) void k_fvjp_paintgrad(Parts<T> p, SortBufs s, G
                     T ph = p.mom[a * n + k] - k2 * p.acc[a * n + k];
                     a1 += (double)xb[a] * (double)ph;
                     xbar_out[a * n + L] = xb[a] / H;
-                    pbar_out[a * n + L] = (pb[a] + dr * xb[a]) / H;
+                    pbar_out[a * n + L] = (pb[a] + dr * xb[a]) / H + (phbar ? phbar[a * n + L] : T(0));
                 }
             } else {
                 T* sbo[3] = {sb0, sb1, sb2};
@@ -290,20 +291,28 @@ __global__ __launch_bounds__(256) void k_map_sums(const T* kbar, long npix2, int
 //    gradient; position cotangent accumulated in registers, one write per
 //    particle (no atomics); Omega_m part of the weights reduced.
 // ---------------------------------------------------------------------------
+// Cubic Hermite interpolant of a (value, d/dchi) table on the chi grid, and
+// its derivative: the interpolation the projection uses.
 template <class T>
-__device__ __forceinline__ void a_interp(const LensArgs<T>& la, T chi, T& a, T& dadchi) {
+__device__ __forceinline__ void tab_interp(const T* tab, const LensArgs<T>& la, T chi, T& a,
+                                           T& dadchi) {
     T xk = chi / la.dchi;
     int k = (int)floor(xk);
     k = min(max(k, 0), la.ntab - 2);
     T s = xk - T(k);
-    T a0 = la.atab[2 * k], m0 = la.atab[2 * k + 1] * la.dchi;
-    T a1 = la.atab[2 * k + 2], m1 = la.atab[2 * k + 3] * la.dchi;
+    T a0 = tab[2 * k], m0 = tab[2 * k + 1] * la.dchi;
+    T a1 = tab[2 * k + 2], m1 = tab[2 * k + 3] * la.dchi;
     T s2 = s * s, s3 = s2 * s;
     a = (T(2) * s3 - T(3) * s2 + T(1)) * a0 + (s3 - T(2) * s2 + s) * m0 + (T(3) * s2 - T(2) * s3) * a1 +
         (s3 - s2) * m1;
     T da = (T(6) * s2 - T(6) * s) * a0 + (T(3) * s2 - T(4) * s + T(1)) * m0 +
            (T(6) * s - T(6) * s2) * a1 + (T(3) * s2 - T(2) * s) * m1;
     dadchi = da / la.dchi;
+}
+
+template <class T>
+__device__ __forceinline__ void a_interp(const LensArgs<T>& la, T chi, T& a, T& dadchi) {
+    tab_interp(la.atab, la, chi, a, dadchi);
 }
 
 template <class T>
@@ -406,45 +415,91 @@ __global__ __launch_bounds__(256) void k_lens_vjp(Parts<T> p, Geo g, LensArgs<T>
         }
         if (!(isfinite(u[0]) && isfinite(u[1]) && isfinite(u[2]))) continue;
         T gx = 0, gy = 0, gz = 0;
-        if (la.rot) {
+        T qx = 0, qy = 0, qz = 0;  // drift-momentum cotangent (sub-evolution)
+        if (la.rot || la.sub) {
+            // the step's drift momentum (cells) and the largest move it
+            // makes within the shell: |dr| <= the step's drift factor
+            T ph[3] = {T(0), T(0), T(0)};
+            T margin = T(0);
+            if (la.sub) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) ph[a] = p.mom[a * n + k] - la.sub_k2 * p.acc[a * n + k];
+                margin = min(la.sub_dr * max(max(fabs(ph[0]), fabs(ph[1])), fabs(ph[2])), nmf);
+            }
             // every replica whose box can reach the shell and the map: an
-            // image's depth in replica nz lies in [nz Nm, (nz + 1) Nm]
+            // image's end-of-step depth in replica nz lies in [nz Nm, (nz + 1) Nm]
             const int mz0 = max((int)floor(cnear / nmf), 0), mz1 = (int)floor(cfar / nmf);
             for (int nz = mz0; nz <= mz1; ++nz) {
-                const T rz_hi = min(T(nz + 1) * nmf, cfar);
-                const T rmax = tmax * rz_hi / la.inv_dtheta;
+                const T rz_hi = min(T(nz + 1) * nmf, cfar) + margin;
+                const T rmax = tmax * rz_hi / la.inv_dtheta + margin;
                 const int mx0 = (int)floor((-rmax + half) / nmf) - 1;
                 const int mx1 = (int)floor((rmax + half) / nmf);
                 for (int nx = mx0; nx <= mx1; ++nx)
                     for (int ny = mx0; ny <= mx1; ++ny) {
-                        const int sym = vjp_replica_symmetry(nx, ny, nz, la.rot_seed);
-                        T ui[3];
+                        const int sym = la.rot ? vjp_replica_symmetry(nx, ny, nz, la.rot_seed) : 0;
+                        T ui[3], pi[3];
 #pragma unroll
                         for (int j = 0; j < 3; ++j) {
                             const int ax = vjp_sym_axis(sym, j);
-                            T c = ax == 0 ? u[0] : (ax == 1 ? u[1] : u[2]);
-                            ui[j] = ((sym >> j) & 1) ? nmf - c : c;
+                            const T c = ax == 0 ? u[0] : (ax == 1 ? u[1] : u[2]);
+                            const T q = ax == 0 ? ph[0] : (ax == 1 ? ph[1] : ph[2]);
+                            const bool fl = (sym >> j) & 1;
+                            ui[j] = fl ? nmf - c : c;
+                            pi[j] = fl ? -q : q;
                         }
-                        const T rz = ui[2] + T(nz) * nmf;
+                        T rx = ui[0] + T(nx) * nmf - half, ry = ui[1] + T(ny) * nmf - half;
+                        T rz = ui[2] + T(nz) * nmf;
                         if (!(rz > cnear && rz <= cfar && rz > T(0))) continue;
+                        T dr = T(0), ddr = T(0), de = T(0);
+                        T chi_e = rz * la.cell;
+                        if (la.sub) {
+                            // along the step's drift to a(chi) of the
+                            // end-of-step depth
+                            T dd;
+                            tab_interp(la.dtab, la, chi_e, de, dd);
+                            dr = (de - la.d_end) * la.sub_scale;
+                            ddr = dd * la.sub_scale;  // d dr / d chi_e, per Mpc/h
+                            rx += dr * pi[0];
+                            ry += dr * pi[1];
+                            rz += dr * pi[2];
+                            if (!(rz > T(0))) continue;
+                        }
                         const T chi = rz * la.cell;
                         if (chi >= chi_max_src) continue;
                         T a, dadchi;
                         a_interp(la, chi, a, dadchi);
                         T hx = 0, hy = 0, hz = 0;
-                        lens_vjp_image(la, lv, kbar, npix2, ui[0] + T(nx) * nmf - half,
-                                       ui[1] + T(ny) * nmf - half, rz, chi, a, dadchi,
-                                       lv.dadom_at(chi), hp, dth, hx, hy, hz, om_acc);
+                        double om_img = 0.0;
+                        lens_vjp_image(la, lv, kbar, npix2, rx, ry, rz, chi, a, dadchi,
+                                       lv.dadom_at(chi), hp, dth, hx, hy, hz, om_img);
+                        om_acc += om_img;
+                        T ix = hx, iy = hy, iz = hz;
+                        if (la.sub) {
+                            // r' = r + dr(chi_e) p_h: the depth also moves dr
+                            const T gp = (hx * pi[0] + hy * pi[1] + hz * pi[2]) * la.cell;
+                            iz += ddr * gp;
+                            const T ddr_dom = (lv.ddom_at(chi_e) - lv.dd_end_dom) * la.sub_scale +
+                                              (de - la.d_end) * lv.dscale_dom;
+                            om_acc += (double)gp * (double)ddr_dom;
+                        }
                         // back to the box frame: image axis j is box axis
                         // vjp_sym_axis(sym, j), reflected when flip j is set
 #pragma unroll
                         for (int j = 0; j < 3; ++j) {
-                            T v = j == 0 ? hx : (j == 1 ? hy : hz);
-                            if ((sym >> j) & 1) v = -v;
+                            T v = j == 0 ? ix : (j == 1 ? iy : iz);
+                            T w = j == 0 ? hx : (j == 1 ? hy : hz);
+                            if ((sym >> j) & 1) {
+                                v = -v;
+                                w = -w;
+                            }
+                            w *= dr;
                             const int ax = vjp_sym_axis(sym, j);
                             gx += ax == 0 ? v : T(0);
                             gy += ax == 1 ? v : T(0);
                             gz += ax == 2 ? v : T(0);
+                            qx += ax == 0 ? w : T(0);
+                            qy += ax == 1 ? w : T(0);
+                            qz += ax == 2 ? w : T(0);
                         }
                     }
             }
@@ -498,6 +553,12 @@ __global__ __launch_bounds__(256) void k_lens_vjp(Parts<T> p, Geo g, LensArgs<T>
             xbar[L] += gx;
             xbar[n + L] += gy;
             xbar[2 * n + L] += gz;
+        }
+        if (la.sub && (qx != T(0) || qy != T(0) || qz != T(0))) {
+            long L = lattice_index(id, g.np);
+            lv.phbar[L] += qx;
+            lv.phbar[n + L] += qy;
+            lv.phbar[2 * n + L] += qz;
         }
     }
     block_add<256>(&dots[4], om_acc, red);
@@ -808,11 +869,12 @@ void launch_fvjp_readout(Parts<T> p, SortBufs s, Geo g, const T* f0, const T* f1
 template <class T>
 void launch_fvjp_paintgrad(Parts<T> p, SortBufs s, Geo g, const T* rhobar, T mass, const T* xbc,
                            T H, int mode, T dr, T k2, T d0, T gp0, T* xbar_out, const T* pbar_in,
-                           T* pbar_out, T* sb0, T* sb1, T* sb2, double* dots, hipStream_t st) {
+                           T* pbar_out, const T* phbar, T* sb0, T* sb1, T* sb2, double* dots,
+                           hipStream_t st) {
     int ntiles = g.nt * g.nt * g.nt;
     hipLaunchKernelGGL(k_fvjp_paintgrad<T>, dim3(ntiles), dim3(AB), 0, st, p, s, g, rhobar, mass,
-                       xbc, H, mode, dr, k2, d0, gp0, xbar_out, pbar_in, pbar_out, sb0, sb1, sb2,
-                       dots);
+                       xbc, H, mode, dr, k2, d0, gp0, xbar_out, pbar_in, pbar_out, phbar, sb0, sb1,
+                       sb2, dots);
 }
 
 template <class T>
@@ -939,8 +1001,8 @@ ML_INST_JVP(double)
                                          const T*, const T*, T, T, T*, T*, double*, uint32_t*,       \
                                          hipStream_t);                                               \
     template void launch_fvjp_paintgrad<T>(Parts<T>, SortBufs, Geo, const T*, T, const T*, T, int,   \
-                                           T, T, T, T, T*, const T*, T*, T*, T*, T*, double*,        \
-                                           hipStream_t);                                             \
+                                           T, T, T, T, T*, const T*, T*, const T*, T*, T*, T*,       \
+                                           double*, hipStream_t);                                    \
     template void launch_dot3<T>(const T*, const T*, const T*, const T*, const T*, const T*, long,   \
                                  double*, hipStream_t);                                              \
     template void launch_map_sums<T>(const T*, int, int, double*, hipStream_t);                      \

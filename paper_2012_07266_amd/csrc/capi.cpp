@@ -44,7 +44,7 @@ struct Layout {
 struct ArenaPlan {
     size_t disp[2], mom[2], id[2], acc, key, count, start, scan_sum, status;
     size_t mesh[3], nyq[3], halo, tw_nm, tw_hm, twp_nm, tw_np, tw_hp, twp_np, g_ic, atab, dtab, pmax;
-    size_t xbc, fbc, dots, fmax, noise, g_ic_dom, adom;
+    size_t xbc, fbc, dots, fmax, noise, g_ic_dom, adom, ddom;
     size_t total;
 };
 
@@ -95,6 +95,7 @@ ArenaPlan plan_arena(const pm_params& p, const lens_params& l, size_t es) {
     a.noise = L.take(n * es);
     a.g_ic_dom = L.take((3 * (np_ / 2) * (np_ / 2) + 1) * es);
     a.adom = L.take(ATAB_N * es);
+    a.ddom = L.take(ATAB_N * es);
     a.total = L.bytes;
     return a;
 }
@@ -213,8 +214,10 @@ struct SimBase {
     virtual int sync() = 0;
     virtual int background(double a, double out[3]) const = 0;
     virtual hipStream_t stream() const = 0;
-    virtual int lens_vjp(double a0, double a1, const void* kbar, void* xbar, double* cb) = 0;
-    virtual int step_vjp(double a0, double a1, double a2, void* xbar, void* pbar, double* cb) = 0;
+    virtual int lens_vjp(double a0, double a1, const void* kbar, void* xbar, void* phbar,
+                         double* cb) = 0;
+    virtual int step_vjp(double a0, double a1, double a2, void* xbar, void* pbar,
+                         const void* phbar, double* cb) = 0;
     virtual int init_ic_vjp(double a1, const void* xbar, const void* pbar, void* nbar,
                             double* cb) = 0;
     virtual int init_ic_jvp(const void* nd, double om_dot, double s8_dot) = 0;
@@ -244,7 +247,7 @@ template <class T> struct Sim final : SimBase {
     cx<T>*tw_nm, *tw_hm, *twp_nm, *tw_np, *tw_hp, *twp_np;
     T *g_ic, *atab, *dtab;
     uint32_t* pmax_bits = nullptr;
-    T *xbc, *fbc, *noise_copy, *g_ic_dom, *adom;
+    T *xbc, *fbc, *noise_copy, *g_ic_dom, *adom, *ddom;
     double* dots = nullptr;
     uint32_t* fmax_bits = nullptr;
     HostCosmo cosmo_p, cosmo_m;  // Omega_m +- DOM for the finite-difference factors
@@ -370,6 +373,7 @@ template <class T> struct Sim final : SimBase {
         noise_copy = at<T>(ap.noise);
         g_ic_dom = at<T>(ap.g_ic_dom);
         adom = at<T>(ap.adom);
+        ddom = at<T>(ap.ddom);
         return upload_tables();
     }
 
@@ -460,6 +464,13 @@ template <class T> struct Sim final : SimBase {
             std::vector<T> w(ATAB_N);
             for (int k = 0; k < ATAB_N; ++k) w[k] = (T)((ap_[k] - am_[k]) / (2.0 * DOM));
             if ((rc = upload(ap.adom, w))) return rc;
+            // d D(a(chi)) / d Omega_m on the same grid (the sub-evolution
+            // move's cosmology derivative), each side on its own a(chi)
+            std::vector<double> dp(ATAB_N), dm(ATAB_N), tmp(ATAB_N);
+            cosmo_p.growth_grid(ap_.data(), ATAB_N, dp.data(), tmp.data());
+            cosmo_m.growth_grid(am_.data(), ATAB_N, dm.data(), tmp.data());
+            for (int k = 0; k < ATAB_N; ++k) w[k] = (T)((dp[k] - dm[k]) / (2.0 * DOM));
+            if ((rc = upload(ap.ddom, w))) return rc;
         }
         launch_fill_u32(status, 0u, 1, st);
         HIPCHK(hipStreamSynchronize(st));
@@ -853,7 +864,7 @@ template <class T> struct Sim final : SimBase {
     // mode 0: drift reverse (pbar += dr xbar, dots[1] = sum xbar . p_half);
     // mode 1: initial-condition cotangent sbar = d0 xbar + gp0 pbar into fbc.
     void force_vjp(T ckick, const T* xbar_in, const T* pbar_in, int mode, T dr, T k2, T d0,
-                   T gp0, T* xbar_out, T* pbar_out) {
+                   T gp0, T* xbar_out, T* pbar_out, const T* phbar = nullptr) {
         const long n = geo.npart;
         const T H = (T)cell;
         if (!meshes_valid) {
@@ -890,10 +901,11 @@ template <class T> struct Sim final : SimBase {
         T mass = (T)std::pow((double)geo.B, 3);
         ProfScope ps(prof, "vjp_paintgrad");
         launch_fvjp_paintgrad<T>(cur, sb, geo, mesh[0], mass, xbc, H, mode, dr, k2, d0, gp0, xbar_out,
-                                 pbar_in, pbar_out, fbc, fbc + n, fbc + 2 * n, dots, st);
+                                 pbar_in, pbar_out, phbar, fbc, fbc + n, fbc + 2 * n, dots, st);
     }
 
-    int step_vjp(double a0, double a1, double a2, void* xbar, void* pbar, double* cb) override {
+    int step_vjp(double a0, double a1, double a2, void* xbar, void* pbar, const void* phbar,
+                 double* cb) override {
         if (!xbar || !pbar || !cb) return PM_EINVAL;
         if (!at_a(a1)) return PM_ESTATE;
         double ah = 0.5 * (a0 + a1);
@@ -909,7 +921,8 @@ template <class T> struct Sim final : SimBase {
         launch_fill<double>(dots, 0.0, 64, st);
         T* xb = reinterpret_cast<T*>(xbar);
         T* pb = reinterpret_cast<T*>(pbar);
-        force_vjp((T)(k2 + k1n), xb, pb, 0, (T)dr, (T)k2, T(0), T(1), xb, pb);
+        force_vjp((T)(k2 + k1n), xb, pb, 0, (T)dr, (T)k2, T(0), T(1), xb, pb,
+                  reinterpret_cast<const T*>(phbar));
         int rc = check_launch();
         if (rc) return rc;
         double d[2];
@@ -993,14 +1006,31 @@ template <class T> struct Sim final : SimBase {
         return true;
     }
 
-    int lens_vjp(double a0, double a1, const void* kbar, void* xbar, double* cb) override {
+    int lens_vjp(double a0, double a1, const void* kbar, void* xbar, void* phbar,
+                 double* cb) override {
         if (!kbar || !xbar || !cb) return PM_EINVAL;
-        if (interp || pgd) return PM_EINVAL;  // no reverse pass for these modes
+        if (pgd) return PM_EINVAL;  // no reverse pass for the PGD correction
+        if (interp && !phbar) return PM_EINVAL;
         if (!at_a(a1)) return PM_ESTATE;
         LensArgs<T> la;
         LensVjpArgs<T> lv;
         double chi_near, chi_far;
         if (!derivative_lens_args(a0, a1, la, lv, chi_near, chi_far)) return PM_OK;
+        if (interp) {
+            // the step's drift momentum is p - K2 f of the state at a1 (the
+            // force there is recomputed by pm_set_state or left by pm_step)
+            const double ah = 0.5 * (a0 + a1);
+            la.sub = 1;
+            la.dtab = dtab;
+            la.d_end = (T)cosmo.D(a1);
+            la.sub_scale = (T)(1.0 / cosmo.gp(ah));
+            la.sub_dr = (T)std::fabs(cosmo.drift(a0, a1, ah));
+            la.sub_k2 = (T)cosmo.kick(ah, a1, a1);
+            lv.ddom = ddom;
+            lv.dd_end_dom = (T)((cosmo_p.D(a1) - cosmo_m.D(a1)) / (2 * DOM));
+            lv.dscale_dom = (T)((1.0 / cosmo_p.gp(ah) - 1.0 / cosmo_m.gp(ah)) / (2 * DOM));
+            lv.phbar = reinterpret_cast<T*>(phbar);
+        }
         launch_fill<double>(dots, 0.0, 64, st);
         const T* kb = reinterpret_cast<const T*>(kbar);
         { ProfScope ps(prof, "lens_vjp");
@@ -1278,12 +1308,12 @@ int pm_get_force(pm_sim* sim, void* rho, void* fm, void* acc) {
 }
 int pm_sync(pm_sim* sim) { return sim ? sim->impl->sync() : PM_EINVAL; }
 int lens_project_vjp(pm_sim* sim, double a0, double a1, const void* kappa_bar, void* x_bar,
-                     double cosmo_bar[2]) {
-    return sim ? sim->impl->lens_vjp(a0, a1, kappa_bar, x_bar, cosmo_bar) : PM_EINVAL;
+                     void* ph_bar, double cosmo_bar[2]) {
+    return sim ? sim->impl->lens_vjp(a0, a1, kappa_bar, x_bar, ph_bar, cosmo_bar) : PM_EINVAL;
 }
 int pm_step_vjp(pm_sim* sim, double a0, double a1, double a2, void* x_bar, void* p_bar,
-                double cosmo_bar[2]) {
-    return sim ? sim->impl->step_vjp(a0, a1, a2, x_bar, p_bar, cosmo_bar) : PM_EINVAL;
+                const void* ph_bar, double cosmo_bar[2]) {
+    return sim ? sim->impl->step_vjp(a0, a1, a2, x_bar, p_bar, ph_bar, cosmo_bar) : PM_EINVAL;
 }
 int pm_init_ic_vjp(pm_sim* sim, double a1, const void* x_bar, const void* p_bar, void* noise_bar,
                    double cosmo_bar[2]) {

@@ -67,6 +67,7 @@ class Simulation:
               "pm_create")
         self._h = h
         self.a = None
+        self.interpolation = False
         if interpolation:
             self.set_interpolation(True)
         if pgd is not None:
@@ -130,6 +131,7 @@ class Simulation:
     def set_interpolation(self, on: bool):
         """Sub-evolution projection on or off (pm_set_interpolation)."""
         check(lib().pm_set_interpolation(self._h, int(bool(on))), "pm_set_interpolation")
+        self.interpolation = bool(on)
 
     def set_replica_rotation(self, seed):
         """Rotate every box replica by a cube symmetry hashed from its offsets
@@ -207,18 +209,19 @@ class Simulation:
         check(lib().pm_sync(self._h), "pm_sync")
 
     # -- reverse mode -------------------------------------------------------
-    def lens_vjp(self, a0, a1, kappa_bar, x_bar, cosmo_bar):
+    def lens_vjp(self, a0, a1, kappa_bar, x_bar, cosmo_bar, ph_bar=None):
         """x_bar += d kappa/dx^T kappa_bar (state at a1); cosmo_bar (2,) float64
-        numpy array, accumulated."""
+        numpy array, accumulated.  With sub-evolution on, ph_bar [3][Np^3]
+        receives the drift momentum's cotangent (accumulated), for step_vjp."""
         cb = (ctypes.c_double * 2)(*cosmo_bar)
         check(lib().lens_project_vjp(self._h, float(a0), float(a1), _ptr(kappa_bar),
-                                     _ptr(x_bar), cb), "lens_project_vjp")
+                                     _ptr(x_bar), _ptr(ph_bar), cb), "lens_project_vjp")
         cosmo_bar[:] = list(cb)
 
-    def step_vjp(self, a0, a1, a2, x_bar, p_bar, cosmo_bar):
+    def step_vjp(self, a0, a1, a2, x_bar, p_bar, cosmo_bar, ph_bar=None):
         cb = (ctypes.c_double * 2)(*cosmo_bar)
         check(lib().pm_step_vjp(self._h, float(a0), float(a1), float(a2), _ptr(x_bar),
-                                _ptr(p_bar), cb), "pm_step_vjp")
+                                _ptr(p_bar), _ptr(ph_bar), cb), "pm_step_vjp")
         cosmo_bar[:] = list(cb)
 
     def init_ic_vjp(self, a1, x_bar, p_bar, cosmo_bar):

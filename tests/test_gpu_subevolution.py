@@ -145,7 +145,7 @@ def test_interpolation_error_paths():
             sim.lens(0.25, 0.3, kap)    # not the interval of that step
         assert e.value.code == PM_ESTATE
         sim.lens(0.2, 0.3, kap)
-        with pytest.raises(MadlensError) as e:
+        with pytest.raises(MadlensError) as e:   # no drift-momentum cotangent array
             sim.lens_vjp(0.2, 0.3, torch.ones_like(kap),
                          torch.zeros((3, 16 ** 3), dtype=kap.dtype, device=kap.device),
                          np.zeros(2))
@@ -156,3 +156,126 @@ def test_interpolation_error_paths():
         sim.step(0.2, 0.3)
         sim.lens(0.2, 0.3, kap)
         sim.sync()
+
+
+def _clear_of_kinks(x, ph, a_far, a_near, c, box, geom, ah, dt=1e-4, dchi=1e-3):
+    """Particles none of whose (moved) images lies within dt pixels of a
+    pixel edge or dchi Mpc/h of a shell bound or a source plane: there the
+    splat's gradient jumps, so a float32 image a rounding away from the
+    oracle's has another valid one-sided cotangent."""
+    from oracle import lens
+    chi_near, chi_far = c.chi(a_near), c.chi(a_far)
+    d_near, gp_h = c.D(a_near), c.gp(ah)
+    clear = np.ones(x.shape[1], bool)
+    for idx, rx, ry, chi, sym in lens.shell_images(x, box, chi_near - dchi, chi_far + dchi, geom):
+        perm, flips = lens.PERMS[sym // 8], sym % 8
+        q = [(-1.0 if flips >> j & 1 else 1.0) * ph[perm[j], idx] for j in range(3)]
+        near = (np.abs(chi - chi_near) < dchi) | (np.abs(chi - chi_far) < dchi)
+        dr = (c.D_vec(c.a_of_chi_vec(chi)) - d_near) / gp_h
+        cm = chi + dr * q[2]
+        t0 = (rx + dr * q[0]) / cm / geom.dtheta + 0.5 * geom.npix - 0.5
+        t1 = (ry + dr * q[1]) / cm / geom.dtheta + 0.5 * geom.npix - 0.5
+        near |= (np.abs(t0 - np.round(t0)) < dt) | (np.abs(t1 - np.round(t1)) < dt)
+        for cs in geom.chi_src:
+            near |= np.abs(cm - cs) < dchi
+        clear[idx[near]] = False
+    return clear
+
+
+@pytest.mark.parametrize("seed", [None, 0x5EED1234ABCD], ids=["plain", "rotated"])
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+def test_lens_vjp_with_subevolution(dtype, seed):
+    """One sub-evolved shell's reverse pass at a state with momenta: position
+    and drift-momentum cotangents against the oracle's adjoint (pinned by
+    finite differences), and the Omega_m part against a central difference
+    of the oracle projection at fixed positions and drift momenta."""
+    from oracle import adjoint, lens, pm
+    from oracle.cosmology import Cosmology
+    wl = W.Workload("subvjp", 16, 32, 64.0, 0.4, 1.0, 3, 24, 4.0, (1.0, 2.0))
+    c = cosmo_of(wl)
+    x = W.clustered_positions(16, 32, wl.box, seed=21)
+    rng = np.random.default_rng(23)
+    p = 30.0 * rng.standard_normal(x.shape)
+    kbar = rng.standard_normal((2, 24, 24))
+    a_far, a_near = 0.55, 0.7
+    ah = 0.5 * (a_far + a_near)
+    log(f"sub-evolved lens vjp {dtype} rotation={seed}")
+    with new_sim(wl, dtype) as sim:
+        sim.set_interpolation(True)
+        if seed is not None:
+            sim.set_replica_rotation(seed)
+        sim.set_state(torch.from_numpy(x), torch.from_numpy(p), a_near)
+        xb = torch.zeros((3, 16 ** 3), dtype=dtype, device="cuda")
+        phb = torch.zeros_like(xb)
+        cb = np.zeros(2)
+        sim.lens_vjp(a_far, a_near, torch.tensor(kbar, dtype=dtype, device="cuda"), xb, cb, phb)
+        xg, pg = to_np(xb), to_np(phb)
+        sim.sync()
+    log("oracle")
+    ph = p - c.kick_factor(ah, a_near, a_near) * pm.particle_force(x, 16, 32, wl.box)
+    geom = lens.MapGeometry(wl.npix, wl.fov_deg, wl.z_src, c, rotation_seed=seed)
+    xo, po = adjoint.lens_vjp(x, a_far, a_near, kbar, c, wl.box, 16, geom, sub=(ph, ah))
+    # Omega_m moves the images too, so a step of 1e-5 straddles pixel-edge
+    # kinks of the splat (these momenta move images by ~10 Mpc/h); 1e-7 none
+    h = 1e-7
+    cb0 = (c.chi(a_near), c.chi(a_far))
+    f = lambda cc: np.sum(kbar * lens.project_shell(
+        x, a_far, a_near, cc, wl.box, 16,
+        lens.MapGeometry(wl.npix, wl.fov_deg, wl.z_src, cc, rotation_seed=seed),
+        chi_bounds=cb0, src_cut=geom.chi_src, sub=(ph, ah), hold=c))
+    om = (f(Cosmology(0.3 + h)) - f(Cosmology(0.3 - h))) / (2 * h)
+    plain = adjoint.lens_vjp(x, a_far, a_near, kbar, c, wl.box, 16, geom)
+    clear = np.ones(x.shape[1], bool) if dtype == torch.float64 else \
+        _clear_of_kinks(x, ph, a_far, a_near, c, wl.box, geom, ah)
+    e_x = rel_rms(xg[:, clear], xo[:, clear])
+    e_p = rel_rms(pg[:, clear], po[:, clear])
+    e_om = abs(cb[0] - om) / abs(om)
+    log(f"sub-evolved lens vjp {dtype}: x {e_x:.2e}, p_h {e_p:.2e} ({clear.mean():.4f} of "
+        f"particles compared; all: x {rel_rms(xg, xo):.2e}), Om {cb[0]:.10e} vs {om:.10e} "
+        f"({e_om:.2e}); sub-evolution changes x_bar by {rel_rms(plain, xo):.2e}")
+    assert rel_rms(plain, xo) > 1e-3 and np.abs(po).max() > 0
+    assert e_x < _tol(dtype, 1e-9, 1e-4) and e_p < _tol(dtype, 1e-9, 1e-4)
+    # analytic weight and move derivatives with differenced tables against
+    # a difference of the whole projection.  In float32 the few images a
+    # rounding away from a pixel edge take the other one-sided gradient, and
+    # with these momenta (moves of ~10 Mpc/h) their move term is large: the
+    # float32 bound is the 1e-3 relative one for the Omega_m cotangent.
+    assert e_om < _tol(dtype, 1e-6, 1e-3)
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+def test_reverse_pass_with_subevolution_matches_oracle(dtype):
+    from oracle import adjoint, lens
+    from paper_2012_07266_amd.autograd import LensingModel
+    wl = W.Workload("adjsub", 16, 32, 48.0, 0.4, 1.0, 3, 16, 3.0, (1.0,), seed=11)
+    kbar = np.random.default_rng(12).standard_normal((1, 16, 16))
+    log(f"reverse pass with sub-evolution {dtype}")
+    noise = W.white_noise(wl.np_side, wl.seed)
+    model = LensingModel(wl.np_side, wl.nm_side, wl.box, wl.npix, wl.fov_deg, wl.z_src,
+                         wl.a_grid(), dtype=dtype, interpolation=True)
+    w = torch.tensor(noise, dtype=dtype, device="cuda", requires_grad=True)
+    om = torch.tensor(wl.omega_m, dtype=dtype, device="cuda", requires_grad=True)
+    s8 = torch.tensor(wl.sigma8, dtype=dtype, device="cuda", requires_grad=True)
+    (model(w, om, s8) * torch.tensor(kbar, dtype=dtype, device="cuda")).sum().backward()
+    torch.cuda.synchronize()
+    model.close()
+    log("oracle")
+    c = cosmo_of(wl)
+    geom = lens.MapGeometry(wl.npix, wl.fov_deg, wl.z_src, c)
+    terms = []
+    # a step of 1e-7 in the oracle's Omega_m differences: with sub-evolution
+    # Omega_m moves the images, and 1e-5 can straddle a pixel-edge kink
+    nb, g_om, g_s8 = adjoint.kappa_vjp_cosmo(noise, kbar, c, wl.box, wl.nm_side, wl.a_grid(),
+                                             geom, terms=terms, interpolation=True, dom=1e-7)
+    plain = adjoint.kappa_vjp_noise(noise, kbar, c, wl.box, wl.nm_side, wl.a_grid(), geom)
+    e_n = rel_rms(to_np(w.grad), nb)
+    e_om = abs(float(om.grad) - g_om) / abs(g_om)
+    e_s8 = abs(float(s8.grad) - g_s8) / abs(g_s8)
+    cond = sum(abs(t) for t in terms) / abs(g_om)
+    log(f"reverse with sub-evolution {dtype}: noise_bar {e_n:.2e}  Om {e_om:.2e} (cond "
+        f"{cond:.1f})  s8 {e_s8:.2e}; sub-evolution changes noise_bar by {rel_rms(plain, nb):.2e}")
+    assert rel_rms(plain, nb) > 1e-3
+    if dtype == torch.float64:
+        assert e_n < 1e-9 and e_s8 < 1e-9 and e_om < 1e-8 * cond
+    else:
+        assert e_n < 1e-3 and e_s8 < 1e-3 and e_om < 3e-4 * cond
