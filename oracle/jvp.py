@@ -118,26 +118,51 @@ def bilinear_paint_tangent(t0, t1, c, c0, c1, npix):
     return out.reshape(npix, npix)
 
 
-def lens_jvp(x, x_dot, a_far, a_near, cosmo: Cosmology, box, np_side, geom: lens.MapGeometry):
+def lens_jvp(x, x_dot, a_far, a_near, cosmo: Cosmology, box, np_side, geom: lens.MapGeometry,
+             sub=None, ph_dot=None):
     """Tangent of the shell's convergence (particle term) along x_dot at
-    fixed cosmology: [nsrc][npix][npix]."""
+    fixed cosmology: [nsrc][npix][npix].
+
+    With `sub` = (p_h, a_h) (sub-evolution) the image at end-of-step depth
+    chi_e is projected at r' = r + dr(chi_e) p_h, whose tangent is
+    r'_dot = r_dot + (d dr / d chi_e) r_dot_z p_h + dr p_h_dot (p_h_dot the
+    drift momentum's tangent, zero if None); the splat's tangent is then
+    taken at r' along r'_dot."""
     chi_far = float(cosmo.chi(a_far))
     chi_near = float(cosmo.chi(a_near))
     pref = lens_prefactor(cosmo.omega_m)
     vp = (box / np_side) ** 3
     out = np.zeros((len(geom.chi_src), geom.npix, geom.npix))
     c = 0.5 * geom.npix - 0.5
+    if sub is not None:
+        p_h, a_h = sub
+        d_near, gp_h = cosmo.D(a_near), cosmo.gp(a_h)
+        if ph_dot is None:
+            ph_dot = np.zeros_like(p_h)
     for idx, rx, ry, chi, sym in lens.shell_images(x, box, chi_near, chi_far, geom):
-        t0 = rx / chi / geom.dtheta + c
-        t1 = ry / chi / geom.dtheta + c
-        keep = (t0 > -1.0) & (t0 < geom.npix) & (t1 > -1.0) & (t1 < geom.npix)
-        if not np.any(keep):
-            continue
-        idx, rx, ry, chi, t0, t1 = idx[keep], rx[keep], ry[keep], chi[keep], t0[keep], t1[keep]
         # tangent in the image frame: image axis j is box axis perm[j],
         # reflected when flip j is set
         perm, flips = lens.PERMS[sym // 8], sym % 8
-        xd = [(-1.0 if flips >> j & 1 else 1.0) * x_dot[perm[j], idx] for j in range(3)]
+        sgn = [-1.0 if flips >> j & 1 else 1.0 for j in range(3)]
+        xd = [sgn[j] * x_dot[perm[j], idx] for j in range(3)]
+        if sub is not None:
+            q = [sgn[j] * p_h[perm[j], idx] for j in range(3)]
+            qd = [sgn[j] * ph_dot[perm[j], idx] for j in range(3)]
+            ae = cosmo.a_of_chi_vec(chi)
+            dr = (cosmo.D_vec(ae) - d_near) / gp_h
+            ddr = cosmo.dD_da_vec(ae) * (-ae * ae * cosmo.E(ae) / 2997.92458) / gp_h
+            zd = xd[2]
+            xd = [xd[j] + ddr * zd * q[j] + dr * qd[j] for j in range(3)]
+            rx = rx + dr * q[0]
+            ry = ry + dr * q[1]
+            chi = chi + dr * q[2]
+        t0 = rx / chi / geom.dtheta + c
+        t1 = ry / chi / geom.dtheta + c
+        keep = (t0 > -1.0) & (t0 < geom.npix) & (t1 > -1.0) & (t1 < geom.npix) & (chi > 0.0)
+        if not np.any(keep):
+            continue
+        idx, rx, ry, chi, t0, t1 = idx[keep], rx[keep], ry[keep], chi[keep], t0[keep], t1[keep]
+        xd = [v[keep] for v in xd]
         a = cosmo.a_of_chi_vec(chi)
         dadchi = -a * a * cosmo.E(a) / 2997.92458
         for s, chis in enumerate(geom.chi_src):
@@ -168,16 +193,17 @@ def _geom_at(geom: lens.MapGeometry, cosmo: Cosmology):
 
 
 def lens_om_tangent(x, a_far, a_near, cosmo: Cosmology, box, np_side, geom: lens.MapGeometry,
-                    dom=1e-5):
-    """d kappa_shell / d Omega_m at fixed positions: central difference with
-    the shell's distance bounds and the source membership held at the
-    central cosmology (membership is piecewise constant), mean term included."""
+                    dom=1e-5, sub=None):
+    """d kappa_shell / d Omega_m at fixed positions (and drift momenta, with
+    `sub`): central difference with the shell's distance bounds and the
+    source membership held at the central cosmology (membership is piecewise
+    constant), mean term included."""
     cp, cm = _with_om(cosmo, cosmo.omega_m + dom), _with_om(cosmo, cosmo.omega_m - dom)
     cb = (cosmo.chi(a_near), cosmo.chi(a_far))
     kp = lens.project_shell(x, a_far, a_near, cp, box, np_side, _geom_at(geom, cp),
-                            chi_bounds=cb, src_cut=geom.chi_src)
+                            chi_bounds=cb, src_cut=geom.chi_src, sub=sub, hold=cosmo)
     km = lens.project_shell(x, a_far, a_near, cm, box, np_side, _geom_at(geom, cm),
-                            chi_bounds=cb, src_cut=geom.chi_src)
+                            chi_bounds=cb, src_cut=geom.chi_src, sub=sub, hold=cosmo)
     return (kp - km) / (2 * dom)
 
 
@@ -229,9 +255,11 @@ def step_jvp(x, p, f, x_dot, p_dot, f_dot, a0, a1, om_dot, cosmo: Cosmology, np_
 # whole model
 # ---------------------------------------------------------------------------
 def kappa_jvp(noise, noise_dot, om_dot, s8_dot, cosmo: Cosmology, box, nm_side, a_grid,
-              geom: lens.MapGeometry, dom=1e-5):
+              geom: lens.MapGeometry, dom=1e-5, interpolation=False):
     """(kappa, kappa_dot): the maps and their directional derivative along
-    (noise_dot, Om_dot, s8_dot)."""
+    (noise_dot, Om_dot, s8_dot).  `interpolation` projects with
+    sub-evolution; the drift momentum p_h = p - K2 f and its tangent
+    p_dot - K2 f_dot - Om_dot K2' f enter the shell's tangent."""
     np_side = noise.shape[0]
     x, p = pm.zeldovich_ic(noise, cosmo, box, nm_side, a_grid[0])
     x_dot, p_dot = ic_jvp(noise, noise_dot, om_dot, s8_dot, cosmo, box, a_grid[0], dom)
@@ -243,10 +271,18 @@ def kappa_jvp(noise, noise_dot, om_dot, s8_dot, cosmo: Cosmology, box, nm_side, 
         a0, a1 = a_grid[i], a_grid[i + 1]
         x, p, f, x_dot, p_dot, f_dot = step_jvp(x, p, f, x_dot, p_dot, f_dot, a0, a1, om_dot,
                                                 cosmo, np_side, nm_side, box, dom)
-        kappa += lens.project_shell(x, a0, a1, cosmo, box, np_side, geom)
-        kappa_dot += lens_jvp(x, x_dot, a0, a1, cosmo, box, np_side, geom)
+        sub, ph_dot = None, None
+        if interpolation:
+            k2 = step_factors(cosmo, a0, a1)[2]
+            dk2 = (step_factors(_with_om(cosmo, cosmo.omega_m + dom), a0, a1)[2]
+                   - step_factors(_with_om(cosmo, cosmo.omega_m - dom), a0, a1)[2]) / (2 * dom)
+            sub = (p - k2 * f, 0.5 * (a0 + a1))
+            ph_dot = p_dot - k2 * f_dot - om_dot * dk2 * f
+        kappa += lens.project_shell(x, a0, a1, cosmo, box, np_side, geom, sub=sub)
+        kappa_dot += lens_jvp(x, x_dot, a0, a1, cosmo, box, np_side, geom, sub=sub, ph_dot=ph_dot)
         if om_dot != 0.0:
-            kappa_dot += om_dot * lens_om_tangent(x, a0, a1, cosmo, box, np_side, geom, dom)
+            kappa_dot += om_dot * lens_om_tangent(x, a0, a1, cosmo, box, np_side, geom, dom,
+                                                  sub=sub)
     return kappa, kappa_dot
 
 
