@@ -160,8 +160,8 @@ int lens_project(pm_sim* sim, double a0, double a1, void* kappa);
  * depth, a(chi) and weight are those of the moved image (the image may then
  * fall behind a source plane or off the map).  lens_project then needs the
  * state that pm_step(a0, a1) (or pm_run ending at a1) left, where
- * p_h = p - K2 f (else PM_ESTATE); lens_project_vjp differentiates it (see
- * there), lens_project_jvp refuses it (PM_EINVAL).
+ * p_h = p - K2 f (else PM_ESTATE); lens_project_vjp and lens_project_jvp
+ * differentiate it (see there).
  * on: 0 or 1.  Errors: PM_EINVAL (NULL sim). */
 int pm_set_interpolation(pm_sim* sim, int32_t on);
 
@@ -299,8 +299,9 @@ int pm_init_ic_vjp(pm_sim* sim, double a1, const void* x_bar, const void* p_bar,
  * thus satisfy <kappa_bar, J v> = <J^T kappa_bar, v>.  The calls are
  * asynchronous on the simulation's stream.  Any call that changes the state
  * other than pm_step_jvp (pm_init_ic*, pm_step, pm_run, pm_set_state,
- * pm_reconfigure) drops the tangent.  Sub-evolution and PGD have no tangent
- * pass (PM_EINVAL from lens_project_jvp); replica rotation does.
+ * pm_reconfigure) drops the tangent.  Replica rotation and sub-evolution
+ * have tangent passes; the PGD correction has none (PM_EINVAL from
+ * lens_project_jvp).
  *
  * pm_init_ic_jvp: the state must be the initial conditions that pm_init_ic
  * (or pm_init_ic_seed) just made (no step, run or pm_set_state since, else
@@ -338,8 +339,11 @@ int pm_step_jvp(pm_sim* sim, double a0, double a1);
  * [nsrc][npix][npix], ACCUMULATED) += d kappa_shell along the tangent: per
  * image, (dw/dchi chi_dot + Om_dot dw/dOm) B + w (dB/dtheta . theta_dot)
  * with w the lens weight and B the bilinear weights, plus Om_dot times the
- * mean term's Omega_m difference.  Errors: PM_EINVAL (NULL array,
- * sub-evolution or PGD on), PM_ESTATE. */
+ * mean term's Omega_m difference.  With sub-evolution the image at end-of-
+ * step depth chi_e is projected at r + dr p_h (see lens_project_vjp), and
+ * its tangent is r_dot + (d dr / d chi_e) r_dot_z p_h + dr p_h_dot +
+ * Om_dot (d dr / dOm) p_h with p_h_dot = p_dot - K2 f_dot - Om_dot K2' f.
+ * Errors: PM_EINVAL (NULL array, PGD on), PM_ESTATE. */
 int lens_project_jvp(pm_sim* sim, double a0, double a1, void* kappa_dot);
 
 /* Per-kernel timing (tracing).  pm_profile(sim, 1) starts recording a pair

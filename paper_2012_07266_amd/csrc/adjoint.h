@@ -94,10 +94,13 @@ template <class T>
 void launch_fjvp_readout_kick(Parts<T> p, SortBufs s, Geo g, const T* m0, const T* m1, const T* m2,
                               const T* fbc, T H, T k2, T ck2, T* pdot, T* fdot, hipStream_t st);
 // Lens projection tangent (particle term, plus om_dot times the weights'
-// Omega_m derivative) accumulated into kdot [nsrc][npix][npix].
+// Omega_m derivative) accumulated into kdot [nsrc][npix][npix].  With
+// sub-evolution (la.sub) the drift momentum's tangent is pdot - K2 fdot -
+// ck2 f (ck2 = om_dot dK2/dOm).
 template <class T>
 void launch_lens_jvp(Parts<T> p, Geo g, const LensArgs<T>& la, const LensVjpArgs<T>& lv,
-                     const T* xdot, T om_dot, T* kdot, hipStream_t st);
+                     const T* xdot, const T* pdot, const T* fdot, T ck2, T om_dot, T* kdot,
+                     hipStream_t st);
 // kdot[s] += mv.v[s] on every pixel.
 template <class T>
 void launch_map_add(T* kdot, int npix, int nsrc, const MapAdd<T>& mv, hipStream_t st);

@@ -763,10 +763,14 @@ __device__ __forceinline__ void lens_jvp_image(const LensArgs<T>& la, const Lens
 }
 
 // Lens projection tangent: every image of every particle splats its tangent
-// (same image set as the projection and its VJP).
+// (same image set as the projection and its VJP).  With sub-evolution the
+// image moves to r' = r + dr(chi_e) p_h and its tangent to
+// r'_dot = r_dot + (d dr / d chi_e) r_dot_z p_h + dr p_h_dot + Om_dot (d dr / dOm) p_h,
+// p_h = p - K2 f and p_h_dot = p_dot - K2 f_dot - ck2 f (ck2 = Om_dot dK2/dOm).
 template <class T>
 __global__ __launch_bounds__(256) void k_lens_jvp(Parts<T> p, Geo g, LensArgs<T> la, LensVjpArgs<T> lv,
-                                                  const T* xdot, T om_dot, T* kdot) {
+                                                  const T* xdot, const T* pdot, const T* fdot,
+                                                  T ck2, T om_dot, T* kdot) {
     const long n = g.npart;
     const T nmf = T(g.nm), half = T(0.5) * nmf;
     const T cnear = la.chi_near / la.cell, cfar = la.chi_far / la.cell;
@@ -791,34 +795,68 @@ __global__ __launch_bounds__(256) void k_lens_jvp(Parts<T> p, Geo g, LensArgs<T>
         }
         if (!(isfinite(u[0]) && isfinite(u[1]) && isfinite(u[2]))) continue;
         const T xb[3] = {xdot[k], xdot[n + k], xdot[2 * n + k]};
-        if (la.rot) {
+        if (la.rot || la.sub) {
+            // drift momentum (cells) and its tangent (Mpc/h), and the largest
+            // move within the shell: |dr| <= the step's drift factor
+            T ph[3] = {T(0), T(0), T(0)}, phd[3] = {T(0), T(0), T(0)};
+            T margin = T(0);
+            if (la.sub) {
+#pragma unroll
+                for (int a = 0; a < 3; ++a) {
+                    const T f = p.acc[a * n + k];
+                    ph[a] = p.mom[a * n + k] - la.sub_k2 * f;
+                    phd[a] = pdot[a * n + k] - la.sub_k2 * fdot[a * n + k] - ck2 * la.cell * f;
+                }
+                margin = min(la.sub_dr * max(max(fabs(ph[0]), fabs(ph[1])), fabs(ph[2])), nmf);
+            }
             const int mz0 = max((int)floor(cnear / nmf), 0), mz1 = (int)floor(cfar / nmf);
             for (int nz = mz0; nz <= mz1; ++nz) {
-                const T rz_hi = min(T(nz + 1) * nmf, cfar);
-                const T rmax = tmax * rz_hi / la.inv_dtheta;
+                const T rz_hi = min(T(nz + 1) * nmf, cfar) + margin;
+                const T rmax = tmax * rz_hi / la.inv_dtheta + margin;
                 const int mx0 = (int)floor((-rmax + half) / nmf) - 1;
                 const int mx1 = (int)floor((rmax + half) / nmf);
                 for (int nx = mx0; nx <= mx1; ++nx)
                     for (int ny = mx0; ny <= mx1; ++ny) {
-                        const int sym = vjp_replica_symmetry(nx, ny, nz, la.rot_seed);
-                        T ui[3], ti[3];
+                        const int sym = la.rot ? vjp_replica_symmetry(nx, ny, nz, la.rot_seed) : 0;
+                        T ui[3], ti[3], pi[3], qi[3];
 #pragma unroll
                         for (int j = 0; j < 3; ++j) {
                             const int ax = vjp_sym_axis(sym, j);
                             const T c = ax == 0 ? u[0] : (ax == 1 ? u[1] : u[2]);
                             const T v = ax == 0 ? xb[0] : (ax == 1 ? xb[1] : xb[2]);
+                            const T q = ax == 0 ? ph[0] : (ax == 1 ? ph[1] : ph[2]);
+                            const T qd = ax == 0 ? phd[0] : (ax == 1 ? phd[1] : phd[2]);
                             const bool fl = (sym >> j) & 1;
                             ui[j] = fl ? nmf - c : c;
                             ti[j] = fl ? -v : v;
+                            pi[j] = fl ? -q : q;
+                            qi[j] = fl ? -qd : qd;
                         }
-                        const T rz = ui[2] + T(nz) * nmf;
+                        T rx = ui[0] + T(nx) * nmf - half, ry = ui[1] + T(ny) * nmf - half;
+                        T rz = ui[2] + T(nz) * nmf;
                         if (!(rz > cnear && rz <= cfar && rz > T(0))) continue;
+                        if (la.sub) {
+                            const T chi_e = rz * la.cell;
+                            T de, dd;
+                            tab_interp(la.dtab, la, chi_e, de, dd);
+                            const T dr = (de - la.d_end) * la.sub_scale;
+                            const T ddr = dd * la.sub_scale;  // per Mpc/h
+                            const T ddr_dom = (lv.ddom_at(chi_e) - lv.dd_end_dom) * la.sub_scale +
+                                              (de - la.d_end) * lv.dscale_dom;
+                            const T zd = ti[2];
+#pragma unroll
+                            for (int j = 0; j < 3; ++j)
+                                ti[j] += (ddr * zd + om_dot * ddr_dom) * pi[j] * la.cell + dr * qi[j];
+                            rx += dr * pi[0];
+                            ry += dr * pi[1];
+                            rz += dr * pi[2];
+                            if (!(rz > T(0))) continue;
+                        }
                         const T chi = rz * la.cell;
                         if (chi >= chi_max_src) continue;
                         T a, dadchi;
                         a_interp(la, chi, a, dadchi);
-                        lens_jvp_image(la, lv, kdot, npix2, ui[0] + T(nx) * nmf - half,
-                                       ui[1] + T(ny) * nmf - half, rz, chi, a, dadchi,
+                        lens_jvp_image(la, lv, kdot, npix2, rx, ry, rz, chi, a, dadchi,
                                        lv.dadom_at(chi), hp, dth, ti[0], ti[1], ti[2], om_dot);
                     }
             }
@@ -968,9 +1006,10 @@ void launch_fjvp_readout_kick(Parts<T> p, SortBufs s, Geo g, const T* m0, const 
 
 template <class T>
 void launch_lens_jvp(Parts<T> p, Geo g, const LensArgs<T>& la, const LensVjpArgs<T>& lv,
-                     const T* xdot, T om_dot, T* kdot, hipStream_t st) {
+                     const T* xdot, const T* pdot, const T* fdot, T ck2, T om_dot, T* kdot,
+                     hipStream_t st) {
     hipLaunchKernelGGL(k_lens_jvp<T>, dim3(grid_of(g.npart, 16384)), dim3(256), 0, st, p, g, la,
-                       lv, xdot, om_dot, kdot);
+                       lv, xdot, pdot, fdot, ck2, om_dot, kdot);
 }
 
 template <class T>
@@ -991,7 +1030,7 @@ void launch_map_add(T* kdot, int npix, int nsrc, const MapAdd<T>& mv, hipStream_
     template void launch_fjvp_readout_kick<T>(Parts<T>, SortBufs, Geo, const T*, const T*, const T*, \
                                               const T*, T, T, T, T*, T*, hipStream_t);               \
     template void launch_lens_jvp<T>(Parts<T>, Geo, const LensArgs<T>&, const LensVjpArgs<T>&,       \
-                                     const T*, T, T*, hipStream_t);                                  \
+                                     const T*, const T*, const T*, T, T, T*, hipStream_t);           \
     template void launch_map_add<T>(T*, int, int, const MapAdd<T>&, hipStream_t);
 ML_INST_JVP(float)
 ML_INST_JVP(double)

@@ -1019,16 +1019,7 @@ template <class T> struct Sim final : SimBase {
         if (interp) {
             // the step's drift momentum is p - K2 f of the state at a1 (the
             // force there is recomputed by pm_set_state or left by pm_step)
-            const double ah = 0.5 * (a0 + a1);
-            la.sub = 1;
-            la.dtab = dtab;
-            la.d_end = (T)cosmo.D(a1);
-            la.sub_scale = (T)(1.0 / cosmo.gp(ah));
-            la.sub_dr = (T)std::fabs(cosmo.drift(a0, a1, ah));
-            la.sub_k2 = (T)cosmo.kick(ah, a1, a1);
-            lv.ddom = ddom;
-            lv.dd_end_dom = (T)((cosmo_p.D(a1) - cosmo_m.D(a1)) / (2 * DOM));
-            lv.dscale_dom = (T)((1.0 / cosmo_p.gp(ah) - 1.0 / cosmo_m.gp(ah)) / (2 * DOM));
+            sub_lens_args(a0, a1, la, lv);
             lv.phbar = reinterpret_cast<T*>(phbar);
         }
         launch_fill<double>(dots, 0.0, 64, st);
@@ -1185,18 +1176,39 @@ template <class T> struct Sim final : SimBase {
         return check_launch();
     }
 
+    // Sub-evolution fields of the derivative passes' lens arguments for the
+    // step a0 -> a1: the drift momentum is p - K2 f of the state at a1.
+    void sub_lens_args(double a0, double a1, LensArgs<T>& la, LensVjpArgs<T>& lv) {
+        const double ah = 0.5 * (a0 + a1);
+        la.sub = 1;
+        la.dtab = dtab;
+        la.d_end = (T)cosmo.D(a1);
+        la.sub_scale = (T)(1.0 / cosmo.gp(ah));
+        la.sub_dr = (T)std::fabs(cosmo.drift(a0, a1, ah));
+        la.sub_k2 = (T)cosmo.kick(ah, a1, a1);
+        lv.ddom = ddom;
+        lv.dd_end_dom = (T)((cosmo_p.D(a1) - cosmo_m.D(a1)) / (2 * DOM));
+        lv.dscale_dom = (T)((1.0 / cosmo_p.gp(ah) - 1.0 / cosmo_m.gp(ah)) / (2 * DOM));
+    }
+
     int lens_jvp(double a0, double a1, void* kd) override {
         if (!kd) return PM_EINVAL;
-        if (interp || pgd) return PM_EINVAL;  // no tangent pass for these modes
+        if (pgd) return PM_EINVAL;  // no tangent pass for the PGD correction
         if (!tan_valid || !at_a(a1)) return PM_ESTATE;
         LensArgs<T> la;
         LensVjpArgs<T> lv;
         double chi_near, chi_far;
         if (!derivative_lens_args(a0, a1, la, lv, chi_near, chi_far)) return PM_OK;
         const double om_dot = tan_om;
+        T ck2 = T(0);
+        if (interp) {
+            sub_lens_args(a0, a1, la, lv);
+            const double ah = 0.5 * (a0 + a1);
+            ck2 = (T)(om_dot * (cosmo_p.kick(ah, a1, a1) - cosmo_m.kick(ah, a1, a1)) / (2 * DOM));
+        }
         T* kdot = reinterpret_cast<T*>(kd);
         { ProfScope ps(prof, "lens_jvp");
-          launch_lens_jvp<T>(cur, geo, la, lv, tx, (T)om_dot, kdot, st); }
+          launch_lens_jvp<T>(cur, geo, la, lv, tx, tp, tf, ck2, (T)om_dot, kdot, st); }
         if (om_dot != 0.0) {
             // the mean term's Omega_m derivative at a fixed shell partition
             MapAdd<T> mv{};

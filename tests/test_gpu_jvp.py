@@ -236,9 +236,9 @@ def test_tangent_error_paths():
         sim.step_jvp(0.4, 0.5)
         assert code(sim.init_ic_jvp, noise) == PM_ESTATE     # no longer the initial conditions
         kd = sim.new_maps()
-        sim.set_interpolation(True)
-        assert code(sim.lens_jvp, 0.4, 0.5, kd) == PM_EINVAL
-        sim.set_interpolation(False)
+        sim.set_pgd(0.5, 0.5, 0.05, 1.5)
+        assert code(sim.lens_jvp, 0.4, 0.5, kd) == PM_EINVAL   # no tangent of the PGD shift
+        sim.set_pgd(0.5, 0.5, 0.05, 1.5, on=False)
         sim.lens_jvp(0.4, 0.5, kd)
         xd, pd, fd = sim.get_tangent()
         sim.step(0.5, 0.6)                                     # a plain step drops the tangent
@@ -249,3 +249,86 @@ def test_tangent_error_paths():
         sim.sync()
         assert torch.isfinite(kd).all() and torch.isfinite(xd).all() and torch.isfinite(fd).all()
         assert torch.count_nonzero(f2) == 0                    # zero tangent, zero force tangent
+
+
+@pytest.mark.parametrize("seed", [None, 0x5EED1234ABCD], ids=["plain", "rotated"])
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+def test_lens_tangent_with_subevolution(dtype, seed):
+    """A sub-evolved shell's tangent at a state with momenta, along a position
+    and momentum tangent and Omega_m: the drift momentum's tangent is
+    p_dot - K2 f_dot - Om_dot K2' f, with the force tangent of the state."""
+    from oracle import jvp, lens, pm
+    wl = W.Workload("lensjvpsub", 16, 32, 64.0, 0.4, 1.0, 3, 24, 4.0, (1.0, 2.0))
+    c = cosmo_of(wl)
+    x = _off_node_planes(W.clustered_positions(16, 32, wl.box, seed=21), wl.box, 32)
+    rng = np.random.default_rng(45)
+    p = 10.0 * rng.standard_normal(x.shape)
+    xd = rng.standard_normal(x.shape)
+    pd = rng.standard_normal(x.shape)
+    a_far, a_near = 0.55, 0.7
+    ah = 0.5 * (a_far + a_near)
+    om_dot = 0.6
+    rd = _rd(dtype)
+    x, p, xd, pd = rd(x), rd(p), rd(xd), rd(pd)
+    log(f"sub-evolved lens tangent {dtype} rotation={seed}")
+    with new_sim(wl, dtype) as sim:
+        sim.set_interpolation(True)
+        if seed is not None:
+            sim.set_replica_rotation(seed)
+        T = lambda v: torch.tensor(v, dtype=dtype, device="cuda")
+        sim.set_state(T(x), T(p), a_near)
+        sim.set_tangent(T(xd), T(pd), om_dot)
+        kd = sim.new_maps()
+        sim.lens_jvp(a_far, a_near, kd)
+        kg = to_np(kd)
+        sim.sync()
+    log("oracle")
+    f = pm.particle_force(x, 16, 32, wl.box)
+    fd = jvp.force_jvp(x, xd, 16, 32, wl.box)
+    k2 = jvp.step_factors(c, a_far, a_near)[2]
+    dk2 = (jvp.step_factors(jvp._with_om(c, 0.3 + 1e-5), a_far, a_near)[2]
+           - jvp.step_factors(jvp._with_om(c, 0.3 - 1e-5), a_far, a_near)[2]) / 2e-5
+    sub = (p - k2 * f, ah)
+    geom = lens.MapGeometry(wl.npix, wl.fov_deg, wl.z_src, c, rotation_seed=seed)
+    ko = jvp.lens_jvp(x, xd, a_far, a_near, c, wl.box, 16, geom, sub=sub,
+                      ph_dot=pd - k2 * fd - om_dot * dk2 * f)
+    # Omega_m moves the images, so its difference takes a small step (the
+    # splat's pixel-edge kinks)
+    ko += om_dot * jvp.lens_om_tangent(x, a_far, a_near, c, wl.box, 16, geom, dom=1e-7, sub=sub)
+    plain = jvp.lens_jvp(x, xd, a_far, a_near, c, wl.box, 16, geom)
+    e = rel_rms(kg, ko)
+    log(f"sub-evolved lens tangent {dtype}: {e:.2e} (sub-evolution changes it by "
+        f"{rel_rms(plain, ko):.2e})")
+    assert rel_rms(plain, ko) > 1e-2
+    assert e < (1e-6 if dtype == torch.float64 else 1e-4)
+
+
+@pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
+def test_model_tangent_with_subevolution(dtype):
+    from oracle import jvp, lens
+    from paper_2012_07266_amd.autograd import jvp as run_jvp
+    wl = _small()
+    c = cosmo_of(wl)
+    a = wl.a_grid()
+    rd = _rd(dtype)
+    noise = rd(W.white_noise(wl.np_side, wl.seed))
+    nd = rd(np.random.default_rng(46).standard_normal(noise.shape))
+    om_dot, s8_dot = 0.5, -0.8
+    log(f"model tangent with sub-evolution {dtype}")
+    with new_sim(wl, dtype) as sim:
+        sim.set_interpolation(True)
+        T = lambda v: torch.tensor(v, dtype=dtype, device="cuda")
+        kap, kd = run_jvp(sim, T(noise), a, T(nd), om_dot, s8_dot)
+        kg, kdg = to_np(kap), to_np(kd)
+        sim.sync()
+    log("oracle")
+    geom = lens.MapGeometry(wl.npix, wl.fov_deg, wl.z_src, c)
+    # a step of 1e-7 in the oracle's Omega_m differences (sub-evolved images
+    # move with Omega_m); the library's 1e-5 differences of the scalar
+    # factors differ from it at O(1e-10)
+    ko, kdo = jvp.kappa_jvp(noise, nd, om_dot, s8_dot, c, wl.box, wl.nm_side, a, geom,
+                            dom=1e-7, interpolation=True)
+    e_k, e_d = rel_rms(kg, ko), rel_rms(kdg, kdo)
+    log(f"model tangent with sub-evolution {dtype}: kappa {e_k:.2e}, kappa_dot {e_d:.2e}")
+    assert e_k < (1e-10 if dtype == torch.float64 else 1e-4)
+    assert e_d < (1e-8 if dtype == torch.float64 else 1e-3)
