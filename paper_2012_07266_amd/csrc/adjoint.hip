@@ -90,17 +90,43 @@ __device__ __forceinline__ void block_max(uint32_t* dst, float v, float* red) {
     }
 }
 
-template <class T>
-__device__ __forceinline__ void stage_tile(T* ft, const T* mesh, int nm, int ox, int oy, int oz,
-                                           int tid) {
+// Global offset of entry i of a tile's 17^3 box at origin (ox, oy, oz),
+// periodic.
+__device__ __forceinline__ long tile_offset(int i, int nm, int ox, int oy, int oz) {
+    const int x = i / (TE * TE), y = (i / TE) % TE, z = i % TE;
+    int gx = ox + x, gy = oy + y, gz = oz + z;
+    if (gx >= nm) gx -= nm;
+    if (gy >= nm) gy -= nm;
+    if (gz >= nm) gz -= nm;
+    return ((long)gx * nm + gy) * nm + gz;
+}
+
+// Stage the 17^3 boxes of NM meshes into LDS.  Every load of the batch is
+// issued before the first LDS store (slots past the box repeat its last
+// entry and are not stored): a loop that stores each value as it arrives
+// waits for every load in turn.
+template <class T, int NM>
+__device__ __forceinline__ void stage_tiles(T (*ft)[TE * TE * TE], const T* const (&mesh)[NM],
+                                            int nm, int ox, int oy, int oz, int tid) {
     constexpr int TC = TE * TE * TE;
-    for (int i = tid; i < TC; i += AB) {
-        int x = i / (TE * TE), y = (i / TE) % TE, z = i % TE;
-        int gx = ox + x, gy = oy + y, gz = oz + z;
-        if (gx >= nm) gx -= nm;
-        if (gy >= nm) gy -= nm;
-        if (gz >= nm) gz -= nm;
-        ft[i] = mesh[((long)gx * nm + gy) * nm + gz];
+    constexpr int IT = (TC + AB - 1) / AB;
+    T v[NM][IT];
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        int i = tid + it * AB;
+        i = i < TC ? i : TC - 1;
+        const long c = tile_offset(i, nm, ox, oy, oz);
+#pragma unroll
+        for (int m = 0; m < NM; ++m) v[m][it] = mesh[m][c];
+    }
+    issue_fence();
+#pragma unroll
+    for (int it = 0; it < IT; ++it) {
+        const int i = tid + it * AB;
+        if (i < TC) {
+#pragma unroll
+            for (int m = 0; m < NM; ++m) ft[m][i] = v[m][it];
+        }
     }
 }
 
@@ -123,9 +149,10 @@ __global__ __launch_bounds__(AB) void k_fvjp_readout(Parts<T> p, SortBufs s, Geo
     const int b0 = tile_block(g, tx, ty, tz);
     const uint32_t lo = s.start[b0], hi = s.start[b0 + TILE / KZ];
     if (lo == hi) return;
-    stage_tile(ft[0], f0, g.nm, ox, oy, oz, tid);
-    stage_tile(ft[1], f1, g.nm, ox, oy, oz, tid);
-    stage_tile(ft[2], f2, g.nm, ox, oy, oz, tid);
+    {
+        const T* const fm[3] = {f0, f1, f2};
+        stage_tiles<T, 3>(ft, fm, g.nm, ox, oy, oz, tid);
+    }
     __syncthreads();
     const long n = g.npart;
     double dot = 0.0;
@@ -178,7 +205,7 @@ __global__ __launch_bounds__(AB) void k_fvjp_paintgrad(Parts<T> p, SortBufs s, G
                                                        const T* phbar, T* sb0, T* sb1, T* sb2,
                                                        double* dots) {
     constexpr int TC = TE * TE * TE;
-    __shared__ T ft[TC];
+    __shared__ T ft[1][TC];
     __shared__ double red[AB / 64];
     const int tid = threadIdx.x;
     const int t = xcd_remap(blockIdx.x, gridDim.x);
@@ -187,7 +214,10 @@ __global__ __launch_bounds__(AB) void k_fvjp_paintgrad(Parts<T> p, SortBufs s, G
     const int b0 = tile_block(g, tx, ty, tz);
     const uint32_t lo = s.start[b0], hi = s.start[b0 + TILE / KZ];
     if (lo == hi) return;
-    stage_tile(ft, rhobar, g.nm, ox, oy, oz, tid);
+    {
+        const T* const fm[1] = {rhobar};
+        stage_tiles<T, 1>(ft, fm, g.nm, ox, oy, oz, tid);
+    }
     __syncthreads();
     const long n = g.npart;
     double a1 = 0.0, a2 = 0.0, a3 = 0.0;
@@ -201,7 +231,7 @@ __global__ __launch_bounds__(AB) void k_fvjp_paintgrad(Parts<T> p, SortBufs s, G
             T w[3][2];
             cic_setup(g, id, d, ox, oy, oz, base, w);
             T val, gr[3];
-            cic_grad(ft, base, w, val, gr);
+            cic_grad(ft[0], base, w, val, gr);
             T xb[3], pb[3];
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
@@ -640,9 +670,10 @@ __global__ __launch_bounds__(AB) void k_fjvp_gather(Parts<T> p, SortBufs s, Geo 
     const int b0 = tile_block(g, tx, ty, tz);
     const uint32_t lo = s.start[b0], hi = s.start[b0 + TILE / KZ];
     if (lo == hi) return;
-    stage_tile(ft[0], f0, g.nm, ox, oy, oz, tid);
-    stage_tile(ft[1], f1, g.nm, ox, oy, oz, tid);
-    stage_tile(ft[2], f2, g.nm, ox, oy, oz, tid);
+    {
+        const T* const fm[3] = {f0, f1, f2};
+        stage_tiles<T, 3>(ft, fm, g.nm, ox, oy, oz, tid);
+    }
     __syncthreads();
     const long n = g.npart;
     float vmax = 0.f;
@@ -687,9 +718,10 @@ __global__ __launch_bounds__(AB) void k_fjvp_readout_kick(Parts<T> p, SortBufs s
     const int b0 = tile_block(g, tx, ty, tz);
     const uint32_t lo = s.start[b0], hi = s.start[b0 + TILE / KZ];
     if (lo == hi) return;
-    stage_tile(ft[0], m0, g.nm, ox, oy, oz, tid);
-    stage_tile(ft[1], m1, g.nm, ox, oy, oz, tid);
-    stage_tile(ft[2], m2, g.nm, ox, oy, oz, tid);
+    {
+        const T* const fm[3] = {m0, m1, m2};
+        stage_tiles<T, 3>(ft, fm, g.nm, ox, oy, oz, tid);
+    }
     __syncthreads();
     const long n = g.npart;
     for (uint32_t k0 = lo; k0 < hi; k0 += AB) {
