@@ -240,8 +240,11 @@ int pm_background(const pm_sim* sim, double a, double out[3]);
  * dL/dsigma_8), ACCUMULATED.  Omega_m derivatives of scalar factors are
  * central differences with step 1e-5; membership is held fixed: the distance
  * bounds of each shell, and which images lie in front of each source plane
- * (the lens weight vanishes there, so this changes no derivative).  Each call waits for its stream at the end
- * (it reads reduced scalars back).
+ * (the lens weight vanishes there, so this changes no derivative).  With a
+ * host cosmo_bar each call waits for its stream at the end (it reads reduced
+ * scalars back).  cosmo_bar may be NULL: the call then adds its contribution
+ * to an accumulator on the device, in stream order and without waiting, and
+ * pm_vjp_cosmo_read returns the sum (a reverse pass then waits once).
  *
  * lens_project_vjp: state at a1.  x_bar += (d kappa_shell / dx)^T kappa_bar,
  * cosmo_bar[0] += kappa_bar . d kappa_shell / dOmega_m at fixed positions.
@@ -279,6 +282,12 @@ int pm_step_vjp(pm_sim* sim, double a0, double a1, double a2, void* x_bar, void*
  * x_bar, p_bar are read only.  Errors: PM_ESTATE, PM_EINVAL. */
 int pm_init_ic_vjp(pm_sim* sim, double a1, const void* x_bar, const void* p_bar, void* noise_bar,
                    double cosmo_bar[2]);
+
+/* pm_vjp_cosmo_read: wait for the stream, add the device accumulator of the
+ * calls above made with cosmo_bar = NULL to cosmo_bar (host [2]) and clear
+ * it (it is also cleared by pm_create and pm_reconfigure).
+ * Errors: PM_EINVAL (NULL pointer), PM_EDEVICE. */
+int pm_vjp_cosmo_read(pm_sim* sim, double cosmo_bar[2]);
 
 /* ---- forward mode (Jacobian-vector products) -------------------------------
  * The paper's automatic differentiation gives directional derivatives (Jvp)

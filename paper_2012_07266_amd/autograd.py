@@ -36,7 +36,9 @@ def reverse_pass(sim: Simulation, a_grid: Sequence[float], states, kappa_bar: to
     kappa_bar = kappa_bar.to(device=sim.device, dtype=sim.dtype).contiguous()
     x_bar = torch.zeros((3, sim.n_particles), dtype=sim.dtype, device=sim.device)
     p_bar = torch.zeros_like(x_bar)
-    cb = np.zeros(2)
+    # the cosmology cotangent accumulates on the device: no wait per call
+    sim.vjp_cosmo_read()
+    cb = None
     # with sub-evolution each shell also has the cotangent of its step's
     # drift momentum, which joins p_bar at that step's drift
     ph_bar = torch.zeros_like(x_bar) if sim.interpolation else None
@@ -51,7 +53,8 @@ def reverse_pass(sim: Simulation, a_grid: Sequence[float], states, kappa_bar: to
     x0, p0 = states[0]
     sim.set_state(x0, p0, a_grid[0])
     noise_bar = sim.init_ic_vjp(a_grid[1], x_bar, p_bar, cb)
-    return noise_bar, float(cb[0]), float(cb[1])
+    g_om, g_s8 = sim.vjp_cosmo_read()
+    return noise_bar, float(g_om), float(g_s8)
 
 
 def jvp(sim: Simulation, noise: torch.Tensor, a_grid: Sequence[float], noise_dot: torch.Tensor,

@@ -65,6 +65,22 @@ template <class T>
 void launch_lens_vjp(Parts<T> p, Geo g, const LensArgs<T>& la, const LensVjpArgs<T>& lv,
                      const T* kbar, T* xbar, double* dots, hipStream_t st);
 
+// acc[0] += sum_i c0[i] dots[idx[i]], acc[1] += sum_i c1[i] dots[idx[i]]
+// (the cosmology cotangent accumulated on the device, in stream order).
+struct CosmoCoef {
+    int n = 0;
+    int idx[8 + MAX_SRC];
+    double c0[8 + MAX_SRC];
+    double c1[8 + MAX_SRC];
+    void add(int i, double a, double b) {
+        idx[n] = i;
+        c0[n] = a;
+        c1[n] = b;
+        ++n;
+    }
+};
+void launch_cosmo_acc(const double* dots, double* acc, const CosmoCoef& c, hipStream_t st);
+
 // ---- forward mode (tangents; tangent arrays [3][npart] in tile order, Mpc/h)
 // y = a y + b x over n elements (y not read when a == 0).
 template <class T>

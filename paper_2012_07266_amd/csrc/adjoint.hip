@@ -1051,6 +1051,21 @@ void launch_map_add(T* kdot, int npix, int nsrc, const MapAdd<T>& mv, hipStream_
                        npix2, nsrc, mv);
 }
 
+__global__ void k_cosmo_acc(const double* dots, double* acc, CosmoCoef c) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double a0 = 0.0, a1 = 0.0;
+    for (int i = 0; i < c.n; ++i) {
+        a0 += c.c0[i] * dots[c.idx[i]];
+        a1 += c.c1[i] * dots[c.idx[i]];
+    }
+    acc[0] += a0;
+    acc[1] += a1;
+}
+
+void launch_cosmo_acc(const double* dots, double* acc, const CosmoCoef& c, hipStream_t st) {
+    hipLaunchKernelGGL(k_cosmo_acc, dim3(1), dim3(64), 0, st, dots, acc, c);
+}
+
 #define ML_INST_JVP(T)                                                                               \
     template void launch_lin<T>(T*, const T*, T, T, long, hipStream_t);                              \
     template void launch_ic_tangent<T>(const T*, const T*, const T*, const T*, const T*, const T*,   \

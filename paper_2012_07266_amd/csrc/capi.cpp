@@ -44,7 +44,7 @@ struct Layout {
 struct ArenaPlan {
     size_t disp[2], mom[2], id[2], acc, key, count, start, scan_sum, status;
     size_t mesh[3], nyq[3], halo, tw_nm, tw_hm, twp_nm, tw_np, tw_hp, twp_np, g_ic, atab, dtab, pmax;
-    size_t xbc, fbc, dots, fmax, noise, g_ic_dom, adom, ddom;
+    size_t xbc, fbc, dots, fmax, noise, g_ic_dom, adom, ddom, cacc;
     size_t total;
 };
 
@@ -96,6 +96,7 @@ ArenaPlan plan_arena(const pm_params& p, const lens_params& l, size_t es) {
     a.g_ic_dom = L.take((3 * (np_ / 2) * (np_ / 2) + 1) * es);
     a.adom = L.take(ATAB_N * es);
     a.ddom = L.take(ATAB_N * es);
+    a.cacc = L.take(256);
     a.total = L.bytes;
     return a;
 }
@@ -220,6 +221,7 @@ struct SimBase {
                          const void* phbar, double* cb) = 0;
     virtual int init_ic_vjp(double a1, const void* xbar, const void* pbar, void* nbar,
                             double* cb) = 0;
+    virtual int vjp_cosmo_read(double* cb) = 0;
     virtual int init_ic_jvp(const void* nd, double om_dot, double s8_dot) = 0;
     virtual int set_tangent(const void* xd, const void* pd, double om_dot) = 0;
     virtual int get_tangent(void* xd, void* pd, void* fd) = 0;
@@ -249,6 +251,7 @@ template <class T> struct Sim final : SimBase {
     uint32_t* pmax_bits = nullptr;
     T *xbc, *fbc, *noise_copy, *g_ic_dom, *adom, *ddom;
     double* dots = nullptr;
+    double* cacc = nullptr;  // device accumulator of (dL/dOmega_m, dL/dsigma_8)
     uint32_t* fmax_bits = nullptr;
     HostCosmo cosmo_p, cosmo_m;  // Omega_m +- DOM for the finite-difference factors
     static constexpr double DOM = 1e-5;
@@ -374,6 +377,7 @@ template <class T> struct Sim final : SimBase {
         g_ic_dom = at<T>(ap.g_ic_dom);
         adom = at<T>(ap.adom);
         ddom = at<T>(ap.ddom);
+        cacc = at<double>(ap.cacc);
         return upload_tables();
     }
 
@@ -473,6 +477,7 @@ template <class T> struct Sim final : SimBase {
             if ((rc = upload(ap.ddom, w))) return rc;
         }
         launch_fill_u32(status, 0u, 1, st);
+        launch_fill<double>(cacc, 0.0, 2, st);
         HIPCHK(hipStreamSynchronize(st));
         return PM_OK;
     }
@@ -906,7 +911,7 @@ template <class T> struct Sim final : SimBase {
 
     int step_vjp(double a0, double a1, double a2, void* xbar, void* pbar, const void* phbar,
                  double* cb) override {
-        if (!xbar || !pbar || !cb) return PM_EINVAL;
+        if (!xbar || !pbar) return PM_EINVAL;
         if (!at_a(a1)) return PM_ESTATE;
         double ah = 0.5 * (a0 + a1);
         double k2 = cosmo.kick(ah, a1, a1), dr = cosmo.drift(a0, a1, ah);
@@ -925,6 +930,13 @@ template <class T> struct Sim final : SimBase {
                   reinterpret_cast<const T*>(phbar));
         int rc = check_launch();
         if (rc) return rc;
+        if (!cb) {
+            CosmoCoef c;
+            c.add(0, dk2 + dk1n, 0.0);
+            c.add(1, ddr, 0.0);
+            launch_cosmo_acc(dots, cacc, c, st);
+            return check_launch();
+        }
         double d[2];
         if ((rc = read_dots(d, 2))) return rc;
         cb[0] += d[0] * (dk2 + dk1n) + d[1] * ddr;
@@ -932,7 +944,7 @@ template <class T> struct Sim final : SimBase {
     }
 
     int init_ic_vjp(double a1, const void* xbar, const void* pbar, void* nbar, double* cb) override {
-        if (!xbar || !pbar || !nbar || !cb) return PM_EINVAL;
+        if (!xbar || !pbar || !nbar) return PM_EINVAL;
         if (a_cur < 0 || !(a1 > a_cur)) return PM_ESTATE;
         const double a0 = a_cur, ah = 0.5 * (a0 + a1);
         const double k1 = cosmo.kick(a0, ah, a0);
@@ -963,6 +975,16 @@ template <class T> struct Sim final : SimBase {
         meshes_valid = false;
         int rc = check_launch();
         if (rc) return rc;
+        if (!cb) {
+            CosmoCoef c;
+            c.add(0, dk1, 0.0);
+            c.add(1, dd0, 0.0);
+            c.add(2, dgp0, 0.0);
+            c.add(5, 1.0, 0.0);
+            c.add(3, 0.0, 1.0 / P.sigma8);
+            launch_cosmo_acc(dots, cacc, c, st);
+            return check_launch();
+        }
         double d[6];
         if ((rc = read_dots(d, 6))) return rc;
         cb[0] += d[0] * dk1 + d[1] * dd0 + d[2] * dgp0 + d[5];
@@ -1008,7 +1030,7 @@ template <class T> struct Sim final : SimBase {
 
     int lens_vjp(double a0, double a1, const void* kbar, void* xbar, void* phbar,
                  double* cb) override {
-        if (!kbar || !xbar || !cb) return PM_EINVAL;
+        if (!kbar || !xbar) return PM_EINVAL;
         if (pgd) return PM_EINVAL;  // no reverse pass for the PGD correction
         if (interp && !phbar) return PM_EINVAL;
         if (!at_a(a1)) return PM_ESTATE;
@@ -1029,17 +1051,37 @@ template <class T> struct Sim final : SimBase {
         launch_map_sums<T>(kb, npix, nsrc, dots + 8, st);
         int rc = check_launch();
         if (rc) return rc;
-        double d[8 + MAX_SRC];
-        if ((rc = read_dots(d, 8 + nsrc))) return rc;
-        double g = d[4];
-        // mean term of each map at a fixed shell partition
+        // the mean term of each map at a fixed shell partition
+        double dmean[MAX_SRC];
         for (int s = 0; s < nsrc; ++s) {
             double mp = cosmo_p.shell_mean(chi_near, chi_far, chisrc_p[s]);
             double mm = cosmo_m.shell_mean(chi_near, chi_far, chisrc_m[s]);
-            g += d[8 + s] * (mp - mm) / (2 * DOM);
+            dmean[s] = (mp - mm) / (2 * DOM);
         }
+        if (!cb) {
+            CosmoCoef c;
+            c.add(4, 1.0, 0.0);
+            for (int s = 0; s < nsrc; ++s) c.add(8 + s, dmean[s], 0.0);
+            launch_cosmo_acc(dots, cacc, c, st);
+            return check_launch();
+        }
+        double d[8 + MAX_SRC];
+        if ((rc = read_dots(d, 8 + nsrc))) return rc;
+        double g = d[4];
+        for (int s = 0; s < nsrc; ++s) g += d[8 + s] * dmean[s];
         cb[0] += g;
         return PM_OK;
+    }
+
+    int vjp_cosmo_read(double* cb) override {
+        if (!cb) return PM_EINVAL;
+        double acc[2];
+        HIPCHK(hipMemcpyAsync(acc, cacc, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        launch_fill<double>(cacc, 0.0, 2, st);
+        cb[0] += acc[0];
+        cb[1] += acc[1];
+        return check_launch();
     }
 
     // ---- forward mode (tangents) ---------------------------------------------
@@ -1330,6 +1372,9 @@ int pm_step_vjp(pm_sim* sim, double a0, double a1, double a2, void* x_bar, void*
 int pm_init_ic_vjp(pm_sim* sim, double a1, const void* x_bar, const void* p_bar, void* noise_bar,
                    double cosmo_bar[2]) {
     return sim ? sim->impl->init_ic_vjp(a1, x_bar, p_bar, noise_bar, cosmo_bar) : PM_EINVAL;
+}
+int pm_vjp_cosmo_read(pm_sim* sim, double cosmo_bar[2]) {
+    return sim ? sim->impl->vjp_cosmo_read(cosmo_bar) : PM_EINVAL;
 }
 int pm_init_ic_jvp(pm_sim* sim, const void* noise_dot, double omega_m_dot, double sigma8_dot) {
     return sim ? sim->impl->init_ic_jvp(noise_dot, omega_m_dot, sigma8_dot) : PM_EINVAL;

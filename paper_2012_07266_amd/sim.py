@@ -209,28 +209,46 @@ class Simulation:
         check(lib().pm_sync(self._h), "pm_sync")
 
     # -- reverse mode -------------------------------------------------------
+    # cosmo_bar: a (2,) float64 numpy array, accumulated (the call waits for
+    # the stream), or None: accumulated on the device, see vjp_cosmo_read
+    @staticmethod
+    def _cb(cosmo_bar):
+        return None if cosmo_bar is None else (ctypes.c_double * 2)(*cosmo_bar)
+
+    @staticmethod
+    def _cb_back(cb, cosmo_bar):
+        if cosmo_bar is not None:
+            cosmo_bar[:] = list(cb)
+
     def lens_vjp(self, a0, a1, kappa_bar, x_bar, cosmo_bar, ph_bar=None):
-        """x_bar += d kappa/dx^T kappa_bar (state at a1); cosmo_bar (2,) float64
-        numpy array, accumulated.  With sub-evolution on, ph_bar [3][Np^3]
-        receives the drift momentum's cotangent (accumulated), for step_vjp."""
-        cb = (ctypes.c_double * 2)(*cosmo_bar)
+        """x_bar += d kappa/dx^T kappa_bar (state at a1).  With sub-evolution
+        on, ph_bar [3][Np^3] receives the drift momentum's cotangent
+        (accumulated), for step_vjp."""
+        cb = self._cb(cosmo_bar)
         check(lib().lens_project_vjp(self._h, float(a0), float(a1), _ptr(kappa_bar),
                                      _ptr(x_bar), _ptr(ph_bar), cb), "lens_project_vjp")
-        cosmo_bar[:] = list(cb)
+        self._cb_back(cb, cosmo_bar)
 
     def step_vjp(self, a0, a1, a2, x_bar, p_bar, cosmo_bar, ph_bar=None):
-        cb = (ctypes.c_double * 2)(*cosmo_bar)
+        cb = self._cb(cosmo_bar)
         check(lib().pm_step_vjp(self._h, float(a0), float(a1), float(a2), _ptr(x_bar),
                                 _ptr(p_bar), _ptr(ph_bar), cb), "pm_step_vjp")
-        cosmo_bar[:] = list(cb)
+        self._cb_back(cb, cosmo_bar)
 
     def init_ic_vjp(self, a1, x_bar, p_bar, cosmo_bar):
         noise_bar = torch.empty((self.np_side,) * 3, dtype=self.dtype, device=self.device)
-        cb = (ctypes.c_double * 2)(*cosmo_bar)
+        cb = self._cb(cosmo_bar)
         check(lib().pm_init_ic_vjp(self._h, float(a1), _ptr(x_bar), _ptr(p_bar),
                                    _ptr(noise_bar), cb), "pm_init_ic_vjp")
-        cosmo_bar[:] = list(cb)
+        self._cb_back(cb, cosmo_bar)
         return noise_bar
+
+    def vjp_cosmo_read(self):
+        """(dL/dOmega_m, dL/dsigma_8) accumulated on the device by the reverse
+        calls made with cosmo_bar=None; waits for the stream, then clears."""
+        cb = (ctypes.c_double * 2)(0.0, 0.0)
+        check(lib().pm_vjp_cosmo_read(self._h, cb), "pm_vjp_cosmo_read")
+        return np.array(list(cb))
 
     # -- forward mode (tangents) -------------------------------------------
     def _tangent(self, t, shape):

@@ -216,3 +216,36 @@ def test_lens_vjp_static_field(dtype):
     log(f"lens vjp {dtype}: x rel-rms {e_x:.2e}, Om {cb[0]:.10e} vs {om:.10e} ({e_om:.2e})")
     assert e_x < (1e-9 if dtype == torch.float64 else 1e-4)
     assert e_om < (1e-6 if dtype == torch.float64 else 1e-4)
+
+
+def test_device_cosmology_accumulator_matches_host_reads():
+    """The reverse calls with cosmo_bar = None add the same Omega_m and
+    sigma_8 cotangents on the device as the calls that read them back."""
+    from tests.gpu_util import new_sim
+    wl, kbar = _small()
+    wl = W.Workload("acc", 16, 32, 48.0, 0.4, 1.0, 3, 16, 3.0, (1.0,), seed=11)
+    a = wl.a_grid()
+    noise = torch.tensor(W.white_noise(16, 5), dtype=torch.float64, device="cuda")
+    kb = torch.tensor(np.random.default_rng(6).standard_normal((1, 16, 16)), device="cuda")
+    xb0 = torch.tensor(np.random.default_rng(7).standard_normal((3, 16 ** 3)), device="cuda")
+    with new_sim(wl, torch.float64) as sim:
+        sim.init_ic(noise, a[0])
+        st0 = sim.get_state()
+        sim.step(a[0], a[1])
+        st1 = sim.get_state()
+        res = []
+        for host in (True, False):
+            sim.vjp_cosmo_read()
+            cb = np.zeros(2) if host else None
+            xb, pb = xb0.clone(), torch.zeros_like(xb0)
+            sim.set_state(*st1, a[1])
+            sim.lens_vjp(a[0], a[1], kb, xb, cb)
+            sim.step_vjp(a[0], a[1], -1.0, xb, pb, cb)
+            sim.init_ic(noise, a[0])
+            sim.set_state(*st0, a[0])
+            sim.init_ic_vjp(a[1], xb, pb, cb)
+            res.append(cb if host else sim.vjp_cosmo_read())
+        sim.sync()
+    log(f"cosmology cotangent: host reads {res[0]}, device accumulator {res[1]}")
+    assert np.all(res[0] != 0)
+    np.testing.assert_allclose(res[1], res[0], rtol=1e-13)
