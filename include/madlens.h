@@ -283,6 +283,20 @@ int pm_step_vjp(pm_sim* sim, double a0, double a1, double a2, void* x_bar, void*
 int pm_init_ic_vjp(pm_sim* sim, double a1, const void* x_bar, const void* p_bar, void* noise_bar,
                    double cosmo_bar[2]);
 
+/* Checkpoints for the reverse pass, in the library's own particle order
+ * (displacements, momenta, particle ids and the sort's block offsets): no
+ * conversion to lattice order on save and no sort on load.
+ * pm_checkpoint_bytes: the size of one checkpoint of this handle (0 for a
+ * NULL handle).  pm_checkpoint_save: copy the current state into buf (a
+ * device buffer of that size, owned by the caller; asynchronous).
+ * pm_checkpoint_load: restore a checkpoint made by a handle of the same
+ * shape, at scale factor a; the force is recomputed there, as with
+ * pm_set_state.  Errors: PM_EINVAL (NULL buffer, a <= 0), PM_ESTATE (save
+ * without a state). */
+size_t pm_checkpoint_bytes(const pm_sim* sim);
+int pm_checkpoint_save(pm_sim* sim, void* buf);
+int pm_checkpoint_load(pm_sim* sim, const void* buf, double a);
+
 /* pm_vjp_cosmo_read: wait for the stream, add the device accumulator of the
  * calls above made with cosmo_bar = NULL to cosmo_bar (host [2]) and clear
  * it (it is also cleared by pm_create and pm_reconfigure).

@@ -71,6 +71,9 @@ SIGNATURES = {
     "lens_project_vjp": (_I, [_P, _D, _D, _P, _P, _P, ctypes.POINTER(_D)]),
     "pm_step_vjp": (_I, [_P, _D, _D, _D, _P, _P, _P, ctypes.POINTER(_D)]),
     "pm_init_ic_vjp": (_I, [_P, _D, _P, _P, _P, ctypes.POINTER(_D)]),
+    "pm_checkpoint_bytes": (ctypes.c_size_t, [_P]),
+    "pm_checkpoint_save": (_I, [_P, _P]),
+    "pm_checkpoint_load": (_I, [_P, _P, _D]),
     "pm_vjp_cosmo_read": (_I, [_P, ctypes.POINTER(_D)]),
     "pm_init_ic_jvp": (_I, [_P, _P, _D, _D]),
     "pm_set_tangent": (_I, [_P, _P, _P, _D]),

@@ -1,10 +1,11 @@
 """Differentiable convergence maps: torch.autograd.Function over the C ABI.
 
 Forward: Zel'dovich initial conditions from white noise, the KDK steps and
-the lens projection of every shell, keeping (x, p) after each step as a
-checkpoint (24 bytes per particle per step in float32).  Backward: for each
-step in reverse, restore its end state (which recomputes the force there),
-reverse its shell and its step, then reverse the initial conditions.
+the lens projection of every shell, keeping the state after each step as a
+checkpoint in the library's own particle order (28 bytes per particle per
+step in float32).  Backward: for each step in reverse, restore its end state
+(which recomputes the force there), reverse its shell and its step, then
+reverse the initial conditions.
 Forward mode (jvp): the tangent of (x, p, f) is carried with every step and
 each shell's tangent is accumulated, in one pass without checkpoints.  All
 arithmetic runs in the library; this module only orders the calls.
@@ -22,11 +23,11 @@ from .sim import Simulation
 def forward_with_checkpoints(sim: Simulation, noise: torch.Tensor, a_grid: Sequence[float]):
     kappa = sim.new_maps()
     sim.init_ic(noise, a_grid[0])
-    states = [sim.get_state()]
+    states = [sim.checkpoint()]
     for i in range(len(a_grid) - 1):
         sim.step(a_grid[i], a_grid[i + 1])
         sim.lens(a_grid[i], a_grid[i + 1], kappa)
-        states.append(sim.get_state())
+        states.append(sim.checkpoint())
     return kappa, states
 
 
@@ -43,15 +44,13 @@ def reverse_pass(sim: Simulation, a_grid: Sequence[float], states, kappa_bar: to
     # drift momentum, which joins p_bar at that step's drift
     ph_bar = torch.zeros_like(x_bar) if sim.interpolation else None
     for i in range(n - 1, -1, -1):
-        x1, p1 = states[i + 1]
-        sim.set_state(x1, p1, a_grid[i + 1])
+        sim.restore(states[i + 1], a_grid[i + 1])
         if ph_bar is not None:
             ph_bar.zero_()
         sim.lens_vjp(a_grid[i], a_grid[i + 1], kappa_bar, x_bar, cb, ph_bar)
         a2 = a_grid[i + 2] if i + 1 < n else -1.0
         sim.step_vjp(a_grid[i], a_grid[i + 1], a2, x_bar, p_bar, cb, ph_bar)
-    x0, p0 = states[0]
-    sim.set_state(x0, p0, a_grid[0])
+    sim.restore(states[0], a_grid[0])
     noise_bar = sim.init_ic_vjp(a_grid[1], x_bar, p_bar, cb)
     g_om, g_s8 = sim.vjp_cosmo_read()
     return noise_bar, float(g_om), float(g_s8)

@@ -222,6 +222,9 @@ struct SimBase {
     virtual int init_ic_vjp(double a1, const void* xbar, const void* pbar, void* nbar,
                             double* cb) = 0;
     virtual int vjp_cosmo_read(double* cb) = 0;
+    virtual size_t checkpoint_bytes() const = 0;
+    virtual int checkpoint_save(void* buf) = 0;
+    virtual int checkpoint_load(const void* buf, double a) = 0;
     virtual int init_ic_jvp(const void* nd, double om_dot, double s8_dot) = 0;
     virtual int set_tangent(const void* xd, const void* pd, double om_dot) = 0;
     virtual int get_tangent(void* xd, void* pd, void* fd) = 0;
@@ -830,6 +833,54 @@ template <class T> struct Sim final : SimBase {
         return check_launch();
     }
 
+    // Checkpoints in the library's own particle order: displacements,
+    // momenta, ids and the sort's block offsets, each 256-byte aligned.
+    size_t checkpoint_bytes() const override {
+        const size_t n = (size_t)geo.npart, es = sizeof(T);
+        const size_t nkeys = (size_t)ntiles;
+        auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+        return 2 * al(3 * n * es) + al(n * 4) + al((nkeys + 1) * 4);
+    }
+
+    int checkpoint_save(void* buf) override {
+        if (!buf) return PM_EINVAL;
+        if (a_cur < 0) return PM_ESTATE;
+        const size_t n = (size_t)geo.npart, es = sizeof(T);
+        auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+        char* b = reinterpret_cast<char*>(buf);
+        HIPCHK(hipMemcpyAsync(b, cur.disp, 3 * n * es, hipMemcpyDeviceToDevice, st));
+        b += al(3 * n * es);
+        HIPCHK(hipMemcpyAsync(b, cur.mom, 3 * n * es, hipMemcpyDeviceToDevice, st));
+        b += al(3 * n * es);
+        HIPCHK(hipMemcpyAsync(b, cur.id, n * 4, hipMemcpyDeviceToDevice, st));
+        b += al(n * 4);
+        HIPCHK(hipMemcpyAsync(b, sb.start, ((size_t)ntiles + 1) * 4, hipMemcpyDeviceToDevice, st));
+        return check_launch();
+    }
+
+    // Restore a checkpoint of this handle's shape at scale factor a: the
+    // particles come back in the order they were saved in, so no sort is
+    // needed; the force there is recomputed, as pm_set_state does.
+    int checkpoint_load(const void* buf, double a) override {
+        if (!buf || !(a > 0)) return PM_EINVAL;
+        const size_t n = (size_t)geo.npart, es = sizeof(T);
+        auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+        const char* b = reinterpret_cast<const char*>(buf);
+        HIPCHK(hipMemcpyAsync(cur.disp, b, 3 * n * es, hipMemcpyDeviceToDevice, st));
+        b += al(3 * n * es);
+        HIPCHK(hipMemcpyAsync(cur.mom, b, 3 * n * es, hipMemcpyDeviceToDevice, st));
+        b += al(3 * n * es);
+        HIPCHK(hipMemcpyAsync(cur.id, b, n * 4, hipMemcpyDeviceToDevice, st));
+        b += al(n * 4);
+        HIPCHK(hipMemcpyAsync(sb.start, b, ((size_t)ntiles + 1) * 4, hipMemcpyDeviceToDevice, st));
+        force(T(0), 0);
+        a_cur = a;
+        ic_fresh = false;
+        tan_valid = false;
+        kdk_a0 = kdk_a1 = -1.0;
+        return check_launch();
+    }
+
     int get_force(void* rho, void* fm, void* acc) override {
         if (a_cur < 0) return PM_ESTATE;
         size_t n3 = (size_t)P.nm * P.nm * P.nm;
@@ -1372,6 +1423,13 @@ int pm_step_vjp(pm_sim* sim, double a0, double a1, double a2, void* x_bar, void*
 int pm_init_ic_vjp(pm_sim* sim, double a1, const void* x_bar, const void* p_bar, void* noise_bar,
                    double cosmo_bar[2]) {
     return sim ? sim->impl->init_ic_vjp(a1, x_bar, p_bar, noise_bar, cosmo_bar) : PM_EINVAL;
+}
+size_t pm_checkpoint_bytes(const pm_sim* sim) { return sim ? sim->impl->checkpoint_bytes() : 0; }
+int pm_checkpoint_save(pm_sim* sim, void* buf) {
+    return sim ? sim->impl->checkpoint_save(buf) : PM_EINVAL;
+}
+int pm_checkpoint_load(pm_sim* sim, const void* buf, double a) {
+    return sim ? sim->impl->checkpoint_load(buf, a) : PM_EINVAL;
 }
 int pm_vjp_cosmo_read(pm_sim* sim, double cosmo_bar[2]) {
     return sim ? sim->impl->vjp_cosmo_read(cosmo_bar) : PM_EINVAL;

@@ -197,6 +197,21 @@ class Simulation:
         self._state_keep = (x, p)
         self.a = float(a)
 
+    def checkpoint(self) -> torch.Tensor:
+        """The current state in the library's own particle order (a device
+        byte tensor for restore)."""
+        buf = torch.empty(int(lib().pm_checkpoint_bytes(self._h)), dtype=torch.uint8,
+                          device=self.device)
+        check(lib().pm_checkpoint_save(self._h, _ptr(buf)), "pm_checkpoint_save")
+        return buf
+
+    def restore(self, buf: torch.Tensor, a: float):
+        """Restore a checkpoint at scale factor a (the force is recomputed)."""
+        if buf.dtype != torch.uint8 or buf.numel() != int(lib().pm_checkpoint_bytes(self._h)):
+            raise ValueError("not a checkpoint of this simulation's shape")
+        check(lib().pm_checkpoint_load(self._h, _ptr(buf), float(a)), "pm_checkpoint_load")
+        self.a = float(a)
+
     def get_force(self):
         nm, n = self.nm_side, self.n_particles
         rho = torch.empty((nm, nm, nm), dtype=self.dtype, device=self.device)

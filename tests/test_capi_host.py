@@ -83,6 +83,9 @@ def test_null_handles(lib):
     assert lib.pm_step(None, 0.1, 0.2) == PM_EINVAL
     assert lib.lens_project(None, 0.1, 0.2, None) == PM_EINVAL
     assert lib.pm_vjp_cosmo_read(None, None) == PM_EINVAL
+    assert lib.pm_checkpoint_bytes(None) == 0
+    assert lib.pm_checkpoint_save(None, None) == PM_EINVAL
+    assert lib.pm_checkpoint_load(None, None, 0.5) == PM_EINVAL
     assert lib.pm_init_ic_jvp(None, None, 0.0, 0.0) == PM_EINVAL
     assert lib.pm_set_tangent(None, None, None, 0.0) == PM_EINVAL
     assert lib.pm_get_tangent(None, None, None, None) == PM_EINVAL

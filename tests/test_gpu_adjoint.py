@@ -75,22 +75,22 @@ def test_gradient_configuration_pm_directional_derivative():
         u = torch.tensor(np.random.default_rng(7).standard_normal((3, wl.n_particles)),
                          dtype=dtype, device="cuda")
         _, states = forward_with_checkpoints(sim, noise, a)
-        xf = states[-1][0].clone()
+        xf = sim.get_state()[0]
         x_bar = u.clone()
         p_bar = torch.zeros_like(u)
         cb = np.zeros(2)
         for i in range(n - 1, -1, -1):
-            sim.set_state(*states[i + 1], a[i + 1])
+            sim.restore(states[i + 1], a[i + 1])
             sim.step_vjp(a[i], a[i + 1], a[i + 2] if i + 1 < n else -1.0, x_bar, p_bar, cb)
         sim.init_ic(noise, a[0])
-        sim.set_state(*states[0], a[0])
+        sim.restore(states[0], a[0])
         g = sim.init_ic_vjp(a[1], x_bar, p_bar, cb)
         v = torch.tensor(np.random.default_rng(8).standard_normal(g.shape), dtype=dtype, device="cuda")
         eps = 1e-7
         outs = []
         for sgn in (1.0, -1.0):
-            _, st = forward_with_checkpoints(sim, noise + sgn * eps * v, a)
-            dx = st[-1][0] - xf
+            forward_with_checkpoints(sim, noise + sgn * eps * v, a)
+            dx = sim.get_state()[0] - xf
             dx = torch.remainder(dx + 0.5 * wl.box, wl.box) - 0.5 * wl.box
             outs.append(float((u * dx).sum()))
         sim.sync()
@@ -249,3 +249,29 @@ def test_device_cosmology_accumulator_matches_host_reads():
     log(f"cosmology cotangent: host reads {res[0]}, device accumulator {res[1]}")
     assert np.all(res[0] != 0)
     np.testing.assert_allclose(res[1], res[0], rtol=1e-13)
+
+
+def test_checkpoint_restores_the_state_bit_for_bit():
+    """A checkpoint in the library's particle order, restored later, gives the
+    same state, force and next step as the state it was saved from."""
+    from tests.gpu_util import new_sim
+    wl = W.Workload("ckpt", 32, 64, 64.0, 0.4, 1.0, 3, 16, 3.0, (1.0,), seed=13)
+    a = wl.a_grid()
+    with new_sim(wl, torch.float32) as sim:
+        sim.init_ic(torch.tensor(W.white_noise(32, 13), device="cuda"), a[0])
+        sim.step(a[0], a[1])
+        ck = sim.checkpoint()
+        x1, p1 = sim.get_state()
+        f1 = sim.get_force()[2]
+        sim.step(a[1], a[2])
+        x2, p2 = sim.get_state()
+        sim.restore(ck, a[1])                    # back from a later state
+        xr, pr = sim.get_state()
+        fr = sim.get_force()[2]
+        sim.step(a[1], a[2])
+        x2r, p2r = sim.get_state()
+        with pytest.raises(ValueError):
+            sim.restore(ck[:-1], a[1])
+        sim.sync()
+    assert torch.equal(xr, x1) and torch.equal(pr, p1) and torch.equal(fr, f1)
+    assert torch.equal(x2r, x2) and torch.equal(p2r, p2)
