@@ -114,7 +114,7 @@ def test_sigma8_normalisation_independent_quadrature(cosmo):
     assert abs(s8 - cosmo.sigma8) < 1e-6
 
 
-def test_survey_distance_values(cosmo):
+def test_source_plane_distances(cosmo):
     """chi(z) at the source planes of the workloads (independent check of
     the order of magnitude, from the quadrature over z)."""
     chis = [cosmo.chi_of_z(z) for z in (0.5, 1.0, 1.5, 2.0)]
