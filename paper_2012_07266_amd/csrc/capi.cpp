@@ -280,6 +280,8 @@ template <class T> struct Sim final : SimBase {
     double pgd_alpha0 = 0, pgd_mu = 0;
     T* pgd_g = nullptr;            // [3 (Nm/2)^2 + 1] filtered Green's function
     T* pgd_s = nullptr;            // [3][Np^3] filtered force at the particles
+    T* pgd_m = nullptr;            // [Nm^3] + Nyquist plane: the filtered force's
+    T* pgd_nyq = nullptr;          // first component (the others use mesh 1, 2)
     uint32_t* pgd_bits = nullptr;  // max |pgd_s| (float bits)
     // forward-mode tangent of (x, p, f) along (noise, Omega_m, sigma_8), in
     // tile order and Mpc/h, allocated on first use: x_dot and p_dot (each
@@ -298,6 +300,8 @@ template <class T> struct Sim final : SimBase {
         if (pgd_g) (void)hipFree(pgd_g);
         if (pgd_s) (void)hipFree(pgd_s);
         if (pgd_bits) (void)hipFree(pgd_bits);
+        if (pgd_m) (void)hipFree(pgd_m);
+        if (pgd_nyq) (void)hipFree(pgd_nyq);
     }
 
     template <class U> U* at(size_t off) { return reinterpret_cast<U*>(arena + off); }
@@ -654,14 +658,19 @@ template <class T> struct Sim final : SimBase {
         const int h = P.nm / 2;
         const size_t ng = 3 * (size_t)h * h + 1;
         if (!pgd_g) {
+            const size_t nm = (size_t)P.nm;
             if (hipMalloc(&pgd_g, ng * sizeof(T)) != hipSuccess ||
                 hipMalloc(&pgd_s, 3 * n * sizeof(T)) != hipSuccess ||
-                hipMalloc(&pgd_bits, 256) != hipSuccess) {
+                hipMalloc(&pgd_bits, 256) != hipSuccess ||
+                hipMalloc(&pgd_m, nm * nm * nm * sizeof(T)) != hipSuccess ||
+                hipMalloc(&pgd_nyq, nm * nm * 2 * sizeof(T)) != hipSuccess) {
                 (void)hipGetLastError();
                 if (pgd_g) (void)hipFree(pgd_g);
                 if (pgd_s) (void)hipFree(pgd_s);
                 if (pgd_bits) (void)hipFree(pgd_bits);
-                pgd_g = pgd_s = nullptr;
+                if (pgd_m) (void)hipFree(pgd_m);
+                if (pgd_nyq) (void)hipFree(pgd_nyq);
+                pgd_g = pgd_s = pgd_m = pgd_nyq = nullptr;
                 pgd_bits = nullptr;
                 return PM_ENOMEM;
             }
@@ -689,19 +698,65 @@ template <class T> struct Sim final : SimBase {
     // (cells) and max |pgd_s| into pgd_bits; the lens adds alpha0 a^mu times
     // it to every image.  Uses the meshes (the force meshes are no longer
     // valid).
+    //
+    // The density's spectrum after the axis-2 and axis-1 passes stays in
+    // mesh 0 (and its Nyquist plane): the force of the same positions starts
+    // from it (force_from_spectrum), so a run pays for one paint and one
+    // forward transform per step.  The filtered force's components go to
+    // pgd_m, mesh 1 and mesh 2.
     void pgd_shift(double a) {
-        paint();
-        fft_forward_grad(P.nm, pgd_g, tw_nm, tw_hm, twp_nm);
+        const int nm = P.nm;
+        paint(true);
+        { ProfScope ps(prof, "fft_r2c_axis2");
+          fft_r2c_rows<T>(nm, mesh[0], nyq[0], tw_hm, twp_nm, st, paint_halo_merge<T>(geo, halo)); }
+        { ProfScope ps(prof, "fft_c2c_axis1_fwd");
+          fft_c2c_axis1<T>(nm, 1, reinterpret_cast<cx<T>*>(mesh[0]), nyq[0], tw_nm, st); }
+        cx<T>* pm_ = reinterpret_cast<cx<T>*>(pgd_m);
+        cx<T>* pn_ = reinterpret_cast<cx<T>*>(pgd_nyq);
+        PtrTriple om{{pgd_m, mesh[1], mesh[2]}}, on{{pgd_nyq, nyq[1], nyq[2]}};
+        { ProfScope ps(prof, "fft_grad_axis0");
+          fft_grad_axis0<T>(nm, reinterpret_cast<cx<T>*>(mesh[0]), nyq[0], om, on, tw_nm, pgd_g,
+                            T(0), st); }
+        { ProfScope ps(prof, "fft_c2c_axis1_inv"); fft_c2c_axis1<T>(nm, -1, pm_, pn_, tw_nm, st); }
+        { ProfScope ps(prof, "fft_c2c_axis1_dual");
+          fft_c2c_axis1_dual<T>(nm, reinterpret_cast<cx<T>*>(mesh[1]), nyq[1],
+                                reinterpret_cast<cx<T>*>(mesh[2]), nyq[2], tw_nm, st); }
+        T* comp[3] = {pgd_m, mesh[1], mesh[2]};
+        const cx<T>* cn[3] = {pn_, nyq[1], nyq[2]};
+        for (int j = 0; j < 3; ++j) {
+            ProfScope ps(prof, "fft_c2r_axis2");
+            fft_c2r_rows<T>(nm, comp[j], cn[j], tw_hm, twp_nm, st, j == 2);
+        }
         Parts<T> q = cur;
         q.acc = pgd_s;
         { ProfScope ps(prof, "pgd_readout");
-          launch_readout<T>(q, sb, geo, mesh[0], mesh[1], mesh[2], T(0), 0, status, st); }
+          launch_readout<T>(q, sb, geo, pgd_m, mesh[1], mesh[2], T(0), 0, status, st); }
         (void)a;
         Parts<T> m = cur;
         m.mom = pgd_s;
         launch_fill_u32(pgd_bits, 0u, 1, st);
         launch_drift_momentum_max<T>(m, geo.npart, T(0), pgd_bits, st);
         meshes_valid = false;
+    }
+
+    // The force meshes from the spectrum that pgd_shift left in mesh 0: the
+    // passes of fft_forward_grad after the axis-2 and axis-1 forward passes.
+    void force_from_spectrum() {
+        const int n = P.nm;
+        const T gscale = (T)(1.0 / (2.0 * PI * (double)n * (double)n));
+        PtrTriple om{{mesh[0], mesh[1], mesh[2]}}, on{{nyq[0], nyq[1], nyq[2]}};
+        { ProfScope ps(prof, "fft_grad_axis0");
+          fft_grad_axis0<T>(n, reinterpret_cast<cx<T>*>(mesh[0]), nyq[0], om, on, tw_nm, nullptr,
+                            gscale, st); }
+        { ProfScope ps(prof, "fft_c2c_axis1_inv");
+          fft_c2c_axis1<T>(n, -1, reinterpret_cast<cx<T>*>(mesh[0]), nyq[0], tw_nm, st); }
+        { ProfScope ps(prof, "fft_c2c_axis1_dual");
+          fft_c2c_axis1_dual<T>(n, reinterpret_cast<cx<T>*>(mesh[1]), nyq[1],
+                                reinterpret_cast<cx<T>*>(mesh[2]), nyq[2], tw_nm, st); }
+        for (int j = 0; j < 3; ++j) {
+            ProfScope ps(prof, "fft_c2r_axis2");
+            fft_c2r_rows<T>(n, mesh[j], nyq[j], tw_hm, twp_nm, st, j == 2);
+        }
     }
 
     // Born projection of the shell (chi(a1), chi(a0)] of the current,
@@ -784,11 +839,13 @@ template <class T> struct Sim final : SimBase {
                 std::swap(cur.mom, alt.mom);
                 std::swap(cur.id, alt.id);
             }
-            if (pgd) pgd_shift(a1);  // before the force's paint: it uses the meshes
-            paint(true);
+            // with PGD the shift's paint and forward passes are the force's
+            if (pgd) pgd_shift(a1);
+            else paint(true);
             int rc = project_shell(a0, a1, kap, T(0));  // mom is the drift momentum here
             if (rc) return rc;
-            fft_forward_grad(P.nm, nullptr, tw_nm, tw_hm, twp_nm, paint_halo_merge<T>(geo, halo));
+            if (pgd) force_from_spectrum();
+            else fft_forward_grad(P.nm, nullptr, tw_nm, tw_hm, twp_nm, paint_halo_merge<T>(geo, halo));
             const T k2 = (T)cosmo.kick(ah, a1, a1);
             ReadoutNext<T> nx;
             if (i + 1 < nsteps) {
