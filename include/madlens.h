@@ -174,11 +174,15 @@ int pm_set_interpolation(pm_sim* sim, int32_t on);
  * the CIC readout at x of the force of x's own CIC density with that
  * filter; the run itself continues from the uncorrected state.  With
  * sub-evolution on as well, the corrected images are then moved.  Each
- * corrected projection costs one more paint, force transform and readout.
- * k_l, k_s in h/Mpc; alpha0 dimensionless.  lens_project_vjp refuses the
- * mode (PM_EINVAL).  on: 0 or 1.  Errors: PM_EINVAL (NULL sim, non-finite
- * parameter, k_l < 0 or k_s <= 0 with on = 1), PM_ENOMEM (the filter table
- * and the displacement buffer are allocated on first use). */
+ * corrected projection costs the filtered force's axis-0, axis-1 and c2r
+ * passes and one more readout: in pm_run the shift and the force share one
+ * paint and the forward passes along axes 2 and 1 (lens_project after
+ * pm_step paints and transforms once more).  k_l, k_s in h/Mpc; alpha0
+ * dimensionless.  lens_project_vjp and lens_project_jvp refuse the mode
+ * (PM_EINVAL).  on: 0 or 1.  Errors: PM_EINVAL (NULL sim, non-finite
+ * parameter, k_l < 0 or k_s <= 0 with on = 1), PM_ENOMEM (the filter table,
+ * the displacement buffer and one spare mesh [Nm^3] are allocated on first
+ * use; none is counted by pm_footprint). */
 int pm_set_pgd(pm_sim* sim, int32_t on, double alpha0, double mu, double k_l, double k_s);
 
 /* Replica rotation (the package-design section: the box is rotated before it
