@@ -12,8 +12,10 @@ from tests.gpu_util import cosmo_of, log, new_sim, rel_rms, to_np
 pytestmark = pytest.mark.gpu
 
 DTYPES = [torch.float64, torch.float32]
-# cell sizes 1.25, 2 and 0.5: node positions k * cell are exact in float32
-SHAPES = [(16, 32, 40.0), (32, 32, 64.0), (128, 256, 128.0)]
+# cell sizes 2, 1.25, 2 and 0.5: node positions k * cell are exact in
+# float32.  16^3/16^3 is the smallest mesh: one tile, its own neighbour on
+# every side.
+SHAPES = [(16, 16, 32.0), (16, 32, 40.0), (32, 32, 64.0), (128, 256, 128.0)]
 
 
 def _tol(dtype, f64, f32):
@@ -78,18 +80,19 @@ def test_degenerate_density_force_readout(dtype, shape, kind):
     assert e_acc <= _tol(dtype, 1e-12, 1e-4)
 
 
+@pytest.mark.parametrize("shape", [(16, 16, 32.0), (32, 32, 64.0)], ids=lambda s: f"{s[0]}p{s[1]}m")
 @pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
-def test_step_from_node_field(dtype):
+def test_step_from_node_field(dtype, shape):
     """One KDK step from particles that all sit on mesh nodes (their CIC
     weights are 0 and 1, and a step's first readout is at those nodes)."""
     from oracle import pm
-    np_side, nm, box = 32, 32, 64.0
+    np_side, nm, box = shape
     wl = _wl(np_side, nm, box)
     c = cosmo_of(wl)
     x = _field("nodes", np_side, nm, box, seed=63)
     p = W.random_momenta(np_side ** 3, 0.05, seed=64)
     a0, a1 = 0.5, 0.55
-    log(f"edge step nodes {dtype}")
+    log(f"edge step nodes {shape} {dtype}")
     with new_sim(wl, dtype) as sim:
         sim.set_state(torch.from_numpy(x), torch.from_numpy(p), a0)
         sim.step(a0, a1)
@@ -99,7 +102,7 @@ def test_step_from_node_field(dtype):
     xo, po, _ = pm.kdk_step(x, p, f0, a0, a1, c, np_side, nm, box)
     d = np.mod(xg - xo + 0.5 * box, box) - 0.5 * box
     err = np.max(np.abs(d)) / (box / nm)
-    log(f"edge step nodes {dtype}: pos max {err:.2e} cells, mom rel-rms {rel_rms(pg, po):.2e}")
+    log(f"edge step nodes {shape} {dtype}: pos max {err:.2e} cells, mom rel-rms {rel_rms(pg, po):.2e}")
     assert err <= _tol(dtype, 1e-10, 1e-4)
     assert rel_rms(pg, po) <= _tol(dtype, 1e-10, 1e-4)
 
