@@ -138,3 +138,78 @@ def test_empty_lens_shell(dtype):
     e = rel_rms(kg, ko)
     log(f"edge empty shell {dtype}: kappa rel-rms {e:.2e}")
     assert e <= _tol(dtype, 1e-10, 1e-5)
+
+
+def _exact_grid(v, cell):
+    """v rounded to a multiple of cell / 64 (for the box and cell below such
+    values, their sums with the box and their quotients by the cell are
+    exact in float32)."""
+    return np.round(v / cell * 64.0) * (cell / 64.0)
+
+
+@pytest.mark.timeout(900)
+def test_largest_mesh_replicated_configuration():
+    """The largest mesh (1024^3, 512^3 particles, float32) against the
+    benchmark-size path: a configuration repeated 2 x 2 x 2 in a box twice
+    as large has, node for node and particle for particle, the density, the
+    force and the step of one copy.  (The transform of the repeated field
+    lives on even modes, where the doubled box's Green's function equals
+    the original's.)  Positions and momenta sit on a 1/64-cell grid, so both
+    sides get bit-identical CIC weights and differ only in FFT rounding."""
+    L, np_s, nm_s = 205.0, 256, 512
+    cell = L / nm_s
+    n = np_s ** 3
+    x = _exact_grid(W.clustered_positions(np_s, nm_s, L, seed=66), cell)
+    x = np.mod(x, L)
+    p = _exact_grid(W.random_momenta(n, 1.0, seed=67), cell)
+    a0, a1 = 0.5, 0.52
+    log("edge replicated: 256^3/512^3 copy")
+    with new_sim(_wl(np_s, nm_s, L), torch.float32) as sim:
+        sim.set_state(torch.from_numpy(x.astype(np.float32)),
+                      torch.from_numpy(p.astype(np.float32)), a0)
+        rho_s, fm_s, acc_s = sim.get_force()
+        sim.step(a0, a1)
+        xs, ps = sim.get_state()
+        sim.sync()
+    x32, p32 = x.astype(np.float32), p.astype(np.float32)
+    xb = np.empty((3, 8 * n), dtype=np.float32)
+    for c in range(8):
+        off = np.array([(c >> 2) & 1, (c >> 1) & 1, c & 1], dtype=np.float32)[:, None] * L
+        xb[:, c * n:(c + 1) * n] = x32 + off
+    pb = np.tile(p32, (1, 8))
+    log("edge replicated: 512^3/1024^3 repeated")
+    with new_sim(_wl(2 * np_s, 2 * nm_s, 2 * L), torch.float32) as sim:
+        sim.set_state(torch.from_numpy(xb), torch.from_numpy(pb), a0)
+        del xb, pb
+        rho_b, fm_b, acc_b = sim.get_force()
+        fmax = float(fm_s.abs().max())
+        rho_same = True
+        e_f = 0.0
+        for c in range(8):
+            i, j, k = ((c >> 2) & 1) * nm_s, ((c >> 1) & 1) * nm_s, (c & 1) * nm_s
+            rho_same &= bool(torch.equal(rho_b[i:i + nm_s, j:j + nm_s, k:k + nm_s], rho_s))
+            d = fm_b[:, i:i + nm_s, j:j + nm_s, k:k + nm_s] - fm_s
+            e_f = max(e_f, float(d.abs().max()) / fmax)
+            del d
+        del rho_b, fm_b
+        e_acc = max(float((acc_b[:, c * n:(c + 1) * n] - acc_s).abs().max())
+                    for c in range(8)) / fmax
+        sim.step(a0, a1)
+        xb_g, pb_g = sim.get_state()
+        sim.sync()
+        e_x = 0.0
+        e_x_rms = 0.0
+        for c in range(8):
+            d = torch.remainder(xb_g[:, c * n:(c + 1) * n] - xs + 0.5 * L, L) - 0.5 * L
+            e_x = max(e_x, float(d.abs().max()) / cell)
+            e_x_rms = max(e_x_rms, float(d.double().pow(2).mean().sqrt()) / cell)
+        ps64 = ps.double()
+        e_p = max(float((pb_g[:, c * n:(c + 1) * n].double() - ps64).pow(2).mean().sqrt()
+                        / ps64.pow(2).mean().sqrt()) for c in range(8))
+    log(f"edge replicated: rho bitwise {rho_same}, force max {e_f:.2e}, acc max {e_acc:.2e}, "
+        f"step pos max {e_x:.2e} rms {e_x_rms:.2e} cells, mom rel-rms {e_p:.2e}")
+    assert rho_same
+    assert e_f <= 2e-5
+    assert e_acc <= 2e-5
+    assert e_x_rms <= 1e-4 and e_x <= 1e-3
+    assert e_p <= 1e-4

@@ -66,6 +66,28 @@ def test_force_zero_mean_and_nyquist_plane():
     assert np.max(np.abs(f[1])) > 1e-2
 
 
+def test_repeated_configuration_has_the_force_of_one_copy():
+    """A configuration repeated 2 x 2 x 2 in a box twice as large (same cell
+    size) has, node for node and particle for particle, the density and
+    force of one copy: its transform lives on even modes, where the doubled
+    box's wave numbers equal the original's (and its Nyquist planes are the
+    original's)."""
+    L, np_s, nm_s = 40.0, 16, 32
+    n = np_s ** 3
+    x = W.clustered_positions(np_s, nm_s, L, seed=66)
+    offs = [np.array([(c >> 2) & 1, (c >> 1) & 1, c & 1])[:, None] * L for c in range(8)]
+    xb = np.concatenate([x + o for o in offs], axis=1)
+    f = pm.force_mesh(pm.density(x, np_s, nm_s, L), L)
+    fb = pm.force_mesh(pm.density(xb, 2 * np_s, 2 * nm_s, 2 * L), 2 * L)
+    for c in range(8):
+        i, j, k = ((c >> 2) & 1) * nm_s, ((c >> 1) & 1) * nm_s, (c & 1) * nm_s
+        assert np.max(np.abs(fb[:, i:i + nm_s, j:j + nm_s, k:k + nm_s] - f)) <= 1e-12 * np.max(np.abs(f))
+    a = pm.particle_force(x, np_s, nm_s, L)
+    ab = pm.particle_force(xb, 2 * np_s, 2 * nm_s, 2 * L)
+    for c in range(8):
+        assert np.max(np.abs(ab[:, c * n:(c + 1) * n] - a)) <= 1e-12 * np.max(np.abs(a))
+
+
 def test_paint_mass_conservation():
     x = W.random_positions(5000, 37.0, seed=11)
     rho = pm.density(x, 17, 12, 37.0)  # 17^3 = 4913 < 5000: mass per particle
