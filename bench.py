@@ -83,11 +83,12 @@ KERNEL_SYMBOL = {
 COPY_BYTES = 1 << 30  # the calibration copy moves 1 GiB in and 1 GiB out
 
 
-def traffic_from_pmc(fetch_csv, write_csv):
+def traffic_from_pmc(fetch_csv, write_csv, workload):
     """Write profiles/traffic.json from two rocprofv3 --pmc runs of
     `bench.py --calibrate-copy` (FETCH_SIZE, then WRITE_SIZE, in KiB per
     dispatch).  Each counter is scaled by what it reads for the 1 GiB
-    calibration copy, whose true traffic is known."""
+    calibration copy, whose true traffic is known.  `workload` names the
+    workload the counted runs stepped."""
     import csv
     import hashlib
 
@@ -115,7 +116,7 @@ def traffic_from_pmc(fetch_csv, write_csv):
     sw = COPY_BYTES / cw if cw else 1.0
     out = {"_about": "HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled "
                      "by the counters of a 1 GiB device copy",
-           "_scale": {"fetch": sf, "write": sw}}
+           "_scale": {"fetch": sf, "write": sw}, "_workload": workload}
     for cls, (sub, src) in KERNEL_SYMBOL.items():
         f, w = find(fetch, sub), find(write, sub)
         if f is None or w is None:
@@ -128,14 +129,17 @@ def traffic_from_pmc(fetch_csv, write_csv):
     print(json.dumps(out))
 
 
-def load_traffic(kernel):
-    """HBM traffic per launch measured with rocprofv3 counters, if the kernel
-    source has not changed since (hash recorded with the counters)."""
+def load_traffic(kernel, workload):
+    """HBM traffic per launch measured with rocprofv3 counters, if they were
+    taken on this workload and the kernel source has not changed since (hash
+    recorded with the counters)."""
     path = TRAFFIC_JSON
     if not os.path.exists(path):
         return None
     try:
         rec = json.load(open(path))
+        if rec.get("_workload") != workload:
+            return None
         ent = rec.get(kernel)
         if not ent:
             return None
@@ -366,19 +370,19 @@ def main():
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/traffic.json from two rocprofv3 --pmc CSVs and exit")
     args = ap.parse_args()
+    import workloads as W
+    wl = {"cfg1": W.CFG1.with_(name="plain_fp32_32p_32m"), "cfg2": W.CFG2,
+          "cfg3": W.CFG3, "cfg5": W.CFG5}[args.workload]
     if args.traffic_from:
-        traffic_from_pmc(*args.traffic_from)
+        traffic_from_pmc(*args.traffic_from, wl.name)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
 
     import torch
-    import workloads as W
     from paper_2012_07266_amd import Simulation
 
-    wl = {"cfg1": W.CFG1.with_(name="plain_fp32_32p_32m"), "cfg2": W.CFG2,
-          "cfg3": W.CFG3, "cfg5": W.CFG5}[args.workload]
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
     stream = torch.cuda.current_stream()
@@ -459,7 +463,7 @@ def main():
         out["roofline"] = {"kernel": dom, "bound": "hbm", "achieved": d["alg_gbs"],
                            "peak": HBM_PEAK_GBS, "unit": "GB/s",
                            "frac": d["alg_gbs"] / HBM_PEAK_GBS if d["alg_gbs"] else None,
-                           "traffic": load_traffic(dom)}
+                           "traffic": load_traffic(dom, wl.name)}
         out["hbm_effective_gbs_all_kernels"] = total_bytes / (total_ms * 1e-3) / 1e9
         out["kernels"] = kern
     # the same schedule with sub-evolution projection (pm_set_interpolation)
