@@ -293,6 +293,39 @@ def serving_bench(n_requests):
     return res
 
 
+def large_mix_bench(n_background=40, rate=20.0):
+    """The 512^3/1024^3 run (10 x 4096^2 maps, 40 steps) submitted at t = 0,
+    with a Poisson stream of small requests behind it at `rate` per second:
+    64^3 particles, 128^3 mesh, box 64 Mpc/h, 10-30 steps from a = 0.1,
+    Om ~ U[0.25, 0.35], s8 ~ U[0.7, 0.9], one 512^2 map over 2 deg at z_s = 1.
+    Served (up to 8 concurrent) against plain (one at a time, FIFO)."""
+    import workloads as W
+    from paper_2012_07266_amd.serve import poisson_arrivals, run_stream
+    gen = np.random.Generator(np.random.Philox(key=8))
+    small = []
+    for i in range(n_background):
+        nsteps = int(gen.integers(10, 31))
+        om, s8 = float(gen.uniform(0.25, 0.35)), float(gen.uniform(0.7, 0.9))
+        small.append(W.Workload(f"bg{i}", 64, 128, 64.0, 0.1, 1.0, nsteps, 512, 2.0, (1.0,),
+                                omega_m=om, sigma8=s8, seed=2000 + i))
+    reqs = [W.CFG5] + small
+    arr = np.concatenate([[0.0], poisson_arrivals(n_background, rate, seed=8)])
+    budget = 64 << 30
+    res = {"workload": (f"{W.CFG5.name} (512^3 particles, 1024^3 mesh, 40 steps, 10 x 4096^2 "
+                        f"maps) at t = 0, then {n_background} requests of 64^3/128^3, 10-30 "
+                        f"steps, 1 x 512^2 map, Poisson at {rate:g}/s"),
+           "hbm_budget_gb": budget / 2 ** 30, "served_max_active": 8}
+    for form, act in (("served", 8), ("plain", 1)):
+        r, _ = run_stream(reqs, arr, budget, act)
+        lat = np.array(r.latencies_ms)
+        res[form] = {"large_latency_ms": float(lat[0]),
+                     "background_p50_ms": float(np.percentile(lat[1:], 50)),
+                     "background_p99_ms": float(np.percentile(lat[1:], 99)),
+                     "particle_steps_per_s": r.throughput, "makespan_s": r.makespan_s,
+                     "peak_running": r.peak_running}
+    return res
+
+
 # alpha0, mu, k_l, k_s [h/Mpc] for timing only: a correction of about 1% of
 # the (filtered) force, shifts of order a cell at the 512^3 mesh.  The cost
 # of the lens grows with the largest shift, which widens its frustum margin.
@@ -365,6 +398,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the serving streams (p50/p99 latency, served vs plain)")
     ap.add_argument("--serve-requests", type=int, default=100)
+    ap.add_argument("--no-large-mix", action="store_true",
+                    help="skip serving the 512^3/1024^3 run with a stream of small requests")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a 1 GiB device copy (counter calibration for --pmc runs)")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -476,6 +511,8 @@ def main():
         out["gradient"] = gradient_bench()
     if not args.no_serving:
         out["serving"] = serving_bench(args.serve_requests)
+    if not args.no_large_mix:
+        out["serving_large_mix"] = large_mix_bench()
     out["paper_context"] = ("MADLens on 32 Haswell cores: ~6.2e6 particle-steps/s "
                             "(256^3, 11 steps, 30 s incl. projection; different workload)")
     if not args.no_cpu_baseline:

@@ -13,7 +13,7 @@ from __future__ import annotations
 
 import ctypes
 import time
-from dataclasses import dataclass
+from dataclasses import dataclass, field
 from typing import List, Sequence
 
 import numpy as np
@@ -95,6 +95,7 @@ class StreamResult:
     n: int
     peak_running: int
     peak_bytes: int
+    latencies_ms: List[float] = field(default_factory=list)  # per request, in order
 
     def as_dict(self) -> dict:
         return dict(self.__dict__)
@@ -133,7 +134,7 @@ def run_stream(requests: Sequence, arrivals: Sequence[float], hbm_budget: int,
     lat = np.array(lat) * 1e3
     res = StreamResult(float(np.percentile(lat, 50)), float(np.percentile(lat, 99)),
                        float(lat.mean()), work / (last - first), last - first, len(requests),
-                       int(st["peak_running"]), int(st["peak_bytes"]))
+                       int(st["peak_running"]), int(st["peak_bytes"]), lat.tolist())
     return res, (maps if keep_maps else None)
 
 
