@@ -351,6 +351,21 @@ struct ViewDesc {
     int n_wg;
 };
 
+// Workgroups are handed to the 8 XCDs round-robin.  When a workgroup's row
+// segment is narrower than a 128-byte line (8 float pencils, meshes above
+// 512), workgroups g and g + 1 share every line they touch; renumber so that
+// each XCD walks a contiguous run of g and such pairs meet in one L2.
+// A bijection of [0, nb) whenever nb % 8 == 0; the identity otherwise.
+template <class T, int W>
+__device__ __forceinline__ int view_wg(int b, int nb) {
+    if constexpr (W * sizeof(cx<T>) >= 128) {
+        return b;
+    } else {
+        if (nb % 8) return b;
+        return (b % 8) * (nb / 8) + b / 8;
+    }
+}
+
 template <class T, int N, int W>
 __device__ __forceinline__ long view_offset(const ViewDesc& v, int g, int w, int n) {
     if (v.contig) return ((long)g * W + w) * N + n;
@@ -417,7 +432,7 @@ __global__ __launch_bounds__(NT) void k_c2c_view(ViewDesc va, ViewDesc vb, const
     __shared__ cx<T> buf[N * (W + 1)];
     __shared__ cx<T> tws[N];
     const int tid = threadIdx.x;
-    int g = blockIdx.x;
+    int g = view_wg<T, W>(blockIdx.x, gridDim.x);
     const ViewDesc& v = g < va.n_wg ? va : vb;
     if (g >= va.n_wg) g -= va.n_wg;
     TwFetch<T, N> twr;
@@ -480,7 +495,7 @@ __global__ __launch_bounds__(NT) void k_c2c_view_dual(ViewDesc va, ViewDesc vb, 
     __shared__ cx<T> tws[N];
     constexpr int LD = W + 1;
     const int tid = threadIdx.x;
-    int g = blockIdx.x;
+    int g = view_wg<T, W>(blockIdx.x, gridDim.x);
     const bool is_a = g < va.n_wg;
     const ViewDesc& v = is_a ? va : vb;
     cx<T>* dst2 = is_a ? dst2a : dst2b;
@@ -579,7 +594,7 @@ __global__ __launch_bounds__(NTG, (NTG == 512 ? 4 : 1)) void k_grad_x0(ViewDesc 
     constexpr int LD = W + 1;
     constexpr int HN = N / 2;
     const int tid = threadIdx.x;
-    int g = blockIdx.x;
+    int g = view_wg<T, W>(blockIdx.x, gridDim.x);
     const bool is_a = g < va.n_wg;
     const ViewDesc& v = is_a ? va : vb;
     const PtrTriple& out = is_a ? outa : outb;
@@ -743,7 +758,7 @@ __global__ __launch_bounds__(NT) void k_div_x0(ViewDesc va, ViewDesc vb, PtrTrip
     constexpr int HN = N / 2;
     constexpr int IT = (W * N + NT - 1) / NT;
     const int tid = threadIdx.x;
-    int g = blockIdx.x;
+    int g = view_wg<T, W>(blockIdx.x, gridDim.x);
     const bool is_a = g < va.n_wg;
     ViewDesc v = is_a ? va : vb;
     const PtrTriple& in = is_a ? ina : inb;
