@@ -351,14 +351,17 @@ struct ViewDesc {
     int n_wg;
 };
 
-// Workgroups are handed to the 8 XCDs round-robin.  When a workgroup's row
-// segment is narrower than a 128-byte line (8 float pencils, meshes above
-// 512), workgroups g and g + 1 share every line they touch; renumber so that
-// each XCD walks a contiguous run of g and such pairs meet in one L2.
+// Workgroups are handed to the 8 XCDs round-robin.  Renumber them so that
+// each XCD walks a contiguous run of g.  When a workgroup's row segment is
+// narrower than a 128-byte line (8 float pencils, meshes above 512),
+// workgroups g and g + 1 share every line they touch, and such pairs then
+// meet in one L2.  With full-line segments the axis-1 passes still gain
+// (neighbouring pencils of one plane stay on one XCD) and the fused axis-0
+// passes do not, so those keep the hardware order (ALL = false).
 // A bijection of [0, nb) whenever nb % 8 == 0; the identity otherwise.
-template <class T, int W>
+template <class T, int W, bool ALL>
 __device__ __forceinline__ int view_wg(int b, int nb) {
-    if constexpr (W * sizeof(cx<T>) >= 128) {
+    if constexpr (!ALL && W * sizeof(cx<T>) >= 128) {
         return b;
     } else {
         if (nb % 8) return b;
@@ -432,7 +435,7 @@ __global__ __launch_bounds__(NT) void k_c2c_view(ViewDesc va, ViewDesc vb, const
     __shared__ cx<T> buf[N * (W + 1)];
     __shared__ cx<T> tws[N];
     const int tid = threadIdx.x;
-    int g = view_wg<T, W>(blockIdx.x, gridDim.x);
+    int g = view_wg<T, W, true>(blockIdx.x, gridDim.x);
     const ViewDesc& v = g < va.n_wg ? va : vb;
     if (g >= va.n_wg) g -= va.n_wg;
     TwFetch<T, N> twr;
@@ -495,7 +498,7 @@ __global__ __launch_bounds__(NT) void k_c2c_view_dual(ViewDesc va, ViewDesc vb, 
     __shared__ cx<T> tws[N];
     constexpr int LD = W + 1;
     const int tid = threadIdx.x;
-    int g = view_wg<T, W>(blockIdx.x, gridDim.x);
+    int g = view_wg<T, W, true>(blockIdx.x, gridDim.x);
     const bool is_a = g < va.n_wg;
     const ViewDesc& v = is_a ? va : vb;
     cx<T>* dst2 = is_a ? dst2a : dst2b;
@@ -594,7 +597,7 @@ __global__ __launch_bounds__(NTG, (NTG == 512 ? 4 : 1)) void k_grad_x0(ViewDesc 
     constexpr int LD = W + 1;
     constexpr int HN = N / 2;
     const int tid = threadIdx.x;
-    int g = view_wg<T, W>(blockIdx.x, gridDim.x);
+    int g = view_wg<T, W, false>(blockIdx.x, gridDim.x);
     const bool is_a = g < va.n_wg;
     const ViewDesc& v = is_a ? va : vb;
     const PtrTriple& out = is_a ? outa : outb;
@@ -758,7 +761,7 @@ __global__ __launch_bounds__(NT) void k_div_x0(ViewDesc va, ViewDesc vb, PtrTrip
     constexpr int HN = N / 2;
     constexpr int IT = (W * N + NT - 1) / NT;
     const int tid = threadIdx.x;
-    int g = view_wg<T, W>(blockIdx.x, gridDim.x);
+    int g = view_wg<T, W, false>(blockIdx.x, gridDim.x);
     const bool is_a = g < va.n_wg;
     ViewDesc v = is_a ? va : vb;
     const PtrTriple& in = is_a ? ina : inb;
