@@ -382,6 +382,13 @@ int lens_project_jvp(pm_sim* sim, double a0, double a1, void* kappa_dot);
  * the launch count since the last read, then resets the totals.  *n_out gets
  * the number of distinct names.  Any output array may be NULL. */
 int pm_profile(pm_sim* sim, int enable);
+/* Restricts the recording to launches of one kernel name (as pm_profile_read
+ * reports it, e.g. "readout_kick_drift_key"); NULL or "" records every
+ * launch again.  Each recorded launch adds two events to the stream, and
+ * between kernels they cost time of their own, so a run timed as a whole
+ * records only the kernel it reports.  The name is copied.  PM_EINVAL on a
+ * NULL sim. */
+int pm_profile_only(pm_sim* sim, const char* name);
 int pm_profile_read(pm_sim* sim, int max_kernels, char* names, double* ms_total, long* counts,
                     int* n_out);
 

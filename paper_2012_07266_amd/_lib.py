@@ -81,6 +81,7 @@ SIGNATURES = {
     "pm_step_jvp": (_I, [_P, _D, _D]),
     "lens_project_jvp": (_I, [_P, _D, _D, _P]),
     "pm_profile": (_I, [_P, _I]),
+    "pm_profile_only": (_I, [_P, ctypes.c_char_p]),
     "pm_profile_read": (_I, [_P, _I, ctypes.c_char_p, ctypes.POINTER(_D),
                              ctypes.POINTER(ctypes.c_long), ctypes.POINTER(_I)]),
     "pm_srv_create": (_I, [ctypes.c_size_t, ctypes.c_int32, ctypes.POINTER(_P)]),

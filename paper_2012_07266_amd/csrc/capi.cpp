@@ -140,6 +140,7 @@ struct Prof {
     std::vector<long> cnt;
     hipStream_t st = nullptr;
     int cur = -1;
+    std::string only;  // when set, only launches of this name are recorded
 
     int name_id(const char* n) {
         for (size_t i = 0; i < names.size(); ++i)
@@ -152,6 +153,7 @@ struct Prof {
     void begin(const char* n) {
         cur = -1;
         if (!on || used + 2 > pool.size()) return;
+        if (!only.empty() && only != n) return;
         cur = (int)recs.size();
         recs.push_back({name_id(n), pool[used], pool[used + 1]});
         used += 2;
@@ -1513,6 +1515,12 @@ int pm_background(const pm_sim* sim, double a, double out[3]) {
 int pm_profile(pm_sim* sim, int enable) {
     if (!sim) return PM_EINVAL;
     return sim->impl->prof.enable(enable != 0, sim->impl->stream());
+}
+
+int pm_profile_only(pm_sim* sim, const char* name) {
+    if (!sim) return PM_EINVAL;
+    sim->impl->prof.only = name ? name : "";
+    return PM_OK;
 }
 
 int pm_profile_read(pm_sim* sim, int max_kernels, char* names, double* ms_total, long* counts,

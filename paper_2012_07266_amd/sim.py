@@ -308,6 +308,11 @@ class Simulation:
     def profile(self, enable: bool):
         check(lib().pm_profile(self._h, 1 if enable else 0), "pm_profile")
 
+    def profile_only(self, name=None):
+        """Record only launches of kernel `name` (None: every launch)."""
+        check(lib().pm_profile_only(self._h, name.encode() if name else None),
+              "pm_profile_only")
+
     def profile_read(self):
         """{kernel name: (total ms, launches)} since the last read."""
         cap = 64

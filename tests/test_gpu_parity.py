@@ -282,3 +282,29 @@ def test_full_size_step_and_shell():
     e_k = rel_rms(klg, ko)
     log(f"full size shell: kappa rel-rms {e_k:.2e}")
     assert np.abs(ko).max() > 0 and e_k < 1e-4
+
+
+def test_profile_only_records_one_kernel():
+    """pm_profile_only limits the event pairs to one kernel name: a fused
+    5-step run records every kernel when unrestricted, and only the paint
+    (six launches: the initial force and one per step) when restricted to
+    it; the maps are the same either way."""
+    wl = W.Workload("prof", 16, 32, 40.0, 0.2, 1.0, 5, 64, 4.0, (1.0,), seed=9)
+    log("profile_only: 16^3/32^3, 5 steps")
+    noise = torch.from_numpy(W.white_noise(16, wl.seed))
+    a = wl.a_grid()
+    with new_sim(wl) as sim:
+        sim.profile(True)
+        k1 = sim.run(noise, a).clone()
+        every = sim.profile_read()
+        sim.profile_only("paint")
+        k2 = sim.run(noise, a)
+        only = sim.profile_read()
+        sim.profile(False)
+        sim.profile_only(None)
+        sim.sync()
+    assert len(every) > 3 and every["paint"][1] == 6
+    assert only.get("paint", (0.0, 0))[1] == 6
+    assert all(c == 0 for n, (_, c) in only.items() if n != "paint")
+    assert only["paint"][0] > 0.0
+    assert torch.equal(k1, k2)
