@@ -219,7 +219,7 @@ __device__ __forceinline__ void reg_chain(cx<T>* v, cx<T>* buf, const cx<T>* tw,
 // groups, which measured faster there; with 16 rows the hardware order
 // measured faster.  A bijection of [0, nb) whenever nb % 8 == 0.
 template <class T, int W>
-__device__ __forceinline__ int row_wg(int b, int nb) {
+__device__ __forceinline__ unsigned row_wg(unsigned b, unsigned nb) {
     if constexpr (sizeof(T) != 4 || W != 8) {
         return b;
     } else {
