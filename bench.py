@@ -208,8 +208,8 @@ def gradient_bench(reps=3):
     a = wl.a_grid()
     dev = torch.device("cuda", 0)
     sim = Simulation(wl.np_side, wl.nm_side, wl.box, wl.npix, wl.fov_deg, wl.z_src,
-                     dtype=torch.float32, omega_m=wl.omega_m, sigma8=wl.sigma8, h=wl.h,
-                     n_s=wl.n_s, omega_b=wl.omega_b, t_cmb=wl.t_cmb)
+                     dtype=torch.float32, tangent=True, omega_m=wl.omega_m, sigma8=wl.sigma8,
+                     h=wl.h, n_s=wl.n_s, omega_b=wl.omega_b, t_cmb=wl.t_cmb)
     sigma = 0.01
     target, _ = forward_with_checkpoints(
         sim, torch.from_numpy(W.white_noise(wl.np_side, 4)).to(dev, torch.float32), a)
@@ -431,8 +431,10 @@ def main():
     stream = torch.cuda.current_stream()
     noise = torch.from_numpy(W.white_noise(wl.np_side, wl.seed)).to(dev, torch.float32)
     a = wl.a_grid()
+    from paper_2012_07266_amd._lib import PM_MODE_PGD
     sim = Simulation(wl.np_side, wl.nm_side, wl.box, wl.npix, wl.fov_deg, wl.z_src,
-                     dtype=torch.float32, omega_m=wl.omega_m, sigma8=wl.sigma8, h=wl.h,
+                     dtype=torch.float32, modes=0 if args.no_interpolation else PM_MODE_PGD,
+                     omega_m=wl.omega_m, sigma8=wl.sigma8, h=wl.h,
                      n_s=wl.n_s, omega_b=wl.omega_b, t_cmb=wl.t_cmb)
     kappa = sim.new_maps()
 

@@ -68,7 +68,16 @@ typedef struct pm_params {
     double  sigma8;    /* rms linear fluctuation in 8 Mpc/h spheres at a = 1 */
     double  t_cmb;     /* CMB temperature, K                                 */
     int32_t dtype;     /* PM_F32 or PM_F64: precision of every kernel        */
+    uint32_t modes;    /* PM_MODE_* bits: optional passes whose buffers the
+                          arena must hold (0: forward and reverse only)     */
 } pm_params;
+
+/* Optional passes of a handle.  Their device buffers are part of the arena
+ * that pm_create allocates and pm_footprint counts; a call that needs a
+ * mode the handle was created without fails with PM_EINVAL. */
+#define PM_MODE_PGD     1u  /* pm_set_pgd: filter table, shift [3][Np^3] and
+                               one spare mesh [Nm^3] + Nyquist plane         */
+#define PM_MODE_TANGENT 2u  /* forward-mode tangents: 15 Np^3 values         */
 
 typedef struct lens_params {
     int32_t       npix;     /* map pixels per side                           */
@@ -81,7 +90,8 @@ typedef struct pm_sim pm_sim;
 
 /* Size rules: Nm and Np are multiples of 16 (Np >= 16), Nm / Np is 1 or 2,
  * Nm and Np have no prime factor other than 2 and 3 and are at most 1024;
- * 0 < Omega_m < 1; box > 0; 16 <= npix <= 8192.  Violations give PM_EINVAL. */
+ * 0 < Omega_m < 1; box > 0; 16 <= npix <= 8192; modes holds no bit other
+ * than the PM_MODE_* ones.  Violations give PM_EINVAL. */
 
 /* Bytes of device memory pm_create would allocate for these parameters; 0
  * when they are invalid.  Pure host function (used for admission by HBM
@@ -125,8 +135,9 @@ int pm_init_ic_seed(pm_sim* sim, uint64_t seed, double a0);
 int pm_noise(pm_sim* sim, uint64_t seed, void* noise_out);
 
 /* Reuse the arena for new physical parameters: cosmology, box, field of view
- * and source redshifts may change; Np, Nm, dtype, npix and nsrc must equal
- * those of pm_create.  Rebuilds and uploads the float64 tables and clears
+ * and source redshifts may change; Np, Nm, dtype, modes, npix and nsrc must
+ * equal those of pm_create.  Rebuilds and uploads the float64 tables (the
+ * PGD filter too, for the new box, when the correction is on) and clears
  * the state (pm_init_ic* must follow).  Waits for the stream.
  * Errors: PM_EINVAL (invalid or arena-changing parameters), PM_EDEVICE. */
 int pm_reconfigure(pm_sim* sim, const pm_params* p, const lens_params* l);
@@ -179,10 +190,10 @@ int pm_set_interpolation(pm_sim* sim, int32_t on);
  * paint and the forward passes along axes 2 and 1 (lens_project after
  * pm_step paints and transforms once more).  k_l, k_s in h/Mpc; alpha0
  * dimensionless.  lens_project_vjp and lens_project_jvp refuse the mode
- * (PM_EINVAL).  on: 0 or 1.  Errors: PM_EINVAL (NULL sim, non-finite
- * parameter, k_l < 0 or k_s <= 0 with on = 1), PM_ENOMEM (the filter table,
- * the displacement buffer and one spare mesh [Nm^3] are allocated on first
- * use; none is counted by pm_footprint). */
+ * (PM_EINVAL).  The filter table, the displacement buffer and the spare mesh
+ * are part of the arena of a handle created with PM_MODE_PGD.  on: 0 or 1.
+ * Errors: PM_EINVAL (NULL sim, handle without PM_MODE_PGD, non-finite
+ * parameter, k_l < 0 or k_s <= 0 with on = 1). */
 int pm_set_pgd(pm_sim* sim, int32_t on, double alpha0, double mu, double k_l, double k_s);
 
 /* Replica rotation (the package-design section: the box is rotated before it
@@ -317,8 +328,9 @@ int pm_vjp_cosmo_read(pm_sim* sim, double cosmo_bar[2]);
  * simulation, one step / shell at a time, without checkpoints.  The
  * tangent (x_dot, p_dot and the force tangent f_dot at the current state)
  * is held by the library in its own particle order, and travels with the
- * particles through each step's sort; it is allocated on first use (15
- * Np^3 values of dtype, not counted by pm_footprint).  pm_set_tangent and
+ * particles through each step's sort; its 15 Np^3 values of dtype are part
+ * of the arena of a handle created with PM_MODE_TANGENT (every call below
+ * fails with PM_EINVAL on a handle without it).  pm_set_tangent and
  * pm_get_tangent exchange it with device arrays [3][Np^3] of dtype in
  * lattice order and Mpc/h.  Omega_m derivatives of scalar factors are the
  * central differences (step 1e-5) of the reverse mode, with the same fixed
@@ -337,7 +349,7 @@ int pm_vjp_cosmo_read(pm_sim* sim, double cosmo_bar[2]);
  *   s_dot = S(noise_dot + (s8_dot / s8) noise) + Om_dot dS/dOm(noise)
  * (S the Zel'dovich displacement map at D = 1), f_dot the force tangent at
  * the initial positions, and Omega_m_dot for the steps and shells to come.
- * Errors: PM_EINVAL (NULL array, non-finite scalar), PM_ESTATE, PM_ENOMEM. */
+ * Errors: PM_EINVAL (NULL array, non-finite scalar), PM_ESTATE. */
 int pm_init_ic_jvp(pm_sim* sim, const void* noise_dot, double omega_m_dot, double sigma8_dot);
 
 /* pm_set_tangent: set the tangent of the current state to (x_dot, p_dot)
@@ -346,7 +358,7 @@ int pm_init_ic_jvp(pm_sim* sim, const void* noise_dot, double omega_m_dot, doubl
  * force meshes' gradient along x_dot read out at the particles, plus the
  * force of the tangent density (the cloud-in-cell paint differentiated
  * along x_dot) read out at the particles.
- * Errors: PM_EINVAL, PM_ESTATE (no state), PM_ENOMEM. */
+ * Errors: PM_EINVAL, PM_ESTATE (no state). */
 int pm_set_tangent(pm_sim* sim, const void* x_dot, const void* p_dot, double omega_m_dot);
 
 /* pm_get_tangent: copy the tangent out in lattice order (device [3][Np^3]

@@ -15,6 +15,7 @@ LIB_PATH = os.path.join(HERE, "libmadlens_amd.so")
 PM_OK, PM_EINVAL, PM_ENOMEM, PM_EDEVICE, PM_ESTATE, PM_ENONFINITE, PM_EAGAIN = \
     0, -1, -2, -3, -4, -5, -7
 PM_F32, PM_F64 = 0, 1
+PM_MODE_PGD, PM_MODE_TANGENT = 1, 2
 
 
 class PmParams(ctypes.Structure):
@@ -22,7 +23,8 @@ class PmParams(ctypes.Structure):
                 ("box", ctypes.c_double), ("omega_m", ctypes.c_double),
                 ("omega_b", ctypes.c_double), ("h", ctypes.c_double),
                 ("n_s", ctypes.c_double), ("sigma8", ctypes.c_double),
-                ("t_cmb", ctypes.c_double), ("dtype", ctypes.c_int32)]
+                ("t_cmb", ctypes.c_double), ("dtype", ctypes.c_int32),
+                ("modes", ctypes.c_uint32)]
 
 
 class LensParams(ctypes.Structure):

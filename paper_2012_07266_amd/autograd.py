@@ -99,15 +99,17 @@ class LensingModel:
     """kappa(noise, Omega_m, sigma_8) with gradients for all three inputs.
 
     One library handle is kept per (Omega_m, sigma_8); its device arena is
-    allocated once and reused by every forward and backward pass.
+    allocated once and reused by every forward and backward pass.  `tangent`
+    sizes the arenas for forward-mode tangents (`jvp`).
     """
 
     def __init__(self, np_side, nm_side, box, npix, fov_deg, z_src, a_grid,
-                 dtype=torch.float32, interpolation=False, **cosmo):
+                 dtype=torch.float32, interpolation=False, tangent=False, **cosmo):
         self.shape = (np_side, nm_side, box, npix, fov_deg, tuple(z_src))
         self.a_grid = [float(a) for a in a_grid]
         self.dtype = dtype
         self.interpolation = bool(interpolation)
+        self.tangent = bool(tangent)
         self.cosmo = dict(cosmo)
         self._sims: Dict[Tuple[float, float], Simulation] = {}
 
@@ -117,7 +119,8 @@ class LensingModel:
             np_side, nm_side, box, npix, fov, zs = self.shape
             self._sims[key] = Simulation(np_side, nm_side, box, npix, fov, zs, dtype=self.dtype,
                                          interpolation=self.interpolation,
-                                         omega_m=key[0], sigma8=key[1], **self.cosmo)
+                                         tangent=self.tangent, omega_m=key[0], sigma8=key[1],
+                                         **self.cosmo)
         return self._sims[key]
 
     def __call__(self, noise: torch.Tensor, omega_m: torch.Tensor, sigma8: torch.Tensor):

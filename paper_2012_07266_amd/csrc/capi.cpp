@@ -45,6 +45,10 @@ struct ArenaPlan {
     size_t disp[2], mom[2], id[2], acc, key, count, start, scan_sum, status;
     size_t mesh[3], nyq[3], halo, tw_nm, tw_hm, twp_nm, tw_np, tw_hp, twp_np, g_ic, atab, dtab, pmax;
     size_t xbc, fbc, dots, fmax, noise, g_ic_dom, adom, ddom, cacc;
+    // PM_MODE_PGD: filtered Green's function, shift, its bound, spare mesh
+    size_t pgd_g, pgd_s, pgd_bits, pgd_m, pgd_nyq;
+    // PM_MODE_TANGENT: x_dot, p_dot (each with the sort's second buffer), f_dot
+    size_t tan;
     size_t total;
 };
 
@@ -97,6 +101,15 @@ ArenaPlan plan_arena(const pm_params& p, const lens_params& l, size_t es) {
     a.adom = L.take(ATAB_N * es);
     a.ddom = L.take(ATAB_N * es);
     a.cacc = L.take(256);
+    a.pgd_g = a.pgd_s = a.pgd_bits = a.pgd_m = a.pgd_nyq = a.tan = 0;
+    if (p.modes & PM_MODE_PGD) {
+        a.pgd_g = L.take((3 * (nm / 2) * (nm / 2) + 1) * es);
+        a.pgd_s = L.take(3 * n * es);
+        a.pgd_bits = L.take(256);
+        a.pgd_m = L.take(nm * nm * nm * es);
+        a.pgd_nyq = L.take(nm * nm * 2 * es);
+    }
+    if (p.modes & PM_MODE_TANGENT) a.tan = L.take(15 * n * es);
     a.total = L.bytes;
     return a;
 }
@@ -104,6 +117,7 @@ ArenaPlan plan_arena(const pm_params& p, const lens_params& l, size_t es) {
 int validate(const pm_params* p, const lens_params* l) {
     if (!p || !l) return PM_EINVAL;
     if (p->dtype != PM_F32 && p->dtype != PM_F64) return PM_EINVAL;
+    if (p->modes & ~(PM_MODE_PGD | PM_MODE_TANGENT)) return PM_EINVAL;
     if (p->np < 16 || p->nm < 16 || p->np % 16 || p->nm % 16) return PM_EINVAL;
     if (p->nm != p->np && p->nm != 2 * p->np) return PM_EINVAL;
     if (!only_2_3(p->np) || !only_2_3(p->nm) || p->nm > 1024) return PM_EINVAL;
@@ -279,15 +293,15 @@ template <class T> struct Sim final : SimBase {
     // PGD correction of the projected positions: S = alpha0 a^mu times the
     // force of the density filtered by exp(-k_l^2/k^2) exp(-(k/k_s)^4)
     bool pgd = false;
-    double pgd_alpha0 = 0, pgd_mu = 0;
+    double pgd_alpha0 = 0, pgd_mu = 0, pgd_kl = 0, pgd_ks = 1;
     T* pgd_g = nullptr;            // [3 (Nm/2)^2 + 1] filtered Green's function
     T* pgd_s = nullptr;            // [3][Np^3] filtered force at the particles
     T* pgd_m = nullptr;            // [Nm^3] + Nyquist plane: the filtered force's
     T* pgd_nyq = nullptr;          // first component (the others use mesh 1, 2)
     uint32_t* pgd_bits = nullptr;  // max |pgd_s| (float bits)
     // forward-mode tangent of (x, p, f) along (noise, Omega_m, sigma_8), in
-    // tile order and Mpc/h, allocated on first use: x_dot and p_dot (each
-    // with a second buffer the sort's scatter permutes into) and f_dot
+    // tile order and Mpc/h (PM_MODE_TANGENT): x_dot and p_dot (each with a
+    // second buffer the sort's scatter permutes into) and f_dot
     T* tan_mem = nullptr;
     T *tx = nullptr, *tx_alt = nullptr, *tp = nullptr, *tp_alt = nullptr, *tf = nullptr;
     bool tan_valid = false;  // the tangent belongs to the current state
@@ -298,12 +312,6 @@ template <class T> struct Sim final : SimBase {
 
     ~Sim() override {
         if (arena) (void)hipFree(arena);
-        if (tan_mem) (void)hipFree(tan_mem);
-        if (pgd_g) (void)hipFree(pgd_g);
-        if (pgd_s) (void)hipFree(pgd_s);
-        if (pgd_bits) (void)hipFree(pgd_bits);
-        if (pgd_m) (void)hipFree(pgd_m);
-        if (pgd_nyq) (void)hipFree(pgd_nyq);
     }
 
     template <class U> U* at(size_t off) { return reinterpret_cast<U*>(arena + off); }
@@ -387,12 +395,28 @@ template <class T> struct Sim final : SimBase {
         adom = at<T>(ap.adom);
         ddom = at<T>(ap.ddom);
         cacc = at<double>(ap.cacc);
+        if (p->modes & PM_MODE_PGD) {
+            pgd_g = at<T>(ap.pgd_g);
+            pgd_s = at<T>(ap.pgd_s);
+            pgd_bits = at<uint32_t>(ap.pgd_bits);
+            pgd_m = at<T>(ap.pgd_m);
+            pgd_nyq = at<T>(ap.pgd_nyq);
+        }
+        if (p->modes & PM_MODE_TANGENT) {
+            const size_t n3 = 3 * (size_t)geo.npart;
+            tan_mem = at<T>(ap.tan);
+            tx = tan_mem;
+            tx_alt = tan_mem + n3;
+            tp = tan_mem + 2 * n3;
+            tp_alt = tan_mem + 3 * n3;
+            tf = tan_mem + 4 * n3;
+        }
         return upload_tables();
     }
 
     int reconfigure(const pm_params* p, const lens_params* l) override {
-        if (p->np != P.np || p->nm != P.nm || p->dtype != P.dtype || l->npix != npix ||
-            l->nsrc != nsrc)
+        if (p->np != P.np || p->nm != P.nm || p->dtype != P.dtype || p->modes != P.modes ||
+            l->npix != npix || l->nsrc != nsrc)
             return PM_EINVAL;
         HIPCHK(hipStreamSynchronize(st));
         set_physics(p, l);
@@ -485,8 +509,29 @@ template <class T> struct Sim final : SimBase {
             for (int k = 0; k < ATAB_N; ++k) w[k] = (T)((dp[k] - dm[k]) / (2.0 * DOM));
             if ((rc = upload(ap.ddom, w))) return rc;
         }
+        // the PGD filter lives on the box's wave numbers
+        if (pgd && (rc = upload_pgd_table())) return rc;
         launch_fill_u32(status, 0u, 1, st);
         launch_fill<double>(cacc, 0.0, 2, st);
+        HIPCHK(hipStreamSynchronize(st));
+        return PM_OK;
+    }
+
+    // G(q) = 1 / (2 pi q Nm^2) of the Poisson solve (mesh-cell units), times
+    // the PGD filter exp(-k_l^2 / k^2) exp(-(k / k_s)^4) at k = 2 pi sqrt(q) / L
+    int upload_pgd_table() {
+        const int h = P.nm / 2;
+        const size_t ng = 3 * (size_t)h * h + 1;
+        std::vector<T> g(ng);
+        const double gscale = 1.0 / (2.0 * PI * (double)P.nm * (double)P.nm);
+        g[0] = T(0);
+        for (size_t q = 1; q < ng; ++q) {
+            const double k = 2.0 * PI * std::sqrt((double)q) / P.box;
+            const double kq = k / pgd_ks;
+            g[q] = (T)(gscale / (double)q * std::exp(-(pgd_kl * pgd_kl) / (k * k)) *
+                       std::exp(-(kq * kq) * (kq * kq)));
+        }
+        HIPCHK(hipMemcpyAsync(pgd_g, g.data(), ng * sizeof(T), hipMemcpyHostToDevice, st));
         HIPCHK(hipStreamSynchronize(st));
         return PM_OK;
     }
@@ -653,43 +698,14 @@ template <class T> struct Sim final : SimBase {
             pgd = false;
             return PM_OK;
         }
+        if (!(P.modes & PM_MODE_PGD)) return PM_EINVAL;  // no buffers in the arena
         if (!std::isfinite(alpha0) || !std::isfinite(mu) || !std::isfinite(k_l) ||
             !(k_l >= 0) || !(k_s > 0))
             return PM_EINVAL;
-        const size_t n = (size_t)geo.npart;
-        const int h = P.nm / 2;
-        const size_t ng = 3 * (size_t)h * h + 1;
-        if (!pgd_g) {
-            const size_t nm = (size_t)P.nm;
-            if (hipMalloc(&pgd_g, ng * sizeof(T)) != hipSuccess ||
-                hipMalloc(&pgd_s, 3 * n * sizeof(T)) != hipSuccess ||
-                hipMalloc(&pgd_bits, 256) != hipSuccess ||
-                hipMalloc(&pgd_m, nm * nm * nm * sizeof(T)) != hipSuccess ||
-                hipMalloc(&pgd_nyq, nm * nm * 2 * sizeof(T)) != hipSuccess) {
-                (void)hipGetLastError();
-                if (pgd_g) (void)hipFree(pgd_g);
-                if (pgd_s) (void)hipFree(pgd_s);
-                if (pgd_bits) (void)hipFree(pgd_bits);
-                if (pgd_m) (void)hipFree(pgd_m);
-                if (pgd_nyq) (void)hipFree(pgd_nyq);
-                pgd_g = pgd_s = pgd_m = pgd_nyq = nullptr;
-                pgd_bits = nullptr;
-                return PM_ENOMEM;
-            }
-        }
-        // G(q) = 1 / (2 pi q Nm^2) of the Poisson solve (mesh-cell units),
-        // times the filter at k = 2 pi sqrt(q) / L
-        std::vector<T> g(ng);
-        const double gscale = 1.0 / (2.0 * PI * (double)P.nm * (double)P.nm);
-        g[0] = T(0);
-        for (size_t q = 1; q < ng; ++q) {
-            const double k = 2.0 * PI * std::sqrt((double)q) / P.box;
-            const double kq = k / k_s;
-            g[q] = (T)(gscale / (double)q * std::exp(-(k_l * k_l) / (k * k)) *
-                       std::exp(-(kq * kq) * (kq * kq)));
-        }
-        HIPCHK(hipMemcpyAsync(pgd_g, g.data(), ng * sizeof(T), hipMemcpyHostToDevice, st));
-        HIPCHK(hipStreamSynchronize(st));
+        pgd_kl = k_l;
+        pgd_ks = k_s;
+        int rc = upload_pgd_table();
+        if (rc) return rc;
         pgd_alpha0 = alpha0;
         pgd_mu = mu;
         pgd = true;
@@ -1195,21 +1211,8 @@ template <class T> struct Sim final : SimBase {
     }
 
     // ---- forward mode (tangents) ---------------------------------------------
-    int ensure_tangent() {
-        if (tan_mem) return PM_OK;
-        const size_t n3 = 3 * (size_t)geo.npart;
-        if (hipMalloc(&tan_mem, 5 * n3 * sizeof(T)) != hipSuccess) {
-            (void)hipGetLastError();
-            tan_mem = nullptr;
-            return PM_ENOMEM;
-        }
-        tx = tan_mem;
-        tx_alt = tan_mem + n3;
-        tp = tan_mem + 2 * n3;
-        tp_alt = tan_mem + 3 * n3;
-        tf = tan_mem + 4 * n3;
-        return PM_OK;
-    }
+    // The tangent's buffers are part of the arena of a PM_MODE_TANGENT handle.
+    int ensure_tangent() const { return tan_mem ? PM_OK : PM_EINVAL; }
 
     // Force tangent at the current state along tx into tf; with pd set, also
     // the second half-kick p_dot += K2 f_dot + ck2 f.  Leaves the meshes
@@ -1237,10 +1240,9 @@ template <class T> struct Sim final : SimBase {
     }
 
     int init_ic_jvp(const void* nd, double om_dot, double s8_dot) override {
+        if (ensure_tangent()) return PM_EINVAL;
         if (!nd || !std::isfinite(om_dot) || !std::isfinite(s8_dot)) return PM_EINVAL;
         if (!ic_fresh) return PM_ESTATE;
-        int rc = ensure_tangent();
-        if (rc) return rc;
         const int np = P.np;
         const long n = geo.npart;
         const double a0 = a_cur;
@@ -1281,10 +1283,9 @@ template <class T> struct Sim final : SimBase {
     }
 
     int set_tangent(const void* xd, const void* pd, double om_dot) override {
+        if (ensure_tangent()) return PM_EINVAL;
         if (!xd || !pd || !std::isfinite(om_dot)) return PM_EINVAL;
         if (a_cur < 0) return PM_ESTATE;
-        int rc = ensure_tangent();
-        if (rc) return rc;
         launch_lattice_to_sorted<T>(cur, geo, reinterpret_cast<const T*>(xd), tx, st);
         launch_lattice_to_sorted<T>(cur, geo, reinterpret_cast<const T*>(pd), tp, st);
         force_jvp_cur(nullptr, T(0), T(0));
@@ -1294,6 +1295,7 @@ template <class T> struct Sim final : SimBase {
     }
 
     int get_tangent(void* xd, void* pd, void* fd) override {
+        if (ensure_tangent()) return PM_EINVAL;
         if (!tan_valid) return PM_ESTATE;
         const long n = geo.npart;
         T* out[3] = {reinterpret_cast<T*>(xd), reinterpret_cast<T*>(pd), reinterpret_cast<T*>(fd)};
@@ -1305,6 +1307,7 @@ template <class T> struct Sim final : SimBase {
     }
 
     int step_jvp(double a0, double a1) override {
+        if (ensure_tangent()) return PM_EINVAL;
         if (!tan_valid) return PM_ESTATE;
         if (!at_a(a0)) return PM_ESTATE;
         if (!(a1 > 0 && a1 <= 1.5)) return PM_EINVAL;
@@ -1344,7 +1347,7 @@ template <class T> struct Sim final : SimBase {
     }
 
     int lens_jvp(double a0, double a1, void* kd) override {
-        if (!kd) return PM_EINVAL;
+        if (ensure_tangent() || !kd) return PM_EINVAL;
         if (pgd) return PM_EINVAL;  // no tangent pass for the PGD correction
         if (!tan_valid || !at_a(a1)) return PM_ESTATE;
         LensArgs<T> la;

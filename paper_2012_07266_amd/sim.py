@@ -24,8 +24,9 @@ def _ptr(t: Optional[torch.Tensor]):
 
 
 def make_params(np_side, nm_side, box, omega_m=0.3, sigma8=0.8, h=0.7, n_s=0.96,
-                omega_b=0.05, t_cmb=2.7255, dtype=torch.float32):
+                omega_b=0.05, t_cmb=2.7255, dtype=torch.float32, modes=0):
     p = PmParams()
+    p.modes = int(modes)
     p.np, p.nm, p.box = int(np_side), int(nm_side), float(box)
     p.omega_m, p.omega_b, p.h, p.n_s = float(omega_m), float(omega_b), float(h), float(n_s)
     p.sigma8, p.t_cmb = float(sigma8), float(t_cmb)
@@ -42,24 +43,33 @@ def make_lens(npix, fov_deg, z_src: Sequence[float]):
     return l
 
 
-def footprint(np_side, nm_side, box, npix, fov_deg, z_src, dtype=torch.float32, **cosmo):
-    p = make_params(np_side, nm_side, box, dtype=dtype, **cosmo)
+def footprint(np_side, nm_side, box, npix, fov_deg, z_src, dtype=torch.float32, modes=0,
+              **cosmo):
+    p = make_params(np_side, nm_side, box, dtype=dtype, modes=modes, **cosmo)
     l = make_lens(npix, fov_deg, z_src)
     return int(lib().pm_footprint(ctypes.byref(p), ctypes.byref(l)))
 
 
 class Simulation:
-    """A PM + lightcone simulation resident on one GPU."""
+    """A PM + lightcone simulation resident on one GPU.
+
+    `modes` (PM_MODE_* bits) sizes the arena for the optional passes: the PGD
+    correction (implied by `pgd`) and forward-mode tangents (`tangent`).
+    """
 
     def __init__(self, np_side, nm_side, box, npix, fov_deg, z_src, *,
                  dtype=torch.float32, stream: Optional[torch.cuda.Stream] = None,
-                 interpolation: bool = False, pgd=None, **cosmo):
+                 interpolation: bool = False, pgd=None, tangent: bool = False, modes: int = 0,
+                 **cosmo):
         self.np_side, self.nm_side, self.box = int(np_side), int(nm_side), float(box)
         self.npix, self.fov_deg, self.z_src = int(npix), float(fov_deg), tuple(z_src)
         self.dtype = dtype
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.stream = stream if stream is not None else torch.cuda.current_stream()
-        p = make_params(np_side, nm_side, box, dtype=dtype, **cosmo)
+        modes = int(modes) | (_lib.PM_MODE_PGD if pgd is not None else 0) | \
+            (_lib.PM_MODE_TANGENT if tangent else 0)
+        self.modes = modes
+        p = make_params(np_side, nm_side, box, dtype=dtype, modes=modes, **cosmo)
         l = make_lens(npix, fov_deg, z_src)
         h = ctypes.c_void_p()
         check(lib().pm_create(ctypes.byref(p), ctypes.byref(l),
@@ -119,7 +129,8 @@ class Simulation:
             if len(z_src) != len(self.z_src):
                 raise ValueError("the number of source planes is fixed by the arena")
             self.z_src = tuple(z_src)
-        p = make_params(self.np_side, self.nm_side, self.box, dtype=self.dtype, **cosmo)
+        p = make_params(self.np_side, self.nm_side, self.box, dtype=self.dtype, modes=self.modes,
+                        **cosmo)
         l = make_lens(self.npix, self.fov_deg, self.z_src)
         check(lib().pm_reconfigure(self._h, ctypes.byref(p), ctypes.byref(l)), "pm_reconfigure")
         self.a = None

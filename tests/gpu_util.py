@@ -13,14 +13,14 @@ def log(msg):
     sys.stdout.flush()
 
 
-def new_sim(wl: W.Workload, dtype=torch.float32, npix=None, fov=None, z_src=None):
+def new_sim(wl: W.Workload, dtype=torch.float32, npix=None, fov=None, z_src=None, modes=0):
     from paper_2012_07266_amd import Simulation
     return Simulation(wl.np_side, wl.nm_side, wl.box,
                       npix if npix is not None else wl.npix,
                       fov if fov is not None else wl.fov_deg,
                       z_src if z_src is not None else wl.z_src,
-                      dtype=dtype, omega_m=wl.omega_m, sigma8=wl.sigma8, h=wl.h,
-                      n_s=wl.n_s, omega_b=wl.omega_b, t_cmb=wl.t_cmb)
+                      dtype=dtype, modes=modes, omega_m=wl.omega_m, sigma8=wl.sigma8,
+                      h=wl.h, n_s=wl.n_s, omega_b=wl.omega_b, t_cmb=wl.t_cmb)
 
 
 def cosmo_of(wl: W.Workload):

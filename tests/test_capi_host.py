@@ -58,6 +58,41 @@ def test_footprint(lib):
     assert 3.2e9 < fp < 3.7e9
 
 
+def test_footprint_counts_the_optional_modes(lib):
+    """PM_MODE_PGD adds the filter table, the shift [3][P] and one spare mesh
+    with its Nyquist plane; PM_MODE_TANGENT adds 15 P values (x_dot, p_dot,
+    each with the sort's second buffer, and f_dot); both add their sum."""
+    from paper_2012_07266_amd._lib import PM_MODE_PGD, PM_MODE_TANGENT
+    np_, nm = 128, 256
+    P, es = np_ ** 3, 4
+    fp = {}
+    for m in (0, PM_MODE_PGD, PM_MODE_TANGENT, PM_MODE_PGD | PM_MODE_TANGENT):
+        p, l = _params(np_side=np_, nm_side=nm, box=128.0, modes=m)
+        fp[m] = lib.pm_footprint(ctypes.byref(p), ctypes.byref(l))
+    pgd = (3 * (nm // 2) ** 2 + 1) * es + 3 * P * es + nm ** 3 * es + 2 * nm * nm * es
+    tan = 15 * P * es
+    slack = 5 * 256  # each buffer is 256-byte aligned
+    assert 0 <= fp[PM_MODE_PGD] - fp[0] - pgd <= slack
+    assert 0 <= fp[PM_MODE_TANGENT] - fp[0] - tan <= slack
+    assert 0 <= fp[PM_MODE_PGD | PM_MODE_TANGENT] - fp[0] - pgd - tan <= 2 * slack
+    p, l = _params(modes=4)  # no such mode
+    assert lib.pm_footprint(ctypes.byref(p), ctypes.byref(l)) == 0
+
+
+def test_device_memory_is_allocated_only_at_creation():
+    """Every hipMalloc / hipFree of the simulation library sits in pm_create's
+    arena set-up or the handle's destructor (capi.cpp), or in the serving
+    loop's slot management (server.cpp); no other source allocates."""
+    csrc = os.path.join(ROOT, "paper_2012_07266_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        src = open(os.path.join(csrc, f)).read()
+        calls = re.findall(r"\bhip(?:Malloc\w*|Free|ExtMalloc\w*)\s*\(", src)
+        if f == "capi.cpp":
+            assert len(calls) == 2, calls  # the arena and its release
+        elif f != "server.cpp":
+            assert not calls, (f, calls)
+
+
 @pytest.mark.parametrize("bad", [
     dict(np_side=30, nm_side=60),       # not a multiple of 16
     dict(np_side=32, nm_side=96),       # B = 3

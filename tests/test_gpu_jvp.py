@@ -7,6 +7,7 @@ import pytest
 import torch
 
 import workloads as W
+from paper_2012_07266_amd._lib import PM_MODE_TANGENT
 from tests.gpu_util import cosmo_of, log, new_sim, rel_rms, to_np
 
 pytestmark = pytest.mark.gpu
@@ -57,7 +58,7 @@ def test_force_and_step_tangents_match_oracle(dtype, shape):
     xd0 = rd(rng.standard_normal((3, wl.n_particles)))
     pd0 = rd(rng.standard_normal((3, wl.n_particles)))
     om_dot = 0.7
-    with new_sim(wl, dtype) as sim:
+    with new_sim(wl, dtype, modes=PM_MODE_TANGENT) as sim:
         T = lambda v: torch.tensor(v, dtype=dtype, device="cuda")
         sim.set_state(T(x0), T(p0), a[0])
         sim.set_tangent(T(xd0), T(pd0), om_dot)
@@ -110,7 +111,7 @@ def test_lens_tangent_of_static_field(dtype, seed):
     a_far, a_near = 0.55, 0.7
     om_dot = 0.6
     log(f"lens tangent {dtype} rotation={seed}")
-    with new_sim(wl, dtype) as sim:
+    with new_sim(wl, dtype, modes=PM_MODE_TANGENT) as sim:
         if seed is not None:
             sim.set_replica_rotation(seed)
         sim.set_state(torch.from_numpy(x), torch.zeros((3, 16 ** 3), dtype=torch.float64), a_near)
@@ -162,7 +163,7 @@ def test_model_tangent_matches_oracle(dtype, direction):
         nd = rd(np.random.default_rng(43).standard_normal(noise.shape))
         om_dot, s8_dot = 0.5, -0.8
     log(f"model tangent {dtype} {direction}")
-    with new_sim(wl, dtype) as sim:
+    with new_sim(wl, dtype, modes=PM_MODE_TANGENT) as sim:
         T = lambda v: torch.tensor(v, dtype=dtype, device="cuda")
         kap, kd = run_jvp(sim, T(noise), a, T(nd), om_dot, s8_dot)
         kg, kdg = to_np(kap), to_np(kd)
@@ -188,8 +189,8 @@ def test_tangent_transposes_the_reverse_pass_at_the_gradient_workload():
     dtype = torch.float64
     log("transpose identity, gradient workload, float64")
     model = LensingModel(wl.np_side, wl.nm_side, wl.box, wl.npix, wl.fov_deg, wl.z_src,
-                         wl.a_grid(), dtype=dtype, h=wl.h, n_s=wl.n_s, omega_b=wl.omega_b,
-                         t_cmb=wl.t_cmb)
+                         wl.a_grid(), dtype=dtype, tangent=True, h=wl.h, n_s=wl.n_s,
+                         omega_b=wl.omega_b, t_cmb=wl.t_cmb)
     noise = torch.tensor(W.white_noise(wl.np_side, wl.seed), dtype=dtype, device="cuda")
     rng = np.random.default_rng(44)
     nd = torch.tensor(rng.standard_normal(noise.shape), dtype=dtype, device="cuda")
@@ -224,7 +225,7 @@ def test_tangent_error_paths():
         with pytest.raises(MadlensError) as e:
             fn(*args)
         return e.value.code
-    with new_sim(wl) as sim:
+    with new_sim(wl, modes=PM_MODE_TANGENT) as sim:
         assert code(sim.init_ic_jvp, noise) == PM_ESTATE     # no initial conditions yet
         sim.init_ic(noise, 0.4)
         assert code(sim.step_jvp, 0.4, 0.5) == PM_ESTATE     # no tangent yet
@@ -271,7 +272,7 @@ def test_lens_tangent_with_subevolution(dtype, seed):
     rd = _rd(dtype)
     x, p, xd, pd = rd(x), rd(p), rd(xd), rd(pd)
     log(f"sub-evolved lens tangent {dtype} rotation={seed}")
-    with new_sim(wl, dtype) as sim:
+    with new_sim(wl, dtype, modes=PM_MODE_TANGENT) as sim:
         sim.set_interpolation(True)
         if seed is not None:
             sim.set_replica_rotation(seed)
@@ -315,7 +316,7 @@ def test_model_tangent_with_subevolution(dtype):
     nd = rd(np.random.default_rng(46).standard_normal(noise.shape))
     om_dot, s8_dot = 0.5, -0.8
     log(f"model tangent with sub-evolution {dtype}")
-    with new_sim(wl, dtype) as sim:
+    with new_sim(wl, dtype, modes=PM_MODE_TANGENT) as sim:
         sim.set_interpolation(True)
         T = lambda v: torch.tensor(v, dtype=dtype, device="cuda")
         kap, kd = run_jvp(sim, T(noise), a, T(nd), om_dot, s8_dot)

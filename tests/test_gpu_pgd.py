@@ -7,6 +7,7 @@ import pytest
 import torch
 
 import workloads as W
+from paper_2012_07266_amd._lib import PM_MODE_PGD
 from tests.gpu_util import cosmo_of, log, new_sim, rel_rms, to_np
 
 pytestmark = pytest.mark.gpu
@@ -38,7 +39,7 @@ def test_pgd_run_matches_oracle(dtype, shape):
     c = cosmo_of(wl)
     noise = W.white_noise(np_side, wl.seed)
     a = wl.a_grid()
-    with new_sim(wl, dtype) as sim:
+    with new_sim(wl, dtype, modes=PM_MODE_PGD) as sim:
         sim.set_pgd(*PGD)
         kg = to_np(sim.run(torch.from_numpy(noise), a))
         sim.sync()
@@ -59,7 +60,7 @@ def test_pgd_stepwise_equals_fused(dtype):
     wl = _wl(32, 64, 64.0)
     noise = torch.from_numpy(W.white_noise(32, wl.seed))
     a = wl.a_grid()
-    with new_sim(wl, dtype) as sim:
+    with new_sim(wl, dtype, modes=PM_MODE_PGD) as sim:
         sim.set_pgd(*PGD)
         k1 = sim.run_stepwise(noise, a).clone()
         k2 = sim.run(noise, a)
@@ -79,7 +80,7 @@ def test_pgd_with_interpolation_matches_oracle(dtype):
     c = cosmo_of(wl)
     noise = W.white_noise(16, wl.seed)
     a = wl.a_grid()
-    with new_sim(wl, dtype) as sim:
+    with new_sim(wl, dtype, modes=PM_MODE_PGD) as sim:
         sim.set_pgd(*PGD)
         sim.set_interpolation(True)
         kg = to_np(sim.run(torch.from_numpy(noise), a))
@@ -97,7 +98,7 @@ def test_pgd_error_paths():
     from paper_2012_07266_amd._lib import PM_EINVAL
     wl = _wl(16, 32, 40.0)
     noise = torch.from_numpy(W.white_noise(16, 3))
-    with new_sim(wl) as sim:
+    with new_sim(wl, modes=PM_MODE_PGD) as sim:
         for bad in ((0.5, 0.5, -0.1, 1.0), (0.5, 0.5, 0.1, 0.0), (float("nan"), 0.5, 0.1, 1.0)):
             with pytest.raises(MadlensError) as e:
                 sim.set_pgd(*bad)
@@ -116,3 +117,39 @@ def test_pgd_error_paths():
         sim.lens(0.3, 0.4, kap)
         sim.sync()
         assert torch.isfinite(kap).all()
+
+
+def test_pgd_needs_its_mode():
+    """A handle created without PM_MODE_PGD has no PGD buffers in its arena
+    and refuses the correction (PM_EINVAL); switching it off is allowed."""
+    from paper_2012_07266_amd import MadlensError
+    from paper_2012_07266_amd._lib import PM_EINVAL
+    with new_sim(_wl(16, 32, 40.0)) as sim:
+        with pytest.raises(MadlensError) as e:
+            sim.set_pgd(*PGD)
+        assert e.value.code == PM_EINVAL
+        sim.set_pgd(*PGD, on=False)
+
+
+def test_pgd_reconfigured_to_a_new_box_equals_fresh_handle():
+    """pm_reconfigure to another box with the correction on rebuilds the
+    filter on the new box's wave numbers: the run equals, bit for bit in
+    float32, that of a handle created for the new box."""
+    wl = _wl(32, 64, 64.0)
+    big = wl.with_(box=96.0)
+    noise = torch.from_numpy(W.white_noise(32, 5))
+    a = wl.a_grid()
+    log("pgd reconfigure to a new box")
+    with new_sim(wl, modes=PM_MODE_PGD) as sim:
+        sim.set_pgd(*PGD)
+        k0 = sim.run(noise, a).clone()
+        sim.reconfigure(box=big.box, h=wl.h, n_s=wl.n_s, omega_b=wl.omega_b, t_cmb=wl.t_cmb,
+                        omega_m=wl.omega_m, sigma8=wl.sigma8)
+        k1 = sim.run(noise, a).clone()
+        sim.sync()
+    with new_sim(big, modes=PM_MODE_PGD) as fresh:
+        fresh.set_pgd(*PGD)
+        k2 = fresh.run(noise, a)
+        fresh.sync()
+    assert not torch.equal(k0, k1)
+    assert torch.equal(k1, k2)

@@ -9,6 +9,7 @@ import pytest
 import torch
 
 import workloads as W
+from paper_2012_07266_amd._lib import PM_MODE_PGD
 from tests.gpu_util import cosmo_of, log, new_sim, rel_rms, to_np
 
 pytestmark = pytest.mark.gpu
@@ -74,7 +75,7 @@ def test_rotated_run_matches_oracle(dtype):
     a = wl.a_grid()
     pgd = (0.5, 0.5, 0.05, 1.5)
     log(f"rotated run {dtype}")
-    with new_sim(wl, dtype) as sim:
+    with new_sim(wl, dtype, modes=PM_MODE_PGD) as sim:
         sim.set_replica_rotation(SEED)
         sim.set_interpolation(True)
         sim.set_pgd(*pgd)
