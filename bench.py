@@ -1,28 +1,37 @@
 """Benchmark: particle-steps/s of the PM step + Born lens projection on one GPU.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload cfg2]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--repeats R] [--workload cfg2]
 
 Workload (default): 256^3 particles on a 512^3 force mesh in a 205 Mpc/h
 box, 40 PM steps linear in a from 0.01 to 1.0, four 2048^2 convergence maps
 over 5 deg x 5 deg at z_s = 0.5, 1, 1.5, 2 (float32), seeded Gaussian white
 noise initial conditions.  A "step" is one step of pm_run: a KDK step and
-the Born projection of its shell (bit for bit pm_step + lens_project).  W
-untimed steps run first; then the initial conditions are regenerated
-(untimed) and K consecutive steps of the schedule are timed
-(the schedule restarts from fresh initial conditions, inside the timed
-region, if K exceeds it).  Per-kernel durations come from HIP events the
-library records on its own stream: for every kernel, over an untimed pass
-of the same K steps; for the roofline's kernel alone, during the timed
-region (events between kernels cost time of their own: recording every
-launch measured about 2% more time per step).
+the Born projection of its shell (bit for bit pm_step + lens_project).
 
-The line also carries the same run with sub-evolution projection, with
-the PGD correction and with replica rotation (mode_bench), the forward + reverse timing of the gradient
-workload (gradient_bench), the serving figures named by the metric: p50/p99
-latency (arrival to maps on the host) and throughput of Poisson streams of
-mixed-size requests, served (continuous batching) and plain (one
-simulation at a time), see serving_bench; and the float64 oracle timed on
-a bounded sample of the same step (cpu_baseline).
+Timing: W untimed warm-up steps; then R repeats, each from fresh initial
+conditions, of the schedule with its LAST K steps timed (the first N - K
+steps run untimed before the timer starts; with K > N the schedule restarts
+from fresh initial conditions inside the timed region).  The reported step
+time is the median of the R repeats.  With the default K = 40 the whole
+schedule is timed; K = 20 times the late, clustered half (a = 0.505 -> 1)
+with 20 of its 27 lens shells.  Per-kernel durations come from HIP events
+the library records on its own stream: for every kernel over one more,
+untimed, pass of the same window; for the roofline's kernel alone inside the
+timed repeats (events between kernels cost time of their own).
+
+The line also carries the same run with sub-evolution projection, with the
+PGD correction and with replica rotation (mode_bench), the forward + reverse
+timing of the gradient workload (gradient_bench), the serving figures named
+by the metric: p50/p99 latency (arrival to maps on the host) and throughput
+of Poisson streams of mixed-size requests, served (continuous batching) and
+plain (one simulation at a time), see serving_bench; and the float64 oracle
+on the host (cpu_baseline): timed in full on the 32^3 workload and on a
+bounded sample of one step of the benchmark's workload.
+
+Counter-measured HBM traffic (profiles/traffic.json) is taken over one
+steady-state step late in the schedule: run `bench.py --traffic-step S`
+under rocprofv3 --pmc FETCH_SIZE, then WRITE_SIZE, and convert with
+`bench.py --traffic-from FETCH_CSV WRITE_CSV` (see traffic_from_pmc).
 
 Prints ONE JSON line.
 """
@@ -40,13 +49,15 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, GB/s
+STEP_GATE = 0.60       # fraction of the HBM peak the PM step is to sustain
 
 
 def algorithmic_bytes(wl, esize=4):
     """Algorithmic HBM bytes of one launch of every timed kernel class.
 
     P = particles, M = one real mesh, S = one half spectrum (main + Nyquist
-    plane).  Counts each input read once and each output written once.
+    plane).  Counts each input read once and each output written once, for
+    the arrays each kernel of this library actually reads and writes.
     """
     P = wl.np_side ** 3
     nm = wl.nm_side
@@ -71,103 +82,162 @@ def algorithmic_bytes(wl, esize=4):
     }
 
 
+def model_bytes(wl, esize=4):
+    """The byte model of the method's hot path per particle-step unit (one
+    step's particles and meshes), for the kernels it names: readout + kick +
+    drift reads three force meshes and reads and writes position and
+    momentum, 3 M + 48 P (no particle id, no sort key)."""
+    P = wl.np_side ** 3
+    M = wl.nm_side ** 3 * esize
+    return {"readout_kick_drift_key": 3 * M + 48 * P, "readout_kick": 3 * M + 48 * P}
+
+
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
 # kernel class -> (substring of the HIP kernel name in rocprofv3 output, source)
 KERNEL_SYMBOL = {
-    "fft_grad_axis0": ("k_grad_x0<float, 512", "paper_2012_07266_amd/csrc/fft.hip"),
-    "readout_kick": ("k_readout<float>", "paper_2012_07266_amd/csrc/particles.hip"),
-    "readout_kick_drift_key": ("k_readout<float>", "paper_2012_07266_amd/csrc/particles.hip"),
+    "kick_drift_key": ("k_kick_drift_key<float", "paper_2012_07266_amd/csrc/particles.hip"),
+    "scan": ("k_scan_", "paper_2012_07266_amd/csrc/particles.hip"),
+    "scatter": ("k_scatter<float", "paper_2012_07266_amd/csrc/particles.hip"),
     "paint": ("k_paint_group<float", "paper_2012_07266_amd/csrc/particles.hip"),
-    "fft_c2c_axis1_inv": ("k_c2c_view<float, 512, 16, -1>", "paper_2012_07266_amd/csrc/fft.hip"),
-    "fft_c2c_axis1_dual": ("k_c2c_view_dual<float, 512", "paper_2012_07266_amd/csrc/fft.hip"),
-    "fft_c2r_axis2": ("k_c2r_rows<float, 256", "paper_2012_07266_amd/csrc/fft.hip"),
     "lens_gather": ("k_lens_gather<float", "paper_2012_07266_amd/csrc/lens.hip"),
+    "fft_r2c_axis2": ("k_r2c_rows<float", "paper_2012_07266_amd/csrc/fft.hip"),
+    "fft_c2c_axis1_fwd": ("k_c2c_view<float, 512, 16, 1>", "paper_2012_07266_amd/csrc/fft.hip"),
+    "fft_grad_axis0": ("k_grad_x0<float", "paper_2012_07266_amd/csrc/fft.hip"),
+    "fft_c2c_axis1_inv": ("k_c2c_view<float, 512, 16, -1>", "paper_2012_07266_amd/csrc/fft.hip"),
+    "fft_c2c_axis1_dual": ("k_c2c_view_dual<float", "paper_2012_07266_amd/csrc/fft.hip"),
+    "fft_c2r_axis2": ("k_c2r_rows<float", "paper_2012_07266_amd/csrc/fft.hip"),
+    "readout_kick_drift_key": ("k_readout<float>", "paper_2012_07266_amd/csrc/particles.hip"),
+    "fill": ("k_fill", "paper_2012_07266_amd/csrc/particles.hip"),
 }
 COPY_BYTES = 1 << 30  # the calibration copy moves 1 GiB in and 1 GiB out
 
 
-def traffic_from_pmc(fetch_csv, write_csv, workload):
-    """Write profiles/traffic.json from two rocprofv3 --pmc runs of
-    `bench.py --calibrate-copy` (FETCH_SIZE, then WRITE_SIZE, in KiB per
-    dispatch).  Each counter is scaled by what it reads for the 1 GiB
-    calibration copy, whose true traffic is known.  `workload` names the
-    workload the counted runs stepped."""
+def _pmc_rows(path, counter):
+    """(dispatch order, kernel name, bytes) of every dispatch of one counter."""
     import csv
-    import hashlib
-
-    def per_kernel(path, counter):
-        acc = {}
-        for r in csv.DictReader(open(path)):
-            if r["Counter_Name"] != counter:
-                continue
-            acc.setdefault(r["Kernel_Name"], []).append(float(r["Counter_Value"]) * 1024.0)
-        return acc
-
-    fetch = per_kernel(fetch_csv, "FETCH_SIZE")
-    write = per_kernel(write_csv, "WRITE_SIZE")
-
-    def find(d, sub):
-        hits = [x for k, v in d.items() if sub in k for x in v]
-        return sum(hits) / len(hits) if hits else None
-
-    def calib(d):  # the largest copy dispatch is the 1 GiB calibration copy
-        vals = [x for k, v in d.items() if "copy" in k.lower() for x in v]
-        return max(vals) if vals else None
-
-    cf, cw = calib(fetch), calib(write)
-    sf = COPY_BYTES / cf if cf else 1.0
-    sw = COPY_BYTES / cw if cw else 1.0
-    out = {"_about": "HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE, scaled "
-                     "by the counters of a 1 GiB device copy",
-           "_scale": {"fetch": sf, "write": sw}, "_workload": workload}
-    for cls, (sub, src) in KERNEL_SYMBOL.items():
-        f, w = find(fetch, sub), find(write, sub)
-        if f is None or w is None:
+    rows = []
+    for r in csv.DictReader(open(path)):
+        if r["Counter_Name"] != counter:
             continue
-        h = hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()
-        out[cls] = {"symbol": sub, "source": src, "sha256": h,
-                    "fetch_bytes": f * sf, "write_bytes": w * sw,
-                    "bytes_per_launch": f * sf + w * sw}
+        key = int(r.get("Dispatch_Id") or r.get("Correlation_Id") or len(rows))
+        rows.append((key, r["Kernel_Name"], float(r["Counter_Value"]) * 1024.0))
+    rows.sort()
+    return rows
+
+
+def _late_step(rows):
+    """The dispatches of the steady-state step that `--traffic-step` runs:
+    after the calibration copy (the marker), pm_run steps S and S + 1; step
+    S + 1 is every dispatch after the first readout up to and including the
+    second.  Returns (calibration bytes, [(name, bytes)])."""
+    i_copy = max(range(len(rows)), key=lambda i: rows[i][2] if "copy" in rows[i][1].lower() else -1)
+    calib = rows[i_copy][2]
+    reads = [i for i in range(i_copy + 1, len(rows)) if "k_readout" in rows[i][1]]
+    if len(reads) < 2:
+        raise RuntimeError("the counted run holds fewer than two readouts after the marker")
+    return calib, [(n, b) for _, n, b in rows[reads[0] + 1:reads[1] + 1]]
+
+
+def traffic_from_pmc(fetch_csv, write_csv, workload, step):
+    """Write profiles/traffic.json from two rocprofv3 --pmc runs of
+    `bench.py --traffic-step S` (FETCH_SIZE, then WRITE_SIZE, in KiB per
+    dispatch): the HBM bytes of every dispatch of step S + 1 of the
+    schedule, a steady-state step of pm_run late in the run.  Each counter
+    is scaled by what it reads for the 1 GiB calibration copy that precedes
+    the counted steps, whose true traffic is known."""
+    import hashlib
+    cf, fetch = _late_step(_pmc_rows(fetch_csv, "FETCH_SIZE"))
+    cw, write = _late_step(_pmc_rows(write_csv, "WRITE_SIZE"))
+    if [n for n, _ in fetch] != [n for n, _ in write]:
+        raise RuntimeError("the two counted runs dispatched different kernels")
+    sf, sw = COPY_BYTES / cf, COPY_BYTES / cw
+    per = {}
+    for (name, f), (_, w) in zip(fetch, write):
+        cls = next((c for c, (sub, _) in KERNEL_SYMBOL.items() if sub in name), name[:48])
+        e = per.setdefault(cls, {"launches": 0, "fetch_bytes": 0.0, "write_bytes": 0.0})
+        e["launches"] += 1
+        e["fetch_bytes"] += f * sf
+        e["write_bytes"] += w * sw
+    out = {"_about": ("HBM bytes of one steady-state pm_run step late in the schedule, from "
+                      "rocprofv3 FETCH_SIZE and WRITE_SIZE scaled by the counters of a 1 GiB "
+                      "device copy; per kernel class: bytes per launch"),
+           "_scale": {"fetch": sf, "write": sw}, "_workload": workload, "_step": step + 1,
+           "_step_bytes": sum(f * sf + w * sw for (_, f), (_, w) in zip(fetch, write))}
+    for cls, e in per.items():
+        src = KERNEL_SYMBOL.get(cls, (None, None))[1]
+        h = (hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest()
+             if src else None)
+        n = e["launches"]
+        out[cls] = {"symbol": KERNEL_SYMBOL.get(cls, (cls, None))[0], "source": src,
+                    "sha256": h, "launches": n, "fetch_bytes": e["fetch_bytes"] / n,
+                    "write_bytes": e["write_bytes"] / n,
+                    "bytes_per_launch": (e["fetch_bytes"] + e["write_bytes"]) / n}
     json.dump(out, open(TRAFFIC_JSON, "w"), indent=1)
     print(json.dumps(out))
 
 
-def load_traffic(kernel, workload):
-    """HBM traffic per launch measured with rocprofv3 counters, if they were
-    taken on this workload and the kernel source has not changed since (hash
-    recorded with the counters)."""
-    path = TRAFFIC_JSON
-    if not os.path.exists(path):
+def _source_current(ent):
+    import hashlib
+    if not ent.get("source"):
+        return True
+    h = hashlib.sha256(open(os.path.join(ROOT, ent["source"]), "rb").read()).hexdigest()
+    return h == ent["sha256"]
+
+
+def load_traffic(workload):
+    """The counter record of profiles/traffic.json if it was taken on this
+    workload, else None; entries whose kernel source has changed since (hash
+    recorded with the counters) are marked stale."""
+    if not os.path.exists(TRAFFIC_JSON):
         return None
     try:
-        rec = json.load(open(path))
-        if rec.get("_workload") != workload:
-            return None
-        ent = rec.get(kernel)
-        if not ent:
-            return None
-        import hashlib
-        src = os.path.join(ROOT, ent["source"])
-        h = hashlib.sha256(open(src, "rb").read()).hexdigest()
-        if h != ent["sha256"]:
-            return None
-        return ent["bytes_per_launch"]
-    except Exception:
+        rec = json.load(open(TRAFFIC_JSON))
+    except ValueError:
         return None
+    if rec.get("_workload") != workload:
+        return None
+    for k, v in rec.items():
+        if not k.startswith("_"):
+            v["current"] = _source_current(v)
+    return rec
 
 
 def cpu_baseline(wl, frac=8):
-    """The float64 oracle on a bounded sample of one step of the workload.
+    """The float64 oracle on the host, as it stands.
 
-    Sample: the oracle's own Zel'dovich state at a = 0.5; CIC paint and CIC
-    readout of 1/frac of the particles and the lens projection of the same
-    subsample for one late shell, each scaled by frac; the three full-size
-    Fourier force transforms.  Reported as particle-steps/s of one step.
+    In full: the 32^3 particle / 32^3 mesh workload (5 steps from a = 0.1,
+    one 64^2 map), initial conditions excluded, particle-steps/s.
+    Sample of the benchmark's workload: the oracle's own Zel'dovich state at
+    a = 0.5; CIC paint and CIC readout of 1/frac of the particles and the
+    lens projection of the same subsample for one late shell, each scaled by
+    frac; the three full-size Fourier force transforms.  Reported as
+    particle-steps/s of one step (an estimate from the sample).
     """
     from oracle import lens, pm
     from oracle.cosmology import Cosmology
     import workloads as W
-    c = Cosmology(wl.omega_m, wl.h, wl.n_s, wl.sigma8, wl.omega_b, wl.t_cmb)
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+
+    def cosmo(w):
+        return Cosmology(w.omega_m, w.h, w.n_s, w.sigma8, w.omega_b, w.t_cmb)
+    # the 32^3 workload in full
+    w1 = W.CFG1
+    c1 = cosmo(w1)
+    g1 = lens.MapGeometry(w1.npix, w1.fov_deg, w1.z_src, c1)
+    a1 = w1.a_grid()
+    n1 = W.white_noise(w1.np_side, w1.seed)
+    x, p = pm.zeldovich_ic(n1, c1, w1.box, w1.nm_side, a1[0])
+    f = pm.particle_force(x, w1.np_side, w1.nm_side, w1.box)
+    kap = np.zeros((1, w1.npix, w1.npix))
+    t0 = time.perf_counter()
+    for i in range(w1.nsteps):
+        x, p, f = pm.kdk_step(x, p, f, a1[i], a1[i + 1], c1, w1.np_side, w1.nm_side, w1.box)
+        kap += lens.project_shell(x, a1[i], a1[i + 1], c1, w1.box, w1.np_side, g1)
+    t_full = time.perf_counter() - t0
+    full = {"workload": w1.name, "value": w1.np_side ** 3 * w1.nsteps / t_full,
+            "unit": "particle-steps/s", "seconds": t_full, "s_per_step": t_full / w1.nsteps}
+    # a bounded sample of one step of the benchmark's workload
+    c = cosmo(wl)
     noise = W.white_noise(wl.np_side, wl.seed)
     x, _ = pm.zeldovich_ic(noise, c, wl.box, wl.nm_side, 0.5)
     sub = x[:, ::frac]
@@ -185,12 +255,13 @@ def cpu_baseline(wl, frac=8):
     lens.project_shell(sub, a[i], a[i + 1], c, wl.box, wl.np_side, geom)
     t4 = time.perf_counter()
     per_step = (t1 - t0) * frac + (t2 - t1) + (t3 - t2) * frac + (t4 - t3) * frac
-    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
     return {"value": wl.np_side ** 3 / per_step, "unit": "particle-steps/s",
             "cores": cores, "kind": "oracle",
-            "sample": (f"one PM step + lens shell {i} of {wl.name}: paint, readout and lens of "
-                       f"1/{frac} of the particles (scaled x{frac}) + full {wl.nm_side}^3 "
-                       f"float64 FFT force; {t4 - t0:.1f} s of CPU work, est. {per_step:.1f} s/step")}
+            "sample": (f"SAMPLE, an estimate: one PM step + lens shell {i} of {wl.name}: paint, "
+                       f"readout and lens of 1/{frac} of the particles (scaled x{frac}) + full "
+                       f"{wl.nm_side}^3 float64 FFT force; {t4 - t0:.1f} s of CPU work, est. "
+                       f"{per_step:.1f} s/step"),
+            "full_run": full}
 
 
 def gradient_bench(reps=3):
@@ -336,37 +407,20 @@ PGD_TIMING = (0.005, 0.5, 0.5, 5.0)
 ROTATION_SEED = 12345
 
 
-def mode_bench(sim, noise, a, kappa, run_steps, wl, steps, mode):
-    """The benchmark's schedule with sub-evolution projection (every image
-    moved along its step's drift to the scale factor of its own distance)
-    or with the PGD correction of the projected positions."""
-    import torch
+def mode_bench(sim, timed_window, wl, steps, mode):
+    """The benchmark's timed window with sub-evolution projection (every
+    image moved along its step's drift to the scale factor of its own
+    distance), with the PGD correction of the projected positions, or with
+    rotated replicas."""
     if mode == "interpolation":
         sim.set_interpolation(True)
     elif mode == "rotation":
         sim.set_replica_rotation(ROTATION_SEED)
     else:
         sim.set_pgd(*PGD_TIMING)
-    sim.init_ic(noise, a[0])
-    kappa.zero_()
-    run_steps(2, 0)
-    sim.init_ic(noise, a[0])
-    kappa.zero_()
-    sim.sync()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    run_steps(steps, 0)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    # kernel averages from a second, untimed pass with events around every launch
-    sim.init_ic(noise, a[0])
-    kappa.zero_()
-    sim.sync()
-    sim.profile(True)
-    run_steps(steps, 0)
-    sim.sync()
-    prof = sim.profile_read()
-    sim.profile(False)
+    times = [timed_window() for _ in range(3)]
+    # kernel averages from another, untimed pass with events around every launch
+    prof = timed_window(profile=True)
     sim.set_interpolation(False)
     sim.set_pgd(*PGD_TIMING, on=False)
     sim.set_replica_rotation(None)
@@ -375,8 +429,9 @@ def mode_bench(sim, noise, a, kappa, run_steps, wl, steps, mode):
         ms, cnt = prof.get(name, (0.0, 0))
         return ms / max(cnt, 1)
 
-    out = {"ms_per_step": 1e3 * (t1 - t0) / steps,
-           "particle_steps_per_s": wl.np_side ** 3 * steps / (t1 - t0),
+    t = float(np.median(times))
+    out = {"ms_per_step": 1e3 * t / steps,
+           "particle_steps_per_s": wl.np_side ** 3 * steps / t,
            "lens_gather_avg_ms": avg("lens_gather")}
     if mode == "interpolation":
         out["what"] = "the same run with sub-evolution projection"
@@ -395,6 +450,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=40)
     ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--repeats", type=int, default=5,
+                    help="timed repeats of the window; the median is reported")
     ap.add_argument("--workload", default="cfg2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
@@ -408,16 +465,20 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=100)
     ap.add_argument("--no-large-mix", action="store_true",
                     help="skip serving the 512^3/1024^3 run with a stream of small requests")
-    ap.add_argument("--calibrate-copy", action="store_true",
-                    help="also run a 1 GiB device copy (counter calibration for --pmc runs)")
+    ap.add_argument("--traffic-step", type=int, default=None, metavar="S",
+                    help="counter run: S untimed steps, a 1 GiB calibration copy, then steps "
+                         "S and S + 1 (run under rocprofv3 --pmc), and exit")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
-                    help="write profiles/traffic.json from two rocprofv3 --pmc CSVs and exit")
+                    help="write profiles/traffic.json from two rocprofv3 --pmc CSVs of "
+                         "--traffic-step runs and exit")
     args = ap.parse_args()
     import workloads as W
     wl = {"cfg1": W.CFG1.with_(name="plain_fp32_32p_32m"), "cfg2": W.CFG2,
           "cfg3": W.CFG3, "cfg5": W.CFG5}[args.workload]
+    late = int(0.75 * wl.nsteps)  # step 30 of 40: strong clustering
     if args.traffic_from:
-        traffic_from_pmc(*args.traffic_from, wl.name)
+        traffic_from_pmc(*args.traffic_from, wl.name, late if args.traffic_step is None
+                         else args.traffic_step)
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -425,13 +486,12 @@ def main():
 
     import torch
     from paper_2012_07266_amd import Simulation
+    from paper_2012_07266_amd._lib import PM_MODE_PGD
 
     torch.cuda.set_device(0)
     dev = torch.device("cuda", 0)
-    stream = torch.cuda.current_stream()
     noise = torch.from_numpy(W.white_noise(wl.np_side, wl.seed)).to(dev, torch.float32)
     a = wl.a_grid()
-    from paper_2012_07266_amd._lib import PM_MODE_PGD
     sim = Simulation(wl.np_side, wl.nm_side, wl.box, wl.npix, wl.fov_deg, wl.z_src,
                      dtype=torch.float32, modes=0 if args.no_interpolation else PM_MODE_PGD,
                      omega_m=wl.omega_m, sigma8=wl.sigma8, h=wl.h,
@@ -453,59 +513,88 @@ def main():
             k -= m
         return i
 
-    if args.calibrate_copy:
+    if args.traffic_step is not None:
+        s0 = args.traffic_step
+        sim.init_ic(noise, a[0])
+        kappa.zero_()
+        run_steps(s0, 0)
         src = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        dst.copy_(src)  # the calibration copy, and the marker before the counted steps
+        run_steps(2, s0)
         torch.cuda.synchronize()
-        del src, dst
+        sim.close()
+        print(json.dumps({"traffic_step": s0, "workload": wl.name}))
+        return
+
+    # the timed window: the last K steps of the schedule (all of it, and
+    # restarts, when K exceeds it); the steps before it run untimed
+    K = args.steps
+    prefix = wl.nsteps - K if K <= wl.nsteps else 0
+
+    def timed_window(profile=False, only=None):
+        """Fresh initial conditions, the untimed prefix, then the timed K
+        steps; seconds, or with `profile` the per-kernel event table of the
+        window (every kernel, or `only` that one, recorded)."""
+        sim.init_ic(noise, a[0])
+        kappa.zero_()
+        run_steps(prefix, 0)
+        sim.sync()
+        if profile:
+            sim.profile_only(only)
+            sim.profile(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run_steps(K, prefix)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        if profile:
+            prof = sim.profile_read()
+            sim.profile(False)
+            sim.profile_only(None)
+            return prof if only is None else (t1 - t0, prof)
+        return t1 - t0
+
     sim.init_ic(noise, a[0])
     run_steps(args.warmup, 0)
     prof = {}
     dom = None
     if not args.no_profile:
-        # Per-kernel table: an untimed pass over the same steps with events
-        # around every launch.  The events cost time between kernels, so the
-        # timed pass below records only the dominant kernel, for its roofline.
-        sim.init_ic(noise, a[0])
-        kappa.zero_()
-        sim.sync()
-        sim.profile(True)
-        run_steps(args.steps, 0)
-        sim.sync()
-        prof = sim.profile_read()
-        sim.profile(False)
+        # per-kernel table: an untimed pass of the window with events around
+        # every launch (they cost time between kernels, so the timed repeats
+        # below record only the dominant kernel)
+        prof = timed_window(profile=True)
         dom = max(prof, key=lambda k: prof[k][0])
-    sim.init_ic(noise, a[0])
-    kappa.zero_()
-    sim.sync()
-    if dom:
-        sim.profile_only(dom)
-        sim.profile(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    run_steps(args.steps, 0)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    sim.sync()
-    prof_dom = {}
-    if dom:
-        prof_dom = sim.profile_read()
-        sim.profile(False)
-        sim.profile_only(None)
-    elapsed = t1 - t0
-    ps = wl.np_side ** 3 * args.steps / elapsed
+    times = []
+    dom_ms, dom_cnt = 0.0, 0
+    for _ in range(max(1, args.repeats)):
+        if dom:
+            t, pd = timed_window(profile=True, only=dom)
+            ms, cnt = pd.get(dom, (0.0, 0))
+            dom_ms += ms
+            dom_cnt += cnt
+        else:
+            t = timed_window()
+        times.append(t)
+    elapsed = float(np.median(times))
+    ps = wl.np_side ** 3 * K / elapsed
+    ms_step = 1e3 * elapsed / K
 
     out = {
         "metric": "particle-steps/s at 256^3 (PM+lens) + HBM GB/s; p50/p99 served-sim latency",
-        "value": ps, "unit": "particle-steps/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": 1e3 * elapsed / args.steps,
+        "value": ps, "unit": "particle-steps/s", "n_gpus": 1, "steps": K,
+        "warmup": args.warmup, "ms_per_step": ms_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32", "data": "synthetic",
         "config": {"workload": wl.name, "np": wl.np_side, "nm": wl.nm_side, "box": wl.box,
                    "a_range": [wl.a_start, wl.a_end], "nsteps_schedule": wl.nsteps,
+                   "timed_steps": [prefix, prefix + K - 1] if K <= wl.nsteps else "restarts",
                    "maps": f"{len(wl.z_src)}x{wl.npix}^2 over {wl.fov_deg} deg",
                    "z_src": list(wl.z_src)},
+        "repeats_ms_per_step": [1e3 * t / K for t in times],
+        "timing": (f"median of {len(times)} repeats, each from fresh initial conditions with "
+                   f"steps 0..{prefix - 1} untimed and steps {prefix}..{prefix + K - 1} timed"
+                   if prefix else f"median of {len(times)} repeats of steps 0..{K - 1}"),
     }
     if prof:
         alg = algorithmic_bytes(wl)
@@ -520,27 +609,52 @@ def main():
                           "alg_gbs": (b / (avg * 1e-3) / 1e9) if avg > 0 and b else None}
             total_ms += ms
             total_bytes += b * cnt
-        # the dominant kernel's launches inside the timed region
-        ms_d, cnt_d = prof_dom.get(dom, (0.0, 0))
-        avg_d = ms_d / max(cnt_d, 1)
-        b_d = alg.get(dom, 0)
+        # the dominant kernel's launches inside the timed repeats
+        avg_d = dom_ms / max(dom_cnt, 1)
+        b_d = model_bytes(wl).get(dom, alg.get(dom, 0))
+        b_own = alg.get(dom, 0)
         gbs_d = (b_d / (avg_d * 1e-3) / 1e9) if avg_d > 0 and b_d else None
-        out["roofline"] = {"kernel": dom, "bound": "hbm", "achieved": gbs_d,
-                           "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": gbs_d / HBM_PEAK_GBS if gbs_d else None,
-                           "traffic": load_traffic(dom, wl.name),
-                           "avg_ms": avg_d, "launches": cnt_d}
+        tr = load_traffic(wl.name)
+        t_ent = tr.get(dom) if tr else None
+        out["roofline"] = {
+            "kernel": dom, "bound": "hbm", "achieved": gbs_d, "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": gbs_d / HBM_PEAK_GBS if gbs_d else None,
+            "traffic": t_ent["bytes_per_launch"] if t_ent and t_ent["current"] else None,
+            "avg_ms": avg_d, "launches": dom_cnt,
+            "algorithmic_bytes": b_d,
+            "algorithmic_bytes_what": "3 M + 48 P: three force meshes, position and momentum "
+                                      "read and written",
+            "achieved_own_bytes": (b_own / (avg_d * 1e-3) / 1e9) if avg_d > 0 and b_own else None,
+            "own_bytes": b_own,
+            "own_bytes_what": "3 M + 56 P: the kernel's own arrays, with the particle id read "
+                              "and the next step's sort key written"}
         out["hbm_effective_gbs_all_kernels"] = total_bytes / (total_ms * 1e-3) / 1e9
+        kern_ms_step = total_ms / K
+        if tr and "_step_bytes" in tr:
+            stale = sorted(k for k, v in tr.items() if not k.startswith("_") and not v["current"])
+            sb = tr["_step_bytes"]
+            out["step_hbm"] = {
+                "counter_bytes_per_step": sb, "counted_step": tr["_step"],
+                "achieved_gbs_wall": sb / (ms_step * 1e-3) / 1e9,
+                "frac_wall": sb / (ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                "achieved_gbs_kernel_time": sb / (kern_ms_step * 1e-3) / 1e9,
+                "frac_kernel_time": sb / (kern_ms_step * 1e-3) / 1e9 / HBM_PEAK_GBS,
+                "gate": STEP_GATE, "stale_kernels": stale,
+                "what": ("rocprofv3 FETCH_SIZE + WRITE_SIZE of every dispatch of one steady-state "
+                         "step late in the schedule (profiles/traffic.json), divided by the "
+                         "median ms per step of the timed window (wall) and by the summed "
+                         "kernel time per step of the profiled pass")}
         out["kernels"] = kern
-        out["kernels_note"] = ("per-kernel table from an untimed pass over the same steps "
-                               "with events around every launch; the timed pass records "
+        out["kernels_note"] = ("per-kernel table from an untimed pass over the same window "
+                               "with events around every launch; the timed repeats record "
                                "only the roofline's kernel")
-    # the same schedule with sub-evolution projection (pm_set_interpolation)
+
+    def mode_window(profile=False):
+        return timed_window(profile=profile)
     if not args.no_interpolation:
-        out["interpolation"] = mode_bench(sim, noise, a, kappa, run_steps, wl, args.steps,
-                                          "interpolation")
-        out["pgd"] = mode_bench(sim, noise, a, kappa, run_steps, wl, args.steps, "pgd")
-        out["rotation"] = mode_bench(sim, noise, a, kappa, run_steps, wl, args.steps, "rotation")
+        out["interpolation"] = mode_bench(sim, mode_window, wl, K, "interpolation")
+        out["pgd"] = mode_bench(sim, mode_window, wl, K, "pgd")
+        out["rotation"] = mode_bench(sim, mode_window, wl, K, "rotation")
     if not args.no_gradient:
         out["gradient"] = gradient_bench()
     if not args.no_serving:

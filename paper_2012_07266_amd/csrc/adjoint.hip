@@ -435,6 +435,8 @@ __global__ __launch_bounds__(256) void k_lens_vjp(Parts<T> p, Geo g, LensArgs<T>
         int li[3];
         lattice_of_l(id, g.np, li);
         T u[3];
+        int cz = 0;   // axis 2 as an integer cell and a fraction (membership)
+        T fz = T(0);
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             T v = T(0.5) + p.disp[a * n + k];
@@ -442,6 +444,10 @@ __global__ __launch_bounds__(256) void k_lens_vjp(Parts<T> p, Geo g, LensArgs<T>
             int c = g.B * li[a] + (int)fl;
             if ((unsigned)c >= (unsigned)g.nm) c = pmod(c, g.nm);
             u[a] = T(c) + (v - fl);
+            if (a == 2) {
+                cz = c;
+                fz = v - fl;
+            }
         }
         if (!(isfinite(u[0]) && isfinite(u[1]) && isfinite(u[2]))) continue;
         T gx = 0, gy = 0, gz = 0;
@@ -479,7 +485,13 @@ __global__ __launch_bounds__(256) void k_lens_vjp(Parts<T> p, Geo g, LensArgs<T>
                         }
                         T rx = ui[0] + T(nx) * nmf - half, ry = ui[1] + T(ny) * nmf - half;
                         T rz = ui[2] + T(nz) * nmf;
-                        if (!(rz > cnear && rz <= cfar && rz > T(0))) continue;
+                        int cr = cz;
+                        T fr = fz;
+                        if (sym) split_cell(ui[2], cr, fr);
+                        if (!depth_in_shell(cr, fr, zbound<T>(la.cnear_d, nz, g.nm),
+                                            zbound<T>(la.cfar_d, nz, g.nm)) ||
+                            !(rz > T(0)))
+                            continue;
                         T dr = T(0), ddr = T(0), de = T(0);
                         T chi_e = rz * la.cell;
                         if (la.sub) {
@@ -538,7 +550,10 @@ __global__ __launch_bounds__(256) void k_lens_vjp(Parts<T> p, Geo g, LensArgs<T>
         int nz1 = (int)floor((cfar - u[2]) / nmf) + 1;
         for (int nz = nz0; nz <= nz1; ++nz) {
             T rz = u[2] + T(nz) * nmf;
-            if (!(rz > cnear && rz <= cfar && rz > T(0))) continue;
+            if (!depth_in_shell(cz, fz, zbound<T>(la.cnear_d, nz, g.nm),
+                                zbound<T>(la.cfar_d, nz, g.nm)) ||
+                !(rz > T(0)))
+                continue;
             T chi = rz * la.cell;
             if (chi >= chi_max_src) continue;
             T inv = la.inv_dtheta / rz;
@@ -817,6 +832,8 @@ __global__ __launch_bounds__(256) void k_lens_jvp(Parts<T> p, Geo g, LensArgs<T>
         int li[3];
         lattice_of_l(id, g.np, li);
         T u[3];
+        int cz = 0;   // axis 2 as an integer cell and a fraction (membership)
+        T fz = T(0);
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             T v = T(0.5) + p.disp[a * n + k];
@@ -824,6 +841,10 @@ __global__ __launch_bounds__(256) void k_lens_jvp(Parts<T> p, Geo g, LensArgs<T>
             int c = g.B * li[a] + (int)fl;
             if ((unsigned)c >= (unsigned)g.nm) c = pmod(c, g.nm);
             u[a] = T(c) + (v - fl);
+            if (a == 2) {
+                cz = c;
+                fz = v - fl;
+            }
         }
         if (!(isfinite(u[0]) && isfinite(u[1]) && isfinite(u[2]))) continue;
         const T xb[3] = {xdot[k], xdot[n + k], xdot[2 * n + k]};
@@ -866,7 +887,13 @@ __global__ __launch_bounds__(256) void k_lens_jvp(Parts<T> p, Geo g, LensArgs<T>
                         }
                         T rx = ui[0] + T(nx) * nmf - half, ry = ui[1] + T(ny) * nmf - half;
                         T rz = ui[2] + T(nz) * nmf;
-                        if (!(rz > cnear && rz <= cfar && rz > T(0))) continue;
+                        int cr = cz;
+                        T fr = fz;
+                        if (sym) split_cell(ui[2], cr, fr);
+                        if (!depth_in_shell(cr, fr, zbound<T>(la.cnear_d, nz, g.nm),
+                                            zbound<T>(la.cfar_d, nz, g.nm)) ||
+                            !(rz > T(0)))
+                            continue;
                         if (la.sub) {
                             const T chi_e = rz * la.cell;
                             T de, dd;
@@ -897,7 +924,10 @@ __global__ __launch_bounds__(256) void k_lens_jvp(Parts<T> p, Geo g, LensArgs<T>
             const int nz1 = (int)floor((cfar - u[2]) / nmf) + 1;
             for (int nz = nz0; nz <= nz1; ++nz) {
                 const T rz = u[2] + T(nz) * nmf;
-                if (!(rz > cnear && rz <= cfar && rz > T(0))) continue;
+                if (!depth_in_shell(cz, fz, zbound<T>(la.cnear_d, nz, g.nm),
+                                    zbound<T>(la.cfar_d, nz, g.nm)) ||
+                    !(rz > T(0)))
+                    continue;
                 const T chi = rz * la.cell;
                 if (chi >= chi_max_src) continue;
                 const T rmax = tmax * rz / la.inv_dtheta;

@@ -794,6 +794,8 @@ template <class T> struct Sim final : SimBase {
         if (chi_near >= chis_max) return PM_OK;
         la.chi_near = (T)chi_near;
         la.chi_far = (T)chi_far;
+        la.cnear_d = chi_near / cell;
+        la.cfar_d = chi_far / cell;
         double dth = fov * PI / 180.0 / npix;
         la.inv_dtheta = (T)(1.0 / dth);
         double vp = std::pow(P.box / P.np, 3);
@@ -1136,6 +1138,8 @@ template <class T> struct Sim final : SimBase {
         if (chi_near >= chis_max) return false;
         la.chi_near = (T)chi_near;
         la.chi_far = (T)chi_far;
+        la.cnear_d = chi_near / cell;
+        la.cfar_d = chi_far / cell;
         double dth = fov * PI / 180.0 / npix;
         la.inv_dtheta = (T)(1.0 / dth);
         double vp = std::pow(P.box / P.np, 3);

@@ -247,6 +247,7 @@ __global__ __launch_bounds__(LG) void k_lens_gather(Parts<T> p, SortBufs sb, Geo
         T zlo = max(cnear - T(nz) * nmf, -zclip), zhi = min(cmax - T(nz) * nmf, nmf + zclip);
         if (!(zlo < zhi)) continue;
         T ca = zlo + T(nz) * nmf, cb = zhi + T(nz) * nmf;  // depth range, cells
+        const ZBound<T> zb_near = zbound<T>(la.cnear_d, nz, nm), zb_far = zbound<T>(la.cfar_d, nz, nm);
         T x0lo = min(a0lo * ca, a0lo * cb) - margin, x0hi = max(a0hi * ca, a0hi * cb) + margin;
         T x1lo = min(a1lo * ca, a1lo * cb) - margin, x1hi = max(a1hi * ca, a1hi * cb) + margin;
         // sort blocks (KZ cells deep) along axis 2 that the replica's depth
@@ -344,6 +345,8 @@ __global__ __launch_bounds__(LG) void k_lens_gather(Parts<T> p, SortBufs sb, Geo
                                 int li[3];
                                 lattice_of_l(idv[u], g.np, li);
                                 T uu[3];
+                                int cz = 0;
+                                T fz = T(0);
 #pragma unroll
                                 for (int a = 0; a < 3; ++a) {
                                     T v = T(0.5) + dv[u][a];
@@ -351,6 +354,10 @@ __global__ __launch_bounds__(LG) void k_lens_gather(Parts<T> p, SortBufs sb, Geo
                                     int c = g.B * li[a] + (int)fl;
                                     if ((unsigned)c >= (unsigned)nm) c = pmod(c, nm);
                                     uu[a] = T(c) + (v - fl);
+                                    if (a == 2) {
+                                        cz = c;
+                                        fz = v - fl;
+                                    }
                                 }
                                 T pimg[3] = {T(0), T(0), T(0)};
                                 if constexpr (EXT) {
@@ -367,9 +374,10 @@ __global__ __launch_bounds__(LG) void k_lens_gather(Parts<T> p, SortBufs sb, Geo
                                         sym_apply(sym, uu, nmf, false);
                                         sym_apply(sym, pimg, T(0), true);
                                     }
+                                    if (sym || la.shift) split_cell(uu[2], cz, fz);
                                 }
                                 T rz = uu[2] + T(nz) * nmf;
-                                if (!(rz > cnear && rz <= cfar && rz > T(0))) continue;
+                                if (!depth_in_shell(cz, fz, zb_near, zb_far) || !(rz > T(0))) continue;
                                 if (EXT && la.sub) {
                                     // along the step's drift to a(chi) of the
                                     // end-of-step depth

@@ -155,6 +155,7 @@ template <class T> struct LensArgs {
     int npix, nsrc;
     T cell;             // mesh cell size, Mpc/h
     T chi_near, chi_far;
+    double cnear_d, cfar_d;  // the shell's depth bounds in cells, float64 (membership)
     T inv_dtheta;       // 1 / pixel size (radians)
     T wbase;            // 3/2 Om (H0/c)^2 V_p / Omega_pix
     T chi_src[MAX_SRC];
@@ -185,6 +186,38 @@ template <class T> struct LensArgs {
     unsigned long long rot_seed;
 };
 template <class T> struct MapAdd { T v[MAX_SRC]; };
+
+// Shell membership.  An image's depth is its in-box coordinate along axis 2,
+// an integer cell c plus a fraction f in [0, 1), plus nz Nm for replica nz.
+// A depth bound (float64 cells) is moved into the replica's box and split the
+// same way, so that comparing the pairs decides "depth > bound" exactly for
+// the stored position, whatever the size of nz Nm: a float32 depth of ~2000
+// cells would carry 1e-4 cells of rounding, far above the positions' own
+// accuracy, and an image that changes sides moves its whole weight from one
+// shell to the next.
+template <class T> struct ZBound {
+    int c;
+    T f;
+};
+template <class T>
+__device__ __forceinline__ ZBound<T> zbound(double b, int nz, int nm) {
+    const double r = b - (double)nz * (double)nm;
+    const double fl = floor(r);
+    return {(int)fl, (T)(r - fl)};
+}
+template <class T>
+__device__ __forceinline__ bool depth_in_shell(int c, T f, ZBound<T> lo, ZBound<T> hi) {
+    const bool above = c > lo.c || (c == lo.c && f > lo.f);
+    const bool at_most = c < hi.c || (c == hi.c && f <= hi.f);
+    return above && at_most;
+}
+// The (cell, fraction) split of a float in-box coordinate.
+template <class T>
+__device__ __forceinline__ void split_cell(T u, int& c, T& f) {
+    const T fl = floor(u);
+    c = (int)fl;
+    f = u - fl;
+}
 // Region-driven projection (each pixel written by one workgroup) that also
 // adds mean.v[s] to every pixel of map s.  Particles must be tile-sorted.
 template <class T>

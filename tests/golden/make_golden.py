@@ -29,7 +29,8 @@ inside the GPU test suite:
               serving ranges (Omega_m in [0.25, 0.35], sigma_8 in [0.7,
               0.9]) and a seeded request noise; the noise is the
               oracle's own implementation of the counter-based generator
-              the library draws on the device.  Stores the map.
+              the library draws on the device.  Stores the map and the
+              final positions of every 128th particle.
 """
 from __future__ import annotations
 
@@ -56,6 +57,7 @@ GRAD_TARGET_SEED, GRAD_PIXEL_SEED, GRAD_SIGMA = 4, 5, 0.01
 GRAD_NOISE_STRIDE, GRAD_MAP_STRIDE = 8, 16
 SERVED192 = W.Workload("served192", 192, 384, 192.0, 0.1, 1.0, 10, 512, 2.0, (1.0,),
                        omega_m=0.3137, sigma8=0.7461, seed=1000 + 192)
+SERVED192_STRIDE = 128     # particles stored: every 128th in lattice order
 
 
 def path(name):
@@ -111,8 +113,10 @@ def make_served192():
     c = cosmo_of(wl)
     geom = lens.MapGeometry(wl.npix, wl.fov_deg, wl.z_src, c)
     noise = rng.white_noise(wl.np_side, wl.seed)
-    kappa, _, _ = lens.run_lensing(noise, c, wl.box, wl.nm_side, wl.a_grid(), geom)
-    np.savez_compressed(path(wl.name), kappa=kappa.astype(np.float32))
+    kappa, x, _ = lens.run_lensing(noise, c, wl.box, wl.nm_side, wl.a_grid(), geom)
+    s = SERVED192_STRIDE
+    np.savez_compressed(path(wl.name), kappa=kappa.astype(np.float32), x_sample=x[:, ::s],
+                        stride=s)
 
 
 CASES = {"schedule40": make_schedule40, "grad": make_grad, "served192": make_served192}

@@ -148,22 +148,26 @@ def _exact_grid(v, cell):
 
 
 @pytest.mark.timeout(900)
-def test_largest_mesh_replicated_configuration():
-    """The largest mesh (1024^3, 512^3 particles, float32) against the
-    benchmark-size path: a configuration repeated 2 x 2 x 2 in a box twice
-    as large has, node for node and particle for particle, the density, the
-    force and the step of one copy.  (The transform of the repeated field
-    lives on even modes, where the doubled box's Green's function equals
-    the original's.)  Positions and momenta sit on a 1/64-cell grid, so both
-    sides get bit-identical CIC weights and differ only in FFT rounding."""
-    L, np_s, nm_s = 205.0, 256, 512
+@pytest.mark.parametrize("copy", [(205.0, 256, 512), (192.0, 192, 384)],
+                         ids=["1024m_from_512m", "768m_from_384m"])
+def test_largest_mesh_replicated_configuration(copy):
+    """The largest meshes (1024^3 with 512^3 particles; 768^3 with 384^3,
+    radix 3), float32, against the path at half their size: a configuration
+    repeated 2 x 2 x 2 in a box twice as large has, node for node and
+    particle for particle, the density, the force and the step of one copy.
+    (The transform of the repeated field lives on even modes, where the
+    doubled box's Green's function equals the original's.)  Positions and
+    momenta sit on a 1/64-cell grid, so both sides get bit-identical CIC
+    weights and differ only in FFT rounding.  The copies (512^3 and 384^3
+    meshes) are themselves held against the oracle in test_gpu_parity.py."""
+    L, np_s, nm_s = copy
     cell = L / nm_s
     n = np_s ** 3
     x = _exact_grid(W.clustered_positions(np_s, nm_s, L, seed=66), cell)
     x = np.mod(x, L)
     p = _exact_grid(W.random_momenta(n, 1.0, seed=67), cell)
     a0, a1 = 0.5, 0.52
-    log("edge replicated: 256^3/512^3 copy")
+    log(f"edge replicated: {np_s}^3/{nm_s}^3 copy")
     with new_sim(_wl(np_s, nm_s, L), torch.float32) as sim:
         sim.set_state(torch.from_numpy(x.astype(np.float32)),
                       torch.from_numpy(p.astype(np.float32)), a0)
@@ -177,7 +181,7 @@ def test_largest_mesh_replicated_configuration():
         off = np.array([(c >> 2) & 1, (c >> 1) & 1, c & 1], dtype=np.float32)[:, None] * L
         xb[:, c * n:(c + 1) * n] = x32 + off
     pb = np.tile(p32, (1, 8))
-    log("edge replicated: 512^3/1024^3 repeated")
+    log(f"edge replicated: {2 * np_s}^3/{2 * nm_s}^3 repeated")
     with new_sim(_wl(2 * np_s, 2 * nm_s, 2 * L), torch.float32) as sim:
         sim.set_state(torch.from_numpy(xb), torch.from_numpy(pb), a0)
         del xb, pb

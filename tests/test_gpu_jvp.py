@@ -7,7 +7,7 @@ import pytest
 import torch
 
 import workloads as W
-from paper_2012_07266_amd._lib import PM_MODE_TANGENT
+from paper_2012_07266_amd._lib import PM_MODE_PGD, PM_MODE_TANGENT
 from tests.gpu_util import cosmo_of, log, new_sim, rel_rms, to_np
 
 pytestmark = pytest.mark.gpu
@@ -225,7 +225,12 @@ def test_tangent_error_paths():
         with pytest.raises(MadlensError) as e:
             fn(*args)
         return e.value.code
-    with new_sim(wl, modes=PM_MODE_TANGENT) as sim:
+    with new_sim(wl) as sim:                                  # no tangent buffers
+        sim.init_ic(noise, 0.4)
+        assert code(sim.init_ic_jvp, noise) == PM_EINVAL
+        assert code(sim.set_tangent, z(), z()) == PM_EINVAL
+        sim.sync()
+    with new_sim(wl, modes=PM_MODE_TANGENT | PM_MODE_PGD) as sim:
         assert code(sim.init_ic_jvp, noise) == PM_ESTATE     # no initial conditions yet
         sim.init_ic(noise, 0.4)
         assert code(sim.step_jvp, 0.4, 0.5) == PM_ESTATE     # no tangent yet

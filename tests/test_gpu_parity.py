@@ -72,6 +72,24 @@ def test_density_force_readout(dtype, shape):
     assert e_acc <= _tol(dtype, 1e-12, 2e-5)
 
 
+# Radix-3 lengths of the serving sizes and of the 768^3 mesh: meshes of 192
+# and 384 (float32 only: the float64 instantiation stops at 256).
+RADIX3_SHAPES = [(96, 192, 120.0), (192, 384, 192.0)]
+
+
+@pytest.mark.parametrize("shape", RADIX3_SHAPES, ids=lambda s: f"{s[0]}p{s[1]}m")
+def test_density_force_readout_radix3_lengths(shape):
+    test_density_force_readout(torch.float32, shape)
+
+
+@pytest.mark.parametrize("shape", [(192, 384, 192.0), (384, 768, 384.0)],
+                         ids=lambda s: f"{s[0]}p{s[1]}m")
+def test_zeldovich_ic_radix3_lengths(shape):
+    """Initial conditions transformed on the particle lattice at lengths 192
+    and 384 (the 768^3 mesh's lattice), float32."""
+    test_zeldovich_ic(torch.float32, shape)
+
+
 @pytest.mark.parametrize("dtype", DTYPES, ids=["f64", "f32"])
 @pytest.mark.parametrize("shape", [(16, 32, 40.0), (32, 32, 64.0), (48, 96, 100.0)],
                          ids=lambda s: f"{s[0]}p{s[1]}m")
@@ -90,9 +108,11 @@ def test_zeldovich_ic(dtype, shape):
     x, p = pm.zeldovich_ic(noise, c, box, nm, a0)
     err = periodic_cells(xg - x, box, nm)
     log(f"ic {shape} {dtype}: pos max {err.max():.2e} cells, mom rel-rms {rel_rms(pg, p):.2e}")
-    # float32 output positions alone carry half an ulp of the box coordinate,
-    # about 3e-8 Nm cells
-    assert err.max() <= _tol(dtype, 1e-10, 2e-5)
+    # float32 output positions alone carry half an ulp of the box coordinate
+    # (1.5e-5 Mpc/h = 3e-5 cells for coordinates in [256, 384) on the 768^3
+    # mesh), on top of the displacement's own rounding
+    half_ulp = 0.5 * float(np.spacing(np.float32(box))) / (box / nm)
+    assert err.max() <= _tol(dtype, 1e-10, max(2e-5, half_ulp + 1e-5))
     assert rel_rms(pg, p) <= _tol(dtype, 1e-12, 1e-5)
 
 
