@@ -52,6 +52,7 @@ extern "C" {
 #define PM_ESTATE      -4   /* the simulation is not in the required state   */
 #define PM_ENONFINITE  -5   /* a kernel produced a non-finite position       */
 #define PM_EAGAIN      -7   /* not finished yet (serving)                    */
+#define PM_ETOOBIG     -8   /* beyond pm_run_noalloc's static scratch        */
 
 #define PM_F32 0
 #define PM_F64 1
@@ -460,6 +461,28 @@ int pm_srv_stats_get(pm_srv* s, pm_srv_stats* out);
 
 /* Drop queued requests, let running ones finish, free every arena. */
 int pm_srv_destroy(pm_srv* s);
+
+/* ---- a run that allocates nothing -------------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one whole
+ * simulation, the same as pm_create, pm_init_ic(noise, a_grid[0]),
+ * pm_run(a_grid, nsteps, kappa) and pm_destroy, with the arena placed in a
+ * static device array of PM_NOALLOC_MAX_BYTES that the library holds on
+ * every GPU it runs on until the process ends (a 64^3-particle, 128^3-mesh
+ * float32 simulation needs 51 MiB).  No device memory is allocated or freed.
+ * The call first waits for hip_stream (NULL = the default stream), whose
+ * earlier calls may still use the array, uploads the host-side tables, and
+ * returns with the run enqueued on hip_stream for the current device.  noise: device [Np^3] of dtype (read); kappa: device
+ * [nsrc][npix][npix] of dtype, ACCUMULATED.  Every call on one GPU uses the
+ * same array, so calls that overlap on one GPU (other streams, other host
+ * threads) race; each call sets up everything it reads (the histogram, the
+ * status word and the reverse-pass accumulator are cleared by kernels).
+ * Errors: PM_EINVAL (invalid parameters, modes != 0, NULL pointer,
+ * nsteps < 1, a0 as for pm_init_ic), PM_ETOOBIG (the arena, pm_footprint,
+ * exceeds PM_NOALLOC_MAX_BYTES), PM_EDEVICE. */
+#define PM_NOALLOC_MAX_BYTES (64u << 20)
+int pm_run_noalloc(const pm_params* p, const lens_params* l, void* hip_stream, const void* noise,
+                   const double* a_grid, int32_t nsteps, void* kappa);
 
 const char* pm_strerror(int code);
 

@@ -12,8 +12,9 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libmadlens_amd.so")
 
-PM_OK, PM_EINVAL, PM_ENOMEM, PM_EDEVICE, PM_ESTATE, PM_ENONFINITE, PM_EAGAIN = \
-    0, -1, -2, -3, -4, -5, -7
+PM_OK, PM_EINVAL, PM_ENOMEM, PM_EDEVICE, PM_ESTATE, PM_ENONFINITE, PM_EAGAIN, PM_ETOOBIG = \
+    0, -1, -2, -3, -4, -5, -7, -8
+PM_NOALLOC_MAX_BYTES = 64 << 20
 PM_F32, PM_F64 = 0, 1
 PM_MODE_PGD, PM_MODE_TANGENT = 1, 2
 
@@ -92,6 +93,8 @@ SIGNATURES = {
     "pm_srv_result": (_I, [_P, ctypes.c_int64, _P, ctypes.POINTER(_D)]),
     "pm_srv_stats_get": (_I, [_P, ctypes.POINTER(PmSrvStats)]),
     "pm_srv_destroy": (_I, [_P]),
+    "pm_run_noalloc": (_I, [ctypes.POINTER(PmParams), ctypes.POINTER(LensParams), _P, _P,
+                            ctypes.POINTER(_D), ctypes.c_int32, _P]),
     "pm_strerror": (ctypes.c_char_p, [_I]),
 }
 

@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -310,8 +311,10 @@ template <class T> struct Sim final : SimBase {
     double cell = 0;  // mesh cell, Mpc/h
     int ntiles = 0;
 
+    bool own_arena = true;  // false: the arena is the static scratch array
+
     ~Sim() override {
-        if (arena) (void)hipFree(arena);
+        if (arena && own_arena) (void)hipFree(arena);
     }
 
     template <class U> U* at(size_t off) { return reinterpret_cast<U*>(arena + off); }
@@ -343,7 +346,9 @@ template <class T> struct Sim final : SimBase {
         meshes_valid = false;
     }
 
-    int create(const pm_params* p, const lens_params* l, void* stream) {
+    // mem: device memory of at least plan_arena's size to hold the arena
+    // (not owned); NULL allocates it.
+    int create(const pm_params* p, const lens_params* l, void* stream, void* mem = nullptr) {
         st = reinterpret_cast<hipStream_t>(stream);
         set_physics(p, l);
         geo.np = p->np;
@@ -354,7 +359,10 @@ template <class T> struct Sim final : SimBase {
         geo.npart = (long)p->np * p->np * p->np;
         ntiles = geo.nt * geo.nt * geo.nkz;  // sort blocks (keys)
         ap = plan_arena(*p, *l, sizeof(T));
-        if (hipMalloc(&arena, ap.total) != hipSuccess) {
+        if (mem) {
+            arena = static_cast<char*>(mem);
+            own_arena = false;
+        } else if (hipMalloc(&arena, ap.total) != hipSuccess) {
             arena = nullptr;
             (void)hipGetLastError();
             return PM_ENOMEM;
@@ -1398,7 +1406,65 @@ struct pm_sim {
     int dtype;
 };
 
+namespace {
+
+// The arena of pm_run_noalloc: a file-scope device array, one copy per GPU
+// the library runs on, held until the process ends.  In host code its name
+// is a host-side stand-in; the device address of each GPU's copy comes from
+// hipGetSymbolAddress, taken once per device (with that device current) on
+// the entry point's first call there, and only that address is passed on.
+__device__ __align__(256) unsigned char scratch[PM_NOALLOC_MAX_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void* scratch_ptr[MAX_DEVICES] = {};
+
+int scratch_for_current_device(void** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return PM_EDEVICE;
+    std::lock_guard<std::mutex> lk(scratch_mu);
+    if (!scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            return PM_EDEVICE;
+        }
+        scratch_ptr[dev] = ptr;
+    }
+    *out = scratch_ptr[dev];
+    return PM_OK;
+}
+
+template <class T>
+int run_noalloc_t(const pm_params* p, const lens_params* l, void* stream, const void* noise,
+                  const double* a_grid, int32_t nsteps, void* kappa) {
+    void* mem = nullptr;
+    int rc = scratch_for_current_device(&mem);
+    if (rc) return rc;
+    // the previous call on this stream may still read the array: the table
+    // uploads below are ordered with the host, not with the stream
+    if (hipStreamSynchronize(reinterpret_cast<hipStream_t>(stream)) != hipSuccess) return PM_EDEVICE;
+    Sim<T> sim;
+    if ((rc = sim.create(p, l, stream, mem))) return rc;
+    if ((rc = sim.init_ic(noise, a_grid[0]))) return rc;
+    return sim.run(a_grid, nsteps, kappa);
+}
+
+}  // namespace
+
 extern "C" {
+
+int pm_run_noalloc(const pm_params* p, const lens_params* l, void* hip_stream, const void* noise,
+                   const double* a_grid, int32_t nsteps, void* kappa) {
+    int rc = validate(p, l);
+    if (rc) return rc;
+    if (p->modes != 0 || !noise || !a_grid || !kappa || nsteps < 1) return PM_EINVAL;
+    if (plan_arena(*p, *l, p->dtype == PM_F64 ? 8 : 4).total > PM_NOALLOC_MAX_BYTES)
+        return PM_ETOOBIG;
+    return p->dtype == PM_F32
+               ? run_noalloc_t<float>(p, l, hip_stream, noise, a_grid, nsteps, kappa)
+               : run_noalloc_t<double>(p, l, hip_stream, noise, a_grid, nsteps, kappa);
+}
 
 size_t pm_footprint(const pm_params* p, const lens_params* l) {
     if (validate(p, l) != PM_OK) return 0;
@@ -1560,6 +1626,8 @@ const char* pm_strerror(int code) {
         case PM_ESTATE: return "simulation is not in the required state";
         case PM_ENONFINITE: return "non-finite particle position";
         case PM_EAGAIN: return "not finished yet";
+        case PM_ETOOBIG:
+            return "arena larger than the static scratch of the non-allocating entry point";
         default: return "unknown error";
     }
 }

@@ -343,3 +343,20 @@ class Simulation:
         out = (ctypes.c_double * 3)()
         check(lib().pm_background(self._h, float(a), out), "pm_background")
         return tuple(out)
+
+
+def run_noalloc(noise: torch.Tensor, a_grid, kappa: torch.Tensor, np_side, nm_side, box, npix,
+                fov_deg, z_src, *, dtype=torch.float32, stream: Optional[torch.cuda.Stream] = None,
+                **cosmo):
+    """One whole simulation through pm_run_noalloc: initial conditions from
+    `noise`, the steps of `a_grid` and their shells accumulated into `kappa`,
+    with the arena in the library's static device scratch (nothing is
+    allocated; the tensors are the caller's)."""
+    st = stream if stream is not None else torch.cuda.current_stream()
+    p = make_params(np_side, nm_side, box, dtype=dtype, **cosmo)
+    l = make_lens(npix, fov_deg, z_src)
+    a = np.ascontiguousarray(a_grid, dtype=np.float64)
+    check(lib().pm_run_noalloc(ctypes.byref(p), ctypes.byref(l), ctypes.c_void_p(st.cuda_stream),
+                               _ptr(noise), a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                               len(a) - 1, _ptr(kappa)), "pm_run_noalloc")
+    return kappa
