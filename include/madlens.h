@@ -53,6 +53,7 @@ extern "C" {
 #define PM_ENONFINITE  -5   /* a kernel produced a non-finite position       */
 #define PM_EAGAIN      -7   /* not finished yet (serving)                    */
 #define PM_ETOOBIG     -8   /* beyond pm_run_noalloc's static scratch        */
+#define PM_EFULL       -9   /* every slot of a batch is taken                */
 
 #define PM_F32 0
 #define PM_F64 1
@@ -461,6 +462,57 @@ int pm_srv_stats_get(pm_srv* s, pm_srv_stats* out);
 
 /* Drop queued requests, let running ones finish, free every arena. */
 int pm_srv_destroy(pm_srv* s);
+
+/* ---- batched stepping ---------------------------------------------------------
+ * Many simulations of one shape (Np, Nm, dtype, npix, nsrc) stepped together,
+ * each with its own arena, cosmology, box, field of view, time grid and maps
+ * (the paper's use case of many fast simulations across cosmologies): one
+ * launch per pass of the fused step serves every slot of the batch, so small
+ * simulations fill the device together, and the launches are replayed from a
+ * HIP graph captured at the first step (kernel nodes only).  Each slot's
+ * arguments of every pass (its arena's pointers, the step's kick, drift and
+ * kick factors, the shell's bounds, lens weights and mean terms) live in a
+ * device parameter block that the batch rewrites before each replay (one
+ * host-to-device copy on the batch's stream), so the captured graph replays
+ * unchanged.  A slot's results are bit for bit those of pm_run on its handle
+ * (float32; float64 to round-off).
+ *
+ * pm_batch_create: shape from p and l (their cosmology, box and geometry are
+ * not used); capacity slots (1..1024); use_graph 0 launches the passes
+ * directly instead of replaying the graph; hip_stream (NULL: a stream of the
+ * batch's own) carries every batched launch.  Allocates the parameter block
+ * (device) and its two pinned host copies.  Errors: PM_EINVAL, PM_ENOMEM,
+ * PM_EDEVICE.
+ * pm_batch_attach: sim (same shape, no sub-evolution, PGD or rotation) must
+ * be at a_grid[0], its initial conditions made (pm_init_ic*); a_grid [0 ..
+ * nsteps] (host, copied) is its time grid.  Waits for the handle's stream,
+ * then enqueues the first step's half-kick, drift and sort keys on the
+ * batch's stream.  *slot_out (may be NULL) receives the slot.  Until
+ * pm_batch_detach the handle belongs to the batch (no other call on it).
+ * Errors: PM_EINVAL (NULL, shape or mode mismatch, attached already,
+ * invalid grid), PM_ESTATE (state not at a_grid[0]), PM_EFULL.
+ * pm_batch_lens: the maps (device [nsrc][npix][npix] of dtype, ACCUMULATED,
+ * caller-owned) into which the shells of sim's coming steps are projected;
+ * NULL projects none.  Errors: PM_EINVAL (not attached).
+ * pm_batch_step: one fused step (pm_run's: sort, paint, the Born projection
+ * of the step's shell, force, readout with the next step's half-kick, drift
+ * and keys) of every attached slot with steps left, asynchronous on the
+ * batch's stream; *running_out (may be NULL) receives the number of slots
+ * with steps left after it.  A slot whose last step this was is at the end
+ * of its time grid.
+ * pm_batch_detach: waits for the batch's stream and frees sim's slot; the
+ * handle then is at the end of its grid if it finished it, else between
+ * two steps, where only pm_init_ic*, pm_set_state or pm_checkpoint_load
+ * can continue it.  Errors: PM_EINVAL (not attached). */
+typedef struct pm_batch pm_batch;
+int pm_batch_create(const pm_params* p, const lens_params* l, int32_t capacity, int32_t use_graph,
+                    void* hip_stream, pm_batch** out);
+int pm_batch_attach(pm_batch* b, pm_sim* sim, const double* a_grid, int32_t nsteps,
+                    int32_t* slot_out);
+int pm_batch_lens(pm_batch* b, pm_sim* sim, void* kappa);
+int pm_batch_step(pm_batch* b, int32_t* running_out);
+int pm_batch_detach(pm_batch* b, pm_sim* sim);
+int pm_batch_destroy(pm_batch* b);
 
 /* ---- a run that allocates nothing -------------------------------------------
  * For callers that cannot allocate device memory (code under HIP graph

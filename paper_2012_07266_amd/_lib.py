@@ -14,6 +14,7 @@ LIB_PATH = os.path.join(HERE, "libmadlens_amd.so")
 
 PM_OK, PM_EINVAL, PM_ENOMEM, PM_EDEVICE, PM_ESTATE, PM_ENONFINITE, PM_EAGAIN, PM_ETOOBIG = \
     0, -1, -2, -3, -4, -5, -7, -8
+PM_EFULL = -9
 PM_NOALLOC_MAX_BYTES = 64 << 20
 PM_F32, PM_F64 = 0, 1
 PM_MODE_PGD, PM_MODE_TANGENT = 1, 2
@@ -93,6 +94,14 @@ SIGNATURES = {
     "pm_srv_result": (_I, [_P, ctypes.c_int64, _P, ctypes.POINTER(_D)]),
     "pm_srv_stats_get": (_I, [_P, ctypes.POINTER(PmSrvStats)]),
     "pm_srv_destroy": (_I, [_P]),
+    "pm_batch_create": (_I, [ctypes.POINTER(PmParams), ctypes.POINTER(LensParams), ctypes.c_int32,
+                             ctypes.c_int32, _P, ctypes.POINTER(_P)]),
+    "pm_batch_attach": (_I, [_P, _P, ctypes.POINTER(_D), ctypes.c_int32,
+                             ctypes.POINTER(ctypes.c_int32)]),
+    "pm_batch_lens": (_I, [_P, _P, _P]),
+    "pm_batch_step": (_I, [_P, ctypes.POINTER(ctypes.c_int32)]),
+    "pm_batch_detach": (_I, [_P, _P]),
+    "pm_batch_destroy": (_I, [_P]),
     "pm_run_noalloc": (_I, [ctypes.POINTER(PmParams), ctypes.POINTER(LensParams), _P, _P,
                             ctypes.POINTER(_D), ctypes.c_int32, _P]),
     "pm_strerror": (ctypes.c_char_p, [_I]),

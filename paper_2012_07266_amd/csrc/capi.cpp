@@ -16,6 +16,7 @@
 #include "../../include/madlens.h"
 #include "cosmo_host.h"
 #include "adjoint.h"
+#include "batch.h"
 #include "fft.h"
 #include "particles.h"
 
@@ -211,6 +212,23 @@ struct ProfScope {
     Prof& p;
     ProfScope(Prof& pr, const char* n) : p(pr) { p.begin(n); }
     ~ProfScope() { p.end(); }
+};
+
+// The arguments of every pass of one slot's fused step (the device
+// parameter block of a batch holds one array per pass).
+template <class T> struct BatchSlotArgs {
+    FillArgs fill;
+    ScanArgs scan;
+    ScatterArgs<T> scatter;
+    PaintArgs<T> paint;
+    LensGatherArgs<T> lens;
+    R2cArgs<T> r2c;
+    C2cArgs<T> fwd;
+    GradArgs<T> grad;
+    C2cArgs<T> inv;
+    DualArgs<T> dual;
+    C2rArgs<T> c2r[3];
+    ReadoutArgs<T> readout;
 };
 
 struct SimBase {
@@ -785,21 +803,20 @@ template <class T> struct Sim final : SimBase {
         }
     }
 
-    // Born projection of the shell (chi(a1), chi(a0)] of the current,
-    // tile-sorted positions (which must be those at a1) into kappa.  With
-    // sub-evolution the step's drift momentum is mom - sub_k2 * acc.
-    // With PGD on, pgd_shift must have run for the current state.
-    int project_shell(double a0, double a1, T* kappa, T sub_k2 = T(0)) {
-        LensArgs<T> la{};
+    // The plain projection's arguments and mean terms of the shell
+    // (chi(a1), chi(a0)]; false when the shell lies wholly behind the
+    // farthest source plane (its images and its mean term both need
+    // chi < chi_s, so it adds nothing).
+    bool plain_lens_args(double a0, double a1, LensArgs<T>& la, MapAdd<T>& mv) const {
+        la = LensArgs<T>{};
+        mv = MapAdd<T>{};
         la.npix = npix;
         la.nsrc = nsrc;
         la.cell = (T)cell;
         double chi_far = cosmo.chi(a0), chi_near = cosmo.chi(a1);
-        // a shell wholly behind the farthest source plane adds nothing (its
-        // images and its mean term both need chi < chi_s)
         double chis_max = 0;
         for (double c : chisrc) chis_max = std::max(chis_max, c);
-        if (chi_near >= chis_max) return PM_OK;
+        if (chi_near >= chis_max) return false;
         la.chi_near = (T)chi_near;
         la.chi_far = (T)chi_far;
         la.cnear_d = chi_near / cell;
@@ -812,10 +829,26 @@ template <class T> struct Sim final : SimBase {
         la.atab = atab;
         la.ntab = ATAB_N;
         la.dchi = (T)dchi_tab;
-        // 64 x 64-pixel regions when their fixed-point accumulators fit in
-        // 128 KB of LDS: each region's frustum is then twice as wide, and
-        // the tile columns it reads hold fewer particles outside it
-        la.rs = ((size_t)nsrc * 64 * 64 * 8 <= 131072 && npix >= 256) ? 64 : 32;
+        la.rs = region_side(nsrc, npix);
+        for (int s = 0; s < nsrc; ++s) mv.v[s] = (T)cosmo.shell_mean(chi_near, chi_far, chisrc[s]);
+        return true;
+    }
+
+    // 64 x 64-pixel regions when their fixed-point accumulators fit in 128 KB
+    // of LDS: each region's frustum is then twice as wide, and the tile
+    // columns it reads hold fewer particles outside it
+    static int region_side(int ns, int np_) {
+        return ((size_t)ns * 64 * 64 * 8 <= 131072 && np_ >= 256) ? 64 : 32;
+    }
+
+    // Born projection of the shell (chi(a1), chi(a0)] of the current,
+    // tile-sorted positions (which must be those at a1) into kappa.  With
+    // sub-evolution the step's drift momentum is mom - sub_k2 * acc.
+    // With PGD on, pgd_shift must have run for the current state.
+    int project_shell(double a0, double a1, T* kappa, T sub_k2 = T(0)) {
+        LensArgs<T> la;
+        MapAdd<T> mv;
+        if (!plain_lens_args(a0, a1, la, mv)) return PM_OK;
         la.rot = rot ? 1 : 0;
         la.rot_seed = (unsigned long long)rot_seed;
         if (interp) {
@@ -836,8 +869,6 @@ template <class T> struct Sim final : SimBase {
             la.shift_scale = (T)(pgd_alpha0 * std::pow(a1, pgd_mu));
             la.shift_bits = pgd_bits;
         }
-        MapAdd<T> mv{};
-        for (int s = 0; s < nsrc; ++s) mv.v[s] = (T)cosmo.shell_mean(chi_near, chi_far, chisrc[s]);
         { ProfScope ps(prof, "lens_gather");
           launch_lens_gather<T>(cur, sb, geo, la, mv, kappa, st); }
         return PM_OK;
@@ -1389,6 +1420,92 @@ template <class T> struct Sim final : SimBase {
         return check_launch();
     }
 
+    // ---- batched stepping (pm_batch_*) ----------------------------------------
+    // A handle joins a batch at a_grid[0] after its initial conditions: the
+    // batch enqueues this step's first half-kick, drift and sort keys on its
+    // own stream; each batched step then runs pm_run's fused step (sort,
+    // paint, shell, force, readout that starts the next step).
+    bool batch_compatible(const pm_params& shape, int npx, int ns) const {
+        return P.np == shape.np && P.nm == shape.nm && P.dtype == shape.dtype && npix == npx &&
+               nsrc == ns && !interp && !pgd && !rot;
+    }
+
+    int batch_begin(hipStream_t bst, double a0, double a1) {
+        if (a_cur < 0 || std::fabs(a0 - a_cur) > 1e-12 * std::fabs(a_cur) + 1e-15) return PM_ESTATE;
+        HIPCHK(hipStreamSynchronize(st));  // the handle's own work (its initial conditions)
+        const double ah = 0.5 * (a0 + a1);
+        launch_fill_u32(sb.count, 0u, ntiles, bst);
+        launch_kick_drift_key<T>(cur, sb, geo, (T)cosmo.kick(a0, ah, a0),
+                                 (T)cosmo.drift(a0, a1, ah), MODE_KICK | MODE_DRIFT, status, bst);
+        a_cur = -1.0;  // between steps until the batch leaves it at a step's end
+        ic_fresh = false;
+        tan_valid = false;
+        kdk_a0 = kdk_a1 = -1.0;
+        meshes_valid = false;
+        return check_launch();
+    }
+
+    // The arguments of every pass of the fused step a0 -> a1 (a2 > a1: the
+    // next step's end, whose first half-kick and drift the readout applies;
+    // a2 <= 0: the last step), and the host's bookkeeping of the sort's
+    // buffer swap.  kappa NULL: no projection.
+    void batch_step_args(double a0, double a1, double a2, T* kappa, BatchSlotArgs<T>& o) {
+        const int nm = P.nm;
+        o.scan = ScanArgs{sb.count, sb.start, scan_sum, ntiles, 1};
+        o.scatter = ScatterArgs<T>{cur, alt, sb, geo, 1};
+        std::swap(cur.disp, alt.disp);
+        std::swap(cur.mom, alt.mom);
+        std::swap(cur.id, alt.id);
+        o.paint = PaintArgs<T>{cur, sb, geo, (T)std::pow((double)geo.B, 3), mesh[0], halo, 1};
+        o.lens = LensGatherArgs<T>{};
+        if (kappa && plain_lens_args(a0, a1, o.lens.la, o.lens.mean)) {
+            o.lens.p = cur;
+            o.lens.sb = sb;
+            o.lens.g = geo;
+            o.lens.kappa = kappa;
+            o.lens.on = 1;
+        }
+        o.r2c = R2cArgs<T>{mesh[0], nyq[0], tw_hm, twp_nm, paint_halo_merge<T>(geo, halo), 1};
+        o.fwd = fft_c2c_axis1_args<T>(nm, reinterpret_cast<cx<T>*>(mesh[0]), nyq[0], tw_nm);
+        const T gscale = (T)(1.0 / (2.0 * PI * (double)nm * (double)nm));
+        PtrTriple om{{mesh[0], mesh[1], mesh[2]}}, on{{nyq[0], nyq[1], nyq[2]}};
+        o.grad = fft_grad_axis0_args<T>(nm, reinterpret_cast<cx<T>*>(mesh[0]), nyq[0], om, on,
+                                        tw_nm, nullptr, gscale);
+        C2cArgs<T> inv = fft_c2c_axis1_args<T>(nm, reinterpret_cast<cx<T>*>(mesh[0]), nyq[0], tw_nm);
+        o.inv = inv;
+        o.dual = fft_c2c_axis1_dual_args<T>(nm, reinterpret_cast<cx<T>*>(mesh[1]), nyq[1],
+                                            reinterpret_cast<cx<T>*>(mesh[2]), nyq[2], tw_nm);
+        for (int j = 0; j < 3; ++j)
+            o.c2r[j] = C2rArgs<T>{mesh[j], nyq[j], tw_hm, twp_nm, j == 2 ? 1 : 0, 1};
+        const double ah = 0.5 * (a0 + a1);
+        ReadoutNext<T> nx;
+        o.fill = FillArgs{sb.count, (long)ntiles, 0};
+        if (a2 > a1) {
+            const double ah2 = 0.5 * (a1 + a2);
+            nx.on = 1;
+            nx.kick = (T)cosmo.kick(a1, ah2, a1);
+            nx.drift = (T)cosmo.drift(a1, a2, ah2);
+            o.fill.on = 1;
+        }
+        o.readout = ReadoutArgs<T>{cur, sb, geo, mesh[0], mesh[1], mesh[2],
+                                   (T)cosmo.kick(ah, a1, a1), 1, status, nx, 1};
+        if (a2 <= a1) {  // the step ends the handle's run: the state is at a1
+            meshes_valid = true;
+            a_cur = a1;
+            kdk_a0 = a0;
+            kdk_a1 = a1;
+            kdk_k2 = (T)cosmo.kick(ah, a1, a1);
+        }
+    }
+
+    // Leaving a batch before its last step: the state is between two steps
+    // (drifted, keys written) and no call can continue it.
+    void batch_abandon() {
+        a_cur = -1.0;
+        kdk_a0 = kdk_a1 = -1.0;
+        meshes_valid = false;
+    }
+
     hipStream_t stream() const override { return st; }
 
     int background(double a, double out[3]) const override {
@@ -1404,6 +1521,242 @@ template <class T> struct Sim final : SimBase {
 struct pm_sim {
     std::unique_ptr<SimBase> impl;
     int dtype;
+};
+
+namespace {
+
+// ---- batches: one launch per pass over same-shape simulations ---------------
+// The device parameter block holds one array of argument structs per pass
+// (capacity entries; three per slot for the c2r pass).  A step fills a
+// pinned host copy, copies it to the device on the batch's stream and
+// replays the launches (a HIP graph of kernel nodes only, captured at the
+// first step, or the launches themselves), so nothing in the launches
+// changes from step to step.
+struct BatchBase {
+    virtual ~BatchBase() {}
+    virtual int attach(pm_sim* sim, const double* a_grid, int nsteps, int* slot_out) = 0;
+    virtual int lens(pm_sim* sim, void* kappa) = 0;
+    virtual int detach(pm_sim* sim) = 0;
+    virtual int step(int* running_out) = 0;
+};
+
+template <class T> struct Batch final : BatchBase {
+    pm_params shape{};
+    int npix = 0, nsrc = 0, cap = 0;
+    bool use_graph = true;
+    hipStream_t st = nullptr;
+    bool own_stream = false;
+    Geo geo{};
+    LensArgs<T> lshape{};
+    struct Slot {
+        pm_sim* h = nullptr;
+        Sim<T>* sim = nullptr;
+        std::vector<double> agrid;
+        int next = 0;
+        T* kappa = nullptr;
+    };
+    std::vector<Slot> slots;
+    // parameter block: offsets of the per-pass arrays
+    size_t o_fill, o_scan, o_scatter, o_paint, o_lens, o_r2c, o_fwd, o_grad, o_inv, o_dual, o_c2r,
+        o_readout, bytes;
+    char* dev = nullptr;
+    char* host[2] = {nullptr, nullptr};
+    hipEvent_t copied[2] = {nullptr, nullptr};
+    int ring = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+
+    ~Batch() override {
+        if (st) (void)hipStreamSynchronize(st);
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        for (int i = 0; i < 2; ++i) {
+            if (copied[i]) (void)hipEventDestroy(copied[i]);
+            if (host[i]) (void)hipHostFree(host[i]);
+        }
+        if (dev) (void)hipFree(dev);
+        if (own_stream && st) (void)hipStreamDestroy(st);
+    }
+
+    int create(const pm_params* p, const lens_params* l, int capacity, int graph_on,
+               void* stream) {
+        shape = *p;
+        npix = l->npix;
+        nsrc = l->nsrc;
+        cap = capacity;
+        use_graph = graph_on != 0;
+        geo.np = p->np;
+        geo.nm = p->nm;
+        geo.B = p->nm / p->np;
+        geo.nt = p->nm / TILE;
+        geo.nkz = p->nm / KZ;
+        geo.npart = (long)p->np * p->np * p->np;
+        lshape.npix = npix;
+        lshape.nsrc = nsrc;
+        lshape.rs = Sim<T>::region_side(nsrc, npix);
+        slots.resize(cap);
+        size_t b = 0;
+        auto take = [&](size_t n) {
+            size_t off = (b + 255) & ~size_t(255);
+            b = off + n;
+            return off;
+        };
+        o_fill = take(cap * sizeof(FillArgs));
+        o_scan = take(cap * sizeof(ScanArgs));
+        o_scatter = take(cap * sizeof(ScatterArgs<T>));
+        o_paint = take(cap * sizeof(PaintArgs<T>));
+        o_lens = take(cap * sizeof(LensGatherArgs<T>));
+        o_r2c = take(cap * sizeof(R2cArgs<T>));
+        o_fwd = take(cap * sizeof(C2cArgs<T>));
+        o_grad = take(cap * sizeof(GradArgs<T>));
+        o_inv = take(cap * sizeof(C2cArgs<T>));
+        o_dual = take(cap * sizeof(DualArgs<T>));
+        o_c2r = take(3 * cap * sizeof(C2rArgs<T>));
+        o_readout = take(cap * sizeof(ReadoutArgs<T>));
+        bytes = b;
+        if (stream) {
+            st = reinterpret_cast<hipStream_t>(stream);
+        } else {
+            // graph capture needs a stream other than the legacy default one
+            if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return PM_EDEVICE;
+            own_stream = true;
+        }
+        prepare_lens_gather_batch<T>();
+        if (hipMalloc(&dev, bytes) != hipSuccess) {
+            dev = nullptr;
+            (void)hipGetLastError();
+            return PM_ENOMEM;
+        }
+        for (int i = 0; i < 2; ++i) {
+            if (hipHostMalloc(&host[i], bytes, hipHostMallocDefault) != hipSuccess) {
+                host[i] = nullptr;
+                (void)hipGetLastError();
+                return PM_ENOMEM;
+            }
+            std::memset(host[i], 0, bytes);
+            HIPCHK(hipEventCreateWithFlags(&copied[i], hipEventDisableTiming));
+        }
+        return PM_OK;
+    }
+
+    int find(pm_sim* h) const {
+        for (int i = 0; i < cap; ++i)
+            if (slots[i].h == h) return i;
+        return -1;
+    }
+
+    int attach(pm_sim* h, const double* a_grid, int nsteps, int* slot_out) override {
+        if (!h || !a_grid || nsteps < 1 || h->dtype != shape.dtype) return PM_EINVAL;
+        if (find(h) >= 0) return PM_EINVAL;
+        auto* sim = dynamic_cast<Sim<T>*>(h->impl.get());
+        if (!sim || !sim->batch_compatible(shape, npix, nsrc)) return PM_EINVAL;
+        for (int i = 0; i < nsteps; ++i)
+            if (!(a_grid[i + 1] > 0 && a_grid[i + 1] <= 1.5)) return PM_EINVAL;
+        int k = find(nullptr);
+        if (k < 0) return PM_EFULL;
+        int rc = sim->batch_begin(st, a_grid[0], a_grid[1]);
+        if (rc) return rc;
+        Slot& s = slots[k];
+        s.h = h;
+        s.sim = sim;
+        s.agrid.assign(a_grid, a_grid + nsteps + 1);
+        s.next = 0;
+        s.kappa = nullptr;
+        if (slot_out) *slot_out = k;
+        return PM_OK;
+    }
+
+    int lens(pm_sim* h, void* kappa) override {
+        int k = find(h);
+        if (k < 0) return PM_EINVAL;
+        slots[k].kappa = reinterpret_cast<T*>(kappa);
+        return PM_OK;
+    }
+
+    int detach(pm_sim* h) override {
+        int k = find(h);
+        if (k < 0) return PM_EINVAL;
+        HIPCHK(hipStreamSynchronize(st));
+        Slot& s = slots[k];
+        if (s.next < (int)s.agrid.size() - 1) s.sim->batch_abandon();
+        s = Slot{};
+        return PM_OK;
+    }
+
+    template <class A> A* arr(char* base, size_t off) { return reinterpret_cast<A*>(base + off); }
+
+    void launch_all(char* base) {
+        const int nm = shape.nm;
+        const int ntiles = geo.nt * geo.nt * geo.nkz;
+        launch_scan_batch(arr<ScanArgs>(base, o_scan), ntiles, cap, st);
+        launch_scatter_batch<T>(arr<ScatterArgs<T>>(base, o_scatter), geo, cap, st);
+        launch_paint_batch<T>(arr<PaintArgs<T>>(base, o_paint), geo, cap, st);
+        launch_lens_gather_batch<T>(arr<LensGatherArgs<T>>(base, o_lens), lshape, cap, st);
+        fft_r2c_rows_batch<T>(nm, arr<R2cArgs<T>>(base, o_r2c), cap, st);
+        fft_c2c_axis1_batch<T>(nm, 1, arr<C2cArgs<T>>(base, o_fwd), cap, st);
+        fft_grad_axis0_batch<T>(nm, arr<GradArgs<T>>(base, o_grad), cap, st);
+        fft_c2c_axis1_batch<T>(nm, -1, arr<C2cArgs<T>>(base, o_inv), cap, st);
+        fft_c2c_axis1_dual_batch<T>(nm, arr<DualArgs<T>>(base, o_dual), cap, st);
+        fft_c2r_rows_batch<T>(nm, arr<C2rArgs<T>>(base, o_c2r), 3 * cap, st);
+        launch_fill_batch(arr<FillArgs>(base, o_fill), ntiles, cap, st);
+        launch_readout_batch<T>(arr<ReadoutArgs<T>>(base, o_readout), geo, cap, st);
+    }
+
+    int step(int* running_out) override {
+        char* h = host[ring];
+        HIPCHK(hipEventSynchronize(copied[ring]));  // its last copy has been read
+        std::memset(h, 0, bytes);  // every pass of an idle slot: on = 0
+        int running = 0;
+        for (int k = 0; k < cap; ++k) {
+            Slot& s = slots[k];
+            const int n = (int)s.agrid.size() - 1;
+            if (!s.sim || s.next >= n) continue;
+            const int i = s.next;
+            BatchSlotArgs<T> a;
+            s.sim->batch_step_args(s.agrid[i], s.agrid[i + 1], i + 1 < n ? s.agrid[i + 2] : -1.0,
+                                   s.kappa, a);
+            arr<FillArgs>(h, o_fill)[k] = a.fill;
+            arr<ScanArgs>(h, o_scan)[k] = a.scan;
+            arr<ScatterArgs<T>>(h, o_scatter)[k] = a.scatter;
+            arr<PaintArgs<T>>(h, o_paint)[k] = a.paint;
+            arr<LensGatherArgs<T>>(h, o_lens)[k] = a.lens;
+            arr<R2cArgs<T>>(h, o_r2c)[k] = a.r2c;
+            arr<C2cArgs<T>>(h, o_fwd)[k] = a.fwd;
+            arr<GradArgs<T>>(h, o_grad)[k] = a.grad;
+            arr<C2cArgs<T>>(h, o_inv)[k] = a.inv;
+            arr<DualArgs<T>>(h, o_dual)[k] = a.dual;
+            for (int j = 0; j < 3; ++j) arr<C2rArgs<T>>(h, o_c2r)[3 * k + j] = a.c2r[j];
+            arr<ReadoutArgs<T>>(h, o_readout)[k] = a.readout;
+            ++s.next;
+            if (s.next < n) ++running;
+        }
+        if (running_out) *running_out = running;
+        HIPCHK(hipMemcpyAsync(dev, h, bytes, hipMemcpyHostToDevice, st));
+        HIPCHK(hipEventRecord(copied[ring], st));
+        ring ^= 1;
+        if (!use_graph) {
+            launch_all(dev);
+            return hipGetLastError() == hipSuccess ? PM_OK : PM_EDEVICE;
+        }
+        if (!exec) {
+            HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+            launch_all(dev);
+            hipError_t e = hipStreamEndCapture(st, &graph);
+            if (e != hipSuccess || !graph) {
+                (void)hipGetLastError();
+                return PM_EDEVICE;
+            }
+            HIPCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+        }
+        HIPCHK(hipGraphLaunch(exec, st));
+        return PM_OK;
+    }
+};
+
+}  // namespace
+
+struct pm_batch {
+    std::unique_ptr<BatchBase> impl;
 };
 
 namespace {
@@ -1453,6 +1806,61 @@ int run_noalloc_t(const pm_params* p, const lens_params* l, void* stream, const 
 }  // namespace
 
 extern "C" {
+
+int pm_batch_create(const pm_params* shape, const lens_params* lens_shape, int32_t capacity,
+                    int32_t use_graph, void* hip_stream, pm_batch** out) {
+    if (!out) return PM_EINVAL;
+    *out = nullptr;
+    int rc = validate(shape, lens_shape);
+    if (rc) return rc;
+    if (capacity < 1 || capacity > 1024) return PM_EINVAL;
+    pm_batch* b = new (std::nothrow) pm_batch;
+    if (!b) return PM_ENOMEM;
+    if (shape->dtype == PM_F32) {
+        auto* impl = new (std::nothrow) Batch<float>;
+        b->impl.reset(impl);
+        rc = impl ? impl->create(shape, lens_shape, capacity, use_graph, hip_stream) : PM_ENOMEM;
+    } else {
+        auto* impl = new (std::nothrow) Batch<double>;
+        b->impl.reset(impl);
+        rc = impl ? impl->create(shape, lens_shape, capacity, use_graph, hip_stream) : PM_ENOMEM;
+    }
+    if (rc) {
+        delete b;
+        return rc;
+    }
+    *out = b;
+    return PM_OK;
+}
+
+int pm_batch_destroy(pm_batch* b) {
+    if (!b) return PM_EINVAL;
+    delete b;
+    return PM_OK;
+}
+
+int pm_batch_attach(pm_batch* b, pm_sim* sim, const double* a_grid, int32_t nsteps,
+                    int32_t* slot_out) {
+    if (!b) return PM_EINVAL;
+    int k = -1;
+    int rc = b->impl->attach(sim, a_grid, nsteps, &k);
+    if (rc == PM_OK && slot_out) *slot_out = k;
+    return rc;
+}
+
+int pm_batch_lens(pm_batch* b, pm_sim* sim, void* kappa) {
+    return b ? b->impl->lens(sim, kappa) : PM_EINVAL;
+}
+
+int pm_batch_detach(pm_batch* b, pm_sim* sim) { return b ? b->impl->detach(sim) : PM_EINVAL; }
+
+int pm_batch_step(pm_batch* b, int32_t* running_out) {
+    if (!b) return PM_EINVAL;
+    int r = 0;
+    int rc = b->impl->step(&r);
+    if (running_out) *running_out = r;
+    return rc;
+}
 
 int pm_run_noalloc(const pm_params* p, const lens_params* l, void* hip_stream, const void* noise,
                    const double* a_grid, int32_t nsteps, void* kappa) {
@@ -1626,6 +2034,7 @@ const char* pm_strerror(int code) {
         case PM_ESTATE: return "simulation is not in the required state";
         case PM_ENONFINITE: return "non-finite particle position";
         case PM_EAGAIN: return "not finished yet";
+        case PM_EFULL: return "every slot of the batch is taken";
         case PM_ETOOBIG:
             return "arena larger than the static scratch of the non-allocating entry point";
         default: return "unknown error";

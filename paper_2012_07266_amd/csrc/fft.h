@@ -9,6 +9,16 @@ struct PtrTriple {
     void* p[3];
 };
 
+// Pencils of length N of a strided pass: element n of pencil w of workgroup
+// g sits at base(g) + n*C + w (base = (g / (C/W)) * N*C + (g % (C/W)) * W),
+// or at g*W*N + w*N + n when contig; n_wg workgroups.
+struct ViewDesc {
+    void* ptr;
+    long C;
+    int contig;
+    int n_wg;
+};
+
 // true when an n^3 mesh can be transformed in precision T
 template <class T> bool fft_supported(int n);
 

@@ -23,6 +23,7 @@
 // place: every stage reads its butterfly inputs into registers, barriers,
 // and writes its outputs in natural-order Stockham positions.
 #include "fft.h"
+#include "batch.h"
 
 namespace ml {
 
@@ -229,7 +230,7 @@ __device__ __forceinline__ unsigned row_wg(unsigned b, unsigned nb) {
 }
 
 template <class T, int H, int W>
-__global__ __launch_bounds__(NT) void k_r2c_rows(T* io, cx<T>* nyq, const cx<T>* tw_h,
+__device__ __forceinline__ void r2c_rows_body(T* io, cx<T>* nyq, const cx<T>* tw_h,
                                                  const cx<T>* tw_post, HaloMerge<T> hm) {
     __shared__ cx<T> buf[H * (W + 1)];
     __shared__ cx<T> tws[H];
@@ -284,6 +285,18 @@ __global__ __launch_bounds__(NT) void k_r2c_rows(T* io, cx<T>* nyq, const cx<T>*
     }
 }
 
+template <class T, int H, int W>
+__global__ __launch_bounds__(NT) void k_r2c_rows(T* io, cx<T>* nyq, const cx<T>* tw_h,
+                                                 const cx<T>* tw_post, HaloMerge<T> hm) {
+    r2c_rows_body<T, H, W>(io, nyq, tw_h, tw_post, hm);
+}
+template <class T, int H, int W>
+__global__ __launch_bounds__(NT) void k_r2c_rows_b(const R2cArgs<T>* __restrict__ tab) {
+    const R2cArgs<T> a = tab[blockIdx.y];
+    if (!a.on) return;
+    r2c_rows_body<T, H, W>(a.io, a.nyq, a.tw_h, a.tw_post, a.hm);
+}
+
 // ---------------------------------------------------------------------------
 // pass 5: c2r along the contiguous axis (unnormalised inverse).
 // ---------------------------------------------------------------------------
@@ -291,7 +304,7 @@ __global__ __launch_bounds__(NT) void k_r2c_rows(T* io, cx<T>* nyq, const cx<T>*
 // the Nyquist plane k2 = N/2): the axis-2 gradient component of the fused
 // axis-0 pass.
 template <class T, int H, int W>
-__global__ __launch_bounds__(NT) void k_c2r_rows(T* io, const cx<T>* nyq, const cx<T>* tw_h,
+__device__ __forceinline__ void c2r_rows_body(T* io, const cx<T>* nyq, const cx<T>* tw_h,
                                                  const cx<T>* tw_post, int mul_k2) {
     __shared__ cx<T> buf[H * (W + 1)];
     __shared__ cx<T> tws[H];
@@ -351,6 +364,18 @@ __global__ __launch_bounds__(NT) void k_c2r_rows(T* io, const cx<T>* nyq, const 
     }
 }
 
+template <class T, int H, int W>
+__global__ __launch_bounds__(NT) void k_c2r_rows(T* io, const cx<T>* nyq, const cx<T>* tw_h,
+                                                 const cx<T>* tw_post, int mul_k2) {
+    c2r_rows_body<T, H, W>(io, nyq, tw_h, tw_post, mul_k2);
+}
+template <class T, int H, int W>
+__global__ __launch_bounds__(NT) void k_c2r_rows_b(const C2rArgs<T>* __restrict__ tab) {
+    const C2rArgs<T> a = tab[blockIdx.y];
+    if (!a.on) return;
+    c2r_rows_body<T, H, W>(a.io, a.nyq, a.tw_h, a.tw_post, a.mul_k2);
+}
+
 // ---------------------------------------------------------------------------
 // passes 2 and 4: c2c along a strided axis.  A "view" describes pencils of
 // length N: element n of pencil w of workgroup g sits at
@@ -358,13 +383,6 @@ __global__ __launch_bounds__(NT) void k_c2r_rows(T* io, const cx<T>* nyq, const 
 //   contig : g*W*N + w*N + n
 // Workgroups [0, g_main) work on view a, the rest on view b.
 // ---------------------------------------------------------------------------
-struct ViewDesc {
-    void* ptr;
-    long C;
-    int contig;
-    int n_wg;
-};
-
 // Workgroups are handed to the 8 XCDs round-robin.  Renumber them so that
 // each XCD walks a contiguous run of g.  When a workgroup's row segment is
 // narrower than a 128-byte line (8 float pencils, meshes above 512),
@@ -445,7 +463,7 @@ __device__ __forceinline__ void view_store(const cx<T>* buf, void* dst, const Vi
 }
 
 template <class T, int N, int W, int S>
-__global__ __launch_bounds__(NT) void k_c2c_view(ViewDesc va, ViewDesc vb, const cx<T>* tw) {
+__device__ __forceinline__ void c2c_view_body(ViewDesc va, ViewDesc vb, const cx<T>* tw) {
     __shared__ cx<T> buf[N * (W + 1)];
     __shared__ cx<T> tws[N];
     const int tid = threadIdx.x;
@@ -492,6 +510,17 @@ __global__ __launch_bounds__(NT) void k_c2c_view(ViewDesc va, ViewDesc vb, const
     view_store<T, N, W>(buf, v.ptr, v, g, tid);
 }
 
+template <class T, int N, int W, int S>
+__global__ __launch_bounds__(NT) void k_c2c_view(ViewDesc va, ViewDesc vb, const cx<T>* tw) {
+    c2c_view_body<T, N, W, S>(va, vb, tw);
+}
+template <class T, int N, int W, int S>
+__global__ __launch_bounds__(NT) void k_c2c_view_b(const C2cArgs<T>* __restrict__ tab) {
+    const C2cArgs<T> a = tab[blockIdx.y];
+    if (!a.on) return;
+    c2c_view_body<T, N, W, S>(a.va, a.vb, a.tw);
+}
+
 // ---------------------------------------------------------------------------
 // Inverse pass along axis 1 that produces two outputs from one input H:
 //   in place:  IFFT1(n1 H)   (zero on the plane |n1| = N/2)
@@ -506,7 +535,7 @@ __device__ __forceinline__ T n1_mult(int n) {
 }
 
 template <class T, int N, int W>
-__global__ __launch_bounds__(NT) void k_c2c_view_dual(ViewDesc va, ViewDesc vb, cx<T>* dst2a,
+__device__ __forceinline__ void c2c_view_dual_body(ViewDesc va, ViewDesc vb, cx<T>* dst2a,
                                                       cx<T>* dst2b, const cx<T>* tw) {
     __shared__ cx<T> buf[N * (W + 1)];
     __shared__ cx<T> tws[N];
@@ -587,6 +616,18 @@ __global__ __launch_bounds__(NT) void k_c2c_view_dual(ViewDesc va, ViewDesc vb, 
     view_store<T, N, W>(buf, v.ptr, v, g, tid);
 }
 
+template <class T, int N, int W>
+__global__ __launch_bounds__(NT) void k_c2c_view_dual(ViewDesc va, ViewDesc vb, cx<T>* dst2a,
+                                                      cx<T>* dst2b, const cx<T>* tw) {
+    c2c_view_dual_body<T, N, W>(va, vb, dst2a, dst2b, tw);
+}
+template <class T, int N, int W>
+__global__ __launch_bounds__(NT) void k_c2c_view_dual_b(const DualArgs<T>* __restrict__ tab) {
+    const DualArgs<T> a = tab[blockIdx.y];
+    if (!a.on) return;
+    c2c_view_dual_body<T, N, W>(a.va, a.vb, a.dst2a, a.dst2b, a.tw);
+}
+
 // ---------------------------------------------------------------------------
 // pass 3: fused outer-axis pass.  Forward FFT of W pencils along axis 0,
 // h = i G[n0^2+n1^2+n2^2] X, then two inverse FFTs along axis 0:
@@ -604,7 +645,7 @@ __global__ __launch_bounds__(NT) void k_c2c_view_dual(ViewDesc va, ViewDesc vb, 
 // per CU, so that one workgroup's loads and stores overlap the other's
 // transforms.
 template <class T, int N, int W, int NTG>
-__global__ __launch_bounds__(NTG, (NTG == 512 ? 4 : 1)) void k_grad_x0(ViewDesc va, ViewDesc vb, PtrTriple outa,
+__device__ __forceinline__ void grad_x0_body(ViewDesc va, ViewDesc vb, PtrTriple outa,
                                                 PtrTriple outb, const cx<T>* tw, const T* G, T gscale) {
     __shared__ cx<T> buf[N * (W + 1)];
     __shared__ cx<T> tws[N];
@@ -757,6 +798,20 @@ __global__ __launch_bounds__(NTG, (NTG == 512 ? 4 : 1)) void k_grad_x0(ViewDesc 
         __syncthreads();
     }
     }
+}
+
+template <class T, int N, int W, int NTG>
+__global__ __launch_bounds__(NTG, (NTG == 512 ? 4 : 1)) void k_grad_x0(
+    ViewDesc va, ViewDesc vb, PtrTriple outa, PtrTriple outb, const cx<T>* tw, const T* G,
+    T gscale) {
+    grad_x0_body<T, N, W, NTG>(va, vb, outa, outb, tw, G, gscale);
+}
+template <class T, int N, int W, int NTG>
+__global__ __launch_bounds__(NTG, (NTG == 512 ? 4 : 1)) void k_grad_x0_b(
+    const GradArgs<T>* __restrict__ tab) {
+    const GradArgs<T> a = tab[blockIdx.y];
+    if (!a.on) return;
+    grad_x0_body<T, N, W, NTG>(a.va, a.vb, a.outa, a.outb, a.tw, a.G, a.gscale);
 }
 
 // ---------------------------------------------------------------------------
@@ -1006,6 +1061,138 @@ void fft_div_axis0(int n, PtrTriple in_main, PtrTriple in_nyq, cx<T>* out_main, 
     else { ML_SIZES_D(ML_CASE) }
 #undef ML_CASE
 }
+
+// ---- batched launches (one launch per pass over the slots of a batch) ----
+template <class T>
+C2cArgs<T> fft_c2c_axis1_args(int n, cx<T>* main, cx<T>* nyq, const cx<T>* tw) {
+    C2cArgs<T> a{};
+    const int W = lanes_w<T>(n);
+    a.va = ViewDesc{main, n / 2, 0, (int)((long)n * (n / 2) / W)};
+    a.vb = ViewDesc{nyq, 1, 1, n / W};
+    a.tw = tw;
+    a.on = 1;
+    return a;
+}
+
+template <class T>
+DualArgs<T> fft_c2c_axis1_dual_args(int n, cx<T>* main, cx<T>* nyq, cx<T>* main2, cx<T>* nyq2,
+                                    const cx<T>* tw) {
+    DualArgs<T> a{};
+    const int W = lanes_w<T>(n);
+    a.va = ViewDesc{main, n / 2, 0, (int)((long)n * (n / 2) / W)};
+    a.vb = ViewDesc{nyq, 1, 1, n / W};
+    a.dst2a = main2;
+    a.dst2b = nyq2;
+    a.tw = tw;
+    a.on = 1;
+    return a;
+}
+
+template <class T>
+GradArgs<T> fft_grad_axis0_args(int n, cx<T>* main_in, cx<T>* nyq_in, PtrTriple out_main,
+                                PtrTriple out_nyq, const cx<T>* tw, const T* G, T gscale) {
+    GradArgs<T> a{};
+    const int W = lanes_w<T>(n);
+    a.va = ViewDesc{main_in, (long)n * (n / 2), 0, (int)((long)n * (n / 2) / W)};
+    a.vb = ViewDesc{nyq_in, n, 0, n / W};
+    a.outa = out_main;
+    a.outb = out_nyq;
+    a.tw = tw;
+    a.G = G;
+    a.gscale = gscale;
+    a.on = 1;
+    return a;
+}
+
+template <class T, int H>
+static void r2c_rows_batch_n(const R2cArgs<T>* tab, long nrows, int slots, hipStream_t st) {
+    constexpr int W = rows_w<T>(2 * H);
+    hipLaunchKernelGGL((k_r2c_rows_b<T, H, W>), dim3(nrows / W, slots), dim3(NT), 0, st, tab);
+}
+template <class T, int H>
+static void c2r_rows_batch_n(const C2rArgs<T>* tab, long nrows, int slots, hipStream_t st) {
+    constexpr int W = rows_w<T>(2 * H);
+    hipLaunchKernelGGL((k_c2r_rows_b<T, H, W>), dim3(nrows / W, slots), dim3(NT), 0, st, tab);
+}
+template <class T, int N, int S>
+static void c2c_axis1_batch_n(const C2cArgs<T>* tab, int slots, hipStream_t st) {
+    constexpr int W = lanes_w<T>(N);
+    const int nwg = (int)((long)N * (N / 2) / W) + N / W;
+    hipLaunchKernelGGL((k_c2c_view_b<T, N, W, S>), dim3(nwg, slots), dim3(NT), 0, st, tab);
+}
+template <class T, int N>
+static void c2c_axis1_dual_batch_n(const DualArgs<T>* tab, int slots, hipStream_t st) {
+    constexpr int W = lanes_w<T>(N);
+    const int nwg = (int)((long)N * (N / 2) / W) + N / W;
+    hipLaunchKernelGGL((k_c2c_view_dual_b<T, N, W>), dim3(nwg, slots), dim3(NT), 0, st, tab);
+}
+template <class T, int N>
+static void grad_axis0_batch_n(const GradArgs<T>* tab, int slots, hipStream_t st) {
+    constexpr int W = lanes_w<T>(N);
+    constexpr int NTG = (grad_nt<T>(N) == 512 && reg_path_ok<N, W, 512>()) ? 512 : NT;
+    const int nwg = (int)((long)N * (N / 2) / W) + N / W;
+    hipLaunchKernelGGL((k_grad_x0_b<T, N, W, NTG>), dim3(nwg, slots), dim3(NTG), 0, st, tab);
+}
+
+template <class T>
+void fft_r2c_rows_batch(int n, const R2cArgs<T>* tab, int slots, hipStream_t st) {
+    long rows = (long)n * n;
+#define ML_CASE(v) if (n == v) return r2c_rows_batch_n<T, v / 2>(tab, rows, slots, st);
+    if constexpr (sizeof(T) == 4) { ML_SIZES_F(ML_CASE) }
+    else { ML_SIZES_D(ML_CASE) }
+#undef ML_CASE
+}
+
+template <class T>
+void fft_c2r_rows_batch(int n, const C2rArgs<T>* tab, int slots, hipStream_t st) {
+    long rows = (long)n * n;
+#define ML_CASE(v) if (n == v) return c2r_rows_batch_n<T, v / 2>(tab, rows, slots, st);
+    if constexpr (sizeof(T) == 4) { ML_SIZES_F(ML_CASE) }
+    else { ML_SIZES_D(ML_CASE) }
+#undef ML_CASE
+}
+
+template <class T>
+void fft_c2c_axis1_batch(int n, int sign, const C2cArgs<T>* tab, int slots, hipStream_t st) {
+#define ML_CASE(v)                                                                  \
+    if (n == v) {                                                                   \
+        if (sign > 0) return c2c_axis1_batch_n<T, v, 1>(tab, slots, st);            \
+        return c2c_axis1_batch_n<T, v, -1>(tab, slots, st);                         \
+    }
+    if constexpr (sizeof(T) == 4) { ML_SIZES_F(ML_CASE) }
+    else { ML_SIZES_D(ML_CASE) }
+#undef ML_CASE
+}
+
+template <class T>
+void fft_c2c_axis1_dual_batch(int n, const DualArgs<T>* tab, int slots, hipStream_t st) {
+#define ML_CASE(v) if (n == v) return c2c_axis1_dual_batch_n<T, v>(tab, slots, st);
+    if constexpr (sizeof(T) == 4) { ML_SIZES_F(ML_CASE) }
+    else { ML_SIZES_D(ML_CASE) }
+#undef ML_CASE
+}
+
+template <class T>
+void fft_grad_axis0_batch(int n, const GradArgs<T>* tab, int slots, hipStream_t st) {
+#define ML_CASE(v) if (n == v) return grad_axis0_batch_n<T, v>(tab, slots, st);
+    if constexpr (sizeof(T) == 4) { ML_SIZES_F(ML_CASE) }
+    else { ML_SIZES_D(ML_CASE) }
+#undef ML_CASE
+}
+
+#define ML_INST_BATCH(T)                                                                           \
+    template C2cArgs<T> fft_c2c_axis1_args<T>(int, cx<T>*, cx<T>*, const cx<T>*);                  \
+    template DualArgs<T> fft_c2c_axis1_dual_args<T>(int, cx<T>*, cx<T>*, cx<T>*, cx<T>*,           \
+                                                    const cx<T>*);                                \
+    template GradArgs<T> fft_grad_axis0_args<T>(int, cx<T>*, cx<T>*, PtrTriple, PtrTriple,         \
+                                                const cx<T>*, const T*, T);                       \
+    template void fft_r2c_rows_batch<T>(int, const R2cArgs<T>*, int, hipStream_t);                \
+    template void fft_c2r_rows_batch<T>(int, const C2rArgs<T>*, int, hipStream_t);                \
+    template void fft_c2c_axis1_batch<T>(int, int, const C2cArgs<T>*, int, hipStream_t);          \
+    template void fft_c2c_axis1_dual_batch<T>(int, const DualArgs<T>*, int, hipStream_t);         \
+    template void fft_grad_axis0_batch<T>(int, const GradArgs<T>*, int, hipStream_t);
+ML_INST_BATCH(float)
+ML_INST_BATCH(double)
 
 #define ML_INST(T)                                                                                  \
     template void fft_div_axis0<T>(int, PtrTriple, PtrTriple, cx<T>*, cx<T>*, const cx<T>*,        \

@@ -9,6 +9,7 @@
 // adds  wbase (chi_s - chi) / (chi_s chi a(chi))  to the map, bilinearly, and
 // the shell's mean term is added to every pixel in the same pass.
 #include "particles.h"
+#include "batch.h"
 
 namespace ml {
 
@@ -175,7 +176,7 @@ constexpr int LU = 4;  // particles per thread in flight
 // LG threads per workgroup: 256 for 32 x 32-pixel regions, 1024 for 64 x 64
 // (one workgroup per CU then holds the LDS, so it brings 16 waves)
 template <class T, int LG, bool EXT>
-__global__ __launch_bounds__(LG) void k_lens_gather(Parts<T> p, SortBufs sb, Geo g, LensArgs<T> la,
+__device__ __forceinline__ void lens_gather_body(Parts<T> p, SortBufs sb, Geo g, LensArgs<T> la,
                                                     MapAdd<T> mean, T* kappa) {
     using A = LensAcc<T>;
     using S = typename A::S;
@@ -424,6 +425,18 @@ __global__ __launch_bounds__(LG) void k_lens_gather(Parts<T> p, SortBufs sb, Geo
     }
 }
 
+template <class T, int LG, bool EXT>
+__global__ __launch_bounds__(LG) void k_lens_gather(Parts<T> p, SortBufs sb, Geo g, LensArgs<T> la,
+                                                    MapAdd<T> mean, T* kappa) {
+    lens_gather_body<T, LG, EXT>(p, sb, g, la, mean, kappa);
+}
+template <class T, int LG>
+__global__ __launch_bounds__(LG) void k_lens_gather_b(const LensGatherArgs<T>* __restrict__ tab) {
+    const LensGatherArgs<T> a = tab[blockIdx.y];
+    if (!a.on) return;
+    lens_gather_body<T, LG, false>(a.p, a.sb, a.g, a.la, a.mean, a.kappa);
+}
+
 // LDS bytes after the accumulator for the D(a(chi)) window of sub-evolution
 constexpr size_t DWIN_BYTES = 16384;
 
@@ -457,6 +470,31 @@ void launch_lens_gather_t(Parts<T> p, SortBufs sb, Geo g, LensArgs<T> la,
         hipLaunchKernelGGL((k_lens_gather<T, 256, EXT>), dim3(nreg * nreg), dim3(256), lds, st, p,
                            sb, g, la, mean, kappa);
     }
+}
+
+// The plain projection over the slots of a batch (one shape: the map size,
+// source count and region side of `shape` are every slot's).
+// Raises the batched kernels' dynamic LDS limit (before any capture).
+template <class T>
+void prepare_lens_gather_batch() {
+    constexpr size_t LDS_MAX = 163840;  // per workgroup on gfx950
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_lens_gather_b<T, 1024>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_MAX);
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_lens_gather_b<T, 256>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_MAX);
+}
+
+template <class T>
+void launch_lens_gather_batch(const LensGatherArgs<T>* tab, const LensArgs<T>& shape, int slots,
+                              hipStream_t st) {
+    const int nreg = (shape.npix + shape.rs - 1) / shape.rs;
+    const size_t lds = (size_t)shape.nsrc * shape.rs * shape.rs * sizeof(typename LensAcc<T>::S);
+    if (shape.rs >= 64)
+        hipLaunchKernelGGL((k_lens_gather_b<T, 1024>), dim3(nreg * nreg, slots), dim3(1024), lds, st,
+                           tab);
+    else
+        hipLaunchKernelGGL((k_lens_gather_b<T, 256>), dim3(nreg * nreg, slots), dim3(256), lds, st,
+                           tab);
 }
 
 // The plain projection is its own instantiation, free of the per-particle
@@ -535,5 +573,12 @@ template void launch_lens_gather<float>(Parts<float>, SortBufs, Geo, const LensA
 template void launch_lens_gather<double>(Parts<double>, SortBufs, Geo, const LensArgs<double>&,
                                          const MapAdd<double>&, double*, hipStream_t);
 
+
+template void prepare_lens_gather_batch<float>();
+template void prepare_lens_gather_batch<double>();
+template void launch_lens_gather_batch<float>(const LensGatherArgs<float>*,
+                                              const LensArgs<float>&, int, hipStream_t);
+template void launch_lens_gather_batch<double>(const LensGatherArgs<double>*,
+                                               const LensArgs<double>&, int, hipStream_t);
 
 }  // namespace ml

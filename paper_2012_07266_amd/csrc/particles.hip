@@ -9,6 +9,7 @@
 // floor(u) + 1 along each axis, t = u - floor(u), nodes taken modulo Nm.
 #include "particles.h"
 #include "paint_halo.h"
+#include "batch.h"
 
 namespace ml {
 
@@ -53,6 +54,20 @@ void launch_fill(T* p, T v, long n, hipStream_t st) {
     hipLaunchKernelGGL(k_fill<T>, dim3(blocks), dim3(PB), 0, st, p, v, n);
 }
 void launch_fill_u32(uint32_t* p, uint32_t v, long n, hipStream_t st) { launch_fill<uint32_t>(p, v, n, st); }
+
+__global__ void k_fill_b(const FillArgs* __restrict__ tab) {
+    const FillArgs a = tab[blockIdx.y];
+    if (!a.on) return;
+    for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < a.n; i += (long)gridDim.x * blockDim.x)
+        a.p[i] = 0u;
+}
+
+void launch_fill_batch(const FillArgs* tab, long n_max, int slots, hipStream_t st) {
+    long blocks = (n_max + PB - 1) / PB;
+    if (blocks > 65536) blocks = 65536;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_fill_b, dim3(blocks, slots), dim3(PB), 0, st, tab);
+}
 
 template <class T>
 __global__ void k_scale_copy(T* dst, const T* src, T s, long n) {
@@ -230,7 +245,7 @@ __device__ __forceinline__ uint32_t block_exclusive_scan(uint32_t v, uint32_t* t
 }
 
 // pass 1: every block scans its 1024 counts (coalesced) and records its sum
-__global__ __launch_bounds__(SCAN_T) void k_scan_blocks(const uint32_t* count, uint32_t* start,
+__device__ __forceinline__ void scan_blocks_body(const uint32_t* count, uint32_t* start,
                                                         uint32_t* block_sum, int n) {
     const int i = blockIdx.x * SCAN_T + threadIdx.x;
     uint32_t total;
@@ -239,9 +254,19 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_blocks(const uint32_t* count, u
     if (threadIdx.x == 0) block_sum[blockIdx.x] = total;
 }
 
+__global__ __launch_bounds__(SCAN_T) void k_scan_blocks(const uint32_t* count, uint32_t* start,
+                                                        uint32_t* block_sum, int n) {
+    scan_blocks_body(count, start, block_sum, n);
+}
+__global__ __launch_bounds__(SCAN_T) void k_scan_blocks_b(const ScanArgs* __restrict__ tab) {
+    const ScanArgs a = tab[blockIdx.y];
+    if (!a.on) return;
+    scan_blocks_body(a.count, a.start, a.block_sum, a.n);
+}
+
 // pass 2: every block adds the sum of the blocks before it; the last one
 // also writes start[n] (the particle count)
-__global__ __launch_bounds__(SCAN_T) void k_scan_add(uint32_t* start, const uint32_t* block_sum,
+__device__ __forceinline__ void scan_add_body(uint32_t* start, const uint32_t* block_sum,
                                                      int n, int nblocks) {
     const int t = threadIdx.x;
     uint32_t total;
@@ -253,6 +278,23 @@ __global__ __launch_bounds__(SCAN_T) void k_scan_add(uint32_t* start, const uint
     const int i = blockIdx.x * SCAN_T + t;
     if (i < n) start[i] += mine;
     if (blockIdx.x == nblocks - 1 && t == 0) start[n] = total;
+}
+
+__global__ __launch_bounds__(SCAN_T) void k_scan_add(uint32_t* start, const uint32_t* block_sum,
+                                                     int n, int nblocks) {
+    scan_add_body(start, block_sum, n, nblocks);
+}
+__global__ __launch_bounds__(SCAN_T) void k_scan_add_b(const ScanArgs* __restrict__ tab,
+                                                       int nblocks) {
+    const ScanArgs a = tab[blockIdx.y];
+    if (!a.on) return;
+    scan_add_body(a.start, a.block_sum, a.n, nblocks);
+}
+
+void launch_scan_batch(const ScanArgs* tab, int n, int slots, hipStream_t st) {
+    const int nb = (n + SCAN_T - 1) / SCAN_T;
+    hipLaunchKernelGGL(k_scan_blocks_b, dim3(nb, slots), dim3(SCAN_T), 0, st, tab);
+    hipLaunchKernelGGL(k_scan_add_b, dim3(nb, slots), dim3(SCAN_T), 0, st, tab, nb);
 }
 
 void launch_scan(const uint32_t* count, uint32_t* start, uint32_t* block_sum, int n,
@@ -273,7 +315,7 @@ constexpr int SU = 4;
 // With TAN the two tangent arrays of tc ([3][n] each) travel with the
 // particles (the forward-mode pass keeps its tangents in tile order).
 template <class T, bool TAN>
-__global__ __launch_bounds__(PB) void k_scatter(Parts<T> src, Parts<T> dst, SortBufs s, Geo g,
+__device__ __forceinline__ void scatter_body(Parts<T> src, Parts<T> dst, SortBufs s, Geo g,
                                                 TanCarry<T> tc) {
     const long n = g.npart;
     for (long base = blockIdx.x * (long)(PB * SU); base < n; base += (long)gridDim.x * PB * SU) {
@@ -325,6 +367,18 @@ __global__ __launch_bounds__(PB) void k_scatter(Parts<T> src, Parts<T> dst, Sort
             dst.id[d] = idv[u];
         }
     }
+}
+
+template <class T, bool TAN>
+__global__ __launch_bounds__(PB) void k_scatter(Parts<T> src, Parts<T> dst, SortBufs s, Geo g,
+                                                TanCarry<T> tc) {
+    scatter_body<T, TAN>(src, dst, s, g, tc);
+}
+template <class T>
+__global__ __launch_bounds__(PB) void k_scatter_b(const ScatterArgs<T>* __restrict__ tab) {
+    const ScatterArgs<T> a = tab[blockIdx.y];
+    if (!a.on) return;
+    scatter_body<T, false>(a.src, a.dst, a.s, a.g, TanCarry<T>());
 }
 
 template <class T>
@@ -411,7 +465,7 @@ __device__ __forceinline__ void paint_load_batch(const Parts<T>& p, long n, uint
 // vals = xdot ([3][n] cells): corner c of a particle receives
 // mass sum_a (dW_c/du_a) xdot_a (vmax_bits then bounds mass sum_a |xdot_a|).
 template <class T, int G, bool TAN>
-__global__ __launch_bounds__(PBP) void k_paint_group(Parts<T> p, SortBufs s, Geo g, T mass, T* rho,
+__device__ __forceinline__ void paint_group_body(Parts<T> p, SortBufs s, Geo g, T mass, T* rho,
                                                      T* halo, const T* vals,
                                                      const uint32_t* vmax_bits) {
     using BX = PaintBox<G>;
@@ -495,6 +549,19 @@ __global__ __launch_bounds__(PBP) void k_paint_group(Parts<T> p, SortBufs s, Geo
         halo_coords_g<G>(h, x, y, z);
         halo[(long)grp * BX::HALO + h] = A::dec(box[(x * TE + y) * BX::EZ + z], inv_scale);
     }
+}
+
+template <class T, int G, bool TAN>
+__global__ __launch_bounds__(PBP) void k_paint_group(Parts<T> p, SortBufs s, Geo g, T mass, T* rho,
+                                                     T* halo, const T* vals,
+                                                     const uint32_t* vmax_bits) {
+    paint_group_body<T, G, TAN>(p, s, g, mass, rho, halo, vals, vmax_bits);
+}
+template <class T, int G>
+__global__ __launch_bounds__(PBP) void k_paint_group_b(const PaintArgs<T>* __restrict__ tab) {
+    const PaintArgs<T> a = tab[blockIdx.y];
+    if (!a.on) return;
+    paint_group_body<T, G, false>(a.p, a.s, a.g, a.mass, a.rho, a.halo, nullptr, nullptr);
 }
 
 // Add the upper shells of the neighbouring groups into the low faces of each
@@ -691,7 +758,7 @@ __device__ __forceinline__ void readout_load_batch(const Parts<T>& p, long n, ui
 }
 
 template <class T>
-__global__ __launch_bounds__(PBR) void k_readout(Parts<T> p, SortBufs s, Geo g, const T* f0,
+__device__ __forceinline__ void readout_body(Parts<T> p, SortBufs s, Geo g, const T* f0,
                                                 const T* f1, const T* f2, T kick, int do_kick,
                                                 uint32_t* status, ReadoutNext<T> nx) {
     constexpr int TC = RC;
@@ -771,6 +838,19 @@ __global__ __launch_bounds__(PBR) void k_readout(Parts<T> p, SortBufs s, Geo g, 
             }
         }
     }
+}
+
+template <class T>
+__global__ __launch_bounds__(PBR) void k_readout(Parts<T> p, SortBufs s, Geo g, const T* f0,
+                                                const T* f1, const T* f2, T kick, int do_kick,
+                                                uint32_t* status, ReadoutNext<T> nx) {
+    readout_body<T>(p, s, g, f0, f1, f2, kick, do_kick, status, nx);
+}
+template <class T>
+__global__ __launch_bounds__(PBR) void k_readout_b(const ReadoutArgs<T>* __restrict__ tab) {
+    const ReadoutArgs<T> a = tab[blockIdx.y];
+    if (!a.on) return;
+    readout_body<T>(a.p, a.s, a.g, a.f0, a.f1, a.f2, a.kick, a.do_kick, a.status, a.nx);
 }
 
 template <class T>
@@ -924,6 +1004,36 @@ void launch_noise(T* out, long n, uint64_t seed, hipStream_t st) {
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_noise<T>, dim3(blocks), dim3(PB), 0, st, out, n, seed, (uint64_t)0);
 }
+
+template <class T>
+void launch_scatter_batch(const ScatterArgs<T>* tab, const Geo& g, int slots, hipStream_t st) {
+    long blocks = (g.npart + PB * SU - 1) / (PB * SU);
+    if (blocks > 16384) blocks = 16384;
+    hipLaunchKernelGGL((k_scatter_b<T>), dim3(blocks, slots), dim3(PB), 0, st, tab);
+}
+
+template <class T>
+void launch_paint_batch(const PaintArgs<T>* tab, const Geo& g, int slots, hipStream_t st) {
+    const int G = paint_group_size(g.nt, sizeof(T));
+    const int groups = g.nt * g.nt * (g.nt / G);
+    if (G == 2)
+        hipLaunchKernelGGL((k_paint_group_b<T, 2>), dim3(groups, slots), dim3(PBP), 0, st, tab);
+    else
+        hipLaunchKernelGGL((k_paint_group_b<T, 1>), dim3(groups, slots), dim3(PBP), 0, st, tab);
+}
+
+template <class T>
+void launch_readout_batch(const ReadoutArgs<T>* tab, const Geo& g, int slots, hipStream_t st) {
+    const int ntiles = g.nt * g.nt * g.nt;
+    hipLaunchKernelGGL(k_readout_b<T>, dim3(ntiles, slots), dim3(PBR), 0, st, tab);
+}
+
+#define ML_INST_BATCH(T)                                                                           \
+    template void launch_scatter_batch<T>(const ScatterArgs<T>*, const Geo&, int, hipStream_t);   \
+    template void launch_paint_batch<T>(const PaintArgs<T>*, const Geo&, int, hipStream_t);       \
+    template void launch_readout_batch<T>(const ReadoutArgs<T>*, const Geo&, int, hipStream_t);
+ML_INST_BATCH(float)
+ML_INST_BATCH(double)
 
 #define ML_INST(T)                                                                                \
     template void launch_fill<T>(T*, T, long, hipStream_t);                                       \

@@ -360,3 +360,68 @@ def run_noalloc(noise: torch.Tensor, a_grid, kappa: torch.Tensor, np_side, nm_si
                                _ptr(noise), a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                len(a) - 1, _ptr(kappa)), "pm_run_noalloc")
     return kappa
+
+
+class Batch:
+    """Same-shape simulations stepped together (pm_batch_*): one launch per
+    pass over every slot, replayed from a HIP graph.  `shape` is any
+    Simulation of the shape (its cosmology is not used)."""
+
+    def __init__(self, shape: "Simulation", capacity: int, use_graph: bool = True,
+                 stream: Optional[torch.cuda.Stream] = None):
+        p = make_params(shape.np_side, shape.nm_side, shape.box, dtype=shape.dtype)
+        l = make_lens(shape.npix, shape.fov_deg, shape.z_src)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        st = ctypes.c_void_p(stream.cuda_stream) if stream is not None else None
+        check(lib().pm_batch_create(ctypes.byref(p), ctypes.byref(l), int(capacity),
+                                    int(bool(use_graph)), st, ctypes.byref(h)),
+              "pm_batch_create")
+        self._h = h
+        self._sims = {}
+
+    def attach(self, sim: "Simulation", a_grid, kappa: Optional[torch.Tensor] = None) -> int:
+        a = np.ascontiguousarray(a_grid, dtype=np.float64)
+        slot = ctypes.c_int32()
+        check(lib().pm_batch_attach(self._h, sim._h,
+                                    a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                    len(a) - 1, ctypes.byref(slot)), "pm_batch_attach")
+        self._sims[slot.value] = (sim, a)
+        if kappa is not None:
+            self.lens(sim, kappa)
+        return slot.value
+
+    def lens(self, sim: "Simulation", kappa: Optional[torch.Tensor]):
+        check(lib().pm_batch_lens(self._h, sim._h, _ptr(kappa)), "pm_batch_lens")
+
+    def step(self) -> int:
+        """One fused step of every slot with steps left; returns how many
+        still have steps left."""
+        r = ctypes.c_int32()
+        check(lib().pm_batch_step(self._h, ctypes.byref(r)), "pm_batch_step")
+        return r.value
+
+    def detach(self, sim: "Simulation"):
+        check(lib().pm_batch_detach(self._h, sim._h), "pm_batch_detach")
+        for k, (s, a) in list(self._sims.items()):
+            if s is sim:
+                del self._sims[k]
+                if len(a) > 1:
+                    sim.a = float(a[-1])
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            lib().pm_batch_destroy(self._h)
+            self._h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -81,14 +81,18 @@ def test_footprint_counts_the_optional_modes(lib):
 
 def test_device_memory_is_allocated_only_at_creation():
     """Every hipMalloc / hipFree of the simulation library sits in pm_create's
-    arena set-up or the handle's destructor (capi.cpp), or in the serving
+    arena set-up or the handle's destructor, or in pm_batch_create's
+    parameter block and the batch's destructor (capi.cpp), or in the serving
     loop's slot management (server.cpp); no other source allocates."""
     csrc = os.path.join(ROOT, "paper_2012_07266_amd", "csrc")
     for f in sorted(os.listdir(csrc)):
         src = open(os.path.join(csrc, f)).read()
         calls = re.findall(r"\bhip(?:Malloc\w*|Free|ExtMalloc\w*)\s*\(", src)
         if f == "capi.cpp":
-            assert len(calls) == 2, calls  # the arena and its release
+            # the arena and its release; the batch's block and its release
+            assert len(calls) == 4, calls
+            for fn in ("int create(", "~Sim()", "~Batch()"):
+                assert fn in src
         elif f != "server.cpp":
             assert not calls, (f, calls)
 
