@@ -341,12 +341,17 @@ def gradient_bench(reps=3):
             "jvp_finite": jvp_finite}
 
 
-def serving_bench(n_requests):
+SERVING_FORMS = (("batched", 8, True), ("streams", 8, False), ("plain", 1, False))
+
+
+def serving_bench(n_requests, rates=(20.0, 100.0, 200.0)):
     """Poisson streams of serving requests: sizes 64^3/128^3, 128^3/256^3,
     192^3/384^3 (box = Np Mpc/h), 10-30 steps from a = 0.1, Om ~ U[0.25, 0.35],
-    s8 ~ U[0.7, 0.9], one 512^2 map over 2 deg at z_s = 1; served (up to 8
-    concurrent, continuous batching) against plain (one at a time, FIFO),
-    at 20 requests/s and at a saturating 100 requests/s."""
+    s8 ~ U[0.7, 0.9], one 512^2 map over 2 deg at z_s = 1, in three forms:
+    batched (up to 8 running, same-shape requests stepped together by
+    batched launches replayed from a HIP graph), streams (up to 8 running,
+    each on a stream of its own) and plain (one at a time, FIFO); at 20
+    requests/s and at the saturating 100 and 200 requests/s."""
     import workloads as W
     from paper_2012_07266_amd.serve import poisson_arrivals, run_stream
     gen = np.random.Generator(np.random.Philox(key=6))
@@ -355,11 +360,11 @@ def serving_bench(n_requests):
     res = {"workload": (f"{n_requests} requests, sizes uniform over 64^3/128^3, 128^3/256^3, "
                         "192^3/384^3, 10-30 steps, 1 x 512^2 map; Poisson arrivals"),
            "hbm_budget_gb": budget / 2 ** 30, "served_max_active": 8}
-    for rate in (20.0, 100.0):
+    for rate in rates:
         arr = poisson_arrivals(n_requests, rate, seed=int(rate))
         row = {}
-        for form, act in (("served", 8), ("plain", 1)):
-            r, _ = run_stream(reqs, arr, budget, act)
+        for form, act, batched in SERVING_FORMS:
+            r, _ = run_stream(reqs, arr, budget, act, batched=batched)
             row[form] = {"p50_ms": r.latency_p50_ms, "p99_ms": r.latency_p99_ms,
                          "mean_ms": r.latency_mean_ms, "particle_steps_per_s": r.throughput,
                          "makespan_s": r.makespan_s, "peak_running": r.peak_running}
@@ -372,7 +377,7 @@ def large_mix_bench(n_background=40, rate=20.0):
     with a Poisson stream of small requests behind it at `rate` per second:
     64^3 particles, 128^3 mesh, box 64 Mpc/h, 10-30 steps from a = 0.1,
     Om ~ U[0.25, 0.35], s8 ~ U[0.7, 0.9], one 512^2 map over 2 deg at z_s = 1.
-    Served (up to 8 concurrent) against plain (one at a time, FIFO)."""
+    In the three forms of serving_bench."""
     import workloads as W
     from paper_2012_07266_amd.serve import poisson_arrivals, run_stream
     gen = np.random.Generator(np.random.Philox(key=8))
@@ -389,8 +394,8 @@ def large_mix_bench(n_background=40, rate=20.0):
                         f"maps) at t = 0, then {n_background} requests of 64^3/128^3, 10-30 "
                         f"steps, 1 x 512^2 map, Poisson at {rate:g}/s"),
            "hbm_budget_gb": budget / 2 ** 30, "served_max_active": 8}
-    for form, act in (("served", 8), ("plain", 1)):
-        r, _ = run_stream(reqs, arr, budget, act)
+    for form, act, batched in SERVING_FORMS:
+        r, _ = run_stream(reqs, arr, budget, act, batched=batched)
         lat = np.array(r.latencies_ms)
         res[form] = {"large_latency_ms": float(lat[0]),
                      "background_p50_ms": float(np.percentile(lat[1:], 50)),

@@ -440,6 +440,15 @@ typedef struct pm_srv pm_srv;
 /* Errors: PM_EINVAL (max_active < 1, zero budget), PM_ENOMEM. */
 int pm_srv_create(size_t hbm_budget, int32_t max_active, pm_srv** out);
 
+/* The same server with batched stepping when `batched` is 1: every running
+ * request is a slot of the batch of its shape (pm_batch_*, capacity
+ * max_active, each batch on a stream of its own), so same-shape requests
+ * step together in one set of launches replayed from a HIP graph, up to two
+ * batched steps in flight per batch; requests of other shapes run in their
+ * own batches side by side.  batched = 0 is pm_srv_create.  A request's maps
+ * are bit for bit those of the other forms.  Errors as pm_srv_create. */
+int pm_srv_create_ex(size_t hbm_budget, int32_t max_active, int32_t batched, pm_srv** out);
+
 /* Queue a request; *id_out identifies it.  The request's maps start at zero
  * and receive every shell of its steps.  Errors: PM_EINVAL (invalid
  * parameters or time range), PM_ENOMEM (footprint above the budget),
@@ -485,9 +494,9 @@ int pm_srv_destroy(pm_srv* s);
  * PM_EDEVICE.
  * pm_batch_attach: sim (same shape, no sub-evolution, PGD or rotation) must
  * be at a_grid[0], its initial conditions made (pm_init_ic*); a_grid [0 ..
- * nsteps] (host, copied) is its time grid.  Waits for the handle's stream,
- * then enqueues the first step's half-kick, drift and sort keys on the
- * batch's stream.  *slot_out (may be NULL) receives the slot.  Until
+ * nsteps] (host, copied) is its time grid.  The batch's stream waits (an
+ * event, not the host) for the work enqueued on the handle's stream so far,
+ * then gets the first step's half-kick, drift and sort keys.  *slot_out (may be NULL) receives the slot.  Until
  * pm_batch_detach the handle belongs to the batch (no other call on it).
  * Errors: PM_EINVAL (NULL, shape or mode mismatch, attached already,
  * invalid grid), PM_ESTATE (state not at a_grid[0]), PM_EFULL.
@@ -500,10 +509,11 @@ int pm_srv_destroy(pm_srv* s);
  * batch's stream; *running_out (may be NULL) receives the number of slots
  * with steps left after it.  A slot whose last step this was is at the end
  * of its time grid.
- * pm_batch_detach: waits for the batch's stream and frees sim's slot; the
- * handle then is at the end of its grid if it finished it, else between
- * two steps, where only pm_init_ic*, pm_set_state or pm_checkpoint_load
- * can continue it.  Errors: PM_EINVAL (not attached). */
+ * pm_batch_detach: frees sim's slot; the handle's stream waits (an event)
+ * for the batch's work enqueued so far, so calls on the handle see its
+ * results.  The handle then is at the end of its grid if it finished it,
+ * else between two steps, where only pm_init_ic*, pm_set_state or
+ * pm_checkpoint_load can continue it.  Errors: PM_EINVAL (not attached). */
 typedef struct pm_batch pm_batch;
 int pm_batch_create(const pm_params* p, const lens_params* l, int32_t capacity, int32_t use_graph,
                     void* hip_stream, pm_batch** out);

@@ -89,6 +89,8 @@ SIGNATURES = {
     "pm_profile_read": (_I, [_P, _I, ctypes.c_char_p, ctypes.POINTER(_D),
                              ctypes.POINTER(ctypes.c_long), ctypes.POINTER(_I)]),
     "pm_srv_create": (_I, [ctypes.c_size_t, ctypes.c_int32, ctypes.POINTER(_P)]),
+    "pm_srv_create_ex": (_I, [ctypes.c_size_t, ctypes.c_int32, ctypes.c_int32,
+                              ctypes.POINTER(_P)]),
     "pm_srv_submit": (_I, [_P, ctypes.POINTER(PmRequest), ctypes.POINTER(ctypes.c_int64)]),
     "pm_srv_wait": (_I, [_P, ctypes.c_int64, _D]),
     "pm_srv_result": (_I, [_P, ctypes.c_int64, _P, ctypes.POINTER(_D)]),

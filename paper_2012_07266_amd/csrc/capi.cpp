@@ -1430,9 +1430,9 @@ template <class T> struct Sim final : SimBase {
                nsrc == ns && !interp && !pgd && !rot;
     }
 
+    // bst must already wait for the handle's own stream (its initial conditions).
     int batch_begin(hipStream_t bst, double a0, double a1) {
         if (a_cur < 0 || std::fabs(a0 - a_cur) > 1e-12 * std::fabs(a_cur) + 1e-15) return PM_ESTATE;
-        HIPCHK(hipStreamSynchronize(st));  // the handle's own work (its initial conditions)
         const double ah = 0.5 * (a0 + a1);
         launch_fill_u32(sb.count, 0u, ntiles, bst);
         launch_kick_drift_key<T>(cur, sb, geo, (T)cosmo.kick(a0, ah, a0),
@@ -1562,6 +1562,7 @@ template <class T> struct Batch final : BatchBase {
     char* dev = nullptr;
     char* host[2] = {nullptr, nullptr};
     hipEvent_t copied[2] = {nullptr, nullptr};
+    hipEvent_t handoff = nullptr;  // orders a handle's stream with the batch's
     int ring = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -1574,6 +1575,7 @@ template <class T> struct Batch final : BatchBase {
             if (copied[i]) (void)hipEventDestroy(copied[i]);
             if (host[i]) (void)hipHostFree(host[i]);
         }
+        if (handoff) (void)hipEventDestroy(handoff);
         if (dev) (void)hipFree(dev);
         if (own_stream && st) (void)hipStreamDestroy(st);
     }
@@ -1636,6 +1638,14 @@ template <class T> struct Batch final : BatchBase {
             std::memset(host[i], 0, bytes);
             HIPCHK(hipEventCreateWithFlags(&copied[i], hipEventDisableTiming));
         }
+        HIPCHK(hipEventCreateWithFlags(&handoff, hipEventDisableTiming));
+        return PM_OK;
+    }
+
+    // Later work on `to` waits for everything enqueued on `from` so far.
+    int order(hipStream_t from, hipStream_t to) {
+        HIPCHK(hipEventRecord(handoff, from));
+        HIPCHK(hipStreamWaitEvent(to, handoff, 0));
         return PM_OK;
     }
 
@@ -1654,8 +1664,12 @@ template <class T> struct Batch final : BatchBase {
             if (!(a_grid[i + 1] > 0 && a_grid[i + 1] <= 1.5)) return PM_EINVAL;
         int k = find(nullptr);
         if (k < 0) return PM_EFULL;
-        int rc = sim->batch_begin(st, a_grid[0], a_grid[1]);
+        if (sim->a_cur < 0 ||
+            std::fabs(a_grid[0] - sim->a_cur) > 1e-12 * std::fabs(sim->a_cur) + 1e-15)
+            return PM_ESTATE;
+        int rc = order(sim->st, st);  // the handle's initial conditions first
         if (rc) return rc;
+        if ((rc = sim->batch_begin(st, a_grid[0], a_grid[1]))) return rc;
         Slot& s = slots[k];
         s.h = h;
         s.sim = sim;
@@ -1676,8 +1690,10 @@ template <class T> struct Batch final : BatchBase {
     int detach(pm_sim* h) override {
         int k = find(h);
         if (k < 0) return PM_EINVAL;
-        HIPCHK(hipStreamSynchronize(st));
         Slot& s = slots[k];
+        // the handle's later work waits for the batch's steps enqueued so far
+        int rc = order(st, s.sim->st);
+        if (rc) return rc;
         if (s.next < (int)s.agrid.size() - 1) s.sim->batch_abandon();
         s = Slot{};
         return PM_OK;

@@ -9,12 +9,20 @@
 //    pm_reconfigure), else frees idle arenas, least recently used first,
 //    and creates one on a stream of its own.  It then enqueues the seeded
 //    initial conditions and hands the slot to the issue thread.
-//  - issue: keeps up to `depth` chunks of PM steps (pm_run: steps with the
+//  - issue, in one of two forms:
+//    streams: keeps up to `depth` chunks of PM steps (pm_run: steps with the
 //    projection of their shells) in flight on every running slot,
 //    round-robin over slots, so the kernels of different requests overlap
-//    on the device.  When a slot has issued its last step it copies the
-//    maps to pinned host memory; when that copy completes it hands the maps
-//    to the request and returns the arena to the idle pool.
+//    on the device (as far as the device's hardware queues let streams run
+//    side by side);
+//    batched: attaches every running slot to the batch of its shape
+//    (pm_batch_*: one launch per pass over the batch's slots, replayed from
+//    a HIP graph) and keeps up to `depth` batched steps in flight per batch,
+//    so same-shape requests step together in one set of launches whatever
+//    the number of hardware queues.
+//    When a slot has issued its last step it copies the maps to pinned host
+//    memory; when that copy completes it hands the maps to the request and
+//    returns the arena to the idle pool.
 // The same kernels run as for a lone simulation, and paint and projection
 // accumulate in fixed point, so a request's maps are bitwise the same alone
 // and in any mix.
@@ -102,6 +110,7 @@ Key key_of(const pm_request& r) {
 struct pm_srv {
     size_t budget = 0;
     int max_active = 1;
+    int batch_cap = 0;  // 0: the streams form; else batches of this many slots
     int depth = 2;   // chunks in flight per request
     int chunk = 1;   // steps per chunk (1: finest interleaving)
     clk::time_point t0 = clk::now();
@@ -151,6 +160,17 @@ struct pm_srv {
 
     void admit_loop();
     void issue_loop();
+    void issue_loop_batched();
+
+    // Called with mu held: hand the maps over and return the slot.
+    void complete_locked(std::unique_ptr<Slot> own, int rc) {
+        Req& q = *own->req;
+        if (rc == PM_OK)
+            q.kappa.assign(reinterpret_cast<unsigned char*>(own->khost),
+                           reinterpret_cast<unsigned char*>(own->khost) + own->kbytes);
+        finish_locked(own->req, rc);
+        release_locked(std::move(own));
+    }
 };
 
 void pm_srv::admit_loop() {
@@ -232,6 +252,7 @@ void pm_srv::admit_loop() {
 }
 
 void pm_srv::issue_loop() {
+    if (batch_cap > 0) return issue_loop_batched();
     std::vector<std::unique_ptr<Slot>> active;
     for (;;) {
         {
@@ -305,15 +326,143 @@ void pm_srv::issue_loop() {
     }
 }
 
+// The batched form.  One batch per shape (Np, Nm, npix, nsrc, dtype), each
+// on a stream of its own; a slot stays attached from admission to its last
+// step.  Per batch, up to `depth` steps are in flight; after the step that
+// ends a slot's grid, the copy of its maps follows on the batch's stream.
+void pm_srv::issue_loop_batched() {
+    struct B {
+        Key key{};
+        pm_batch* b = nullptr;
+        hipStream_t st = nullptr;
+        std::vector<std::unique_ptr<Slot>> slots;
+        std::vector<int> left;  // steps still to issue, per slot
+        std::deque<hipEvent_t> inflight;
+        std::vector<hipEvent_t> spare;
+    };
+    std::vector<std::unique_ptr<B>> batches;
+    auto batch_for = [&](const Key& k, const pm_request& r) -> B* {
+        for (auto& b : batches)
+            if (b->key == k) return b.get();
+        std::unique_ptr<B> nb(new B);
+        nb->key = k;
+        if (hipStreamCreateWithFlags(&nb->st, hipStreamNonBlocking) != hipSuccess) return nullptr;
+        if (pm_batch_create(&r.p, &r.l, max_active, 1, nb->st, &nb->b) != PM_OK) {
+            (void)hipStreamDestroy(nb->st);
+            return nullptr;
+        }
+        batches.push_back(std::move(nb));
+        return batches.back().get();
+    };
+    for (;;) {
+        std::vector<std::unique_ptr<Slot>> fresh;
+        {
+            std::lock_guard<std::mutex> lk(mu);
+            while (!ready.empty()) {
+                fresh.push_back(std::move(ready.front()));
+                ready.pop_front();
+            }
+            bool any = false;
+            for (auto& b : batches) any = any || !b->slots.empty();
+            if (stop && fresh.empty() && !any && running == 0) break;
+        }
+        bool progress = !fresh.empty();
+        for (auto& s : fresh) {
+            Req& q = *s->req;
+            B* b = batch_for(s->key, q.r);
+            int rc = b ? pm_batch_attach(b->b, s->sim, q.agrid.data(), q.r.nsteps, nullptr)
+                       : PM_EDEVICE;
+            if (rc == PM_OK) rc = pm_batch_lens(b->b, s->sim, s->kdev);
+            if (rc != PM_OK) {
+                std::lock_guard<std::mutex> lk(mu);
+                finish_locked(s->req, rc);
+                release_locked(std::move(s));
+                continue;
+            }
+            b->slots.push_back(std::move(s));
+            b->left.push_back(q.r.nsteps);
+        }
+        for (auto& bp : batches) {
+            B& b = *bp;
+            while (!b.inflight.empty() && hipEventQuery(b.inflight.front()) == hipSuccess) {
+                b.spare.push_back(b.inflight.front());
+                b.inflight.pop_front();
+                progress = true;
+            }
+            bool work = false;
+            for (int l : b.left) work = work || l > 0;
+            int rc = PM_OK;
+            while (rc == PM_OK && work && (int)b.inflight.size() < depth) {
+                rc = pm_batch_step(b.b, nullptr);
+                work = false;
+                for (size_t i = 0; i < b.slots.size() && rc == PM_OK; ++i) {
+                    if (b.left[i] <= 0) continue;
+                    if (--b.left[i] == 0) {  // its last step: the maps follow
+                        Slot& s = *b.slots[i];
+                        if (hipMemcpyAsync(s.khost, s.kdev, s.kbytes, hipMemcpyDeviceToHost, b.st) !=
+                                hipSuccess ||
+                            hipEventRecord(s.done_ev, b.st) != hipSuccess)
+                            rc = PM_EDEVICE;
+                        s.finishing = true;
+                    }
+                    work = work || b.left[i] > 0;
+                }
+                hipEvent_t e = nullptr;
+                if (!b.spare.empty()) {
+                    e = b.spare.back();
+                    b.spare.pop_back();
+                } else if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+                    rc = PM_EDEVICE;
+                }
+                if (e && hipEventRecord(e, b.st) != hipSuccess) rc = PM_EDEVICE;
+                if (e) b.inflight.push_back(e);
+                progress = true;
+            }
+            for (size_t i = 0; i < b.slots.size();) {
+                Slot& s = *b.slots[i];
+                const bool done = rc != PM_OK ||
+                                  (s.finishing && hipEventQuery(s.done_ev) == hipSuccess);
+                if (!done) {
+                    ++i;
+                    continue;
+                }
+                int st = rc;
+                if (st == PM_OK) st = pm_sync(s.sim);  // the handle's sticky status
+                int rd = pm_batch_detach(b.b, s.sim);
+                if (st == PM_OK) st = rd;
+                std::unique_ptr<Slot> own = std::move(b.slots[i]);
+                b.slots.erase(b.slots.begin() + i);
+                b.left.erase(b.left.begin() + i);
+                std::lock_guard<std::mutex> lk(mu);
+                complete_locked(std::move(own), st);
+                progress = true;
+            }
+        }
+        if (!progress) std::this_thread::sleep_for(std::chrono::microseconds(20));
+    }
+    for (auto& b : batches) {
+        (void)hipStreamSynchronize(b->st);
+        for (hipEvent_t e : b->inflight) (void)hipEventDestroy(e);
+        for (hipEvent_t e : b->spare) (void)hipEventDestroy(e);
+        pm_batch_destroy(b->b);
+        (void)hipStreamDestroy(b->st);
+    }
+}
+
 extern "C" {
 
 int pm_srv_create(size_t hbm_budget, int32_t max_active, pm_srv** out) {
-    if (!out || max_active < 1 || hbm_budget == 0) return PM_EINVAL;
+    return pm_srv_create_ex(hbm_budget, max_active, 0, out);
+}
+
+int pm_srv_create_ex(size_t hbm_budget, int32_t max_active, int32_t batched, pm_srv** out) {
+    if (!out || max_active < 1 || hbm_budget == 0 || batched < 0) return PM_EINVAL;
     *out = nullptr;
     pm_srv* s = new (std::nothrow) pm_srv;
     if (!s) return PM_ENOMEM;
     s->budget = hbm_budget;
     s->max_active = max_active;
+    s->batch_cap = batched ? max_active : 0;
     try {
         s->admit_thr = std::thread([s] { s->admit_loop(); });
         s->issue_thr = std::thread([s] { s->issue_loop(); });

@@ -7,7 +7,10 @@ clock; admission, slots and stepping run in the library's own threads).
 
 `run_stream` replays a stream of requests at their arrival times and
 reports latency percentiles and throughput; `max_active = 1` is the plain
-form (one simulation at a time, first in first out, the same kernels).
+form (one simulation at a time, first in first out, the same kernels), and
+`batched=True` steps the running requests of each shape together
+(pm_srv_create_ex: batched launches replayed from a HIP graph) instead of
+on streams of their own.
 """
 from __future__ import annotations
 
@@ -29,12 +32,12 @@ def _check(rc, what):
 
 
 class Server:
-    def __init__(self, hbm_budget: int, max_active: int, dtype=np.float32):
+    def __init__(self, hbm_budget: int, max_active: int, dtype=np.float32, batched=False):
         self._L = _lib.lib()
         self.dtype = np.dtype(dtype)
         h = ctypes.c_void_p()
-        _check(self._L.pm_srv_create(int(hbm_budget), int(max_active), ctypes.byref(h)),
-               "pm_srv_create")
+        _check(self._L.pm_srv_create_ex(int(hbm_budget), int(max_active), int(bool(batched)),
+                                        ctypes.byref(h)), "pm_srv_create_ex")
         self._h = h
         self._shapes = {}
 
@@ -102,11 +105,11 @@ class StreamResult:
 
 
 def run_stream(requests: Sequence, arrivals: Sequence[float], hbm_budget: int,
-               max_active: int, dtype=np.float32, keep_maps: bool = False):
+               max_active: int, dtype=np.float32, keep_maps: bool = False, batched=False):
     """Submit requests[i] at time arrivals[i] (seconds from the start) and
     wait for all.  Returns (StreamResult, maps or None)."""
     maps: List = [None] * len(requests)
-    with Server(hbm_budget, max_active, dtype) as srv:
+    with Server(hbm_budget, max_active, dtype, batched=batched) as srv:
         # untimed: one short request per shape, so that both forms start with
         # an arena of every shape in the pool
         shapes = {}

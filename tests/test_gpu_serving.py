@@ -140,3 +140,45 @@ def test_admission_by_footprint():
     log(f"admission: peak running {st['peak_running']}, peak {st['peak_bytes']} of {budget}")
     assert st["peak_running"] == 1 and st["peak_bytes"] <= budget
     assert st["completed"] == 4
+
+
+def test_result_alone_equals_result_in_the_batched_mix():
+    """The batched server (same-shape requests stepped together, replayed
+    from a HIP graph): every request's maps are bitwise those of the plain
+    form, for a mix of three shapes arriving together."""
+    from paper_2012_07266_amd.serve import Server
+    reqs = [_req(0, 64, 128, 10, 0.31, 0.78), _req(1, 128, 256, 6, 0.26, 0.88),
+            _req(2, 32, 64, 12, 0.34, 0.72), _req(3, 64, 128, 8, 0.29, 0.81),
+            _req(4, 64, 128, 5, 0.33, 0.75), _req(5, 32, 64, 7, 0.27, 0.86)]
+    log("serving: alone vs batched mix")
+    with Server(16 << 30, 1) as srv:
+        alone = [srv.result(srv.submit(r), timeout=120)[0] for r in reqs]
+    with Server(16 << 30, 6, batched=True) as srv:
+        ids = [srv.submit(r) for r in reqs]
+        mix = [srv.result(i, timeout=120)[0] for i in ids]
+        st = srv.stats()
+    log(f"batched mix: peak running {st['peak_running']}")
+    assert st["peak_running"] >= 2
+    for a, m in zip(alone, mix):
+        assert np.isfinite(a).all() and np.abs(a).max() > 0
+        assert np.array_equal(a, m)
+
+
+def test_batched_served_request_matches_oracle():
+    from oracle import lens, rng
+    from paper_2012_07266_amd.serve import Server
+    wl = W.Workload("served_b", 16, 32, 48.0, 0.3, 1.0, 4, 32, 3.0, (1.0,), omega_m=0.28,
+                    sigma8=0.83, seed=4242)
+    other = wl.with_(name="served_b2", box=40.0, nsteps=6, seed=4243)
+    log("batched served request vs oracle")
+    with Server(4 << 30, 2, np.float64, batched=True) as srv:
+        i0, i1 = srv.submit(wl), srv.submit(other)
+        k, t = srv.result(i0, timeout=120)
+        srv.result(i1, timeout=120)
+    c = cosmo_of(wl)
+    geom = lens.MapGeometry(wl.npix, wl.fov_deg, wl.z_src, c)
+    ref, _, _ = lens.run_lensing(rng.white_noise(16, wl.seed), c, wl.box, wl.nm_side,
+                                 wl.a_grid(), geom)
+    e = rel_rms(k, ref)
+    log(f"batched served vs oracle: kappa rel-rms {e:.2e}")
+    assert e < 1e-10
