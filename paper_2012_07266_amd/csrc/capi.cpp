@@ -149,7 +149,7 @@ struct Prof {
     bool on = false;
     std::vector<hipEvent_t> pool;
     size_t used = 0;
-    struct Rec { int name; hipEvent_t a, b; };
+    struct Rec { int name; hipEvent_t a, b; hipStream_t s; };
     std::vector<Rec> recs;
     std::vector<std::string> names;
     std::vector<double> ms;
@@ -166,18 +166,19 @@ struct Prof {
         cnt.push_back(0);
         return (int)names.size() - 1;
     }
-    void begin(const char* n) {
+    // s: the stream the timed launch goes to (NULL: the simulation's)
+    void begin(const char* n, hipStream_t s = nullptr) {
         cur = -1;
         if (!on || used + 2 > pool.size()) return;
         if (!only.empty() && only != n) return;
         cur = (int)recs.size();
-        recs.push_back({name_id(n), pool[used], pool[used + 1]});
+        recs.push_back({name_id(n), pool[used], pool[used + 1], s ? s : st});
         used += 2;
-        (void)hipEventRecord(recs.back().a, st);
+        (void)hipEventRecord(recs.back().a, recs.back().s);
     }
     void end() {
         if (cur < 0) return;
-        (void)hipEventRecord(recs[cur].b, st);
+        (void)hipEventRecord(recs[cur].b, recs[cur].s);
         cur = -1;
     }
     int enable(bool e, hipStream_t s) {
@@ -192,7 +193,8 @@ struct Prof {
     }
     int resolve() {
         if (recs.empty()) return PM_OK;
-        if (hipStreamSynchronize(st) != hipSuccess) return PM_EDEVICE;
+        for (auto& r : recs)
+            if (hipEventSynchronize(r.b) != hipSuccess) return PM_EDEVICE;
         for (auto& r : recs) {
             float t = 0.f;
             if (hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) return PM_EDEVICE;
@@ -210,7 +212,7 @@ struct Prof {
 
 struct ProfScope {
     Prof& p;
-    ProfScope(Prof& pr, const char* n) : p(pr) { p.begin(n); }
+    ProfScope(Prof& pr, const char* n, hipStream_t s = nullptr) : p(pr) { p.begin(n, s); }
     ~ProfScope() { p.end(); }
 };
 
@@ -330,8 +332,19 @@ template <class T> struct Sim final : SimBase {
     int ntiles = 0;
 
     bool own_arena = true;  // false: the arena is the static scratch array
+    // pm_run projects each shell on a second stream, beside the paint and the
+    // force transform (the projection reads only the sorted particles; the
+    // readout, which moves them, waits for it)
+    hipStream_t st_lens = nullptr;
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr;
 
     ~Sim() override {
+        if (st_lens) {
+            (void)hipStreamSynchronize(st_lens);
+            (void)hipStreamDestroy(st_lens);
+        }
+        if (ev_fork) (void)hipEventDestroy(ev_fork);
+        if (ev_join) (void)hipEventDestroy(ev_join);
         if (arena && own_arena) (void)hipFree(arena);
     }
 
@@ -377,6 +390,13 @@ template <class T> struct Sim final : SimBase {
         geo.npart = (long)p->np * p->np * p->np;
         ntiles = geo.nt * geo.nt * geo.nkz;  // sort blocks (keys)
         ap = plan_arena(*p, *l, sizeof(T));
+        // (a handle in the static scratch creates nothing: it projects in line)
+        if (!mem && (hipStreamCreateWithFlags(&st_lens, hipStreamNonBlocking) != hipSuccess ||
+                     hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming) != hipSuccess ||
+                     hipEventCreateWithFlags(&ev_join, hipEventDisableTiming) != hipSuccess)) {
+            (void)hipGetLastError();
+            return PM_EDEVICE;
+        }
         if (mem) {
             arena = static_cast<char*>(mem);
             own_arena = false;
@@ -845,7 +865,8 @@ template <class T> struct Sim final : SimBase {
     // tile-sorted positions (which must be those at a1) into kappa.  With
     // sub-evolution the step's drift momentum is mom - sub_k2 * acc.
     // With PGD on, pgd_shift must have run for the current state.
-    int project_shell(double a0, double a1, T* kappa, T sub_k2 = T(0)) {
+    int project_shell(double a0, double a1, T* kappa, T sub_k2 = T(0), hipStream_t ls = nullptr) {
+        if (!ls) ls = st;
         LensArgs<T> la;
         MapAdd<T> mv;
         if (!plain_lens_args(a0, a1, la, mv)) return PM_OK;
@@ -860,17 +881,17 @@ template <class T> struct Sim final : SimBase {
             la.sub_dr = (T)cosmo.drift(a0, a1, ah);
             la.sub_k2 = sub_k2;
             la.pmax_bits = pmax_bits;
-            launch_fill_u32(pmax_bits, 0u, 1, st);
-            { ProfScope ps(prof, "drift_momentum_max");
-              launch_drift_momentum_max<T>(cur, geo.npart, sub_k2, pmax_bits, st); }
+            launch_fill_u32(pmax_bits, 0u, 1, ls);
+            { ProfScope ps(prof, "drift_momentum_max", ls);
+              launch_drift_momentum_max<T>(cur, geo.npart, sub_k2, pmax_bits, ls); }
         }
         if (pgd) {  // images shifted by alpha0 a1^mu times the filtered force
             la.shift = pgd_s;
             la.shift_scale = (T)(pgd_alpha0 * std::pow(a1, pgd_mu));
             la.shift_bits = pgd_bits;
         }
-        { ProfScope ps(prof, "lens_gather");
-          launch_lens_gather<T>(cur, sb, geo, la, mv, kappa, st); }
+        { ProfScope ps(prof, "lens_gather", ls);
+          launch_lens_gather<T>(cur, sb, geo, la, mv, kappa, ls); }
         return PM_OK;
     }
 
@@ -899,12 +920,26 @@ template <class T> struct Sim final : SimBase {
                 std::swap(cur.id, alt.id);
             }
             // with PGD the shift's paint and forward passes are the force's
-            if (pgd) pgd_shift(a1);
-            else paint(true);
-            int rc = project_shell(a0, a1, kap, T(0));  // mom is the drift momentum here
-            if (rc) return rc;
-            if (pgd) force_from_spectrum();
-            else fft_forward_grad(P.nm, nullptr, tw_nm, tw_hm, twp_nm, paint_halo_merge<T>(geo, halo));
+            // (and the projection needs the shift); without, the projection
+            // runs on the second stream beside the paint and the transform
+            if (pgd || !st_lens) {
+                if (pgd) pgd_shift(a1);
+                else paint(true);
+                int rc = project_shell(a0, a1, kap, T(0));  // mom is the drift momentum here
+                if (rc) return rc;
+                if (pgd) force_from_spectrum();
+                else fft_forward_grad(P.nm, nullptr, tw_nm, tw_hm, twp_nm,
+                                      paint_halo_merge<T>(geo, halo));
+            } else {
+                HIPCHK(hipEventRecord(ev_fork, st));
+                HIPCHK(hipStreamWaitEvent(st_lens, ev_fork, 0));
+                int rc = project_shell(a0, a1, kap, T(0), st_lens);
+                if (rc) return rc;
+                HIPCHK(hipEventRecord(ev_join, st_lens));
+                paint(true);
+                fft_forward_grad(P.nm, nullptr, tw_nm, tw_hm, twp_nm, paint_halo_merge<T>(geo, halo));
+                HIPCHK(hipStreamWaitEvent(st, ev_join, 0));
+            }
             const T k2 = (T)cosmo.kick(ah, a1, a1);
             ReadoutNext<T> nx;
             if (i + 1 < nsteps) {
