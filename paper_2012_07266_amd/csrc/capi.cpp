@@ -931,12 +931,12 @@ template <class T> struct Sim final : SimBase {
                 else fft_forward_grad(P.nm, nullptr, tw_nm, tw_hm, twp_nm,
                                       paint_halo_merge<T>(geo, halo));
             } else {
+                paint(true);
                 HIPCHK(hipEventRecord(ev_fork, st));
                 HIPCHK(hipStreamWaitEvent(st_lens, ev_fork, 0));
                 int rc = project_shell(a0, a1, kap, T(0), st_lens);
                 if (rc) return rc;
                 HIPCHK(hipEventRecord(ev_join, st_lens));
-                paint(true);
                 fft_forward_grad(P.nm, nullptr, tw_nm, tw_hm, twp_nm, paint_halo_merge<T>(geo, halo));
                 HIPCHK(hipStreamWaitEvent(st, ev_join, 0));
             }
