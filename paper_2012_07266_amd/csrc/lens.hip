@@ -171,7 +171,13 @@ __device__ __forceinline__ bool column_depths(T alo, T ahi, T Xa, T margin, T& z
     return zmin <= zmax;
 }
 
-constexpr int LU = 4;  // particles per thread in flight
+constexpr int LU = 4;   // particles per thread in flight
+constexpr int LQ = 128;  // entries of a wave's image queue (63 waiting + 64 new at most)
+
+// LDS bytes of the image queues of an LG-thread workgroup (float only)
+template <class T> constexpr size_t lens_queue_bytes(int lg) {
+    return sizeof(T) == 4 ? (size_t)(lg / 64) * 3 * LQ * sizeof(T) : 0;
+}
 
 // LG threads per workgroup: 256 for 32 x 32-pixel regions, 1024 for 64 x 64
 // (one workgroup per CU then holds the LDS, so it brings 16 waves)
@@ -181,6 +187,7 @@ __device__ __forceinline__ void lens_gather_body(Parts<T> p, SortBufs sb, Geo g,
     using A = LensAcc<T>;
     using S = typename A::S;
     constexpr int LUT = sizeof(T) == 4 ? LU : LU / 2;  // registers of double
+    constexpr bool COMPACT = sizeof(T) == 4;
     extern __shared__ unsigned char smem[];
     S* acc = reinterpret_cast<S*>(smem);
     const int rs = la.rs;
@@ -240,6 +247,46 @@ __device__ __forceinline__ void lens_gather_body(Parts<T> p, SortBufs sb, Geo g,
         }
     }
     const int npix2 = la.npix * la.npix;
+    // an accepted image: its weight for every source behind it, bilinearly
+    // into the region
+    auto deposit = [&](T t0, T t1, T chi) {
+        T base_w = la.wbase / (chi * a_of_chi(la, chi));
+        for (int s = 0; s < la.nsrc; ++s) {
+            T cs = la.chi_src[s];
+            if (chi < cs)
+                splat_region<T>(acc + s * rs * rs, rs, p0x, p0y, la.npix, kappa + (long)s * npix2,
+                                t0, t1, base_w * (cs - chi) / cs);
+        }
+    };
+    // float: a wave's accepted images wait in its own LDS queue (after the
+    // accumulator and the D window) until 64 of them fill every lane, so
+    // the weights and splats run on full waves, not on the few lanes of each
+    // visit that land in the region.  The queue count is wave-uniform, and
+    // a wave's LDS accesses complete in order, so no barrier is needed.
+    const int dwin = (EXT && la.sub) ? la.dwin : 0;
+    T* q = reinterpret_cast<T*>(smem + (size_t)ncell * sizeof(S) + (size_t)dwin * 2 * sizeof(T)) +
+           (tid >> 6) * 3 * LQ;
+    const int lane = tid & 63;
+    int qn = 0;
+    auto queue_push = [&](bool ok, T t0, T t1, T chi) {
+        const unsigned long long m = __ballot(ok);
+        if (!m) return;
+        if (ok) {
+            const int pos = qn + (int)__builtin_amdgcn_mbcnt_hi(
+                                     (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+            q[pos] = t0;
+            q[LQ + pos] = t1;
+            q[2 * LQ + pos] = chi;
+        }
+        qn += __popcll(m);
+        if (qn >= 64) {
+            issue_fence();  // the stores above stay before the loads
+            qn -= 64;
+            const int e = qn + lane;
+            deposit(q[e], q[LQ + e], q[2 * LQ + e]);
+            issue_fence();  // and these loads before the next stores
+        }
+    };
 
     int nz0 = (int)floor(cnear / nmf) - 1;
     if (nz0 < 0) nz0 = 0;
@@ -339,10 +386,9 @@ __device__ __forceinline__ void lens_gather_body(Parts<T> p, SortBufs sb, Geo g,
                                     }
                                 }
                             }
-#pragma unroll
-                            for (int u = 0; u < LUT; ++u) {
-                                uint32_t k = base + u * LG + tid;
-                                if (k >= hi) continue;
+                            // the particle's image in this replica: its pixel coordinates and
+                            // distance when it falls in the shell and in the region's window
+                            auto image = [&](int u, T& t0, T& t1, T& chi) -> bool {
                                 int li[3];
                                 lattice_of_l(idv[u], g.np, li);
                                 T uu[3];
@@ -378,7 +424,7 @@ __device__ __forceinline__ void lens_gather_body(Parts<T> p, SortBufs sb, Geo g,
                                     if (sym || la.shift) split_cell(uu[2], cz, fz);
                                 }
                                 T rz = uu[2] + T(nz) * nmf;
-                                if (!depth_in_shell(cz, fz, zb_near, zb_far) || !(rz > T(0))) continue;
+                                if (!depth_in_shell(cz, fz, zb_near, zb_far) || !(rz > T(0))) return false;
                                 if (EXT && la.sub) {
                                     // along the step's drift to a(chi) of the
                                     // end-of-step depth
@@ -390,29 +436,37 @@ __device__ __forceinline__ void lens_gather_body(Parts<T> p, SortBufs sb, Geo g,
                                     uu[0] += dd * pimg[0];
                                     uu[1] += dd * pimg[1];
                                     rz += dd * pimg[2];
-                                    if (!(rz > T(0))) continue;
+                                    if (!(rz > T(0))) return false;
                                 }
-                                T chi = rz * la.cell;
-                                if (!(chi < chi_max_src)) continue;
+                                chi = rz * la.cell;
+                                if (!(chi < chi_max_src)) return false;
                                 T inv = la.inv_dtheta / rz;
-                                T t0 = (uu[0] + T(nx) * nmf - half) * inv + hp;
-                                T t1 = (uu[1] + T(ny) * nmf - half) * inv + hp;
+                                t0 = (uu[0] + T(nx) * nmf - half) * inv + hp;
+                                t1 = (uu[1] + T(ny) * nmf - half) * inv + hp;
                                 if (!(t0 >= T(p0x - 1) && t0 < T(p0x + rs) && t0 > T(-1) &&
                                       t1 >= T(p0y - 1) && t1 < T(p0y + rs) && t1 > T(-1)))
-                                    continue;
-                                T base_w = la.wbase / (chi * a_of_chi(la, chi));
-                                for (int s = 0; s < la.nsrc; ++s) {
-                                    T cs = la.chi_src[s];
-                                    if (chi < cs)
-                                        splat_region<T>(acc + s * rs * rs, rs, p0x, p0y, la.npix,
-                                                        kappa + (long)s * npix2, t0, t1,
-                                                        base_w * (cs - chi) / cs);
+                                    return false;
+                                return true;
+                            };
+#pragma unroll
+                            for (int u = 0; u < LUT; ++u) {
+                                const uint32_t k = base + u * LG + tid;
+                                T t0 = T(0), t1 = T(0), chi = T(0);
+                                const bool ok = k < hi && image(u, t0, t1, chi);
+                                if constexpr (COMPACT) {
+                                    queue_push(ok, t0, t1, chi);
+                                } else {
+                                    if (ok) deposit(t0, t1, chi);
                                 }
                             }
                         }
                     }
             }
         }
+    }
+    if (COMPACT && qn > 0) {  // the images left in the queue
+        issue_fence();
+        if (lane < qn) deposit(q[lane], q[LQ + lane], q[2 * LQ + lane]);
     }
     __syncthreads();
     for (int i = tid; i < ncell; i += LG) {
@@ -444,12 +498,15 @@ template <class T, bool EXT>
 void launch_lens_gather_t(Parts<T> p, SortBufs sb, Geo g, LensArgs<T> la,
                           const MapAdd<T>& mean, T* kappa, hipStream_t st) {
     int nreg = (la.npix + la.rs - 1) / la.rs;
-    size_t lds = (size_t)la.nsrc * la.rs * la.rs * sizeof(typename LensAcc<T>::S);
+    size_t lds = (size_t)la.nsrc * la.rs * la.rs * sizeof(typename LensAcc<T>::S) +
+                 lens_queue_bytes<T>(la.rs >= 64 ? 1024 : 256);
     constexpr size_t LDS_MAX = 163840;  // per workgroup on gfx950
     la.dwin = 0;
-    if (EXT && la.sub && lds + DWIN_BYTES <= LDS_MAX) {
-        la.dwin = (int)(DWIN_BYTES / (2 * sizeof(T)));
-        lds += DWIN_BYTES;
+    if (EXT && la.sub && lds < LDS_MAX) {
+        // as much of DWIN_BYTES as the accumulator and the queues leave
+        const size_t w = std::min(DWIN_BYTES, LDS_MAX - lds) / (2 * sizeof(T));
+        la.dwin = (int)w;
+        lds += w * 2 * sizeof(T);
     }
     // above the default dynamic LDS limit: raised once per instantiation
     static bool raised[2] = {false, false};
@@ -488,7 +545,8 @@ template <class T>
 void launch_lens_gather_batch(const LensGatherArgs<T>* tab, const LensArgs<T>& shape, int slots,
                               hipStream_t st) {
     const int nreg = (shape.npix + shape.rs - 1) / shape.rs;
-    const size_t lds = (size_t)shape.nsrc * shape.rs * shape.rs * sizeof(typename LensAcc<T>::S);
+    const size_t lds = (size_t)shape.nsrc * shape.rs * shape.rs * sizeof(typename LensAcc<T>::S) +
+                       lens_queue_bytes<T>(shape.rs >= 64 ? 1024 : 256);
     if (shape.rs >= 64)
         hipLaunchKernelGGL((k_lens_gather_b<T, 1024>), dim3(nreg * nreg, slots), dim3(1024), lds, st,
                            tab);

@@ -166,12 +166,14 @@ def test_headline_schedule_128p_256m(dtype):
     assert e_k <= _tol(dtype, 1e-6, 1e-3)
 
 
-def _gradient_workload(dtype, npix=None):
+def _gradient_workload(dtype, npix=None, noise_add=None, with_x=False):
     """Forward with checkpoints and the reverse pass of the gradient
-    workload on the GPU: (kappa, noise_bar, dL/dOmega_m, dL/dsigma_8).  The
-    GPU builds its own target map, the map of the target seed plus the same
-    seeded pixel noise (so its kappa_bar differs from the oracle's by the
-    maps' own error)."""
+    workload on the GPU: (kappa, noise_bar, dL/dOmega_m, dL/dsigma_8), and
+    the final positions (lattice order, Mpc/h) when with_x.  The GPU builds
+    its own target map, the map of the target seed plus the same seeded
+    pixel noise (so its kappa_bar differs from the oracle's by the maps' own
+    error).  noise_add, if given, is added to the initial noise (not to the
+    target's)."""
     from paper_2012_07266_amd.autograd import forward_with_checkpoints, reverse_pass
     from tests.golden import make_golden as G
     wl = G.GRAD if npix is None else G.GRAD.with_(npix=npix)
@@ -181,12 +183,16 @@ def _gradient_workload(dtype, npix=None):
         kt, _ = forward_with_checkpoints(
             sim, torch.from_numpy(W.white_noise(wl.np_side, G.GRAD_TARGET_SEED)).to(dev), a)
         kt = kt + torch.from_numpy(G.pixel_noise(tuple(kt.shape))).to(dev, dtype)
-        noise = torch.from_numpy(W.white_noise(wl.np_side, wl.seed)).to(dev, dtype)
+        noise = W.white_noise(wl.np_side, wl.seed)
+        if noise_add is not None:
+            noise = noise + noise_add
+        noise = torch.from_numpy(noise).to(dev, dtype)
         kappa, states = forward_with_checkpoints(sim, noise, a)
+        x_end = to_np(sim.get_state()[0]) if with_x else None
         kbar = 2.0 * (kappa - kt) / G.GRAD_SIGMA ** 2
         sim.init_ic(noise, a[0])
         nb, g_om, g_s8 = reverse_pass(sim, a, states, kbar)
-        out = (to_np(kappa), to_np(nb), g_om, g_s8)
+        out = (to_np(kappa), to_np(nb), g_om, g_s8) + ((x_end,) if with_x else ())
         sim.sync()
         del states
     return out
@@ -220,20 +226,26 @@ def test_gradient_workload_reverse_pass_float64():
 @pytest.mark.timeout(900)
 def test_gradient_workload_reverse_pass_float32():
     """The same in float32.  Its gradient with respect to the positions
-    jumps wherever an image crosses a pixel edge of the 7 arcsec map (the
-    bilinear splat's derivative is piecewise constant), or a particle a
-    mesh-node plane; the float32 trajectory, 1e-5 cells from the float64
-    one, puts about 6e-4 of the images on the other side of such an edge,
-    each with an O(1) different cotangent.  So the float32 gradient is held
-    against the oracle's to that floor: noise_bar and dL/dOmega_m within
-    0.1, the maps within 5e-3 (their own conditioning at this resolution);
-    and the mechanism is checked: the float32-to-float64 difference of
-    noise_bar shrinks on 4x coarser pixels (256^2 maps over the same field),
-    where 4x fewer images lie that close to an edge."""
+    jumps wherever an image crosses a pixel edge of the map (the bilinear
+    splat's derivative is piecewise constant) or a particle a mesh-node plane
+    (so does the CIC readout's); the float32 trajectory, a few 1e-5 cells
+    from the float64 one, puts a small fraction of them on the other side of
+    such an edge, each with an O(1) different cotangent.  So the float32
+    gradient is held against the oracle's to that floor: noise_bar and
+    dL/dOmega_m within 0.1, the maps within 5e-3 (their own conditioning at
+    this resolution).  And the floor is shown to be the trajectory's, not
+    float32 arithmetic in the reverse pass: a float64 run whose initial noise
+    is perturbed so that its trajectory moves about as far from the
+    unperturbed float64 one as the float32 trajectory does changes the
+    gradient by the same amount (within a factor of 3, after scaling by the
+    square root of the ratio of the two moves: the number of edge crossings
+    grows with the move, and the rel-rms with the square root of that
+    number)."""
     from tests.golden import make_golden as G
     g = _golden(G.GRAD.name)
+    wl = G.GRAD
     log("gradient workload reverse pass float32")
-    kappa, nb32, g_om, g_s8 = _gradient_workload(torch.float32)
+    kappa, nb32, g_om, g_s8, x32 = _gradient_workload(torch.float32, with_x=True)
     kg = kappa.ravel()[::int(g["map_stride"])]
     nb = nb32.ravel()[::int(g["noise_stride"])]
     e_k = rel_rms(kg, g["kappa_sample"])
@@ -243,15 +255,30 @@ def test_gradient_workload_reverse_pass_float32():
     log(f"gradient workload float32: kappa rel-rms {e_k:.2e}; noise_bar rel-rms {e_n:.2e} "
         f"({nb.size} elements); Om rel {e_om:.2e}; s8 rel {e_s8:.2e}")
     assert e_k <= 5e-3 and e_n <= 0.1 and e_om <= 0.1
-    log("gradient workload: float32 vs float64 at 1024^2 and 256^2 pixels")
-    coarse32 = _gradient_workload(torch.float32, npix=256)[1]
-    coarse64 = _gradient_workload(torch.float64, npix=256)[1]
-    fine64 = _gradient_workload(torch.float64)[1]
-    d_fine = rel_rms(nb32, fine64)
-    d_coarse = rel_rms(coarse32, coarse64)
-    log(f"gradient workload: noise_bar float32 vs float64 {d_fine:.2e} (1024^2), "
-        f"{d_coarse:.2e} (256^2)")
-    assert d_coarse < 0.7 * d_fine
+
+    cell = wl.box / wl.nm_side
+
+    def move(xa, xb):  # rms minimum-image distance, cells
+        d = xa.astype(np.float64) - xb
+        d -= wl.box * np.round(d / wl.box)
+        return float(np.sqrt(np.mean(np.sum(d * d, axis=0)))) / cell
+
+    _, nb64, _, _, x64 = _gradient_workload(torch.float64, with_x=True)
+    ii = np.indices((wl.np_side,) * 3).reshape(3, -1) * (wl.box / wl.np_side)
+    disp = move(x64, ii)           # rms displacement from the lattice
+    m32 = move(x32, x64)
+    eta = m32 / disp               # noise perturbation of about that relative size
+    pert = eta * W.white_noise(wl.np_side, 777)
+    _, nb64p, _, _, x64p = _gradient_workload(torch.float64, noise_add=pert, with_x=True)
+    mp = move(x64p, x64)
+    d32 = rel_rms(nb32, nb64)
+    dp = rel_rms(nb64p, nb64)
+    dps = dp * np.sqrt(m32 / mp)
+    log(f"gradient workload: trajectory move float32 {m32:.2e} cells, perturbed float64 "
+        f"{mp:.2e} cells (noise eta {eta:.1e}); noise_bar change {d32:.2e} vs {dp:.2e} "
+        f"({dps:.2e} scaled)")
+    assert m32 < 1e-3 and mp > 0
+    assert d32 / 3 <= dps <= 3 * d32
 
 
 @pytest.mark.timeout(300)
