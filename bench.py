@@ -270,7 +270,10 @@ def gradient_bench(reps=3):
     1024^2 map over 2 deg at z_s = 1, float32; loss chi^2 = sum (kappa -
     kappa_t)^2 / sigma^2 against a target map from another seed with
     Gaussian pixel noise sigma = 0.01; gradients with respect to the 128^3
-    noise values, Omega_m and sigma_8, with per-step checkpoints."""
+    noise values, Omega_m and sigma_8, with per-step checkpoints that carry
+    the force at their state (restored by copy; 0.23 GB each at this size).
+    The same with state-only checkpoints (whose restores recompute the
+    force) is timed beside it."""
     import torch
     import workloads as W
     from paper_2012_07266_amd import Simulation
@@ -279,8 +282,8 @@ def gradient_bench(reps=3):
     a = wl.a_grid()
     dev = torch.device("cuda", 0)
     sim = Simulation(wl.np_side, wl.nm_side, wl.box, wl.npix, wl.fov_deg, wl.z_src,
-                     dtype=torch.float32, tangent=True, omega_m=wl.omega_m, sigma8=wl.sigma8,
-                     h=wl.h, n_s=wl.n_s, omega_b=wl.omega_b, t_cmb=wl.t_cmb)
+                     dtype=torch.float32, tangent=True, ckpt_force=True, omega_m=wl.omega_m,
+                     sigma8=wl.sigma8, h=wl.h, n_s=wl.n_s, omega_b=wl.omega_b, t_cmb=wl.t_cmb)
     sigma = 0.01
     target, _ = forward_with_checkpoints(
         sim, torch.from_numpy(W.white_noise(wl.np_side, 4)).to(dev, torch.float32), a)
@@ -321,12 +324,39 @@ def gradient_bench(reps=3):
     sim.profile(False)
     jvp_finite = bool(torch.isfinite(kd).all().item())
     sim.close()
+    # state-only checkpoints
+    sim0 = Simulation(wl.np_side, wl.nm_side, wl.box, wl.npix, wl.fov_deg, wl.z_src,
+                      dtype=torch.float32, omega_m=wl.omega_m, sigma8=wl.sigma8, h=wl.h,
+                      n_s=wl.n_s, omega_b=wl.omega_b, t_cmb=wl.t_cmb)
+    t_f0, t_b0 = [], []
+    for r in range(reps + 1):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        kappa0, states0 = forward_with_checkpoints(sim0, noise, a)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        kbar0 = 2.0 * (kappa0 - target) / sigma ** 2
+        sim0.init_ic(noise, a[0])
+        reverse_pass(sim0, a, states0, kbar0)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        del states0
+        if r > 0:
+            t_f0.append(t1 - t0)
+            t_b0.append(t2 - t1)
+    sim0.close()
+    f0, b0 = float(np.median(t_f0)), float(np.median(t_b0))
     f, b = float(np.median(t_f)), float(np.median(t_b))
     pf, jf = float(np.median(t_p)), float(np.median(t_j))
     ps = wl.np_side ** 3 * wl.nsteps
     return {"workload": (f"{wl.name}: 128^3 particles, 256^3 mesh, 20 steps, 1 x 1024^2 map, "
                          "float32, chi^2 loss, gradients w.r.t. noise, Omega_m, sigma_8"),
+            "checkpoints": "state and force (PM_MODE_CKPT_FORCE)",
             "forward_ms": 1e3 * f, "reverse_ms": 1e3 * b, "reverse_over_forward": b / f,
+            "gradient_over_plain_forward": (f + b) / pf,
+            "state_only_checkpoints": {"forward_ms": 1e3 * f0, "reverse_ms": 1e3 * b0,
+                                       "reverse_over_forward": b0 / f0,
+                                       "gradient_over_plain_forward": (f0 + b0) / pf},
             "forward_particle_steps_per_s": ps / f,
             "forward_plus_reverse_particle_steps_per_s": ps / (f + b),
             "grad_finite": bool(torch.isfinite(nb).all().item() and np.isfinite(g_om)

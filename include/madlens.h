@@ -80,6 +80,12 @@ typedef struct pm_params {
 #define PM_MODE_PGD     1u  /* pm_set_pgd: filter table, shift [3][Np^3] and
                                one spare mesh [Nm^3] + Nyquist plane         */
 #define PM_MODE_TANGENT 2u  /* forward-mode tangents: 15 Np^3 values         */
+#define PM_MODE_CKPT_FORCE 4u /* checkpoints also carry the force at the saved
+                               state (three force meshes [3][Nm^3] and the
+                               particles' accelerations [3][Np^3]), so that
+                               pm_checkpoint_load restores it, bit for bit,
+                               instead of recomputing it (a paint, the force
+                               transform and a readout); no arena buffers   */
 
 typedef struct lens_params {
     int32_t       npix;     /* map pixels per side                           */
@@ -302,14 +308,18 @@ int pm_init_ic_vjp(pm_sim* sim, double a1, const void* x_bar, const void* p_bar,
 
 /* Checkpoints for the reverse pass, in the library's own particle order
  * (displacements, momenta, particle ids and the sort's block offsets): no
- * conversion to lattice order on save and no sort on load.
+ * conversion to lattice order on save and no sort on load.  With
+ * PM_MODE_CKPT_FORCE they also hold the force at the saved state.
  * pm_checkpoint_bytes: the size of one checkpoint of this handle (0 for a
  * NULL handle).  pm_checkpoint_save: copy the current state into buf (a
- * device buffer of that size, owned by the caller; asynchronous).
- * pm_checkpoint_load: restore a checkpoint made by a handle of the same
- * shape, at scale factor a; the force is recomputed there, as with
- * pm_set_state.  Errors: PM_EINVAL (NULL buffer, a <= 0), PM_ESTATE (save
- * without a state). */
+ * device buffer of that size, owned by the caller; asynchronous; with
+ * PM_MODE_CKPT_FORCE the force is computed first if no call since the last
+ * change of state has left it in the meshes).  pm_checkpoint_load: restore
+ * a checkpoint made by a handle of the same shape and modes, at scale
+ * factor a; the force there is copied from the checkpoint with
+ * PM_MODE_CKPT_FORCE, else recomputed, as with pm_set_state (the same
+ * values either way).  Errors: PM_EINVAL (NULL buffer, a <= 0), PM_ESTATE
+ * (save without a state). */
 size_t pm_checkpoint_bytes(const pm_sim* sim);
 int pm_checkpoint_save(pm_sim* sim, void* buf);
 int pm_checkpoint_load(pm_sim* sim, const void* buf, double a);

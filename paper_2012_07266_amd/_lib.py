@@ -17,7 +17,7 @@ PM_OK, PM_EINVAL, PM_ENOMEM, PM_EDEVICE, PM_ESTATE, PM_ENONFINITE, PM_EAGAIN, PM
 PM_EFULL = -9
 PM_NOALLOC_MAX_BYTES = 64 << 20
 PM_F32, PM_F64 = 0, 1
-PM_MODE_PGD, PM_MODE_TANGENT = 1, 2
+PM_MODE_PGD, PM_MODE_TANGENT, PM_MODE_CKPT_FORCE = 1, 2, 4
 
 
 class PmParams(ctypes.Structure):

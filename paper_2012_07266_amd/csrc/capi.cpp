@@ -119,7 +119,7 @@ ArenaPlan plan_arena(const pm_params& p, const lens_params& l, size_t es) {
 int validate(const pm_params* p, const lens_params* l) {
     if (!p || !l) return PM_EINVAL;
     if (p->dtype != PM_F32 && p->dtype != PM_F64) return PM_EINVAL;
-    if (p->modes & ~(PM_MODE_PGD | PM_MODE_TANGENT)) return PM_EINVAL;
+    if (p->modes & ~(PM_MODE_PGD | PM_MODE_TANGENT | PM_MODE_CKPT_FORCE)) return PM_EINVAL;
     if (p->np < 16 || p->nm < 16 || p->np % 16 || p->nm % 16) return PM_EINVAL;
     if (p->nm != p->np && p->nm != 2 * p->np) return PM_EINVAL;
     if (!only_2_3(p->np) || !only_2_3(p->nm) || p->nm > 1024) return PM_EINVAL;
@@ -985,12 +985,19 @@ template <class T> struct Sim final : SimBase {
     }
 
     // Checkpoints in the library's own particle order: displacements,
-    // momenta, ids and the sort's block offsets, each 256-byte aligned.
+    // momenta, ids and the sort's block offsets, each 256-byte aligned; with
+    // PM_MODE_CKPT_FORCE then the three force meshes and the accelerations.
+    bool ckpt_force() const { return (P.modes & PM_MODE_CKPT_FORCE) != 0; }
     size_t checkpoint_bytes() const override {
         const size_t n = (size_t)geo.npart, es = sizeof(T);
         const size_t nkeys = (size_t)ntiles;
         auto al = [](size_t b) { return (b + 255) / 256 * 256; };
-        return 2 * al(3 * n * es) + al(n * 4) + al((nkeys + 1) * 4);
+        size_t b = 2 * al(3 * n * es) + al(n * 4) + al((nkeys + 1) * 4);
+        if (ckpt_force()) {
+            const size_t n3 = (size_t)P.nm * P.nm * P.nm;
+            b += 3 * al(n3 * es) + al(3 * n * es);
+        }
+        return b;
     }
 
     int checkpoint_save(void* buf) override {
@@ -1006,12 +1013,25 @@ template <class T> struct Sim final : SimBase {
         HIPCHK(hipMemcpyAsync(b, cur.id, n * 4, hipMemcpyDeviceToDevice, st));
         b += al(n * 4);
         HIPCHK(hipMemcpyAsync(b, sb.start, ((size_t)ntiles + 1) * 4, hipMemcpyDeviceToDevice, st));
+        if (ckpt_force()) {
+            b += al(((size_t)ntiles + 1) * 4);
+            // every path that leaves the meshes valid has also left the
+            // accelerations of the current state (its readout wrote them)
+            if (!meshes_valid) force(T(0), 0);
+            const size_t n3 = (size_t)P.nm * P.nm * P.nm;
+            for (int j = 0; j < 3; ++j) {
+                HIPCHK(hipMemcpyAsync(b, mesh[j], n3 * es, hipMemcpyDeviceToDevice, st));
+                b += al(n3 * es);
+            }
+            HIPCHK(hipMemcpyAsync(b, cur.acc, 3 * n * es, hipMemcpyDeviceToDevice, st));
+        }
         return check_launch();
     }
 
     // Restore a checkpoint of this handle's shape at scale factor a: the
     // particles come back in the order they were saved in, so no sort is
-    // needed; the force there is recomputed, as pm_set_state does.
+    // needed; the force there is copied back (PM_MODE_CKPT_FORCE) or
+    // recomputed, as pm_set_state does.
     int checkpoint_load(const void* buf, double a) override {
         if (!buf || !(a > 0)) return PM_EINVAL;
         const size_t n = (size_t)geo.npart, es = sizeof(T);
@@ -1024,7 +1044,18 @@ template <class T> struct Sim final : SimBase {
         HIPCHK(hipMemcpyAsync(cur.id, b, n * 4, hipMemcpyDeviceToDevice, st));
         b += al(n * 4);
         HIPCHK(hipMemcpyAsync(sb.start, b, ((size_t)ntiles + 1) * 4, hipMemcpyDeviceToDevice, st));
-        force(T(0), 0);
+        if (ckpt_force()) {
+            b += al(((size_t)ntiles + 1) * 4);
+            const size_t n3 = (size_t)P.nm * P.nm * P.nm;
+            for (int j = 0; j < 3; ++j) {
+                HIPCHK(hipMemcpyAsync(mesh[j], b, n3 * es, hipMemcpyDeviceToDevice, st));
+                b += al(n3 * es);
+            }
+            HIPCHK(hipMemcpyAsync(cur.acc, b, 3 * n * es, hipMemcpyDeviceToDevice, st));
+            meshes_valid = true;
+        } else {
+            force(T(0), 0);
+        }
         a_cur = a;
         ic_fresh = false;
         tan_valid = false;

@@ -54,20 +54,24 @@ class Simulation:
     """A PM + lightcone simulation resident on one GPU.
 
     `modes` (PM_MODE_* bits) sizes the arena for the optional passes: the PGD
-    correction (implied by `pgd`) and forward-mode tangents (`tangent`).
+    correction (implied by `pgd`) and forward-mode tangents (`tangent`);
+    `ckpt_force` makes checkpoints carry the force at their state, so that a
+    restore copies it back instead of recomputing it (larger checkpoints,
+    faster reverse pass, the same values).
     """
 
     def __init__(self, np_side, nm_side, box, npix, fov_deg, z_src, *,
                  dtype=torch.float32, stream: Optional[torch.cuda.Stream] = None,
                  interpolation: bool = False, pgd=None, tangent: bool = False, modes: int = 0,
-                 **cosmo):
+                 ckpt_force: bool = False, **cosmo):
         self.np_side, self.nm_side, self.box = int(np_side), int(nm_side), float(box)
         self.npix, self.fov_deg, self.z_src = int(npix), float(fov_deg), tuple(z_src)
         self.dtype = dtype
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.stream = stream if stream is not None else torch.cuda.current_stream()
         modes = int(modes) | (_lib.PM_MODE_PGD if pgd is not None else 0) | \
-            (_lib.PM_MODE_TANGENT if tangent else 0)
+            (_lib.PM_MODE_TANGENT if tangent else 0) | \
+            (_lib.PM_MODE_CKPT_FORCE if ckpt_force else 0)
         self.modes = modes
         p = make_params(np_side, nm_side, box, dtype=dtype, modes=modes, **cosmo)
         l = make_lens(npix, fov_deg, z_src)

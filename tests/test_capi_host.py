@@ -61,7 +61,8 @@ def test_footprint(lib):
 def test_footprint_counts_the_optional_modes(lib):
     """PM_MODE_PGD adds the filter table, the shift [3][P] and one spare mesh
     with its Nyquist plane; PM_MODE_TANGENT adds 15 P values (x_dot, p_dot,
-    each with the sort's second buffer, and f_dot); both add their sum."""
+    each with the sort's second buffer, and f_dot); both add their sum;
+    PM_MODE_CKPT_FORCE adds nothing to the arena."""
     from paper_2012_07266_amd._lib import PM_MODE_PGD, PM_MODE_TANGENT
     np_, nm = 128, 256
     P, es = np_ ** 3, 4
@@ -75,7 +76,11 @@ def test_footprint_counts_the_optional_modes(lib):
     assert 0 <= fp[PM_MODE_PGD] - fp[0] - pgd <= slack
     assert 0 <= fp[PM_MODE_TANGENT] - fp[0] - tan <= slack
     assert 0 <= fp[PM_MODE_PGD | PM_MODE_TANGENT] - fp[0] - pgd - tan <= 2 * slack
-    p, l = _params(modes=4)  # no such mode
+    # PM_MODE_CKPT_FORCE enlarges the caller's checkpoints, not the arena
+    from paper_2012_07266_amd._lib import PM_MODE_CKPT_FORCE
+    p, l = _params(np_side=np_, nm_side=nm, box=128.0, modes=PM_MODE_CKPT_FORCE)
+    assert lib.pm_footprint(ctypes.byref(p), ctypes.byref(l)) == fp[0]
+    p, l = _params(modes=8)  # no such mode
     assert lib.pm_footprint(ctypes.byref(p), ctypes.byref(l)) == 0
 
 

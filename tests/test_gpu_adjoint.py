@@ -275,3 +275,48 @@ def test_checkpoint_restores_the_state_bit_for_bit():
         sim.sync()
     assert torch.equal(xr, x1) and torch.equal(pr, p1) and torch.equal(fr, f1)
     assert torch.equal(x2r, x2) and torch.equal(p2r, p2)
+
+
+@pytest.mark.parametrize("interp", [False, True], ids=["plain", "subevolution"])
+def test_checkpoints_with_force_give_the_same_reverse_pass(interp):
+    """PM_MODE_CKPT_FORCE: checkpoints that carry the force at their state
+    (restored by copy) give a reverse pass bit for bit equal to the one from
+    state-only checkpoints (whose restores recompute the force), float32 (the
+    cosmology cotangents, float64 sums of atomic adds, to round-off),
+    with and without sub-evolution (which reads the restored accelerations).
+    One checkpoint is taken after a reverse step at its state has used the
+    meshes, so that the save computes the force first."""
+    from paper_2012_07266_amd._lib import PM_MODE_CKPT_FORCE
+    from paper_2012_07266_amd.autograd import reverse_pass
+    from tests.gpu_util import new_sim
+    wl = W.Workload("ckf", 32, 64, 64.0, 0.3, 1.0, 5, 64, 3.0, (1.0,), seed=21)
+    a = wl.a_grid()
+    res = []
+    for modes in (0, PM_MODE_CKPT_FORCE):
+        with new_sim(wl, torch.float32, modes=modes) as sim:
+            sim.set_interpolation(interp)
+            noise = torch.tensor(W.white_noise(32, 21), dtype=torch.float32, device="cuda")
+            kappa = sim.new_maps()
+            sim.init_ic(noise, a[0])
+            states = [sim.checkpoint()]
+            for i in range(len(a) - 1):
+                sim.step(a[i], a[i + 1])
+                sim.lens(a[i], a[i + 1], kappa)
+                if i == 2:  # a reverse step at this state leaves other values in the meshes
+                    z = torch.zeros((3, sim.n_particles), dtype=torch.float32, device="cuda")
+                    sim.step_vjp(a[i], a[i + 1], a[i + 2], z, z.clone(), None,
+                                 z.clone() if interp else None)
+                states.append(sim.checkpoint())
+            kbar = (2.0 * kappa).contiguous()
+            sim.init_ic(noise, a[0])
+            nb, g_om, g_s8 = reverse_pass(sim, a, states, kbar)
+            sim.sync()
+            res.append((kappa.clone(), nb.clone(), g_om, g_s8, states[0].numel()))
+    log(f"checkpoint bytes {res[0][4]} state only, {res[1][4]} with the force")
+    assert res[1][4] > res[0][4]
+    assert torch.abs(res[0][1]).max() > 0
+    assert torch.equal(res[0][0], res[1][0]) and torch.equal(res[0][1], res[1][1])
+    # dL/dOmega_m and dL/dsigma_8 are float64 sums of atomic adds, whose order
+    # varies from run to run
+    assert abs(res[0][2] - res[1][2]) <= 1e-13 * abs(res[0][2])
+    assert abs(res[0][3] - res[1][3]) <= 1e-13 * abs(res[0][3])
