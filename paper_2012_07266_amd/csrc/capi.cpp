@@ -849,9 +849,42 @@ template <class T> struct Sim final : SimBase {
         la.atab = atab;
         la.ntab = ATAB_N;
         la.dchi = (T)dchi_tab;
-        la.rs = region_side(nsrc, npix);
+        plan_sources(la, chi_near, chi_far, true);
         for (int s = 0; s < nsrc; ++s) mv.v[s] = (T)cosmo.shell_mean(chi_near, chi_far, chisrc[s]);
         return true;
+    }
+
+    // Which maps take which images of the shell (chi_near, chi_far]: a
+    // source beyond the far bound takes every image, one inside the shell
+    // those in front of it, one in front of the shell none (a relative margin
+    // of 1e-6 keeps images whose float distance rounds across a source on the
+    // per-image test).  With moved images allowed (sub-evolution, the PGD
+    // shift: images can leave the shell's bounds) every source takes the
+    // per-image test.  Two or more sources beyond the shell share the
+    // accumulators A and B, their maps A - ratio B with ratio = 1 / (cs
+    // inv_chi_ref), inv_chi_ref being the factor the kernel applies in T.
+    // The region side follows from the accumulator count.
+    void plan_sources(LensArgs<T>& la, double chi_near, double chi_far, bool fixed_bounds) const {
+        int nbeyond = 0;
+        for (int s = 0; s < nsrc; ++s)
+            if (chisrc[s] > chi_far * (1.0 + 1e-6)) ++nbeyond;
+        la.dec = (fixed_bounds && nbeyond >= 2) ? 1 : 0;
+        la.inv_chi_ref = (T)(1.0 / chi_far);
+        la.ndirect = 0;
+        for (int s = 0; s < nsrc; ++s) {
+            la.ratio[s] = 0.0;
+            if (la.dec && chisrc[s] > chi_far * (1.0 + 1e-6)) {
+                la.slot[s] = -1;
+                la.ratio[s] = 1.0 / ((double)la.inv_chi_ref * chisrc[s]);
+            } else if (fixed_bounds && chisrc[s] < chi_near * (1.0 - 1e-6)) {
+                la.slot[s] = -2;
+            } else {
+                la.slot[s] = 2 * la.dec + la.ndirect;
+                la.direct_src[la.ndirect++] = s;
+            }
+        }
+        la.nacc = 2 * la.dec + la.ndirect;
+        la.rs = region_side(la.nacc > 0 ? la.nacc : 1, npix);
     }
 
     // 64 x 64-pixel regions when their fixed-point accumulators fit in 128 KB
@@ -890,6 +923,7 @@ template <class T> struct Sim final : SimBase {
             la.shift_scale = (T)(pgd_alpha0 * std::pow(a1, pgd_mu));
             la.shift_bits = pgd_bits;
         }
+        if (interp || pgd) plan_sources(la, cosmo.chi(a1), cosmo.chi(a0), false);
         { ProfScope ps(prof, "lens_gather", ls);
           launch_lens_gather<T>(cur, sb, geo, la, mv, kappa, ls); }
         return PM_OK;
@@ -1525,6 +1559,7 @@ template <class T> struct Sim final : SimBase {
         o.paint = PaintArgs<T>{cur, sb, geo, (T)std::pow((double)geo.B, 3), mesh[0], halo, 1};
         o.lens = LensGatherArgs<T>{};
         if (kappa && plain_lens_args(a0, a1, o.lens.la, o.lens.mean)) {
+            o.lens.la.rs = region_side(nsrc, npix);  // the batch's grid: one side for every shell
             o.lens.p = cur;
             o.lens.sb = sb;
             o.lens.g = geo;

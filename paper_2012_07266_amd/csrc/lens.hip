@@ -115,17 +115,23 @@ template <> struct LensAcc<float> {
     static __device__ __forceinline__ float dec(S v) {
         return (float)((double)v * (1.0 / 1099511627776.0));
     }
+    static __device__ __forceinline__ double dec_d(S v) { return (double)v * (1.0 / 1099511627776.0); }
 };
 template <> struct LensAcc<double> {
     using S = double;
     static constexpr double LIM = 1e300;
     static __device__ __forceinline__ S enc(double w) { return w; }
     static __device__ __forceinline__ double dec(S v) { return v; }
+    static __device__ __forceinline__ double dec_d(S v) { return v; }
 };
 
+// The bilinear splat of weight w at pixel coordinates (t0, t1) into the
+// region's accumulator, a corner weight at or above the fixed-point limit
+// (or every corner, global_only) going to the map kmap with a float atomic.
 template <class T>
 __device__ __forceinline__ void splat_region(typename LensAcc<T>::S* acc, int rs, int p0x, int p0y,
-                                             int npix, T* kmap, T t0, T t1, T w) {
+                                             int npix, T* kmap, T t0, T t1, T w,
+                                             bool global_only = false) {
     using A = LensAcc<T>;
     T fl0 = floor(t0), fl1 = floor(t1);
     int j0 = (int)fl0, j1 = (int)fl1;
@@ -140,7 +146,7 @@ __device__ __forceinline__ void splat_region(typename LensAcc<T>::S* acc, int rs
             int c = j1 + b;
             if (c < p0y || c >= p0y + rs || c >= npix) continue;
             T v = w * wa[a] * wb[b];
-            if (v < T(A::LIM)) atomicAdd(&acc[(r - p0x) * rs + (c - p0y)], A::enc(v));
+            if (!global_only && v < T(A::LIM)) atomicAdd(&acc[(r - p0x) * rs + (c - p0y)], A::enc(v));
             else unsafeAtomicAdd(&kmap[(long)r * npix + c], v);
         }
     }
@@ -200,7 +206,8 @@ __device__ __forceinline__ void lens_gather_body(Parts<T> p, SortBufs sb, Geo g,
     const int rx = b / nreg, ry = b % nreg;
     const int p0x = rx * rs, p0y = ry * rs;
     const int tid = threadIdx.x;
-    const int ncell = la.nsrc * rs * rs;
+    const int rs2 = rs * rs;
+    const int ncell = la.nacc * rs2;
     for (int i = tid; i < ncell; i += LG) acc[i] = S(0);
     // sub-evolution: the part of the D(a(chi)) table that end-of-step
     // depths in the shell can reach (one entry of margin below, two above)
@@ -248,14 +255,33 @@ __device__ __forceinline__ void lens_gather_body(Parts<T> p, SortBufs sb, Geo g,
     }
     const int npix2 = la.npix * la.npix;
     // an accepted image: its weight for every source behind it, bilinearly
-    // into the region
+    // into the region (the shared accumulators A and B for the sources
+    // beyond the shell, unless the weight is near the fixed-point limit:
+    // then per source, as for the sources of their own)
     auto deposit = [&](T t0, T t1, T chi) {
         T base_w = la.wbase / (chi * a_of_chi(la, chi));
-        for (int s = 0; s < la.nsrc; ++s) {
+        if (la.dec) {
+            if (base_w < T(0.5) * T(A::LIM)) {
+                // every corner weight is below the limit: the map argument
+                // is never written
+                splat_region<T>(acc, rs, p0x, p0y, la.npix, kappa, t0, t1, base_w);
+                splat_region<T>(acc + rs2, rs, p0x, p0y, la.npix, kappa, t0, t1,
+                                base_w * chi * la.inv_chi_ref);
+            } else {
+                for (int s = 0; s < la.nsrc; ++s) {
+                    if (la.slot[s] != -1) continue;
+                    T cs = la.chi_src[s];
+                    splat_region<T>(acc, rs, p0x, p0y, la.npix, kappa + (long)s * npix2, t0, t1,
+                                    base_w * (cs - chi) / cs, true);
+                }
+            }
+        }
+        for (int d = 0; d < la.ndirect; ++d) {
+            const int s = la.direct_src[d];
             T cs = la.chi_src[s];
             if (chi < cs)
-                splat_region<T>(acc + s * rs * rs, rs, p0x, p0y, la.npix, kappa + (long)s * npix2,
-                                t0, t1, base_w * (cs - chi) / cs);
+                splat_region<T>(acc + (2 * la.dec + d) * rs2, rs, p0x, p0y, la.npix,
+                                kappa + (long)s * npix2, t0, t1, base_w * (cs - chi) / cs);
         }
     };
     // float: a wave's accepted images wait in its own LDS queue (after the
@@ -469,12 +495,17 @@ __device__ __forceinline__ void lens_gather_body(Parts<T> p, SortBufs sb, Geo g,
         if (lane < qn) deposit(q[lane], q[LQ + lane], q[2 * LQ + lane]);
     }
     __syncthreads();
-    for (int i = tid; i < ncell; i += LG) {
-        int s = i / (rs * rs), r = (i / rs) % rs, c = i % rs;
+    for (int i = tid; i < la.nsrc * rs2; i += LG) {
+        const int s = i / rs2, rc = i - s * rs2, r = rc / rs, c = rc % rs;
         int px = p0x + r, py = p0y + c;
         if (px < la.npix && py < la.npix) {
             long o = (long)s * npix2 + (long)px * la.npix + py;
-            kappa[o] += A::dec(acc[i]) + mean.v[s];
+            const int sl = la.slot[s];
+            T v = T(0);
+            if (sl >= 0) v = A::dec(acc[sl * rs2 + rc]);
+            else if (sl == -1)
+                v = (T)(A::dec_d(acc[rc]) - (double)la.ratio[s] * A::dec_d(acc[rs2 + rc]));
+            kappa[o] += v + mean.v[s];
         }
     }
 }
@@ -498,7 +529,7 @@ template <class T, bool EXT>
 void launch_lens_gather_t(Parts<T> p, SortBufs sb, Geo g, LensArgs<T> la,
                           const MapAdd<T>& mean, T* kappa, hipStream_t st) {
     int nreg = (la.npix + la.rs - 1) / la.rs;
-    size_t lds = (size_t)la.nsrc * la.rs * la.rs * sizeof(typename LensAcc<T>::S) +
+    size_t lds = (size_t)la.nacc * la.rs * la.rs * sizeof(typename LensAcc<T>::S) +
                  lens_queue_bytes<T>(la.rs >= 64 ? 1024 : 256);
     constexpr size_t LDS_MAX = 163840;  // per workgroup on gfx950
     la.dwin = 0;

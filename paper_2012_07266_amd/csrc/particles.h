@@ -163,6 +163,19 @@ template <class T> struct LensArgs {
     int ntab;
     T dchi;
     int rs;             // region side (pixels) of the gather projection
+    // The region's LDS accumulators.  Map s takes its weight
+    // w (cs - chi) / cs from every image in front of its source: slot[s] >= 0
+    // is its own accumulator; slot[s] == -1 (dec != 0: two or more sources
+    // beyond the shell's far bound, so that every image is in front of them)
+    // is built at the end as A - ratio[s] B from the shared accumulators
+    // A = sum w, B = sum w chi / chi_ref (slots 0 and 1), ratio = chi_ref / cs;
+    // slot[s] == -2 takes nothing (its source is in front of the shell).
+    // ndirect sources have their own slot, 2 dec + d, source direct_src[d].
+    int dec, nacc, ndirect;
+    int slot[MAX_SRC];
+    int direct_src[MAX_SRC];
+    double ratio[MAX_SRC];
+    T inv_chi_ref;
     // sub-evolution (sub != 0): an image keeps the shell of its end-of-step
     // depth and moves by (D(a(chi)) - d_end) * sub_scale * p_h, p_h = mom -
     // sub_k2 * acc being the step's drift momentum (cells)
