@@ -860,15 +860,21 @@ template <class T> struct Sim final : SimBase {
     // of 1e-6 keeps images whose float distance rounds across a source on the
     // per-image test).  With moved images allowed (sub-evolution, the PGD
     // shift: images can leave the shell's bounds) every source takes the
-    // per-image test.  Two or more sources beyond the shell share the
+    // per-image test.  Two or more sources beyond the shell can share the
     // accumulators A and B, their maps A - ratio B with ratio = 1 / (cs
-    // inv_chi_ref), inv_chi_ref being the factor the kernel applies in T.
-    // The region side follows from the accumulator count.
+    // inv_chi_ref), inv_chi_ref being the factor the kernel applies in T;
+    // that is done when it lets the region grow (the region side follows
+    // from the accumulator count): at the same region side it measured
+    // slower than one accumulator per source.
     void plan_sources(LensArgs<T>& la, double chi_near, double chi_far, bool fixed_bounds) const {
-        int nbeyond = 0;
-        for (int s = 0; s < nsrc; ++s)
+        int nbeyond = 0, nnone = 0;
+        for (int s = 0; s < nsrc; ++s) {
             if (chisrc[s] > chi_far * (1.0 + 1e-6)) ++nbeyond;
-        la.dec = (fixed_bounds && nbeyond >= 2) ? 1 : 0;
+            if (fixed_bounds && chisrc[s] < chi_near * (1.0 - 1e-6)) ++nnone;
+        }
+        const int n_own = std::max(nsrc - nnone, 1), n_dec = 2 + (nsrc - nnone - nbeyond);
+        la.dec = (fixed_bounds && nbeyond >= 2 &&
+                  region_side(n_dec, npix) > region_side(n_own, npix)) ? 1 : 0;
         la.inv_chi_ref = (T)(1.0 / chi_far);
         la.ndirect = 0;
         for (int s = 0; s < nsrc; ++s) {
@@ -884,7 +890,7 @@ template <class T> struct Sim final : SimBase {
             }
         }
         la.nacc = 2 * la.dec + la.ndirect;
-        la.rs = region_side(la.nacc > 0 ? la.nacc : 1, npix);
+        la.rs = region_side(la.dec ? la.nacc : nsrc, npix);
     }
 
     // 64 x 64-pixel regions when their fixed-point accumulators fit in 128 KB
@@ -1559,7 +1565,10 @@ template <class T> struct Sim final : SimBase {
         o.paint = PaintArgs<T>{cur, sb, geo, (T)std::pow((double)geo.B, 3), mesh[0], halo, 1};
         o.lens = LensGatherArgs<T>{};
         if (kappa && plain_lens_args(a0, a1, o.lens.la, o.lens.mean)) {
-            o.lens.la.rs = region_side(nsrc, npix);  // the batch's grid: one side for every shell
+            // the batch's grid has one region side for every shell: one
+            // accumulator per source
+            o.lens.la.dec = 0;
+            o.lens.la.rs = region_side(nsrc, npix);
             o.lens.p = cur;
             o.lens.sb = sb;
             o.lens.g = geo;

@@ -187,7 +187,9 @@ template <class T> constexpr size_t lens_queue_bytes(int lg) {
 
 // LG threads per workgroup: 256 for 32 x 32-pixel regions, 1024 for 64 x 64
 // (one workgroup per CU then holds the LDS, so it brings 16 waves)
-template <class T, int LG, bool EXT>
+// DEC: the maps of the sources beyond the shell come from the shared
+// accumulators A and B (la.dec); else one accumulator per source.
+template <class T, int LG, bool EXT, bool DEC>
 __device__ __forceinline__ void lens_gather_body(Parts<T> p, SortBufs sb, Geo g, LensArgs<T> la,
                                                     MapAdd<T> mean, T* kappa) {
     using A = LensAcc<T>;
@@ -207,7 +209,7 @@ __device__ __forceinline__ void lens_gather_body(Parts<T> p, SortBufs sb, Geo g,
     const int p0x = rx * rs, p0y = ry * rs;
     const int tid = threadIdx.x;
     const int rs2 = rs * rs;
-    const int ncell = la.nacc * rs2;
+    const int ncell = (DEC ? la.nacc : la.nsrc) * rs2;
     for (int i = tid; i < ncell; i += LG) acc[i] = S(0);
     // sub-evolution: the part of the D(a(chi)) table that end-of-step
     // depths in the shell can reach (one entry of margin below, two above)
@@ -260,27 +262,34 @@ __device__ __forceinline__ void lens_gather_body(Parts<T> p, SortBufs sb, Geo g,
     // then per source, as for the sources of their own)
     auto deposit = [&](T t0, T t1, T chi) {
         T base_w = la.wbase / (chi * a_of_chi(la, chi));
-        if (la.dec) {
-            if (base_w < T(0.5) * T(A::LIM)) {
-                // every corner weight is below the limit: the map argument
-                // is never written
-                splat_region<T>(acc, rs, p0x, p0y, la.npix, kappa, t0, t1, base_w);
-                splat_region<T>(acc + rs2, rs, p0x, p0y, la.npix, kappa, t0, t1,
-                                base_w * chi * la.inv_chi_ref);
-            } else {
-                for (int s = 0; s < la.nsrc; ++s) {
-                    if (la.slot[s] != -1) continue;
-                    T cs = la.chi_src[s];
-                    splat_region<T>(acc, rs, p0x, p0y, la.npix, kappa + (long)s * npix2, t0, t1,
-                                    base_w * (cs - chi) / cs, true);
-                }
+        if constexpr (!DEC) {
+            for (int s = 0; s < la.nsrc; ++s) {
+                T cs = la.chi_src[s];
+                if (chi < cs)
+                    splat_region<T>(acc + s * rs2, rs, p0x, p0y, la.npix, kappa + (long)s * npix2,
+                                    t0, t1, base_w * (cs - chi) / cs);
+            }
+            return;
+        }
+        if (base_w < T(0.5) * T(A::LIM)) {
+            // every corner weight is below the limit: the map argument is
+            // never written
+            splat_region<T>(acc, rs, p0x, p0y, la.npix, kappa, t0, t1, base_w);
+            splat_region<T>(acc + rs2, rs, p0x, p0y, la.npix, kappa, t0, t1,
+                            base_w * chi * la.inv_chi_ref);
+        } else {
+            for (int s = 0; s < la.nsrc; ++s) {
+                if (la.slot[s] != -1) continue;
+                T cs = la.chi_src[s];
+                splat_region<T>(acc, rs, p0x, p0y, la.npix, kappa + (long)s * npix2, t0, t1,
+                                base_w * (cs - chi) / cs, true);
             }
         }
         for (int d = 0; d < la.ndirect; ++d) {
             const int s = la.direct_src[d];
             T cs = la.chi_src[s];
             if (chi < cs)
-                splat_region<T>(acc + (2 * la.dec + d) * rs2, rs, p0x, p0y, la.npix,
+                splat_region<T>(acc + (2 + d) * rs2, rs, p0x, p0y, la.npix,
                                 kappa + (long)s * npix2, t0, t1, base_w * (cs - chi) / cs);
         }
     };
@@ -500,37 +509,59 @@ __device__ __forceinline__ void lens_gather_body(Parts<T> p, SortBufs sb, Geo g,
         int px = p0x + r, py = p0y + c;
         if (px < la.npix && py < la.npix) {
             long o = (long)s * npix2 + (long)px * la.npix + py;
-            const int sl = la.slot[s];
-            T v = T(0);
-            if (sl >= 0) v = A::dec(acc[sl * rs2 + rc]);
-            else if (sl == -1)
-                v = (T)(A::dec_d(acc[rc]) - (double)la.ratio[s] * A::dec_d(acc[rs2 + rc]));
+            T v;
+            if constexpr (DEC) {
+                const int sl = la.slot[s];
+                v = T(0);
+                if (sl >= 0) v = A::dec(acc[sl * rs2 + rc]);
+                else if (sl == -1)
+                    v = (T)(A::dec_d(acc[rc]) - la.ratio[s] * A::dec_d(acc[rs2 + rc]));
+            } else {
+                v = A::dec(acc[i]);
+            }
             kappa[o] += v + mean.v[s];
         }
     }
 }
 
-template <class T, int LG, bool EXT>
+template <class T, int LG, bool EXT, bool DEC>
 __global__ __launch_bounds__(LG) void k_lens_gather(Parts<T> p, SortBufs sb, Geo g, LensArgs<T> la,
                                                     MapAdd<T> mean, T* kappa) {
-    lens_gather_body<T, LG, EXT>(p, sb, g, la, mean, kappa);
+    lens_gather_body<T, LG, EXT, DEC>(p, sb, g, la, mean, kappa);
 }
 template <class T, int LG>
 __global__ __launch_bounds__(LG) void k_lens_gather_b(const LensGatherArgs<T>* __restrict__ tab) {
     const LensGatherArgs<T> a = tab[blockIdx.y];
     if (!a.on) return;
-    lens_gather_body<T, LG, false>(a.p, a.sb, a.g, a.la, a.mean, a.kappa);
+    lens_gather_body<T, LG, false, false>(a.p, a.sb, a.g, a.la, a.mean, a.kappa);
 }
 
 // LDS bytes after the accumulator for the D(a(chi)) window of sub-evolution
 constexpr size_t DWIN_BYTES = 16384;
 
+template <class T, int LG, bool EXT, bool DEC>
+static void launch_lens_gather_k(Parts<T> p, SortBufs sb, Geo g, const LensArgs<T>& la,
+                                 const MapAdd<T>& mean, T* kappa, size_t lds, hipStream_t st) {
+    constexpr size_t LDS_MAX = 163840;  // per workgroup on gfx950
+    // above the default dynamic LDS limit: raised once per instantiation
+    static bool raised = false;
+    if (!raised) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_lens_gather<T, LG, EXT, DEC>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_MAX);
+        raised = true;
+    }
+    const int nreg = (la.npix + la.rs - 1) / la.rs;
+    hipLaunchKernelGGL((k_lens_gather<T, LG, EXT, DEC>), dim3(nreg * nreg), dim3(LG), lds, st, p,
+                       sb, g, la, mean, kappa);
+}
+
 template <class T, bool EXT>
 void launch_lens_gather_t(Parts<T> p, SortBufs sb, Geo g, LensArgs<T> la,
                           const MapAdd<T>& mean, T* kappa, hipStream_t st) {
-    int nreg = (la.npix + la.rs - 1) / la.rs;
-    size_t lds = (size_t)la.nacc * la.rs * la.rs * sizeof(typename LensAcc<T>::S) +
-                 lens_queue_bytes<T>(la.rs >= 64 ? 1024 : 256);
+    const int lg = la.rs >= 64 ? 1024 : 256;
+    size_t lds = (size_t)(la.dec ? la.nacc : la.nsrc) * la.rs * la.rs *
+                     sizeof(typename LensAcc<T>::S) +
+                 lens_queue_bytes<T>(lg);
     constexpr size_t LDS_MAX = 163840;  // per workgroup on gfx950
     la.dwin = 0;
     if (EXT && la.sub && lds < LDS_MAX) {
@@ -539,24 +570,12 @@ void launch_lens_gather_t(Parts<T> p, SortBufs sb, Geo g, LensArgs<T> la,
         la.dwin = (int)w;
         lds += w * 2 * sizeof(T);
     }
-    // above the default dynamic LDS limit: raised once per instantiation
-    static bool raised[2] = {false, false};
-    if (la.rs >= 64) {
-        if (!raised[1]) {
-            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_lens_gather<T, 1024, EXT>),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_MAX);
-            raised[1] = true;
-        }
-        hipLaunchKernelGGL((k_lens_gather<T, 1024, EXT>), dim3(nreg * nreg), dim3(1024), lds, st, p,
-                           sb, g, la, mean, kappa);
+    if (lg == 1024) {
+        if (la.dec) launch_lens_gather_k<T, 1024, EXT, true>(p, sb, g, la, mean, kappa, lds, st);
+        else launch_lens_gather_k<T, 1024, EXT, false>(p, sb, g, la, mean, kappa, lds, st);
     } else {
-        if (!raised[0]) {
-            (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_lens_gather<T, 256, EXT>),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)LDS_MAX);
-            raised[0] = true;
-        }
-        hipLaunchKernelGGL((k_lens_gather<T, 256, EXT>), dim3(nreg * nreg), dim3(256), lds, st, p,
-                           sb, g, la, mean, kappa);
+        if (la.dec) launch_lens_gather_k<T, 256, EXT, true>(p, sb, g, la, mean, kappa, lds, st);
+        else launch_lens_gather_k<T, 256, EXT, false>(p, sb, g, la, mean, kappa, lds, st);
     }
 }
 

@@ -150,6 +150,10 @@ LENS_GEOMETRIES = {
     "near": (32, 64.0, 48, 6.0, (0.5, 1.0), 0.9, 1.0),
     # a 256^2 map: 64 x 64-pixel regions with 1024-thread workgroups
     "regions64": (16, 64.0, 256, 4.0, (1.0, 2.0), 0.5, 0.6),
+    # six source planes, one in front of the shell, one inside and four
+    # beyond it: those four share two accumulators, which lets the regions
+    # grow to 64 x 64 pixels (six accumulators would need 32 x 32)
+    "many": (16, 64.0, 256, 4.0, (0.3, 0.6, 1.0, 1.4, 1.8, 2.2), 0.6, 0.7),
 }
 
 
