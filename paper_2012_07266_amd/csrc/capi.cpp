@@ -7,6 +7,7 @@
 #include <complex>
 #include <algorithm>
 #include <cstring>
+#include <functional>
 #include <memory>
 #include <mutex>
 #include <new>
@@ -606,12 +607,14 @@ template <class T> struct Sim final : SimBase {
     }
 
     void fft_forward_grad(int n, const T* G, const cx<T>* tw, const cx<T>* twh, const cx<T>* twp,
-                          HaloMerge<T> hm = HaloMerge<T>()) {
+                          HaloMerge<T> hm = HaloMerge<T>(),
+                          const std::function<void()>& after_fwd = nullptr) {
         // Poisson: G(q) = 1 / (2 pi q Nm^2) computed in the kernel (G == NULL)
         const T gscale = (T)(1.0 / (2.0 * PI * (double)n * (double)n));
         { ProfScope ps(prof, "fft_r2c_axis2"); fft_r2c_rows<T>(n, mesh[0], nyq[0], twh, twp, st, hm); }
         { ProfScope ps(prof, "fft_c2c_axis1_fwd");
           fft_c2c_axis1<T>(n, 1, reinterpret_cast<cx<T>*>(mesh[0]), nyq[0], tw, st); }
+        if (after_fwd) after_fwd();  // work to overlap with the rest of the transform
         PtrTriple om{{mesh[0], mesh[1], mesh[2]}}, on{{nyq[0], nyq[1], nyq[2]}};
         // axis 0: IFFT0(n0 h) -> mesh 0, IFFT0(h) -> mesh 1 (h = i G X)
         { ProfScope ps(prof, "fft_grad_axis0");
@@ -961,7 +964,7 @@ template <class T> struct Sim final : SimBase {
             }
             // with PGD the shift's paint and forward passes are the force's
             // (and the projection needs the shift); without, the projection
-            // runs on the second stream beside the paint and the transform
+            // runs on the second stream beside the transform
             if (pgd || !st_lens) {
                 if (pgd) pgd_shift(a1);
                 else paint(true);
@@ -971,13 +974,22 @@ template <class T> struct Sim final : SimBase {
                 else fft_forward_grad(P.nm, nullptr, tw_nm, tw_hm, twp_nm,
                                       paint_halo_merge<T>(geo, halo));
             } else {
+                // The shell's projection, started after the forward axis-1
+                // pass, shares the GPU with the fused axis-0 pass and the
+                // inverse passes: it costs the step less there than beside
+                // the paint, the axis-2 or the forward axis-1 pass.
+                int rc = 0;
                 paint(true);
-                HIPCHK(hipEventRecord(ev_fork, st));
-                HIPCHK(hipStreamWaitEvent(st_lens, ev_fork, 0));
-                int rc = project_shell(a0, a1, kap, T(0), st_lens);
+                fft_forward_grad(P.nm, nullptr, tw_nm, tw_hm, twp_nm, paint_halo_merge<T>(geo, halo), [&] {
+                    if (hipEventRecord(ev_fork, st) != hipSuccess ||
+                        hipStreamWaitEvent(st_lens, ev_fork, 0) != hipSuccess) {
+                        rc = PM_EDEVICE;
+                        return;
+                    }
+                    rc = project_shell(a0, a1, kap, T(0), st_lens);
+                    if (hipEventRecord(ev_join, st_lens) != hipSuccess && !rc) rc = PM_EDEVICE;
+                });
                 if (rc) return rc;
-                HIPCHK(hipEventRecord(ev_join, st_lens));
-                fft_forward_grad(P.nm, nullptr, tw_nm, tw_hm, twp_nm, paint_halo_merge<T>(geo, halo));
                 HIPCHK(hipStreamWaitEvent(st, ev_join, 0));
             }
             const T k2 = (T)cosmo.kick(ah, a1, a1);
