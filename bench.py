@@ -92,6 +92,20 @@ def model_bytes(wl, esize=4):
     return {"readout_kick_drift_key": 3 * M + 48 * P, "readout_kick": 3 * M + 48 * P}
 
 
+# kernel classes launched on the second stream (beside the force transform)
+SIDE_STREAM = {"lens_gather"}
+# (method's bytes, kernel's own bytes) of the kernels model_bytes names
+BYTES_WHAT = {
+    "readout_kick_drift_key": (
+        "3 M + 48 P: three force meshes, position and momentum read and written",
+        "3 M + 56 P: the kernel's own arrays, with the particle id read and the next step's "
+        "sort key written"),
+    "readout_kick": (
+        "3 M + 48 P: three force meshes, position and momentum read, momentum and force "
+        "written",
+        "3 M + 52 P: the kernel's own arrays, with the particle id read and the force written"),
+}
+
 TRAFFIC_JSON = os.path.join(ROOT, "profiles", "traffic.json")
 # kernel class -> (substring of the HIP kernel name in rocprofv3 output, source)
 KERNEL_SYMBOL = {
@@ -599,7 +613,10 @@ def main():
         # every launch (they cost time between kernels, so the timed repeats
         # below record only the dominant kernel)
         prof = timed_window(profile=True)
-        dom = max(prof, key=lambda k: prof[k][0])
+        # the shell projection runs on a second stream beside the force
+        # transform, off the step's critical path: the dominant kernel is the
+        # main stream's longest in total
+        dom = max((k for k in prof if k not in SIDE_STREAM), key=lambda k: prof[k][0])
     times = []
     dom_ms, dom_cnt = 0.0, 0
     for _ in range(max(1, args.repeats)):
@@ -657,12 +674,10 @@ def main():
             "traffic": t_ent["bytes_per_launch"] if t_ent and t_ent["current"] else None,
             "avg_ms": avg_d, "launches": dom_cnt,
             "algorithmic_bytes": b_d,
-            "algorithmic_bytes_what": "3 M + 48 P: three force meshes, position and momentum "
-                                      "read and written",
+            "algorithmic_bytes_what": BYTES_WHAT.get(dom, ("the kernel's own arrays",))[0],
             "achieved_own_bytes": (b_own / (avg_d * 1e-3) / 1e9) if avg_d > 0 and b_own else None,
             "own_bytes": b_own,
-            "own_bytes_what": "3 M + 56 P: the kernel's own arrays, with the particle id read "
-                              "and the next step's sort key written"}
+            "own_bytes_what": BYTES_WHAT.get(dom, ("", "the kernel's own arrays"))[-1]}
         out["hbm_effective_gbs_all_kernels"] = total_bytes / (total_ms * 1e-3) / 1e9
         kern_ms_step = total_ms / K
         if tr and "_step_bytes" in tr:

@@ -147,7 +147,7 @@ __global__ __launch_bounds__(AB) void k_fvjp_readout(Parts<T> p, SortBufs s, Geo
     const int tx = t / (g.nt * g.nt), ty = (t / g.nt) % g.nt, tz = t % g.nt;
     const int ox = tx * TILE, oy = ty * TILE, oz = tz * TILE;
     const int b0 = tile_block(g, tx, ty, tz);
-    const uint32_t lo = s.start[b0], hi = s.start[b0 + TILE / KZ];
+    const uint32_t lo = s.start[b0], hi = s.start[b0 + BPT];
     if (lo == hi) return;
     {
         const T* const fm[3] = {f0, f1, f2};
@@ -212,7 +212,7 @@ __global__ __launch_bounds__(AB) void k_fvjp_paintgrad(Parts<T> p, SortBufs s, G
     const int tx = t / (g.nt * g.nt), ty = (t / g.nt) % g.nt, tz = t % g.nt;
     const int ox = tx * TILE, oy = ty * TILE, oz = tz * TILE;
     const int b0 = tile_block(g, tx, ty, tz);
-    const uint32_t lo = s.start[b0], hi = s.start[b0 + TILE / KZ];
+    const uint32_t lo = s.start[b0], hi = s.start[b0 + BPT];
     if (lo == hi) return;
     {
         const T* const fm[1] = {rhobar};
@@ -683,7 +683,7 @@ __global__ __launch_bounds__(AB) void k_fjvp_gather(Parts<T> p, SortBufs s, Geo 
     const int tx = t / (g.nt * g.nt), ty = (t / g.nt) % g.nt, tz = t % g.nt;
     const int ox = tx * TILE, oy = ty * TILE, oz = tz * TILE;
     const int b0 = tile_block(g, tx, ty, tz);
-    const uint32_t lo = s.start[b0], hi = s.start[b0 + TILE / KZ];
+    const uint32_t lo = s.start[b0], hi = s.start[b0 + BPT];
     if (lo == hi) return;
     {
         const T* const fm[3] = {f0, f1, f2};
@@ -731,7 +731,7 @@ __global__ __launch_bounds__(AB) void k_fjvp_readout_kick(Parts<T> p, SortBufs s
     const int tx = t / (g.nt * g.nt), ty = (t / g.nt) % g.nt, tz = t % g.nt;
     const int ox = tx * TILE, oy = ty * TILE, oz = tz * TILE;
     const int b0 = tile_block(g, tx, ty, tz);
-    const uint32_t lo = s.start[b0], hi = s.start[b0 + TILE / KZ];
+    const uint32_t lo = s.start[b0], hi = s.start[b0 + BPT];
     if (lo == hi) return;
     {
         const T* const fm[3] = {m0, m1, m2};

@@ -72,7 +72,7 @@ ArenaPlan plan_arena(const pm_params& p, const lens_params& l, size_t es) {
     }
     a.acc = L.take(3 * n * es);
     a.key = L.take(n * 4);
-    const size_t nkeys = nt * nt * (nm / KZ);  // sort blocks
+    const size_t nkeys = nt * nt * nt * BPT;  // sort blocks
     a.count = L.take(nkeys * 4);
     a.start = L.take((nkeys + 1) * 4);
     a.scan_sum = L.take((nkeys + 1023) / 1024 * 4);
@@ -387,9 +387,9 @@ template <class T> struct Sim final : SimBase {
         geo.nm = p->nm;
         geo.B = p->nm / p->np;
         geo.nt = p->nm / TILE;
-        geo.nkz = p->nm / KZ;
+        geo.ncb = geo.nt * BPT;
         geo.npart = (long)p->np * p->np * p->np;
-        ntiles = geo.nt * geo.nt * geo.nkz;  // sort blocks (keys)
+        ntiles = geo.nt * geo.nt * geo.ncb;  // sort blocks (keys)
         ap = plan_arena(*p, *l, sizeof(T));
         // (a handle in the static scratch creates nothing: it projects in line)
         if (!mem && (hipStreamCreateWithFlags(&st_lens, hipStreamNonBlocking) != hipSuccess ||
@@ -1713,7 +1713,7 @@ template <class T> struct Batch final : BatchBase {
         geo.nm = p->nm;
         geo.B = p->nm / p->np;
         geo.nt = p->nm / TILE;
-        geo.nkz = p->nm / KZ;
+        geo.ncb = geo.nt * BPT;
         geo.npart = (long)p->np * p->np * p->np;
         lshape.npix = npix;
         lshape.nsrc = nsrc;
@@ -1825,7 +1825,7 @@ template <class T> struct Batch final : BatchBase {
 
     void launch_all(char* base) {
         const int nm = shape.nm;
-        const int ntiles = geo.nt * geo.nt * geo.nkz;
+        const int ntiles = geo.nt * geo.nt * geo.ncb;
         launch_scan_batch(arr<ScanArgs>(base, o_scan), ntiles, cap, st);
         launch_scatter_batch<T>(arr<ScatterArgs<T>>(base, o_scatter), geo, cap, st);
         launch_paint_batch<T>(arr<PaintArgs<T>>(base, o_paint), geo, cap, st);

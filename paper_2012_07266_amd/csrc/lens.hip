@@ -323,6 +323,10 @@ __device__ __forceinline__ void lens_gather_body(Parts<T> p, SortBufs sb, Geo g,
         }
     };
 
+    // the first and last sort block, within a tile column, of the tile at
+    // depth z (cells; a column's blocks run along axis 2 a tile at a time)
+    auto first_block_at = [](T z) { return (int)floor(z / T(TILE)) * BPT; };
+    auto last_block_at = [](T z) { return (int)floor(z / T(TILE)) * BPT + BPT - 1; };
     int nz0 = (int)floor(cnear / nmf) - 1;
     if (nz0 < 0) nz0 = 0;
     const int nz1 = (int)floor(cmax / nmf) + (zclip > T(0) ? 1 : 0);
@@ -333,10 +337,10 @@ __device__ __forceinline__ void lens_gather_body(Parts<T> p, SortBufs sb, Geo g,
         const ZBound<T> zb_near = zbound<T>(la.cnear_d, nz, nm), zb_far = zbound<T>(la.cfar_d, nz, nm);
         T x0lo = min(a0lo * ca, a0lo * cb) - margin, x0hi = max(a0hi * ca, a0hi * cb) + margin;
         T x1lo = min(a1lo * ca, a1lo * cb) - margin, x1hi = max(a1hi * ca, a1hi * cb) + margin;
-        // sort blocks (KZ cells deep) along axis 2 that the replica's depth
-        // range can reach
-        int tz0 = max((int)floor((zlo - margin) / T(KZ)), 0);
-        int tz1 = min((int)floor((zhi + margin) / T(KZ)), g.nkz - 1);
+        // sort blocks of the tiles (TILE cells deep) along axis 2 that the
+        // replica's depth range can reach
+        int tz0 = max(first_block_at(zlo - margin), 0);
+        int tz1 = min(last_block_at(zhi + margin), g.ncb - 1);
         int nx0 = (int)floor((x0lo + half) / nmf), nx1 = (int)floor((x0hi + half) / nmf);
         int ny0 = (int)floor((x1lo + half) / nmf), ny1 = (int)floor((x1hi + half) / nmf);
         for (int nx = nx0; nx <= nx1; ++nx) {
@@ -373,8 +377,8 @@ __device__ __forceinline__ void lens_gather_body(Parts<T> p, SortBufs sb, Geo g,
                 const int tx1 = min((int)floor(hi3[0] / T(TILE)), nt - 1);
                 const int ty0 = max((int)floor(lo3[1] / T(TILE)), 0);
                 const int ty1 = min((int)floor(hi3[1] / T(TILE)), nt - 1);
-                const int kza = sym ? max((int)floor(lo3[2] / T(KZ)), 0) : tz0;
-                const int kzb = sym ? min((int)floor(hi3[2] / T(KZ)), g.nkz - 1) : tz1;
+                const int kza = sym ? max(first_block_at(lo3[2]), 0) : tz0;
+                const int kzb = sym ? min(last_block_at(hi3[2]), g.ncb - 1) : tz1;
                 for (int tx = tx0; tx <= tx1; ++tx)
                     for (int ty = ty0; ty <= ty1; ++ty) {
                         int tza = kza, tzb = kzb;
@@ -387,11 +391,11 @@ __device__ __forceinline__ void lens_gather_body(Parts<T> p, SortBufs sb, Geo g,
                                 !column_depths(a1lo, a1hi, T(ty * TILE) + T(ny) * nmf - half,
                                                margin, zmin, zmax))
                                 continue;
-                            tza = max(tz0, (int)floor((zmin - T(nz) * nmf) / T(KZ)));
-                            tzb = min(tz1, (int)floor((zmax - T(nz) * nmf) / T(KZ)));
+                            tza = max(tz0, first_block_at(zmin - T(nz) * nmf));
+                            tzb = min(tz1, last_block_at(zmax - T(nz) * nmf));
                         }
                         if (tza > tzb) continue;
-                        const int col = (tx * nt + ty) * g.nkz;
+                        const int col = (tx * nt + ty) * g.ncb;
                         const uint32_t lo = sb.start[col + tza], hi = sb.start[col + tzb + 1];
                         for (uint32_t base = lo; base < hi; base += LG * LUT) {
                             uint32_t idv[LUT];

@@ -11,10 +11,12 @@ constexpr int HALO = TE * TE + TILE * TE + TILE * TILE;  // 817 upper-shell cell
 // Particle-lattice and mesh geometry.  Positions are stored as displacements
 // from the lattice point in mesh-cell units; the lattice point of particle
 // (i0, i1, i2) is u = B*i + 1/2 cells.
-// Particles are sorted by blocks of TILE x TILE x KZ cells (the key), z
-// fastest: the two blocks of a 16^3 tile, and the tiles of a column along
-// axis 2, are consecutive, so any run of them is one index range.
-constexpr int KZ = 8;
+// Particles are sorted by blocks of KX x TILE x TILE cells (the key): a
+// 16^3 tile is its two halves along axis 0, numbered consecutively, and the
+// tiles of a column along axis 2 follow each other, so any run of tiles
+// along axis 2 is one index range.
+constexpr int BPT = 2;           // sort blocks per tile
+constexpr int KX = TILE / BPT;   // extent of a sort block along axis 0
 
 struct Geo {
     int np;      // particles per side
@@ -22,13 +24,13 @@ struct Geo {
     int B;       // nm / np
     int nt;      // tiles per side = nm / TILE
     long npart;  // np^3
-    int nkz;     // sort blocks along axis 2 = nm / KZ
+    int ncb;     // sort blocks per tile column along axis 2 = nt * BPT
 };
 
 // Index of the first sort block of tile (tx, ty, tz); the tile's particles
-// are start[b] .. start[b + TILE / KZ].
+// are start[b] .. start[b + BPT].
 __host__ __device__ __forceinline__ int tile_block(const Geo& g, int tx, int ty, int tz) {
-    return (tx * g.nt + ty) * g.nkz + tz * (TILE / KZ);
+    return (tx * g.nt + ty) * g.ncb + tz * BPT;
 }
 
 // Particle state in tile-sorted order (SoA, [3][npart] each).

@@ -96,7 +96,8 @@ __device__ __forceinline__ uint32_t tile_key(uint32_t id, const T (&d)[3], const
     cell_of(g.B, i0, d[0], g.nm, c0, t);
     cell_of(g.B, i1, d[1], g.nm, c1, t);
     cell_of(g.B, i2, d[2], g.nm, c2, t);
-    return (uint32_t)(((c0 / TILE) * g.nt + c1 / TILE) * g.nkz + c2 / KZ);
+    return (uint32_t)(((c0 / TILE) * g.nt + c1 / TILE) * g.ncb + (c2 / TILE) * BPT +
+                      (c0 % TILE) / KX);
 }
 
 // Histogram of the tile keys of the valid lanes: one atomic per distinct key
@@ -481,7 +482,7 @@ __device__ __forceinline__ void paint_group_body(Parts<T> p, SortBufs s, Geo g, 
     const double inv_scale = 1.0 / (double)scale;
     const long n = g.npart;
     const int b0 = tile_block(g, tx, ty, gz * G);
-    const uint32_t lo = s.start[b0], hi = s.start[b0 + G * (TILE / KZ)];
+    const uint32_t lo = s.start[b0], hi = s.start[b0 + G * BPT];
     uint32_t idv[PU];
     T dv[PU][3], mv[PU], tv[PU][3];
     // the first batch is in flight while the box is cleared
@@ -648,18 +649,21 @@ HaloMerge<T> paint_halo_merge(Geo g, const T* halo) {
 // ---------------------------------------------------------------------------
 // LDS-staged CIC readout + kick
 // ---------------------------------------------------------------------------
-// The readout works on one 16^3 tile (its two sort blocks) per workgroup,
-// with the tile's 17^3 force values of each component in LDS.  (Blocks of
-// 16 x 16 x 8 with a 17 x 17 x 9 box would fit more workgroups per CU, but
-// their 9-value rows along axis 2 waste most of each memory segment, and
-// measure slower.)
-constexpr int PBR = 512;  // threads per readout workgroup
-constexpr int RZ = TE;    // LDS depth of the readout box
-constexpr int RC = TE * TE * RZ;  // LDS cells of the readout box
+// The readout works on one sort block (8 x 16 x 16 cells) per workgroup,
+// with the block's 9 x 17 x 17 force values of each component in LDS
+// (31 KB in float32, five workgroups per CU).  The box's rows along axis 2,
+// the contiguous one, keep their full 17 values, so the box costs hardly
+// more memory requests per particle than a whole tile's 17^3 box, which
+// fits only two workgroups per CU.
+constexpr int PBR = 256;  // threads per readout workgroup
+constexpr int PUR = 2;    // particles per readout thread in flight
+constexpr int RX = KX + 1;  // LDS extents of the readout box: RX x TE x RZ
+constexpr int RZ = TE;
+constexpr int RC = RX * TE * RZ;  // LDS cells of the readout box
 
 // Workgroups are handed to the 8 XCDs round-robin.  Renumber them so that
-// each XCD walks a contiguous run of tiles: neighbouring tiles along axis 2
-// then share the 128-byte lines of their one-cell overlap in the same L2.
+// each XCD walks a contiguous run of blocks: neighbouring blocks then share
+// the 128-byte lines of their one-cell overlap in the same L2.
 __device__ __forceinline__ int xcd_tile(int b, int nb) {
     constexpr int NX = 8;
     if (nb % NX) return b;
@@ -667,7 +671,7 @@ __device__ __forceinline__ int xcd_tile(int b, int nb) {
 }
 
 // CIC force at a particle (displacement d from lattice point id) from the
-// 17^3 LDS tile of the three components at origin (ox, oy, oz).
+// LDS box of the three components at origin (ox, oy, oz).
 template <class T>
 __device__ __forceinline__ void tile_force(const Geo& g, uint32_t id, const T (&d)[3],
                                            const T (*ft)[RC], int ox, int oy, int oz,
@@ -679,7 +683,7 @@ __device__ __forceinline__ void tile_force(const Geo& g, uint32_t id, const T (&
     cell_of(g.B, i0, d[0], g.nm, c0, w0);
     cell_of(g.B, i1, d[1], g.nm, c1, w1);
     cell_of(g.B, i2, d[2], g.nm, c2, w2);
-    int l0 = min(max(c0 - ox, 0), TILE - 1);
+    int l0 = min(max(c0 - ox, 0), KX - 1);
     int l1 = min(max(c1 - oy, 0), TILE - 1);
     int l2 = min(max(c2 - oz, 0), TILE - 1);
     T wa[2] = {T(1) - w0, w0}, wb[2] = {T(1) - w1, w1}, wc[2] = {T(1) - w2, w2};
@@ -735,17 +739,17 @@ __device__ __forceinline__ void readout_kick_drift_key(
     wave_count(valid, key, s.count);
 }
 
-// Particles k0, k0 + PBR, ... (PU of them) of a readout batch.  Slots at or
+// Particles k0, k0 + PBR, ... (PUR of them) of a readout batch.  Slots at or
 // past hi load particle hi - 1 instead (hi > lo, so it exists) and are not
 // used: with no load conditional, the compiler keeps every load of the
-// batch and of the force tile in flight together.  Momenta are loaded even
+// batch and of the force box in flight together.  Momenta are loaded even
 // without a kick.
 template <class T>
 __device__ __forceinline__ void readout_load_batch(const Parts<T>& p, long n, uint32_t k0,
-                                                   uint32_t hi, uint32_t (&idv)[PU],
-                                                   T (&dv)[PU][3], T (&mv)[PU][3]) {
+                                                   uint32_t hi, uint32_t (&idv)[PUR],
+                                                   T (&dv)[PUR][3], T (&mv)[PUR][3]) {
 #pragma unroll
-    for (int u = 0; u < PU; ++u) {
+    for (int u = 0; u < PUR; ++u) {
         uint32_t k = k0 + u * PBR;
         k = k < hi ? k : hi - 1u;
         idv[u] = p.id[k];
@@ -764,21 +768,20 @@ __device__ __forceinline__ void readout_body(Parts<T> p, SortBufs s, Geo g, cons
     constexpr int TC = RC;
     __shared__ T ft[3][TC];
     const int tid = threadIdx.x;
-    const int t = xcd_tile(blockIdx.x, gridDim.x);
-    const int tx = t / (g.nt * g.nt), ty = (t / g.nt) % g.nt, tz = t % g.nt;
-    const int ox = tx * TILE, oy = ty * TILE, oz = tz * TILE;
+    const int b0 = xcd_tile(blockIdx.x, gridDim.x);  // one sort block
+    const int tx = b0 / (g.nt * g.ncb), ty = (b0 / g.ncb) % g.nt, kz = b0 % g.ncb;
+    const int ox = tx * TILE + (kz % BPT) * KX, oy = ty * TILE, oz = (kz / BPT) * TILE;
     const int nm = g.nm;
-    const int b0 = tile_block(g, tx, ty, tz);
     const long n = g.npart;
-    uint32_t idv[PU];
-    T dv[PU][3], mv[PU][3];
-    // Issue order: the tile's particle range and the force tile (which does
+    uint32_t idv[PUR];
+    T dv[PUR][3], mv[PUR][3];
+    // Issue order: the block's particle range and the force box (which does
     // not depend on it), then the first batch of particles, which waits
-    // only for the range; then the force tile goes to LDS.  The fences keep
+    // only for the range; then the force box goes to LDS.  The fences keep
     // this order (the compiler would otherwise test the range before issuing
     // the force loads, and move LDS stores, each waiting for its load, in
     // between the particle loads).
-    const uint32_t lo = s.start[b0], hi = s.start[b0 + TILE / KZ];
+    const uint32_t lo = s.start[b0], hi = s.start[b0 + 1];
     {
         constexpr int IT = (TC + PBR - 1) / PBR;
         T v0[IT], v1[IT], v2[IT];
@@ -813,10 +816,10 @@ __device__ __forceinline__ void readout_body(Parts<T> p, SortBufs s, Geo g, cons
         }
     }
     __syncthreads();
-    for (uint32_t base = lo; base < hi; base += PBR * PU) {
+    for (uint32_t base = lo; base < hi; base += PBR * PUR) {
         if (base != lo) readout_load_batch<T>(p, n, base + tid, hi, idv, dv, mv);
 #pragma unroll
-        for (int u = 0; u < PU; ++u) {
+        for (int u = 0; u < PUR; ++u) {
             uint32_t k = base + u * PBR + tid;
             const bool valid = k < hi;
             if (nx.on) {  // wave-uniform: every lane takes part in the histogram
@@ -856,8 +859,8 @@ __global__ __launch_bounds__(PBR) void k_readout_b(const ReadoutArgs<T>* __restr
 template <class T>
 void launch_readout(Parts<T> p, SortBufs s, Geo g, const T* f0, const T* f1, const T* f2,
                     T kick, int do_kick, uint32_t* status, hipStream_t st, ReadoutNext<T> nx) {
-    int ntiles = g.nt * g.nt * g.nt;
-    hipLaunchKernelGGL(k_readout<T>, dim3(ntiles), dim3(PBR), 0, st, p, s, g, f0, f1, f2, kick,
+    const int nblocks = g.nt * g.nt * g.ncb;
+    hipLaunchKernelGGL(k_readout<T>, dim3(nblocks), dim3(PBR), 0, st, p, s, g, f0, f1, f2, kick,
                        do_kick, status, nx);
 }
 
@@ -1024,8 +1027,8 @@ void launch_paint_batch(const PaintArgs<T>* tab, const Geo& g, int slots, hipStr
 
 template <class T>
 void launch_readout_batch(const ReadoutArgs<T>* tab, const Geo& g, int slots, hipStream_t st) {
-    const int ntiles = g.nt * g.nt * g.nt;
-    hipLaunchKernelGGL(k_readout_b<T>, dim3(ntiles, slots), dim3(PBR), 0, st, tab);
+    const int nblocks = g.nt * g.nt * g.ncb;
+    hipLaunchKernelGGL(k_readout_b<T>, dim3(nblocks, slots), dim3(PBR), 0, st, tab);
 }
 
 #define ML_INST_BATCH(T)                                                                           \
