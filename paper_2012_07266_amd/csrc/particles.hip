@@ -651,12 +651,14 @@ HaloMerge<T> paint_halo_merge(Geo g, const T* halo) {
 // ---------------------------------------------------------------------------
 // The readout works on one sort block (8 x 16 x 16 cells) per workgroup,
 // with the block's 9 x 17 x 17 force values of each component in LDS
-// (31 KB in float32, five workgroups per CU).  The box's rows along axis 2,
-// the contiguous one, keep their full 17 values, so the box costs hardly
-// more memory requests per particle than a whole tile's 17^3 box, which
-// fits only two workgroups per CU.
+// (31 KB in float32).  The box's rows along axis 2, the contiguous one, keep
+// their full 17 values, so the box costs hardly more memory requests per
+// particle than a whole tile's 17^3 box, which fits only two workgroups per
+// CU.  Four particles per thread in flight hold the kernel to four
+// workgroups per CU (by registers): with five, their boxes in flight
+// outgrow an XCD's L2 and the overlap rows are fetched again.
 constexpr int PBR = 256;  // threads per readout workgroup
-constexpr int PUR = 2;    // particles per readout thread in flight
+constexpr int PUR = 4;    // particles per readout thread in flight
 constexpr int RX = KX + 1;  // LDS extents of the readout box: RX x TE x RZ
 constexpr int RZ = TE;
 constexpr int RC = RX * TE * RZ;  // LDS cells of the readout box
