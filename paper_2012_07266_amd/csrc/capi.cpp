@@ -328,6 +328,7 @@ template <class T> struct Sim final : SimBase {
     T *tx = nullptr, *tx_alt = nullptr, *tp = nullptr, *tp_alt = nullptr, *tf = nullptr;
     bool tan_valid = false;  // the tangent belongs to the current state
     bool tan_carry = false;  // the next sort permutes the tangent too
+    bool tan_gather = false;  // the next force readout computes the tangent's share too
     double tan_om = 0;       // its Omega_m component
     double cell = 0;  // mesh cell, Mpc/h
     int ntiles = 0;
@@ -644,6 +645,19 @@ template <class T> struct Sim final : SimBase {
         paint(true);
         fft_forward_grad(P.nm, nullptr, tw_nm, tw_hm, twp_nm, paint_halo_merge<T>(geo, halo));
         meshes_valid = true;
+        if (tan_gather) {  // the first part of force_jvp_cur, on the same force boxes
+            launch_fill_u32(fmax_bits, 0u, 1, st);
+            TanGather<T> tg;
+            tg.xdot = tx;
+            tg.fbc = fbc;
+            tg.vmax_bits = fmax_bits;
+            tg.inv_h = T(1) / (T)cell;
+            tg.mass = (T)std::pow((double)geo.B, 3);
+            ProfScope ps(prof, "readout_kick_jvp_gather");
+            launch_readout_tangent<T>(cur, sb, geo, mesh[0], mesh[1], mesh[2], kick2, do_kick, status,
+                                      tg, st);
+            return;
+        }
         ProfScope ps(prof, "readout_kick");
         launch_readout<T>(cur, sb, geo, mesh[0], mesh[1], mesh[2], kick2, do_kick, status, st);
     }
@@ -1377,19 +1391,22 @@ template <class T> struct Sim final : SimBase {
 
     // Force tangent at the current state along tx into tf; with pd set, also
     // the second half-kick p_dot += K2 f_dot + ck2 f.  Leaves the meshes
-    // holding the tangent's force meshes.
-    void force_jvp_cur(T* pd, T k2, T ck2) {
+    // holding the tangent's force meshes.  gathered: the step's readout has
+    // already computed fbc and the paint's bound (tan_gather).
+    void force_jvp_cur(T* pd, T k2, T ck2, bool gathered = false) {
         const T H = (T)cell;
         const T mass = (T)std::pow((double)geo.B, 3);
-        if (!meshes_valid) {
-            paint();
-            fft_forward_grad(P.nm, nullptr, tw_nm, tw_hm, twp_nm);
-            meshes_valid = true;
+        if (!gathered) {
+            if (!meshes_valid) {
+                paint();
+                fft_forward_grad(P.nm, nullptr, tw_nm, tw_hm, twp_nm);
+                meshes_valid = true;
+            }
+            launch_fill_u32(fmax_bits, 0u, 1, st);
+            ProfScope ps(prof, "jvp_gather");
+            launch_fjvp_gather<T>(cur, sb, geo, mesh[0], mesh[1], mesh[2], tx, T(1) / H, mass, fbc,
+                                  fmax_bits, st);
         }
-        launch_fill_u32(fmax_bits, 0u, 1, st);
-        { ProfScope ps(prof, "jvp_gather");
-          launch_fjvp_gather<T>(cur, sb, geo, mesh[0], mesh[1], mesh[2], tx, T(1) / H, mass, fbc,
-                                fmax_bits, st); }
         meshes_valid = false;
         // the tangent paint reads x_dot (Mpc/h): mass / H turns it into cells
         { ProfScope ps(prof, "jvp_paint");
@@ -1482,12 +1499,15 @@ template <class T> struct Sim final : SimBase {
         { ProfScope ps(prof, "jvp_kick_drift");
           launch_jvp_pre<T>(cur, geo, tx, tp, tf, (T)cell, (T)k1, (T)dr, (T)(om_dot * dk1),
                             (T)(om_dot * ddr), st); }
-        // the forward step with the kernels of pm_step; its sort carries the tangent
+        // the forward step with the kernels of pm_step; its sort carries the
+        // tangent, and its readout computes the tangent's share of the force
         tan_carry = true;
+        tan_gather = true;
         int rc = step(a0, a1);
         tan_carry = false;
+        tan_gather = false;
         if (rc) return rc;
-        force_jvp_cur(tp, (T)k2, (T)(om_dot * dk2));
+        force_jvp_cur(tp, (T)k2, (T)(om_dot * dk2), true);
         tan_valid = true;
         return check_launch();
     }

@@ -136,6 +136,24 @@ template <class T>
 void launch_readout(Parts<T> p, SortBufs s, Geo g, const T* f0, const T* f1, const T* f2,
                     T kick, int do_kick, uint32_t* status, hipStream_t st,
                     ReadoutNext<T> nx = ReadoutNext<T>());
+// The tangent's share of a readout: the gradient of the CIC readout of each
+// force mesh along u_dot = inv_h x_dot (x_dot [3][n] in Mpc/h, tile order),
+// fbc_j = u_dot . grad R(x, M_j) (cells), and a bound of
+// mass sum_a |u_dot_a| (the tangent paint's fixed-point scale) raised into
+// *vmax_bits (float bits; the caller zeroes it).
+template <class T> struct TanGather {
+    const T* xdot = nullptr;
+    T* fbc = nullptr;
+    uint32_t* vmax_bits = nullptr;
+    T inv_h = T(0);
+    T mass = T(0);
+};
+// launch_readout (without the next step's kick and drift) that also
+// computes the tangent's share of the same force meshes.
+template <class T>
+void launch_readout_tangent(Parts<T> p, SortBufs s, Geo g, const T* f0, const T* f1, const T* f2,
+                            T kick, int do_kick, uint32_t* status, const TanGather<T>& tg,
+                            hipStream_t st);
 // Zel'dovich: disp = dfac*s, mom = pfac*s from the three displacement meshes
 // on the particle lattice (cells), id = lattice index.
 template <class T>

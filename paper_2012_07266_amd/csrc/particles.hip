@@ -703,6 +703,45 @@ __device__ __forceinline__ void tile_force(const Geo& g, uint32_t id, const T (&
         }
 }
 
+// The gradient of the CIC readout of each component along ud, fg_j =
+// ud . grad R(x, M_j), from the same LDS box: the operations, in the same
+// order, of the derivative passes' gather (CIC derivative -1 to the low node
+// and +1 to the high one along each axis).
+template <class T>
+__device__ __forceinline__ void tile_force_grad(const Geo& g, uint32_t id, const T (&d)[3],
+                                                const T (*ft)[RC], int ox, int oy, int oz,
+                                                const T (&ud)[3], T (&fg)[3]) {
+    int i0, i1, i2;
+    lattice_of(id, g.np, i0, i1, i2);
+    int c0, c1, c2;
+    T t0, t1, t2;
+    cell_of(g.B, i0, d[0], g.nm, c0, t0);
+    cell_of(g.B, i1, d[1], g.nm, c1, t1);
+    cell_of(g.B, i2, d[2], g.nm, c2, t2);
+    const int l0 = min(max(c0 - ox, 0), KX - 1);
+    const int l1 = min(max(c1 - oy, 0), TILE - 1);
+    const int l2 = min(max(c2 - oz, 0), TILE - 1);
+    const T w[3][2] = {{T(1) - t0, t0}, {T(1) - t1, t1}, {T(1) - t2, t2}};
+    const int base = (l0 * TE + l1) * RZ + l2;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        T gr[3] = {T(0), T(0), T(0)};
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+#pragma unroll
+                for (int c = 0; c < 2; ++c) {
+                    const T m = ft[j][base + (a * TE + b) * RZ + c];
+                    const T d0 = a ? T(1) : T(-1), d1 = b ? T(1) : T(-1), d2 = c ? T(1) : T(-1);
+                    gr[0] += d0 * w[1][b] * w[2][c] * m;
+                    gr[1] += w[0][a] * d1 * w[2][c] * m;
+                    gr[2] += w[0][a] * w[1][b] * d2 * m;
+                }
+        fg[j] = ud[0] * gr[0] + ud[1] * gr[1] + ud[2] * gr[2];
+    }
+}
+
 // Readout fused with the start of the next step: p += K2 f, then the next
 // step's p += K1' f and disp += Dr' p, and the particle's new tile key and
 // its histogram count (the work of k_kick_drift_key, with f still in
@@ -763,10 +802,12 @@ __device__ __forceinline__ void readout_load_batch(const Parts<T>& p, long n, ui
     }
 }
 
-template <class T>
+// TG: also the tangent's share (TanGather) for the plain readout.
+template <class T, bool TG = false>
 __device__ __forceinline__ void readout_body(Parts<T> p, SortBufs s, Geo g, const T* f0,
                                                 const T* f1, const T* f2, T kick, int do_kick,
-                                                uint32_t* status, ReadoutNext<T> nx) {
+                                                uint32_t* status, ReadoutNext<T> nx,
+                                                TanGather<T> tg = TanGather<T>()) {
     constexpr int TC = RC;
     __shared__ T ft[3][TC];
     const int tid = threadIdx.x;
@@ -818,6 +859,7 @@ __device__ __forceinline__ void readout_body(Parts<T> p, SortBufs s, Geo g, cons
         }
     }
     __syncthreads();
+    float vmax = 0.f;  // TG: the tangent paint's bound over this block
     for (uint32_t base = lo; base < hi; base += PBR * PUR) {
         if (base != lo) readout_load_batch<T>(p, n, base + tid, hi, idv, dv, mv);
 #pragma unroll
@@ -841,6 +883,28 @@ __device__ __forceinline__ void readout_body(Parts<T> p, SortBufs s, Geo g, cons
                 p.mom[n + k] = mv[u][1] + kick * a1;
                 p.mom[2 * n + k] = mv[u][2] + kick * a2;
             }
+            if constexpr (TG) {
+                T ud[3], fg[3];
+#pragma unroll
+                for (int a = 0; a < 3; ++a) ud[a] = tg.inv_h * tg.xdot[a * n + k];
+                vmax = fmaxf(vmax, (float)(tg.mass * (fabs(ud[0]) + fabs(ud[1]) + fabs(ud[2]))));
+                tile_force_grad<T>(g, idv[u], dv[u], ft, ox, oy, oz, ud, fg);
+#pragma unroll
+                for (int a = 0; a < 3; ++a) tg.fbc[a * n + k] = fg[a];
+            }
+        }
+    }
+    if constexpr (TG) {
+        // one atomic per workgroup; a bound slightly above the maximum keeps
+        // float rounding of the bound from under-sizing the fixed-point scale
+        __shared__ float redv[PBR / 64];
+        float v = vmax * 1.0001f;
+        for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
+        if ((tid & 63) == 0) redv[tid >> 6] = v;
+        __syncthreads();
+        if (tid == 0) {
+            for (int i = 1; i < PBR / 64; ++i) v = fmaxf(v, redv[i]);
+            if (v > 0.f) atomicMax(tg.vmax_bits, __float_as_uint(v));
         }
     }
 }
@@ -856,6 +920,22 @@ __global__ __launch_bounds__(PBR) void k_readout_b(const ReadoutArgs<T>* __restr
     const ReadoutArgs<T> a = tab[blockIdx.y];
     if (!a.on) return;
     readout_body<T>(a.p, a.s, a.g, a.f0, a.f1, a.f2, a.kick, a.do_kick, a.status, a.nx);
+}
+
+template <class T>
+__global__ __launch_bounds__(PBR) void k_readout_tg(Parts<T> p, SortBufs s, Geo g, const T* f0,
+                                                   const T* f1, const T* f2, T kick, int do_kick,
+                                                   uint32_t* status, TanGather<T> tg) {
+    readout_body<T, true>(p, s, g, f0, f1, f2, kick, do_kick, status, ReadoutNext<T>(), tg);
+}
+
+template <class T>
+void launch_readout_tangent(Parts<T> p, SortBufs s, Geo g, const T* f0, const T* f1, const T* f2,
+                            T kick, int do_kick, uint32_t* status, const TanGather<T>& tg,
+                            hipStream_t st) {
+    const int nblocks = g.nt * g.nt * g.ncb;
+    hipLaunchKernelGGL(k_readout_tg<T>, dim3(nblocks), dim3(PBR), 0, st, p, s, g, f0, f1, f2, kick,
+                       do_kick, status, tg);
 }
 
 template <class T>
@@ -1054,6 +1134,9 @@ ML_INST_BATCH(double)
     template HaloMerge<T> paint_halo_merge<T>(Geo, const T*);                                     \
     template void launch_readout<T>(Parts<T>, SortBufs, Geo, const T*, const T*, const T*, T, int, \
                                     uint32_t*, hipStream_t, ReadoutNext<T>);                      \
+    template void launch_readout_tangent<T>(Parts<T>, SortBufs, Geo, const T*, const T*,          \
+                                            const T*, T, int, uint32_t*, const TanGather<T>&,     \
+                                            hipStream_t);                                         \
     template void launch_init_ic<T>(Parts<T>, Geo, const T*, const T*, const T*, T, T,            \
                                     hipStream_t);                                                 \
     template void launch_get_state<T>(Parts<T>, Geo, T, T*, T*, T*, hipStream_t);                 \
