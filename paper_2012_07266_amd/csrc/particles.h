@@ -27,6 +27,15 @@ struct Geo {
     int ncb;     // sort blocks per tile column along axis 2 = nt * BPT
 };
 
+// Cell origin of sort block b (KX x TILE x TILE cells).
+__host__ __device__ __forceinline__ void block_origin(const Geo& g, int b, int& ox, int& oy,
+                                                      int& oz) {
+    const int tx = b / (g.nt * g.ncb), ty = (b / g.ncb) % g.nt, kz = b % g.ncb;
+    ox = tx * TILE + (kz % BPT) * KX;
+    oy = ty * TILE;
+    oz = (kz / BPT) * TILE;
+}
+
 // Index of the first sort block of tile (tx, ty, tz); the tile's particles
 // are start[b] .. start[b + BPT].
 __host__ __device__ __forceinline__ int tile_block(const Geo& g, int tx, int ty, int tz) {

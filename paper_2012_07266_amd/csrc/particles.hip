@@ -812,8 +812,8 @@ __device__ __forceinline__ void readout_body(Parts<T> p, SortBufs s, Geo g, cons
     __shared__ T ft[3][TC];
     const int tid = threadIdx.x;
     const int b0 = xcd_tile(blockIdx.x, gridDim.x);  // one sort block
-    const int tx = b0 / (g.nt * g.ncb), ty = (b0 / g.ncb) % g.nt, kz = b0 % g.ncb;
-    const int ox = tx * TILE + (kz % BPT) * KX, oy = ty * TILE, oz = (kz / BPT) * TILE;
+    int ox, oy, oz;
+    block_origin(g, b0, ox, oy, oz);
     const int nm = g.nm;
     const long n = g.npart;
     uint32_t idv[PUR];
