@@ -877,21 +877,22 @@ template <class T> struct Sim final : SimBase {
     // of 1e-6 keeps images whose float distance rounds across a source on the
     // per-image test).  With moved images allowed (sub-evolution, the PGD
     // shift: images can leave the shell's bounds) every source takes the
-    // per-image test.  Two or more sources beyond the shell can share the
+    // per-image test.  The sources beyond the shell can share the
     // accumulators A and B, their maps A - ratio B with ratio = 1 / (cs
-    // inv_chi_ref), inv_chi_ref being the factor the kernel applies in T;
-    // that is done when it lets the region grow (the region side follows
-    // from the accumulator count): at the same region side it measured
-    // slower than one accumulator per source.
+    // inv_chi_ref), inv_chi_ref being the factor the kernel applies in T,
+    // and the sources in front of it then take no accumulator.  That is
+    // done when it lets the region grow against one accumulator per source
+    // (the region side follows from the accumulator count): at the same
+    // region side it measured slower.  A shell with no source beyond it
+    // keeps A and B unused.
     void plan_sources(LensArgs<T>& la, double chi_near, double chi_far, bool fixed_bounds) const {
         int nbeyond = 0, nnone = 0;
         for (int s = 0; s < nsrc; ++s) {
             if (chisrc[s] > chi_far * (1.0 + 1e-6)) ++nbeyond;
             if (fixed_bounds && chisrc[s] < chi_near * (1.0 - 1e-6)) ++nnone;
         }
-        const int n_own = std::max(nsrc - nnone, 1), n_dec = 2 + (nsrc - nnone - nbeyond);
-        la.dec = (fixed_bounds && nbeyond >= 2 &&
-                  region_side(n_dec, npix) > region_side(n_own, npix)) ? 1 : 0;
+        const int n_dec = 2 + (nsrc - nnone - nbeyond);
+        la.dec = (fixed_bounds && region_side(n_dec, npix) > region_side(nsrc, npix)) ? 1 : 0;
         la.inv_chi_ref = (T)(1.0 / chi_far);
         la.ndirect = 0;
         for (int s = 0; s < nsrc; ++s) {

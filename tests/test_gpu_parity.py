@@ -154,6 +154,11 @@ LENS_GEOMETRIES = {
     # beyond it: those four share two accumulators, which lets the regions
     # grow to 64 x 64 pixels (six accumulators would need 32 x 32)
     "many": (16, 64.0, 256, 4.0, (0.3, 0.6, 1.0, 1.4, 1.8, 2.2), 0.6, 0.7),
+    # the same planes, a shell around z_s = 1.8: one plane beyond it, one
+    # inside, four in front, so A and B serve one plane
+    "many_one_beyond": (16, 64.0, 256, 4.0, (0.3, 0.6, 1.0, 1.4, 1.8, 2.2), 0.35, 0.365),
+    # a shell around the farthest plane: none beyond it (A and B unused)
+    "many_none_beyond": (16, 64.0, 256, 4.0, (0.3, 0.6, 1.0, 1.4, 1.8, 2.2), 0.305, 0.32),
 }
 
 
